@@ -1,0 +1,296 @@
+"""Seeded synthetic SAMR workloads.
+
+This module only *constructs inputs*: patch boxes, cell values, transfer
+function tables and camera frames.  It holds none of the rendering method's
+arithmetic (no tree building, no interpolation, no compositing), so both the
+HIP library and the FP64 oracle can be fed from it without sharing any code
+path of the method.
+
+Data model (Section 3 of the paper): a hierarchy of axis-aligned subgrids
+("patches") on levels l = 0..L-1 with a constant refinement factor r, mesh
+spacing h^l = h^0 / r^l.  Patch boxes are given in integer level-l cell
+coordinates (lo, dims); cell values are fp32, x fastest (array shape
+(nz, ny, nx)).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Sequence
+
+import numpy as np
+
+MASTER_SEED = 12123333
+
+
+@dataclasses.dataclass
+class Patch:
+    level: int
+    lo: np.ndarray          # int64[3], level-l cell coordinates
+    dims: np.ndarray        # int64[3]
+    cells: np.ndarray       # float32[nz, ny, nx], x fastest
+
+    @property
+    def hi(self) -> np.ndarray:
+        return self.lo + self.dims
+
+
+@dataclasses.dataclass
+class Hierarchy:
+    origin: np.ndarray      # float64[3]
+    h0: np.ndarray          # float64[3] root spacing
+    refine: int
+    nlevels: int
+    patches: List[Patch]
+
+    @property
+    def lmax(self) -> int:
+        return self.nlevels - 1
+
+    def scale(self, level: int) -> int:
+        """Finest cells per level-`level` cell along one axis."""
+        return self.refine ** (self.lmax - level)
+
+    def boxes_finest(self) -> np.ndarray:
+        """int64[np, 7]: level, lo[3], hi[3] in finest-level cell units."""
+        out = np.zeros((len(self.patches), 7), dtype=np.int64)
+        for i, p in enumerate(self.patches):
+            s = self.scale(p.level)
+            out[i, 0] = p.level
+            out[i, 1:4] = p.lo * s
+            out[i, 4:7] = (p.lo + p.dims) * s
+        return out
+
+    def cell_centres(self, p: Patch):
+        """World coordinates of the cell centres of patch p (x, y, z 1-D arrays)."""
+        h = self.h0 / float(self.refine) ** p.level
+        ax = [self.origin[a] + (p.lo[a] + np.arange(p.dims[a]) + 0.5) * h[a] for a in range(3)]
+        return ax
+
+    def nbytes_cells(self) -> int:
+        return int(sum(p.cells.nbytes for p in self.patches))
+
+    def with_field(self, fn) -> "Hierarchy":
+        """Same boxes, cells replaced by fn(X, Y, Z) evaluated at cell centres (FP64 -> fp32)."""
+        ps = []
+        for p in self.patches:
+            x, y, z = self.cell_centres(p)
+            Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
+            v = np.asarray(fn(X, Y, Z), dtype=np.float64)
+            v = np.broadcast_to(v, X.shape)
+            ps.append(Patch(p.level, p.lo.copy(), p.dims.copy(), np.ascontiguousarray(v, dtype=np.float32)))
+        return Hierarchy(self.origin.copy(), self.h0.copy(), self.refine, self.nlevels, ps)
+
+    def shuffled(self, seed: int) -> "Hierarchy":
+        rng = np.random.default_rng(seed)
+        perm = rng.permutation(len(self.patches))
+        return Hierarchy(self.origin.copy(), self.h0.copy(), self.refine, self.nlevels,
+                         [self.patches[i] for i in perm])
+
+
+def _rng(config: int, stream: str, seed: int = MASTER_SEED) -> np.random.Generator:
+    names = ["field", "patches", "lut", "cameras", "mlp_init", "train_views", "eval_views", "misc"]
+    ss = np.random.SeedSequence(seed).spawn(8)[config]
+    child = ss.spawn(len(names))[names.index(stream)]
+    return np.random.default_rng(child)
+
+
+def _disjoint(a_lo, a_hi, b_lo, b_hi) -> bool:
+    return bool(np.any(a_hi <= b_lo) or np.any(b_hi <= a_lo))
+
+
+# ----------------------------------------------------------------------------------------------
+# Fields (evaluated at cell centres by Hierarchy.with_field)
+# ----------------------------------------------------------------------------------------------
+
+def gaussian_sum_field(rng: np.random.Generator, n: int = 8, smin=0.02, smax=0.1):
+    c = rng.random((n, 3))
+    s = rng.uniform(smin, smax, n)
+    a = rng.random(n)
+
+    def fn(X, Y, Z):
+        v = np.zeros_like(X)
+        for j in range(n):
+            r2 = (X - c[j, 0]) ** 2 + (Y - c[j, 1]) ** 2 + (Z - c[j, 2]) ** 2
+            v = v + a[j] * np.exp(-r2 / (2.0 * s[j] ** 2))
+        return v
+    return fn
+
+
+def linear_field(a: Sequence[float], b: float):
+    a = np.asarray(a, dtype=np.float64)
+    return lambda X, Y, Z: a[0] * X + a[1] * Y + a[2] * Z + b
+
+
+def constant_field(c: float):
+    return lambda X, Y, Z: np.full_like(X, c)
+
+
+# ----------------------------------------------------------------------------------------------
+# Hierarchies
+# ----------------------------------------------------------------------------------------------
+
+def _empty_patch(level, lo, dims) -> Patch:
+    lo = np.asarray(lo, dtype=np.int64)
+    dims = np.asarray(dims, dtype=np.int64)
+    return Patch(level, lo, dims, np.zeros(tuple(int(d) for d in dims[::-1]), dtype=np.float32))
+
+
+def tiny_samr(seed: int = 0) -> Hierarchy:
+    """Config 1 geometry: root 32^3 on [0,1]^3, r = 2, four level-1 patches of 8..16
+    coarse cells per axis at cell-aligned random positions, pairwise disjoint
+    (same-level SAMR patches never overlap), field = sum of 8 Gaussians."""
+    rng = _rng(0, "patches", MASTER_SEED + seed)
+    root = _empty_patch(0, [0, 0, 0], [32, 32, 32])
+    boxes = []
+    while len(boxes) < 4:
+        ext = rng.integers(8, 17, 3)
+        lo = np.array([rng.integers(0, 32 - e + 1) for e in ext])
+        hi = lo + ext
+        if all(_disjoint(lo, hi, b0, b1) for b0, b1 in boxes):
+            boxes.append((lo, hi))
+    ps = [root] + [_empty_patch(1, 2 * lo, 2 * (hi - lo)) for lo, hi in boxes]
+    h = Hierarchy(np.zeros(3), np.full(3, 1.0 / 32), 2, 2, ps)
+    return h.with_field(gaussian_sum_field(_rng(0, "field", MASTER_SEED + seed)))
+
+
+def random_tiny(seed: int, max_patches: int = 6, nlevels: int = 3, refine: int | None = None,
+                root_cells: int = 8, multi_root: bool = False) -> Hierarchy:
+    """Small random hierarchies for builder/oracle pins: up to `max_patches` patches on
+    `nlevels` levels, r in {2, 4}; patches need not be properly nested (a level-l patch may
+    span several level-(l-1) parents or stick out of them)."""
+    rng = np.random.default_rng(np.random.SeedSequence([MASTER_SEED, 101, seed]))
+    r = int(refine if refine is not None else rng.choice([2, 4]))
+    ps: List[Patch] = []
+    if multi_root:
+        half = root_cells // 2
+        for i in range(2):
+            for j in range(2):
+                if rng.random() < 0.85 or not ps:
+                    ps.append(_empty_patch(0, [i * half, j * half, 0], [half, half, root_cells]))
+    else:
+        ps.append(_empty_patch(0, [0, 0, 0], [root_cells] * 3))
+    count = len(ps)
+    for lev in range(1, nlevels):
+        n_here = rng.integers(1, 3)
+        ncell = root_cells * r ** lev
+        boxes = [(p.lo, p.hi) for p in ps if p.level == lev]
+        tries = 0
+        while n_here > 0 and count < max_patches and tries < 200:
+            tries += 1
+            ext = rng.integers(1, max(2, ncell // 2) + 1, 3)
+            lo = np.array([rng.integers(0, ncell - e + 1) for e in ext])
+            hi = lo + ext
+            if all(_disjoint(lo, hi, b0, b1) for b0, b1 in boxes):
+                boxes.append((lo, hi))
+                ps.append(_empty_patch(lev, lo, hi - lo))
+                count += 1
+                n_here -= 1
+    h = Hierarchy(np.zeros(3), np.full(3, 1.0 / root_cells), r, nlevels, ps)
+    return h.with_field(gaussian_sum_field(np.random.default_rng(seed + 7), n=4, smin=0.1, smax=0.3))
+
+
+def single_level(n=(12, 10, 8), seed: int = 0) -> Hierarchy:
+    """One level-0 patch: the render reduces to a uniform-grid raycast."""
+    p = _empty_patch(0, [0, 0, 0], list(n))
+    h = Hierarchy(np.array([0.1, -0.2, 0.3]), np.array([0.05, 0.05, 0.05]), 2, 1, [p])
+    return h.with_field(gaussian_sum_field(np.random.default_rng(seed + 3), n=5, smin=0.1, smax=0.3))
+
+
+# ----------------------------------------------------------------------------------------------
+# Transfer functions (256 x RGBA; rgb emission, alpha channel = extinction per unit length)
+# ----------------------------------------------------------------------------------------------
+
+def lut_bumps(rng: np.random.Generator, sigma_scale: float = 20.0, power: float = 2.0) -> np.ndarray:
+    u = np.arange(256) / 255.0
+    lut = np.zeros((256, 4))
+    for c in range(3):
+        v = np.zeros(256)
+        for _ in range(3):
+            mu, w, a = rng.random(), rng.uniform(0.05, 0.3), rng.uniform(0.3, 1.0)
+            v += a * np.exp(-((u - mu) ** 2) / (2 * w * w))
+        lut[:, c] = np.clip(v, 0.0, 1.0)
+    lut[:, 3] = sigma_scale * u ** power
+    return lut.astype(np.float32)
+
+
+def lut_config1(seed: int = 0) -> np.ndarray:
+    return lut_bumps(_rng(0, "lut", MASTER_SEED + seed))
+
+
+def lut_linear_sigma(s: float, rgb=(0.8, 0.5, 0.2)) -> np.ndarray:
+    """sigma_i = s * i / 255 and constant emission colour."""
+    lut = np.zeros((256, 4), dtype=np.float64)
+    lut[:, :3] = rgb
+    lut[:, 3] = s * np.arange(256) / 255.0
+    return lut.astype(np.float32)
+
+
+def lut_constant(rgb=(0.8, 0.5, 0.2), sigma=3.0) -> np.ndarray:
+    lut = np.zeros((256, 4), dtype=np.float32)
+    lut[:, :3] = rgb
+    lut[:, 3] = sigma
+    return lut
+
+
+# ----------------------------------------------------------------------------------------------
+# Cameras: explicit FP64 frames (eye, right u, up v, forward w)
+# ----------------------------------------------------------------------------------------------
+
+def camera(eye, u, v, w, width, height, ortho=False, tan_half_fov=0.0, win=(0.0, 0.0)) -> dict:
+    return dict(eye=np.asarray(eye, np.float64), u=np.asarray(u, np.float64),
+                v=np.asarray(v, np.float64), w=np.asarray(w, np.float64),
+                tan_half_fov=float(tan_half_fov), ortho=bool(ortho),
+                win=np.asarray(win, np.float64), width=int(width), height=int(height))
+
+
+def look_at(eye, centre, up=(0.0, 1.0, 0.0)):
+    eye = np.asarray(eye, np.float64)
+    w = np.asarray(centre, np.float64) - eye
+    w /= np.linalg.norm(w)
+    u = np.cross(w, np.asarray(up, np.float64))
+    u /= np.linalg.norm(u)
+    v = np.cross(u, w)
+    return eye, u, v, w
+
+
+def ortho_axis_z(width=256, height=256, lo=(0.0, 0.0), hi=(1.0, 1.0), z=-1.0) -> dict:
+    """Orthographic view along +z whose window spans [lo, hi] in x, y."""
+    cx, cy = 0.5 * (lo[0] + hi[0]), 0.5 * (lo[1] + hi[1])
+    return camera([cx, cy, z], [1, 0, 0], [0, 1, 0], [0, 0, 1], width, height, ortho=True,
+                  win=(0.5 * (hi[0] - lo[0]), 0.5 * (hi[1] - lo[1])))
+
+
+def ortho_oblique(width=256, height=256, az_deg=30.0, el_deg=20.0, centre=(0.5, 0.5, 0.5),
+                  dist=2.0, half=0.9) -> dict:
+    az, el = math.radians(az_deg), math.radians(el_deg)
+    eye = np.asarray(centre) + dist * np.array([math.cos(el) * math.sin(az), math.sin(el),
+                                                -math.cos(el) * math.cos(az)])
+    e, u, v, w = look_at(eye, centre)
+    return camera(e, u, v, w, width, height, ortho=True, win=(half, half * height / width))
+
+
+def perspective_orbit(width, height, az, el, radius=2.0, centre=(0.5, 0.5, 0.5), fov_deg=40.0) -> dict:
+    eye = np.asarray(centre) + radius * np.array([math.cos(el) * math.sin(az), math.sin(el),
+                                                  -math.cos(el) * math.cos(az)])
+    e, u, v, w = look_at(eye, centre)
+    return camera(e, u, v, w, width, height, ortho=False, tan_half_fov=math.tan(math.radians(fov_deg) / 2))
+
+
+def config1_cameras(width=256, height=256):
+    return [ortho_axis_z(width, height), ortho_oblique(width, height)]
+
+
+def default_params(**kw) -> dict:
+    p = dict(v_lo=0.0, v_hi=1.0, step_frac=0.5, uniform_step=False, t_min=1e-5, lighting=False,
+             light=(1.0, 1.0, 1.0), k_a=0.3, k_d=0.7, eps_g=1e-3,
+             clip_lo=(-1e300, -1e300, -1e300), clip_hi=(1e300, 1e300, 1e300))
+    p.update(kw)
+    return p
+
+
+def config1(seed: int = 0):
+    """Tiny SAMR workload: hierarchy, LUT, cameras and params (v_hi = max cell)."""
+    h = tiny_samr(seed)
+    vmax = float(max(p.cells.max() for p in h.patches))
+    return h, lut_config1(seed), config1_cameras(), default_params(v_lo=0.0, v_hi=vmax)
