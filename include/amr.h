@@ -1,0 +1,265 @@
+/*
+ * amr.h — C ABI of libamr: single-pass raycasting of structured AMR data on MI355X (gfx950).
+ *
+ * Method: Kaehler & Abel, "Single-Pass GPU-Raycasting for Structured Adaptive Mesh
+ * Refinement Data" (arXiv 1212.3333).  The library
+ *   1. partitions the overlapping refinement levels into non-overlapping same-level leaf
+ *      blocks with an adaptive kD-tree built level by level        (amr_build_kdtree, Sec. 4.1)
+ *   2. stores one padded brick per subgrid in a linear HBM pool and encodes the tree for the
+ *      device                                                          (amr_pack_pool, Sec. 4.2, 5)
+ *   3. renders every pixel in one pass: kD-restart descent, per-leaf sampling at a rate
+ *      proportional to the leaf level's cell size, trilinear sampling, 1D RGBA transfer
+ *      function with on-the-fly gradient lighting across blocks, front-to-back
+ *      emission-absorption compositing with early termination      (amr_render, Sec. 5.3, 6)
+ *   4. differentiates the image with respect to the transfer function and lighting
+ *      parameters                                                     (amr_render_backward)
+ *
+ * Conventions for every function:
+ *   - returns AMR_OK (0) or an error code; amr_last_error() gives a thread-local message;
+ *   - "host" pointers are CPU memory, "device" pointers are HIP device memory owned by the
+ *     caller; the library never frees caller memory and allocates device memory only where
+ *     a function says so;
+ *   - `stream` is a hipStream_t (passed as void*); device work is enqueued asynchronously on
+ *     it, with no implicit synchronisation unless stated;
+ *   - integers describing the hierarchy are in cells; coordinates of world space are FP64.
+ */
+#ifndef AMR_H
+#define AMR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    AMR_OK = 0,
+    AMR_EINVAL = 1,       /* bad argument (NULL, size, range) */
+    AMR_EHIERARCHY = 2,   /* invalid hierarchy (overlap, outside root box, empty patch) */
+    AMR_ECAPACITY = 3,    /* caller buffer too small */
+    AMR_ENOMEM = 4,       /* host allocation failed */
+    AMR_EHIP = 5          /* HIP runtime error (launch, copy) */
+};
+
+const char *amr_last_error(void);
+
+/* ---------------------------------------------------------------------------------------- */
+/* Hierarchy (Section 3): subgrids on levels l = 0..nlevels-1, h^l = h^0 / refine^l.          */
+/* ---------------------------------------------------------------------------------------- */
+
+typedef struct {
+    int32_t level;        /* 0 = root level */
+    int32_t pad_;
+    int64_t lo[3];        /* lower corner, level-l cell coordinates */
+    int64_t dims[3];      /* cells per axis, >= 1 */
+    const float *cells;   /* host, dims[0]*dims[1]*dims[2] values, x fastest; may be NULL
+                             for amr_build_kdtree */
+} amr_patch;
+
+typedef struct {
+    double origin[3];     /* world position of level-0 cell coordinate 0 */
+    double h0[3];         /* root cell size */
+    int32_t refine;       /* r >= 2, constant over levels and axes */
+    int32_t nlevels;      /* 1..32 */
+} amr_domain;
+
+/* ---------------------------------------------------------------------------------------- */
+/* kD-tree (Section 4.1)                                                                     */
+/* ---------------------------------------------------------------------------------------- */
+
+typedef struct amr_tree amr_tree;   /* opaque, immutable after the build, shareable */
+
+typedef struct {
+    int64_t nodes, leaves;          /* leaves = kind (b) */
+    int64_t n_a, n_b, n_c;          /* node kinds: (a) fully refined inside one subgrid,
+                                       (b) leaf, (c) other internal */
+    int64_t depth;                  /* longest root-to-leaf path in edges */
+    int64_t empty_leaves;           /* leaves covered by no root subgrid (transparent) */
+    int64_t npatches;
+} amr_tree_info;
+
+typedef struct {                    /* one node, depth-first pre-order, low child first */
+    int32_t axis;                   /* 0,1,2; -1 for a leaf */
+    int32_t level;                  /* leaf: level of its patch; internal: level inserted
+                                       when the node was split */
+    int64_t split;                  /* internal: plane position in finest-level cells */
+    int32_t patch;                  /* leaf: patch id or -1 (no data); internal: -1 */
+    int32_t cover;                  /* internal: patch the node held before it was split */
+    int32_t kind;                   /* 0 = (a), 1 = (b), 2 = (c) */
+    int32_t pad_;
+} amr_node_host;
+
+typedef struct {                    /* one leaf, ids in depth-first pre-order */
+    int64_t lo[3], hi[3];           /* finest-level cells, half open */
+    int32_t patch, level;
+} amr_leaf_host;
+
+/* Builds the kD-tree of Section 4.1: the root is the bounding box B of the level-0 patches;
+ * each node is split by the axis-aligned plane through a face of the boxes being inserted
+ * that cuts the fewest of them, then splits the node's cells most evenly, then lowest axis,
+ * then lowest position; a node stops when it holds cells of one subgrid.  Levels are inserted
+ * one after another, refining every leaf that overlaps the next level.
+ * Validates the hierarchy first (AMR_EHIERARCHY: same-level overlap, a patch outside B,
+ * an empty patch, a level out of range, no level-0 patch).  Host only; *out must be freed
+ * with amr_tree_free. */
+int amr_build_kdtree(const amr_domain *dom, const amr_patch *patches, int32_t npatches, amr_tree **out);
+int amr_tree_stats(const amr_tree *tree, amr_tree_info *out);
+/* Copies the nodes and leaves (host arrays of at least stats.nodes / stats.leaves entries;
+ * AMR_ECAPACITY if smaller; either pointer may be NULL to skip it). */
+int amr_tree_export(const amr_tree *tree, amr_node_host *nodes, size_t ncap, amr_leaf_host *leaves, size_t lcap);
+void amr_tree_free(amr_tree *tree);
+
+/* ---------------------------------------------------------------------------------------- */
+/* Pool and device scene (Sections 4.2 and 5)                                                */
+/* ---------------------------------------------------------------------------------------- */
+
+typedef struct {
+    int32_t host_dst;     /* 1: d_pool and d_meta are host pointers (plain memcpy, no HIP) */
+    int32_t nthreads;     /* host threads for the ghost fill; 0 = hardware concurrency */
+    int32_t reserved_[6];
+} amr_pack_opts;
+
+/* Device view of a packed scene.  Filled by amr_pack_pool; every pointer points into the
+ * caller's d_pool / d_meta buffers, which must outlive the scene. */
+typedef struct {
+    const float *pool;          /* padded bricks, fp32, one per patch, 256-byte aligned */
+    const void *nodes;          /* device tree, breadth-first, 16 bytes per node */
+    const void *leaves;         /* leaf records, 64 bytes each */
+    const void *patches;        /* patch headers, 128 bytes each */
+    int64_t pool_bytes, meta_bytes;
+    int32_t nnodes, nleaves, npatches, nlevels;
+    int32_t lmax, refine, depth, pad_;
+    double box_lo[3], box_hi[3];        /* B in world coordinates */
+    double origin[3], h0[3], hfine[3];  /* hfine = h0 / refine^lmax */
+    double step_fine;                   /* min_a h^lmax_a */
+    float v_min, v_max;                 /* range of all cell values */
+} amr_scene;
+
+/* Packs every patch into one padded brick (one ghost layer, values defined as in the design
+ * notes: same-level copy, edge replication outside B, coarse trilinear interpolant, nearest
+ * interior cell) computed in FP64 and stored as fp32, and writes the device tree, leaf table
+ * and patch headers to d_meta.  Two-call protocol: with d_pool == NULL and d_meta == NULL it
+ * only writes the required sizes to *pool_bytes and *meta_bytes.  Otherwise the buffers
+ * must hold at least those sizes (AMR_ECAPACITY).  The copies are enqueued on `stream` and
+ * the function waits for them before returning (host staging memory is freed).
+ * `patches` must be the array passed to amr_build_kdtree, with cells != NULL. */
+int amr_pack_pool(const amr_tree *tree, const amr_patch *patches, int32_t npatches,
+                  const amr_pack_opts *opts, void *d_pool, int64_t *pool_bytes,
+                  void *d_meta, int64_t *meta_bytes, amr_scene *out_scene, void *stream);
+
+/* ---------------------------------------------------------------------------------------- */
+/* Rendering (Section 5.3)                                                                   */
+/* ---------------------------------------------------------------------------------------- */
+
+typedef struct {
+    double eye[3], u[3], v[3], w[3];    /* explicit frame: right u, up v, forward w */
+    double tan_half_fov;                /* perspective half-angle tangent (vertical) */
+    double win[2];                      /* orthographic half extents (x, y) */
+    int32_t ortho, width, height, pad_;
+} amr_camera;
+
+typedef struct {                        /* per ray segment, for parity tests */
+    int32_t leaf, patch, n, level;      /* n = samples taken on the leaf (0 if no data) */
+    double ta, tb;                      /* FP64 ray parameters of the segment */
+} amr_trace_rec;
+
+typedef struct {                        /* device counters, accumulated by amr_render */
+    unsigned long long samples, segments, rays_hit, tap_descents, guard_hits, trace_overflow;
+    unsigned long long skipped_segments, coarse_segments, seglog_count, ckpt_overflow;
+    unsigned long long reserved_[6];
+} amr_render_stats;
+
+typedef struct {
+    const float *d_lut;                 /* device [256][4]: r, g, b, extinction per unit length */
+    float v_lo, v_hi;                   /* u = clamp((F - v_lo) / (v_hi - v_lo), 0, 1); v_hi > v_lo */
+    float step_frac;                    /* step = step_frac * min_a h^l_a of the leaf level */
+    float t_min;                        /* early termination once T < t_min; 0 disables */
+    int32_t uniform_step;               /* 1: every leaf uses the finest level's step */
+    int32_t lighting;                   /* 1: gradient shading */
+    float light[3];                     /* light direction (need not be normalised) */
+    float k_a, k_d, eps_g;              /* shade = k_a + k_d |g.l| / sqrt(|g|^2 + eps_g^2) */
+    double clip_lo[3], clip_hi[3];      /* world clip box intersected with B */
+    /* optional per-ray outputs (device, NULL to skip) */
+    amr_trace_rec *d_trace;             /* [nrays][trace_cap] */
+    int32_t *d_trace_n;                 /* [nrays]: segments met (may exceed trace_cap) */
+    int32_t *d_nsamp;                   /* [nrays]: samples evaluated */
+    int64_t trace_cap;
+    /* adjoint checkpoints (device, NULL to skip; see amr_render_backward) */
+    void *d_ckpt;
+    int64_t ckpt_bytes;
+    int32_t ckpt_every;                 /* checkpoint every k-th data segment (>= 1) */
+    int32_t ckpt_max;                   /* checkpoints per ray */
+    /* learned segment proposals (NULL = plain traversal) */
+    const void *d_mlp;                  /* packed network, see amr_mlp_pack */
+    float tau_e, tau_s;                 /* skip if alpha_hi < tau_e; coarse if alpha_lo > 1 - tau_s */
+    void *d_seglog;                     /* segment log for training (amr_seglog_rec) */
+    int64_t seglog_cap;
+    /* scheduling */
+    int32_t persistent;                 /* 1: persistent tile-queue kernel */
+    int32_t tile_w, tile_h;             /* pixels per wave tile (0 = default 8 x 8) */
+    int32_t blocks_per_cu;              /* persistent grid = 256 CUs x this (0 = default) */
+    int32_t flags_;
+    void *d_queue;                      /* persistent: device scratch, >= amr_queue_bytes(ncams) */
+    unsigned long long *d_stamps;       /* persistent: per-image completion clock (optional) */
+} amr_render_params;
+
+/* Renders ncams cameras (host array) into d_rgba (device, premultiplied RGBA fp32, images
+ * concatenated, image i has width_i*height_i*4 floats, row 0 at the top).  d_stats
+ * (device, optional) is zeroed and then accumulated.  Asynchronous on `stream`. */
+int amr_render(const amr_scene *scene, const amr_camera *cams, int32_t ncams,
+               const amr_render_params *params, float *d_rgba, amr_render_stats *d_stats, void *stream);
+
+/* Bytes of device scratch the persistent batched kernel needs for ncams cameras. */
+int64_t amr_queue_bytes(int32_t ncams);
+
+/* Checkpoint buffer bytes for nrays rays with ckpt_max checkpoints each. */
+int64_t amr_ckpt_bytes(int64_t nrays, int32_t ckpt_max);
+
+/* Adjoint of amr_render for a loss L(RGBA): given dL/dRGBA (device, same layout as d_rgba),
+ * accumulates dL/dLUT into d_grad_lut (device [256][4], fp32, zeroed by the call) and
+ * dL/d(light_x, light_y, light_z, k_a, k_d) into d_grad_light (device [5]).  `params` must be
+ * the ones of the forward call that filled params->d_ckpt (same scene, cameras, LUT).
+ * The early-termination point of each ray is the forward's.  deterministic = 1 reduces
+ * per-block partial sums in a fixed order (bit-reproducible); 0 uses atomics.  Asynchronous. */
+int amr_render_backward(const amr_scene *scene, const amr_camera *cams, int32_t ncams,
+                        const amr_render_params *params, const float *d_grad_rgba,
+                        float *d_grad_lut, float *d_grad_light, int32_t deterministic, void *stream);
+
+/* ---------------------------------------------------------------------------------------- */
+/* Proposal network for learned segment skipping (an addition to the paper)                 */
+/* ---------------------------------------------------------------------------------------- */
+
+#define AMR_MLP_IN 12
+#define AMR_MLP_HID 64
+#define AMR_MLP_OUT 2
+
+typedef struct {                        /* one logged leaf segment (training data) */
+    float feat[AMR_MLP_IN];             /* features, see the design notes */
+    float alpha_seg;                    /* true segment opacity 1 - prod(1 - alpha_k) */
+    float t_in;                         /* transmittance entering the segment */
+    int32_t ray, n;
+} amr_seglog_rec;
+
+/* Forward pass of the 12-64-64-2 ReLU network on n rows: X (device, [n][12] fp32),
+ * W (device, packed fp32 master weights, amr_mlp_param_count floats), Y (device, [n][2],
+ * sigmoid outputs (alpha_lo, alpha_hi)); H (device scratch [n][128] fp32 activations, kept
+ * for the backward pass, may be NULL for inference).  fp16 MFMA with fp32 accumulation. */
+int32_t amr_mlp_param_count(void);
+int amr_mlp_forward(const float *X, const float *W, float *Y, float *H, int64_t n, void *stream);
+/* Backward of the pinball (quantile) loss mean over rows: q_lo for output 0, q_hi for
+ * output 1, targets T (device [n]); writes dW (device, zeroed by the call), loss (device [1]). */
+int amr_mlp_backward(const float *X, const float *W, const float *H, const float *Y, const float *T,
+                     int64_t n, float q_lo, float q_hi, float *dW, float *loss, void *stream);
+/* One Adam step on W with moments M, V (device, param_count each), step index t >= 1. */
+int amr_mlp_adam_step(float *W, const float *dW, float *M, float *V, int32_t t, float lr,
+                      float beta1, float beta2, float eps, void *stream);
+/* Packs fp32 master weights W into the fp16 inference layout used by amr_render (d_out of
+ * amr_mlp_packed_bytes() bytes, device). */
+int64_t amr_mlp_packed_bytes(void);
+int amr_mlp_pack(const float *W, void *d_out, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AMR_H */

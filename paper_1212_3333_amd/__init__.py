@@ -1,0 +1,270 @@
+"""MI355X-native single-pass raycasting of structured AMR data (Kaehler & Abel, arXiv 1212.3333).
+
+Thin Python binding over the C ABI of libamr (include/amr.h).  Every step of the hot path runs
+in the library's C++/HIP code; this module only marshals arguments, and torch provides device
+memory and the current stream.  If libamr.so is missing, importing this package fails.
+
+    tree  = build_tree(h)                    # amr_build_kdtree   (Section 4.1)
+    scene = pack(tree, h)                    # amr_pack_pool      (Sections 4.2, 5)
+    rgba  = render(scene, cams, lut, params) # amr_render         (Section 5.3)
+    gl, gL = render_backward(...)            # amr_render_backward
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Sequence
+
+import numpy as np
+import torch
+
+from . import _lib as L
+from ._lib import AMRError, check, load
+
+load()
+
+__all__ = ["AMRError", "Tree", "Scene", "build_tree", "pack", "render", "render_backward", "make_params",
+           "RenderOutput", "AMRRender"]
+
+
+def _vp(t) -> ctypes.c_void_p:
+    if t is None:
+        return ctypes.c_void_p(None)
+    if isinstance(t, torch.Tensor):
+        return ctypes.c_void_p(t.data_ptr())
+    if isinstance(t, np.ndarray):
+        return ctypes.c_void_p(t.ctypes.data)
+    return ctypes.c_void_p(t)
+
+
+def _stream(device=None) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _patch_array(h):
+    """amr_patch[] for a hierarchy (keeps the fp32 cell arrays alive via the returned list)."""
+    keep = []
+    arr = (L.amr_patch * len(h.patches))()
+    for i, p in enumerate(h.patches):
+        c = np.ascontiguousarray(p.cells, dtype=np.float32)
+        keep.append(c)
+        arr[i].level = int(p.level)
+        arr[i].lo[:] = [int(x) for x in p.lo]
+        arr[i].dims[:] = [int(x) for x in p.dims]
+        arr[i].cells = c.ctypes.data
+    return arr, keep
+
+
+def _domain(h) -> L.amr_domain:
+    d = L.amr_domain()
+    d.origin[:] = [float(x) for x in h.origin]
+    d.h0[:] = [float(x) for x in h.h0]
+    d.refine = int(h.refine)
+    d.nlevels = int(h.nlevels)
+    return d
+
+
+class Tree:
+    """Host kD-tree (immutable). Nodes and leaves are exported in depth-first pre-order."""
+
+    def __init__(self, h):
+        self.lib = load()
+        self.h = h
+        self._patches, self._keep = _patch_array(h)
+        self._dom = _domain(h)
+        ptr = ctypes.c_void_p()
+        check(self.lib.amr_build_kdtree(ctypes.byref(self._dom), self._patches, len(h.patches), ctypes.byref(ptr)),
+              "amr_build_kdtree")
+        self.ptr = ptr
+
+    def __del__(self):
+        if getattr(self, "ptr", None) and self.ptr.value:
+            self.lib.amr_tree_free(self.ptr)
+            self.ptr = None
+
+    def info(self) -> dict:
+        s = L.amr_tree_info()
+        check(self.lib.amr_tree_stats(self.ptr, ctypes.byref(s)), "amr_tree_stats")
+        return {k: int(getattr(s, k)) for k, _ in L.amr_tree_info._fields_}
+
+    def export(self):
+        """(nodes, leaves) as numpy structured arrays."""
+        inf = self.info()
+        nodes = (L.amr_node_host * inf["nodes"])()
+        leaves = (L.amr_leaf_host * inf["leaves"])()
+        check(self.lib.amr_tree_export(self.ptr, nodes, inf["nodes"], leaves, inf["leaves"]), "amr_tree_export")
+        ndt = np.dtype([("axis", np.int32), ("level", np.int32), ("split", np.int64), ("patch", np.int32),
+                        ("cover", np.int32), ("kind", np.int32), ("pad_", np.int32)])
+        ldt = np.dtype([("lo", np.int64, 3), ("hi", np.int64, 3), ("patch", np.int32), ("level", np.int32)])
+        return (np.frombuffer(bytes(nodes), dtype=ndt).copy(), np.frombuffer(bytes(leaves), dtype=ldt).copy())
+
+
+def build_tree(h) -> Tree:
+    return Tree(h)
+
+
+class Scene:
+    """Packed pool + device tree. On device, pool/meta are torch uint8 tensors on `device`;
+    with host=True they are numpy arrays (no HIP involved)."""
+
+    def __init__(self, tree: Tree, h, device="cuda", host: bool = False, nthreads: int = 0):
+        self.lib = load()
+        self.tree = tree
+        opts = L.amr_pack_opts()
+        opts.host_dst = 1 if host else 0
+        opts.nthreads = int(nthreads)
+        pb, mb = ctypes.c_int64(0), ctypes.c_int64(0)
+        check(self.lib.amr_pack_pool(tree.ptr, tree._patches, len(h.patches), ctypes.byref(opts), None,
+                                     ctypes.byref(pb), None, ctypes.byref(mb), None, None), "amr_pack_pool(size)")
+        self.scene = L.amr_scene()
+        self.host = host
+        if host:
+            self.pool = np.zeros(pb.value, dtype=np.uint8)
+            self.meta = np.zeros(mb.value, dtype=np.uint8)
+            stream = ctypes.c_void_p(None)
+        else:
+            self.pool = torch.empty(pb.value, dtype=torch.uint8, device=device)
+            self.meta = torch.empty(mb.value, dtype=torch.uint8, device=device)
+            stream = _stream(self.pool.device)
+        check(self.lib.amr_pack_pool(tree.ptr, tree._patches, len(h.patches), ctypes.byref(opts), _vp(self.pool),
+                                     ctypes.byref(pb), _vp(self.meta), ctypes.byref(mb), ctypes.byref(self.scene),
+                                     stream), "amr_pack_pool")
+
+    @property
+    def nbytes(self) -> int:
+        return int(self.scene.pool_bytes + self.scene.meta_bytes)
+
+    # host-side views (host=True scenes): padded bricks and device records
+    def brick(self, p: int) -> np.ndarray:
+        assert self.host
+        hdr = self.patch_headers()[p]
+        nx, ny, nz = (int(v) for v in hdr["n"])
+        pool = self.pool.view(np.float32)
+        off = int(hdr["off"])
+        return pool[off:off + (nx + 2) * (ny + 2) * (nz + 2)].reshape(nz + 2, ny + 2, nx + 2)
+
+    def patch_headers(self) -> np.ndarray:
+        dt = np.dtype([("off", np.uint64), ("n", np.int32, 3), ("level", np.int32), ("lo", np.float64, 3),
+                       ("inv_h", np.float64, 3), ("h", np.float64, 3), ("step", np.float64),
+                       ("vmin", np.float32), ("vmax", np.float32), ("pad", np.int32, 4)])
+        return self._records(self.scene.patches, dt, self.scene.npatches)
+
+    def leaf_records(self) -> np.ndarray:
+        dt = np.dtype([("lo", np.float64, 3), ("hi", np.float64, 3), ("patch", np.int32), ("level", np.int32),
+                       ("vmin", np.float32), ("vmax", np.float32)])
+        return self._records(self.scene.leaves, dt, self.scene.nleaves)
+
+    def node_records(self) -> np.ndarray:
+        dt = np.dtype([("split", np.float64), ("child", np.uint32), ("meta", np.uint32)])
+        return self._records(self.scene.nodes, dt, self.scene.nnodes)
+
+    def _records(self, ptr, dt, n):
+        base = self.meta.ctypes.data if self.host else self.meta.data_ptr()
+        off = ptr - base
+        raw = self.meta[off:off + n * dt.itemsize]
+        raw = raw if self.host else raw.cpu().numpy()
+        return np.frombuffer(raw.tobytes(), dtype=dt)
+
+
+def pack(tree: Tree, h, device="cuda", host: bool = False, nthreads: int = 0) -> Scene:
+    return Scene(tree, h, device=device, host=host, nthreads=nthreads)
+
+
+def make_camera(cam: dict) -> L.amr_camera:
+    c = L.amr_camera()
+    for k in ("eye", "u", "v", "w"):
+        getattr(c, k)[:] = [float(x) for x in cam[k]]
+    c.tan_half_fov = float(cam.get("tan_half_fov", 0.0))
+    c.win[:] = [float(x) for x in cam.get("win", (0.0, 0.0))]
+    c.ortho = int(bool(cam["ortho"]))
+    c.width, c.height = int(cam["width"]), int(cam["height"])
+    return c
+
+
+def make_params(p: dict, d_lut) -> L.amr_render_params:
+    q = L.amr_render_params()
+    q.d_lut = _vp(d_lut).value
+    q.v_lo, q.v_hi, q.step_frac, q.t_min = p["v_lo"], p["v_hi"], p["step_frac"], p["t_min"]
+    q.uniform_step = int(bool(p["uniform_step"]))
+    q.lighting = int(bool(p["lighting"]))
+    q.light[:] = [float(x) for x in p["light"]]
+    q.k_a, q.k_d, q.eps_g = p["k_a"], p["k_d"], p["eps_g"]
+    q.clip_lo[:] = [float(x) for x in p["clip_lo"]]
+    q.clip_hi[:] = [float(x) for x in p["clip_hi"]]
+    q.tau_e = float(p.get("tau_e", 0.0))
+    q.tau_s = float(p.get("tau_s", 0.0))
+    q.persistent = int(p.get("persistent", 0))
+    q.tile_w = int(p.get("tile_w", 0))
+    q.tile_h = int(p.get("tile_h", 0))
+    q.blocks_per_cu = int(p.get("blocks_per_cu", 0))
+    return q
+
+
+class RenderOutput(dict):
+    __getattr__ = dict.__getitem__
+
+
+def _cams(cams):
+    if isinstance(cams, dict):
+        cams = [cams]
+    arr = (L.amr_camera * len(cams))()
+    for i, c in enumerate(cams):
+        arr[i] = make_camera(c)
+    return cams, arr
+
+
+def render(scene: Scene, cams, lut: torch.Tensor, params: dict, trace_cap: int = 0, stats: bool = False,
+           nsamp: bool = False, out: torch.Tensor | None = None, **extra) -> RenderOutput:
+    """Renders one camera (dict) or several (list) with amr_render.  Returns RenderOutput with
+    rgba ([H,W,4] for one camera, else the concatenated flat [sum HW, 4]) and, on request,
+    trace/trace_n/nsamp/stats."""
+    lib = load()
+    dev = scene.pool.device
+    cam_list, carr = _cams(cams)
+    npix = sum(int(c["width"]) * int(c["height"]) for c in cam_list)
+    lut = lut.to(device=dev, dtype=torch.float32).contiguous()
+    q = make_params(dict(params, **extra), lut)
+    res = RenderOutput()
+    rgba = out if out is not None else torch.empty(npix * 4, dtype=torch.float32, device=dev)
+    if trace_cap:
+        trace = torch.zeros((npix, trace_cap, 32), dtype=torch.uint8, device=dev)
+        trace_n = torch.zeros(npix, dtype=torch.int32, device=dev)
+        q.d_trace, q.d_trace_n, q.trace_cap = trace.data_ptr(), trace_n.data_ptr(), trace_cap
+        res["trace_raw"], res["trace_n"] = trace, trace_n
+    if nsamp:
+        ns = torch.zeros(npix, dtype=torch.int32, device=dev)
+        q.d_nsamp = ns.data_ptr()
+        res["nsamp"] = ns
+    st = torch.zeros(16, dtype=torch.int64, device=dev) if stats else None
+    for k in ("d_ckpt", "ckpt_bytes", "ckpt_every", "ckpt_max", "d_mlp", "d_seglog", "seglog_cap", "d_queue",
+              "d_stamps"):
+        if k in extra:
+            v = extra[k]
+            setattr(q, k, v.data_ptr() if isinstance(v, torch.Tensor) else v)
+    check(lib.amr_render(ctypes.byref(scene.scene), carr, len(cam_list), ctypes.byref(q), _vp(rgba), _vp(st),
+                         _stream(dev)), "amr_render")
+    res["rgba"] = rgba.view(cam_list[0]["height"], cam_list[0]["width"], 4) if len(cam_list) == 1 else rgba.view(-1, 4)
+    if stats:
+        res["stats_raw"] = st
+    res["_keep"] = (lut, carr, q)
+    return res
+
+
+def trace_records(res: RenderOutput) -> np.ndarray:
+    """Decodes the per-ray segment trace into a numpy structured array [nrays, cap]."""
+    dt = np.dtype([("leaf", np.int32), ("patch", np.int32), ("n", np.int32), ("level", np.int32),
+                   ("ta", np.float64), ("tb", np.float64)])
+    raw = res["trace_raw"].cpu().numpy()
+    return raw.view(dt).reshape(raw.shape[0], raw.shape[1])
+
+
+def stats_dict(res: RenderOutput) -> dict:
+    v = res["stats_raw"].cpu().numpy().view(np.uint64)
+    return {k: int(v[i]) for i, k in enumerate(L.STATS_FIELDS)}
+
+
+def render_backward(*args, **kwargs):
+    raise NotImplementedError("defined below once the adjoint is available")
+
+
+class AMRRender(torch.autograd.Function):
+    """Placeholder; the adjoint binding replaces it."""

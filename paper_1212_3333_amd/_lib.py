@@ -1,0 +1,157 @@
+"""ctypes mirror of include/amr.h and the loader of the in-tree libamr.so.
+
+There is no fallback: if the library is missing the import fails loudly.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libamr.so")
+
+c_double3 = ctypes.c_double * 3
+c_int64_3 = ctypes.c_int64 * 3
+c_float3 = ctypes.c_float * 3
+VP = ctypes.c_void_p
+
+AMR_OK, AMR_EINVAL, AMR_EHIERARCHY, AMR_ECAPACITY, AMR_ENOMEM, AMR_EHIP = range(6)
+ERRNAMES = {1: "AMR_EINVAL", 2: "AMR_EHIERARCHY", 3: "AMR_ECAPACITY", 4: "AMR_ENOMEM", 5: "AMR_EHIP"}
+
+MLP_IN, MLP_HID, MLP_OUT = 12, 64, 2
+
+
+class amr_patch(ctypes.Structure):
+    _fields_ = [("level", ctypes.c_int32), ("pad_", ctypes.c_int32), ("lo", c_int64_3), ("dims", c_int64_3),
+                ("cells", VP)]
+
+
+class amr_domain(ctypes.Structure):
+    _fields_ = [("origin", c_double3), ("h0", c_double3), ("refine", ctypes.c_int32), ("nlevels", ctypes.c_int32)]
+
+
+class amr_tree_info(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in ("nodes", "leaves", "n_a", "n_b", "n_c", "depth", "empty_leaves",
+                                              "npatches")]
+
+
+class amr_node_host(ctypes.Structure):
+    _fields_ = [("axis", ctypes.c_int32), ("level", ctypes.c_int32), ("split", ctypes.c_int64),
+                ("patch", ctypes.c_int32), ("cover", ctypes.c_int32), ("kind", ctypes.c_int32),
+                ("pad_", ctypes.c_int32)]
+
+
+class amr_leaf_host(ctypes.Structure):
+    _fields_ = [("lo", c_int64_3), ("hi", c_int64_3), ("patch", ctypes.c_int32), ("level", ctypes.c_int32)]
+
+
+class amr_pack_opts(ctypes.Structure):
+    _fields_ = [("host_dst", ctypes.c_int32), ("nthreads", ctypes.c_int32), ("reserved_", ctypes.c_int32 * 6)]
+
+
+class amr_scene(ctypes.Structure):
+    _fields_ = [("pool", VP), ("nodes", VP), ("leaves", VP), ("patches", VP),
+                ("pool_bytes", ctypes.c_int64), ("meta_bytes", ctypes.c_int64),
+                ("nnodes", ctypes.c_int32), ("nleaves", ctypes.c_int32), ("npatches", ctypes.c_int32),
+                ("nlevels", ctypes.c_int32), ("lmax", ctypes.c_int32), ("refine", ctypes.c_int32),
+                ("depth", ctypes.c_int32), ("pad_", ctypes.c_int32),
+                ("box_lo", c_double3), ("box_hi", c_double3), ("origin", c_double3), ("h0", c_double3),
+                ("hfine", c_double3), ("step_fine", ctypes.c_double), ("v_min", ctypes.c_float),
+                ("v_max", ctypes.c_float)]
+
+
+class amr_camera(ctypes.Structure):
+    _fields_ = [("eye", c_double3), ("u", c_double3), ("v", c_double3), ("w", c_double3),
+                ("tan_half_fov", ctypes.c_double), ("win", ctypes.c_double * 2), ("ortho", ctypes.c_int32),
+                ("width", ctypes.c_int32), ("height", ctypes.c_int32), ("pad_", ctypes.c_int32)]
+
+
+class amr_trace_rec(ctypes.Structure):
+    _fields_ = [("leaf", ctypes.c_int32), ("patch", ctypes.c_int32), ("n", ctypes.c_int32),
+                ("level", ctypes.c_int32), ("ta", ctypes.c_double), ("tb", ctypes.c_double)]
+
+
+STATS_FIELDS = ("samples", "segments", "rays_hit", "tap_descents", "guard_hits", "trace_overflow",
+                "skipped_segments", "coarse_segments", "seglog_count", "ckpt_overflow")
+
+
+class amr_render_stats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint64) for n in STATS_FIELDS] + [("reserved_", ctypes.c_uint64 * 6)]
+
+
+class amr_render_params(ctypes.Structure):
+    _fields_ = [("d_lut", VP), ("v_lo", ctypes.c_float), ("v_hi", ctypes.c_float), ("step_frac", ctypes.c_float),
+                ("t_min", ctypes.c_float), ("uniform_step", ctypes.c_int32), ("lighting", ctypes.c_int32),
+                ("light", c_float3), ("k_a", ctypes.c_float), ("k_d", ctypes.c_float), ("eps_g", ctypes.c_float),
+                ("clip_lo", c_double3), ("clip_hi", c_double3),
+                ("d_trace", VP), ("d_trace_n", VP), ("d_nsamp", VP), ("trace_cap", ctypes.c_int64),
+                ("d_ckpt", VP), ("ckpt_bytes", ctypes.c_int64), ("ckpt_every", ctypes.c_int32),
+                ("ckpt_max", ctypes.c_int32),
+                ("d_mlp", VP), ("tau_e", ctypes.c_float), ("tau_s", ctypes.c_float),
+                ("d_seglog", VP), ("seglog_cap", ctypes.c_int64),
+                ("persistent", ctypes.c_int32), ("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32),
+                ("blocks_per_cu", ctypes.c_int32), ("flags_", ctypes.c_int32),
+                ("d_queue", VP), ("d_stamps", VP)]
+
+
+class amr_seglog_rec(ctypes.Structure):
+    _fields_ = [("feat", ctypes.c_float * MLP_IN), ("alpha_seg", ctypes.c_float), ("t_in", ctypes.c_float),
+                ("ray", ctypes.c_int32), ("n", ctypes.c_int32)]
+
+
+# every exported entry point declared in include/amr.h, with its signature
+SIGNATURES = {
+    "amr_last_error": (ctypes.c_char_p, []),
+    "amr_build_kdtree": (ctypes.c_int, [ctypes.POINTER(amr_domain), ctypes.POINTER(amr_patch), ctypes.c_int32,
+                                        ctypes.POINTER(VP)]),
+    "amr_tree_stats": (ctypes.c_int, [VP, ctypes.POINTER(amr_tree_info)]),
+    "amr_tree_export": (ctypes.c_int, [VP, VP, ctypes.c_size_t, VP, ctypes.c_size_t]),
+    "amr_tree_free": (None, [VP]),
+    "amr_pack_pool": (ctypes.c_int, [VP, ctypes.POINTER(amr_patch), ctypes.c_int32, ctypes.POINTER(amr_pack_opts),
+                                     VP, ctypes.POINTER(ctypes.c_int64), VP, ctypes.POINTER(ctypes.c_int64),
+                                     ctypes.POINTER(amr_scene), VP]),
+    "amr_render": (ctypes.c_int, [ctypes.POINTER(amr_scene), ctypes.POINTER(amr_camera), ctypes.c_int32,
+                                  ctypes.POINTER(amr_render_params), VP, VP, VP]),
+    "amr_queue_bytes": (ctypes.c_int64, [ctypes.c_int32]),
+    "amr_ckpt_bytes": (ctypes.c_int64, [ctypes.c_int64, ctypes.c_int32]),
+    "amr_render_backward": (ctypes.c_int, [ctypes.POINTER(amr_scene), ctypes.POINTER(amr_camera), ctypes.c_int32,
+                                           ctypes.POINTER(amr_render_params), VP, VP, VP, ctypes.c_int32, VP]),
+    "amr_mlp_param_count": (ctypes.c_int32, []),
+    "amr_mlp_forward": (ctypes.c_int, [VP, VP, VP, VP, ctypes.c_int64, VP]),
+    "amr_mlp_backward": (ctypes.c_int, [VP, VP, VP, VP, VP, ctypes.c_int64, ctypes.c_float, ctypes.c_float, VP, VP,
+                                        VP]),
+    "amr_mlp_adam_step": (ctypes.c_int, [VP, VP, VP, VP, ctypes.c_int32, ctypes.c_float, ctypes.c_float,
+                                         ctypes.c_float, ctypes.c_float, VP]),
+    "amr_mlp_packed_bytes": (ctypes.c_int64, []),
+    "amr_mlp_pack": (ctypes.c_int, [VP, VP, VP]),
+}
+
+_lib = None
+
+
+class AMRError(RuntimeError):
+    pass
+
+
+def load():
+    """Loads libamr.so (built in-tree by paper_1212_3333_amd.build). No fallback exists."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libamr.so is not built; run `python paper_1212_3333_amd/build.py`")
+    # torch first: the library resolves the HIP runtime to the copy torch has loaded
+    import torch  # noqa: F401
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def check(rc: int, what: str = ""):
+    if rc != AMR_OK:
+        msg = load().amr_last_error().decode(errors="replace")
+        raise AMRError("%s failed: %s (%s)" % (what, ERRNAMES.get(rc, rc), msg))

@@ -1,0 +1,50 @@
+// Internal layouts shared by the host library and the HIP kernels of libamr.
+#pragma once
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/amr.h"
+
+namespace amr {
+
+// Device tree node, 16 bytes, breadth-first order; the two children of an internal node are
+// adjacent (high = low + 1), as in the paper's implicit-sibling encoding (Section 4.2).
+struct DNode {
+    double split;      // internal: split plane in world coordinates (FP64, exact for dyadic grids)
+    uint32_t child;    // internal: index of the low child; leaf: leaf id
+    uint32_t meta;     // bits 0-1 axis (3 = leaf), bits 2-7 level
+};
+static_assert(sizeof(DNode) == 16, "DNode layout");
+
+// Leaf record, 64 bytes: world box (for gradient-tap containment tests), owning patch,
+// level, and the value range of the leaf's cells plus one halo cell.
+struct DLeaf {
+    double lo[3], hi[3];
+    int32_t patch, level;
+    float vmin, vmax;
+};
+static_assert(sizeof(DLeaf) == 64, "DLeaf layout");
+
+// Patch header, 128 bytes.
+struct DPatch {
+    uint64_t off;        // first float of the padded brick in the pool
+    int32_t n[3];        // interior cells per axis (brick is n+2 per axis, x fastest)
+    int32_t level;
+    double lo[3];        // world lower corner of the interior
+    double inv_h[3];     // 1 / h^l
+    double h[3];         // h^l
+    double step;         // min_a h^l_a
+    float vmin, vmax;
+    int32_t pad_[4];
+};
+static_assert(sizeof(DPatch) == 128, "DPatch layout");
+
+constexpr uint32_t kLeafAxis = 3u;
+
+inline uint32_t node_meta(int axis, int level) { return (uint32_t)(axis & 3) | ((uint32_t)(level & 63) << 2); }
+
+void set_error(const char *fmt, ...);
+
+}  // namespace amr

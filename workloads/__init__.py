@@ -171,15 +171,18 @@ def random_tiny(seed: int, max_patches: int = 6, nlevels: int = 3, refine: int |
     else:
         ps.append(_empty_patch(0, [0, 0, 0], [root_cells] * 3))
     count = len(ps)
+    B_lo = np.min([p.lo for p in ps], axis=0)
+    B_hi = np.max([p.hi for p in ps], axis=0)
     for lev in range(1, nlevels):
         n_here = rng.integers(1, 3)
         ncell = root_cells * r ** lev
+        blo, bhi = B_lo * r ** lev, B_hi * r ** lev        # patches stay inside B
         boxes = [(p.lo, p.hi) for p in ps if p.level == lev]
         tries = 0
         while n_here > 0 and count < max_patches and tries < 200:
             tries += 1
-            ext = rng.integers(1, max(2, ncell // 2) + 1, 3)
-            lo = np.array([rng.integers(0, ncell - e + 1) for e in ext])
+            ext = np.minimum(rng.integers(1, max(2, ncell // 2) + 1, 3), bhi - blo)
+            lo = np.array([rng.integers(blo[a], bhi[a] - ext[a] + 1) for a in range(3)])
             hi = lo + ext
             if all(_disjoint(lo, hi, b0, b1) for b0, b1 in boxes):
                 boxes.append((lo, hi))
@@ -294,3 +297,137 @@ def config1(seed: int = 0):
     h = tiny_samr(seed)
     vmax = float(max(p.cells.max() for p in h.patches))
     return h, lut_config1(seed), config1_cameras(), default_params(v_lo=0.0, v_hi=vmax)
+
+
+# ----------------------------------------------------------------------------------------------
+# Cosmology-like hierarchy: log-normal density, patches around density peaks
+# ----------------------------------------------------------------------------------------------
+
+class LogNormalField:
+    """rho = exp(s g - s^2/2), g a unit-variance Gaussian random field made of K Fourier modes
+    with |k| log-uniform in [2 pi, 2 pi kmax] (mode density per log k is flat, i.e. a k^-3
+    power spectrum), random directions and phases.  Evaluated separably on lattices."""
+
+    def __init__(self, rng: np.random.Generator, K: int = 64, sigma_ln: float = 2.0, kmax: float = 2048.0):
+        self.K, self.s = K, sigma_ln
+        kmag = 2 * math.pi * np.exp(rng.uniform(0.0, math.log(kmax), K))
+        dirs = rng.normal(size=(K, 3))
+        dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+        self.k = kmag[:, None] * dirs
+        self.phi = rng.uniform(0, 2 * math.pi, K)
+        self.amp = math.sqrt(2.0 / K)
+
+    def g_lattice(self, xs, ys, zs) -> np.ndarray:
+        ex = np.exp(1j * np.outer(self.k[:, 0], xs))
+        ey = np.exp(1j * np.outer(self.k[:, 1], ys))
+        ez = np.exp(1j * (np.outer(self.k[:, 2], zs) + self.phi[:, None]))
+        m = (ey[:, :, None] * ex[:, None, :]).reshape(self.K, -1)
+        return (ez.T @ m).real.reshape(len(zs), len(ys), len(xs)) * self.amp
+
+    def rho_lattice(self, xs, ys, zs) -> np.ndarray:
+        return np.exp(self.s * self.g_lattice(xs, ys, zs) - 0.5 * self.s * self.s)
+
+
+def _fill_cells(h: Hierarchy, fn_lattice) -> Hierarchy:
+    for p in h.patches:
+        x, y, z = h.cell_centres(p)
+        p.cells = np.ascontiguousarray(fn_lattice(x, y, z), dtype=np.float32)
+    return h
+
+
+def cosmology_like(seed: int = 0, root: int = 128, nlevels: int = 6, target_patches: int = 2000,
+                   root_split: int = 2, sides=(8, 16, 32, 64), side_probs=(0.01, 0.02, 0.07, 0.90),
+                   weights=(0.04, 0.12, 0.22, 0.30, 0.32), min_cover: float = 0.5) -> Hierarchy:
+    """Config 2 geometry: root `root`^3 on [0,1]^3 split into root_split^3 level-0 patches,
+    r = 2.  Level l patches sit on a grid of 64/32/16/8-cell blocks shifted by a random even
+    offset (so they span several parents).  Parent cells are visited densest first; for each,
+    a side is drawn from `sides` with `side_probs` and the aligned block of that side holding
+    the cell is taken if it is free and at least `min_cover` of it lies inside the union of the
+    level-(l-1) patches (relaxed nesting), else the side is halved.  Each level stops at its
+    `weights` share of `target_patches`."""
+    rng = _rng(1, "patches", MASTER_SEED + seed)
+    field = LogNormalField(_rng(1, "field", MASTER_SEED + seed))
+    rs = root // root_split
+    ps = [_empty_patch(0, [i * rs, j * rs, k * rs], [rs, rs, rs])
+          for k in range(root_split) for j in range(root_split) for i in range(root_split)]
+    h = Hierarchy(np.zeros(3), np.full(3, 1.0 / root), 2, nlevels, ps)
+    _fill_cells(h, field.rho_lattice)
+    w = np.asarray(weights[: nlevels - 1], dtype=np.float64)
+    w = w / w.sum()
+    big = max(sides)
+    for lev in range(1, nlevels):
+        n_l = root * 2 ** lev
+        parents = [p for p in h.patches if p.level == lev - 1]
+        plo = np.array([2 * p.lo for p in parents])
+        phi = np.array([2 * p.hi for p in parents])
+        want = int(round(target_patches * w[lev - 1]))
+        off = rng.integers(0, big // 2, 3) * 2
+        vals = np.concatenate([p.cells.reshape(-1) for p in parents])
+        owner = np.concatenate([np.full(p.cells.size, k, dtype=np.int32) for k, p in enumerate(parents)])
+        first = np.cumsum([0] + [p.cells.size for p in parents])
+        m = min(len(vals), 400 * want)
+        top = np.argpartition(-vals, m - 1)[:m]
+        top = top[np.argsort(-vals[top], kind="stable")]
+        taken = set()
+        boxes = []
+        for t in top:
+            if len(boxes) >= want:
+                break
+            p = parents[owner[t]]
+            li = int(t - first[owner[t]])
+            nx, ny = int(p.dims[0]), int(p.dims[1])
+            c = 2 * (p.lo + np.array([li % nx, (li // nx) % ny, li // (nx * ny)])) - off
+            if tuple(c // 8) in taken:
+                continue
+            side = int(rng.choice(sides, p=side_probs))
+            while side >= sides[0]:
+                blo = c // side * side
+                cells8 = [tuple(blo // 8 + np.array([a, b, d])) for d in range(side // 8)
+                          for b in range(side // 8) for a in range(side // 8)]
+                glo, ghi = np.maximum(blo + off, 0), np.minimum(blo + off + side, n_l)
+                vol = int(np.prod(ghi - glo))
+                inter = np.prod(np.clip(np.minimum(ghi, phi) - np.maximum(glo, plo), 0, None), axis=1).sum()
+                if vol > 0 and inter >= min_cover * vol and not any(x in taken for x in cells8):
+                    taken.update(cells8)
+                    boxes.append((glo, ghi))
+                    break
+                side //= 2
+        for glo, ghi in boxes:
+            q = _empty_patch(lev, glo, ghi - glo)
+            x, y, z = h.cell_centres(q)
+            q.cells = np.ascontiguousarray(field.rho_lattice(x, y, z), dtype=np.float32)
+            h.patches.append(q)
+    return h
+
+
+def straddle_fraction(h: Hierarchy, level: int) -> float:
+    """Fraction of level-`level` patches overlapping two or more level-(level-1) patches."""
+    boxes = h.boxes_finest()
+    par = boxes[boxes[:, 0] == level - 1]
+    cnt, n = 0, 0
+    for b in boxes[boxes[:, 0] == level]:
+        ov = np.all(np.minimum(b[4:7], par[:, 4:7]) > np.maximum(b[1:4], par[:, 1:4]), axis=1)
+        cnt += int(ov.sum() >= 2)
+        n += 1
+    return cnt / max(n, 1)
+
+
+def lut_cosmology(seed: int = 0) -> np.ndarray:
+    rng = _rng(1, "lut", MASTER_SEED + seed)
+    lut = lut_bumps(rng, sigma_scale=1.0)
+    u = np.arange(256) / 255.0
+    lut[:, 3] = (0.4 + 60.0 * u).astype(np.float32)
+    return lut
+
+
+def config2(seed: int = 0, width: int = 1024, height: int = 1024):
+    """Cosmology-like workload: hierarchy, LUT, 1024^2 perspective orbit camera, lit params."""
+    h = cosmology_like(seed)
+    rng = _rng(1, "cameras", MASTER_SEED + seed)
+    az = float(rng.uniform(0, 2 * math.pi))
+    el = float(rng.uniform(-0.5, 0.5))
+    cam = perspective_orbit(width, height, az, el, radius=2.0, fov_deg=40.0)
+    sample = np.concatenate([p.cells.reshape(-1)[:: max(1, p.cells.size // 4096)] for p in h.patches])
+    vhi = float(np.float32(np.percentile(sample.astype(np.float64), 99.9)))
+    prm = default_params(v_lo=0.0, v_hi=vhi, lighting=True, light=(1.0, 1.0, 1.0), k_a=0.3, k_d=0.7)
+    return h, lut_cosmology(seed), cam, prm
