@@ -201,7 +201,13 @@ typedef struct {
     int32_t blocks_per_cu;              /* persistent grid = 256 CUs x this (0 = default) */
     int32_t flags_;
     void *d_queue;                      /* persistent: device scratch, >= amr_queue_bytes(ncams) */
-    unsigned long long *d_stamps;       /* persistent: per-image completion clock (optional) */
+    unsigned long long *d_stamps;       /* persistent: [ncams + 1] device clock when each image
+                                           completed, then the launch start (optional) */
+    const amr_camera *d_cams;           /* persistent: device copy of `cams` (read by the kernel,
+                                           so a captured graph can be replayed with new cameras) */
+    /* measurement (device, NULL to skip): one bit per pool float, set for every cell a sample
+       or gradient tap reads; its population count gives a frame's compulsory pool bytes */
+    uint32_t *d_touch;
 } amr_render_params;
 
 /* Renders ncams cameras (host array) into d_rgba (device, premultiplied RGBA fp32, images
@@ -210,8 +216,14 @@ typedef struct {
 int amr_render(const amr_scene *scene, const amr_camera *cams, int32_t ncams,
                const amr_render_params *params, float *d_rgba, amr_render_stats *d_stats, void *stream);
 
+/* Persistent mode (params.persistent = 1): one launch renders all cameras; waves take 64-pixel
+ * tiles (tile_w x tile_h) from a device queue ordered largest image first; the launch and its
+ * setup are device-only work, so the call may be captured in a hipGraph.  Needs d_queue and
+ * d_cams; images are identical to the non-persistent path's. */
 /* Bytes of device scratch the persistent batched kernel needs for ncams cameras. */
 int64_t amr_queue_bytes(int32_t ncams);
+/* Rate of the device clock written to d_stamps, in kHz. */
+int64_t amr_wall_clock_khz(void);
 
 /* Checkpoint buffer bytes for nrays rays with ckpt_max checkpoints each. */
 int64_t amr_ckpt_bytes(int64_t nrays, int32_t ckpt_max);

@@ -149,8 +149,8 @@ class Scene:
         return self._records(self.scene.patches, dt, self.scene.npatches)
 
     def leaf_records(self) -> np.ndarray:
-        dt = np.dtype([("lo", np.float64, 3), ("hi", np.float64, 3), ("patch", np.int32), ("level", np.int32),
-                       ("vmin", np.float32), ("vmax", np.float32)])
+        dt = np.dtype([("lo", np.float64, 3), ("hi", np.float64, 3), ("patch", np.int32),
+                       ("level_flags", np.uint32), ("vmin", np.float32), ("vmax", np.float32)])
         return self._records(self.scene.leaves, dt, self.scene.nleaves)
 
     def node_records(self) -> np.ndarray:
@@ -236,7 +236,7 @@ def render(scene: Scene, cams, lut: torch.Tensor, params: dict, trace_cap: int =
         res["nsamp"] = ns
     st = torch.zeros(16, dtype=torch.int64, device=dev) if stats else None
     for k in ("d_ckpt", "ckpt_bytes", "ckpt_every", "ckpt_max", "d_mlp", "d_seglog", "seglog_cap", "d_queue",
-              "d_stamps"):
+              "d_stamps", "d_touch", "d_cams"):
         if k in extra:
             v = extra[k]
             setattr(q, k, v.data_ptr() if isinstance(v, torch.Tensor) else v)
@@ -247,6 +247,62 @@ def render(scene: Scene, cams, lut: torch.Tensor, params: dict, trace_cap: int =
         res["stats_raw"] = st
     res["_keep"] = (lut, carr, q)
     return res
+
+
+# ----------------------------------------------------------------------------------------------
+# Proposal network (training runs on the GPU through the library's kernels)
+# ----------------------------------------------------------------------------------------------
+
+def mlp_param_count() -> int:
+    return int(load().amr_mlp_param_count())
+
+
+def mlp_forward(X: torch.Tensor, W: torch.Tensor, keep_hidden: bool = True):
+    """Y [n,2] = (alpha_lo, alpha_hi) and, if keep_hidden, the activations H [n,128]."""
+    lib = load()
+    n = X.shape[0]
+    Y = torch.empty((n, 2), dtype=torch.float32, device=X.device)
+    H = torch.empty((n, 128), dtype=torch.float32, device=X.device) if keep_hidden else None
+    check(lib.amr_mlp_forward(_vp(X), _vp(W), _vp(Y), _vp(H), n, _stream(X.device)), "amr_mlp_forward")
+    return Y, H
+
+
+def mlp_backward(X, W, H, Y, T, q_lo=0.01, q_hi=0.99):
+    """(dW, loss) of the mean pinball loss."""
+    lib = load()
+    dW = torch.empty_like(W)
+    loss = torch.empty(1, dtype=torch.float32, device=W.device)
+    check(lib.amr_mlp_backward(_vp(X), _vp(W), _vp(H), _vp(Y), _vp(T), X.shape[0], q_lo, q_hi, _vp(dW), _vp(loss),
+                               _stream(W.device)), "amr_mlp_backward")
+    return dW, loss
+
+
+def mlp_adam_step(W, dW, M, V, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    check(load().amr_mlp_adam_step(_vp(W), _vp(dW), _vp(M), _vp(V), int(t), lr, beta1, beta2, eps, _stream(W.device)),
+          "amr_mlp_adam_step")
+
+
+def mlp_pack(W: torch.Tensor) -> torch.Tensor:
+    """fp16 inference image of the network, for params d_mlp."""
+    lib = load()
+    out = torch.empty(int(lib.amr_mlp_packed_bytes()), dtype=torch.uint8, device=W.device)
+    check(lib.amr_mlp_pack(_vp(W), _vp(out), _stream(W.device)), "amr_mlp_pack")
+    return out
+
+
+def camera_table(cams, device="cuda") -> torch.Tensor:
+    """Device copy of a camera list (amr_camera records) for persistent rendering."""
+    _, carr = _cams(cams)
+    raw = np.frombuffer(bytes(carr), dtype=np.uint8).copy()
+    return torch.from_numpy(raw).to(device)
+
+
+def queue_buffer(ncams: int, device="cuda") -> torch.Tensor:
+    return torch.zeros(int(load().amr_queue_bytes(ncams)), dtype=torch.uint8, device=device)
+
+
+def wall_clock_khz() -> int:
+    return int(load().amr_wall_clock_khz())
 
 
 def trace_records(res: RenderOutput) -> np.ndarray:
@@ -262,9 +318,64 @@ def stats_dict(res: RenderOutput) -> dict:
     return {k: int(v[i]) for i, k in enumerate(L.STATS_FIELDS)}
 
 
-def render_backward(*args, **kwargs):
-    raise NotImplementedError("defined below once the adjoint is available")
+class Checkpoints:
+    """Device buffer the checkpointed forward fills and the adjoint reads: per ray a header
+    (final T and C, samples, checkpoint count) and up to ckpt_max (t, T, C) records taken at the
+    start of every ckpt_every-th data segment (the rate halves when a ray runs out of slots)."""
+
+    def __init__(self, nrays: int, device, ckpt_every: int = 4, ckpt_max: int = 16):
+        self.nbytes = int(load().amr_ckpt_bytes(nrays, ckpt_max))
+        self.buf = torch.empty(self.nbytes, dtype=torch.uint8, device=device)
+        self.every, self.max = int(ckpt_every), int(ckpt_max)
+
+    def params(self) -> dict:
+        return dict(d_ckpt=self.buf, ckpt_bytes=self.nbytes, ckpt_every=self.every, ckpt_max=self.max)
+
+
+def render_checkpointed(scene: Scene, cams, lut: torch.Tensor, params: dict, ckpt_every: int = 4,
+                        ckpt_max: int = 16, **kw):
+    """Forward render that also records the adjoint's checkpoints. Returns (RenderOutput, Checkpoints)."""
+    cam_list = [cams] if isinstance(cams, dict) else list(cams)
+    npix = sum(int(c["width"]) * int(c["height"]) for c in cam_list)
+    ck = Checkpoints(npix, scene.pool.device, ckpt_every, ckpt_max)
+    out = render(scene, cams, lut, params, **ck.params(), **kw)
+    return out, ck
+
+
+def render_backward(scene: Scene, cams, lut: torch.Tensor, params: dict, ckpt: Checkpoints,
+                    grad_rgba: torch.Tensor, deterministic: bool = False):
+    """dL/dLUT [256,4] and dL/d(light_x, light_y, light_z, k_a, k_d) [5] from dL/dRGBA, using the
+    checkpoints of the matching forward call (amr_render_backward)."""
+    lib = load()
+    dev = scene.pool.device
+    cam_list, carr = _cams(cams)
+    lut = lut.to(device=dev, dtype=torch.float32).contiguous()
+    g = grad_rgba.to(device=dev, dtype=torch.float32).contiguous()
+    q = make_params(params, lut)
+    q.d_ckpt, q.ckpt_bytes, q.ckpt_every, q.ckpt_max = ckpt.buf.data_ptr(), ckpt.nbytes, ckpt.every, ckpt.max
+    glut = torch.empty((256, 4), dtype=torch.float32, device=dev)
+    glight = torch.empty(5, dtype=torch.float32, device=dev)
+    check(lib.amr_render_backward(ctypes.byref(scene.scene), carr, len(cam_list), ctypes.byref(q), _vp(g), _vp(glut),
+                                  _vp(glight), int(bool(deterministic)), _stream(dev)), "amr_render_backward")
+    return glut, glight
 
 
 class AMRRender(torch.autograd.Function):
-    """Placeholder; the adjoint binding replaces it."""
+    """Differentiable render: rgba = AMRRender.apply(lut [256,4], shading [5] = (light xyz, k_a,
+    k_d), scene, cams, params).  Gradients flow to the LUT and the shading parameters through
+    the library's adjoint kernel; the forward keeps segment checkpoints, not samples."""
+
+    @staticmethod
+    def forward(ctx, lut, shading, scene, cams, params, ckpt_every=4, ckpt_max=16, deterministic=False):
+        sh = shading.detach().double().cpu().tolist()
+        prm = dict(params, light=tuple(sh[:3]), k_a=sh[3], k_d=sh[4])
+        out, ck = render_checkpointed(scene, cams, lut.detach(), prm, ckpt_every, ckpt_max)
+        ctx.scene, ctx.cams, ctx.prm, ctx.ck, ctx.det = scene, cams, prm, ck, deterministic
+        ctx.lut = lut.detach().to(device=scene.pool.device, dtype=torch.float32).contiguous()
+        ctx.lut_device, ctx.sh_device = lut.device, shading.device
+        return out["rgba"].clone()
+
+    @staticmethod
+    def backward(ctx, grad_rgba):
+        glut, glight = render_backward(ctx.scene, ctx.cams, ctx.lut, ctx.prm, ctx.ck, grad_rgba, ctx.det)
+        return glut.to(ctx.lut_device), glight.to(ctx.sh_device), None, None, None, None, None, None

@@ -91,7 +91,7 @@ class amr_render_params(ctypes.Structure):
                 ("d_seglog", VP), ("seglog_cap", ctypes.c_int64),
                 ("persistent", ctypes.c_int32), ("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32),
                 ("blocks_per_cu", ctypes.c_int32), ("flags_", ctypes.c_int32),
-                ("d_queue", VP), ("d_stamps", VP)]
+                ("d_queue", VP), ("d_stamps", VP), ("d_cams", VP), ("d_touch", VP)]
 
 
 class amr_seglog_rec(ctypes.Structure):
@@ -113,6 +113,7 @@ SIGNATURES = {
     "amr_render": (ctypes.c_int, [ctypes.POINTER(amr_scene), ctypes.POINTER(amr_camera), ctypes.c_int32,
                                   ctypes.POINTER(amr_render_params), VP, VP, VP]),
     "amr_queue_bytes": (ctypes.c_int64, [ctypes.c_int32]),
+    "amr_wall_clock_khz": (ctypes.c_int64, []),
     "amr_ckpt_bytes": (ctypes.c_int64, [ctypes.c_int64, ctypes.c_int32]),
     "amr_render_backward": (ctypes.c_int, [ctypes.POINTER(amr_scene), ctypes.POINTER(amr_camera), ctypes.c_int32,
                                            ctypes.POINTER(amr_render_params), VP, VP, VP, ctypes.c_int32, VP]),

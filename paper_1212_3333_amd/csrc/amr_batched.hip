@@ -1,0 +1,256 @@
+// Persistent multi-camera raycasting: one launch renders many cameras of different sizes.
+//
+// Work unit: a 64-pixel tile (tile_w x tile_h) rendered by one wave, one ray per lane, with
+// the per-ray code of the single-camera kernel.  Waves take tiles from one global atomic
+// queue that lists the cameras largest first, so the short images of a batch fill the tail of
+// the long ones.  The wave that finishes an image's last tile writes the device clock into
+// stamps[camera]; the wave that takes tile 0 writes stamps[ncams] (launch start).  Everything
+// the launch needs (queue reset, camera order, tile prefix sums) is computed on the device
+// from the device camera table, so the sequence can be captured in a hipGraph and replayed.
+#include <hip/hip_runtime.h>
+
+#include "amr_render_common.h"
+
+namespace amr {
+
+// Queue scratch layout (amr_queue_bytes): counters first, then per-camera tables.
+struct QueueView {
+    unsigned int *next;          // [1] next tile to hand out
+    unsigned int *done;          // [ncams] tiles finished per camera
+    int *order;                  // [ncams] cameras, largest first
+    long long *tile0;            // [ncams + 1] first tile of the k-th camera in `order`
+    long long *pix0;             // [ncams] first pixel of camera c in the rgba output
+    int *tiles_x;                // [ncams]
+};
+
+__host__ __device__ __forceinline__ QueueView queue_view(void *base, int ncams) {
+    char *p = (char *)base;
+    QueueView q;
+    q.next = (unsigned int *)p;
+    p += 256;
+    q.done = (unsigned int *)p;
+    p += ((4 * ncams + 255) / 256) * 256;
+    q.order = (int *)p;
+    p += ((4 * ncams + 255) / 256) * 256;
+    q.tile0 = (long long *)p;
+    p += ((8 * (ncams + 1) + 255) / 256) * 256;
+    q.pix0 = (long long *)p;
+    p += ((8 * ncams + 255) / 256) * 256;
+    q.tiles_x = (int *)p;
+    return q;
+}
+
+inline int64_t queue_bytes(int ncams) {
+    return 256 + 2 * ((4 * (int64_t)ncams + 255) / 256) * 256 + ((8 * ((int64_t)ncams + 1) + 255) / 256) * 256 +
+           ((8 * (int64_t)ncams + 255) / 256) * 256 + ((4 * (int64_t)ncams + 255) / 256) * 256;
+}
+
+// One thread: reset the queue, order cameras by pixel count (descending, ties by index) and
+// build the tile and pixel prefix tables.
+__global__ void queue_setup(const amr_camera *cams, int ncams, void *qbase, int tw, int th,
+                            unsigned long long *stamps) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    QueueView q = queue_view(qbase, ncams);
+    *q.next = 0u;
+    long long pix = 0;
+    for (int c = 0; c < ncams; c++) {
+        q.done[c] = 0u;
+        q.order[c] = c;
+        q.pix0[c] = pix;
+        pix += (long long)cams[c].width * cams[c].height;
+        q.tiles_x[c] = (cams[c].width + tw - 1) / tw;
+        if (stamps) stamps[c] = 0ull;
+    }
+    if (stamps) stamps[ncams] = 0ull;
+    for (int i = 1; i < ncams; i++) {          // insertion sort, largest image first
+        int c = q.order[i];
+        long long sz = (long long)cams[c].width * cams[c].height;
+        int j = i - 1;
+        while (j >= 0 && (long long)cams[q.order[j]].width * cams[q.order[j]].height < sz) {
+            q.order[j + 1] = q.order[j];
+            j--;
+        }
+        q.order[j + 1] = c;
+    }
+    long long t = 0;
+    for (int k = 0; k < ncams; k++) {
+        q.tile0[k] = t;
+        int c = q.order[k];
+        t += (long long)q.tiles_x[c] * ((cams[c].height + th - 1) / th);
+    }
+    q.tile0[ncams] = t;
+}
+
+struct BatchArgs {
+    RenderArgs base;                 // scene, LUT and shading parameters; camera fields unused
+    const amr_camera *cams;          // device camera table
+    int ncams, tw, th;
+    void *queue;
+    unsigned long long *stamps;
+};
+
+__device__ __forceinline__ void set_camera(RenderArgs &A, const amr_camera &C) {
+    for (int a = 0; a < 3; a++) {
+        A.eye[a] = C.eye[a];
+        A.u[a] = C.u[a];
+        A.v[a] = C.v[a];
+        A.w[a] = C.w[a];
+    }
+    A.tanf = C.tan_half_fov;
+    A.win0 = C.win[0];
+    A.win1 = C.win[1];
+    A.ortho = C.ortho;
+    A.width = C.width;
+    A.height = C.height;
+}
+
+template <bool LIT, bool REC>
+__global__ __launch_bounds__(256) void render_batched(BatchArgs B) {
+    __shared__ float4 s_lut[256];
+    s_lut[threadIdx.x] = B.base.lut[threadIdx.x];
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    QueueView q = queue_view(B.queue, B.ncams);
+    const long long total = q.tile0[B.ncams];
+    Counters cnt;
+    RenderArgs A = B.base;
+    while (true) {
+        unsigned int tile = 0;
+        if (lane == 0) tile = atomicAdd(q.next, 1u);
+        tile = __shfl(tile, 0, 64);
+        if ((long long)tile >= total) break;           // every wave leaves once the queue is empty
+        if (tile == 0 && lane == 0 && B.stamps) B.stamps[B.ncams] = wall_clock64();
+        int k = 0;                                     // camera slot: largest k with tile0[k] <= tile
+        int lo = 0, hi = B.ncams - 1;
+        while (lo < hi) {
+            int mid = (lo + hi + 1) >> 1;
+            if (q.tile0[mid] <= (long long)tile) lo = mid;
+            else hi = mid - 1;
+        }
+        k = lo;
+        const int c = q.order[k];
+        const amr_camera C = B.cams[c];
+        set_camera(A, C);
+        const long long local = (long long)tile - q.tile0[k];
+        const int txs = q.tiles_x[c];
+        const int tx = (int)(local % txs), ty = (int)(local / txs);
+        const int pi = tx * B.tw + lane % B.tw;
+        const int pj = ty * B.th + lane / B.tw;
+        const bool valid = pi < C.width && pj < C.height;
+        float C0 = 0.f, C1 = 0.f, C2 = 0.f, T = 1.f;
+        int nsamp_total = 0;
+        Ray R;
+        bool alive = valid && setup_ray(A, pi, pj, R);
+        if (REC) cnt.hit += alive ? 1 : 0;
+        double tcur = R.t0;
+        while (alive && tcur < R.t1) {
+            double tb = R.t1;
+            int leaf = descend(A, R, tcur, tb);
+            if (leaf < 0) break;
+            if (REC) cnt.segments++;
+            const DLeaf &L = A.leaves[leaf];
+            if (L.patch >= 0) {
+                Segment S;
+                setup_segment<LIT>(A, R, L, leaf, tcur, tb, S);
+                for (int k2 = 0; k2 < S.n; k2++) {
+                    SampleVals v;
+                    eval_sample<LIT, REC>(A, s_lut, R, S, k2, v, cnt);
+                    float wgt = T * v.alpha * v.shade;
+                    C0 += wgt * v.r;
+                    C1 += wgt * v.g;
+                    C2 += wgt * v.b;
+                    T *= 1.f - v.alpha;
+                    nsamp_total++;
+                    if (T < A.t_min) { alive = false; break; }
+                }
+            }
+            if (tb <= tcur) {
+                if (REC) cnt.guard++;
+                tb = nextafter(tcur, INFINITY);
+            }
+            tcur = tb;
+        }
+        if (REC) cnt.samples += nsamp_total;
+        if (valid) reinterpret_cast<float4 *>(B.base.rgba)[q.pix0[c] + (long long)pj * C.width + pi] =
+            make_float4(C0, C1, C2, 1.f - T);
+        // completion: the wave that finishes the image's last tile stamps it
+        __threadfence();
+        if (lane == 0) {
+            unsigned int ntiles = (unsigned int)(q.tile0[k + 1] - q.tile0[k]);
+            unsigned int d = atomicAdd(&q.done[c], 1u) + 1u;
+            if (d == ntiles && B.stamps) B.stamps[c] = wall_clock64();
+        }
+    }
+    if (REC && B.base.stats) flush_counters(B.base.stats, cnt, lane);
+}
+
+__global__ void zero_stats(unsigned long long *p, int n) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0ull;
+}
+
+// Compute units of the current device (queried once per device).
+static int device_cus() {
+    static int cached[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    if (!cached[dev]) {
+        int n = 0;
+        cached[dev] = hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0 ? n : 256;
+    }
+    return cached[dev];
+}
+
+int launch_persistent(const amr_scene *S, const amr_camera *cams, int32_t ncams, const amr_render_params *P,
+                      float *d_rgba, amr_render_stats *d_stats, void *stream) {
+    if (!P->d_queue || !P->d_cams) {
+        set_error("persistent mode needs params.d_queue (amr_queue_bytes) and params.d_cams (device cameras)");
+        return AMR_EINVAL;
+    }
+    if (P->d_trace || P->d_ckpt || P->d_nsamp || P->d_touch) {
+        set_error("persistent mode renders images only (no trace, checkpoints, sample counts or touch map)");
+        return AMR_EINVAL;
+    }
+    int tw = P->tile_w > 0 ? P->tile_w : 8, th = P->tile_h > 0 ? P->tile_h : 8;
+    if (tw * th != 64) { set_error("tile_w * tile_h must be 64 (one wave)"); return AMR_EINVAL; }
+    BatchArgs B;
+    int rc = fill_args(S, &cams[0], P, &B.base);   // scene/LUT/shading; camera fields come per tile
+    if (rc) return rc;
+    for (int c = 0; c < ncams; c++)
+        if (cams[c].width <= 0 || cams[c].height <= 0) { set_error("camera %d has no pixels", c); return AMR_EINVAL; }
+    B.base.rgba = d_rgba;
+    B.base.stats = d_stats;
+    B.cams = P->d_cams;
+    B.ncams = ncams;
+    B.tw = tw;
+    B.th = th;
+    B.queue = P->d_queue;
+    B.stamps = P->d_stamps;
+    hipStream_t s = (hipStream_t)stream;
+    if (d_stats)
+        hipLaunchKernelGGL(zero_stats, dim3(1), dim3(64), 0, s, (unsigned long long *)d_stats,
+                           (int)(sizeof(amr_render_stats) / 8));
+    hipLaunchKernelGGL(queue_setup, dim3(1), dim3(64), 0, s, P->d_cams, ncams, P->d_queue, tw, th, P->d_stamps);
+    int bpc = P->blocks_per_cu > 0 ? P->blocks_per_cu : 4;
+    dim3 grid(device_cus() * bpc);
+    const bool rec = d_stats != nullptr;
+    if (B.base.lighting) {
+        if (rec) hipLaunchKernelGGL((render_batched<true, true>), grid, dim3(256), 0, s, B);
+        else hipLaunchKernelGGL((render_batched<true, false>), grid, dim3(256), 0, s, B);
+    } else {
+        if (rec) hipLaunchKernelGGL((render_batched<false, true>), grid, dim3(256), 0, s, B);
+        else hipLaunchKernelGGL((render_batched<false, false>), grid, dim3(256), 0, s, B);
+    }
+    return check_hip(hipGetLastError(), "render_batched launch");
+}
+
+}  // namespace amr
+
+extern "C" int64_t amr_queue_bytes(int32_t ncams) { return ncams > 0 ? amr::queue_bytes(ncams) : 0; }
+
+extern "C" int64_t amr_wall_clock_khz(void) {
+    int dev = 0, khz = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess) return 0;
+    return khz;
+}

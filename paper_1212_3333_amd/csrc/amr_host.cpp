@@ -511,6 +511,35 @@ struct Packer {
     }
 };
 
+// Bit 2a+side is set when the one-cell slab (cells of the leaf's level) beyond that face lies
+// inside the leaf's patch and every leaf meeting it belongs to the same patch.
+uint32_t face_safe_mask(const amr_tree *T, const Node &lf) {
+    if (lf.patch < 0) return 0;
+    const Box &pb = T->pbox[lf.patch];
+    const int64_t S = T->scale[T->plevel[lf.patch]];
+    uint32_t mask = 0;
+    std::vector<int> stack;
+    for (int a = 0; a < 3; a++)
+        for (int side = 0; side < 2; side++) {
+            int64_t lo[3] = {lf.lo[0], lf.lo[1], lf.lo[2]}, hi[3] = {lf.hi[0], lf.hi[1], lf.hi[2]};
+            if (side) { lo[a] = lf.hi[a]; hi[a] = lf.hi[a] + S; }
+            else { lo[a] = lf.lo[a] - S; hi[a] = lf.lo[a]; }
+            bool ok = true;
+            for (int b = 0; b < 3; b++) ok = ok && lo[b] >= pb.lo[b] && hi[b] <= pb.hi[b];
+            stack.assign(1, 0);
+            while (ok && !stack.empty()) {
+                int i = stack.back();
+                stack.pop_back();
+                const Node &n = T->nodes[i];
+                if (!box_overlap(n.lo, n.hi, lo, hi)) continue;
+                if (n.axis < 0) ok = n.patch == lf.patch;
+                else { stack.push_back(n.low); stack.push_back(n.high); }
+            }
+            if (ok) mask |= 1u << (2 * a + side);
+        }
+    return mask;
+}
+
 double world_plane(const amr_tree *T, int a, int64_t G) {
     double g = (double)G;
     double hf = T->dom.h0[a] / (double)T->scale[0];
@@ -699,7 +728,7 @@ int amr_pack_pool(const amr_tree *T, const amr_patch *patches, int32_t npatches,
             DLeaf &L = dl[k];
             for (int a = 0; a < 3; a++) { L.lo[a] = world_plane(T, a, n.lo[a]); L.hi[a] = world_plane(T, a, n.hi[a]); }
             L.patch = n.patch;
-            L.level = n.level;
+            L.level_flags = (uint32_t)n.level | (face_safe_mask(T, n) << 8);
             L.vmin = 0.0f;
             L.vmax = 0.0f;
             if (n.patch >= 0) {

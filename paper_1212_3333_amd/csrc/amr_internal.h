@@ -19,10 +19,14 @@ struct DNode {
 static_assert(sizeof(DNode) == 16, "DNode layout");
 
 // Leaf record, 64 bytes: world box (for gradient-tap containment tests), owning patch,
-// level, and the value range of the leaf's cells plus one halo cell.
+// level (bits 0-7) with six face flags (bits 8-13, face 2a+side): a face is "safe" when the
+// one-cell slab beyond it lies inside the leaf's patch and holds no finer data, so a gradient
+// tap crossing it reads the same brick.  vmin/vmax: value range of the leaf's cells plus one
+// halo cell.
 struct DLeaf {
     double lo[3], hi[3];
-    int32_t patch, level;
+    int32_t patch;
+    uint32_t level_flags;
     float vmin, vmax;
 };
 static_assert(sizeof(DLeaf) == 64, "DLeaf layout");

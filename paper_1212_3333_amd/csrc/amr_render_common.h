@@ -1,0 +1,514 @@
+// Shared device code of the raycasting kernels: FP64 ray geometry and kD-restart traversal,
+// patch-local FP32 sampling, LUT classification and gradient lighting (Sections 5.3 and 6).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+
+#include "amr_internal.h"
+
+namespace amr {
+
+constexpr int kGradLen = 1024 + 5;   // dL/dLUT [256][4] then dL/d(light xyz, k_a, k_d)
+
+struct CkptHeader {                  // per ray, written at the end of the forward
+    float T, C[3];
+    int32_t nsamp, nck, every, pad_;
+};
+struct Ckpt {                        // (t, T, C) at the start of a data segment
+    double t;
+    float T, C[3];
+    int32_t dseg, sidx;
+};
+static_assert(sizeof(CkptHeader) == 32 && sizeof(Ckpt) == 32, "checkpoint layout");
+
+struct RenderArgs {
+    const float *pool;
+    const DNode *nodes;
+    const DLeaf *leaves;
+    const DPatch *patches;
+    const float4 *lut;
+    double box_lo[3], box_hi[3];     // B (closed, for gradient taps)
+    double clip_lo[3], clip_hi[3];   // B ∩ clip box
+    double step_fine;
+    double eye[3], u[3], v[3], w[3];
+    double tanf, win0, win1;
+    int32_t ortho, width, height, depth;
+    float v_lo, inv_range, step_frac, t_min;
+    float lhat[3], inv_lnorm, k_a, k_d, eps2;
+    int32_t uniform_step, lighting;
+    float *rgba;
+    amr_trace_rec *trace;
+    int32_t *trace_n;
+    int32_t *nsamp;
+    int64_t trace_cap;
+    amr_render_stats *stats;
+    uint32_t *touch;
+    uint8_t *ckpt;                   // checkpoint buffer base (all cameras)
+    int64_t ckpt_ray0;               // first ray of this camera in the buffer
+    int64_t ckpt_stride;             // bytes per ray
+    int32_t ckpt_every, ckpt_max;
+    int32_t tiles_x, tiles_y, nblocks;
+};
+
+struct BwdArgs {
+    const float *grad_rgba;
+    float *grad;                     // kGradLen accumulator
+    float *partials;                 // deterministic: [grid][kGradLen]
+};
+
+struct Counters {   // per lane (32-bit); summed over the wave in 64 bits when flushed
+    unsigned int samples = 0, segments = 0, hit = 0, desc = 0, guard = 0, tover = 0, ckover = 0;
+};
+
+// ------------------------------------------------------------------------------------------
+// FP64 geometry
+// ------------------------------------------------------------------------------------------
+
+__device__ __forceinline__ double sel3(int a, double x, double y, double z) { return a == 0 ? x : (a == 1 ? y : z); }
+
+struct Ray {
+    double o[3], d[3], invd[3], t0, t1;
+};
+
+__device__ __forceinline__ void make_ray(const RenderArgs &A, int i, int j, double o[3], double d[3]) {
+#pragma clang fp contract(off)
+    double s = (double)(2 * i + 1) / (double)A.width - 1.0;
+    double t = 1.0 - (double)(2 * j + 1) / (double)A.height;
+    double dd[3];
+    if (A.ortho) {
+        double a = s * A.win0, b = t * A.win1;
+        #pragma unroll
+        for (int k = 0; k < 3; k++) {
+            double e = A.eye[k] + a * A.u[k];
+            o[k] = e + b * A.v[k];
+            dd[k] = A.w[k];
+        }
+    } else {
+        double aspect = (double)A.width / (double)A.height;
+        double a = (s * A.tanf) * aspect, b = t * A.tanf;
+        #pragma unroll
+        for (int k = 0; k < 3; k++) {
+            o[k] = A.eye[k];
+            double e = A.w[k] + a * A.u[k];
+            dd[k] = e + b * A.v[k];
+        }
+    }
+    double n2 = dd[0] * dd[0] + dd[1] * dd[1];
+    n2 = n2 + dd[2] * dd[2];
+    double nr = sqrt(n2);
+    #pragma unroll
+    for (int k = 0; k < 3; k++) d[k] = dd[k] / nr;
+}
+
+__device__ __forceinline__ bool clip_ray(const RenderArgs &A, const double o[3], const double d[3], double *t0, double *t1) {
+#pragma clang fp contract(off)
+    double lo_t = 0.0, hi_t = INFINITY;
+    #pragma unroll
+    for (int a = 0; a < 3; a++) {
+        double lo = A.clip_lo[a], hi = A.clip_hi[a];
+        if (d[a] == 0.0) {
+            if (!(o[a] >= lo && o[a] < hi)) return false;
+            continue;
+        }
+        double inv = 1.0 / d[a];
+        double ta = (lo - o[a]) * inv, tb = (hi - o[a]) * inv;
+        double tn = ta < tb ? ta : tb, tf = ta < tb ? tb : ta;
+        if (tn > lo_t) lo_t = tn;
+        if (tf < hi_t) hi_t = tf;
+    }
+    *t0 = lo_t;
+    *t1 = hi_t;
+    return hi_t > lo_t;
+}
+
+__device__ __forceinline__ bool setup_ray(const RenderArgs &A, int i, int j, Ray &R) {
+    make_ray(A, i, j, R.o, R.d);
+    if (!clip_ray(A, R.o, R.d, &R.t0, &R.t1)) return false;
+    #pragma unroll
+    for (int a = 0; a < 3; a++) R.invd[a] = R.d[a] != 0.0 ? 1.0 / R.d[a] : 0.0;
+    return true;
+}
+
+// kD-restart: descend from the root for the ray interval [tmin, tmax]; returns the leaf id
+// and shrinks tmax to the leaf's exit.  Returns -1 if the walk exceeds the tree depth.
+__device__ __forceinline__ int descend(const RenderArgs &A, const Ray &R, double tmin, double &tmax) {
+#pragma clang fp contract(off)
+    uint32_t ni = 0;
+    for (int it = 0; it <= A.depth; it++) {
+        DNode n = A.nodes[ni];
+        uint32_t axis = n.meta & 3u;
+        if (axis == kLeafAxis) return (int)n.child;
+        double oa = sel3(axis, R.o[0], R.o[1], R.o[2]);
+        double da = sel3(axis, R.d[0], R.d[1], R.d[2]);
+        double s = n.split;
+        uint32_t low = n.child, high = low + 1;
+        if (da == 0.0) {
+            ni = oa < s ? low : high;
+            continue;
+        }
+        bool near_low = (oa < s) || (oa == s && da < 0.0);
+        uint32_t nearc = near_low ? low : high, farc = near_low ? high : low;
+        double ts = (s - oa) * sel3(axis, R.invd[0], R.invd[1], R.invd[2]);
+        if (ts <= 0.0 || ts >= tmax) ni = nearc;
+        else if (ts <= tmin) ni = farc;
+        else { ni = nearc; tmax = ts; }
+    }
+    return -1;
+}
+
+// Leaf holding point x (half-open comparisons against the split planes).
+__device__ __forceinline__ int locate_leaf(const RenderArgs &A, const double x[3]) {
+    uint32_t ni = 0;
+    for (int it = 0; it <= A.depth; it++) {
+        DNode n = A.nodes[ni];
+        uint32_t axis = n.meta & 3u;
+        if (axis == kLeafAxis) return (int)n.child;
+        ni = sel3(axis, x[0], x[1], x[2]) < n.split ? n.child : n.child + 1;
+    }
+    return -1;
+}
+
+__device__ __forceinline__ int leaf_level(const DLeaf &L) { return (int)(L.level_flags & 0xffu); }
+
+// ------------------------------------------------------------------------------------------
+// FP32 sampling
+// ------------------------------------------------------------------------------------------
+
+__device__ __forceinline__ float lerpf(float a, float b, float f) { return a + f * (b - a); }
+
+struct PatchView {
+    const float *brick;
+    int px, pxy, nx, ny, nz;
+};
+
+__device__ __forceinline__ PatchView patch_view(const RenderArgs &A, const DPatch &P) {
+    PatchView v;
+    v.brick = A.pool + P.off;
+    v.nx = P.n[0];
+    v.ny = P.n[1];
+    v.nz = P.n[2];
+    v.px = v.nx + 2;
+    v.pxy = v.px * (v.ny + 2);
+    return v;
+}
+
+// Trilinear value of a padded brick at patch-local continuous index q (cell centres at
+// integers; index -1 and n are the ghost layer).  Indices are clamped into the brick.
+template <bool REC>
+__device__ __forceinline__ float trilinear(const RenderArgs &A, const PatchView &pv, float qx, float qy, float qz) {
+    float fx = floorf(qx), fy = floorf(qy), fz = floorf(qz);
+    int ix = min(max((int)fx, -1), pv.nx - 1);
+    int iy = min(max((int)fy, -1), pv.ny - 1);
+    int iz = min(max((int)fz, -1), pv.nz - 1);
+    fx = qx - (float)ix;
+    fy = qy - (float)iy;
+    fz = qz - (float)iz;
+    const int px = pv.px, pxy = pv.pxy;
+    const float *b = pv.brick + (ix + 1) + (iy + 1) * px + (iz + 1) * pxy;
+    if (REC && A.touch) {   // measurement only: mark the eight cells read
+        uint64_t base = (uint64_t)(b - A.pool);
+        uint64_t offs[8] = {0, 1, (uint64_t)px, (uint64_t)px + 1, (uint64_t)pxy, (uint64_t)pxy + 1,
+                            (uint64_t)(pxy + px), (uint64_t)(pxy + px) + 1};
+        #pragma unroll
+        for (int c = 0; c < 8; c++) {
+            uint64_t e = base + offs[c];
+            atomicOr(&A.touch[e >> 5], 1u << (e & 31));
+        }
+    }
+    float v000 = b[0], v100 = b[1], v010 = b[px], v110 = b[px + 1];
+    float v001 = b[pxy], v101 = b[pxy + 1], v011 = b[pxy + px], v111 = b[pxy + px + 1];
+    float c00 = lerpf(v000, v100, fx), c10 = lerpf(v010, v110, fx);
+    float c01 = lerpf(v001, v101, fx), c11 = lerpf(v011, v111, fx);
+    float c0 = lerpf(c00, c10, fy), c1 = lerpf(c01, c11, fy);
+    return lerpf(c0, c1, fz);
+}
+
+// Field value at world point x located in the tree; false where no patch holds data or x is
+// outside B (closed).
+template <bool REC>
+__device__ __forceinline__ bool field_at(const RenderArgs &A, const double x[3], float *val, Counters &cnt) {
+#pragma clang fp contract(off)
+    #pragma unroll
+    for (int a = 0; a < 3; a++)
+        if (x[a] < A.box_lo[a] || x[a] > A.box_hi[a]) return false;
+    int leaf = locate_leaf(A, x);
+    if (REC) cnt.desc++;
+    if (leaf < 0) return false;
+    int p = A.leaves[leaf].patch;
+    if (p < 0) return false;
+    const DPatch &P = A.patches[p];
+    PatchView pv = patch_view(A, P);
+    float q[3];
+    #pragma unroll
+    for (int a = 0; a < 3; a++) q[a] = (float)((x[a] - P.lo[a]) * P.inv_h[a] - 0.5);
+    *val = trilinear<REC>(A, pv, q[0], q[1], q[2]);
+    return true;
+}
+
+// Per-segment sampling state: n midpoint samples of step delta on [ta, tb] (Section 5.3:
+// the step is proportional to the leaf level's cell size).
+struct Segment {
+    PatchView pv;
+    float q0[3], dq[3], dl;           // patch-local start, step, delta * log2(e)
+    double ta, delta;
+    float lq_lo[3], lq_hi[3];         // leaf box in patch-local continuous cell coordinates
+    uint32_t safe;                    // faces across which a gradient tap stays in this brick
+    int leaf, patch, n;
+};
+
+template <bool LIT>
+__device__ __forceinline__ void setup_segment(const RenderArgs &A, const Ray &R, const DLeaf &L, int leaf, double ta,
+                                              double tb, Segment &S) {
+    const DPatch &P = A.patches[L.patch];
+    {
+#pragma clang fp contract(off)
+        double step = (double)A.step_frac * (A.uniform_step ? A.step_fine : P.step);
+        double ratio = (tb - ta) / step;
+        double nn = ceil(ratio - 0x1p-20);
+        S.n = nn < 1.0 ? 1 : (int)nn;
+        S.delta = (tb - ta) / (double)S.n;
+    }
+    S.ta = ta;
+    S.pv = patch_view(A, P);
+    #pragma unroll
+    for (int a = 0; a < 3; a++) {
+        S.q0[a] = (float)(((R.o[a] - P.lo[a]) + ta * R.d[a]) * P.inv_h[a] - 0.5);
+        S.dq[a] = (float)(S.delta * R.d[a] * P.inv_h[a]);
+    }
+    S.dl = (float)S.delta * 1.44269504088896340736f;
+    if (LIT) {
+        #pragma unroll
+        for (int a = 0; a < 3; a++) {
+            S.lq_lo[a] = (float)((L.lo[a] - P.lo[a]) * P.inv_h[a] - 0.5);
+            S.lq_hi[a] = (float)((L.hi[a] - P.lo[a]) * P.inv_h[a] - 0.5);
+        }
+        S.safe = (L.level_flags >> 8) & 0x3fu;
+        S.leaf = leaf;
+        S.patch = L.patch;
+    }
+}
+
+struct SampleVals {
+    float F, r, g, b, sig, alpha, shade, f;
+    int i0;
+    float gv[3], dot, den;
+};
+
+enum { kTapSame = 0, kTapLocate = 1, kTapUnsure = 2 };
+constexpr float kTapMargin = 1e-3f;   // cells; far above the fp32 error of patch-local positions
+
+// Where does the gradient tap q (the sample moved by +-1 cell along axis a) read its value?
+// Decided in fp32 patch-local coordinates when every comparison clears the margin.
+__device__ __forceinline__ int classify_tap_fp32(const Segment &S, const float q[3], int a, int sgn) {
+    int out_axis = -1;
+    #pragma unroll
+    for (int b = 0; b < 3; b++) {
+        const float lo = S.lq_lo[b], hi = S.lq_hi[b];
+        const bool in_sure = q[b] >= lo + kTapMargin && q[b] < hi - kTapMargin;
+        const bool out_sure = q[b] < lo - kTapMargin || q[b] >= hi + kTapMargin;
+        if (!in_sure && !out_sure) return kTapUnsure;
+        if (out_sure) {
+            if (b != a) return kTapLocate;
+            out_axis = b;
+        }
+    }
+    if (out_axis < 0) return kTapSame;
+    const uint32_t face = 2u * a + (sgn ? 0u : 1u);
+    if (!((S.safe >> face) & 1u)) return kTapLocate;
+    // inside the one-cell slab beyond the face?
+    const float lim = sgn ? S.lq_lo[a] - 1.f : S.lq_hi[a] + 1.f;
+    const float qa = q[a];
+    const bool in_slab = sgn ? qa >= lim + kTapMargin : qa < lim - kTapMargin;
+    const bool out_slab = sgn ? qa < lim - kTapMargin : qa >= lim + kTapMargin;
+    if (in_slab) return kTapSame;
+    if (out_slab) return kTapLocate;
+    return kTapUnsure;
+}
+
+// Exact FP64 decision (same comparisons as the oracle's point location), for taps near a face.
+__device__ __forceinline__ int classify_tap_fp64(const RenderArgs &A, const Segment &S, const double xt[3], int a,
+                                                 int sgn) {
+#pragma clang fp contract(off)
+    const DLeaf &L = A.leaves[S.leaf];
+    const DPatch &P = A.patches[S.patch];
+    bool in_leaf = true, others = true;
+    #pragma unroll
+    for (int b = 0; b < 3; b++) {
+        const bool inb = xt[b] >= L.lo[b] && xt[b] < L.hi[b];
+        in_leaf = in_leaf && inb;
+        if (b != a) others = others && inb;
+    }
+    if (in_leaf) return kTapSame;
+    const uint32_t face = 2u * a + (sgn ? 0u : 1u);
+    if (!others || !((S.safe >> face) & 1u)) return kTapLocate;
+    const double lim = sgn ? L.lo[a] - P.h[a] : L.hi[a] + P.h[a];
+    const bool in_slab = sgn ? (xt[a] >= lim && xt[a] < L.lo[a]) : (xt[a] >= L.hi[a] && xt[a] < lim);
+    return in_slab ? kTapSame : kTapLocate;
+}
+
+// Sample k of a segment: value, LUT classification, opacity over the step, and (LIT) the
+// gradient shading with taps at x +- h^l e_a located in the tree.
+template <bool LIT, bool REC>
+__device__ __forceinline__ void eval_sample(const RenderArgs &A, const float4 *s_lut, const Ray &R, const Segment &S,
+                                            int k, SampleVals &v, Counters &cnt) {
+    const float kk = (float)k + 0.5f;
+    const float qx = S.q0[0] + kk * S.dq[0], qy = S.q0[1] + kk * S.dq[1], qz = S.q0[2] + kk * S.dq[2];
+    const float F = trilinear<REC>(A, S.pv, qx, qy, qz);
+    v.F = F;
+    const float u = __saturatef((F - A.v_lo) * A.inv_range);
+    const float xs = 255.f * u;
+    const int i0 = min((int)xs, 254);
+    const float f = xs - (float)i0;
+    const float4 La = s_lut[i0], Lb = s_lut[i0 + 1];
+    v.i0 = i0;
+    v.f = f;
+    v.r = lerpf(La.x, Lb.x, f);
+    v.g = lerpf(La.y, Lb.y, f);
+    v.b = lerpf(La.z, Lb.z, f);
+    v.sig = lerpf(La.w, Lb.w, f);
+    v.alpha = 1.f - exp2f(-v.sig * S.dl);
+    v.shade = 1.f;
+    if (LIT) {
+        const float qc[3] = {qx, qy, qz};
+        #pragma unroll
+        for (int a = 0; a < 3; a++) {
+            float Fs[2];
+            bool ok[2];
+            #pragma unroll
+            for (int sgn = 0; sgn < 2; sgn++) {
+                float qt[3] = {qc[0], qc[1], qc[2]};
+                qt[a] += sgn ? -1.f : 1.f;
+                int cls = classify_tap_fp32(S, qt, a, sgn);
+                double xt[3];
+                if (cls != kTapSame) {
+                    // exact FP64 tap position: x = o + t_k d, then +- h^l along axis a
+#pragma clang fp contract(off)
+                    const double tk = S.ta + ((double)k + 0.5) * S.delta;
+                    #pragma unroll
+                    for (int b = 0; b < 3; b++) xt[b] = R.o[b] + tk * R.d[b];
+                    const double hl = A.patches[S.patch].h[a];
+                    xt[a] = sgn ? xt[a] - hl : xt[a] + hl;
+                    if (cls == kTapUnsure) cls = classify_tap_fp64(A, S, xt, a, sgn);
+                }
+                if (cls == kTapSame) {
+                    Fs[sgn] = trilinear<REC>(A, S.pv, qt[0], qt[1], qt[2]);
+                    ok[sgn] = true;
+                } else {
+                    ok[sgn] = field_at<REC>(A, xt, &Fs[sgn], cnt);
+                }
+            }
+            float gr;
+            if (ok[0] && ok[1]) gr = (Fs[0] - Fs[1]) * (0.5f * A.inv_range);
+            else if (ok[0]) gr = (Fs[0] - F) * A.inv_range;
+            else if (ok[1]) gr = (F - Fs[1]) * A.inv_range;
+            else gr = 0.f;
+            v.gv[a] = gr;
+        }
+        v.dot = v.gv[0] * A.lhat[0] + v.gv[1] * A.lhat[1] + v.gv[2] * A.lhat[2];
+        v.den = sqrtf(v.gv[0] * v.gv[0] + v.gv[1] * v.gv[1] + v.gv[2] * v.gv[2] + A.eps2);
+        v.shade = A.k_a + (v.den > 0.f ? A.k_d * fabsf(v.dot) / v.den : 0.f);
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// Reductions and counters
+// ------------------------------------------------------------------------------------------
+
+__device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ float wave_sumf(float v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ void flush_counters(amr_render_stats *st, Counters c, int lane) {
+    typedef unsigned long long u64;
+    u64 s = wave_sum((u64)c.samples), g = wave_sum((u64)c.segments), h = wave_sum((u64)c.hit);
+    u64 d = wave_sum((u64)c.desc), gu = wave_sum((u64)c.guard), to = wave_sum((u64)c.tover);
+    u64 co = wave_sum((u64)c.ckover);
+    if (lane == 0) {
+        if (s) atomicAdd(&st->samples, s);
+        if (g) atomicAdd(&st->segments, g);
+        if (h) atomicAdd(&st->rays_hit, h);
+        if (d) atomicAdd(&st->tap_descents, d);
+        if (gu) atomicAdd(&st->guard_hits, gu);
+        if (to) atomicAdd(&st->trace_overflow, to);
+        if (co) atomicAdd(&st->ckpt_overflow, co);
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// Host helpers
+// ------------------------------------------------------------------------------------------
+
+inline int check_hip(hipError_t e, const char *what) {
+    if (e != hipSuccess) {
+        set_error("%s: %s", what, hipGetErrorString(e));
+        return AMR_EHIP;
+    }
+    return AMR_OK;
+}
+
+inline int fill_args(const amr_scene *S, const amr_camera *C, const amr_render_params *P, RenderArgs *A) {
+    memset(A, 0, sizeof(*A));
+    if (!P->d_lut) { set_error("d_lut is NULL"); return AMR_EINVAL; }
+    if (!(P->v_hi > P->v_lo)) { set_error("v_hi must exceed v_lo"); return AMR_EINVAL; }
+    if (!(P->step_frac > 0.f) || !std::isfinite(P->step_frac)) { set_error("step_frac must be positive"); return AMR_EINVAL; }
+    if (C->width <= 0 || C->height <= 0) { set_error("camera size must be positive"); return AMR_EINVAL; }
+    A->pool = S->pool;
+    A->nodes = (const DNode *)S->nodes;
+    A->leaves = (const DLeaf *)S->leaves;
+    A->patches = (const DPatch *)S->patches;
+    A->lut = (const float4 *)P->d_lut;
+    #pragma unroll
+    for (int a = 0; a < 3; a++) {
+        A->box_lo[a] = S->box_lo[a];
+        A->box_hi[a] = S->box_hi[a];
+        A->clip_lo[a] = S->box_lo[a] > P->clip_lo[a] ? S->box_lo[a] : P->clip_lo[a];
+        A->clip_hi[a] = S->box_hi[a] < P->clip_hi[a] ? S->box_hi[a] : P->clip_hi[a];
+        A->eye[a] = C->eye[a];
+        A->u[a] = C->u[a];
+        A->v[a] = C->v[a];
+        A->w[a] = C->w[a];
+    }
+    A->step_fine = S->step_fine;
+    A->tanf = C->tan_half_fov;
+    A->win0 = C->win[0];
+    A->win1 = C->win[1];
+    A->ortho = C->ortho;
+    A->width = C->width;
+    A->height = C->height;
+    A->depth = S->depth;
+    A->v_lo = P->v_lo;
+    A->inv_range = 1.0f / (P->v_hi - P->v_lo);
+    A->step_frac = P->step_frac;
+    A->t_min = P->t_min;
+    float ln = sqrtf(P->light[0] * P->light[0] + P->light[1] * P->light[1] + P->light[2] * P->light[2]);
+    #pragma unroll
+    for (int a = 0; a < 3; a++) A->lhat[a] = ln > 0.f ? P->light[a] / ln : 0.f;
+    A->inv_lnorm = ln > 0.f ? 1.f / ln : 0.f;
+    A->k_a = P->k_a;
+    A->k_d = P->k_d;
+    A->eps2 = P->eps_g * P->eps_g;
+    A->uniform_step = P->uniform_step;
+    A->lighting = P->lighting;
+    A->tiles_x = (C->width + 15) / 16;
+    A->tiles_y = (C->height + 15) / 16;
+    A->nblocks = A->tiles_x * A->tiles_y;
+    A->ckpt = (uint8_t *)P->d_ckpt;
+    A->ckpt_stride = (int64_t)sizeof(Ckpt) * (1 + (int64_t)P->ckpt_max);
+    A->ckpt_every = P->ckpt_every > 0 ? P->ckpt_every : 1;
+    A->ckpt_max = P->ckpt_max;
+    return AMR_OK;
+}
+
+// Persistent multi-camera launch (amr_batched.hip).
+int launch_persistent(const amr_scene *S, const amr_camera *cams, int32_t ncams, const amr_render_params *P,
+                      float *d_rgba, amr_render_stats *d_stats, void *stream);
+
+}  // namespace amr

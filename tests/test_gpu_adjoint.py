@@ -1,0 +1,171 @@
+"""GPU adjoint (amr_render_backward) against the FP64 oracle's reverse mode, GPU finite
+differences, and its own invariants (determinism, checkpoint-rate independence)."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def _scene(amr, h):
+    import torch
+    tree = amr.build_tree(h)
+    scene = amr.pack(tree, h, device="cuda")
+    torch.cuda.synchronize()
+    return tree, scene
+
+
+# fp32 bar: |g - g_ref| <= rel |g_ref| + 1e-5 max|g_ref|.  The absolute term is the fp32 noise
+# floor of a gradient entry summed from ~1e5 per-sample terms (observed worst 2.3e-6 max).
+ABS_FLOOR = 1e-5
+
+
+def _bar_ok(got, ref, rel):
+    ref = np.asarray(ref, np.float64)
+    got = np.asarray(got, np.float64)
+    return bool(np.all(np.abs(got - ref) <= rel * np.abs(ref) + ABS_FLOOR * np.abs(ref).max()))
+
+
+def _rel_ok(got, ref, rel, floor_frac):
+    ref = np.asarray(ref, np.float64)
+    got = np.asarray(got, np.float64)
+    big = np.abs(ref) >= floor_frac * np.abs(ref).max()
+    err = np.abs(got - ref)[big] / np.abs(ref)[big]
+    worst = np.argsort(-np.where(big, np.abs(got - ref) / np.maximum(np.abs(ref), 1e-300), 0).ravel())[:8]
+    for w in worst:
+        print("  entry %s ref %.6g got %.6g rel %.3g abs/max %.3g" % (
+            np.unravel_index(w, ref.shape), ref.ravel()[w], got.ravel()[w],
+            abs(got.ravel()[w] - ref.ravel()[w]) / abs(ref.ravel()[w]),
+            abs(got.ravel()[w] - ref.ravel()[w]) / np.abs(ref).max()))
+    return err.max() if big.any() else 0.0, int(big.sum())
+
+
+@pytest.mark.parametrize("lit", [False, True])
+def test_adjoint_vs_oracle_config1(gpu, lit):
+    import torch
+    amr = gpu
+    h, lut, cams, prm = workloads.config1(1)
+    prm = dict(prm, lighting=lit, t_min=0.0, light=(0.3, 1.0, -0.6))
+    cam = workloads.config1_cameras(64, 64)[1]
+    tree, scene = _scene(amr, h)
+    lut_t = torch.from_numpy(lut).cuda()
+    out, ck = amr.render_checkpointed(scene, cam, lut_t, prm, ckpt_every=2, ckpt_max=8)
+    W = np.random.default_rng(3).normal(size=(64 * 64, 4)).astype(np.float32)
+    glut, glight = amr.render_backward(scene, cam, lut_t, prm, ck, torch.from_numpy(W).cuda())
+    torch.cuda.synchronize()
+    ref_lut, ref_light = oracle.Oracle(h).grad(cam, prm, lut.astype(np.float64), W.astype(np.float64))
+    e, n = _rel_ok(glut.cpu().numpy(), ref_lut, 1e-3, 1e-3)
+    print("lit=%d: LUT grad max rel err %.3g over %d entries" % (lit, e, n))
+    assert _bar_ok(glut.cpu().numpy(), ref_lut, 1e-3) and n > 50
+    if lit:
+        gl = glight.cpu().numpy()
+        assert np.all(np.abs(gl - ref_light) <= 1e-3 * np.abs(ref_light) + 1e-4 * np.abs(ref_light).max())
+    else:
+        assert np.all(glight.cpu().numpy() == 0)
+
+
+def test_adjoint_vs_gpu_finite_differences(gpu):
+    import torch
+    amr = gpu
+    h, lut, cams, prm = workloads.config1(2)
+    prm = dict(prm, lighting=True, t_min=0.0)
+    cam = workloads.config1_cameras(48, 48)[1]
+    tree, scene = _scene(amr, h)
+    lut64 = lut.astype(np.float64)
+    W = np.random.default_rng(5).normal(size=(48 * 48, 4))
+    out, ck = amr.render_checkpointed(scene, cam, torch.from_numpy(lut).cuda(), prm)
+    glut, _ = amr.render_backward(scene, cam, torch.from_numpy(lut).cuda(), prm, ck,
+                                  torch.from_numpy(W.astype(np.float32)).cuda())
+    g = glut.cpu().numpy().astype(np.float64)
+
+    def loss(l):
+        o = amr.render(scene, cam, torch.from_numpy(l.astype(np.float32)).cuda(), prm)["rgba"]
+        return float((o.double().cpu().numpy().reshape(-1, 4) * W).sum())
+    hstep = 1e-3
+    rng = np.random.default_rng(0)
+    idx = np.argwhere(np.abs(g) >= 1e-2 * np.abs(g).max())
+    sel = idx[rng.choice(len(idx), size=min(60, len(idx)), replace=False)]
+    fd = []
+    for e, c in sel:
+        lp = lut64.copy(); lp[e, c] += hstep
+        lm = lut64.copy(); lm[e, c] -= hstep
+        fd.append((loss(lp) - loss(lm)) / (2 * hstep))
+    fd = np.array(fd)
+    ad = np.array([g[e, c] for e, c in sel])
+    cos = fd @ ad / (np.linalg.norm(fd) * np.linalg.norm(ad))
+    print("cosine %.6f, max rel %.3g" % (cos, np.max(np.abs(fd - ad) / np.abs(ad))))
+    assert cos >= 0.999
+    assert np.max(np.abs(fd - ad) / np.abs(ad)) <= 1e-2
+
+
+def test_adjoint_deterministic_and_checkpoint_rate(gpu):
+    import torch
+    amr = gpu
+    h, lut, cams, prm = workloads.config1(0)
+    prm = dict(prm, lighting=True)
+    cam = workloads.config1_cameras(64, 64)[0]
+    tree, scene = _scene(amr, h)
+    lut_t = torch.from_numpy(lut).cuda()
+    W = torch.from_numpy(np.random.default_rng(1).normal(size=(64 * 64, 4)).astype(np.float32)).cuda()
+    res = []
+    for every, cmax in ((1, 2), (1, 64), (4, 8), (1000, 2)):
+        out, ck = amr.render_checkpointed(scene, cam, lut_t, prm, ckpt_every=every, ckpt_max=cmax)
+        r1 = amr.render_backward(scene, cam, lut_t, prm, ck, W, deterministic=True)
+        r2 = amr.render_backward(scene, cam, lut_t, prm, ck, W, deterministic=True)
+        assert torch.equal(r1[0], r2[0]) and torch.equal(r1[1], r2[1]), "deterministic mode not reproducible"
+        res.append(torch.cat([r1[0].flatten(), r1[1]]).cpu().numpy().astype(np.float64))
+    ref = res[0]
+    for r in res[1:]:
+        assert np.abs(r - ref).max() <= 1e-4 * np.abs(ref).max()
+
+
+def test_autograd_function(gpu):
+    import torch
+    amr = gpu
+    h, lut, cams, prm = workloads.config1(0)
+    prm = dict(prm, lighting=True, t_min=0.0)
+    cam = workloads.config1_cameras(32, 32)[1]
+    tree, scene = _scene(amr, h)
+    lut_p = torch.from_numpy(lut).cuda().requires_grad_(True)
+    sh = torch.tensor([1.0, 1.0, 1.0, 0.3, 0.7], dtype=torch.float32, requires_grad=True)
+    rgba = amr.AMRRender.apply(lut_p, sh, scene, cam, prm)
+    target = torch.zeros_like(rgba)
+    loss = ((rgba - target) ** 2).mean()
+    loss.backward()
+    ref_lut, ref_sh = oracle.Oracle(h).grad(cam, prm, lut.astype(np.float64),
+                                           (2 * rgba.detach().double().cpu().numpy().reshape(-1, 4)) / rgba.numel())
+    e, n = _rel_ok(lut_p.grad.cpu().numpy(), ref_lut, 2e-3, 1e-3)
+    assert _bar_ok(lut_p.grad.cpu().numpy(), ref_lut, 1e-3) and n > 20
+    assert np.allclose(sh.grad.numpy(), ref_sh, rtol=2e-3, atol=1e-4 * np.abs(ref_sh).max())
+
+
+@pytest.mark.parametrize("lit", [True])
+def test_adjoint_vs_oracle_config5_subset(gpu, lit):
+    """Config 5 (cosmology-like hierarchy, 8 cameras at 512^2): dL/dRGBA nonzero on 800 random
+    pixels per camera; the GPU adjoint of the full 8-camera batch against the oracle's."""
+    import torch
+    amr = gpu
+    h, cams, target, start, prm = workloads.config5(0)
+    prm = dict(prm, lighting=lit)
+    tree, scene = _scene(amr, h)
+    lut_t = torch.from_numpy(start).cuda()
+    out, ck = amr.render_checkpointed(scene, cams, lut_t, prm, ckpt_every=4, ckpt_max=16)
+    rng = np.random.default_rng(2)
+    npx = 512 * 512
+    G = np.zeros((len(cams), npx, 4), dtype=np.float32)
+    O = oracle.Oracle(h)
+    ref_lut = np.zeros((256, 4)); ref_light = np.zeros(5)
+    for c, cam in enumerate(cams):
+        sel = rng.choice(npx, size=800, replace=False)
+        G[c, sel] = rng.normal(size=(800, 4))
+        pix = np.stack([sel % 512, sel // 512], 1).astype(np.int32)
+        rl, rli = O.grad(cam, prm, start.astype(np.float64), G[c, sel].astype(np.float64), pixels=pix)
+        ref_lut += rl
+        ref_light += rli
+    glut, glight = amr.render_backward(scene, cams, lut_t, prm, ck, torch.from_numpy(G.reshape(-1, 4)).cuda())
+    e, n = _rel_ok(glut.cpu().numpy(), ref_lut, 1e-3, 1e-3)
+    print("config5: LUT grad max rel err %.3g over %d entries; light %s vs %s" % (e, n, glight.cpu().numpy(), ref_light))
+    assert _bar_ok(glut.cpu().numpy(), ref_lut, 1e-3) and n > 50
+    assert np.all(np.abs(glight.cpu().numpy() - ref_light) <= 1e-3 * np.abs(ref_light) + 1e-4 * np.abs(ref_light).max())

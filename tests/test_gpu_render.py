@@ -179,3 +179,46 @@ def test_invalid_arguments(gpu):
         amr.render(scene, dict(cams[0], width=0), lut_t, prm)
     with pytest.raises(amr.AMRError):
         amr.render(scene, cams[0], lut_t, dict(prm, step_frac=0.0))
+
+
+@pytest.fixture(scope="module")
+def config2_scene(gpu):
+    amr = gpu
+    h, lut, cam, prm = workloads.config2(0)
+    tree, scene = _setup(amr, h)
+    return h, lut, cam, prm, tree, scene
+
+
+def _sample_pixels(W, H, seed):
+    rng = np.random.default_rng(seed)
+    pix = [np.stack([rng.integers(0, W, 3000), rng.integers(0, H, 3000)], 1)]
+    for row in (H // 3, H // 2 + 7):
+        pix.append(np.stack([np.arange(W), np.full(W, row)], 1))
+    cy, cx = H // 2 - 16, W // 2 - 16
+    jj, ii = np.meshgrid(np.arange(cy, cy + 32), np.arange(cx, cx + 32), indexing="ij")
+    pix.append(np.stack([ii.ravel(), jj.ravel()], 1))
+    return np.ascontiguousarray(np.concatenate(pix), dtype=np.int32)
+
+
+@pytest.mark.parametrize("lit", [True, False])
+def test_config2_full_size_sampled(gpu, config2_scene, lit):
+    """The 1024x1024 cosmology-like frame in the launch configuration the benchmark times;
+    the oracle checks 3000 random pixels, two full rows and a 32x32 crop."""
+    import torch
+    amr = gpu
+    h, lut, cam, prm, tree, scene = config2_scene
+    prm = dict(prm, lighting=lit)
+    W, H = cam["width"], cam["height"]
+    cap = 192
+    out = _gpu_render(amr, scene, cam, lut, prm, trace_cap=cap, stats=True)
+    pix = _sample_pixels(W, H, 11)
+    idx = torch.from_numpy(pix[:, 1].astype(np.int64) * W + pix[:, 0]).cuda()
+    rgba = out["rgba"].view(-1, 4)[idx].cpu().numpy().astype(np.float64)
+    sub = dict(trace_raw=out["trace_raw"][idx], trace_n=out["trace_n"][idx])
+    del out
+    ores = oracle.Oracle(h).render(cam, prm, lut, pixels=pix, trace_cap=cap)
+    err = np.abs(rgba - ores["rgba"]).max()
+    print("config2 lit=%d: %d pixels, max|err| = %.3g, max segments %d" % (lit, len(pix), err, ores["trace_n"].max()))
+    assert err <= TOL
+    assert ores["trace_n"].max() <= cap
+    _compare_traces(amr, sub, ores)

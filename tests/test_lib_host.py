@@ -130,7 +130,7 @@ def test_device_encoding():
     lr = scene.leaf_records()
     for k, lf in enumerate(leaves):
         assert np.array_equal(lr[k]["lo"], h.origin + lf["lo"] * hf)
-        assert lr[k]["patch"] == lf["patch"] and lr[k]["level"] == lf["level"]
+        assert lr[k]["patch"] == lf["patch"] and (lr[k]["level_flags"] & 0xFF) == lf["level"]
     hdr = scene.patch_headers()
     for p, ph in enumerate(h.patches):
         assert np.array_equal(hdr[p]["n"], ph.dims)

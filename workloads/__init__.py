@@ -431,3 +431,112 @@ def config2(seed: int = 0, width: int = 1024, height: int = 1024):
     vhi = float(np.float32(np.percentile(sample.astype(np.float64), 99.9)))
     prm = default_params(v_lo=0.0, v_hi=vhi, lighting=True, light=(1.0, 1.0, 1.0), k_a=0.3, k_d=0.7)
     return h, lut_cosmology(seed), cam, prm
+
+
+def config5(seed: int = 0, res: int = 512, ncams: int = 8, h: Hierarchy | None = None):
+    """Differentiable transfer function: the config-2 hierarchy, `ncams` seeded orbit cameras at
+    res^2, a hidden target LUT and a different starting LUT."""
+    if h is None:
+        h = cosmology_like(seed)
+    rng = _rng(4, "cameras", MASTER_SEED + seed)
+    cams = [perspective_orbit(res, res, float(rng.uniform(0, 2 * math.pi)), float(rng.uniform(-0.6, 0.6)),
+                              radius=2.0, fov_deg=40.0) for _ in range(ncams)]
+    target = lut_bumps(_rng(4, "lut", MASTER_SEED + seed), sigma_scale=1.0)
+    u = np.arange(256) / 255.0
+    target[:, 3] = (0.4 + 60.0 * u).astype(np.float32)
+    start = lut_bumps(_rng(4, "mlp_init", MASTER_SEED + seed), sigma_scale=1.0)
+    start[:, 3] = (0.4 + 30.0 * u ** 0.7).astype(np.float32)
+    sample = np.concatenate([p.cells.reshape(-1)[:: max(1, p.cells.size // 4096)] for p in h.patches])
+    vhi = float(np.float32(np.percentile(sample.astype(np.float64), 99.9)))
+    prm = default_params(v_lo=0.0, v_hi=vhi, lighting=True, light=(1.0, 1.0, 1.0), k_a=0.3, k_d=0.7, t_min=0.0)
+    return h, cams, target, start, prm
+
+
+def config4_cameras(seed: int = 0, ncams: int = 64, sizes=(256, 512, 768, 1024)):
+    """Batched serving: `ncams` perspective cameras on random orbit positions, square
+    resolutions drawn uniformly from `sizes`."""
+    rng = _rng(3, "cameras", MASTER_SEED + seed)
+    cams = []
+    for _ in range(ncams):
+        res = int(rng.choice(sizes))
+        cams.append(perspective_orbit(res, res, float(rng.uniform(0, 2 * math.pi)), float(rng.uniform(-0.7, 0.7)),
+                                      radius=float(rng.uniform(1.8, 2.4)), fov_deg=40.0))
+    return cams
+
+
+# ----------------------------------------------------------------------------------------------
+# Deep-range hierarchy: three collapsing cores refined over 20 levels
+# ----------------------------------------------------------------------------------------------
+
+class CoreField:
+    """rho = 1 + sum_j A_j (1 + r_j^2 / s^2)^-1 exp(-r_j^2 / (2 w^2)); cells hold log10 rho."""
+
+    def __init__(self, rng: np.random.Generator, ncores: int = 3, s: float = 2.0 ** -24, w: float = 0.05):
+        self.c = rng.uniform(0.3, 0.7, (ncores, 3))
+        self.A = 10.0 ** (14.0 + rng.uniform(-0.5, 0.5, ncores))
+        self.s, self.w = s, w
+
+    def log_rho_lattice(self, xs, ys, zs) -> np.ndarray:
+        Z, Y, X = np.meshgrid(zs, ys, xs, indexing="ij")
+        rho = np.ones_like(X)
+        for j in range(len(self.A)):
+            r2 = (X - self.c[j, 0]) ** 2 + (Y - self.c[j, 1]) ** 2 + (Z - self.c[j, 2]) ** 2
+            rho += self.A[j] / (1.0 + r2 / self.s ** 2) * np.exp(-r2 / (2 * self.w ** 2))
+        return np.log10(rho)
+
+
+def deep_range(seed: int = 0, root: int = 64, nlevels: int = 20, block: int = 16, radius_cells: float = 44.0):
+    """Config 3 geometry: root `root`^3 on [0,1]^3 (one level-0 patch), r = 2, `nlevels` levels.
+    Level l >= 1 tiles a ball of radius `radius_cells` h^l around each core with `block`^3
+    blocks on a grid shifted by a random even offset (so fine blocks span several parents),
+    keeping the blocks that meet a ball, clipped to the domain."""
+    rng = _rng(2, "patches", MASTER_SEED + seed)
+    field = CoreField(_rng(2, "field", MASTER_SEED + seed))
+    h = Hierarchy(np.zeros(3), np.full(3, 1.0 / root), 2, nlevels, [_empty_patch(0, [0, 0, 0], [root] * 3)])
+    for lev in range(1, nlevels):
+        n_l = root * 2 ** lev
+        hl = 1.0 / n_l
+        off = rng.integers(0, block // 2, 3) * 2
+        keys = set()
+        for c in field.c:
+            cc = c / hl                                   # core in level-l cell units
+            lo = np.floor((cc - radius_cells - off) / block).astype(np.int64)
+            hi = np.floor((cc + radius_cells - off) / block).astype(np.int64)
+            for kz in range(lo[2], hi[2] + 1):
+                for ky in range(lo[1], hi[1] + 1):
+                    for kx in range(lo[0], hi[0] + 1):
+                        b0 = np.array([kx, ky, kz]) * block + off
+                        nearest = np.clip(cc, b0, b0 + block)
+                        if np.sum((nearest - cc) ** 2) <= radius_cells ** 2:
+                            keys.add((kx, ky, kz))
+        for key in sorted(keys):
+            b0 = np.array(key) * block + off
+            glo, ghi = np.maximum(b0, 0), np.minimum(b0 + block, n_l)
+            if np.all(ghi > glo):
+                h.patches.append(_empty_patch(lev, glo, ghi - glo))
+    for p in h.patches:
+        x, y, z = h.cell_centres(p)
+        p.cells = np.ascontiguousarray(field.log_rho_lattice(x, y, z), dtype=np.float32)
+    h.cores = field.c
+    return h
+
+
+def lut_deep(seed: int = 0, sigma0: float = 1e-4, decades: float = 10.0) -> np.ndarray:
+    """sigma_i = sigma0 10^(decades i / 255): the bulk is nearly transparent while the deep
+    cores (log10 rho ~ 14) still register."""
+    lut = lut_bumps(_rng(2, "lut", MASTER_SEED + seed), sigma_scale=1.0)
+    u = np.arange(256) / 255.0
+    lut[:, 3] = (sigma0 * 10.0 ** (decades * u)).astype(np.float32)
+    return lut
+
+
+def config3(seed: int = 0, res: int = 1024):
+    """Deep-range workload: hierarchy, LUT, full-domain view and a zoom on core 0 at res^2."""
+    h = deep_range(seed)
+    rng = _rng(2, "cameras", MASTER_SEED + seed)
+    az, el = float(rng.uniform(0, 2 * math.pi)), float(rng.uniform(-0.4, 0.4))
+    full = perspective_orbit(res, res, az, el, radius=2.0, fov_deg=40.0)
+    core = h.cores[0]
+    zoom = perspective_orbit(res, res, az + 0.7, el, radius=4e-6, centre=tuple(core), fov_deg=40.0)
+    prm = default_params(v_lo=0.0, v_hi=14.5, lighting=False, t_min=1e-5)
+    return h, lut_deep(seed), [full, zoom], prm
