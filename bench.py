@@ -83,6 +83,70 @@ def cpu_baseline(h, cam, lut, prm, target_s=15.0, seed=7):
                 seconds=dt)
 
 
+def learned_skip_section(amr, dev, steps, warmup):
+    """Deep-range hierarchy (20 levels) at 1024^2: plain traversal vs learned segment proposals.
+    The network is trained on the GPU from segments logged by the plain kernel on 16 views and
+    its thresholds calibrated on 6 held-out views (worst RGBA error <= 0.5e-3 there); the timed
+    view is the full-domain one."""
+    import torch
+    import workloads
+    from paper_1212_3333_amd import learned
+    t = time.time()
+    h, lut, cams, prm = workloads.deep_range_scene(0, res=1024)
+    tree = amr.build_tree(h)
+    scene = amr.pack(tree, h, device=dev)
+    lut_t = torch.from_numpy(lut).to(dev)
+    torch.cuda.synchronize()
+    prep = time.time() - t
+    t = time.time()
+    X, alpha, t_in, met = learned.log_segments(scene, workloads.deep_range_orbits(h, 16, 1, 192), lut_t, prm)
+    W, losses = learned.train(X, alpha, steps=500, batch=65536, lr=3e-3)
+    net = learned.ProposalMLP(W)
+    held = workloads.deep_range_orbits(h, 6, 2, 192)
+    plain_held = [amr.render(scene, c, lut_t, prm)["rgba"].clone() for c in held]
+    te, ts, table = learned.calibrate(scene, held, lut_t, prm, net.packed, plain_held, max_err=1e-3)
+    torch.cuda.synchronize()
+    train_s = time.time() - t
+    cam = cams[0]
+    W_, H_ = cam["width"], cam["height"]
+    out = torch.empty(W_ * H_ * 4, dtype=torch.float32, device=dev)
+    p_stats = amr.stats_dict(amr.render(scene, cam, lut_t, prm, stats=True))
+    l_res = learned.render_learned(scene, cam, lut_t, prm, net.packed, te, ts, stats=True)
+    l_stats = amr.stats_dict(l_res)
+    plain_img = amr.render(scene, cam, lut_t, prm)["rgba"]
+    err = float((l_res["rgba"] - plain_img).abs().max().item())
+    ms_p = time_frames(amr, scene, cam, lut_t, prm, steps, warmup, out)
+    prm_l = dict(prm, tau_e=te, tau_s=ts)
+
+    def run_l():
+        amr.render(scene, cam, lut_t, prm_l, out=out, d_mlp=net.packed)
+    for _ in range(warmup):
+        run_l()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        run_l()
+    e1.record()
+    torch.cuda.synchronize()
+    ms_l = e0.elapsed_time(e1) / steps
+    log("learned skip: plain %.3f ms, learned %.3f ms, err %.2e, tau_e %g tau_s %g" % (ms_p, ms_l, err, te, ts))
+    return {
+        "workload": "deep-range SAMR: root 64^3, 20 levels, r=2, %d patches around 3 power-law cores; 1024x1024 "
+                    "full-domain view, unlit" % len(h.patches),
+        "plain_ms": round(ms_p, 4), "learned_ms": round(ms_l, 4), "speedup": round(ms_p / ms_l, 3),
+        "plain_samples_per_s": round(p_stats["samples"] / (ms_p * 1e-3), 1),
+        "learned_samples_per_s": round(l_stats["samples"] / (ms_l * 1e-3), 1),
+        "plain_equivalent_samples_per_s": round(p_stats["samples"] / (ms_l * 1e-3), 1),
+        "plain_mrays_per_s": round(W_ * H_ / (ms_p * 1e-3) / 1e6, 3),
+        "learned_mrays_per_s": round(W_ * H_ / (ms_l * 1e-3) / 1e6, 3),
+        "max_rgba_err_vs_plain": err, "tau_e": te, "tau_s": ts,
+        "skipped_segments": l_stats["skipped_segments"], "coarse_segments": l_stats["coarse_segments"],
+        "plain_samples": p_stats["samples"], "learned_samples": l_stats["samples"],
+        "train_segments": int(X.shape[0]), "train_calibrate_s": round(train_s, 2), "prepare_s": round(prep, 2),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -93,10 +157,12 @@ def main():
     ap.add_argument("--no-touch", action="store_true", help="skip the compulsory-bytes measurement run")
     ap.add_argument("--unlit", action="store_true", help="time the unlit kernel instead")
     ap.add_argument("--copy-calib", action="store_true", help="also run a 1 GiB device copy (counter calibration)")
+    ap.add_argument("--brick-layout", type=int, default=1, help="pool layout: 0 linear bricks, 1 4^3 micro-bricks")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-skip section")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build renders on one GPU only (the multi-GPU design is described in DESIGN.md); "
-              "run with --gpus 1", file=sys.stderr)
+        print("bench.py: the renderer runs on one GPU per process and this benchmark measures one GPU; "
+              "multi-GPU runs are not supported, use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -106,7 +172,7 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     t = time.time()
-    h, lut, cam, prm = workloads.config2(args.seed)
+    h, lut, cam, prm = workloads.cosmology_view(args.seed)
     gen_s = time.time() - t
     if args.unlit:
         prm = dict(prm, lighting=False)
@@ -115,7 +181,7 @@ def main():
     tree = amr.build_tree(h)
     build_s = time.time() - t
     t = time.time()
-    scene = amr.pack(tree, h, device=dev)
+    scene = amr.pack(tree, h, device=dev, brick_layout=args.brick_layout)
     torch.cuda.synchronize()
     pack_s = time.time() - t
     info = tree.info()
@@ -168,6 +234,13 @@ def main():
     if prm["lighting"]:
         unlit_ms = time_frames(amr, scene, cam, lut_t, dict(prm, lighting=False), max(3, args.steps // 2), 2, out)
 
+    pool_bytes, meta_bytes = int(scene.scene.pool_bytes), int(scene.scene.meta_bytes)
+    learned_res = None
+    if not args.no_learned:
+        del scene
+        torch.cuda.empty_cache()
+        learned_res = learned_skip_section(amr, dev, max(3, args.steps // 2), 2)
+
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (FP64 oracle)...")
@@ -190,11 +263,11 @@ def main():
         "config": {
             "workload": "cosmology-like SAMR: root 128^3, 6 levels, r=2, %d patches 8^3..64^3 around peaks of a "
                         "seeded log-normal density (sigma_ln=2), %.2f GB pool; 1024x1024 perspective view, "
-                        "gradient lighting %s, plain traversal" % (len(h.patches), scene.scene.pool_bytes / 1e9,
+                        "gradient lighting %s, plain traversal" % (len(h.patches), pool_bytes / 1e9,
                                                                  "on" if prm["lighting"] else "off"),
             "width": W, "height": H, "patches": len(h.patches), "nodes": info["nodes"], "leaves": info["leaves"],
-            "pool_bytes": int(scene.scene.pool_bytes), "lighting": bool(prm["lighting"]),
-            "step_frac": prm["step_frac"], "t_min": prm["t_min"],
+            "pool_bytes": pool_bytes, "lighting": bool(prm["lighting"]),
+            "step_frac": prm["step_frac"], "t_min": prm["t_min"], "brick_layout": args.brick_layout,
         },
         "mrays_per_s": round(mrays, 3),
         "samples_per_frame": int(samples),
@@ -204,7 +277,7 @@ def main():
         "preprocess_s": {"generate": round(gen_s, 2), "build": round(build_s, 4), "pack_upload": round(pack_s, 3)},
         "roofline": roof,
         "cpu_baseline": cpu,
-        "learned_skip": None,
+        "learned_skip": learned_res,
     }
     print(json.dumps(line), flush=True)
 

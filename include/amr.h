@@ -117,7 +117,9 @@ void amr_tree_free(amr_tree *tree);
 typedef struct {
     int32_t host_dst;     /* 1: d_pool and d_meta are host pointers (plain memcpy, no HIP) */
     int32_t nthreads;     /* host threads for the ghost fill; 0 = hardware concurrency */
-    int32_t reserved_[6];
+    int32_t brick_layout; /* 0: each padded brick x-fastest; 1: padded brick stored as 4x4x4-cell
+                             micro-bricks (256 bytes each, x-fastest inside and between them) */
+    int32_t reserved_[5];
 } amr_pack_opts;
 
 /* Device view of a packed scene.  Filled by amr_pack_pool; every pointer points into the
@@ -127,9 +129,13 @@ typedef struct {
     const void *nodes;          /* device tree, breadth-first, 16 bytes per node */
     const void *leaves;         /* leaf records, 64 bytes each */
     const void *patches;        /* patch headers, 128 bytes each */
+    const void *leaf_faces;     /* per leaf, 6 int32 for the one-cell slab beyond each face:
+                                   v >= 0 the single patch owning it; v <= -2 several owners, and
+                                   node -2-v is the smallest tree node holding the slab; -1 the
+                                   slab leaves B */
     int64_t pool_bytes, meta_bytes;
     int32_t nnodes, nleaves, npatches, nlevels;
-    int32_t lmax, refine, depth, pad_;
+    int32_t lmax, refine, depth, brick_layout;
     double box_lo[3], box_hi[3];        /* B in world coordinates */
     double origin[3], h0[3], hfine[3];  /* hfine = h0 / refine^lmax */
     double step_fine;                   /* min_a h^lmax_a */
@@ -190,10 +196,19 @@ typedef struct {
     int64_t ckpt_bytes;
     int32_t ckpt_every;                 /* checkpoint every k-th data segment (>= 1) */
     int32_t ckpt_max;                   /* checkpoints per ray */
-    /* learned segment proposals (NULL = plain traversal) */
+    /* learned segment proposals (NULL = plain traversal).  alpha_max = 1 - exp(-sigma_max L)
+       is the analytic bound on a segment's opacity from the leaf's value range; the network
+       predicts quantiles (r_lo, r_hi) of alpha / alpha_max, clamped to [0, 1], and
+       alpha_hi = r_hi alpha_max, alpha_lo = r_lo alpha_max.  A data segment entered with
+       transmittance T is skipped if B + T * alpha_hi < tau_e (alpha_hi = alpha_max when the
+       bound alone decides), B being the sum of T * alpha_hi over the ray's earlier skips, so
+       the charged opacity of a ray stays below tau_e; it is sampled with one step per cell
+       and ends the ray if alpha_lo > 1 - tau_s; otherwise it is sampled plainly */
     const void *d_mlp;                  /* packed network, see amr_mlp_pack */
-    float tau_e, tau_s;                 /* skip if alpha_hi < tau_e; coarse if alpha_lo > 1 - tau_s */
-    void *d_seglog;                     /* segment log for training (amr_seglog_rec) */
+    float tau_e, tau_s;
+    /* segment log for training (device): a 256-byte header whose first 8 bytes count the
+       segments met, then amr_seglog_rec records; seglog_cap is the buffer size in bytes */
+    void *d_seglog;
     int64_t seglog_cap;
     /* scheduling */
     int32_t persistent;                 /* 1: persistent tile-queue kernel */
@@ -247,9 +262,13 @@ int amr_render_backward(const amr_scene *scene, const amr_camera *cams, int32_t 
 #define AMR_MLP_OUT 2
 
 typedef struct {                        /* one logged leaf segment (training data) */
-    float feat[AMR_MLP_IN];             /* features, see the design notes */
+    float feat[AMR_MLP_IN];             /* level/lmax, log2(L/h)/8, u_min, u_max, analytic
+                                           alpha bounds (max, mean, min extinction of the LUT over
+                                           the leaf's value range times L), n/256, |d_x|, |d_y|,
+                                           |d_z|, log2(min patch dim)/6 */
     float alpha_seg;                    /* true segment opacity 1 - prod(1 - alpha_k) */
-    float t_in;                         /* transmittance entering the segment */
+    float t_in;                         /* transmittance entering the segment; negative if early
+                                           termination cut the segment short */
     int32_t ray, n;
 } amr_seglog_rec;
 

@@ -106,12 +106,13 @@ class Scene:
     """Packed pool + device tree. On device, pool/meta are torch uint8 tensors on `device`;
     with host=True they are numpy arrays (no HIP involved)."""
 
-    def __init__(self, tree: Tree, h, device="cuda", host: bool = False, nthreads: int = 0):
+    def __init__(self, tree: Tree, h, device="cuda", host: bool = False, nthreads: int = 0, brick_layout: int = 1):
         self.lib = load()
         self.tree = tree
         opts = L.amr_pack_opts()
         opts.host_dst = 1 if host else 0
         opts.nthreads = int(nthreads)
+        opts.brick_layout = int(brick_layout)
         pb, mb = ctypes.c_int64(0), ctypes.c_int64(0)
         check(self.lib.amr_pack_pool(tree.ptr, tree._patches, len(h.patches), ctypes.byref(opts), None,
                                      ctypes.byref(pb), None, ctypes.byref(mb), None, None), "amr_pack_pool(size)")
@@ -135,23 +136,37 @@ class Scene:
 
     # host-side views (host=True scenes): padded bricks and device records
     def brick(self, p: int) -> np.ndarray:
+        """Padded brick of patch p as a (nz+2, ny+2, nx+2) array, whatever the pool layout."""
         assert self.host
         hdr = self.patch_headers()[p]
         nx, ny, nz = (int(v) for v in hdr["n"])
         pool = self.pool.view(np.float32)
         off = int(hdr["off"])
-        return pool[off:off + (nx + 2) * (ny + 2) * (nz + 2)].reshape(nz + 2, ny + 2, nx + 2)
+        if int(hdr["layout"]) == 0:
+            return pool[off:off + (nx + 2) * (ny + 2) * (nz + 2)].reshape(nz + 2, ny + 2, nx + 2)
+        bx, by, bz = (int(v) for v in hdr["nb"])
+        blocks = pool[off:off + bx * by * bz * 64].reshape(bz, by, bx, 4, 4, 4)
+        full = blocks.transpose(0, 3, 1, 4, 2, 5).reshape(4 * bz, 4 * by, 4 * bx)
+        return full[: nz + 2, : ny + 2, : nx + 2]
 
     def patch_headers(self) -> np.ndarray:
         dt = np.dtype([("off", np.uint64), ("n", np.int32, 3), ("level", np.int32), ("lo", np.float64, 3),
                        ("inv_h", np.float64, 3), ("h", np.float64, 3), ("step", np.float64),
-                       ("vmin", np.float32), ("vmax", np.float32), ("pad", np.int32, 4)])
+                       ("vmin", np.float32), ("vmax", np.float32), ("nb", np.int32, 3), ("layout", np.int32)])
         return self._records(self.scene.patches, dt, self.scene.npatches)
 
     def leaf_records(self) -> np.ndarray:
         dt = np.dtype([("lo", np.float64, 3), ("hi", np.float64, 3), ("patch", np.int32),
                        ("level_flags", np.uint32), ("vmin", np.float32), ("vmax", np.float32)])
         return self._records(self.scene.leaves, dt, self.scene.nleaves)
+
+    def leaf_face_owners(self) -> np.ndarray:
+        """[nleaves, 6] int32: patch owning the one-cell slab beyond each leaf face (-1: none/several)."""
+        base = self.meta.ctypes.data if self.host else self.meta.data_ptr()
+        off = self.scene.leaf_faces - base
+        raw = self.meta[off:off + self.scene.nleaves * 24]
+        raw = raw if self.host else raw.cpu().numpy()
+        return np.frombuffer(raw.tobytes(), dtype=np.int32).reshape(-1, 6)
 
     def node_records(self) -> np.ndarray:
         dt = np.dtype([("split", np.float64), ("child", np.uint32), ("meta", np.uint32)])
@@ -165,8 +180,8 @@ class Scene:
         return np.frombuffer(raw.tobytes(), dtype=dt)
 
 
-def pack(tree: Tree, h, device="cuda", host: bool = False, nthreads: int = 0) -> Scene:
-    return Scene(tree, h, device=device, host=host, nthreads=nthreads)
+def pack(tree: Tree, h, device="cuda", host: bool = False, nthreads: int = 0, brick_layout: int = 1) -> Scene:
+    return Scene(tree, h, device=device, host=host, nthreads=nthreads, brick_layout=brick_layout)
 
 
 def make_camera(cam: dict) -> L.amr_camera:

@@ -46,15 +46,16 @@ class amr_leaf_host(ctypes.Structure):
 
 
 class amr_pack_opts(ctypes.Structure):
-    _fields_ = [("host_dst", ctypes.c_int32), ("nthreads", ctypes.c_int32), ("reserved_", ctypes.c_int32 * 6)]
+    _fields_ = [("host_dst", ctypes.c_int32), ("nthreads", ctypes.c_int32), ("brick_layout", ctypes.c_int32),
+                ("reserved_", ctypes.c_int32 * 5)]
 
 
 class amr_scene(ctypes.Structure):
-    _fields_ = [("pool", VP), ("nodes", VP), ("leaves", VP), ("patches", VP),
+    _fields_ = [("pool", VP), ("nodes", VP), ("leaves", VP), ("patches", VP), ("leaf_faces", VP),
                 ("pool_bytes", ctypes.c_int64), ("meta_bytes", ctypes.c_int64),
                 ("nnodes", ctypes.c_int32), ("nleaves", ctypes.c_int32), ("npatches", ctypes.c_int32),
                 ("nlevels", ctypes.c_int32), ("lmax", ctypes.c_int32), ("refine", ctypes.c_int32),
-                ("depth", ctypes.c_int32), ("pad_", ctypes.c_int32),
+                ("depth", ctypes.c_int32), ("brick_layout", ctypes.c_int32),
                 ("box_lo", c_double3), ("box_hi", c_double3), ("origin", c_double3), ("h0", c_double3),
                 ("hfine", c_double3), ("step_fine", ctypes.c_double), ("v_min", ctypes.c_float),
                 ("v_max", ctypes.c_float)]

@@ -511,11 +511,13 @@ struct Packer {
     }
 };
 
-// Bit 2a+side is set when the one-cell slab (cells of the leaf's level) beyond that face lies
-// inside the leaf's patch and every leaf meeting it belongs to the same patch.
-uint32_t face_safe_mask(const amr_tree *T, const Node &lf) {
+// For each face 2a+side of a leaf: the patch owning the whole one-cell slab (cells of the
+// leaf's level) beyond the face when a single patch holds every leaf meeting it and the slab
+// lies inside B, else -1.  The returned mask has bit 2a+side set when that owner is the leaf's
+// own patch (the gradient tap then reads the same brick).
+uint32_t face_owners(const amr_tree *T, const Node &lf, const std::vector<int32_t> &bfs_index, int32_t owner[6]) {
+    for (int f = 0; f < 6; f++) owner[f] = -1;
     if (lf.patch < 0) return 0;
-    const Box &pb = T->pbox[lf.patch];
     const int64_t S = T->scale[T->plevel[lf.patch]];
     uint32_t mask = 0;
     std::vector<int> stack;
@@ -525,17 +527,34 @@ uint32_t face_safe_mask(const amr_tree *T, const Node &lf) {
             if (side) { lo[a] = lf.hi[a]; hi[a] = lf.hi[a] + S; }
             else { lo[a] = lf.lo[a] - S; hi[a] = lf.lo[a]; }
             bool ok = true;
-            for (int b = 0; b < 3; b++) ok = ok && lo[b] >= pb.lo[b] && hi[b] <= pb.hi[b];
+            for (int b = 0; b < 3; b++) ok = ok && lo[b] >= T->B_lo[b] && hi[b] <= T->B_hi[b];
+            const bool inB = ok;
+            int own = -2;
             stack.assign(1, 0);
             while (ok && !stack.empty()) {
                 int i = stack.back();
                 stack.pop_back();
                 const Node &n = T->nodes[i];
                 if (!box_overlap(n.lo, n.hi, lo, hi)) continue;
-                if (n.axis < 0) ok = n.patch == lf.patch;
-                else { stack.push_back(n.low); stack.push_back(n.high); }
+                if (n.axis >= 0) { stack.push_back(n.low); stack.push_back(n.high); continue; }
+                if (n.patch < 0 || (own != -2 && own != n.patch)) ok = false;
+                else own = n.patch;
             }
-            if (ok) mask |= 1u << (2 * a + side);
+            if (ok && own >= 0) {
+                owner[2 * a + side] = own;
+                if (own == lf.patch) mask |= 1u << (2 * a + side);
+            } else if (inB) {
+                // several owners: the smallest node whose box holds the whole slab (a rope)
+                int ni = 0;
+                while (T->nodes[ni].axis >= 0) {
+                    const Node &n = T->nodes[ni];
+                    const Node &lo_c = T->nodes[n.low];
+                    if (hi[n.axis] <= lo_c.hi[n.axis]) ni = n.low;
+                    else if (lo[n.axis] >= lo_c.hi[n.axis]) ni = n.high;
+                    else break;
+                }
+                owner[2 * a + side] = -2 - bfs_index[ni];
+            }
         }
     return mask;
 }
@@ -632,20 +651,25 @@ int amr_pack_pool(const amr_tree *T, const amr_patch *patches, int32_t npatches,
     if (!T || !patches || !pool_bytes || !meta_bytes) { set_error("null argument"); return AMR_EINVAL; }
     if (npatches != (int32_t)T->pbox.size()) { set_error("npatches differs from the tree's"); return AMR_EINVAL; }
     const int np = npatches;
-    // pool layout: 256-byte aligned padded bricks
+    const int layout = opts ? opts->brick_layout : 0;
+    if (layout != 0 && layout != 1) { set_error("brick_layout must be 0 or 1"); return AMR_EINVAL; }
+    // pool layout: 256-byte aligned padded bricks (linear, or 4^3 micro-bricks)
     std::vector<int64_t> off(np);
     int64_t nfl = 0;
     for (int p = 0; p < np; p++) {
         const int64_t *n = patches[p].dims;
         if (patches[p].level != T->plevel[p]) { set_error("patch %d differs from the tree's", p); return AMR_EINVAL; }
         off[p] = nfl;
-        nfl = align_up(nfl + (n[0] + 2) * (n[1] + 2) * (n[2] + 2), 64);
+        int64_t cells = layout == 0 ? (n[0] + 2) * (n[1] + 2) * (n[2] + 2)
+                                    : ((n[0] + 5) / 4) * ((n[1] + 5) / 4) * ((n[2] + 5) / 4) * 64;
+        nfl = align_up(nfl + cells, 64);
     }
     const int64_t nn = (int64_t)T->nodes.size(), nl = (int64_t)T->leaves.size();
     const int64_t o_nodes = 0;
     const int64_t o_leaves = align_up(o_nodes + nn * (int64_t)sizeof(DNode), 256);
     const int64_t o_patch = align_up(o_leaves + nl * (int64_t)sizeof(DLeaf), 256);
-    const int64_t mbytes = align_up(o_patch + np * (int64_t)sizeof(DPatch), 256);
+    const int64_t o_faces = align_up(o_patch + np * (int64_t)sizeof(DPatch), 256);
+    const int64_t mbytes = align_up(o_faces + nl * 6 * (int64_t)sizeof(int32_t), 256);
     const int64_t pbytes = std::max<int64_t>(nfl * 4, 256);
     if (!d_pool && !d_meta) {
         *pool_bytes = pbytes;
@@ -673,16 +697,27 @@ int amr_pack_pool(const amr_tree *T, const amr_patch *patches, int32_t npatches,
         float vmin = INFINITY, vmax = -INFINITY;
         for (int p = 0; p < np; p++) {
             const std::vector<double> &b = pk.brick[p];
-            for (size_t i = 0; i < b.size(); i++) pool[(size_t)off[p] + i] = (float)b[i];
+            int32_t n32[3], nb[3];
+            for (int a = 0; a < 3; a++) {
+                n32[a] = (int32_t)patches[p].dims[a];
+                nb[a] = (n32[a] + 5) / 4;
+            }
+            const int64_t px = n32[0] + 2, py = n32[1] + 2, pz = n32[2] + 2;
+            for (int64_t k = 0; k < pz; k++)
+                for (int64_t j = 0; j < py; j++)
+                    for (int64_t i = 0; i < px; i++)
+                        pool[(size_t)(off[p] + brick_index(layout, n32, nb, i, j, k))] = (float)b[(size_t)(i + px * (j + py * k))];
         }
         // device tree, breadth first with adjacent children
         DNode *dn = (DNode *)(meta.data() + o_nodes);
+        std::vector<int32_t> bfs_index(T->nodes.size(), -1);
         std::vector<int32_t> leaf_id(T->nodes.size(), -1);
         for (size_t k = 0; k < T->leaves.size(); k++) leaf_id[T->leaves[k]] = (int32_t)k;
         std::vector<int32_t> order{0};
         order.reserve(nn);
         for (size_t h = 0; h < order.size(); h++) {
             const Node &n = T->nodes[order[h]];
+            bfs_index[order[h]] = (int32_t)h;
             DNode &d = dn[h];
             if (n.axis < 0) {
                 d.split = 0.0;
@@ -706,6 +741,8 @@ int amr_pack_pool(const amr_tree *T, const amr_patch *patches, int32_t npatches,
             for (double v : pk.brick[p]) { pmin = std::min(pmin, (float)v); pmax = std::max(pmax, (float)v); }
             h.vmin = pmin;
             h.vmax = pmax;
+            for (int a = 0; a < 3; a++) h.nb[a] = ((int32_t)patches[p].dims[a] + 5) / 4;
+            h.layout = layout;
             vmin = std::min(vmin, pmin);
             vmax = std::max(vmax, pmax);
             double hmin = INFINITY;
@@ -728,7 +765,8 @@ int amr_pack_pool(const amr_tree *T, const amr_patch *patches, int32_t npatches,
             DLeaf &L = dl[k];
             for (int a = 0; a < 3; a++) { L.lo[a] = world_plane(T, a, n.lo[a]); L.hi[a] = world_plane(T, a, n.hi[a]); }
             L.patch = n.patch;
-            L.level_flags = (uint32_t)n.level | (face_safe_mask(T, n) << 8);
+            int32_t *own = (int32_t *)(meta.data() + o_faces) + 6 * k;
+            L.level_flags = (uint32_t)n.level | (face_owners(T, n, bfs_index, own) << 8);
             L.vmin = 0.0f;
             L.vmax = 0.0f;
             if (n.patch >= 0) {
@@ -741,11 +779,12 @@ int amr_pack_pool(const amr_tree *T, const amr_patch *patches, int32_t npatches,
                     i1[a] = (n.hi[a] - T->pbox[p].lo[a] + S - 1) / S;  // one past the last
                 }
                 const int64_t *d = patches[p].dims;
+                const std::vector<double> &bk = pk.brick[p];
                 float mn = INFINITY, mx = -INFINITY;
                 for (int64_t z = i0[2] - 1; z <= i1[2]; z++)
                     for (int64_t y = i0[1] - 1; y <= i1[1]; y++)
                         for (int64_t x = i0[0] - 1; x <= i1[0]; x++) {
-                            float v = pool[(size_t)off[p] + (size_t)((x + 1) + (d[0] + 2) * ((y + 1) + (d[1] + 2) * (z + 1)))];
+                            float v = (float)bk[(size_t)((x + 1) + (d[0] + 2) * ((y + 1) + (d[1] + 2) * (z + 1)))];
                             mn = std::min(mn, v);
                             mx = std::max(mx, v);
                         }
@@ -759,6 +798,7 @@ int amr_pack_pool(const amr_tree *T, const amr_patch *patches, int32_t npatches,
         out->nodes = (const uint8_t *)d_meta + o_nodes;
         out->leaves = (const uint8_t *)d_meta + o_leaves;
         out->patches = (const uint8_t *)d_meta + o_patch;
+        out->leaf_faces = (const uint8_t *)d_meta + o_faces;
         out->pool_bytes = pbytes;
         out->meta_bytes = mbytes;
         out->nnodes = (int32_t)nn;
@@ -768,6 +808,7 @@ int amr_pack_pool(const amr_tree *T, const amr_patch *patches, int32_t npatches,
         out->lmax = T->lmax;
         out->refine = T->dom.refine;
         out->depth = (int32_t)T->depth;
+        out->brick_layout = layout;
         double hmin = std::min(T->dom.h0[0], std::min(T->dom.h0[1], T->dom.h0[2]));
         double rl = 1.0;
         for (int k = 0; k < T->lmax; k++) rl *= (double)T->dom.refine;

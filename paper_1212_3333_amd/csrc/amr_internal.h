@@ -41,11 +41,18 @@ struct DPatch {
     double h[3];         // h^l
     double step;         // min_a h^l_a
     float vmin, vmax;
-    int32_t pad_[4];
+    int32_t nb[3];       // micro-brick layout: 4^3-cell blocks per axis of the padded brick
+    int32_t layout;      // 0 linear, 1 micro-bricks
 };
 static_assert(sizeof(DPatch) == 128, "DPatch layout");
 
 constexpr uint32_t kLeafAxis = 3u;
+
+// Offset (in floats) of padded-brick cell (i, j, k) (0 <= index <= n + 1) in either layout.
+inline int64_t brick_index(int layout, const int32_t *n, const int32_t *nb, int64_t i, int64_t j, int64_t k) {
+    if (layout == 0) return i + (int64_t)(n[0] + 2) * (j + (int64_t)(n[1] + 2) * k);
+    return (((k >> 2) * nb[1] + (j >> 2)) * nb[0] + (i >> 2)) * 64 + (k & 3) * 16 + (j & 3) * 4 + (i & 3);
+}
 
 inline uint32_t node_meta(int axis, int level) { return (uint32_t)(axis & 3) | ((uint32_t)(level & 63) << 2); }
 

@@ -1,0 +1,328 @@
+// Learned segment proposals (an addition to the paper's method) and the training-data logger.
+//
+// The outer loop is wave-uniform: in every round each live lane takes its next leaf segment
+// (kD-restart), computes 12 features, and the wave decides per lane whether to
+//   skip the segment        (B + T * alpha_hi < tau_e, where B sums T * alpha_hi over the ray's
+//                            earlier skips, so the skipped opacity of a whole ray stays below
+//                            tau_e),
+//   sample it coarsely      (alpha_lo > 1 - tau_s: step h^l instead of step_frac h^l, then
+//                            terminate the ray), or
+//   sample it as the plain traversal does (the fallback).
+// Every sample of the leaf lies in the leaf's value range, so the segment opacity is at most
+// alpha_max = 1 - exp(-sigma_max L) with sigma_max the largest extinction of the LUT over that
+// range; a lane whose bound already proves the skip needs no network.  The network
+// (12 -> 64 -> 64 -> 2, fp16 matrix cores, fp32 accumulation) predicts quantiles of the ratio
+// alpha / alpha_max in [0, 1], so its error scales with the bound instead of being a fixed
+// absolute error at the fp16 resolution; it runs on the 16-lane row tiles that hold
+// undecided lanes.  With d_mlp == NULL and d_seglog set, the
+// kernel renders plainly and logs (features, true segment opacity) for training.
+#include <hip/hip_runtime.h>
+
+#include "amr_mlp.h"
+#include "amr_render_common.h"
+
+namespace amr {
+
+struct SeglogHeader {
+    unsigned long long count;
+    unsigned long long pad_[31];
+};
+static_assert(sizeof(SeglogHeader) == 256, "seglog header");
+
+struct LearnArgs {
+    const MlpLds *mlp;         // packed network, NULL: log-only mode
+    float tau_e, tau_s;
+    uint8_t *seglog;           // SeglogHeader then amr_seglog_rec[cap]
+    int64_t seglog_cap;
+    int32_t lmax;
+};
+
+struct LearnLds {
+    float4 lut[256];
+    float bmax[16], bmin[16];  // extinction max/min per 16-entry bucket
+    float prefix[257];         // prefix sums of extinction
+    _Float16 w1t[64 * 16], w2t[64 * 64], w3t[16 * 64];
+    float b1[64], b2[64], b3[4];
+    _Float16 feat[4][64 * 16];
+    _Float16 h1[4][16 * 64], h2[4][16 * 64];
+    float out[4][64 * 2];
+};
+
+// Extinction range [smin, smax] and mean over LUT entries [i0, i1] (bucket-conservative bounds).
+__device__ __forceinline__ void sigma_range(const LearnLds &s, int i0, int i1, float &smin, float &smax, float &smean) {
+    const int b0 = i0 >> 4, b1 = i1 >> 4;
+    float mx = s.bmax[b0], mn = s.bmin[b0];
+    for (int b = b0 + 1; b <= b1; b++) {
+        mx = fmaxf(mx, s.bmax[b]);
+        mn = fminf(mn, s.bmin[b]);
+    }
+    smax = mx;
+    smin = mn;
+    smean = (s.prefix[i1 + 1] - s.prefix[i0]) / (float)(i1 - i0 + 1);
+}
+
+// Wave-level inference for row tile rt (lanes 16 rt .. 16 rt + 15) of this wave's features.
+__device__ __forceinline__ void infer_tile(LearnLds &s, int wave, int rt) {
+    const int lane = threadIdx.x & 63, lr = lane & 15, lq = lane >> 4;
+    const _Float16 *x16 = s.feat[wave] + rt * 16 * 16;
+    _Float16 *h1 = s.h1[wave], *h2 = s.h2[wave];
+    half4 a = *reinterpret_cast<const half4 *>(x16 + lr * 16 + 4 * lq);
+    #pragma unroll
+    for (int ct = 0; ct < 4; ct++) {
+        half4 b = *reinterpret_cast<const half4 *>(s.w1t + (ct * 16 + lr) * 16 + 4 * lq);
+        float4v acc = {0.f, 0.f, 0.f, 0.f};
+        acc = __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, acc, 0, 0, 0);
+        #pragma unroll
+        for (int j = 0; j < 4; j++) h1[(4 * lq + j) * 64 + ct * 16 + lr] = (_Float16)fmaxf(acc[j] + s.b1[ct * 16 + lr], 0.f);
+    }
+    __builtin_amdgcn_wave_barrier();
+    #pragma unroll
+    for (int ct = 0; ct < 4; ct++) {
+        float4v acc = {0.f, 0.f, 0.f, 0.f};
+        #pragma unroll
+        for (int ks = 0; ks < 4; ks++) {
+            half4 a2 = *reinterpret_cast<const half4 *>(h1 + lr * 64 + ks * 16 + 4 * lq);
+            half4 b = *reinterpret_cast<const half4 *>(s.w2t + (ct * 16 + lr) * 64 + ks * 16 + 4 * lq);
+            acc = __builtin_amdgcn_mfma_f32_16x16x16f16(a2, b, acc, 0, 0, 0);
+        }
+        #pragma unroll
+        for (int j = 0; j < 4; j++) h2[(4 * lq + j) * 64 + ct * 16 + lr] = (_Float16)fmaxf(acc[j] + s.b2[ct * 16 + lr], 0.f);
+    }
+    __builtin_amdgcn_wave_barrier();
+    float4v acc = {0.f, 0.f, 0.f, 0.f};
+    #pragma unroll
+    for (int ks = 0; ks < 4; ks++) {
+        half4 a3 = *reinterpret_cast<const half4 *>(h2 + lr * 64 + ks * 16 + 4 * lq);
+        half4 b = *reinterpret_cast<const half4 *>(s.w3t + lr * 64 + ks * 16 + 4 * lq);
+        acc = __builtin_amdgcn_mfma_f32_16x16x16f16(a3, b, acc, 0, 0, 0);
+    }
+    if (lr < kOut) {
+        #pragma unroll
+        for (int j = 0; j < 4; j++)
+            s.out[wave][(rt * 16 + 4 * lq + j) * 2 + lr] = 1.f / (1.f + __expf(-(acc[j] + s.b3[lr])));
+    }
+    __builtin_amdgcn_wave_barrier();
+}
+
+enum { kModePlain = 0, kModeSkip = 1, kModeCoarse = 2 };
+
+template <bool LIT>
+__global__ __launch_bounds__(256) void render_learned(RenderArgs A, LearnArgs G) {
+    __shared__ LearnLds s;
+    s.lut[threadIdx.x] = A.lut[threadIdx.x];
+    if (G.mlp) {
+        const MlpLds *m = G.mlp;
+        for (int i = threadIdx.x; i < 64 * 16; i += blockDim.x) { s.w1t[i] = m->w1t[i]; s.w3t[i] = m->w3t[i]; }
+        for (int i = threadIdx.x; i < 64 * 64; i += blockDim.x) s.w2t[i] = m->w2t[i];
+        if (threadIdx.x < 64) { s.b1[threadIdx.x] = m->b1[threadIdx.x]; s.b2[threadIdx.x] = m->b2[threadIdx.x]; }
+        if (threadIdx.x < 4) s.b3[threadIdx.x] = m->b3[threadIdx.x];
+    }
+    __syncthreads();
+    if (threadIdx.x < 16) {
+        float mx = -INFINITY, mn = INFINITY;
+        for (int i = 0; i < 16; i++) {
+            float v = s.lut[threadIdx.x * 16 + i].w;
+            mx = fmaxf(mx, v);
+            mn = fminf(mn, v);
+        }
+        s.bmax[threadIdx.x] = mx;
+        s.bmin[threadIdx.x] = mn;
+    }
+    if (threadIdx.x == 64) {
+        float acc = 0.f;
+        s.prefix[0] = 0.f;
+        for (int i = 0; i < 256; i++) { acc += s.lut[i].w; s.prefix[i + 1] = acc; }
+    }
+    __syncthreads();
+    const float4 *s_lut = s.lut;
+
+    const int per = (A.nblocks + 7) / 8;
+    const int tile = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+    if (tile >= A.nblocks) return;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int tx = tile % A.tiles_x, ty = tile / A.tiles_x;
+    const int pi = tx * 16 + (wave & 1) * 8 + (lane & 7);
+    const int pj = ty * 16 + (wave >> 1) * 8 + (lane >> 3);
+    const bool valid = pi < A.width && pj < A.height;
+    const int64_t ray = (int64_t)pj * A.width + pi;
+
+    Counters cnt;
+    unsigned int c_skip = 0, c_coarse = 0;
+    float C0 = 0.f, C1 = 0.f, C2 = 0.f, T = 1.f;
+    float budget = 0.f;                   // sum of T * alpha_hi over the segments skipped so far
+    int nsamp_total = 0;
+    Ray R;
+    bool alive = valid && setup_ray(A, pi, pj, R);
+    cnt.hit = alive ? 1 : 0;
+    double tcur = R.t0;
+    SeglogHeader *lh = reinterpret_cast<SeglogHeader *>(G.seglog);
+    amr_seglog_rec *lrec = reinterpret_cast<amr_seglog_rec *>(G.seglog + sizeof(SeglogHeader));
+    const float inv_lmax = 1.f / (float)(G.lmax > 0 ? G.lmax : 1);
+    while (true) {
+        const bool active = alive && tcur < R.t1;
+        if (!__any(active)) break;
+        double tb = R.t1;
+        int leaf = -1;
+        bool data = false;
+        Segment S;
+        float feat[kIn];
+        float a_bound_hi = 1.f;
+        float a_use = 1.f;                // upper bound charged to the skip budget
+        if (active) {
+            leaf = descend(A, R, tcur, tb);
+            if (leaf < 0) {
+                alive = false;
+            } else {
+                cnt.segments++;
+                const DLeaf &L = A.leaves[leaf];
+                data = L.patch >= 0;
+                if (data) {
+                    setup_segment<LIT>(A, R, L, leaf, tcur, tb, S);
+                    const DPatch &P = A.patches[L.patch];
+                    const float len = (float)(tb - tcur);
+                    const float umin = __saturatef((L.vmin - A.v_lo) * A.inv_range);
+                    const float umax = __saturatef((L.vmax - A.v_lo) * A.inv_range);
+                    const int i0 = min((int)(255.f * umin), 255);
+                    const int i1 = min((int)ceilf(255.f * umax), 255);
+                    float smin, smax, smean;
+                    sigma_range(s, i0, max(i0, i1), smin, smax, smean);
+                    feat[0] = (float)leaf_level(L) * inv_lmax;
+                    feat[1] = log2f(fmaxf(len / (float)P.step, 1e-3f)) * 0.125f;
+                    feat[2] = umin;
+                    feat[3] = umax;
+                    feat[4] = 1.f - __expf(-smax * 1.00001f * len);
+                    feat[5] = 1.f - __expf(-smean * len);
+                    feat[6] = 1.f - __expf(-smin * len);
+                    feat[7] = (float)min(S.n, 256) * (1.f / 256.f);
+                    feat[8] = (float)fabs(R.d[0]);
+                    feat[9] = (float)fabs(R.d[1]);
+                    feat[10] = (float)fabs(R.d[2]);
+                    feat[11] = log2f((float)min(P.n[0], min(P.n[1], P.n[2]))) * (1.f / 6.f);
+                    a_bound_hi = feat[4];
+                    a_use = a_bound_hi;
+                }
+            }
+        }
+        // decide: skip by the analytic bound, else ask the network (wave-level MFMA)
+        int mode = kModePlain;
+        if (G.mlp) {
+            const bool bound_skip = data && budget + T * a_bound_hi < G.tau_e;
+            const bool undecided = data && !bound_skip;
+            if (bound_skip) mode = kModeSkip;
+            const unsigned long long need = __ballot(undecided);
+            if (need) {
+                #pragma unroll
+                for (int j = 0; j < 16; j++)
+                    s.feat[wave][lane * 16 + j] = (_Float16)(undecided && j < kIn ? feat[j < kIn ? j : 0] : 0.f);
+                __builtin_amdgcn_wave_barrier();
+                #pragma unroll
+                for (int rt = 0; rt < 4; rt++)
+                    if ((need >> (16 * rt)) & 0xffffull) infer_tile(s, wave, rt);
+                if (undecided) {
+                    a_use = __saturatef(s.out[wave][lane * 2 + 1]) * a_bound_hi;
+                    const float a_lo = __saturatef(s.out[wave][lane * 2]) * a_bound_hi;
+                    if (budget + T * a_use < G.tau_e) mode = kModeSkip;
+                    else if (a_lo > 1.f - G.tau_s) mode = kModeCoarse;
+                }
+            }
+            if (mode == kModeSkip) budget += T * a_use;   // skipped opacity mass of this ray
+        }
+        float tseg = 1.f;
+        const float t_in = T;
+        bool full = true;
+        if (data && mode != kModeSkip) {
+            if (mode == kModeCoarse) {
+                // one step per cell of the leaf's level, then the ray stops after this segment
+#pragma clang fp contract(off)
+                const DPatch &P = A.patches[S.patch];
+                const double step = A.uniform_step ? A.step_fine : P.step;
+                const double nn = ceil((tb - tcur) / step - 0x1p-20);
+                S.n = nn < 1.0 ? 1 : (int)nn;
+                S.delta = (tb - tcur) / (double)S.n;
+                #pragma unroll
+                for (int a = 0; a < 3; a++) S.dq[a] = (float)(S.delta * R.d[a] * P.inv_h[a]);
+                S.dl = (float)S.delta * 1.44269504088896340736f;
+                c_coarse++;
+            }
+            for (int k = 0; k < S.n; k++) {
+                SampleVals v;
+                eval_sample<LIT, false>(A, s_lut, R, S, k, v, cnt);
+                float wgt = T * v.alpha * v.shade;
+                C0 += wgt * v.r;
+                C1 += wgt * v.g;
+                C2 += wgt * v.b;
+                T *= 1.f - v.alpha;
+                tseg *= 1.f - v.alpha;
+                nsamp_total++;
+                if (T < A.t_min) { alive = false; full = k + 1 == S.n; break; }
+            }
+            if (mode == kModeCoarse) alive = false;
+        } else if (data) {
+            c_skip++;
+        }
+        // training log: every plainly sampled data segment
+        if (G.seglog) {
+            const bool want = data && mode == kModePlain;
+            const unsigned long long mask = __ballot(want);
+            if (mask) {
+                unsigned long long base = 0;
+                if (lane == 0) base = atomicAdd(&lh->count, (unsigned long long)__popcll(mask));
+                base = __shfl(base, 0, 64);
+                if (want) {
+                    const unsigned long long slot = base + __popcll(mask & ((1ull << lane) - 1ull));
+                    if (slot < (unsigned long long)G.seglog_cap) {
+                        amr_seglog_rec r;
+                        #pragma unroll
+                        for (int j = 0; j < kIn; j++) r.feat[j] = feat[j];
+                        r.alpha_seg = 1.f - tseg;
+                        r.t_in = full ? t_in : -t_in;
+                        r.ray = (int32_t)ray;
+                        r.n = S.n;
+                        lrec[slot] = r;
+                    }
+                }
+            }
+        }
+        if (active && leaf >= 0) {
+            if (tb <= tcur) {
+                cnt.guard++;
+                tb = nextafter(tcur, INFINITY);
+            }
+            tcur = tb;
+        }
+    }
+    if (valid) reinterpret_cast<float4 *>(A.rgba)[ray] = make_float4(C0, C1, C2, 1.f - T);
+    if (A.nsamp && valid) A.nsamp[ray] = nsamp_total;
+    if (A.stats) {
+        cnt.samples = nsamp_total;
+        flush_counters(A.stats, cnt, lane);
+        typedef unsigned long long u64;
+        u64 sk = wave_sum((u64)c_skip), co = wave_sum((u64)c_coarse);
+        if (lane == 0) {
+            if (sk) atomicAdd(&A.stats->skipped_segments, sk);
+            if (co) atomicAdd(&A.stats->coarse_segments, co);
+        }
+    }
+}
+
+__global__ void seglog_reset(uint8_t *seglog) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) reinterpret_cast<SeglogHeader *>(seglog)->count = 0ull;
+}
+
+int launch_learned(const RenderArgs &A, const amr_render_params *P, int lmax, void *stream, bool first_camera) {
+    LearnArgs G;
+    G.mlp = (const MlpLds *)P->d_mlp;
+    G.tau_e = P->tau_e;
+    G.tau_s = P->tau_s;
+    G.seglog = (uint8_t *)P->d_seglog;
+    G.seglog_cap = P->d_seglog ? (P->seglog_cap - (int64_t)sizeof(SeglogHeader)) / (int64_t)sizeof(amr_seglog_rec) : 0;
+    G.lmax = lmax;
+    hipStream_t s = (hipStream_t)stream;
+    if (G.seglog && first_camera) hipLaunchKernelGGL(seglog_reset, dim3(1), dim3(64), 0, s, G.seglog);
+    int grid = ((A.nblocks + 7) / 8) * 8;
+    if (A.lighting) hipLaunchKernelGGL(render_learned<true>, dim3(grid), dim3(256), 0, s, A, G);
+    else hipLaunchKernelGGL(render_learned<false>, dim3(grid), dim3(256), 0, s, A, G);
+    return check_hip(hipGetLastError(), "render_learned launch");
+}
+
+}  // namespace amr

@@ -329,6 +329,16 @@ int amr_render(const amr_scene *S, const amr_camera *cams, int32_t ncams, const 
         A.stats = d_stats;
         A.touch = P->d_touch;
         A.ckpt_ray0 = pix_off;
+        if (P->d_mlp || P->d_seglog) {
+            if (P->d_trace || P->d_ckpt || P->d_touch) {
+                set_error("learned proposals / segment logging do not record traces, checkpoints or touch maps");
+                return AMR_EINVAL;
+            }
+            rc = launch_learned(A, P, S->lmax, stream, c == 0);
+            if (rc) return rc;
+            pix_off += (int64_t)cams[c].width * cams[c].height;
+            continue;
+        }
         int grid = ((A.nblocks + 7) / 8) * 8;
         const bool rec = A.trace || A.trace_n || A.nsamp || A.stats || A.touch || A.ckpt;
         if (A.lighting) {

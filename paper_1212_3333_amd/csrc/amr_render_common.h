@@ -28,6 +28,7 @@ struct RenderArgs {
     const DNode *nodes;
     const DLeaf *leaves;
     const DPatch *patches;
+    const int32_t *faces;            // [nleaves][6] slab owners
     const float4 *lut;
     double box_lo[3], box_hi[3];     // B (closed, for gradient taps)
     double clip_lo[3], clip_hi[3];   // B ∩ clip box
@@ -37,7 +38,7 @@ struct RenderArgs {
     int32_t ortho, width, height, depth;
     float v_lo, inv_range, step_frac, t_min;
     float lhat[3], inv_lnorm, k_a, k_d, eps2;
-    int32_t uniform_step, lighting;
+    int32_t uniform_step, lighting, micro;
     float *rgba;
     amr_trace_rec *trace;
     int32_t *trace_n;
@@ -158,9 +159,10 @@ __device__ __forceinline__ int descend(const RenderArgs &A, const Ray &R, double
     return -1;
 }
 
-// Leaf holding point x (half-open comparisons against the split planes).
-__device__ __forceinline__ int locate_leaf(const RenderArgs &A, const double x[3]) {
-    uint32_t ni = 0;
+// Leaf holding point x (half-open comparisons against the split planes), descending from
+// node `start` (the root, or a node known to hold x).
+__device__ __forceinline__ int locate_leaf(const RenderArgs &A, const double x[3], uint32_t start = 0) {
+    uint32_t ni = start;
     for (int it = 0; it <= A.depth; it++) {
         DNode n = A.nodes[ni];
         uint32_t axis = n.meta & 3u;
@@ -180,7 +182,7 @@ __device__ __forceinline__ float lerpf(float a, float b, float f) { return a + f
 
 struct PatchView {
     const float *brick;
-    int px, pxy, nx, ny, nz;
+    int px, pxy, nx, ny, nz;          // linear: row and slab strides; micro-bricks: 64 nbx, 64 nbx nby
 };
 
 __device__ __forceinline__ PatchView patch_view(const RenderArgs &A, const DPatch &P) {
@@ -189,8 +191,13 @@ __device__ __forceinline__ PatchView patch_view(const RenderArgs &A, const DPatc
     v.nx = P.n[0];
     v.ny = P.n[1];
     v.nz = P.n[2];
-    v.px = v.nx + 2;
-    v.pxy = v.px * (v.ny + 2);
+    if (A.micro) {
+        v.px = 64 * P.nb[0];
+        v.pxy = v.px * P.nb[1];
+    } else {
+        v.px = v.nx + 2;
+        v.pxy = v.px * (v.ny + 2);
+    }
     return v;
 }
 
@@ -205,35 +212,131 @@ __device__ __forceinline__ float trilinear(const RenderArgs &A, const PatchView 
     fx = qx - (float)ix;
     fy = qy - (float)iy;
     fz = qz - (float)iz;
-    const int px = pv.px, pxy = pv.pxy;
-    const float *b = pv.brick + (ix + 1) + (iy + 1) * px + (iz + 1) * pxy;
+    const float *b;
+    int dx, dy, dz;                   // offsets of the +1 neighbour along each axis
+    if (A.micro) {
+        // 4^3 micro-bricks: the +1 neighbour is in the same block unless the index is 3 mod 4
+        const int i = ix + 1, j = iy + 1, k = iz + 1;
+        b = pv.brick + ((k >> 2) * pv.pxy + (j >> 2) * pv.px + (i >> 2) * 64 + (k & 3) * 16 + (j & 3) * 4 + (i & 3));
+        dx = (i & 3) == 3 ? 61 : 1;
+        dy = (j & 3) == 3 ? pv.px - 12 : 4;
+        dz = (k & 3) == 3 ? pv.pxy - 48 : 16;
+    } else {
+        b = pv.brick + (ix + 1) + (iy + 1) * pv.px + (iz + 1) * pv.pxy;
+        dx = 1;
+        dy = pv.px;
+        dz = pv.pxy;
+    }
     if (REC && A.touch) {   // measurement only: mark the eight cells read
         uint64_t base = (uint64_t)(b - A.pool);
-        uint64_t offs[8] = {0, 1, (uint64_t)px, (uint64_t)px + 1, (uint64_t)pxy, (uint64_t)pxy + 1,
-                            (uint64_t)(pxy + px), (uint64_t)(pxy + px) + 1};
+        uint64_t offs[8] = {0, (uint64_t)dx, (uint64_t)dy, (uint64_t)(dx + dy), (uint64_t)dz, (uint64_t)(dz + dx),
+                            (uint64_t)(dz + dy), (uint64_t)(dz + dy + dx)};
         #pragma unroll
         for (int c = 0; c < 8; c++) {
             uint64_t e = base + offs[c];
             atomicOr(&A.touch[e >> 5], 1u << (e & 31));
         }
     }
-    float v000 = b[0], v100 = b[1], v010 = b[px], v110 = b[px + 1];
-    float v001 = b[pxy], v101 = b[pxy + 1], v011 = b[pxy + px], v111 = b[pxy + px + 1];
+    float v000 = b[0], v100 = b[dx], v010 = b[dy], v110 = b[dy + dx];
+    float v001 = b[dz], v101 = b[dz + dx], v011 = b[dz + dy], v111 = b[dz + dy + dx];
     float c00 = lerpf(v000, v100, fx), c10 = lerpf(v010, v110, fx);
     float c01 = lerpf(v001, v101, fx), c11 = lerpf(v011, v111, fx);
     float c0 = lerpf(c00, c10, fy), c1 = lerpf(c01, c11, fy);
     return lerpf(c0, c1, fz);
 }
 
+// Trilinear value F(q) and the central differences D_a = F(q + e_a) - F(q - e_a) of a padded
+// brick, for a point whose six one-cell taps all lie in the brick's interior (patch-local
+// index range [-0.5, n - 0.5] on every axis).  The taps use the centre's weights shifted by
+// one cell, so the seven stencils read 32 distinct cells: the 2x2x2 core and a 2x2 pair of
+// cells beyond it on each side of each axis.
+template <bool REC>
+__device__ __forceinline__ float trilinear_taps(const RenderArgs &A, const PatchView &pv, float qx, float qy,
+                                                float qz, float D[3]) {
+    float fx = floorf(qx), fy = floorf(qy), fz = floorf(qz);
+    // the interior condition gives floor(q) in [0, n - 2]; the clamp keeps every read in the
+    // brick regardless
+    const int ix = min(max((int)fx, 0), pv.nx - 2);
+    const int iy = min(max((int)fy, 0), pv.ny - 2);
+    const int iz = min(max((int)fz, 0), pv.nz - 2);
+    fx = qx - (float)ix;
+    fy = qy - (float)iy;
+    fz = qz - (float)iz;
+    // padded indices ix .. ix + 3 hold cells ix - 1 .. ix + 2; offsets are separable per axis
+    int xo[4], yo[4], zo[4];
+    #pragma unroll
+    for (int d = 0; d < 4; d++) {
+        const int i = ix + d, j = iy + d, k = iz + d;
+        if (A.micro) {
+            xo[d] = (i >> 2) * 64 + (i & 3);
+            yo[d] = (j >> 2) * pv.px + (j & 3) * 4;
+            zo[d] = (k >> 2) * pv.pxy + (k & 3) * 16;
+        } else {
+            xo[d] = i;
+            yo[d] = j * pv.px;
+            zo[d] = k * pv.pxy;
+        }
+    }
+    const float *b = pv.brick;
+    // c[x][y][z] for the core (indices 1, 2 on every axis) and the arms (0 or 3 on one axis)
+    float core[2][2][2], ax[2][2][2], ay[2][2][2], az[2][2][2];
+    #pragma unroll
+    for (int u = 0; u < 2; u++)
+        #pragma unroll
+        for (int v = 0; v < 2; v++)
+            #pragma unroll
+            for (int w = 0; w < 2; w++) {
+                core[u][v][w] = b[xo[1 + u] + yo[1 + v] + zo[1 + w]];
+                ax[u][v][w] = b[xo[3 * u] + yo[1 + v] + zo[1 + w]];      // x arm: side u, core (y, z)
+                ay[u][v][w] = b[xo[1 + v] + yo[3 * u] + zo[1 + w]];      // y arm: side u, core (x, z)
+                az[u][v][w] = b[xo[1 + v] + yo[1 + w] + zo[3 * u]];      // z arm: side u, core (x, y)
+            }
+    if (REC && A.touch) {   // measurement only: mark the 32 cells read
+        const uint64_t base = (uint64_t)(b - A.pool);
+        #pragma unroll
+        for (int u = 0; u < 2; u++)
+            #pragma unroll
+            for (int v = 0; v < 2; v++)
+                #pragma unroll
+                for (int w = 0; w < 2; w++) {
+                    const uint64_t e[4] = {base + (uint64_t)(xo[1 + u] + yo[1 + v] + zo[1 + w]),
+                                           base + (uint64_t)(xo[3 * u] + yo[1 + v] + zo[1 + w]),
+                                           base + (uint64_t)(xo[1 + v] + yo[3 * u] + zo[1 + w]),
+                                           base + (uint64_t)(xo[1 + v] + yo[1 + w] + zo[3 * u])};
+                    #pragma unroll
+                    for (int c = 0; c < 4; c++) atomicOr(&A.touch[e[c] >> 5], 1u << (e[c] & 31));
+                }
+    }
+    // value: the core's trilinear
+    const float c00 = lerpf(core[0][0][0], core[1][0][0], fx), c10 = lerpf(core[0][1][0], core[1][1][0], fx);
+    const float c01 = lerpf(core[0][0][1], core[1][0][1], fx), c11 = lerpf(core[0][1][1], core[1][1][1], fx);
+    const float F = lerpf(lerpf(c00, c10, fy), lerpf(c01, c11, fy), fz);
+    // F(q + e_x) - F(q - e_x) = sum_yz w_yz [(1 - fx)(c[2] - c[0]) + fx (c[3] - c[1])]
+    float dx[2][2], dy[2][2], dz[2][2];
+    #pragma unroll
+    for (int v = 0; v < 2; v++)
+        #pragma unroll
+        for (int w = 0; w < 2; w++) {
+            dx[v][w] = lerpf(core[1][v][w] - ax[0][v][w], ax[1][v][w] - core[0][v][w], fx);
+            dy[v][w] = lerpf(core[v][1][w] - ay[0][v][w], ay[1][v][w] - core[v][0][w], fy);
+            dz[v][w] = lerpf(core[v][w][1] - az[0][v][w], az[1][v][w] - core[v][w][0], fz);
+        }
+    D[0] = lerpf(lerpf(dx[0][0], dx[1][0], fy), lerpf(dx[0][1], dx[1][1], fy), fz);
+    D[1] = lerpf(lerpf(dy[0][0], dy[1][0], fx), lerpf(dy[0][1], dy[1][1], fx), fz);
+    D[2] = lerpf(lerpf(dz[0][0], dz[1][0], fx), lerpf(dz[0][1], dz[1][1], fx), fy);
+    return F;
+}
+
 // Field value at world point x located in the tree; false where no patch holds data or x is
 // outside B (closed).
 template <bool REC>
-__device__ __forceinline__ bool field_at(const RenderArgs &A, const double x[3], float *val, Counters &cnt) {
+__device__ __forceinline__ bool field_at(const RenderArgs &A, const double x[3], float *val, Counters &cnt,
+                                         uint32_t start = 0) {
 #pragma clang fp contract(off)
     #pragma unroll
     for (int a = 0; a < 3; a++)
         if (x[a] < A.box_lo[a] || x[a] > A.box_hi[a]) return false;
-    int leaf = locate_leaf(A, x);
+    int leaf = locate_leaf(A, x, start);
     if (REC) cnt.desc++;
     if (leaf < 0) return false;
     int p = A.leaves[leaf].patch;
@@ -296,7 +399,7 @@ struct SampleVals {
     float gv[3], dot, den;
 };
 
-enum { kTapSame = 0, kTapLocate = 1, kTapUnsure = 2 };
+enum { kTapSame = 0, kTapLocate = 1, kTapUnsure = 2, kTapFace = 3 };
 constexpr float kTapMargin = 1e-3f;   // cells; far above the fp32 error of patch-local positions
 
 // Where does the gradient tap q (the sample moved by +-1 cell along axis a) read its value?
@@ -316,13 +419,12 @@ __device__ __forceinline__ int classify_tap_fp32(const Segment &S, const float q
     }
     if (out_axis < 0) return kTapSame;
     const uint32_t face = 2u * a + (sgn ? 0u : 1u);
-    if (!((S.safe >> face) & 1u)) return kTapLocate;
     // inside the one-cell slab beyond the face?
     const float lim = sgn ? S.lq_lo[a] - 1.f : S.lq_hi[a] + 1.f;
     const float qa = q[a];
     const bool in_slab = sgn ? qa >= lim + kTapMargin : qa < lim - kTapMargin;
     const bool out_slab = sgn ? qa < lim - kTapMargin : qa >= lim + kTapMargin;
-    if (in_slab) return kTapSame;
+    if (in_slab) return ((S.safe >> face) & 1u) ? kTapSame : kTapFace;
     if (out_slab) return kTapLocate;
     return kTapUnsure;
 }
@@ -342,10 +444,22 @@ __device__ __forceinline__ int classify_tap_fp64(const RenderArgs &A, const Segm
     }
     if (in_leaf) return kTapSame;
     const uint32_t face = 2u * a + (sgn ? 0u : 1u);
-    if (!others || !((S.safe >> face) & 1u)) return kTapLocate;
+    if (!others) return kTapLocate;
     const double lim = sgn ? L.lo[a] - P.h[a] : L.hi[a] + P.h[a];
     const bool in_slab = sgn ? (xt[a] >= lim && xt[a] < L.lo[a]) : (xt[a] >= L.hi[a] && xt[a] < lim);
-    return in_slab ? kTapSame : kTapLocate;
+    if (!in_slab) return kTapLocate;
+    return ((S.safe >> face) & 1u) ? kTapSame : kTapFace;
+}
+
+// Value of patch p at world point x (x known to lie in p's data region).
+template <bool REC>
+__device__ __forceinline__ float patch_value_at(const RenderArgs &A, int p, const double x[3]) {
+    const DPatch &P = A.patches[p];
+    PatchView pv = patch_view(A, P);
+    float q[3];
+    #pragma unroll
+    for (int a = 0; a < 3; a++) q[a] = (float)((x[a] - P.lo[a]) * P.inv_h[a] - 0.5);
+    return trilinear<REC>(A, pv, q[0], q[1], q[2]);
 }
 
 // Sample k of a segment: value, LUT classification, opacity over the step, and (LIT) the
@@ -355,7 +469,74 @@ __device__ __forceinline__ void eval_sample(const RenderArgs &A, const float4 *s
                                             int k, SampleVals &v, Counters &cnt) {
     const float kk = (float)k + 0.5f;
     const float qx = S.q0[0] + kk * S.dq[0], qy = S.q0[1] + kk * S.dq[1], qz = S.q0[2] + kk * S.dq[2];
-    const float F = trilinear<REC>(A, S.pv, qx, qy, qz);
+    float F;
+    if (LIT) {
+        // classify the six taps x +- h^l e_a first: when all stay in this brick one fused
+        // stencil gives the value and the three differences
+        const float qc[3] = {qx, qy, qz};
+        int cls[3][2];
+        bool all_same = true;
+        #pragma unroll
+        for (int a = 0; a < 3; a++)
+            #pragma unroll
+            for (int sgn = 0; sgn < 2; sgn++) {
+                float qt[3] = {qc[0], qc[1], qc[2]};
+                qt[a] += sgn ? -1.f : 1.f;
+                cls[a][sgn] = classify_tap_fp32(S, qt, a, sgn);
+                all_same = all_same && cls[a][sgn] == kTapSame;
+            }
+        if (all_same) {
+            float D[3];
+            F = trilinear_taps<REC>(A, S.pv, qx, qy, qz, D);
+            #pragma unroll
+            for (int a = 0; a < 3; a++) v.gv[a] = D[a] * (0.5f * A.inv_range);
+        } else {
+            F = trilinear<REC>(A, S.pv, qx, qy, qz);
+            #pragma unroll
+            for (int a = 0; a < 3; a++) {
+                float Fs[2];
+                bool ok[2];
+                #pragma unroll
+                for (int sgn = 0; sgn < 2; sgn++) {
+                    float qt[3] = {qc[0], qc[1], qc[2]};
+                    qt[a] += sgn ? -1.f : 1.f;
+                    int c = cls[a][sgn];
+                    double xt[3];
+                    if (c != kTapSame) {
+                        // exact FP64 tap position: x = o + t_k d, then +- h^l along axis a
+#pragma clang fp contract(off)
+                        const double tk = S.ta + ((double)k + 0.5) * S.delta;
+                        #pragma unroll
+                        for (int b = 0; b < 3; b++) xt[b] = R.o[b] + tk * R.d[b];
+                        const double hl = A.patches[S.patch].h[a];
+                        xt[a] = sgn ? xt[a] - hl : xt[a] + hl;
+                        if (c == kTapUnsure) c = classify_tap_fp64(A, S, xt, a, sgn);
+                    }
+                    int owner = -1;
+                    if (c == kTapFace) owner = A.faces[6 * S.leaf + 2 * a + (sgn ? 0 : 1)];
+                    if (c == kTapSame) {
+                        Fs[sgn] = trilinear<REC>(A, S.pv, qt[0], qt[1], qt[2]);
+                        ok[sgn] = true;
+                    } else if (owner >= 0) {
+                        Fs[sgn] = patch_value_at<REC>(A, owner, xt);      // the slab's single owner
+                        ok[sgn] = true;
+                    } else {
+                        // descend from the rope node holding the slab, else from the root
+                        const uint32_t start = owner <= -2 ? (uint32_t)(-2 - owner) : 0u;
+                        ok[sgn] = field_at<REC>(A, xt, &Fs[sgn], cnt, start);
+                    }
+                }
+                float gr;
+                if (ok[0] && ok[1]) gr = (Fs[0] - Fs[1]) * (0.5f * A.inv_range);
+                else if (ok[0]) gr = (Fs[0] - F) * A.inv_range;
+                else if (ok[1]) gr = (F - Fs[1]) * A.inv_range;
+                else gr = 0.f;
+                v.gv[a] = gr;
+            }
+        }
+    } else {
+        F = trilinear<REC>(A, S.pv, qx, qy, qz);
+    }
     v.F = F;
     const float u = __saturatef((F - A.v_lo) * A.inv_range);
     const float xs = 255.f * u;
@@ -371,41 +552,6 @@ __device__ __forceinline__ void eval_sample(const RenderArgs &A, const float4 *s
     v.alpha = 1.f - exp2f(-v.sig * S.dl);
     v.shade = 1.f;
     if (LIT) {
-        const float qc[3] = {qx, qy, qz};
-        #pragma unroll
-        for (int a = 0; a < 3; a++) {
-            float Fs[2];
-            bool ok[2];
-            #pragma unroll
-            for (int sgn = 0; sgn < 2; sgn++) {
-                float qt[3] = {qc[0], qc[1], qc[2]};
-                qt[a] += sgn ? -1.f : 1.f;
-                int cls = classify_tap_fp32(S, qt, a, sgn);
-                double xt[3];
-                if (cls != kTapSame) {
-                    // exact FP64 tap position: x = o + t_k d, then +- h^l along axis a
-#pragma clang fp contract(off)
-                    const double tk = S.ta + ((double)k + 0.5) * S.delta;
-                    #pragma unroll
-                    for (int b = 0; b < 3; b++) xt[b] = R.o[b] + tk * R.d[b];
-                    const double hl = A.patches[S.patch].h[a];
-                    xt[a] = sgn ? xt[a] - hl : xt[a] + hl;
-                    if (cls == kTapUnsure) cls = classify_tap_fp64(A, S, xt, a, sgn);
-                }
-                if (cls == kTapSame) {
-                    Fs[sgn] = trilinear<REC>(A, S.pv, qt[0], qt[1], qt[2]);
-                    ok[sgn] = true;
-                } else {
-                    ok[sgn] = field_at<REC>(A, xt, &Fs[sgn], cnt);
-                }
-            }
-            float gr;
-            if (ok[0] && ok[1]) gr = (Fs[0] - Fs[1]) * (0.5f * A.inv_range);
-            else if (ok[0]) gr = (Fs[0] - F) * A.inv_range;
-            else if (ok[1]) gr = (F - Fs[1]) * A.inv_range;
-            else gr = 0.f;
-            v.gv[a] = gr;
-        }
         v.dot = v.gv[0] * A.lhat[0] + v.gv[1] * A.lhat[1] + v.gv[2] * A.lhat[2];
         v.den = sqrtf(v.gv[0] * v.gv[0] + v.gv[1] * v.gv[1] + v.gv[2] * v.gv[2] + A.eps2);
         v.shade = A.k_a + (v.den > 0.f ? A.k_d * fabsf(v.dot) / v.den : 0.f);
@@ -464,6 +610,7 @@ inline int fill_args(const amr_scene *S, const amr_camera *C, const amr_render_p
     A->nodes = (const DNode *)S->nodes;
     A->leaves = (const DLeaf *)S->leaves;
     A->patches = (const DPatch *)S->patches;
+    A->faces = (const int32_t *)S->leaf_faces;
     A->lut = (const float4 *)P->d_lut;
     #pragma unroll
     for (int a = 0; a < 3; a++) {
@@ -497,6 +644,7 @@ inline int fill_args(const amr_scene *S, const amr_camera *C, const amr_render_p
     A->eps2 = P->eps_g * P->eps_g;
     A->uniform_step = P->uniform_step;
     A->lighting = P->lighting;
+    A->micro = S->brick_layout;
     A->tiles_x = (C->width + 15) / 16;
     A->tiles_y = (C->height + 15) / 16;
     A->nblocks = A->tiles_x * A->tiles_y;
@@ -506,6 +654,9 @@ inline int fill_args(const amr_scene *S, const amr_camera *C, const amr_render_p
     A->ckpt_max = P->ckpt_max;
     return AMR_OK;
 }
+
+// Learned-proposal / segment-logging launch for one camera (amr_learned.hip).
+int launch_learned(const RenderArgs &A, const amr_render_params *P, int lmax, void *stream, bool first_camera);
 
 // Persistent multi-camera launch (amr_batched.hip).
 int launch_persistent(const amr_scene *S, const amr_camera *cams, int32_t ncams, const amr_render_params *P,

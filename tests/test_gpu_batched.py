@@ -12,7 +12,7 @@ pytestmark = pytest.mark.gpu
 def tiny(gpu):
     import torch
     amr = gpu
-    h, lut, cams, prm = workloads.config1(0)
+    h, lut, cams, prm = workloads.small_nested(0)
     tree = amr.build_tree(h)
     scene = amr.pack(tree, h, device="cuda")
     torch.cuda.synchronize()

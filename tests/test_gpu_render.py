@@ -51,9 +51,9 @@ def _compare_traces(amr, gout, ores, nrays_expect=None):
 @pytest.mark.parametrize("lit", [False, True])
 @pytest.mark.parametrize("uniform", [False, True])
 @pytest.mark.parametrize("cam_idx", [0, 1])
-def test_config1_full_image(gpu, cam_idx, uniform, lit):
+def test_small_nested_full_image(gpu, cam_idx, uniform, lit):
     amr = gpu
-    h, lut, cams, prm = workloads.config1(0)
+    h, lut, cams, prm = workloads.small_nested(0)
     cam = cams[cam_idx]
     prm = dict(prm, uniform_step=uniform, lighting=lit)
     tree, scene = _setup(amr, h)
@@ -62,7 +62,7 @@ def test_config1_full_image(gpu, cam_idx, uniform, lit):
     ores = O.render(cam, prm, lut, trace_cap=64)
     rgba = gout["rgba"].cpu().numpy().reshape(-1, 4).astype(np.float64)
     err = np.abs(rgba - ores["rgba"]).max()
-    print("config1 cam%d uniform=%d lit=%d max|err|=%.3g" % (cam_idx, uniform, lit, err))
+    print("small_nested cam%d uniform=%d lit=%d max|err|=%.3g" % (cam_idx, uniform, lit, err))
     assert err <= TOL
     _compare_traces(amr, gout, ores)
     st = amr.stats_dict(gout)
@@ -77,7 +77,7 @@ def test_constant_field_gpu(gpu, lit):
     amr = gpu
     cv = 0.6
     h = workloads.tiny_samr(2).with_field(workloads.constant_field(cv))
-    lut = workloads.lut_config1(3)
+    lut = workloads.lut_small_nested(3)
     prm = workloads.default_params(v_lo=0.0, v_hi=1.0, t_min=0.0, lighting=lit, k_a=0.25, k_d=0.75)
     cam = workloads.perspective_orbit(48, 40, 0.4, 0.35, radius=1.6)
     tree, scene = _setup(amr, h)
@@ -151,7 +151,7 @@ def test_random_hierarchies(gpu, seed):
 
 def test_degenerate_views(gpu):
     amr = gpu
-    h, lut, cams, prm = workloads.config1(0)
+    h, lut, cams, prm = workloads.small_nested(0)
     tree, scene = _setup(amr, h)
     # one pixel
     cam = workloads.ortho_axis_z(1, 1)
@@ -170,7 +170,7 @@ def test_degenerate_views(gpu):
 def test_invalid_arguments(gpu):
     amr = gpu
     import torch
-    h, lut, cams, prm = workloads.config1(0)
+    h, lut, cams, prm = workloads.small_nested(0)
     tree, scene = _setup(amr, h)
     lut_t = torch.from_numpy(lut).cuda()
     with pytest.raises(amr.AMRError):
@@ -182,9 +182,9 @@ def test_invalid_arguments(gpu):
 
 
 @pytest.fixture(scope="module")
-def config2_scene(gpu):
+def cosmology_scene(gpu):
     amr = gpu
-    h, lut, cam, prm = workloads.config2(0)
+    h, lut, cam, prm = workloads.cosmology_view(0)
     tree, scene = _setup(amr, h)
     return h, lut, cam, prm, tree, scene
 
@@ -201,12 +201,12 @@ def _sample_pixels(W, H, seed):
 
 
 @pytest.mark.parametrize("lit", [True, False])
-def test_config2_full_size_sampled(gpu, config2_scene, lit):
+def test_cosmology_full_size_sampled(gpu, cosmology_scene, lit):
     """The 1024x1024 cosmology-like frame in the launch configuration the benchmark times;
     the oracle checks 3000 random pixels, two full rows and a 32x32 crop."""
     import torch
     amr = gpu
-    h, lut, cam, prm, tree, scene = config2_scene
+    h, lut, cam, prm, tree, scene = cosmology_scene
     prm = dict(prm, lighting=lit)
     W, H = cam["width"], cam["height"]
     cap = 192
@@ -218,7 +218,7 @@ def test_config2_full_size_sampled(gpu, config2_scene, lit):
     del out
     ores = oracle.Oracle(h).render(cam, prm, lut, pixels=pix, trace_cap=cap)
     err = np.abs(rgba - ores["rgba"]).max()
-    print("config2 lit=%d: %d pixels, max|err| = %.3g, max segments %d" % (lit, len(pix), err, ores["trace_n"].max()))
+    print("cosmology_view lit=%d: %d pixels, max|err| = %.3g, max segments %d" % (lit, len(pix), err, ores["trace_n"].max()))
     assert err <= TOL
     assert ores["trace_n"].max() <= cap
     _compare_traces(amr, sub, ores)

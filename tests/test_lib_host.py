@@ -49,7 +49,7 @@ def _compare_trees(h):
     return tree
 
 
-def test_builder_equals_naive_config1():
+def test_builder_equals_naive_small_nested():
     _compare_trees(workloads.tiny_samr(0))
 
 
@@ -71,16 +71,17 @@ def test_builder_shuffle_invariance():
 
 def _compare_ghosts(h):
     tree = amr.build_tree(h)
-    scene = amr.pack(tree, h, host=True, nthreads=3)
     O = Oracle(h)
-    for p in range(len(h.patches)):
-        got = scene.brick(p)
-        ref = O.padded_brick(p).astype(np.float32)
-        assert np.array_equal(got, ref), p
+    for layout in (0, 1):
+        scene = amr.pack(tree, h, host=True, nthreads=3, brick_layout=layout)
+        for p in range(len(h.patches)):
+            got = scene.brick(p)
+            ref = O.padded_brick(p).astype(np.float32)
+            assert np.array_equal(got, ref), (layout, p)
     return scene
 
 
-def test_ghosts_bit_exact_config1():
+def test_ghosts_bit_exact_small_nested():
     _compare_ghosts(workloads.tiny_samr(0))
 
 
@@ -186,6 +187,7 @@ def test_pack_capacity_and_size_query():
                              None, ctypes.byref(mb), None, None) == 0
     expect_pool = sum(((int(p.dims[0]) + 2) * (int(p.dims[1]) + 2) * (int(p.dims[2]) + 2) + 63) // 64 * 64 * 4
                       for p in h.patches)
+    opts.brick_layout = 0
     assert pb.value == expect_pool
     pool = np.zeros(pb.value - 4, dtype=np.uint8)
     meta = np.zeros(mb.value, dtype=np.uint8)
@@ -223,3 +225,63 @@ def test_leaf_value_range():
         sub = b[lo[2]:hi[2] + 2, lo[1]:hi[1] + 2, lo[0]:hi[0] + 2]
         assert lr[k]["vmin"] == sub.min() and lr[k]["vmax"] == sub.max()
     assert s > 0
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_leaf_face_owners(seed):
+    """Where the table names an owner, every point of the one-cell slab beyond the face lies in
+    that patch's data (checked with the oracle's point location); the safe bits mark the faces
+    owned by the leaf's own patch."""
+    h = workloads.random_tiny(seed, multi_root=(seed == 1)) if seed < 2 else workloads.tiny_samr(0)
+    tree = amr.build_tree(h)
+    scene = amr.pack(tree, h, host=True)
+    _, leaves = tree.export()
+    own = scene.leaf_face_owners()
+    flags = scene.leaf_records()["level_flags"]
+    O = Oracle(h)
+    hf = h.h0 / h.refine ** (h.nlevels - 1)
+    rng = np.random.default_rng(seed)
+    named = 0
+    ropes = []
+    for k, lf in enumerate(leaves):
+        if lf["patch"] < 0:
+            assert np.all(own[k] == -1)
+            continue
+        S = h.refine ** (h.lmax - int(lf["level"]))
+        for f in range(6):
+            a, side = f // 2, f % 2
+            assert bool((flags[k] >> (8 + f)) & 1) == (own[k, f] == lf["patch"])
+            if own[k, f] <= -2:
+                ropes.append((k, f, -2 - own[k, f]))
+            if own[k, f] < 0:
+                continue
+            named += 1
+            lo, hi = lf["lo"].astype(np.float64), lf["hi"].astype(np.float64)
+            if side:
+                lo[a], hi[a] = hi[a], hi[a] + S
+            else:
+                lo[a], hi[a] = lo[a] - S, lo[a]
+            for _ in range(4):
+                x = h.origin + (lo + rng.random(3) * (hi - lo)) * hf
+                assert O.locate(x) == own[k, f]
+    assert named > 0
+    # ropes: descending from the stored node reaches the same leaf as descending from the root
+    dn = scene.node_records()
+
+    def descend(x, start):
+        ni = start
+        while (dn[ni]["meta"] & 3) != 3:
+            ax = dn[ni]["meta"] & 3
+            ni = dn[ni]["child"] + (0 if x[ax] < dn[ni]["split"] else 1)
+        return dn[ni]["child"]
+    for k, f, node in ropes:
+        a, side = f // 2, f % 2
+        S = h.refine ** (h.lmax - int(leaves[k]["level"]))
+        lo, hi = leaves[k]["lo"].astype(np.float64), leaves[k]["hi"].astype(np.float64)
+        if side:
+            lo[a], hi[a] = hi[a], hi[a] + S
+        else:
+            lo[a], hi[a] = lo[a] - S, lo[a]
+        for _ in range(4):
+            x = h.origin + (lo + rng.random(3) * (hi - lo)) * hf
+            assert descend(x, node) == descend(x, 0)

@@ -46,7 +46,7 @@ def _check_partition(h, tree):
             assert best == p
 
 
-def test_partition_config1():
+def test_partition_small_nested():
     h = workloads.tiny_samr(0)
     tree = kdbuild.build(finest_boxes(h), h.nlevels)
     _check_partition(h, tree)

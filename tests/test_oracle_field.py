@@ -59,7 +59,7 @@ def test_constant_field_everywhere():
 
 def _linear_hierarchy(seed):
     a = np.array([0.7, -0.4, 0.25])
-    # a properly nested hierarchy (config 1 geometry); the linear function takes values that
+    # a properly nested hierarchy (the small nested geometry); the linear function takes values that
     # are exact in fp32 at cell centres when a and the centres are dyadic
     h = workloads.tiny_samr(seed)
     return h.with_field(workloads.linear_field(a, 0.5)), a

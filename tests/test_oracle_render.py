@@ -81,7 +81,7 @@ def test_constant_field_closed_form(cam_name, lit):
     shade = k_a when lit (the gradient vanishes exactly), 1 when unlit."""
     cv = 0.6
     h = workloads.tiny_samr(2).with_field(workloads.constant_field(cv))
-    lut = workloads.lut_config1(3)
+    lut = workloads.lut_small_nested(3)
     prm = workloads.default_params(v_lo=0.0, v_hi=1.0, t_min=0.0, lighting=lit, k_a=0.25, k_d=0.75)
     cam = CAMS[cam_name]
     O = Oracle(h)
@@ -215,7 +215,7 @@ def test_single_level_matches_scipy(lit):
 
 
 def _brute_check_segments(h, O, cam, prm, pixels):
-    res = O.render(cam, prm, workloads.lut_config1(0), pixels=pixels, trace_cap=512)
+    res = O.render(cam, prm, workloads.lut_small_nested(0), pixels=pixels, trace_cap=512)
     boxes = finest_boxes(h)
     L = O.tree.leaf_array()
     L_lo = h.origin + L[:, 0:3] * (h.h0 / h.refine ** (h.nlevels - 1))
@@ -262,10 +262,10 @@ def _brute_check_segments(h, O, cam, prm, pixels):
 
 @pytest.mark.parametrize("uniform", [False, True])
 @pytest.mark.parametrize("cam_idx", [0, 1])
-def test_segment_ids_brute_force_config1(cam_idx, uniform):
+def test_segment_ids_brute_force_small_nested(cam_idx, uniform):
     h = workloads.tiny_samr(0)
     O = Oracle(h)
-    cam = workloads.config1_cameras(64, 64)[cam_idx]
+    cam = workloads.small_nested_cameras(64, 64)[cam_idx]
     prm = workloads.default_params(uniform_step=uniform, t_min=0.0)
     rng = np.random.default_rng(cam_idx)
     pix = np.stack([rng.integers(0, 64, 150), rng.integers(0, 64, 150)], 1).astype(np.int32)
@@ -285,7 +285,7 @@ def test_segment_ids_brute_force_random(seed):
 
 
 def test_early_termination_bound():
-    h, lut, cams, prm = workloads.config1(0)
+    h, lut, cams, prm = workloads.small_nested(0)
     lut = lut.copy(); lut[:, 3] *= 20
     O = Oracle(h)
     for lit in (False, True):
@@ -300,7 +300,7 @@ def test_early_termination_bound():
 
 
 def test_shuffle_invariance_image():
-    h, lut, cams, prm = workloads.config1(0)
+    h, lut, cams, prm = workloads.small_nested(0)
     hs = h.shuffled(3)
     r1 = Oracle(h).render(cams[1], dict(prm, lighting=True), lut)
     r2 = Oracle(hs).render(cams[1], dict(prm, lighting=True), lut)
@@ -310,10 +310,10 @@ def test_shuffle_invariance_image():
 @pytest.mark.parametrize("lit", [False, True])
 def test_gradient_vs_finite_difference(lit):
     """Reverse-mode dL/dLUT and dL/d(light, k_a, k_d) against FP64 central differences."""
-    h, lut, cams, prm = workloads.config1(1)
+    h, lut, cams, prm = workloads.small_nested(1)
     prm = dict(prm, t_min=0.0, lighting=lit, light=(0.3, 1.0, -0.6), k_a=0.3, k_d=0.7)
     O = Oracle(h)
-    cam = workloads.config1_cameras(48, 48)[1]
+    cam = workloads.small_nested_cameras(48, 48)[1]
     rng = np.random.default_rng(4)
     pix = np.stack([rng.integers(0, 48, 60), rng.integers(0, 48, 60)], 1).astype(np.int32)
     W = rng.normal(size=(len(pix), 4))
@@ -353,7 +353,7 @@ def test_constant_field_sigma_derivative():
     weights (1-f, f)."""
     cv = 0.5
     h = workloads.tiny_samr(2).with_field(workloads.constant_field(cv))
-    lut = workloads.lut_config1(3).astype(np.float64)
+    lut = workloads.lut_small_nested(3).astype(np.float64)
     prm = workloads.default_params(v_lo=0.0, v_hi=1.0, t_min=0.0)
     cam = workloads.ortho_axis_z(8, 8)
     O = Oracle(h)

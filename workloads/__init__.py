@@ -88,9 +88,9 @@ class Hierarchy:
                          [self.patches[i] for i in perm])
 
 
-def _rng(config: int, stream: str, seed: int = MASTER_SEED) -> np.random.Generator:
+def _rng(workload: int, stream: str, seed: int = MASTER_SEED) -> np.random.Generator:
     names = ["field", "patches", "lut", "cameras", "mlp_init", "train_views", "eval_views", "misc"]
-    ss = np.random.SeedSequence(seed).spawn(8)[config]
+    ss = np.random.SeedSequence(seed).spawn(8)[workload]
     child = ss.spawn(len(names))[names.index(stream)]
     return np.random.default_rng(child)
 
@@ -137,7 +137,7 @@ def _empty_patch(level, lo, dims) -> Patch:
 
 
 def tiny_samr(seed: int = 0) -> Hierarchy:
-    """Config 1 geometry: root 32^3 on [0,1]^3, r = 2, four level-1 patches of 8..16
+    """Small nested geometry: root 32^3 on [0,1]^3, r = 2, four level-1 patches of 8..16
     coarse cells per axis at cell-aligned random positions, pairwise disjoint
     (same-level SAMR patches never overlap), field = sum of 8 Gaussians."""
     rng = _rng(0, "patches", MASTER_SEED + seed)
@@ -217,7 +217,7 @@ def lut_bumps(rng: np.random.Generator, sigma_scale: float = 20.0, power: float 
     return lut.astype(np.float32)
 
 
-def lut_config1(seed: int = 0) -> np.ndarray:
+def lut_small_nested(seed: int = 0) -> np.ndarray:
     return lut_bumps(_rng(0, "lut", MASTER_SEED + seed))
 
 
@@ -280,7 +280,7 @@ def perspective_orbit(width, height, az, el, radius=2.0, centre=(0.5, 0.5, 0.5),
     return camera(e, u, v, w, width, height, ortho=False, tan_half_fov=math.tan(math.radians(fov_deg) / 2))
 
 
-def config1_cameras(width=256, height=256):
+def small_nested_cameras(width=256, height=256):
     return [ortho_axis_z(width, height), ortho_oblique(width, height)]
 
 
@@ -292,11 +292,11 @@ def default_params(**kw) -> dict:
     return p
 
 
-def config1(seed: int = 0):
+def small_nested(seed: int = 0):
     """Tiny SAMR workload: hierarchy, LUT, cameras and params (v_hi = max cell)."""
     h = tiny_samr(seed)
     vmax = float(max(p.cells.max() for p in h.patches))
-    return h, lut_config1(seed), config1_cameras(), default_params(v_lo=0.0, v_hi=vmax)
+    return h, lut_small_nested(seed), small_nested_cameras(), default_params(v_lo=0.0, v_hi=vmax)
 
 
 # ----------------------------------------------------------------------------------------------
@@ -338,7 +338,7 @@ def _fill_cells(h: Hierarchy, fn_lattice) -> Hierarchy:
 def cosmology_like(seed: int = 0, root: int = 128, nlevels: int = 6, target_patches: int = 2000,
                    root_split: int = 2, sides=(8, 16, 32, 64), side_probs=(0.01, 0.02, 0.07, 0.90),
                    weights=(0.04, 0.12, 0.22, 0.30, 0.32), min_cover: float = 0.5) -> Hierarchy:
-    """Config 2 geometry: root `root`^3 on [0,1]^3 split into root_split^3 level-0 patches,
+    """Cosmology-like geometry: root `root`^3 on [0,1]^3 split into root_split^3 level-0 patches,
     r = 2.  Level l patches sit on a grid of 64/32/16/8-cell blocks shifted by a random even
     offset (so they span several parents).  Parent cells are visited densest first; for each,
     a side is drawn from `sides` with `side_probs` and the aligned block of that side holding
@@ -420,7 +420,7 @@ def lut_cosmology(seed: int = 0) -> np.ndarray:
     return lut
 
 
-def config2(seed: int = 0, width: int = 1024, height: int = 1024):
+def cosmology_view(seed: int = 0, width: int = 1024, height: int = 1024):
     """Cosmology-like workload: hierarchy, LUT, 1024^2 perspective orbit camera, lit params."""
     h = cosmology_like(seed)
     rng = _rng(1, "cameras", MASTER_SEED + seed)
@@ -433,8 +433,8 @@ def config2(seed: int = 0, width: int = 1024, height: int = 1024):
     return h, lut_cosmology(seed), cam, prm
 
 
-def config5(seed: int = 0, res: int = 512, ncams: int = 8, h: Hierarchy | None = None):
-    """Differentiable transfer function: the config-2 hierarchy, `ncams` seeded orbit cameras at
+def tf_fit(seed: int = 0, res: int = 512, ncams: int = 8, h: Hierarchy | None = None):
+    """Differentiable transfer function: the cosmology-like hierarchy, `ncams` seeded orbit cameras at
     res^2, a hidden target LUT and a different starting LUT."""
     if h is None:
         h = cosmology_like(seed)
@@ -452,7 +452,7 @@ def config5(seed: int = 0, res: int = 512, ncams: int = 8, h: Hierarchy | None =
     return h, cams, target, start, prm
 
 
-def config4_cameras(seed: int = 0, ncams: int = 64, sizes=(256, 512, 768, 1024)):
+def serving_cameras(seed: int = 0, ncams: int = 64, sizes=(256, 512, 768, 1024)):
     """Batched serving: `ncams` perspective cameras on random orbit positions, square
     resolutions drawn uniformly from `sizes`."""
     rng = _rng(3, "cameras", MASTER_SEED + seed)
@@ -486,7 +486,7 @@ class CoreField:
 
 
 def deep_range(seed: int = 0, root: int = 64, nlevels: int = 20, block: int = 16, radius_cells: float = 44.0):
-    """Config 3 geometry: root `root`^3 on [0,1]^3 (one level-0 patch), r = 2, `nlevels` levels.
+    """Deep-range geometry: root `root`^3 on [0,1]^3 (one level-0 patch), r = 2, `nlevels` levels.
     Level l >= 1 tiles a ball of radius `radius_cells` h^l around each core with `block`^3
     blocks on a grid shifted by a random even offset (so fine blocks span several parents),
     keeping the blocks that meet a ball, clipped to the domain."""
@@ -530,7 +530,7 @@ def lut_deep(seed: int = 0, sigma0: float = 1e-4, decades: float = 10.0) -> np.n
     return lut
 
 
-def config3(seed: int = 0, res: int = 1024):
+def deep_range_scene(seed: int = 0, res: int = 1024):
     """Deep-range workload: hierarchy, LUT, full-domain view and a zoom on core 0 at res^2."""
     h = deep_range(seed)
     rng = _rng(2, "cameras", MASTER_SEED + seed)
@@ -540,3 +540,20 @@ def config3(seed: int = 0, res: int = 1024):
     zoom = perspective_orbit(res, res, az + 0.7, el, radius=4e-6, centre=tuple(core), fov_deg=40.0)
     prm = default_params(v_lo=0.0, v_hi=14.5, lighting=False, t_min=1e-5)
     return h, lut_deep(seed), [full, zoom], prm
+
+
+def deep_range_orbits(h: Hierarchy, n: int, seed: int, res: int):
+    """Seeded views of the deep-range hierarchy: every third a full-domain orbit (radius 2 about
+    the centre), the others zooms onto the cores from log-uniform distances in [3e-6, 0.5]
+    (training and held-out sets use different seeds)."""
+    rng = np.random.default_rng(np.random.SeedSequence([MASTER_SEED, 3, seed]))
+    out = []
+    for i in range(n):
+        core = h.cores[i % len(h.cores)]
+        radius = float(10 ** rng.uniform(-5.5, math.log10(0.5)))
+        az, el = float(rng.uniform(0, 2 * math.pi)), float(rng.uniform(-0.8, 0.8))
+        if i % 3 == 0:
+            out.append(perspective_orbit(res, res, az, el, radius=2.0))
+        else:
+            out.append(perspective_orbit(res, res, az, el, radius=radius, centre=tuple(core)))
+    return out
