@@ -173,7 +173,10 @@ typedef struct {                        /* per ray segment, for parity tests */
 typedef struct {                        /* device counters, accumulated by amr_render */
     unsigned long long samples, segments, rays_hit, tap_descents, guard_hits, trace_overflow;
     unsigned long long skipped_segments, coarse_segments, seglog_count, ckpt_overflow;
-    unsigned long long reserved_[6];
+    unsigned long long split_samples;   /* lit samples with a tap outside the sample's brick */
+    unsigned long long face_taps;       /* taps read from a leaf face's single slab owner */
+    unsigned long long unsure_taps;     /* taps classified in FP64 (within 1e-3 cell of a face) */
+    unsigned long long reserved_[3];
 } amr_render_stats;
 
 typedef struct {

@@ -61,6 +61,7 @@ struct BwdArgs {
 
 struct Counters {   // per lane (32-bit); summed over the wave in 64 bits when flushed
     unsigned int samples = 0, segments = 0, hit = 0, desc = 0, guard = 0, tover = 0, ckover = 0;
+    unsigned int split = 0, face = 0, unsure = 0;
 };
 
 // ------------------------------------------------------------------------------------------
@@ -245,28 +246,29 @@ __device__ __forceinline__ float trilinear(const RenderArgs &A, const PatchView 
     return lerpf(c0, c1, fz);
 }
 
-// Trilinear value F(q) and the central differences D_a = F(q + e_a) - F(q - e_a) of a padded
-// brick, for a point whose six one-cell taps all lie in the brick's interior (patch-local
-// index range [-0.5, n - 0.5] on every axis).  The taps use the centre's weights shifted by
-// one cell, so the seven stencils read 32 distinct cells: the 2x2x2 core and a 2x2 pair of
-// cells beyond it on each side of each axis.
+// Trilinear value F(q) and the six tap values F(q + e_a) (Fp) and F(q - e_a) (Fm) of a padded
+// brick.  The taps use the centre's weights shifted by one cell, so the seven stencils read 32
+// distinct cells: the 2x2x2 core and a 2x2 pair of cells beyond it on each side of each axis.
+// The centre must lie in the brick's interior (patch-local index range [-0.5, n - 0.5]); a tap
+// is exact when it also lies there, and the arm reads of a tap that does not are clamped into
+// the brick (the caller replaces that tap's value).
 template <bool REC>
 __device__ __forceinline__ float trilinear_taps(const RenderArgs &A, const PatchView &pv, float qx, float qy,
-                                                float qz, float D[3]) {
+                                                float qz, float Fp[3], float Fm[3]) {
     float fx = floorf(qx), fy = floorf(qy), fz = floorf(qz);
-    // the interior condition gives floor(q) in [0, n - 2]; the clamp keeps every read in the
-    // brick regardless
-    const int ix = min(max((int)fx, 0), pv.nx - 2);
-    const int iy = min(max((int)fy, 0), pv.ny - 2);
-    const int iz = min(max((int)fz, 0), pv.nz - 2);
+    const int ix = min(max((int)fx, -1), pv.nx - 1);
+    const int iy = min(max((int)fy, -1), pv.ny - 1);
+    const int iz = min(max((int)fz, -1), pv.nz - 1);
     fx = qx - (float)ix;
     fy = qy - (float)iy;
     fz = qz - (float)iz;
-    // padded indices ix .. ix + 3 hold cells ix - 1 .. ix + 2; offsets are separable per axis
+    // padded index ix + d holds cell ix - 1 + d; the arms (d = 0, 3) are clamped to [0, n + 1]
     int xo[4], yo[4], zo[4];
     #pragma unroll
     for (int d = 0; d < 4; d++) {
-        const int i = ix + d, j = iy + d, k = iz + d;
+        const int i = d == 0 ? max(ix, 0) : (d == 3 ? min(ix + 3, pv.nx + 1) : ix + d);
+        const int j = d == 0 ? max(iy, 0) : (d == 3 ? min(iy + 3, pv.ny + 1) : iy + d);
+        const int k = d == 0 ? max(iz, 0) : (d == 3 ? min(iz + 3, pv.nz + 1) : iz + d);
         if (A.micro) {
             xo[d] = (i >> 2) * 64 + (i & 3);
             yo[d] = (j >> 2) * pv.px + (j & 3) * 4;
@@ -311,19 +313,25 @@ __device__ __forceinline__ float trilinear_taps(const RenderArgs &A, const Patch
     const float c00 = lerpf(core[0][0][0], core[1][0][0], fx), c10 = lerpf(core[0][1][0], core[1][1][0], fx);
     const float c01 = lerpf(core[0][0][1], core[1][0][1], fx), c11 = lerpf(core[0][1][1], core[1][1][1], fx);
     const float F = lerpf(lerpf(c00, c10, fy), lerpf(c01, c11, fy), fz);
-    // F(q + e_x) - F(q - e_x) = sum_yz w_yz [(1 - fx)(c[2] - c[0]) + fx (c[3] - c[1])]
-    float dx[2][2], dy[2][2], dz[2][2];
+    // F(q +- e_x): the x-lerp moves one cell, the (y, z) weights stay
+    float px[2][2], mx[2][2], py[2][2], my[2][2], pz[2][2], mz[2][2];
     #pragma unroll
     for (int v = 0; v < 2; v++)
         #pragma unroll
         for (int w = 0; w < 2; w++) {
-            dx[v][w] = lerpf(core[1][v][w] - ax[0][v][w], ax[1][v][w] - core[0][v][w], fx);
-            dy[v][w] = lerpf(core[v][1][w] - ay[0][v][w], ay[1][v][w] - core[v][0][w], fy);
-            dz[v][w] = lerpf(core[v][w][1] - az[0][v][w], az[1][v][w] - core[v][w][0], fz);
+            px[v][w] = lerpf(core[1][v][w], ax[1][v][w], fx);
+            mx[v][w] = lerpf(ax[0][v][w], core[0][v][w], fx);
+            py[v][w] = lerpf(core[v][1][w], ay[1][v][w], fy);
+            my[v][w] = lerpf(ay[0][v][w], core[v][0][w], fy);
+            pz[v][w] = lerpf(core[v][w][1], az[1][v][w], fz);
+            mz[v][w] = lerpf(az[0][v][w], core[v][w][0], fz);
         }
-    D[0] = lerpf(lerpf(dx[0][0], dx[1][0], fy), lerpf(dx[0][1], dx[1][1], fy), fz);
-    D[1] = lerpf(lerpf(dy[0][0], dy[1][0], fx), lerpf(dy[0][1], dy[1][1], fx), fz);
-    D[2] = lerpf(lerpf(dz[0][0], dz[1][0], fx), lerpf(dz[0][1], dz[1][1], fx), fy);
+    Fp[0] = lerpf(lerpf(px[0][0], px[1][0], fy), lerpf(px[0][1], px[1][1], fy), fz);
+    Fm[0] = lerpf(lerpf(mx[0][0], mx[1][0], fy), lerpf(mx[0][1], mx[1][1], fy), fz);
+    Fp[1] = lerpf(lerpf(py[0][0], py[1][0], fx), lerpf(py[0][1], py[1][1], fx), fz);
+    Fm[1] = lerpf(lerpf(my[0][0], my[1][0], fx), lerpf(my[0][1], my[1][1], fx), fz);
+    Fp[2] = lerpf(lerpf(pz[0][0], pz[1][0], fx), lerpf(pz[0][1], pz[1][1], fx), fy);
+    Fm[2] = lerpf(lerpf(mz[0][0], mz[1][0], fx), lerpf(mz[0][1], mz[1][1], fx), fy);
     return F;
 }
 
@@ -471,68 +479,82 @@ __device__ __forceinline__ void eval_sample(const RenderArgs &A, const float4 *s
     const float qx = S.q0[0] + kk * S.dq[0], qy = S.q0[1] + kk * S.dq[1], qz = S.q0[2] + kk * S.dq[2];
     float F;
     if (LIT) {
-        // classify the six taps x +- h^l e_a first: when all stay in this brick one fused
-        // stencil gives the value and the three differences
+        // value and the six taps x +- h^l e_a from this brick in one fused stencil; a tap that
+        // leaves the brick (classified in fp32, else FP64) is then read where it lands
         const float qc[3] = {qx, qy, qz};
-        int cls[3][2];
-        bool all_same = true;
+        uint32_t clsbits = 0;             // 2 bits per tap t = 2 a + sgn
         #pragma unroll
         for (int a = 0; a < 3; a++)
             #pragma unroll
             for (int sgn = 0; sgn < 2; sgn++) {
                 float qt[3] = {qc[0], qc[1], qc[2]};
                 qt[a] += sgn ? -1.f : 1.f;
-                cls[a][sgn] = classify_tap_fp32(S, qt, a, sgn);
-                all_same = all_same && cls[a][sgn] == kTapSame;
+                clsbits |= (uint32_t)classify_tap_fp32(S, qt, a, sgn) << (2 * (2 * a + sgn));
             }
-        if (all_same) {
-            float D[3];
-            F = trilinear_taps<REC>(A, S.pv, qx, qy, qz, D);
+        float Fp[3], Fm[3];
+        F = trilinear_taps<REC>(A, S.pv, qx, qy, qz, Fp, Fm);
+        uint32_t okbits = 0x3fu;          // bit t: tap t holds data
+        if (clsbits) {
+            if (REC) cnt.split++;
+            // the taps outside this brick, one at a time
+            uint32_t todo = 0;
             #pragma unroll
-            for (int a = 0; a < 3; a++) v.gv[a] = D[a] * (0.5f * A.inv_range);
-        } else {
-            F = trilinear<REC>(A, S.pv, qx, qy, qz);
-            #pragma unroll
-            for (int a = 0; a < 3; a++) {
-                float Fs[2];
-                bool ok[2];
-                #pragma unroll
-                for (int sgn = 0; sgn < 2; sgn++) {
-                    float qt[3] = {qc[0], qc[1], qc[2]};
-                    qt[a] += sgn ? -1.f : 1.f;
-                    int c = cls[a][sgn];
-                    double xt[3];
-                    if (c != kTapSame) {
-                        // exact FP64 tap position: x = o + t_k d, then +- h^l along axis a
+            for (int t = 0; t < 6; t++) todo |= ((clsbits >> (2 * t)) & 3u) ? (1u << t) : 0u;
+            while (todo) {
+                const int t = __builtin_ctz(todo);
+                todo &= todo - 1u;
+                const int a = t >> 1, sgn = t & 1;
+                int c = (int)((clsbits >> (2 * t)) & 3u);
+                // exact FP64 tap position: x = o + t_k d, then +- h^l along axis a
+                double xt[3];
+                {
 #pragma clang fp contract(off)
-                        const double tk = S.ta + ((double)k + 0.5) * S.delta;
-                        #pragma unroll
-                        for (int b = 0; b < 3; b++) xt[b] = R.o[b] + tk * R.d[b];
-                        const double hl = A.patches[S.patch].h[a];
-                        xt[a] = sgn ? xt[a] - hl : xt[a] + hl;
-                        if (c == kTapUnsure) c = classify_tap_fp64(A, S, xt, a, sgn);
-                    }
-                    int owner = -1;
-                    if (c == kTapFace) owner = A.faces[6 * S.leaf + 2 * a + (sgn ? 0 : 1)];
-                    if (c == kTapSame) {
-                        Fs[sgn] = trilinear<REC>(A, S.pv, qt[0], qt[1], qt[2]);
-                        ok[sgn] = true;
-                    } else if (owner >= 0) {
-                        Fs[sgn] = patch_value_at<REC>(A, owner, xt);      // the slab's single owner
-                        ok[sgn] = true;
+                    const double tk = S.ta + ((double)k + 0.5) * S.delta;
+                    #pragma unroll
+                    for (int b = 0; b < 3; b++) xt[b] = R.o[b] + tk * R.d[b];
+                    const double hl = A.patches[S.patch].h[a];
+                    const double xa = sel3(a, xt[0], xt[1], xt[2]);
+                    const double xn = sgn ? xa - hl : xa + hl;
+                    #pragma unroll
+                    for (int b = 0; b < 3; b++) xt[b] = b == a ? xn : xt[b];
+                }
+                if (REC && c == kTapUnsure) cnt.unsure++;
+                if (c == kTapUnsure) c = classify_tap_fp64(A, S, xt, a, sgn);
+                float Fs = 0.f;
+                bool ok = true;
+                if (c == kTapSame) {
+                    const float step = sgn ? -1.f : 1.f;
+                    Fs = trilinear<REC>(A, S.pv, qx + (a == 0 ? step : 0.f), qy + (a == 1 ? step : 0.f),
+                                        qz + (a == 2 ? step : 0.f));
+                } else {
+                    const int owner = c == kTapFace ? A.faces[6 * S.leaf + 2 * a + (sgn ? 0 : 1)] : -1;
+                    if (owner >= 0) {
+                        if (REC) cnt.face++;
+                        Fs = patch_value_at<REC>(A, owner, xt);      // the slab's single owner
                     } else {
                         // descend from the rope node holding the slab, else from the root
                         const uint32_t start = owner <= -2 ? (uint32_t)(-2 - owner) : 0u;
-                        ok[sgn] = field_at<REC>(A, xt, &Fs[sgn], cnt, start);
+                        ok = field_at<REC>(A, xt, &Fs, cnt, start);
                     }
                 }
-                float gr;
-                if (ok[0] && ok[1]) gr = (Fs[0] - Fs[1]) * (0.5f * A.inv_range);
-                else if (ok[0]) gr = (Fs[0] - F) * A.inv_range;
-                else if (ok[1]) gr = (F - Fs[1]) * A.inv_range;
-                else gr = 0.f;
-                v.gv[a] = gr;
+                if (!ok) okbits &= ~(1u << t);
+                // write the tap back (selects keep the arrays in registers)
+                #pragma unroll
+                for (int b = 0; b < 3; b++) {
+                    Fp[b] = (t == 2 * b) ? Fs : Fp[b];
+                    Fm[b] = (t == 2 * b + 1) ? Fs : Fm[b];
+                }
             }
+        }
+        #pragma unroll
+        for (int a = 0; a < 3; a++) {
+            const bool okp = (okbits >> (2 * a)) & 1u, okm = (okbits >> (2 * a + 1)) & 1u;
+            float gr;
+            if (okp && okm) gr = (Fp[a] - Fm[a]) * (0.5f * A.inv_range);
+            else if (okp) gr = (Fp[a] - F) * A.inv_range;
+            else if (okm) gr = (F - Fm[a]) * A.inv_range;
+            else gr = 0.f;
+            v.gv[a] = gr;
         }
     } else {
         F = trilinear<REC>(A, S.pv, qx, qy, qz);
@@ -577,6 +599,7 @@ __device__ __forceinline__ void flush_counters(amr_render_stats *st, Counters c,
     u64 s = wave_sum((u64)c.samples), g = wave_sum((u64)c.segments), h = wave_sum((u64)c.hit);
     u64 d = wave_sum((u64)c.desc), gu = wave_sum((u64)c.guard), to = wave_sum((u64)c.tover);
     u64 co = wave_sum((u64)c.ckover);
+    u64 sp = wave_sum((u64)c.split), fa = wave_sum((u64)c.face), un = wave_sum((u64)c.unsure);
     if (lane == 0) {
         if (s) atomicAdd(&st->samples, s);
         if (g) atomicAdd(&st->segments, g);
@@ -585,6 +608,9 @@ __device__ __forceinline__ void flush_counters(amr_render_stats *st, Counters c,
         if (gu) atomicAdd(&st->guard_hits, gu);
         if (to) atomicAdd(&st->trace_overflow, to);
         if (co) atomicAdd(&st->ckpt_overflow, co);
+        if (sp) atomicAdd(&st->split_samples, sp);
+        if (fa) atomicAdd(&st->face_taps, fa);
+        if (un) atomicAdd(&st->unsure_taps, un);
     }
 }
 
