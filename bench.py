@@ -26,6 +26,40 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# the sources of the timed kernel; committed counter readings are used only while these match
+KERNEL_SOURCES = ("paper_1212_3333_amd/csrc/amr_render.hip", "paper_1212_3333_amd/csrc/amr_render_common.h",
+                  "paper_1212_3333_amd/csrc/amr_internal.h")
+TRAFFIC_FILE = "profiles/render_fwd_lit_cosmology_1024_traffic.txt"
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    hsh = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as fh:
+            hsh.update(fh.read())
+    return hsh.hexdigest()
+
+
+def committed_traffic():
+    """HBM bytes per launch of the lit kernel from the committed rocprofv3 counter summary
+    (FETCH_SIZE and WRITE_SIZE, each scaled by a copy kernel's reading), or None when the
+    summary is missing or the kernel sources have changed since the counters were taken."""
+    path = os.path.join(ROOT, TRAFFIC_FILE)
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    try:
+        return int(float(kv["traffic_bytes_per_launch"]))
+    except (KeyError, ValueError):
+        return None
 METRIC = "samples/s + Mrays/s at 1024², plain vs learned-skip at ≤1e-3 RGBA error"
 
 
@@ -222,8 +256,9 @@ def main():
         cells = popcount_bytes(touch.view(torch.uint8))
         b_alg = 4 * cells + scene.scene.meta_bytes + 16 * W * H
         achieved = b_alg / (ms * 1e-3) / 1e9
+        traffic = committed_traffic() if prm["lighting"] else None
         roof = dict(bound="hbm", achieved=round(achieved, 2), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 5), traffic=None,
+                    frac=round(achieved / HBM_PEAK_GBS, 5), traffic=traffic,
                     kernel="render_fwd", algorithmic_bytes=int(b_alg), distinct_cells=int(cells),
                     gather_request_bytes=int(samples * (32 + (192 if prm["lighting"] else 0))))
         log("compulsory bytes %.1f MB (%d distinct cells)" % (b_alg / 1e6, cells))
