@@ -254,12 +254,14 @@ def main():
         amr.render(scene, cam, lut_t, prm, d_touch=touch)
         torch.cuda.synchronize()
         cells = popcount_bytes(touch.view(torch.uint8))
+        lines = int((touch != 0).sum().item())      # 128-byte lines (32 cells) holding a read cell
         b_alg = 4 * cells + scene.scene.meta_bytes + 16 * W * H
         achieved = b_alg / (ms * 1e-3) / 1e9
         traffic = committed_traffic() if prm["lighting"] else None
         roof = dict(bound="hbm", achieved=round(achieved, 2), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 5), traffic=traffic,
                     kernel="render_fwd", algorithmic_bytes=int(b_alg), distinct_cells=int(cells),
+                    distinct_line_bytes=128 * lines,
                     gather_request_bytes=int(samples * (32 + (192 if prm["lighting"] else 0))))
         log("compulsory bytes %.1f MB (%d distinct cells)" % (b_alg / 1e6, cells))
         del touch

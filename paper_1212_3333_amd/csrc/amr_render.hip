@@ -1,6 +1,7 @@
 // Device side of libamr: the single-pass raycaster (Section 5.3), its adjoint, and launchers.
 //
-// One lane owns one ray. A wave64 covers an 8x8 pixel tile, a 256-thread block 16x16 pixels.
+// One lane owns one ray and a wave64 covers an 8x8 pixel tile; the forward kernel runs one wave
+// per block, the adjoint four.
 // The FP64 parts (ray generation, slab clip, kD-restart planes, sample positions of gradient
 // taps) are written with contraction disabled so that every operation is correctly rounded
 // exactly once; the per-sample arithmetic (trilinear, LUT, exp, compositing) is fp32 in
@@ -20,20 +21,21 @@ namespace amr {
 // ------------------------------------------------------------------------------------------
 
 template <bool LIT, bool REC>
-__global__ __launch_bounds__(256) void render_fwd(RenderArgs A) {
+__global__ __launch_bounds__(64) void render_fwd(RenderArgs A) {
     __shared__ float4 s_lut[256];
-    s_lut[threadIdx.x] = A.lut[threadIdx.x];
+    for (int i = threadIdx.x; i < 256; i += 64) s_lut[i] = A.lut[i];
     __syncthreads();
 
-    // XCD-aware tile order: blocks are dealt round-robin to the 8 XCDs, so give each XCD a
-    // contiguous band of tiles (neighbouring rays share bricks in that XCD's L2).
-    const int per = (A.nblocks + 7) / 8;
-    const int tile = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
-    if (tile >= A.nblocks) return;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int tx = tile % A.tiles_x, ty = tile / A.tiles_x;
-    const int pi = tx * 16 + (wave & 1) * 8 + (lane & 7);
-    const int pj = ty * 16 + (wave >> 1) * 8 + (lane >> 3);
+    // One wave per block, one 8x8 pixel tile per wave.  XCD-aware order: blocks are dealt
+    // round-robin to the 8 XCDs, so XCD x takes the x-th band of tile rows and walks it column
+    // by column; the tiles in flight on one XCD then form a compact patch of the screen whose
+    // rays share bricks in that XCD's L2.
+    const int xcd = (int)(blockIdx.x % 8), li = (int)(blockIdx.x / 8);
+    const int col = li / A.band8, row = xcd * A.band8 + li % A.band8;
+    if (col >= A.t8x || row >= A.t8y) return;
+    const int lane = threadIdx.x & 63;
+    const int pi = col * 8 + (lane & 7);
+    const int pj = row * 8 + (lane >> 3);
     const bool valid = pi < A.width && pj < A.height;
     const int64_t ray = (int64_t)pj * A.width + pi;
 
@@ -339,14 +341,14 @@ int amr_render(const amr_scene *S, const amr_camera *cams, int32_t ncams, const 
             pix_off += (int64_t)cams[c].width * cams[c].height;
             continue;
         }
-        int grid = ((A.nblocks + 7) / 8) * 8;
+        const int grid = 8 * A.band8 * A.t8x;
         const bool rec = A.trace || A.trace_n || A.nsamp || A.stats || A.touch || A.ckpt;
         if (A.lighting) {
-            if (rec) hipLaunchKernelGGL((render_fwd<true, true>), dim3(grid), dim3(256), 0, s, A);
-            else hipLaunchKernelGGL((render_fwd<true, false>), dim3(grid), dim3(256), 0, s, A);
+            if (rec) hipLaunchKernelGGL((render_fwd<true, true>), dim3(grid), dim3(64), 0, s, A);
+            else hipLaunchKernelGGL((render_fwd<true, false>), dim3(grid), dim3(64), 0, s, A);
         } else {
-            if (rec) hipLaunchKernelGGL((render_fwd<false, true>), dim3(grid), dim3(256), 0, s, A);
-            else hipLaunchKernelGGL((render_fwd<false, false>), dim3(grid), dim3(256), 0, s, A);
+            if (rec) hipLaunchKernelGGL((render_fwd<false, true>), dim3(grid), dim3(64), 0, s, A);
+            else hipLaunchKernelGGL((render_fwd<false, false>), dim3(grid), dim3(64), 0, s, A);
         }
         rc = check_hip(hipGetLastError(), "render_fwd launch");
         if (rc) return rc;

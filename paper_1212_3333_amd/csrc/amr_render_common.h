@@ -50,7 +50,8 @@ struct RenderArgs {
     int64_t ckpt_ray0;               // first ray of this camera in the buffer
     int64_t ckpt_stride;             // bytes per ray
     int32_t ckpt_every, ckpt_max;
-    int32_t tiles_x, tiles_y, nblocks;
+    int32_t tiles_x, tiles_y, nblocks;     // 16x16 tiles of four waves (learned kernel)
+    int32_t t8x, t8y, band8;               // 8x8 one-wave tiles; tile rows per XCD band
 };
 
 struct BwdArgs {
@@ -674,6 +675,9 @@ inline int fill_args(const amr_scene *S, const amr_camera *C, const amr_render_p
     A->tiles_x = (C->width + 15) / 16;
     A->tiles_y = (C->height + 15) / 16;
     A->nblocks = A->tiles_x * A->tiles_y;
+    A->t8x = (C->width + 7) / 8;
+    A->t8y = (C->height + 7) / 8;
+    A->band8 = (A->t8y + 7) / 8;
     A->ckpt = (uint8_t *)P->d_ckpt;
     A->ckpt_stride = (int64_t)sizeof(Ckpt) * (1 + (int64_t)P->ckpt_max);
     A->ckpt_every = P->ckpt_every > 0 ? P->ckpt_every : 1;
