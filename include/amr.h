@@ -133,6 +133,10 @@ typedef struct {
                                    v >= 0 the single patch owning it; v <= -2 several owners, and
                                    node -2-v is the smallest tree node holding the slab; -1 the
                                    slab leaves B */
+    const void *face_taps;      /* per leaf, 6 records of 64 bytes for gradient taps beyond each
+                                   face: the single owner's brick and the affine map from the
+                                   leaf's patch-local cell coordinates into it, or the node to
+                                   descend from */
     int64_t pool_bytes, meta_bytes;
     int32_t nnodes, nleaves, npatches, nlevels;
     int32_t lmax, refine, depth, brick_layout;

@@ -168,6 +168,13 @@ class Scene:
         raw = raw if self.host else raw.cpu().numpy()
         return np.frombuffer(raw.tobytes(), dtype=np.int32).reshape(-1, 6)
 
+    def face_tap_records(self) -> np.ndarray:
+        """[nleaves, 6] gradient-tap records: the single slab owner's brick (n > 0) with the map
+        q_owner = r q + t from the leaf's patch-local cell coordinates, else the rope node."""
+        dt = np.dtype([("off", np.uint64), ("n", np.int32, 3), ("px", np.int32), ("pxy", np.int32),
+                       ("r", np.float32), ("t", np.float32, 3), ("rope", np.int32), ("pad", np.int32, 4)])
+        return self._records(self.scene.face_taps, dt, self.scene.nleaves * 6).reshape(-1, 6)
+
     def node_records(self) -> np.ndarray:
         dt = np.dtype([("split", np.float64), ("child", np.uint32), ("meta", np.uint32)])
         return self._records(self.scene.nodes, dt, self.scene.nnodes)

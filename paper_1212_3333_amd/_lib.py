@@ -51,7 +51,7 @@ class amr_pack_opts(ctypes.Structure):
 
 
 class amr_scene(ctypes.Structure):
-    _fields_ = [("pool", VP), ("nodes", VP), ("leaves", VP), ("patches", VP), ("leaf_faces", VP),
+    _fields_ = [("pool", VP), ("nodes", VP), ("leaves", VP), ("patches", VP), ("leaf_faces", VP), ("face_taps", VP),
                 ("pool_bytes", ctypes.c_int64), ("meta_bytes", ctypes.c_int64),
                 ("nnodes", ctypes.c_int32), ("nleaves", ctypes.c_int32), ("npatches", ctypes.c_int32),
                 ("nlevels", ctypes.c_int32), ("lmax", ctypes.c_int32), ("refine", ctypes.c_int32),

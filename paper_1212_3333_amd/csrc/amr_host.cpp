@@ -669,7 +669,8 @@ int amr_pack_pool(const amr_tree *T, const amr_patch *patches, int32_t npatches,
     const int64_t o_leaves = align_up(o_nodes + nn * (int64_t)sizeof(DNode), 256);
     const int64_t o_patch = align_up(o_leaves + nl * (int64_t)sizeof(DLeaf), 256);
     const int64_t o_faces = align_up(o_patch + np * (int64_t)sizeof(DPatch), 256);
-    const int64_t mbytes = align_up(o_faces + nl * 6 * (int64_t)sizeof(int32_t), 256);
+    const int64_t o_fxf = align_up(o_faces + nl * 6 * (int64_t)sizeof(int32_t), 256);
+    const int64_t mbytes = align_up(o_fxf + nl * 6 * (int64_t)sizeof(DFaceXf), 256);
     const int64_t pbytes = std::max<int64_t>(nfl * 4, 256);
     if (!d_pool && !d_meta) {
         *pool_bytes = pbytes;
@@ -792,6 +793,36 @@ int amr_pack_pool(const amr_tree *T, const amr_patch *patches, int32_t npatches,
                 L.vmax = mx;
             }
         }
+        // gradient-tap records per leaf face (after the patch headers, which they read)
+        DFaceXf *fx = (DFaceXf *)(meta.data() + o_fxf);
+        const int32_t *own_all = (const int32_t *)(meta.data() + o_faces);
+        for (size_t k = 0; k < T->leaves.size(); k++) {
+            const int p = T->nodes[T->leaves[k]].patch;
+            for (int f = 0; f < 6; f++) {
+                DFaceXf &X = fx[6 * k + f];
+                memset(&X, 0, sizeof(X));
+                const int32_t o = own_all[6 * k + f];
+                if (o >= 0 && p >= 0) {
+                    const DPatch &Po = dp[o], &Pp = dp[p];
+                    X.off = Po.off;
+                    for (int a = 0; a < 3; a++) X.n[a] = Po.n[a];
+                    if (layout == 1) {
+                        X.px = 64 * Po.nb[0];
+                        X.pxy = X.px * Po.nb[1];
+                    } else {
+                        X.px = Po.n[0] + 2;
+                        X.pxy = X.px * (Po.n[1] + 2);
+                    }
+                    // x = lo_p + (q + 1/2) h_p  =>  q_o = (x - lo_o) / h_o - 1/2 = r q + t
+                    const double r = Pp.h[0] / Po.h[0];
+                    X.r = (float)r;
+                    for (int a = 0; a < 3; a++) X.t[a] = (float)((Pp.lo[a] - Po.lo[a]) * Po.inv_h[a] + 0.5 * r - 0.5);
+                    X.rope = 0;
+                } else {
+                    X.rope = o <= -2 ? -2 - o : (o == -1 ? -1 : 0);
+                }
+            }
+        }
         // scene
         memset(out, 0, sizeof(*out));
         out->pool = (const float *)d_pool;
@@ -799,6 +830,7 @@ int amr_pack_pool(const amr_tree *T, const amr_patch *patches, int32_t npatches,
         out->leaves = (const uint8_t *)d_meta + o_leaves;
         out->patches = (const uint8_t *)d_meta + o_patch;
         out->leaf_faces = (const uint8_t *)d_meta + o_faces;
+        out->face_taps = (const uint8_t *)d_meta + o_fxf;
         out->pool_bytes = pbytes;
         out->meta_bytes = mbytes;
         out->nnodes = (int32_t)nn;

@@ -46,6 +46,21 @@ struct DPatch {
 };
 static_assert(sizeof(DPatch) == 128, "DPatch layout");
 
+// Gradient-tap record of one leaf face, 64 bytes.  When the one-cell slab beyond the face has a
+// single owner patch (n[0] > 0), a tap in the slab reads that patch's brick at
+// q_owner = r q + t[a], q being the tap in the leaf's own patch-local cell coordinates.
+// Otherwise n[0] == 0 and rope is the node to descend from (0: the root; -1: the slab leaves B).
+struct DFaceXf {
+    uint64_t off;        // first float of the owner's padded brick
+    int32_t n[3];        // owner's interior cells per axis (0: no single owner)
+    int32_t px, pxy;     // owner brick's row and slab strides (layout dependent)
+    float r;             // h_own / h_owner
+    float t[3];
+    int32_t rope;
+    int32_t pad_[4];
+};
+static_assert(sizeof(DFaceXf) == 64, "DFaceXf layout");
+
 constexpr uint32_t kLeafAxis = 3u;
 
 // Offset (in floats) of padded-brick cell (i, j, k) (0 <= index <= n + 1) in either layout.

@@ -28,7 +28,7 @@ struct RenderArgs {
     const DNode *nodes;
     const DLeaf *leaves;
     const DPatch *patches;
-    const int32_t *faces;            // [nleaves][6] slab owners
+    const DFaceXf *face_xf;          // [nleaves][6] gradient-tap records
     const float4 *lut;
     double box_lo[3], box_hi[3];     // B (closed, for gradient taps)
     double clip_lo[3], clip_hi[3];   // B ∩ clip box
@@ -506,9 +506,13 @@ __device__ __forceinline__ void eval_sample(const RenderArgs &A, const float4 *s
                 todo &= todo - 1u;
                 const int a = t >> 1, sgn = t & 1;
                 int c = (int)((clsbits >> (2 * t)) & 3u);
-                // exact FP64 tap position: x = o + t_k d, then +- h^l along axis a
+                const float step = sgn ? -1.f : 1.f;
+                const float qt0 = qx + (a == 0 ? step : 0.f), qt1 = qy + (a == 1 ? step : 0.f),
+                            qt2 = qz + (a == 2 ? step : 0.f);
+                // exact FP64 tap position x = o + t_k d, then +- h^l along axis a (needed near a
+                // face and for descents)
                 double xt[3];
-                {
+                if (c != kTapFace) {
 #pragma clang fp contract(off)
                     const double tk = S.ta + ((double)k + 0.5) * S.delta;
                     #pragma unroll
@@ -524,18 +528,35 @@ __device__ __forceinline__ void eval_sample(const RenderArgs &A, const float4 *s
                 float Fs = 0.f;
                 bool ok = true;
                 if (c == kTapSame) {
-                    const float step = sgn ? -1.f : 1.f;
-                    Fs = trilinear<REC>(A, S.pv, qx + (a == 0 ? step : 0.f), qy + (a == 1 ? step : 0.f),
-                                        qz + (a == 2 ? step : 0.f));
+                    Fs = trilinear<REC>(A, S.pv, qt0, qt1, qt2);
                 } else {
-                    const int owner = c == kTapFace ? A.faces[6 * S.leaf + 2 * a + (sgn ? 0 : 1)] : -1;
-                    if (owner >= 0) {
+                    const DFaceXf X = c == kTapFace ? A.face_xf[6 * S.leaf + 2 * a + (sgn ? 0 : 1)] : DFaceXf{};
+                    if (c == kTapFace && X.n[0] > 0) {
+                        // the slab's single owner: its brick at the mapped position
                         if (REC) cnt.face++;
-                        Fs = patch_value_at<REC>(A, owner, xt);      // the slab's single owner
+                        PatchView pv;
+                        pv.brick = A.pool + X.off;
+                        pv.px = X.px;
+                        pv.pxy = X.pxy;
+                        pv.nx = X.n[0];
+                        pv.ny = X.n[1];
+                        pv.nz = X.n[2];
+                        Fs = trilinear<REC>(A, pv, qt0 * X.r + X.t[0], qt1 * X.r + X.t[1], qt2 * X.r + X.t[2]);
                     } else {
-                        // descend from the rope node holding the slab, else from the root
-                        const uint32_t start = owner <= -2 ? (uint32_t)(-2 - owner) : 0u;
-                        ok = field_at<REC>(A, xt, &Fs, cnt, start);
+                        if (c == kTapFace) {
+#pragma clang fp contract(off)
+                            const double tk = S.ta + ((double)k + 0.5) * S.delta;
+                            #pragma unroll
+                            for (int b = 0; b < 3; b++) xt[b] = R.o[b] + tk * R.d[b];
+                            const double hl = A.patches[S.patch].h[a];
+                            const double xa = sel3(a, xt[0], xt[1], xt[2]);
+                            const double xn = sgn ? xa - hl : xa + hl;
+                            #pragma unroll
+                            for (int b = 0; b < 3; b++) xt[b] = b == a ? xn : xt[b];
+                        }
+                        // descend from the rope node holding the slab, else from the root (a
+                        // slab beyond B fails the box test there, except on B's closed upper faces)
+                        ok = field_at<REC>(A, xt, &Fs, cnt, c == kTapFace && X.rope > 0 ? (uint32_t)X.rope : 0u);
                     }
                 }
                 if (!ok) okbits &= ~(1u << t);
@@ -637,7 +658,7 @@ inline int fill_args(const amr_scene *S, const amr_camera *C, const amr_render_p
     A->nodes = (const DNode *)S->nodes;
     A->leaves = (const DLeaf *)S->leaves;
     A->patches = (const DPatch *)S->patches;
-    A->faces = (const int32_t *)S->leaf_faces;
+    A->face_xf = (const DFaceXf *)S->face_taps;
     A->lut = (const float4 *)P->d_lut;
     #pragma unroll
     for (int a = 0; a < 3; a++) {

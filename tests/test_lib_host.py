@@ -285,3 +285,49 @@ def test_leaf_face_owners(seed):
         for _ in range(4):
             x = h.origin + (lo + rng.random(3) * (hi - lo)) * hf
             assert descend(x, node) == descend(x, 0)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_face_tap_records(seed):
+    """Each single-owner face record maps a point of the slab from the leaf's patch-local cell
+    coordinates into the owner's (q_o = r q + t) as the FP64 world-coordinate formula does, and
+    names the owner's brick; the other faces carry the rope node of the face table."""
+    h = workloads.random_tiny(seed, multi_root=(seed == 1)) if seed < 2 else workloads.tiny_samr(0)
+    tree = amr.build_tree(h)
+    for layout in (0, 1):
+        scene = amr.pack(tree, h, host=True, brick_layout=layout)
+        own = scene.leaf_face_owners()
+        rec = scene.face_tap_records()
+        ph = scene.patch_headers()
+        lr = scene.leaf_records()
+        rng = np.random.default_rng(seed)
+        mapped = 0
+        for k in range(len(lr)):
+            p = int(lr["patch"][k])
+            for f in range(6):
+                X, o = rec[k, f], int(own[k, f])
+                if p < 0 or o < 0:
+                    assert X["n"][0] == 0
+                    assert X["rope"] == (-2 - o if o <= -2 else (-1 if o == -1 else 0))
+                    continue
+                mapped += 1
+                assert X["off"] == ph["off"][o] and np.array_equal(X["n"], ph["n"][o])
+                if layout == 1:
+                    assert X["px"] == 64 * ph["nb"][o][0] and X["pxy"] == X["px"] * ph["nb"][o][1]
+                else:
+                    assert X["px"] == ph["n"][o][0] + 2 and X["pxy"] == X["px"] * (ph["n"][o][1] + 2)
+                a, side = f // 2, f % 2
+                lo, hi = lr["lo"][k].copy(), lr["hi"][k].copy()
+                hl = ph["h"][p]
+                if side:
+                    lo[a], hi[a] = hi[a], hi[a] + hl[a]
+                else:
+                    lo[a], hi[a] = lo[a] - hl[a], lo[a]
+                for _ in range(4):
+                    x = lo + rng.random(3) * (hi - lo)
+                    q = (x - ph["lo"][p]) * ph["inv_h"][p] - 0.5
+                    qo = (x - ph["lo"][o]) * ph["inv_h"][o] - 0.5
+                    got = q * np.float64(X["r"]) + X["t"].astype(np.float64)
+                    assert np.allclose(got, qo, rtol=0, atol=1e-9 * (1 + np.abs(qo).max()))
+        assert mapped > 0
+
