@@ -361,11 +361,16 @@ __device__ __forceinline__ bool field_at(const RenderArgs &A, const double x[3],
 
 // Per-segment sampling state: n midpoint samples of step delta on [ta, tb] (Section 5.3:
 // the step is proportional to the leaf level's cell size).
+enum { kTapSame = 0, kTapLocate = 1, kTapUnsure = 2, kTapFace = 3 };
+constexpr float kTapMargin = 1e-3f;   // cells; far above the fp32 error of patch-local positions
+
 struct Segment {
     PatchView pv;
     float q0[3], dq[3], dl;           // patch-local start, step, delta * log2(e)
     double ta, delta;
-    float lq_lo[3], lq_hi[3];         // leaf box in patch-local continuous cell coordinates
+    float fs_lo[3], fs_hi[3];         // all six taps of a sample stay in this brick (with the
+                                      // classification margin) when every q_a is in [fs_lo, fs_hi);
+                                      // seg_box() recovers the leaf box from them
     uint32_t safe;                    // faces across which a gradient tap stays in this brick
     int leaf, patch, n;
 };
@@ -391,12 +396,19 @@ __device__ __forceinline__ void setup_segment(const RenderArgs &A, const Ray &R,
     }
     S.dl = (float)S.delta * 1.44269504088896340736f;
     if (LIT) {
+        S.safe = (L.level_flags >> 8) & 0x3fu;
         #pragma unroll
         for (int a = 0; a < 3; a++) {
-            S.lq_lo[a] = (float)((L.lo[a] - P.lo[a]) * P.inv_h[a] - 0.5);
-            S.lq_hi[a] = (float)((L.hi[a] - P.lo[a]) * P.inv_h[a] - 0.5);
+            // leaf box in patch-local continuous cell coordinates; a tap q -+ 1 stays in the brick
+            // while inside it, or inside the one-cell slab beyond a face whose slab belongs to
+            // the same patch
+            const float lq_lo = (float)((L.lo[a] - P.lo[a]) * P.inv_h[a] - 0.5);
+            const float lq_hi = (float)((L.hi[a] - P.lo[a]) * P.inv_h[a] - 0.5);
+            const float lo = lq_lo - (((S.safe >> (2 * a)) & 1u) ? 1.f : 0.f);
+            const float hi = lq_hi + (((S.safe >> (2 * a + 1)) & 1u) ? 1.f : 0.f);
+            S.fs_lo[a] = lo + 1.f + kTapMargin;
+            S.fs_hi[a] = hi - 1.f - kTapMargin;
         }
-        S.safe = (L.level_flags >> 8) & 0x3fu;
         S.leaf = leaf;
         S.patch = L.patch;
     }
@@ -408,8 +420,13 @@ struct SampleVals {
     float gv[3], dot, den;
 };
 
-enum { kTapSame = 0, kTapLocate = 1, kTapUnsure = 2, kTapFace = 3 };
-constexpr float kTapMargin = 1e-3f;   // cells; far above the fp32 error of patch-local positions
+
+// Leaf box along axis b in patch-local cell coordinates, recovered from the tap window (within
+// a few fp32 ulps, far below the classification margin).
+__device__ __forceinline__ void seg_box(const Segment &S, int b, float &lo, float &hi) {
+    lo = S.fs_lo[b] - (1.f + kTapMargin) + (((S.safe >> (2 * b)) & 1u) ? 1.f : 0.f);
+    hi = S.fs_hi[b] + (1.f + kTapMargin) - (((S.safe >> (2 * b + 1)) & 1u) ? 1.f : 0.f);
+}
 
 // Where does the gradient tap q (the sample moved by +-1 cell along axis a) read its value?
 // Decided in fp32 patch-local coordinates when every comparison clears the margin.
@@ -417,7 +434,8 @@ __device__ __forceinline__ int classify_tap_fp32(const Segment &S, const float q
     int out_axis = -1;
     #pragma unroll
     for (int b = 0; b < 3; b++) {
-        const float lo = S.lq_lo[b], hi = S.lq_hi[b];
+        float lo, hi;
+        seg_box(S, b, lo, hi);
         const bool in_sure = q[b] >= lo + kTapMargin && q[b] < hi - kTapMargin;
         const bool out_sure = q[b] < lo - kTapMargin || q[b] >= hi + kTapMargin;
         if (!in_sure && !out_sure) return kTapUnsure;
@@ -429,7 +447,9 @@ __device__ __forceinline__ int classify_tap_fp32(const Segment &S, const float q
     if (out_axis < 0) return kTapSame;
     const uint32_t face = 2u * a + (sgn ? 0u : 1u);
     // inside the one-cell slab beyond the face?
-    const float lim = sgn ? S.lq_lo[a] - 1.f : S.lq_hi[a] + 1.f;
+    float alo, ahi;
+    seg_box(S, a, alo, ahi);
+    const float lim = sgn ? alo - 1.f : ahi + 1.f;
     const float qa = q[a];
     const bool in_slab = sgn ? qa >= lim + kTapMargin : qa < lim - kTapMargin;
     const bool out_slab = sgn ? qa < lim - kTapMargin : qa >= lim + kTapMargin;
@@ -484,14 +504,18 @@ __device__ __forceinline__ void eval_sample(const RenderArgs &A, const float4 *s
         // leaves the brick (classified in fp32, else FP64) is then read where it lands
         const float qc[3] = {qx, qy, qz};
         uint32_t clsbits = 0;             // 2 bits per tap t = 2 a + sgn
-        #pragma unroll
-        for (int a = 0; a < 3; a++)
+        const bool inner = qx >= S.fs_lo[0] && qx < S.fs_hi[0] && qy >= S.fs_lo[1] && qy < S.fs_hi[1] &&
+                           qz >= S.fs_lo[2] && qz < S.fs_hi[2];
+        if (!inner) {
             #pragma unroll
-            for (int sgn = 0; sgn < 2; sgn++) {
-                float qt[3] = {qc[0], qc[1], qc[2]};
-                qt[a] += sgn ? -1.f : 1.f;
-                clsbits |= (uint32_t)classify_tap_fp32(S, qt, a, sgn) << (2 * (2 * a + sgn));
-            }
+            for (int a = 0; a < 3; a++)
+                #pragma unroll
+                for (int sgn = 0; sgn < 2; sgn++) {
+                    float qt[3] = {qc[0], qc[1], qc[2]};
+                    qt[a] += sgn ? -1.f : 1.f;
+                    clsbits |= (uint32_t)classify_tap_fp32(S, qt, a, sgn) << (2 * (2 * a + sgn));
+                }
+        }
         float Fp[3], Fm[3];
         F = trilinear_taps<REC>(A, S.pv, qx, qy, qz, Fp, Fm);
         uint32_t okbits = 0x3fu;          // bit t: tap t holds data
