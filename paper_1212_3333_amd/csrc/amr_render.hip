@@ -28,12 +28,21 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void re
     for (int i = threadIdx.x; i < 256; i += 64) s_lut[i] = A.lut[i];
     __syncthreads();
 
-    // One wave per block, one 8x8 pixel tile per wave.  XCD-aware order: blocks are dealt
-    // round-robin to the 8 XCDs, so XCD x takes the x-th band of tile rows and walks it column
-    // by column; the tiles in flight on one XCD then form a compact patch of the screen whose
-    // rays share bricks in that XCD's L2.
+    // One wave per block, one 8x8 pixel tile per wave.  Tiles are grouped in 4x4 super-tiles
+    // (32x32 pixels) numbered along a Morton curve; blocks are dealt round-robin to the 8 XCDs
+    // and XCD x renders super-tiles x, x + 8, x + 16, ...  Every XCD thus gets a share of every
+    // part of the image (the work per tile varies by 10x and more across the screen), while
+    // the tiles in flight on one XCD stay grouped in a few compact 32x32 patches whose rays
+    // share bricks in that XCD's L2.
     const int xcd = (int)(blockIdx.x % 8), li = (int)(blockIdx.x / 8);
-    const int col = li / A.band8, row = xcd * A.band8 + li % A.band8;
+    const int sidx = (li >> 4) * 8 + xcd;          // Morton index of the super-tile
+    int sx = 0, sy = 0;
+    #pragma unroll
+    for (int bit = 0; bit < 12; bit++) {
+        sx |= ((sidx >> (2 * bit)) & 1) << bit;
+        sy |= ((sidx >> (2 * bit + 1)) & 1) << bit;
+    }
+    const int col = sx * 4 + ((li & 15) >> 2), row = sy * 4 + (li & 3);
     if (col >= A.t8x || row >= A.t8y) return;
     const int lane = threadIdx.x & 63;
     const int pi = col * 8 + (lane & 7);
@@ -343,7 +352,7 @@ int amr_render(const amr_scene *S, const amr_camera *cams, int32_t ncams, const 
             pix_off += (int64_t)cams[c].width * cams[c].height;
             continue;
         }
-        const int grid = 8 * A.band8 * A.t8x;
+        const int grid = 8 * ((A.sgrid * A.sgrid + 7) / 8) * 16;
         const bool rec = A.trace || A.trace_n || A.nsamp || A.stats || A.touch || A.ckpt;
         if (A.lighting) {
             if (rec) hipLaunchKernelGGL((render_fwd<true, true>), dim3(grid), dim3(64), 0, s, A);

@@ -51,7 +51,8 @@ struct RenderArgs {
     int64_t ckpt_stride;             // bytes per ray
     int32_t ckpt_every, ckpt_max;
     int32_t tiles_x, tiles_y, nblocks;     // 16x16 tiles of four waves (learned kernel)
-    int32_t t8x, t8y, band8;               // 8x8 one-wave tiles; tile rows per XCD band
+    int32_t t8x, t8y, sgrid;               // 8x8 one-wave tiles; side of the power-of-two
+                                           // grid of 4x4-tile super-tiles covering them
 };
 
 struct BwdArgs {
@@ -722,7 +723,8 @@ inline int fill_args(const amr_scene *S, const amr_camera *C, const amr_render_p
     A->nblocks = A->tiles_x * A->tiles_y;
     A->t8x = (C->width + 7) / 8;
     A->t8y = (C->height + 7) / 8;
-    A->band8 = (A->t8y + 7) / 8;
+    A->sgrid = 1;
+    while (A->sgrid * 4 < A->t8x || A->sgrid * 4 < A->t8y) A->sgrid *= 2;
     A->ckpt = (uint8_t *)P->d_ckpt;
     A->ckpt_stride = (int64_t)sizeof(Ckpt) * (1 + (int64_t)P->ckpt_max);
     A->ckpt_every = P->ckpt_every > 0 ? P->ckpt_every : 1;

@@ -105,3 +105,59 @@ def test_autotune_picks_a_candidate(gpu, tiny, tmp_path):
     assert len(res["table"]) == len(autotune.CANDIDATE_TILES) * len(autotune.CANDIDATE_BPC)
     again = autotune.tune(scene, cams, lut_t, prm, dc, q, out, "tiny-test", cache_path=str(tmp_path / "cache.json"))
     assert again == res
+
+
+def test_serving_batch_latency(gpu, tmp_path):
+    """Serving-style batch on the cosmology-like hierarchy: 64 orbit cameras with resolutions from
+    {256^2, 512^2, 768^2, 1024^2} in one persistent launch captured in a hipGraph, with the tile
+    shape and blocks per CU chosen by the autotuner.  Reports per-image latency (launch start to
+    the image's completion stamp) p50/p99 and aggregate Mrays/s; sampled images are bit-identical
+    to single-camera renders."""
+    import torch
+    amr = gpu
+    from paper_1212_3333_amd import autotune
+    h, lut, cam0, prm = workloads.cosmology_view(0)
+    tree = amr.build_tree(h)
+    scene = amr.pack(tree, h, device="cuda")
+    lut_t = torch.from_numpy(lut).cuda()
+    cams = workloads.serving_cameras(0, 64)
+    dc = amr.camera_table(cams)
+    q = amr.queue_buffer(len(cams))
+    npix = sum(c["width"] * c["height"] for c in cams)
+    out = torch.zeros(npix * 4, dtype=torch.float32, device="cuda")
+    best = autotune.tune(scene, cams, lut_t, prm, dc, q, out, workload_key="serving64", reps=1,
+                         cache_path=str(tmp_path / "tune.json"))
+    print("autotuned:", {k: best[k] for k in ("tile_w", "tile_h", "blocks_per_cu", "ms")})
+    stamps = torch.zeros(len(cams) + 1, dtype=torch.int64, device="cuda")
+    bprm = dict(prm, persistent=1, tile_w=best["tile_w"], tile_h=best["tile_h"], blocks_per_cu=best["blocks_per_cu"])
+    amr.render(scene, cams, lut_t, bprm, out=out, d_cams=dc, d_queue=q, d_stamps=stamps)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            amr.render(scene, cams, lut_t, bprm, out=out, d_cams=dc, d_queue=q, d_stamps=stamps)
+    lat, agg = [], []
+    for rep in range(3):
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        g.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        st = stamps.cpu().numpy()
+        khz = amr.wall_clock_khz()
+        assert np.all(st[:-1] >= st[-1]) and st[-1] > 0
+        lat.append((st[:-1] - st[-1]) / khz)                 # ms
+        agg.append(npix / (e0.elapsed_time(e1) * 1e-3) / 1e6)
+    lat = np.concatenate(lat)
+    print("batch %d rays: p50 %.2f ms, p99 %.2f ms, aggregate %.1f Mrays/s" % (
+        npix, np.percentile(lat, 50), np.percentile(lat, 99), float(np.median(agg))))
+    # images: the smallest and the largest camera against single-camera renders
+    offs = np.cumsum([0] + [c["width"] * c["height"] for c in cams])
+    sizes = [c["width"] * c["height"] for c in cams]
+    for c in (int(np.argmin(sizes)), int(np.argmax(sizes))):
+        ref = amr.render(scene, cams[c], lut_t, prm)["rgba"].reshape(-1, 4)
+        torch.cuda.synchronize()
+        assert torch.equal(out.view(-1, 4)[offs[c]:offs[c + 1]], ref)
+
