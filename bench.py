@@ -176,6 +176,7 @@ def learned_skip_section(amr, dev, steps, warmup):
         "learned_mrays_per_s": round(W_ * H_ / (ms_l * 1e-3) / 1e6, 3),
         "max_rgba_err_vs_plain": err, "tau_e": te, "tau_s": ts,
         "skipped_segments": l_stats["skipped_segments"], "coarse_segments": l_stats["coarse_segments"],
+        "net_segments": l_stats["net_segments"], "segments": l_stats["segments"],
         "plain_samples": p_stats["samples"], "learned_samples": l_stats["samples"],
         "train_segments": int(X.shape[0]), "train_calibrate_s": round(train_s, 2), "prepare_s": round(prep, 2),
     }

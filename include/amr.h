@@ -180,7 +180,8 @@ typedef struct {                        /* device counters, accumulated by amr_r
     unsigned long long split_samples;   /* lit samples with a tap outside the sample's brick */
     unsigned long long face_taps;       /* taps read from a leaf face's single slab owner */
     unsigned long long unsure_taps;     /* taps classified in FP64 (within 1e-3 cell of a face) */
-    unsigned long long reserved_[3];
+    unsigned long long net_segments;    /* learned form: segments the network was asked about */
+    unsigned long long reserved_[2];
 } amr_render_stats;
 
 typedef struct {

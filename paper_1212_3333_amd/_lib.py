@@ -74,11 +74,11 @@ class amr_trace_rec(ctypes.Structure):
 
 STATS_FIELDS = ("samples", "segments", "rays_hit", "tap_descents", "guard_hits", "trace_overflow",
                 "skipped_segments", "coarse_segments", "seglog_count", "ckpt_overflow", "split_samples",
-                "face_taps", "unsure_taps")
+                "face_taps", "unsure_taps", "net_segments")
 
 
 class amr_render_stats(ctypes.Structure):
-    _fields_ = [(n, ctypes.c_uint64) for n in STATS_FIELDS] + [("reserved_", ctypes.c_uint64 * 3)]
+    _fields_ = [(n, ctypes.c_uint64) for n in STATS_FIELDS] + [("reserved_", ctypes.c_uint64 * 2)]
 
 
 class amr_render_params(ctypes.Structure):

@@ -44,7 +44,7 @@ struct LearnLds {
     _Float16 w1t[64 * 16], w2t[64 * 64], w3t[16 * 64];
     float b1[64], b2[64], b3[4];
     _Float16 feat[4][64 * 16];
-    _Float16 h1[4][16 * 64], h2[4][16 * 64];
+    _Float16 hid[4][16 * 64];  // layer 1 output, then layer 2 output in place
     float out[4][64 * 2];
 };
 
@@ -65,7 +65,7 @@ __device__ __forceinline__ void sigma_range(const LearnLds &s, int i0, int i1, f
 __device__ __forceinline__ void infer_tile(LearnLds &s, int wave, int rt) {
     const int lane = threadIdx.x & 63, lr = lane & 15, lq = lane >> 4;
     const _Float16 *x16 = s.feat[wave] + rt * 16 * 16;
-    _Float16 *h1 = s.h1[wave], *h2 = s.h2[wave];
+    _Float16 *hid = s.hid[wave];
     half4 a = *reinterpret_cast<const half4 *>(x16 + lr * 16 + 4 * lq);
     #pragma unroll
     for (int ct = 0; ct < 4; ct++) {
@@ -73,26 +73,31 @@ __device__ __forceinline__ void infer_tile(LearnLds &s, int wave, int rt) {
         float4v acc = {0.f, 0.f, 0.f, 0.f};
         acc = __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, acc, 0, 0, 0);
         #pragma unroll
-        for (int j = 0; j < 4; j++) h1[(4 * lq + j) * 64 + ct * 16 + lr] = (_Float16)fmaxf(acc[j] + s.b1[ct * 16 + lr], 0.f);
+        for (int j = 0; j < 4; j++) hid[(4 * lq + j) * 64 + ct * 16 + lr] = (_Float16)fmaxf(acc[j] + s.b1[ct * 16 + lr], 0.f);
     }
+    __builtin_amdgcn_wave_barrier();
+    // layer 2: the A fragments of h1 are the same for every output block, so read them once and
+    // overwrite the buffer with h2
+    half4 a2[4];
+    #pragma unroll
+    for (int ks = 0; ks < 4; ks++) a2[ks] = *reinterpret_cast<const half4 *>(hid + lr * 64 + ks * 16 + 4 * lq);
     __builtin_amdgcn_wave_barrier();
     #pragma unroll
     for (int ct = 0; ct < 4; ct++) {
         float4v acc = {0.f, 0.f, 0.f, 0.f};
         #pragma unroll
         for (int ks = 0; ks < 4; ks++) {
-            half4 a2 = *reinterpret_cast<const half4 *>(h1 + lr * 64 + ks * 16 + 4 * lq);
             half4 b = *reinterpret_cast<const half4 *>(s.w2t + (ct * 16 + lr) * 64 + ks * 16 + 4 * lq);
-            acc = __builtin_amdgcn_mfma_f32_16x16x16f16(a2, b, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x16f16(a2[ks], b, acc, 0, 0, 0);
         }
         #pragma unroll
-        for (int j = 0; j < 4; j++) h2[(4 * lq + j) * 64 + ct * 16 + lr] = (_Float16)fmaxf(acc[j] + s.b2[ct * 16 + lr], 0.f);
+        for (int j = 0; j < 4; j++) hid[(4 * lq + j) * 64 + ct * 16 + lr] = (_Float16)fmaxf(acc[j] + s.b2[ct * 16 + lr], 0.f);
     }
     __builtin_amdgcn_wave_barrier();
     float4v acc = {0.f, 0.f, 0.f, 0.f};
     #pragma unroll
     for (int ks = 0; ks < 4; ks++) {
-        half4 a3 = *reinterpret_cast<const half4 *>(h2 + lr * 64 + ks * 16 + 4 * lq);
+        half4 a3 = *reinterpret_cast<const half4 *>(hid + lr * 64 + ks * 16 + 4 * lq);
         half4 b = *reinterpret_cast<const half4 *>(s.w3t + lr * 64 + ks * 16 + 4 * lq);
         acc = __builtin_amdgcn_mfma_f32_16x16x16f16(a3, b, acc, 0, 0, 0);
     }
@@ -105,6 +110,7 @@ __device__ __forceinline__ void infer_tile(LearnLds &s, int wave, int rt) {
 }
 
 enum { kModePlain = 0, kModeSkip = 1, kModeCoarse = 2 };
+constexpr int kNetMinSamples = 8;
 
 template <bool LIT>
 __global__ __launch_bounds__(256) void render_learned(RenderArgs A, LearnArgs G) {
@@ -136,18 +142,26 @@ __global__ __launch_bounds__(256) void render_learned(RenderArgs A, LearnArgs G)
     __syncthreads();
     const float4 *s_lut = s.lut;
 
-    const int per = (A.nblocks + 7) / 8;
-    const int tile = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
-    if (tile >= A.nblocks) return;
+    // 16x16-pixel tiles (four waves) grouped in 2x2 super-tiles of 32x32 pixels numbered along
+    // a Morton curve and dealt round-robin to the 8 XCDs, as in the plain forward kernel.
+    const int xcd = (int)(blockIdx.x % 8), li = (int)(blockIdx.x / 8);
+    const int sidx = (li >> 2) * 8 + xcd;
+    int sx = 0, sy = 0;
+    #pragma unroll
+    for (int bit = 0; bit < 12; bit++) {
+        sx |= ((sidx >> (2 * bit)) & 1) << bit;
+        sy |= ((sidx >> (2 * bit + 1)) & 1) << bit;
+    }
+    const int tx = sx * 2 + ((li & 3) >> 1), ty = sy * 2 + (li & 1);
+    if (tx >= A.tiles_x || ty >= A.tiles_y) return;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int tx = tile % A.tiles_x, ty = tile / A.tiles_x;
     const int pi = tx * 16 + (wave & 1) * 8 + (lane & 7);
     const int pj = ty * 16 + (wave >> 1) * 8 + (lane >> 3);
     const bool valid = pi < A.width && pj < A.height;
     const int64_t ray = (int64_t)pj * A.width + pi;
 
     Counters cnt;
-    unsigned int c_skip = 0, c_coarse = 0;
+    unsigned int c_skip = 0, c_coarse = 0, c_net = 0;
     float C0 = 0.f, C1 = 0.f, C2 = 0.f, T = 1.f;
     float budget = 0.f;                   // sum of T * alpha_hi over the segments skipped so far
     int nsamp_total = 0;
@@ -165,9 +179,10 @@ __global__ __launch_bounds__(256) void render_learned(RenderArgs A, LearnArgs G)
         int leaf = -1;
         bool data = false;
         Segment S;
-        float feat[kIn];
-        float a_bound_hi = 1.f;
+        float a_bound_hi = 1.f;           // analytic bound on the segment opacity
+        float a_bound_lo = 0.f;           // and its analytic lower bound
         float a_use = 1.f;                // upper bound charged to the skip budget
+        float len = 0.f, umin = 0.f, umax = 0.f, smin = 0.f, smax = 0.f, smean = 0.f;
         if (active) {
             leaf = descend(A, R, tcur, tb);
             if (leaf < 0) {
@@ -178,42 +193,55 @@ __global__ __launch_bounds__(256) void render_learned(RenderArgs A, LearnArgs G)
                 data = L.patch >= 0;
                 if (data) {
                     setup_segment<LIT>(A, R, L, leaf, tcur, tb, S);
-                    const DPatch &P = A.patches[L.patch];
-                    const float len = (float)(tb - tcur);
-                    const float umin = __saturatef((L.vmin - A.v_lo) * A.inv_range);
-                    const float umax = __saturatef((L.vmax - A.v_lo) * A.inv_range);
+                    len = (float)(tb - tcur);
+                    umin = __saturatef((L.vmin - A.v_lo) * A.inv_range);
+                    umax = __saturatef((L.vmax - A.v_lo) * A.inv_range);
                     const int i0 = min((int)(255.f * umin), 255);
                     const int i1 = min((int)ceilf(255.f * umax), 255);
-                    float smin, smax, smean;
                     sigma_range(s, i0, max(i0, i1), smin, smax, smean);
-                    feat[0] = (float)leaf_level(L) * inv_lmax;
-                    feat[1] = log2f(fmaxf(len / (float)P.step, 1e-3f)) * 0.125f;
-                    feat[2] = umin;
-                    feat[3] = umax;
-                    feat[4] = 1.f - __expf(-smax * 1.00001f * len);
-                    feat[5] = 1.f - __expf(-smean * len);
-                    feat[6] = 1.f - __expf(-smin * len);
-                    feat[7] = (float)min(S.n, 256) * (1.f / 256.f);
-                    feat[8] = (float)fabs(R.d[0]);
-                    feat[9] = (float)fabs(R.d[1]);
-                    feat[10] = (float)fabs(R.d[2]);
-                    feat[11] = log2f((float)min(P.n[0], min(P.n[1], P.n[2]))) * (1.f / 6.f);
-                    a_bound_hi = feat[4];
+                    a_bound_hi = 1.f - __expf(-smax * 1.00001f * len);
+                    a_bound_lo = 1.f - __expf(-smin * len);
                     a_use = a_bound_hi;
                 }
             }
         }
+        // the 12 features of a data segment (logged for training and fed to the network)
+        auto features = [&](float *feat) {
+            const DLeaf &L = A.leaves[leaf];
+            const DPatch &P = A.patches[L.patch];
+            feat[0] = (float)leaf_level(L) * inv_lmax;
+            feat[1] = log2f(fmaxf(len / (float)P.step, 1e-3f)) * 0.125f;
+            feat[2] = umin;
+            feat[3] = umax;
+            feat[4] = a_bound_hi;
+            feat[5] = 1.f - __expf(-smean * len);
+            feat[6] = a_bound_lo;
+            feat[7] = (float)min(S.n, 256) * (1.f / 256.f);
+            feat[8] = (float)fabs(R.d[0]);
+            feat[9] = (float)fabs(R.d[1]);
+            feat[10] = (float)fabs(R.d[2]);
+            feat[11] = log2f((float)min(P.n[0], min(P.n[1], P.n[2]))) * (1.f / 6.f);
+        };
         // decide: skip by the analytic bound, else ask the network (wave-level MFMA)
         int mode = kModePlain;
         if (G.mlp) {
             const bool bound_skip = data && budget + T * a_bound_hi < G.tau_e;
-            const bool undecided = data && !bound_skip;
+            // the network is asked only where its answer can change the decision and skipping
+            // pays for it: segments of at least kNetMinSamples samples whose bound did not
+            // already decide and whose analytic lower bound still fits the budget (or whose
+            // upper bound reaches the coarse threshold)
+            const bool undecided = data && !bound_skip && S.n >= kNetMinSamples &&
+                                   (budget + T * a_bound_lo < G.tau_e || a_bound_hi > 1.f - G.tau_s);
+            if (undecided) c_net++;
             if (bound_skip) mode = kModeSkip;
             const unsigned long long need = __ballot(undecided);
             if (need) {
+                float feat[kIn];
                 #pragma unroll
-                for (int j = 0; j < 16; j++)
-                    s.feat[wave][lane * 16 + j] = (_Float16)(undecided && j < kIn ? feat[j < kIn ? j : 0] : 0.f);
+                for (int j = 0; j < kIn; j++) feat[j] = 0.f;
+                if (undecided) features(feat);
+                #pragma unroll
+                for (int j = 0; j < 16; j++) s.feat[wave][lane * 16 + j] = (_Float16)(j < kIn ? feat[j < kIn ? j : 0] : 0.f);
                 __builtin_amdgcn_wave_barrier();
                 #pragma unroll
                 for (int rt = 0; rt < 4; rt++)
@@ -272,8 +300,7 @@ __global__ __launch_bounds__(256) void render_learned(RenderArgs A, LearnArgs G)
                     const unsigned long long slot = base + __popcll(mask & ((1ull << lane) - 1ull));
                     if (slot < (unsigned long long)G.seglog_cap) {
                         amr_seglog_rec r;
-                        #pragma unroll
-                        for (int j = 0; j < kIn; j++) r.feat[j] = feat[j];
+                        features(r.feat);
                         r.alpha_seg = 1.f - tseg;
                         r.t_in = full ? t_in : -t_in;
                         r.ray = (int32_t)ray;
@@ -297,10 +324,11 @@ __global__ __launch_bounds__(256) void render_learned(RenderArgs A, LearnArgs G)
         cnt.samples = nsamp_total;
         flush_counters(A.stats, cnt, lane);
         typedef unsigned long long u64;
-        u64 sk = wave_sum((u64)c_skip), co = wave_sum((u64)c_coarse);
+        u64 sk = wave_sum((u64)c_skip), co = wave_sum((u64)c_coarse), nn = wave_sum((u64)c_net);
         if (lane == 0) {
             if (sk) atomicAdd(&A.stats->skipped_segments, sk);
             if (co) atomicAdd(&A.stats->coarse_segments, co);
+            if (nn) atomicAdd(&A.stats->net_segments, nn);
         }
     }
 }
@@ -319,7 +347,7 @@ int launch_learned(const RenderArgs &A, const amr_render_params *P, int lmax, vo
     G.lmax = lmax;
     hipStream_t s = (hipStream_t)stream;
     if (G.seglog && first_camera) hipLaunchKernelGGL(seglog_reset, dim3(1), dim3(64), 0, s, G.seglog);
-    int grid = ((A.nblocks + 7) / 8) * 8;
+    const int grid = 8 * ((A.sgrid * A.sgrid + 7) / 8) * 4;
     if (A.lighting) hipLaunchKernelGGL(render_learned<true>, dim3(grid), dim3(256), 0, s, A, G);
     else hipLaunchKernelGGL(render_learned<false>, dim3(grid), dim3(256), 0, s, A, G);
     return check_hip(hipGetLastError(), "render_learned launch");

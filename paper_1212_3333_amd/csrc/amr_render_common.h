@@ -337,6 +337,27 @@ __device__ __forceinline__ float trilinear_taps(const RenderArgs &A, const Patch
     return F;
 }
 
+// Brick and patch-local position of world point x located in the tree; false where no patch
+// holds data or x is outside B (closed).
+template <bool REC>
+__device__ __forceinline__ bool locate_brick(const RenderArgs &A, const double x[3], PatchView &pv, float q[3],
+                                             Counters &cnt, uint32_t start = 0) {
+#pragma clang fp contract(off)
+    #pragma unroll
+    for (int a = 0; a < 3; a++)
+        if (x[a] < A.box_lo[a] || x[a] > A.box_hi[a]) return false;
+    int leaf = locate_leaf(A, x, start);
+    if (REC) cnt.desc++;
+    if (leaf < 0) return false;
+    int p = A.leaves[leaf].patch;
+    if (p < 0) return false;
+    const DPatch &P = A.patches[p];
+    pv = patch_view(A, P);
+    #pragma unroll
+    for (int a = 0; a < 3; a++) q[a] = (float)((x[a] - P.lo[a]) * P.inv_h[a] - 0.5);
+    return true;
+}
+
 // Field value at world point x located in the tree; false where no patch holds data or x is
 // outside B (closed).
 template <bool REC>
@@ -534,10 +555,12 @@ __device__ __forceinline__ void eval_sample(const RenderArgs &A, const float4 *s
                 const float step = sgn ? -1.f : 1.f;
                 const float qt0 = qx + (a == 0 ? step : 0.f), qt1 = qy + (a == 1 ? step : 0.f),
                             qt2 = qz + (a == 2 ? step : 0.f);
-                // exact FP64 tap position x = o + t_k d, then +- h^l along axis a (needed near a
-                // face and for descents)
-                double xt[3];
-                if (c != kTapFace) {
+                // Each tap only chooses a brick and a position in it; one trilinear read follows.
+                // The exact FP64 tap position x = o + t_k d +- h^l e_a is formed near a face
+                // and for descents.
+                double xt[3] = {0.0, 0.0, 0.0};
+                const bool exact = c != kTapFace;
+                if (exact) {
 #pragma clang fp contract(off)
                     const double tk = S.ta + ((double)k + 0.5) * S.delta;
                     #pragma unroll
@@ -550,25 +573,25 @@ __device__ __forceinline__ void eval_sample(const RenderArgs &A, const float4 *s
                 }
                 if (REC && c == kTapUnsure) cnt.unsure++;
                 if (c == kTapUnsure) c = classify_tap_fp64(A, S, xt, a, sgn);
-                float Fs = 0.f;
+                PatchView pv = S.pv;
+                float q0 = qt0, q1 = qt1, q2 = qt2;
                 bool ok = true;
-                if (c == kTapSame) {
-                    Fs = trilinear<REC>(A, S.pv, qt0, qt1, qt2);
-                } else {
+                if (c != kTapSame) {
                     const DFaceXf X = c == kTapFace ? A.face_xf[6 * S.leaf + 2 * a + (sgn ? 0 : 1)] : DFaceXf{};
                     if (c == kTapFace && X.n[0] > 0) {
                         // the slab's single owner: its brick at the mapped position
                         if (REC) cnt.face++;
-                        PatchView pv;
                         pv.brick = A.pool + X.off;
                         pv.px = X.px;
                         pv.pxy = X.pxy;
                         pv.nx = X.n[0];
                         pv.ny = X.n[1];
                         pv.nz = X.n[2];
-                        Fs = trilinear<REC>(A, pv, qt0 * X.r + X.t[0], qt1 * X.r + X.t[1], qt2 * X.r + X.t[2]);
+                        q0 = qt0 * X.r + X.t[0];
+                        q1 = qt1 * X.r + X.t[1];
+                        q2 = qt2 * X.r + X.t[2];
                     } else {
-                        if (c == kTapFace) {
+                        if (!exact) {
 #pragma clang fp contract(off)
                             const double tk = S.ta + ((double)k + 0.5) * S.delta;
                             #pragma unroll
@@ -581,9 +604,14 @@ __device__ __forceinline__ void eval_sample(const RenderArgs &A, const float4 *s
                         }
                         // descend from the rope node holding the slab, else from the root (a
                         // slab beyond B fails the box test there, except on B's closed upper faces)
-                        ok = field_at<REC>(A, xt, &Fs, cnt, c == kTapFace && X.rope > 0 ? (uint32_t)X.rope : 0u);
+                        float qq[3];
+                        ok = locate_brick<REC>(A, xt, pv, qq, cnt, c == kTapFace && X.rope > 0 ? (uint32_t)X.rope : 0u);
+                        q0 = qq[0];
+                        q1 = qq[1];
+                        q2 = qq[2];
                     }
                 }
+                const float Fs = ok ? trilinear<REC>(A, pv, q0, q1, q2) : 0.f;
                 if (!ok) okbits &= ~(1u << t);
                 // write the tap back (selects keep the arrays in registers)
                 #pragma unroll
