@@ -222,7 +222,10 @@ typedef struct {
     int32_t persistent;                 /* 1: persistent tile-queue kernel */
     int32_t tile_w, tile_h;             /* pixels per wave tile (0 = default 8 x 8) */
     int32_t blocks_per_cu;              /* persistent grid = 256 CUs x this (0 = default) */
-    int32_t flags_;
+    int32_t interp;                     /* sampling of the cell-centred data: 0 trilinear with the
+                                           ghost layer, 1 the value of the cell holding the point
+                                           (nearest cell, as Section 5 samples cell data; plain
+                                           forward kernel only, AMR_EINVAL elsewhere) */
     void *d_queue;                      /* persistent: device scratch, >= amr_queue_bytes(ncams) */
     unsigned long long *d_stamps;       /* persistent: [ncams + 1] device clock when each image
                                            completed, then the launch start (optional) */

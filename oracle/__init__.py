@@ -50,7 +50,8 @@ class Params(ctypes.Structure):
     _fields_ = [("v_lo", ctypes.c_double), ("v_hi", ctypes.c_double), ("step_frac", ctypes.c_double),
                 ("t_min", ctypes.c_double), ("light", ctypes.c_double * 3), ("k_a", ctypes.c_double),
                 ("k_d", ctypes.c_double), ("eps_g", ctypes.c_double), ("clip_lo", ctypes.c_double * 3),
-                ("clip_hi", ctypes.c_double * 3), ("uniform_step", ctypes.c_int32), ("lighting", ctypes.c_int32)]
+                ("clip_hi", ctypes.c_double * 3), ("uniform_step", ctypes.c_int32), ("lighting", ctypes.c_int32),
+                ("interp", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
 SEG_DTYPE = np.dtype([("leaf", np.int32), ("patch", np.int32), ("n", np.int32), ("level", np.int32),
@@ -71,6 +72,8 @@ def _load():
             lib.orc_locate.argtypes = [_P, _P, ctypes.c_int]
             lib.orc_field.restype = ctypes.c_double
             lib.orc_field.argtypes = [_P, _P, ctypes.POINTER(ctypes.c_int)]
+            lib.orc_field_mode.restype = ctypes.c_double
+            lib.orc_field_mode.argtypes = [_P, _P, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
             lib.orc_patch_value.restype = ctypes.c_double
             lib.orc_patch_value.argtypes = [_P, ctypes.c_int, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64]
             lib.orc_ray.argtypes = [ctypes.POINTER(Camera), ctypes.c_int, ctypes.c_int, _P, _P]
@@ -111,6 +114,7 @@ def make_params(p: dict, f32: bool = True) -> Params:
     q.clip_hi[:] = [float(x) for x in p["clip_hi"]]
     q.uniform_step = int(bool(p["uniform_step"]))
     q.lighting = int(bool(p["lighting"]))
+    q.interp = int(p.get("interp", 0))
     return q
 
 
@@ -170,10 +174,11 @@ class Oracle:
         x = np.ascontiguousarray(x, dtype=np.float64)
         return self.lib.orc_locate(self.handle, _ptr(x), int(brute))
 
-    def field(self, x):
+    def field(self, x, interp: int = 0):
+        """F(x), trilinear (interp 0) or nearest cell (interp 1); None where no patch holds x."""
         x = np.ascontiguousarray(x, dtype=np.float64)
         ok = ctypes.c_int(0)
-        v = self.lib.orc_field(self.handle, _ptr(x), ctypes.byref(ok))
+        v = self.lib.orc_field_mode(self.handle, _ptr(x), int(interp), ctypes.byref(ok))
         return v if ok.value else None
 
     def patch_value(self, p, i, j, k) -> float:

@@ -46,6 +46,7 @@ typedef struct {
     double k_a, k_d, eps_g;
     double clip_lo[3], clip_hi[3];
     int32_t uniform_step, lighting;
+    int32_t interp, pad_;       /* 0 trilinear (ghosts g1-g4), 1 nearest cell */
 } orc_params;
 
 typedef struct {
@@ -379,13 +380,35 @@ static double field_in(Orc *O, int p, const double x[3]) {
     return trilin(O, p, i0, f);
 }
 
-/* F(x); returns 0 and sets *ok = 0 where no patch holds x. */
-double orc_field(Orc *O, const double *x, int *ok) {
+/* Nearest-neighbour value of patch p at world point x (Section 5 samples cell-centred data
+ * without interpolation): the value of the interior cell holding x, floor((x - lo) / h), the
+ * index clamped into the patch (a point on B's closed upper face lies in the last cell). */
+static double nearest_in(Orc *O, int p, const double x[3]) {
+    int l = (int)O->plev[p];
+    int64_t i[3];
+    for (int a = 0; a < 3; a++) {
+        double lo = plane(O, a, O->gplo[3 * p + a]);
+        int64_t c = (int64_t)floor((x[a] - lo) / O->hl[3 * l + a]);
+        int64_t n = O->pdims[3 * p + a];
+        i[a] = c < 0 ? 0 : (c >= n ? n - 1 : c);
+    }
+    return cell(O, p, i[0], i[1], i[2]);
+}
+
+static double value_in(Orc *O, int p, const double x[3], int interp) {
+    return interp ? nearest_in(O, p, x) : field_in(O, p, x);
+}
+
+/* F(x) with the given interpolation; returns 0 and sets *ok = 0 where no patch holds x. */
+double orc_field_mode(Orc *O, const double *x, int interp, int *ok) {
     int p = orc_locate(O, x, 0);
     if (p < 0) { if (ok) *ok = 0; return 0.0; }
     if (ok) *ok = 1;
-    return field_in(O, p, x);
+    return value_in(O, p, x, interp);
 }
+
+/* F(x) (trilinear); returns 0 and sets *ok = 0 where no patch holds x. */
+double orc_field(Orc *O, const double *x, int *ok) { return orc_field_mode(O, x, 0, ok); }
 
 double orc_patch_value(Orc *O, int p, int64_t i, int64_t j, int64_t k) { return pval(O, p, i, j, k); }
 
@@ -512,7 +535,7 @@ static void shade_sample(Orc *O, const orc_params *P, const double lhat[3], int 
         xp[a] = x[a] + O->hl[3 * lev + a];
         xm[a] = x[a] - O->hl[3 * lev + a];
         int okp, okm;
-        double Fp = orc_field(O, xp, &okp), Fm = orc_field(O, xm, &okm);
+        double Fp = orc_field_mode(O, xp, P->interp, &okp), Fm = orc_field_mode(O, xm, P->interp, &okm);
         double g;
         if (okp && okm) g = (Fp - Fm) / (2.0 * range);
         else if (okp) g = (Fp - F0) / range;
@@ -576,7 +599,7 @@ static int walk_ray(Orc *O, const orc_camera *cam, const orc_params *P, const do
                 double t = ta + ((double)j + 0.5) * delta;
                 double x[3];
                 for (int a = 0; a < 3; a++) x[a] = o[a] + t * d[a];
-                double F0 = field_in(O, p, x);
+                double F0 = value_in(O, p, x, P->interp);
                 sample_t s;
                 classify(lut, F0, P, &s);
                 s.delta = delta;

@@ -92,7 +92,7 @@ class amr_render_params(ctypes.Structure):
                 ("d_mlp", VP), ("tau_e", ctypes.c_float), ("tau_s", ctypes.c_float),
                 ("d_seglog", VP), ("seglog_cap", ctypes.c_int64),
                 ("persistent", ctypes.c_int32), ("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32),
-                ("blocks_per_cu", ctypes.c_int32), ("flags_", ctypes.c_int32),
+                ("blocks_per_cu", ctypes.c_int32), ("interp", ctypes.c_int32),
                 ("d_queue", VP), ("d_stamps", VP), ("d_cams", VP), ("d_touch", VP)]
 
 

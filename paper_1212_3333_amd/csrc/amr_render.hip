@@ -22,7 +22,7 @@ namespace amr {
 
 // At least 3 waves per SIMD: the lit kernel then fits 168 VGPRs with a 12-byte spill instead
 // of running 2 waves at 171 (the unlit one needs 80 and runs 6).
-template <bool LIT, bool REC>
+template <bool LIT, bool REC, bool NEAR>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void render_fwd(RenderArgs A) {
     __shared__ float4 s_lut[256];
     for (int i = threadIdx.x; i < 256; i += 64) s_lut[i] = A.lut[i];
@@ -101,7 +101,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void re
             nsm = S.n;
             for (int k = 0; k < nsm; k++) {
                 SampleVals v;
-                eval_sample<LIT, REC>(A, s_lut, R, S, k, v, cnt);
+                eval_sample<LIT, REC, NEAR>(A, s_lut, R, S, k, v, cnt);
                 float wgt = T * v.alpha * v.shade;
                 C0 += wgt * v.r;
                 C1 += wgt * v.g;
@@ -323,6 +323,11 @@ int amr_render(const amr_scene *S, const amr_camera *cams, int32_t ncams, const 
             return AMR_ECAPACITY;
         }
     }
+    if (P->interp == 1 && (P->persistent || P->d_mlp || P->d_seglog || P->d_ckpt)) {
+        set_error("nearest-cell sampling (interp = 1) is rendered by the plain forward kernel only "
+                  "(not persistent, learned, logging or checkpointed)");
+        return AMR_EINVAL;
+    }
     if (P->persistent) return launch_persistent(S, cams, ncams, P, d_rgba, d_stats, stream);
     hipStream_t s = (hipStream_t)stream;
     if (d_stats) {
@@ -354,12 +359,20 @@ int amr_render(const amr_scene *S, const amr_camera *cams, int32_t ncams, const 
         }
         const int grid = 8 * ((A.sgrid * A.sgrid + 7) / 8) * 16;
         const bool rec = A.trace || A.trace_n || A.nsamp || A.stats || A.touch || A.ckpt;
-        if (A.lighting) {
-            if (rec) hipLaunchKernelGGL((render_fwd<true, true>), dim3(grid), dim3(64), 0, s, A);
-            else hipLaunchKernelGGL((render_fwd<true, false>), dim3(grid), dim3(64), 0, s, A);
+        if (A.nearest) {
+            if (A.lighting) {
+                if (rec) hipLaunchKernelGGL((render_fwd<true, true, true>), dim3(grid), dim3(64), 0, s, A);
+                else hipLaunchKernelGGL((render_fwd<true, false, true>), dim3(grid), dim3(64), 0, s, A);
+            } else {
+                if (rec) hipLaunchKernelGGL((render_fwd<false, true, true>), dim3(grid), dim3(64), 0, s, A);
+                else hipLaunchKernelGGL((render_fwd<false, false, true>), dim3(grid), dim3(64), 0, s, A);
+            }
+        } else if (A.lighting) {
+            if (rec) hipLaunchKernelGGL((render_fwd<true, true, false>), dim3(grid), dim3(64), 0, s, A);
+            else hipLaunchKernelGGL((render_fwd<true, false, false>), dim3(grid), dim3(64), 0, s, A);
         } else {
-            if (rec) hipLaunchKernelGGL((render_fwd<false, true>), dim3(grid), dim3(64), 0, s, A);
-            else hipLaunchKernelGGL((render_fwd<false, false>), dim3(grid), dim3(64), 0, s, A);
+            if (rec) hipLaunchKernelGGL((render_fwd<false, true, false>), dim3(grid), dim3(64), 0, s, A);
+            else hipLaunchKernelGGL((render_fwd<false, false, false>), dim3(grid), dim3(64), 0, s, A);
         }
         rc = check_hip(hipGetLastError(), "render_fwd launch");
         if (rc) return rc;
@@ -376,6 +389,7 @@ int amr_render_backward(const amr_scene *S, const amr_camera *cams, int32_t ncam
         return AMR_EINVAL;
     }
     if (!P->d_ckpt) { set_error("the adjoint needs the forward's checkpoints (params.d_ckpt)"); return AMR_EINVAL; }
+    if (P->interp != 0) { set_error("the adjoint is defined for trilinear sampling (interp = 0)"); return AMR_EINVAL; }
     int64_t total = 0;
     for (int c = 0; c < ncams; c++) total += (int64_t)cams[c].width * cams[c].height;
     if (P->ckpt_max < 2 || P->ckpt_bytes < amr_ckpt_bytes(total, P->ckpt_max)) {

@@ -29,6 +29,7 @@ struct RenderArgs {
     const DLeaf *leaves;
     const DPatch *patches;
     const DFaceXf *face_xf;          // [nleaves][6] gradient-tap records
+    int32_t nearest;                 // 1: nearest-cell sampling instead of trilinear
     const float4 *lut;
     double box_lo[3], box_hi[3];     // B (closed, for gradient taps)
     double clip_lo[3], clip_hi[3];   // B ∩ clip box
@@ -431,9 +432,9 @@ __device__ __forceinline__ void setup_segment(const RenderArgs &A, const Ray &R,
             S.fs_lo[a] = lo + 1.f + kTapMargin;
             S.fs_hi[a] = hi - 1.f - kTapMargin;
         }
-        S.leaf = leaf;
-        S.patch = L.patch;
     }
+    S.leaf = leaf;
+    S.patch = L.patch;
 }
 
 struct SampleVals {
@@ -513,15 +514,127 @@ __device__ __forceinline__ float patch_value_at(const RenderArgs &A, int p, cons
     return trilinear<REC>(A, pv, q[0], q[1], q[2]);
 }
 
+// Interior cell (i, j, k) of a padded brick (0 <= index < n).
+__device__ __forceinline__ float brick_cell(const RenderArgs &A, const PatchView &pv, int i, int j, int k) {
+    i++;
+    j++;
+    k++;
+    if (A.micro) return pv.brick[(k >> 2) * pv.pxy + (j >> 2) * pv.px + (i >> 2) * 64 + (k & 3) * 16 + (j & 3) * 4 + (i & 3)];
+    return pv.brick[i + j * pv.px + k * pv.pxy];
+}
+
+// Index of the cell holding world coordinate x along one axis of a patch, as the definition
+// reads: floor((x - lo) / h), clamped into the patch (FP64, correctly rounded).
+__device__ __forceinline__ int cell_index(double x, double lo, double h, int n) {
+#pragma clang fp contract(off)
+    const double c = floor((x - lo) / h);
+    return c < 0.0 ? 0 : (c >= (double)n ? n - 1 : (int)c);
+}
+
+// Nearest-cell value of world point x located in the tree; false where no patch holds data or
+// x is outside B (closed).
+template <bool REC>
+__device__ __forceinline__ bool nearest_at(const RenderArgs &A, const double x[3], float *val, Counters &cnt) {
+    #pragma unroll
+    for (int a = 0; a < 3; a++)
+        if (x[a] < A.box_lo[a] || x[a] > A.box_hi[a]) return false;
+    const int leaf = locate_leaf(A, x, 0);
+    if (REC) cnt.desc++;
+    if (leaf < 0) return false;
+    const int p = A.leaves[leaf].patch;
+    if (p < 0) return false;
+    const DPatch &P = A.patches[p];
+    const PatchView pv = patch_view(A, P);
+    *val = brick_cell(A, pv, cell_index(x[0], P.lo[0], P.h[0], P.n[0]), cell_index(x[1], P.lo[1], P.h[1], P.n[1]),
+                      cell_index(x[2], P.lo[2], P.h[2], P.n[2]));
+    return true;
+}
+
+// Nearest-cell sampling (interp = 1): F(x) is the value of the cell of the finest patch that
+// holds x.  The cell index is taken in fp32 patch-local coordinates when the point is at least
+// the classification margin away from every cell face, else from the FP64 position exactly as
+// defined; taps x +- h^l e_a step one cell in the same brick when they stay in it, else they
+// are located in the tree from their FP64 position.
+template <bool LIT, bool REC>
+__device__ __forceinline__ float nearest_sample(const RenderArgs &A, const Ray &R, const Segment &S, int k, float qx,
+                                                float qy, float qz, float gv[3], Counters &cnt) {
+    const float qc[3] = {qx, qy, qz};
+    int ci[3];
+    bool sure = true;
+    #pragma unroll
+    for (int a = 0; a < 3; a++) {
+        const float u = qc[a] + 0.5f, fl = floorf(u), fr = u - fl;
+        sure = sure && fr >= kTapMargin && fr <= 1.f - kTapMargin;
+        ci[a] = (int)fl;
+    }
+    const DPatch &P = A.patches[S.patch];
+    double x[3];
+    {
+#pragma clang fp contract(off)
+        const double tk = S.ta + ((double)k + 0.5) * S.delta;
+        #pragma unroll
+        for (int b = 0; b < 3; b++) x[b] = R.o[b] + tk * R.d[b];
+    }
+    if (!sure) {
+        #pragma unroll
+        for (int a = 0; a < 3; a++) ci[a] = cell_index(x[a], P.lo[a], P.h[a], P.n[a]);
+    }
+    ci[0] = min(max(ci[0], 0), S.pv.nx - 1);
+    ci[1] = min(max(ci[1], 0), S.pv.ny - 1);
+    ci[2] = min(max(ci[2], 0), S.pv.nz - 1);
+    const float F = brick_cell(A, S.pv, ci[0], ci[1], ci[2]);
+    if (LIT) {
+        float Fs[6];
+        uint32_t okbits = 0x3fu;
+        #pragma unroll
+        for (int t = 0; t < 6; t++) {
+            const int a = t >> 1, sgn = t & 1;
+            float qt[3] = {qc[0], qc[1], qc[2]};
+            qt[a] += sgn ? -1.f : 1.f;
+            const int c = classify_tap_fp32(S, qt, a, sgn);
+            if (sure && c == kTapSame) {
+                int cj[3] = {ci[0], ci[1], ci[2]};
+                cj[a] += sgn ? -1 : 1;
+                cj[0] = min(max(cj[0], 0), S.pv.nx - 1);
+                cj[1] = min(max(cj[1], 0), S.pv.ny - 1);
+                cj[2] = min(max(cj[2], 0), S.pv.nz - 1);
+                Fs[t] = brick_cell(A, S.pv, cj[0], cj[1], cj[2]);
+            } else {
+                double xt[3] = {x[0], x[1], x[2]};
+                {
+#pragma clang fp contract(off)
+                    xt[a] = sgn ? x[a] - P.h[a] : x[a] + P.h[a];
+                }
+                float val = 0.f;
+                if (!nearest_at<REC>(A, xt, &val, cnt)) okbits &= ~(1u << t);
+                Fs[t] = val;
+            }
+        }
+        #pragma unroll
+        for (int a = 0; a < 3; a++) {
+            const bool okp = (okbits >> (2 * a)) & 1u, okm = (okbits >> (2 * a + 1)) & 1u;
+            float gr;
+            if (okp && okm) gr = (Fs[2 * a] - Fs[2 * a + 1]) * (0.5f * A.inv_range);
+            else if (okp) gr = (Fs[2 * a] - F) * A.inv_range;
+            else if (okm) gr = (F - Fs[2 * a + 1]) * A.inv_range;
+            else gr = 0.f;
+            gv[a] = gr;
+        }
+    }
+    return F;
+}
+
 // Sample k of a segment: value, LUT classification, opacity over the step, and (LIT) the
 // gradient shading with taps at x +- h^l e_a located in the tree.
-template <bool LIT, bool REC>
+template <bool LIT, bool REC, bool NEAR = false>
 __device__ __forceinline__ void eval_sample(const RenderArgs &A, const float4 *s_lut, const Ray &R, const Segment &S,
                                             int k, SampleVals &v, Counters &cnt) {
     const float kk = (float)k + 0.5f;
     const float qx = S.q0[0] + kk * S.dq[0], qy = S.q0[1] + kk * S.dq[1], qz = S.q0[2] + kk * S.dq[2];
     float F;
-    if (LIT) {
+    if (NEAR) {
+        F = nearest_sample<LIT, REC>(A, R, S, k, qx, qy, qz, v.gv, cnt);
+    } else if (LIT) {
         // value and the six taps x +- h^l e_a from this brick in one fused stencil; a tap that
         // leaves the brick (classified in fp32, else FP64) is then read where it lands
         const float qc[3] = {qx, qy, qz};
@@ -712,6 +825,8 @@ inline int fill_args(const amr_scene *S, const amr_camera *C, const amr_render_p
     A->leaves = (const DLeaf *)S->leaves;
     A->patches = (const DPatch *)S->patches;
     A->face_xf = (const DFaceXf *)S->face_taps;
+    if (P->interp != 0 && P->interp != 1) { set_error("interp must be 0 (trilinear) or 1 (nearest cell)"); return AMR_EINVAL; }
+    A->nearest = P->interp;
     A->lut = (const float4 *)P->d_lut;
     #pragma unroll
     for (int a = 0; a < 3; a++) {

@@ -222,3 +222,65 @@ def test_cosmology_full_size_sampled(gpu, cosmology_scene, lit):
     assert err <= TOL
     assert ores["trace_n"].max() <= cap
     _compare_traces(amr, sub, ores)
+
+
+@pytest.mark.parametrize("lit", [False, True])
+@pytest.mark.parametrize("cam_idx", [0, 1])
+def test_nearest_small_nested(gpu, cam_idx, lit):
+    """Nearest-cell sampling (interp = 1): full images against the oracle, traces bit-exact."""
+    amr = gpu
+    h, lut, cams, prm = workloads.small_nested(0)
+    prm = dict(prm, lighting=lit, interp=1)
+    tree, scene = _setup(amr, h)
+    gout = _gpu_render(amr, scene, cams[cam_idx], lut, prm, trace_cap=64, stats=True)
+    ores = oracle.Oracle(h).render(cams[cam_idx], prm, lut, trace_cap=64)
+    err = np.abs(gout["rgba"].cpu().numpy().reshape(-1, 4) - ores["rgba"]).max()
+    print("nearest cam%d lit=%d max|err|=%.3g" % (cam_idx, lit, err))
+    assert err <= TOL
+    _compare_traces(amr, gout, ores)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_nearest_random_hierarchies(gpu, seed):
+    amr = gpu
+    h = workloads.random_tiny(seed, multi_root=(seed % 2 == 1))
+    lut = workloads.lut_bumps(np.random.default_rng(seed), sigma_scale=12.0)
+    vmax = float(max(p.cells.max() for p in h.patches))
+    prm = workloads.default_params(v_hi=vmax, lighting=(seed % 2 == 0), interp=1)
+    cam = workloads.perspective_orbit(37, 23, 0.3 + seed, 0.2 * seed - 0.4, radius=1.8)
+    tree, scene = _setup(amr, h)
+    gout = _gpu_render(amr, scene, cam, lut, prm, trace_cap=256)
+    ores = oracle.Oracle(h).render(cam, prm, lut, trace_cap=256)
+    assert np.abs(gout["rgba"].cpu().numpy().reshape(-1, 4) - ores["rgba"]).max() <= TOL
+    _compare_traces(amr, gout, ores)
+
+
+def test_nearest_cosmology_sampled(gpu, cosmology_scene):
+    """Nearest-cell sampling on the cosmology-like hierarchy at 1024^2, lit: a seeded pixel sample
+    against the oracle."""
+    import torch
+    amr = gpu
+    h, lut, cam, prm, tree, scene = cosmology_scene
+    prm = dict(prm, interp=1)
+    out = amr.render(scene, cam, torch.from_numpy(lut).cuda(), prm)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(11)
+    pix = np.stack([rng.integers(0, cam["width"], 1500), rng.integers(0, cam["height"], 1500)], 1).astype(np.int32)
+    ref = oracle.Oracle(h).render(cam, prm, lut, pixels=pix)["rgba"]
+    got = out["rgba"].cpu().numpy()[pix[:, 1], pix[:, 0]]
+    err = np.abs(got - ref).max()
+    print("nearest cosmology: max|err| = %.3g" % err)
+    assert err <= TOL
+
+
+def test_nearest_rejected_outside_plain_forward(gpu):
+    import torch
+    amr = gpu
+    h, lut, cams, prm = workloads.small_nested(0)
+    tree, scene = _setup(amr, h)
+    lut_t = torch.from_numpy(lut).cuda()
+    with pytest.raises(amr.AMRError, match="nearest"):
+        amr.render_checkpointed(scene, cams[0], lut_t, dict(prm, interp=1))
+    with pytest.raises(amr.AMRError, match="interp"):
+        amr.render(scene, cams[0], lut_t, dict(prm, interp=2))
+

@@ -147,18 +147,19 @@ def test_linear_field_closed_form(cam_name, uniform, lit):
     assert hits > 0
 
 
+@pytest.mark.parametrize("interp", [0, 1])
 @pytest.mark.parametrize("lit", [False, True])
-def test_single_level_matches_scipy(lit):
+def test_single_level_matches_scipy(lit, interp):
     """One subgrid: the tree is a single leaf and the render reduces to a uniform-grid raycast.
-    Samples are evaluated with scipy's textbook trilinear (map_coordinates, order 1, edge
-    replication outside the grid), the LUT with np.interp and compositing with a running
-    product."""
+    Samples are evaluated with scipy's textbook interpolation (map_coordinates, order 1 for
+    trilinear and order 0 for nearest cell, edge replication outside the grid), the LUT with
+    np.interp and compositing with a running product."""
     h = workloads.single_level((12, 10, 8))
     lut = workloads.lut_bumps(np.random.default_rng(9), sigma_scale=8.0)
     cells = h.patches[0].cells.astype(np.float64)
     vmax = float(cells.max())
     prm = workloads.default_params(v_lo=0.0, v_hi=vmax, t_min=0.0, lighting=lit, k_a=0.25, k_d=0.75,
-                                   eps_g=2.0 ** -10, light=(0.5, 1.0, 0.25))
+                                   eps_g=2.0 ** -10, light=(0.5, 1.0, 0.25), interp=interp)
     centre = h.origin + 0.5 * h.h0 * np.array([12, 10, 8])
     e, u, v, w = workloads.look_at(centre + np.array([0.3, 0.5, -0.9]), centre)
     cam = workloads.camera(e, u, v, w, 20, 16, tan_half_fov=0.35)
@@ -172,7 +173,7 @@ def test_single_level_matches_scipy(lit):
 
     def F(pts):
         q = (pts - h.origin) / hgrid - 0.5
-        return map_coordinates(cells, [q[:, 2], q[:, 1], q[:, 0]], order=1, mode="nearest")
+        return map_coordinates(cells, [q[:, 2], q[:, 1], q[:, 0]], order=1 - interp, mode="nearest")
 
     for q in range(len(res["pixels"])):
         i, j = res["pixels"][q]
@@ -364,3 +365,40 @@ def test_constant_field_sigma_derivative():
     dA = 64 * 1.0 * math.exp(-sig * 1.0)       # chord length 1 for every pixel
     assert abs(glut[i0, 3] - (1 - f) * dA) < 1e-12
     assert abs(glut[i0 + 1, 3] - f * dA) < 1e-12
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_nearest_field_brute_force(seed):
+    """Nearest-cell field on random hierarchies: at random points (and points on cell faces) the
+    value is the cell of the finest patch holding the point, found by brute force over patches
+    in integer finest-level coordinates."""
+    h = workloads.random_tiny(seed, multi_root=(seed % 2 == 1))
+    O = Oracle(h)
+    fb = oracle.finest_boxes(h)
+    hf = h.h0 / h.refine ** (h.nlevels - 1)
+    Blo = fb[fb[:, 0] == 0][:, 1:4].min(0)
+    Bhi = fb[fb[:, 0] == 0][:, 4:7].max(0)
+    rng = np.random.default_rng(seed)
+    checked = 0
+    for trial in range(400):
+        g = Blo + rng.random(3) * (Bhi - Blo)
+        if trial % 4 == 0:
+            g = np.floor(g)                  # on finest-cell faces
+        x = h.origin + g * hf
+        best = -1
+        for p, row in enumerate(fb):
+            lo, hi = row[1:4], row[4:7]
+            inside = np.all((g >= lo) & ((g < hi) | ((g == hi) & (hi == Bhi))))
+            if inside and (best < 0 or row[0] > fb[best][0]):
+                best = p
+        v = O.field(x, interp=1)
+        if best < 0:
+            assert v is None
+            continue
+        P = h.patches[best]
+        S = h.refine ** (h.nlevels - 1 - P.level)
+        idx = np.clip(np.floor((g - fb[best][1:4]) / S).astype(np.int64), 0, np.array(P.cells.shape[::-1]) - 1)
+        assert v == float(P.cells[idx[2], idx[1], idx[0]])
+        checked += 1
+    assert checked > 100
+

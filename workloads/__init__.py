@@ -287,7 +287,7 @@ def small_nested_cameras(width=256, height=256):
 def default_params(**kw) -> dict:
     p = dict(v_lo=0.0, v_hi=1.0, step_frac=0.5, uniform_step=False, t_min=1e-5, lighting=False,
              light=(1.0, 1.0, 1.0), k_a=0.3, k_d=0.7, eps_g=1e-3,
-             clip_lo=(-1e300, -1e300, -1e300), clip_hi=(1e300, 1e300, 1e300))
+             clip_lo=(-1e300, -1e300, -1e300), clip_hi=(1e300, 1e300, 1e300), interp=0)
     p.update(kw)
     return p
 
