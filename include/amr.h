@@ -140,6 +140,11 @@ typedef struct {
     int64_t pool_bytes, meta_bytes;
     int32_t nnodes, nleaves, npatches, nlevels;
     int32_t lmax, refine, depth, brick_layout;
+    int32_t nlod;               /* kind-(a) nodes (inside one subgrid, all of its cells refined
+                                   further; Section 4.1): records nleaves .. nleaves + nlod - 1 of
+                                   `leaves` (and of the face tables) describe them in pre-order,
+                                   with the covering coarse patch, for level-of-detail renders */
+    int32_t reserved_i_;
     double box_lo[3], box_hi[3];        /* B in world coordinates */
     double origin[3], h0[3], hfine[3];  /* hfine = h0 / refine^lmax */
     double step_fine;                   /* min_a h^lmax_a */
@@ -226,6 +231,12 @@ typedef struct {
                                            ghost layer, 1 the value of the cell holding the point
                                            (nearest cell, as Section 5 samples cell data; plain
                                            forward kernel only, AMR_EINVAL elsewhere) */
+    float lod;                          /* level of detail (Sections 4.1 and 5.3): the kD-restart
+                                           descent stops at a kind-(a) node when the cells of its
+                                           covering coarse patch project to fewer than lod pixels
+                                           at the segment start (perspective: h < lod t (2 tan /
+                                           height); orthographic: h < lod (2 win_y / height)), and
+                                           renders the node's segment from that patch; 0 = off */
     void *d_queue;                      /* persistent: device scratch, >= amr_queue_bytes(ncams) */
     unsigned long long *d_stamps;       /* persistent: [ncams + 1] device clock when each image
                                            completed, then the launch start (optional) */

@@ -51,7 +51,7 @@ class Params(ctypes.Structure):
                 ("t_min", ctypes.c_double), ("light", ctypes.c_double * 3), ("k_a", ctypes.c_double),
                 ("k_d", ctypes.c_double), ("eps_g", ctypes.c_double), ("clip_lo", ctypes.c_double * 3),
                 ("clip_hi", ctypes.c_double * 3), ("uniform_step", ctypes.c_int32), ("lighting", ctypes.c_int32),
-                ("interp", ctypes.c_int32), ("pad", ctypes.c_int32)]
+                ("interp", ctypes.c_int32), ("pad", ctypes.c_int32), ("lod", ctypes.c_double)]
 
 
 SEG_DTYPE = np.dtype([("leaf", np.int32), ("patch", np.int32), ("n", np.int32), ("level", np.int32),
@@ -72,6 +72,7 @@ def _load():
             lib.orc_locate.argtypes = [_P, _P, ctypes.c_int]
             lib.orc_field.restype = ctypes.c_double
             lib.orc_field.argtypes = [_P, _P, ctypes.POINTER(ctypes.c_int)]
+            lib.orc_set_lod_nodes.argtypes = [_P, ctypes.c_int, _P]
             lib.orc_field_mode.restype = ctypes.c_double
             lib.orc_field_mode.argtypes = [_P, _P, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
             lib.orc_patch_value.restype = ctypes.c_double
@@ -115,6 +116,7 @@ def make_params(p: dict, f32: bool = True) -> Params:
     q.uniform_step = int(bool(p["uniform_step"]))
     q.lighting = int(bool(p["lighting"]))
     q.interp = int(p.get("interp", 0))
+    q.lod = _f32(p.get("lod", 0.0))
     return q
 
 
@@ -134,6 +136,23 @@ def finest_boxes(h) -> np.ndarray:
         out[i, 1:4] = np.asarray(p.lo) * s
         out[i, 4:7] = (np.asarray(p.lo) + np.asarray(p.dims)) * s
     return out
+
+
+def lod_nodes(tree: kdbuild.Tree, h) -> np.ndarray:
+    """int64[na, 9] for the kind-(a) nodes in pre-order: lo[3], hi[3] (finest-cell units), cover
+    patch, cover level, depth (root 0).  A level-of-detail segment through the k-th of them is
+    reported with leaf id nleaves + k."""
+    kinds = tree.kinds()
+    depth = {id(tree.root): 0}
+    for n in tree.nodes:
+        if not n.is_leaf:
+            depth[id(n.low)] = depth[id(n)] + 1
+            depth[id(n.high)] = depth[id(n)] + 1
+    rows = []
+    for n, k in zip(tree.nodes, kinds):
+        if k == kdbuild.KIND_A:
+            rows.append(list(n.lo) + list(n.hi) + [n.cover, h.patches[n.cover].level, depth[id(n)]])
+    return np.ascontiguousarray(np.array(rows, dtype=np.int64).reshape(-1, 9))
 
 
 class Oracle:
@@ -163,6 +182,8 @@ class Oracle:
         self.handle = self.lib.orc_create(_ptr(self._origin), _ptr(self._h0), int(h.refine), int(h.nlevels), np_,
                                           _ptr(self._pmeta), _ptr(self._poff), _ptr(self._cells),
                                           len(self._leaves), _ptr(self._leaves))
+        self._anodes = lod_nodes(self.tree, h)
+        self.lib.orc_set_lod_nodes(self.handle, len(self._anodes), _ptr(self._anodes))
 
     def __del__(self):
         if getattr(self, "handle", None):

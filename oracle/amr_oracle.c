@@ -47,6 +47,9 @@ typedef struct {
     double clip_lo[3], clip_hi[3];
     int32_t uniform_step, lighting;
     int32_t interp, pad_;       /* 0 trilinear (ghosts g1-g4), 1 nearest cell */
+    double lod;                 /* level of detail (Section 4.1, kind-(a) nodes): a node is
+                                   rendered from its coarse patch when that patch's cells
+                                   project to fewer than lod pixels; 0 disables */
 } orc_params;
 
 typedef struct {
@@ -76,6 +79,9 @@ typedef struct {
     int **cand;          /* per patch: patches whose boxes meet the 1-cell dilated box */
     int *ncand;
     int *bin_start, *bin_list;   /* patch lookup bins (conservative) */
+    int na;              /* kind-(a) nodes, in the tree's pre-order */
+    int64_t *anode;      /* [na][9] lo3 hi3 (finest units), cover patch, cover level, depth */
+    double *aw;          /* [na][6] world planes */
 } Orc;
 
 static int64_t ipow(int64_t b, int e) { int64_t r = 1; while (e-- > 0) r *= b; return r; }
@@ -208,7 +214,23 @@ void orc_destroy(Orc *O) {
     free(O->plev); free(O->plo); free(O->pdims); free(O->gplo); free(O->gphi); free(O->poff);
     free(O->hl); free(O->hs); free(O->rpow); free(O->leaf); free(O->lw);
     free(O->bin_start); free(O->bin_list);
+    free(O->anode); free(O->aw);
     free(O);
+}
+
+/* The kind-(a) nodes (internal nodes inside one subgrid whose cells are all refined further,
+ * Section 4.1) that a level-of-detail render may stop at. */
+void orc_set_lod_nodes(Orc *O, int na, const int64_t *recs) {
+    free(O->anode); free(O->aw);
+    O->na = na;
+    O->anode = (int64_t *)malloc(sizeof(int64_t) * 9 * (na > 0 ? na : 1));
+    O->aw = (double *)malloc(sizeof(double) * 6 * (na > 0 ? na : 1));
+    memcpy(O->anode, recs, sizeof(int64_t) * 9 * na);
+    for (int i = 0; i < na; i++)
+        for (int a = 0; a < 3; a++) {
+            O->aw[6 * i + a] = plane(O, a, O->anode[9 * i + a]);
+            O->aw[6 * i + 3 + a] = plane(O, a, O->anode[9 * i + 3 + a]);
+        }
 }
 
 /* ------------------------------------------------------------------------------------ */
@@ -527,15 +549,26 @@ static void classify(const double *lut, double F, const orc_params *P, sample_t 
     s->sigma = lerp(lut[4 * i0 + 3], lut[4 * (i0 + 1) + 3], f);
 }
 
+/* The field a gradient tap reads: inside the box of a level-of-detail segment (half-open) the
+ * segment's coarse patch, elsewhere the finest data. */
+static double tap_field(Orc *O, const orc_params *P, const double *lodbox, int lodp, const double x[3], int *ok) {
+    if (lodbox) {
+        int in = 1;
+        for (int a = 0; a < 3; a++) in = in && x[a] >= lodbox[a] && x[a] < lodbox[3 + a];
+        if (in) { *ok = 1; return value_in(O, lodp, x, P->interp); }
+    }
+    return orc_field_mode(O, x, P->interp, ok);
+}
+
 static void shade_sample(Orc *O, const orc_params *P, const double lhat[3], int lev, double F0,
-                         const double x[3], sample_t *s) {
+                         const double x[3], const double *lodbox, int lodp, sample_t *s) {
     double range = P->v_hi - P->v_lo;
     for (int a = 0; a < 3; a++) {
         double xp[3] = {x[0], x[1], x[2]}, xm[3] = {x[0], x[1], x[2]};
         xp[a] = x[a] + O->hl[3 * lev + a];
         xm[a] = x[a] - O->hl[3 * lev + a];
         int okp, okm;
-        double Fp = orc_field_mode(O, xp, P->interp, &okp), Fm = orc_field_mode(O, xm, P->interp, &okm);
+        double Fp = tap_field(O, P, lodbox, lodp, xp, &okp), Fm = tap_field(O, P, lodbox, lodp, xm, &okm);
         double g;
         if (okp && okm) g = (Fp - Fm) / (2.0 * range);
         else if (okp) g = (Fp - F0) / range;
@@ -578,11 +611,61 @@ static int walk_ray(Orc *O, const orc_camera *cam, const orc_params *P, const do
     double C[3] = {0, 0, 0}, T = 1.0;
     double ta = t0;
     int done = 0;
+    /* level of detail: the kind-(a) nodes the ray crosses, with their slab intervals */
+    const int lod_on = P->lod > 0.0 && O->na > 0;
+    double pix = 0.0;
+    int nA = 0;
+    double *aint = NULL;   /* [nA][2] te, tx */
+    int *aid = NULL;
+    if (lod_on) {
+        pix = cam->ortho ? (2.0 * cam->win[1]) / (double)cam->height : (2.0 * cam->tan_half_fov) / (double)cam->height;
+        aint = (double *)malloc(sizeof(double) * 2 * O->na);
+        aid = (int *)malloc(sizeof(int) * O->na);
+        double inv[3];
+        for (int a = 0; a < 3; a++) inv[a] = d[a] != 0.0 ? 1.0 / d[a] : 0.0;
+        for (int i = 0; i < O->na; i++) {
+            double te = t0, tx = t1;
+            int miss = 0;
+            for (int a = 0; a < 3 && !miss; a++) {
+                double lo = O->aw[6 * i + a], hi = O->aw[6 * i + 3 + a];
+                if (d[a] == 0.0) { if (!(o[a] >= lo && o[a] < hi)) miss = 1; continue; }
+                double tA = (lo - o[a]) * inv[a], tB = (hi - o[a]) * inv[a];
+                double tn = tA < tB ? tA : tB, tf = tA < tB ? tB : tA;
+                if (tn > te) te = tn;
+                if (tf < tx) tx = tf;
+            }
+            if (miss || !(tx > te)) continue;
+            aint[2 * nA] = te; aint[2 * nA + 1] = tx; aid[nA] = i; nA++;
+        }
+    }
     for (int k = 0; k < n && !done; k++) {
         cand_t *c = &(*cbuf)[k];
         double tb = c->tx;
         const int64_t *L = &O->leaf[8 * c->leaf];
         int p = (int)L[6], lev = (int)L[7];
+        int seg_id = c->leaf;
+        const double *lodbox = NULL;
+        if (lod_on) {
+            /* the shallowest kind-(a) node holding the ray just after ta whose coarse cells
+               project to fewer than lod pixels at ta: render it whole from its cover patch */
+            int best = -1;
+            for (int q = 0; q < nA; q++) {
+                if (!(aint[2 * q] <= ta && ta < aint[2 * q + 1])) continue;
+                const int64_t *A = &O->anode[9 * aid[q]];
+                double foot = cam->ortho ? pix : ta * pix;
+                if (!(O->hs[A[7]] < P->lod * foot)) continue;
+                if (best < 0 || A[8] < O->anode[9 * aid[best] + 8]) best = q;
+            }
+            if (best >= 0) {
+                const int64_t *A = &O->anode[9 * aid[best]];
+                tb = aint[2 * best + 1];
+                p = (int)A[6];
+                lev = (int)A[7];
+                seg_id = O->nl + aid[best];
+                lodbox = &O->aw[6 * aid[best]];
+                while (k + 1 < n && (*cbuf)[k + 1].tx <= tb) k++;   /* leaves inside the node */
+            }
+        }
         int slev = P->uniform_step ? O->lmax : lev;
         double step = P->step_frac * O->hs[slev];
         double ratio = (tb - ta) / step;
@@ -591,7 +674,7 @@ static int walk_ray(Orc *O, const orc_camera *cam, const orc_params *P, const do
         double delta = (tb - ta) / (double)ns;
         if (trace && *trace_n < trace_cap) {
             orc_seg *s = &trace[*trace_n];
-            s->leaf = c->leaf; s->patch = p; s->n = p >= 0 ? (int)ns : 0; s->level = lev; s->ta = ta; s->tb = tb;
+            s->leaf = seg_id; s->patch = p; s->n = p >= 0 ? (int)ns : 0; s->level = lev; s->ta = ta; s->tb = tb;
         }
         if (trace_n) (*trace_n)++;
         if (p >= 0) {
@@ -605,7 +688,7 @@ static int walk_ray(Orc *O, const orc_camera *cam, const orc_params *P, const do
                 s.delta = delta;
                 s.alpha = 1.0 - exp(-s.sigma * delta);
                 s.T = T;
-                if (P->lighting) shade_sample(O, P, lhat, lev, F0, x, &s);
+                if (P->lighting) shade_sample(O, P, lhat, lev, F0, x, lodbox, p, &s);
                 else { s.shade = 1.0; s.g[0] = s.g[1] = s.g[2] = 0; s.dot = 0; s.den = 0; }
                 for (int ch = 0; ch < 3; ch++) C[ch] += T * s.alpha * s.shade * s.rgb[ch];
                 T = T * (1.0 - s.alpha);
@@ -616,6 +699,7 @@ static int walk_ray(Orc *O, const orc_camera *cam, const orc_params *P, const do
         }
         ta = tb;
     }
+    free(aint); free(aid);
     rgba[0] = C[0]; rgba[1] = C[1]; rgba[2] = C[2]; rgba[3] = 1.0 - T;
     return flag;
 }

@@ -219,6 +219,7 @@ def make_params(p: dict, d_lut) -> L.amr_render_params:
     q.tile_h = int(p.get("tile_h", 0))
     q.blocks_per_cu = int(p.get("blocks_per_cu", 0))
     q.interp = int(p.get("interp", 0))
+    q.lod = float(p.get("lod", 0.0))
     return q
 
 

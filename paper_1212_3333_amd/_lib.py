@@ -55,7 +55,8 @@ class amr_scene(ctypes.Structure):
                 ("pool_bytes", ctypes.c_int64), ("meta_bytes", ctypes.c_int64),
                 ("nnodes", ctypes.c_int32), ("nleaves", ctypes.c_int32), ("npatches", ctypes.c_int32),
                 ("nlevels", ctypes.c_int32), ("lmax", ctypes.c_int32), ("refine", ctypes.c_int32),
-                ("depth", ctypes.c_int32), ("brick_layout", ctypes.c_int32),
+                ("depth", ctypes.c_int32), ("brick_layout", ctypes.c_int32), ("nlod", ctypes.c_int32),
+                ("reserved_i_", ctypes.c_int32),
                 ("box_lo", c_double3), ("box_hi", c_double3), ("origin", c_double3), ("h0", c_double3),
                 ("hfine", c_double3), ("step_fine", ctypes.c_double), ("v_min", ctypes.c_float),
                 ("v_max", ctypes.c_float)]
@@ -92,7 +93,7 @@ class amr_render_params(ctypes.Structure):
                 ("d_mlp", VP), ("tau_e", ctypes.c_float), ("tau_s", ctypes.c_float),
                 ("d_seglog", VP), ("seglog_cap", ctypes.c_int64),
                 ("persistent", ctypes.c_int32), ("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32),
-                ("blocks_per_cu", ctypes.c_int32), ("interp", ctypes.c_int32),
+                ("blocks_per_cu", ctypes.c_int32), ("interp", ctypes.c_int32), ("lod", ctypes.c_float),
                 ("d_queue", VP), ("d_stamps", VP), ("d_cams", VP), ("d_touch", VP)]
 
 

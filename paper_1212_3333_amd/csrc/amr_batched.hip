@@ -102,10 +102,11 @@ __device__ __forceinline__ void set_camera(RenderArgs &A, const amr_camera &C) {
     A.ortho = C.ortho;
     A.width = C.width;
     A.height = C.height;
+    A.lod_pix = C.ortho ? (2.0 * C.win[1]) / (double)C.height : (2.0 * C.tan_half_fov) / (double)C.height;
 }
 
 template <bool LIT, bool REC>
-__global__ __launch_bounds__(256) void render_batched(BatchArgs B) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void render_batched(BatchArgs B) {
     __shared__ float4 s_lut[256];
     s_lut[threadIdx.x] = B.base.lut[threadIdx.x];
     __syncthreads();

@@ -664,7 +664,13 @@ int amr_pack_pool(const amr_tree *T, const amr_patch *patches, int32_t npatches,
                                     : ((n[0] + 5) / 4) * ((n[1] + 5) / 4) * ((n[2] + 5) / 4) * 64;
         nfl = align_up(nfl + cells, 64);
     }
-    const int64_t nn = (int64_t)T->nodes.size(), nl = (int64_t)T->leaves.size();
+    const int64_t nn = (int64_t)T->nodes.size(), nl0 = (int64_t)T->leaves.size();
+    // kind-(a) nodes in pre-order: level-of-detail records nl0 + k after the leaves
+    std::vector<int32_t> aidx(T->nodes.size(), -1);
+    std::vector<int32_t> anodes;
+    for (int32_t i : T->preorder)
+        if (T->kind[i] == 0) { aidx[i] = (int32_t)anodes.size(); anodes.push_back(i); }
+    const int64_t na = (int64_t)anodes.size(), nl = nl0 + na;
     const int64_t o_nodes = 0;
     const int64_t o_leaves = align_up(o_nodes + nn * (int64_t)sizeof(DNode), 256);
     const int64_t o_patch = align_up(o_leaves + nl * (int64_t)sizeof(DLeaf), 256);
@@ -727,7 +733,7 @@ int amr_pack_pool(const amr_tree *T, const amr_patch *patches, int32_t npatches,
             } else {
                 d.split = world_plane(T, n.axis, n.split);
                 d.child = (uint32_t)order.size();
-                d.meta = node_meta(n.axis, n.level);
+                d.meta = node_meta(n.axis, n.level) | (aidx[order[h]] >= 0 ? (uint32_t)(aidx[order[h]] + 1) << 8 : 0u);
                 order.push_back(n.low);
                 order.push_back(n.high);
             }
@@ -761,18 +767,26 @@ int amr_pack_pool(const amr_tree *T, const amr_patch *patches, int32_t npatches,
             h.step = hmin / rl;
         }
         DLeaf *dl = (DLeaf *)(meta.data() + o_leaves);
-        for (size_t k = 0; k < T->leaves.size(); k++) {
-            const Node &n = T->nodes[T->leaves[k]];
+        for (int64_t k = 0; k < nl; k++) {
+            const bool virt = k >= nl0;           // a kind-(a) node, rendered from its cover patch
+            const Node &n = virt ? T->nodes[anodes[k - nl0]] : T->nodes[T->leaves[k]];
+            const int32_t np_k = virt ? n.cover : n.patch;
             DLeaf &L = dl[k];
             for (int a = 0; a < 3; a++) { L.lo[a] = world_plane(T, a, n.lo[a]); L.hi[a] = world_plane(T, a, n.hi[a]); }
-            L.patch = n.patch;
+            L.patch = np_k;
             int32_t *own = (int32_t *)(meta.data() + o_faces) + 6 * k;
-            L.level_flags = (uint32_t)n.level | (face_owners(T, n, bfs_index, own) << 8);
+            if (virt) {
+                // gradient taps leaving the node are located from the root
+                for (int f = 0; f < 6; f++) own[f] = -2;
+                L.level_flags = (uint32_t)T->plevel[np_k];
+            } else {
+                L.level_flags = (uint32_t)n.level | (face_owners(T, n, bfs_index, own) << 8);
+            }
             L.vmin = 0.0f;
             L.vmax = 0.0f;
-            if (n.patch >= 0) {
+            if (np_k >= 0) {
                 // value range over the leaf's cells plus one halo cell (padded-brick indices)
-                int p = n.patch;
+                int p = np_k;
                 int64_t S = T->scale[T->plevel[p]];
                 int64_t i0[3], i1[3];
                 for (int a = 0; a < 3; a++) {
@@ -796,8 +810,8 @@ int amr_pack_pool(const amr_tree *T, const amr_patch *patches, int32_t npatches,
         // gradient-tap records per leaf face (after the patch headers, which they read)
         DFaceXf *fx = (DFaceXf *)(meta.data() + o_fxf);
         const int32_t *own_all = (const int32_t *)(meta.data() + o_faces);
-        for (size_t k = 0; k < T->leaves.size(); k++) {
-            const int p = T->nodes[T->leaves[k]].patch;
+        for (int64_t k = 0; k < nl; k++) {
+            const int p = dl[k].patch;
             for (int f = 0; f < 6; f++) {
                 DFaceXf &X = fx[6 * k + f];
                 memset(&X, 0, sizeof(X));
@@ -834,7 +848,8 @@ int amr_pack_pool(const amr_tree *T, const amr_patch *patches, int32_t npatches,
         out->pool_bytes = pbytes;
         out->meta_bytes = mbytes;
         out->nnodes = (int32_t)nn;
-        out->nleaves = (int32_t)nl;
+        out->nleaves = (int32_t)nl0;
+        out->nlod = (int32_t)na;
         out->npatches = np;
         out->nlevels = T->dom.nlevels;
         out->lmax = T->lmax;

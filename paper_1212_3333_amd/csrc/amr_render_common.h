@@ -30,6 +30,9 @@ struct RenderArgs {
     const DPatch *patches;
     const DFaceXf *face_xf;          // [nleaves][6] gradient-tap records
     int32_t nearest;                 // 1: nearest-cell sampling instead of trilinear
+    int32_t lod_on, nleaves;         // level of detail enabled; real leaves (kind-(a) records follow)
+    double lod;                      // pixels
+    double lod_pix;                  // pixel footprint per unit distance (perspective) or per pixel
     const float4 *lut;
     double box_lo[3], box_hi[3];     // B (closed, for gradient taps)
     double clip_lo[3], clip_hi[3];   // B ∩ clip box
@@ -145,6 +148,14 @@ __device__ __forceinline__ int descend(const RenderArgs &A, const Ray &R, double
         DNode n = A.nodes[ni];
         uint32_t axis = n.meta & 3u;
         if (axis == kLeafAxis) return (int)n.child;
+        if (A.lod_on && (n.meta >> 8)) {
+            // a kind-(a) node: stop here when the cells of its coarse patch project to fewer than
+            // lod pixels at the segment start; the segment is then [tmin, tmax] across the node
+            const int vl = A.nleaves + (int)(n.meta >> 8) - 1;
+            const double h = A.patches[A.leaves[vl].patch].step;
+            const double foot = A.ortho ? A.lod_pix : tmin * A.lod_pix;
+            if (h < A.lod * foot) return vl;
+        }
         double oa = sel3(axis, R.o[0], R.o[1], R.o[2]);
         double da = sel3(axis, R.d[0], R.d[1], R.d[2]);
         double s = n.split;
@@ -827,6 +838,11 @@ inline int fill_args(const amr_scene *S, const amr_camera *C, const amr_render_p
     A->face_xf = (const DFaceXf *)S->face_taps;
     if (P->interp != 0 && P->interp != 1) { set_error("interp must be 0 (trilinear) or 1 (nearest cell)"); return AMR_EINVAL; }
     A->nearest = P->interp;
+    if (!(P->lod >= 0.f)) { set_error("lod must be >= 0"); return AMR_EINVAL; }
+    A->lod_on = P->lod > 0.f && S->nlod > 0;
+    A->lod = (double)P->lod;
+    A->nleaves = S->nleaves;
+    A->lod_pix = C->ortho ? (2.0 * C->win[1]) / (double)C->height : (2.0 * C->tan_half_fov) / (double)C->height;
     A->lut = (const float4 *)P->d_lut;
     #pragma unroll
     for (int a = 0; a < 3; a++) {

@@ -205,3 +205,28 @@ def test_tf_fit_200_adam_steps(gpu):
     print("colour LUT error on constrained entries %.4g -> %.4g" % (d0, d1))
     assert d1 < d0
 
+
+@pytest.mark.parametrize("lit", [False, True])
+def test_adjoint_with_lod(gpu, lit):
+    """The adjoint replays the level-of-detail segmentation: LUT and light gradients against the
+    oracle's on the level-of-detail geometry with lod = 3 pixels."""
+    import torch
+    amr = gpu
+    h = workloads.lod_blocks(0)
+    lut = workloads.lut_bumps(np.random.default_rng(3), sigma_scale=6.0)
+    vmax = float(max(p.cells.max() for p in h.patches))
+    prm = workloads.default_params(v_hi=vmax, lighting=lit, t_min=0.0, lod=3.0)
+    cam = workloads.perspective_orbit(40, 32, 0.9, 0.25, radius=1.7)
+    tree, scene = _scene(amr, h)
+    lut_t = torch.from_numpy(lut).cuda()
+    out, ck = amr.render_checkpointed(scene, cam, lut_t, prm)
+    G = np.random.default_rng(4).normal(size=(40 * 32, 4))
+    glut, glight = amr.render_backward(scene, cam, lut_t, prm, ck, torch.from_numpy(G.astype(np.float32)).cuda())
+    ref_lut, ref_light = oracle.Oracle(h).grad(cam, prm, lut.astype(np.float64), G)
+    e, n = _rel_ok(glut.cpu().numpy(), ref_lut, 1e-3, 1e-3)
+    print("lod adjoint lit=%d: LUT grad max rel err %.3g over %d entries" % (lit, e, n))
+    assert _bar_ok(glut.cpu().numpy(), ref_lut, 1e-3) and n > 20
+    if lit:
+        gl = glight.cpu().numpy()
+        assert np.all(np.abs(gl - ref_light) <= 1e-3 * np.abs(ref_light) + 1e-4 * np.abs(ref_light).max())
+

@@ -284,3 +284,49 @@ def test_nearest_rejected_outside_plain_forward(gpu):
     with pytest.raises(amr.AMRError, match="interp"):
         amr.render(scene, cams[0], lut_t, dict(prm, interp=2))
 
+
+@pytest.mark.parametrize("lit", [False, True])
+@pytest.mark.parametrize("lod", [1.5, 3.0, 1e6])
+@pytest.mark.parametrize("seed", range(3))
+def test_lod_vs_oracle(gpu, seed, lod, lit):
+    """Level-of-detail renders (the descent stops at kind-(a) nodes whose coarse cells project
+    below `lod` pixels): images against the oracle, traces bit-exact including the ids of the
+    level-of-detail segments (nleaves + the node's pre-order rank among kind-(a) nodes)."""
+    amr = gpu
+    h = workloads.lod_blocks(seed)
+    lut = workloads.lut_bumps(np.random.default_rng(seed), sigma_scale=6.0)
+    vmax = float(max(p.cells.max() for p in h.patches))
+    prm = workloads.default_params(v_hi=vmax, lighting=lit, lod=lod)
+    tree, scene = _setup(amr, h)
+    assert scene.scene.nlod > 0
+    for cam in (workloads.perspective_orbit(33, 25, 0.7 + seed, 0.3 - 0.2 * seed, radius=1.7),
+                workloads.ortho_oblique(24, 24)):
+        gout = _gpu_render(amr, scene, cam, lut, prm, trace_cap=128)
+        ores = oracle.Oracle(h).render(cam, prm, lut, trace_cap=128)
+        assert np.abs(gout["rgba"].cpu().numpy().reshape(-1, 4) - ores["rgba"]).max() <= TOL
+        _compare_traces(amr, gout, ores)
+        if lod >= 3.0:
+            assert np.any(ores["trace"]["leaf"] >= scene.scene.nleaves)
+
+
+def test_lod_cosmology_sampled(gpu, cosmology_scene):
+    """Level of detail (lod = 2 pixels) on the cosmology-like hierarchy at 1024^2, lit: a pixel
+    sample against the oracle; fewer samples than the full-detail render."""
+    import torch
+    amr = gpu
+    h, lut, cam, prm, tree, scene = cosmology_scene
+    lprm = dict(prm, lod=2.0)
+    lut_t = torch.from_numpy(lut).cuda()
+    out = amr.render(scene, cam, lut_t, lprm, stats=True)
+    full = amr.render(scene, cam, lut_t, prm, stats=True)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(12)
+    pix = np.stack([rng.integers(0, cam["width"], 1500), rng.integers(0, cam["height"], 1500)], 1).astype(np.int32)
+    ref = oracle.Oracle(h).render(cam, lprm, lut, pixels=pix)["rgba"]
+    got = out["rgba"].cpu().numpy()[pix[:, 1], pix[:, 0]]
+    err = np.abs(got - ref).max()
+    sl, sf = amr.stats_dict(out)["samples"], amr.stats_dict(full)["samples"]
+    print("lod cosmology: max|err| = %.3g, samples %d vs %d at full detail" % (err, sl, sf))
+    assert err <= TOL
+    assert sl < sf
+

@@ -402,3 +402,95 @@ def test_nearest_field_brute_force(seed):
         checked += 1
     assert checked > 100
 
+
+@pytest.mark.parametrize("lit", [False, True])
+@pytest.mark.parametrize("lod", [0.0, 1.5, 3.0, 1e6])
+@pytest.mark.parametrize("cam_name", ["ortho_z", "oblique", "persp"])
+def test_lod_linear_closed_form(cam_name, lod, lit):
+    """Level of detail on a linear field: a segment rendered from a coarse cover patch samples
+    the same linear function (its cells hold the same exact values), and the midpoint rule
+    integrates linear opacity exactly on any segmentation, so every pixel still obeys
+    A = 1 - exp(-s L u(x_mid)) and C = rgb shade A, whatever the level-of-detail cut."""
+    a = np.array([0.75, -0.375, 0.25]); b = 0.5
+    h = workloads.lod_blocks(1, field=workloads.linear_field(a, b))
+    s = 255.0 / 64
+    lut = workloads.lut_linear_sigma(s, rgb=(0.75, 0.5, 0.25))
+    m = 0.125
+    prm = workloads.default_params(v_lo=0.0, v_hi=2.0, t_min=0.0, lighting=lit, k_a=0.25, k_d=0.75,
+                                   eps_g=0.0, light=(1.0, 2.0, -0.5), lod=lod,
+                                   clip_lo=(m, m, m), clip_hi=(1 - m, 1 - m, 1 - m))
+    cam = CAMS[cam_name]
+    O = Oracle(h)
+    res = O.render(cam, prm, lut, trace_cap=64)
+    nl = len(O.tree.leaves)
+    l = np.array([_f32(x) for x in prm["light"]])
+    shade = 0.25 + 0.75 * abs(a @ l) / (np.linalg.norm(a) * np.linalg.norm(l)) if lit else 1.0
+    rgb = np.array([0.75, 0.5, 0.25])
+    rgba = res["rgba"].reshape(cam["height"], cam["width"], 4)
+    lod_segs = 0
+    for j in range(cam["height"]):
+        for i in range(cam["width"]):
+            q = j * cam["width"] + i
+            tr = res["trace"][q, :res["trace_n"][q]]
+            lod_segs += int(np.sum(tr["leaf"] >= nl))
+            o, d = oracle.ray(cam, i, j)
+            ch = _chord_faces(o, d, np.full(3, m), np.full(3, 1 - m))
+            if ch is None or ch[1] - ch[0] <= 0:
+                continue
+            xm = o + 0.5 * (ch[0] + ch[1]) * d
+            A = 1 - math.exp(-s * (ch[1] - ch[0]) * (a @ xm + b) / 2.0)
+            assert abs(rgba[j, i, 3] - A) < 1e-10
+            assert np.all(np.abs(rgba[j, i, :3] - rgb * shade * A) < 1e-10)
+    if lod >= 3.0:
+        assert lod_segs > 0
+    if lod == 0.0:
+        assert lod_segs == 0
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_lod_segments_structure(seed):
+    """With an unbounded threshold every kind-(a) node the ray enters away from the eye is cut:
+    each ray's segments tile its chord; a level-of-detail segment spans the ray's whole
+    intersection with an outermost kind-(a) node (one with no kind-(a) ancestor, found here by
+    box containment), is reported with that node's id and its cover patch and level; every
+    other segment is the plain render's leaf segment outside those nodes."""
+    h = workloads.lod_blocks(seed)
+    lut = workloads.lut_bumps(np.random.default_rng(seed), sigma_scale=4.0)
+    vmax = float(max(p.cells.max() for p in h.patches))
+    cam = workloads.perspective_orbit(20, 16, 0.7 + seed, 0.3 - 0.2 * seed, radius=1.7)
+    O = Oracle(h)
+    nl = len(O.tree.leaves)
+    an = O._anodes
+    hf = h.h0 / h.refine ** (h.nlevels - 1)
+    lo_w, hi_w = an[:, 0:3] * hf + h.origin, an[:, 3:6] * hf + h.origin
+    outer = [k for k in range(len(an)) if not any(
+        j != k and np.all(an[j, 0:3] <= an[k, 0:3]) and np.all(an[j, 3:6] >= an[k, 3:6]) for j in range(len(an)))]
+    base = O.render(cam, workloads.default_params(v_hi=vmax, t_min=0.0), lut, trace_cap=128)
+    res = O.render(cam, workloads.default_params(v_hi=vmax, t_min=0.0, lod=1e30), lut, trace_cap=128)
+    cut = 0
+    for q in range(len(res["pixels"])):
+        tr = res["trace"][q, :res["trace_n"][q]]
+        tb0 = base["trace"][q, :base["trace_n"][q]]
+        if len(tr) == 0:
+            assert len(tb0) == 0
+            continue
+        assert tr["ta"][0] == tb0["ta"][0] and tr["tb"][-1] == tb0["tb"][-1]
+        assert np.all(tr["tb"][:-1] == tr["ta"][1:])
+        i, j = res["pixels"][q]
+        o, d = oracle.ray(cam, i, j)
+        for sg in tr:
+            xm = o + 0.5 * (sg["ta"] + sg["tb"]) * d
+            inside = [k for k in outer if np.all(xm >= lo_w[k]) and np.all(xm < hi_w[k])]
+            if sg["leaf"] >= nl:
+                k = sg["leaf"] - nl
+                assert inside == [k]
+                assert sg["patch"] == an[k, 6] and sg["level"] == an[k, 7]
+                ch = _chord_faces(o, d, lo_w[k], hi_w[k])
+                assert abs(max(ch[0], tr["ta"][0]) - sg["ta"]) < 1e-12 and abs(min(ch[1], tr["tb"][-1]) - sg["tb"]) < 1e-12
+                cut += 1
+            else:
+                assert inside == []
+                hit = (tb0["ta"] == sg["ta"]) & (tb0["tb"] == sg["tb"]) & (tb0["leaf"] == sg["leaf"])
+                assert hit.sum() == 1
+    assert cut > 0
+

@@ -154,6 +154,39 @@ def tiny_samr(seed: int = 0) -> Hierarchy:
     return h.with_field(gaussian_sum_field(_rng(0, "field", MASTER_SEED + seed)))
 
 
+def lod_blocks(seed: int = 0, field=None) -> Hierarchy:
+    """Level-of-detail geometry: root 16^3 on [0,1]^3 (one level-0 patch); one half of the
+    domain along a seeded axis is fully tiled by k in {2, 4} abutting level-1 patches, and the
+    first of them is fully tiled by two level-2 patches.  The kD tree then holds two nested
+    kind-(a) nodes: the refined half, covered by the root patch, and the first level-1 patch,
+    covered by itself.  Field: sum of Gaussians, or `field`."""
+    rng = _rng(5, "patches", MASTER_SEED + seed)
+    k = int(rng.choice([2, 4]))
+    ax = int(rng.integers(0, 3))
+    side = int(rng.integers(0, 2))
+    b = int(rng.integers(0, 3))                 # second axis for the level-2 split
+    by = (ax + 1 + b % 2) % 3
+
+    def box(level, lo_a, len_a, other):
+        lo = np.zeros(3, dtype=np.int64)
+        dims = np.full(3, other, dtype=np.int64)
+        lo[ax], dims[ax] = lo_a, len_a
+        return lo, dims
+    ps = [_empty_patch(0, [0, 0, 0], [16, 16, 16])]
+    w1 = 16 // k
+    x0 = 16 * side                              # level-1 start of the refined half
+    for i in range(k):
+        lo, dims = box(1, x0 + i * w1, w1, 32)
+        ps.append(_empty_patch(1, lo, dims))
+    lo, dims = box(2, 2 * x0, 2 * w1, 64)
+    for j in range(2):
+        l2, d2 = lo.copy(), dims.copy()
+        l2[by], d2[by] = 32 * j, 32
+        ps.append(_empty_patch(2, l2, d2))
+    h = Hierarchy(np.zeros(3), np.full(3, 1.0 / 16), 2, 3, ps)
+    return h.with_field(field if field is not None else gaussian_sum_field(_rng(5, "field", MASTER_SEED + seed)))
+
+
 def random_tiny(seed: int, max_patches: int = 6, nlevels: int = 3, refine: int | None = None,
                 root_cells: int = 8, multi_root: bool = False) -> Hierarchy:
     """Small random hierarchies for builder/oracle pins: up to `max_patches` patches on
