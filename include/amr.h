@@ -195,7 +195,12 @@ typedef struct {
     float step_frac;                    /* step = step_frac * min_a h^l_a of the leaf level */
     float t_min;                        /* early termination once T < t_min; 0 disables */
     int32_t uniform_step;               /* 1: every leaf uses the finest level's step */
-    int32_t lighting;                   /* 1: gradient shading */
+    int32_t lighting;                   /* 0: none; 1: gradient shading (light = direction);
+                                           2: point light at position `light`: shade =
+                                           k_a + k_d T_L(x), T_L the transmittance of a secondary
+                                           ray from the sample to the light inside B (the paper's
+                                           global-illumination example, Section 6); forward only,
+                                           trilinear, no level of detail */
     float light[3];                     /* light direction (need not be normalised) */
     float k_a, k_d, eps_g;              /* shade = k_a + k_d |g.l| / sqrt(|g|^2 + eps_g^2) */
     double clip_lo[3], clip_hi[3];      /* world clip box intersected with B */

@@ -114,7 +114,7 @@ def make_params(p: dict, f32: bool = True) -> Params:
     q.clip_lo[:] = [float(x) for x in p["clip_lo"]]
     q.clip_hi[:] = [float(x) for x in p["clip_hi"]]
     q.uniform_step = int(bool(p["uniform_step"]))
-    q.lighting = int(bool(p["lighting"]))
+    q.lighting = int(p["lighting"])
     q.interp = int(p.get("interp", 0))
     q.lod = _f32(p.get("lod", 0.0))
     return q

@@ -582,6 +582,62 @@ static void shade_sample(Orc *O, const orc_params *P, const double lhat[3], int 
     s->shade = P->k_a + (den > 0.0 ? P->k_d * fabs(dot) / den : 0.0);
 }
 
+/* Transmittance from x to a point light at pl (lighting = 2, the secondary rays of the paper's
+ * global-illumination example, Section 6): the segment from x to the light, clipped to B, is
+ * cut into leaf segments and sampled with the primary rule (midpoints, step proportional to the
+ * leaf level's cell size); T_L = exp(-sum sigma_j delta_j). */
+static double light_transmittance(Orc *O, const orc_params *P, const double *lut, const double x[3],
+                                  const double pl[3]) {
+    double v[3], dist2 = 0.0;
+    for (int a = 0; a < 3; a++) { v[a] = pl[a] - x[a]; }
+    dist2 = v[0] * v[0] + v[1] * v[1];
+    dist2 = dist2 + v[2] * v[2];
+    double dist = sqrt(dist2);
+    if (!(dist > 0.0)) return 1.0;
+    double d[3];
+    for (int a = 0; a < 3; a++) d[a] = v[a] / dist;
+    /* clip [0, dist] to B */
+    double lo_t = 0.0, hi_t = dist;
+    for (int a = 0; a < 3; a++) {
+        double lo = O->Bw_lo[a], hi = O->Bw_hi[a];
+        if (d[a] == 0.0) { if (!(x[a] >= lo && x[a] < hi)) return 1.0; continue; }
+        double inv = 1.0 / d[a];
+        double ta = (lo - x[a]) * inv, tb = (hi - x[a]) * inv;
+        double tn = ta < tb ? ta : tb, tf = ta < tb ? tb : ta;
+        if (tn > lo_t) lo_t = tn;
+        if (tf < hi_t) hi_t = tf;
+    }
+    if (!(hi_t > lo_t)) return 1.0;
+    int cap = 64, flag = 0;
+    cand_t *buf = (cand_t *)malloc(sizeof(cand_t) * cap);
+    int n = segments(O, x, d, lo_t, hi_t, buf, cap, &flag);
+    while (flag & 2) { cap *= 2; buf = (cand_t *)realloc(buf, sizeof(cand_t) * cap); flag = 0; n = segments(O, x, d, lo_t, hi_t, buf, cap, &flag); }
+    double tau = 0.0, ta = lo_t;
+    for (int k = 0; k < n; k++) {
+        double tb = buf[k].tx;
+        const int64_t *L = &O->leaf[8 * buf[k].leaf];
+        int p = (int)L[6], lev = (int)L[7];
+        if (p >= 0) {
+            int slev = P->uniform_step ? O->lmax : lev;
+            double step = P->step_frac * O->hs[slev];
+            double nn = ceil((tb - ta) / step - 0x1p-20);
+            int64_t ns = nn < 1.0 ? 1 : (int64_t)nn;
+            double delta = (tb - ta) / (double)ns;
+            for (int64_t j = 0; j < ns; j++) {
+                double t = ta + ((double)j + 0.5) * delta;
+                double y[3];
+                for (int a = 0; a < 3; a++) y[a] = x[a] + t * d[a];
+                sample_t sm;
+                classify(lut, value_in(O, p, y, P->interp), P, &sm);
+                tau += sm.sigma * delta;
+            }
+        }
+        ta = tb;
+    }
+    free(buf);
+    return exp(-tau);
+}
+
 /* Walks one ray. Fills rgba; if samples != NULL, appends every evaluated sample to it. */
 typedef struct { sample_t *v; int64_t n, cap; } svec;
 
@@ -688,8 +744,12 @@ static int walk_ray(Orc *O, const orc_camera *cam, const orc_params *P, const do
                 s.delta = delta;
                 s.alpha = 1.0 - exp(-s.sigma * delta);
                 s.T = T;
-                if (P->lighting) shade_sample(O, P, lhat, lev, F0, x, lodbox, p, &s);
-                else { s.shade = 1.0; s.g[0] = s.g[1] = s.g[2] = 0; s.dot = 0; s.den = 0; }
+                if (P->lighting == 2) {
+                    s.g[0] = s.g[1] = s.g[2] = 0; s.dot = 0; s.den = 0;
+                    s.shade = P->k_a + P->k_d * light_transmittance(O, P, lut, x, P->light);
+                } else if (P->lighting) {
+                    shade_sample(O, P, lhat, lev, F0, x, lodbox, p, &s);
+                } else { s.shade = 1.0; s.g[0] = s.g[1] = s.g[2] = 0; s.dot = 0; s.den = 0; }
                 for (int ch = 0; ch < 3; ch++) C[ch] += T * s.alpha * s.shade * s.rgb[ch];
                 T = T * (1.0 - s.alpha);
                 (*nsamp)++;

@@ -207,7 +207,7 @@ def make_params(p: dict, d_lut) -> L.amr_render_params:
     q.d_lut = _vp(d_lut).value
     q.v_lo, q.v_hi, q.step_frac, q.t_min = p["v_lo"], p["v_hi"], p["step_frac"], p["t_min"]
     q.uniform_step = int(bool(p["uniform_step"]))
-    q.lighting = int(bool(p["lighting"]))
+    q.lighting = int(p["lighting"])
     q.light[:] = [float(x) for x in p["light"]]
     q.k_a, q.k_d, q.eps_g = p["k_a"], p["k_d"], p["eps_g"]
     q.clip_lo[:] = [float(x) for x in p["clip_lo"]]

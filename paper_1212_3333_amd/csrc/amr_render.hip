@@ -323,6 +323,11 @@ int amr_render(const amr_scene *S, const amr_camera *cams, int32_t ncams, const 
             return AMR_ECAPACITY;
         }
     }
+    if (P->lighting == 2 && (P->persistent || P->d_mlp || P->d_seglog || P->d_ckpt || P->interp != 0 || P->lod > 0.f)) {
+        set_error("point-light lighting (lighting = 2) is rendered by its own forward kernel only, with trilinear "
+                  "sampling and no level of detail (not persistent, learned, logging or checkpointed)");
+        return AMR_EINVAL;
+    }
     if (P->interp == 1 && (P->persistent || P->d_mlp || P->d_seglog || P->d_ckpt)) {
         set_error("nearest-cell sampling (interp = 1) is rendered by the plain forward kernel only "
                   "(not persistent, learned, logging or checkpointed)");
@@ -359,6 +364,12 @@ int amr_render(const amr_scene *S, const amr_camera *cams, int32_t ncams, const 
         }
         const int grid = 8 * ((A.sgrid * A.sgrid + 7) / 8) * 16;
         const bool rec = A.trace || A.trace_n || A.nsamp || A.stats || A.touch || A.ckpt;
+        if (A.lighting == 2) {
+            rc = launch_shadow(A, rec, stream);
+            if (rc) return rc;
+            pix_off += (int64_t)cams[c].width * cams[c].height;
+            continue;
+        }
         if (A.nearest) {
             if (A.lighting) {
                 if (rec) hipLaunchKernelGGL((render_fwd<true, true, true>), dim3(grid), dim3(64), 0, s, A);
@@ -390,6 +401,7 @@ int amr_render_backward(const amr_scene *S, const amr_camera *cams, int32_t ncam
     }
     if (!P->d_ckpt) { set_error("the adjoint needs the forward's checkpoints (params.d_ckpt)"); return AMR_EINVAL; }
     if (P->interp != 0) { set_error("the adjoint is defined for trilinear sampling (interp = 0)"); return AMR_EINVAL; }
+    if (P->lighting == 2) { set_error("the adjoint is defined for lighting 0 and 1"); return AMR_EINVAL; }
     int64_t total = 0;
     for (int c = 0; c < ncams; c++) total += (int64_t)cams[c].width * cams[c].height;
     if (P->ckpt_max < 2 || P->ckpt_bytes < amr_ckpt_bytes(total, P->ckpt_max)) {

@@ -33,6 +33,7 @@ struct RenderArgs {
     int32_t lod_on, nleaves;         // level of detail enabled; real leaves (kind-(a) records follow)
     double lod;                      // pixels
     double lod_pix;                  // pixel footprint per unit distance (perspective) or per pixel
+    double plight[3];                // lighting = 2: point-light position
     const float4 *lut;
     double box_lo[3], box_hi[3];     // B (closed, for gradient taps)
     double clip_lo[3], clip_hi[3];   // B ∩ clip box
@@ -875,7 +876,9 @@ inline int fill_args(const amr_scene *S, const amr_camera *C, const amr_render_p
     A->k_d = P->k_d;
     A->eps2 = P->eps_g * P->eps_g;
     A->uniform_step = P->uniform_step;
+    if (P->lighting < 0 || P->lighting > 2) { set_error("lighting must be 0, 1 (gradient) or 2 (point light)"); return AMR_EINVAL; }
     A->lighting = P->lighting;
+    for (int a = 0; a < 3; a++) A->plight[a] = (double)P->light[a];
     A->micro = S->brick_layout;
     A->tiles_x = (C->width + 15) / 16;
     A->tiles_y = (C->height + 15) / 16;
@@ -890,6 +893,9 @@ inline int fill_args(const amr_scene *S, const amr_camera *C, const amr_render_p
     A->ckpt_max = P->ckpt_max;
     return AMR_OK;
 }
+
+// Point-light secondary-ray launch for one camera (amr_shadow.hip).
+int launch_shadow(const RenderArgs &A, bool rec, void *stream);
 
 // Learned-proposal / segment-logging launch for one camera (amr_learned.hip).
 int launch_learned(const RenderArgs &A, const amr_render_params *P, int lmax, void *stream, bool first_camera);

@@ -330,3 +330,43 @@ def test_lod_cosmology_sampled(gpu, cosmology_scene):
     assert err <= TOL
     assert sl < sf
 
+
+@pytest.mark.parametrize("light", [(0.5, 0.45, 0.55), (1.6, -0.3, 0.4)])
+@pytest.mark.parametrize("case", ["small0", "small1", "rand0", "rand1"])
+def test_point_light_vs_oracle(gpu, case, light):
+    """Point-light secondary rays (lighting = 2): every primary sample shaded by the
+    transmittance of a secondary ray to the light; images against the oracle, traces bit-exact."""
+    amr = gpu
+    if case.startswith("small"):
+        h, lut, cams, prm = workloads.small_nested(0)
+        cam = workloads.small_nested_cameras(48, 48)[int(case[-1])]
+        prm = dict(prm, lighting=2, light=light, k_a=0.2, k_d=0.8)
+    else:
+        seed = int(case[-1])
+        h = workloads.random_tiny(seed, multi_root=(seed == 1))
+        lut = workloads.lut_bumps(np.random.default_rng(seed), sigma_scale=12.0)
+        vmax = float(max(p.cells.max() for p in h.patches))
+        prm = workloads.default_params(v_hi=vmax, lighting=2, light=light, k_a=0.2, k_d=0.8)
+        cam = workloads.perspective_orbit(37, 23, 0.3 + seed, 0.2 * seed - 0.4, radius=1.8)
+    tree, scene = _setup(amr, h)
+    gout = _gpu_render(amr, scene, cam, lut, prm, trace_cap=128)
+    ores = oracle.Oracle(h).render(cam, prm, lut, trace_cap=128)
+    err = np.abs(gout["rgba"].cpu().numpy().reshape(-1, 4) - ores["rgba"]).max()
+    print("point light %s %s: max|err| = %.3g" % (case, light, err))
+    assert err <= TOL
+    _compare_traces(amr, gout, ores)
+
+
+def test_point_light_rejected_elsewhere(gpu):
+    import torch
+    amr = gpu
+    h, lut, cams, prm = workloads.small_nested(0)
+    tree, scene = _setup(amr, h)
+    lut_t = torch.from_numpy(lut).cuda()
+    with pytest.raises(amr.AMRError, match="point-light"):
+        amr.render_checkpointed(scene, cams[0], lut_t, dict(prm, lighting=2))
+    with pytest.raises(amr.AMRError, match="point-light"):
+        amr.render(scene, cams[0], lut_t, dict(prm, lighting=2, lod=2.0))
+    with pytest.raises(amr.AMRError, match="lighting"):
+        amr.render(scene, cams[0], lut_t, dict(prm, lighting=3))
+

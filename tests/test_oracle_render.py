@@ -494,3 +494,47 @@ def test_lod_segments_structure(seed):
                 assert hit.sum() == 1
     assert cut > 0
 
+
+@pytest.mark.parametrize("light", [(0.5, 0.45, 0.55), (1.7, -0.4, 0.3)])
+@pytest.mark.parametrize("cam_name", ["ortho_z", "persp"])
+def test_point_light_constant_field(cam_name, light):
+    """Point-light secondary rays (lighting = 2) on one subgrid with a constant field: every
+    sample's light transmittance is exp(-sigma |[x, p_L] in B|), the length taken from a
+    face-by-face chord of the box; the primary composite is then a running product over the
+    evenly spaced primary samples."""
+    h = workloads.single_level((12, 10, 8)).with_field(workloads.constant_field(0.5))
+    sig = 3.0
+    lut = workloads.lut_constant(rgb=(0.8, 0.5, 0.2), sigma=sig)
+    prm = workloads.default_params(v_lo=0.0, v_hi=1.0, t_min=0.0, lighting=2, light=light, k_a=0.25, k_d=0.75)
+    cam = CAMS[cam_name]
+    O = Oracle(h)
+    res = O.render(cam, prm, lut, trace_cap=4)
+    hgrid = h.h0[0]
+    Blo, Bhi = h.origin, h.origin + hgrid * np.array([12, 10, 8])
+    pl = np.array([_f32(v) for v in light])
+    rgb = np.array([_f32(0.8), _f32(0.5), _f32(0.2)])     # the LUT holds fp32 values
+    checked = 0
+    for q in range(len(res["pixels"])):
+        if res["trace_n"][q] == 0:
+            continue
+        i, j = res["pixels"][q]
+        o, d = oracle.ray(cam, i, j)
+        seg = res["trace"][q, 0]
+        n = seg["n"]
+        delta = (seg["tb"] - seg["ta"]) / n
+        alpha = 1 - math.exp(-sig * delta)
+        C = np.zeros(3); T = 1.0
+        for k in range(n):
+            x = o + (seg["ta"] + (k + 0.5) * delta) * d
+            v = pl - x
+            dist = np.linalg.norm(v)
+            ch = _chord_faces(x, v / dist, Blo, Bhi)
+            L = 0.0 if ch is None else max(0.0, min(ch[1], dist) - max(ch[0], 0.0))
+            shade = 0.25 + 0.75 * math.exp(-sig * L)
+            C += T * alpha * shade * rgb
+            T *= 1 - alpha
+        assert np.all(np.abs(res["rgba"][q, :3] - C) < 1e-10), q
+        assert abs(res["rgba"][q, 3] - (1 - T)) < 1e-12
+        checked += 1
+    assert checked > 50
+
