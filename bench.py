@@ -192,7 +192,8 @@ def main():
     ap.add_argument("--no-touch", action="store_true", help="skip the compulsory-bytes measurement run")
     ap.add_argument("--unlit", action="store_true", help="time the unlit kernel instead")
     ap.add_argument("--copy-calib", action="store_true", help="also run a 1 GiB device copy (counter calibration)")
-    ap.add_argument("--brick-layout", type=int, default=1, help="pool layout: 0 linear bricks, 1 4^3 micro-bricks")
+    ap.add_argument("--brick-layout", type=int, default=0,
+                    help="pool layout: 0 linear bricks (row loads; faster lit), 1 4^3 micro-bricks")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-skip section")
     args = ap.parse_args()
     if args.gpus != 1:

@@ -117,8 +117,10 @@ void amr_tree_free(amr_tree *tree);
 typedef struct {
     int32_t host_dst;     /* 1: d_pool and d_meta are host pointers (plain memcpy, no HIP) */
     int32_t nthreads;     /* host threads for the ghost fill; 0 = hardware concurrency */
-    int32_t brick_layout; /* 0: each padded brick x-fastest; 1: padded brick stored as 4x4x4-cell
-                             micro-bricks (256 bytes each, x-fastest inside and between them) */
+    int32_t brick_layout; /* 0: each padded brick x-fastest (the pool keeps 64 spare floats
+                             before the first and after the last brick, so the lit kernel reads
+                             whole rows); 1: padded brick stored as 4x4x4-cell micro-bricks
+                             (256 bytes each, x-fastest inside and between them) */
     int32_t reserved_[5];
 } amr_pack_opts;
 

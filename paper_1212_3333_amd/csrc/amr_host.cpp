@@ -655,7 +655,7 @@ int amr_pack_pool(const amr_tree *T, const amr_patch *patches, int32_t npatches,
     if (layout != 0 && layout != 1) { set_error("brick_layout must be 0 or 1"); return AMR_EINVAL; }
     // pool layout: 256-byte aligned padded bricks (linear, or 4^3 micro-bricks)
     std::vector<int64_t> off(np);
-    int64_t nfl = 0;
+    int64_t nfl = 64;   // leading pad: row loads of the linear layout may start one float early
     for (int p = 0; p < np; p++) {
         const int64_t *n = patches[p].dims;
         if (patches[p].level != T->plevel[p]) { set_error("patch %d differs from the tree's", p); return AMR_EINVAL; }
@@ -677,7 +677,7 @@ int amr_pack_pool(const amr_tree *T, const amr_patch *patches, int32_t npatches,
     const int64_t o_faces = align_up(o_patch + np * (int64_t)sizeof(DPatch), 256);
     const int64_t o_fxf = align_up(o_faces + nl * 6 * (int64_t)sizeof(int32_t), 256);
     const int64_t mbytes = align_up(o_fxf + nl * 6 * (int64_t)sizeof(DFaceXf), 256);
-    const int64_t pbytes = std::max<int64_t>(nfl * 4, 256);
+    const int64_t pbytes = std::max<int64_t>((nfl + 64) * 4, 256);   // trailing pad
     if (!d_pool && !d_meta) {
         *pool_bytes = pbytes;
         *meta_bytes = mbytes;

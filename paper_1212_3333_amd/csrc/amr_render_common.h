@@ -253,8 +253,16 @@ __device__ __forceinline__ float trilinear(const RenderArgs &A, const PatchView 
             atomicOr(&A.touch[e >> 5], 1u << (e & 31));
         }
     }
-    float v000 = b[0], v100 = b[dx], v010 = b[dy], v110 = b[dy + dx];
-    float v001 = b[dz], v101 = b[dz + dx], v011 = b[dz + dy], v111 = b[dz + dy + dx];
+    // linear layout: each x pair is one 8-byte row load (the packer pads the pool on both ends)
+    typedef float f2u __attribute__((ext_vector_type(2), aligned(4)));
+    float v000, v100, v010, v110, v001, v101, v011, v111;
+    if (!A.micro) {
+        const f2u r00 = *(const f2u *)b, r10 = *(const f2u *)(b + dy), r01 = *(const f2u *)(b + dz), r11 = *(const f2u *)(b + dz + dy);
+        v000 = r00.x; v100 = r00.y; v010 = r10.x; v110 = r10.y; v001 = r01.x; v101 = r01.y; v011 = r11.x; v111 = r11.y;
+    } else {
+        v000 = b[0]; v100 = b[dx]; v010 = b[dy]; v110 = b[dy + dx];
+        v001 = b[dz]; v101 = b[dz + dx]; v011 = b[dz + dy]; v111 = b[dz + dy + dx];
+    }
     float c00 = lerpf(v000, v100, fx), c10 = lerpf(v010, v110, fx);
     float c01 = lerpf(v001, v101, fx), c11 = lerpf(v011, v111, fx);
     float c0 = lerpf(c00, c10, fy), c1 = lerpf(c01, c11, fy);
@@ -297,6 +305,31 @@ __device__ __forceinline__ float trilinear_taps(const RenderArgs &A, const Patch
     const float *b = pv.brick;
     // c[x][y][z] for the core (indices 1, 2 on every axis) and the arms (0 or 3 on one axis)
     float core[2][2][2], ax[2][2][2], ay[2][2][2], az[2][2][2];
+    if (!A.micro) {
+        // linear layout: the four x cells of a core row are one 16-byte load and each arm row
+        // pair one 8-byte load (12 loads instead of 32).  A row load may touch the float before
+        // or after the brick row (the arms of a tap that leaves the brick, replaced later); the
+        // packer pads the pool by 64 floats on both ends so such reads stay in the allocation.
+        typedef float f4u __attribute__((ext_vector_type(4), aligned(4)));
+        typedef float f2u __attribute__((ext_vector_type(2), aligned(4)));
+        const float *row0 = b + ix;          // padded x index ix holds cell ix - 1
+        #pragma unroll
+        for (int v = 0; v < 2; v++)
+            #pragma unroll
+            for (int w = 0; w < 2; w++) {
+                const f4u r = *(const f4u *)(row0 + yo[1 + v] + zo[1 + w]);
+                ax[0][v][w] = r.x; core[0][v][w] = r.y; core[1][v][w] = r.z; ax[1][v][w] = r.w;
+            }
+        #pragma unroll
+        for (int u = 0; u < 2; u++)
+            #pragma unroll
+            for (int w = 0; w < 2; w++) {
+                const f2u ry = *(const f2u *)(row0 + 1 + yo[3 * u] + zo[1 + w]);
+                ay[u][0][w] = ry.x; ay[u][1][w] = ry.y;
+                const f2u rz = *(const f2u *)(row0 + 1 + yo[1 + w] + zo[3 * u]);
+                az[u][0][w] = rz.x; az[u][1][w] = rz.y;
+            }
+    } else
     #pragma unroll
     for (int u = 0; u < 2; u++)
         #pragma unroll

@@ -15,10 +15,10 @@ pytestmark = pytest.mark.gpu
 TOL = 1e-4
 
 
-def _setup(amr, h):
+def _setup(amr, h, layout=1):
     import torch
     tree = amr.build_tree(h)
-    scene = amr.pack(tree, h, device="cuda")
+    scene = amr.pack(tree, h, device="cuda", brick_layout=layout)
     torch.cuda.synchronize()
     return tree, scene
 
@@ -48,15 +48,16 @@ def _compare_traces(amr, gout, ores, nrays_expect=None):
     return int(ok.sum())
 
 
+@pytest.mark.parametrize("layout", [0, 1])
 @pytest.mark.parametrize("lit", [False, True])
 @pytest.mark.parametrize("uniform", [False, True])
 @pytest.mark.parametrize("cam_idx", [0, 1])
-def test_small_nested_full_image(gpu, cam_idx, uniform, lit):
+def test_small_nested_full_image(gpu, cam_idx, uniform, lit, layout):
     amr = gpu
     h, lut, cams, prm = workloads.small_nested(0)
     cam = cams[cam_idx]
     prm = dict(prm, uniform_step=uniform, lighting=lit)
-    tree, scene = _setup(amr, h)
+    tree, scene = _setup(amr, h, layout)
     gout = _gpu_render(amr, scene, cam, lut, prm, trace_cap=64, stats=True, nsamp=True)
     O = oracle.Oracle(h)
     ores = O.render(cam, prm, lut, trace_cap=64)
@@ -187,6 +188,30 @@ def cosmology_scene(gpu):
     h, lut, cam, prm = workloads.cosmology_view(0)
     tree, scene = _setup(amr, h)
     return h, lut, cam, prm, tree, scene
+
+
+def test_cosmology_linear_layout_sampled(gpu, cosmology_scene):
+    """The linear brick layout (row loads in the lit stencil) on the cosmology-like view, lit and
+    unlit: a pixel sample against the oracle, and the image within 1e-5 of the micro-brick one."""
+    import torch
+    amr = gpu
+    h, lut, cam, prm, tree, scene1 = cosmology_scene
+    scene0 = amr.pack(tree, h, device="cuda", brick_layout=0)
+    lut_t = torch.from_numpy(lut).cuda()
+    rng = np.random.default_rng(21)
+    pix = np.stack([rng.integers(0, cam["width"], 1500), rng.integers(0, cam["height"], 1500)], 1).astype(np.int32)
+    O = oracle.Oracle(h)
+    for lit in (True, False):
+        p = dict(prm, lighting=lit)
+        a = amr.render(scene0, cam, lut_t, p)["rgba"].clone()
+        b = amr.render(scene1, cam, lut_t, p)["rgba"]
+        torch.cuda.synchronize()
+        ref = O.render(cam, p, lut, pixels=pix)["rgba"]
+        err = np.abs(a.cpu().numpy()[pix[:, 1], pix[:, 0]] - ref).max()
+        print("linear layout lit=%d: max|err| vs oracle %.3g, vs micro-bricks %.3g" % (lit, err, (a - b).abs().max().item()))
+        assert err <= TOL
+        assert (a - b).abs().max().item() <= 1e-5
+    del scene0
 
 
 def _sample_pixels(W, H, seed):

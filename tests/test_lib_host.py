@@ -185,8 +185,9 @@ def test_pack_capacity_and_size_query():
     opts.host_dst = 1
     assert lib.amr_pack_pool(tree.ptr, tree._patches, len(h.patches), ctypes.byref(opts), None, ctypes.byref(pb),
                              None, ctypes.byref(mb), None, None) == 0
+    # padded bricks rounded to 64 floats, plus 64 spare floats before the first and after the last
     expect_pool = sum(((int(p.dims[0]) + 2) * (int(p.dims[1]) + 2) * (int(p.dims[2]) + 2) + 63) // 64 * 64 * 4
-                      for p in h.patches)
+                      for p in h.patches) + 2 * 64 * 4
     opts.brick_layout = 0
     assert pb.value == expect_pool
     pool = np.zeros(pb.value - 4, dtype=np.uint8)
