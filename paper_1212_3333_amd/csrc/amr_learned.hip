@@ -112,11 +112,12 @@ __device__ __forceinline__ void infer_tile(LearnLds &s, int wave, int rt) {
 enum { kModePlain = 0, kModeSkip = 1, kModeCoarse = 2 };
 constexpr int kNetMinSamples = 8;
 
-template <bool LIT>
-__global__ __launch_bounds__(256) void render_learned(RenderArgs A, LearnArgs G) {
+// NET: the network decides (G.mlp set); LOG: segments are logged for training (G.seglog set).
+template <bool LIT, bool NET, bool LOG>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(LIT ? 2 : 4))) void render_learned(RenderArgs A, LearnArgs G) {
     __shared__ LearnLds s;
     s.lut[threadIdx.x] = A.lut[threadIdx.x];
-    if (G.mlp) {
+    if (NET) {
         const MlpLds *m = G.mlp;
         for (int i = threadIdx.x; i < 64 * 16; i += blockDim.x) { s.w1t[i] = m->w1t[i]; s.w3t[i] = m->w3t[i]; }
         for (int i = threadIdx.x; i < 64 * 64; i += blockDim.x) s.w2t[i] = m->w2t[i];
@@ -224,7 +225,7 @@ __global__ __launch_bounds__(256) void render_learned(RenderArgs A, LearnArgs G)
         };
         // decide: skip by the analytic bound, else ask the network (wave-level MFMA)
         int mode = kModePlain;
-        if (G.mlp) {
+        if (NET) {
             const bool bound_skip = data && budget + T * a_bound_hi < G.tau_e;
             // the network is asked only where its answer can change the decision and skipping
             // pays for it: segments of at least kNetMinSamples samples whose bound did not
@@ -243,7 +244,7 @@ __global__ __launch_bounds__(256) void render_learned(RenderArgs A, LearnArgs G)
                 #pragma unroll
                 for (int j = 0; j < 16; j++) s.feat[wave][lane * 16 + j] = (_Float16)(j < kIn ? feat[j < kIn ? j : 0] : 0.f);
                 __builtin_amdgcn_wave_barrier();
-                #pragma unroll
+                #pragma unroll 1
                 for (int rt = 0; rt < 4; rt++)
                     if ((need >> (16 * rt)) & 0xffffull) infer_tile(s, wave, rt);
                 if (undecided) {
@@ -289,7 +290,7 @@ __global__ __launch_bounds__(256) void render_learned(RenderArgs A, LearnArgs G)
             c_skip++;
         }
         // training log: every plainly sampled data segment
-        if (G.seglog) {
+        if (LOG) {
             const bool want = data && mode == kModePlain;
             const unsigned long long mask = __ballot(want);
             if (mask) {
@@ -348,8 +349,16 @@ int launch_learned(const RenderArgs &A, const amr_render_params *P, int lmax, vo
     hipStream_t s = (hipStream_t)stream;
     if (G.seglog && first_camera) hipLaunchKernelGGL(seglog_reset, dim3(1), dim3(64), 0, s, G.seglog);
     const int grid = 8 * ((A.sgrid * A.sgrid + 7) / 8) * 4;
-    if (A.lighting) hipLaunchKernelGGL(render_learned<true>, dim3(grid), dim3(256), 0, s, A, G);
-    else hipLaunchKernelGGL(render_learned<false>, dim3(grid), dim3(256), 0, s, A, G);
+    const bool net = G.mlp != nullptr, log = G.seglog != nullptr;
+    if (A.lighting) {
+        if (net && log) hipLaunchKernelGGL((render_learned<true, true, true>), dim3(grid), dim3(256), 0, s, A, G);
+        else if (net) hipLaunchKernelGGL((render_learned<true, true, false>), dim3(grid), dim3(256), 0, s, A, G);
+        else hipLaunchKernelGGL((render_learned<true, false, true>), dim3(grid), dim3(256), 0, s, A, G);
+    } else {
+        if (net && log) hipLaunchKernelGGL((render_learned<false, true, true>), dim3(grid), dim3(256), 0, s, A, G);
+        else if (net) hipLaunchKernelGGL((render_learned<false, true, false>), dim3(grid), dim3(256), 0, s, A, G);
+        else hipLaunchKernelGGL((render_learned<false, false, true>), dim3(grid), dim3(256), 0, s, A, G);
+    }
     return check_hip(hipGetLastError(), "render_learned launch");
 }
 
