@@ -140,16 +140,15 @@ __device__ __forceinline__ bool setup_ray(const RenderArgs &A, int i, int j, Ray
     return true;
 }
 
-// kD-restart: descend from the root for the ray interval [tmin, tmax]; returns the leaf id
-// and shrinks tmax to the leaf's exit.  Returns -1 if the walk exceeds the tree depth.
-__device__ __forceinline__ int descend(const RenderArgs &A, const Ray &R, double tmin, double &tmax) {
+template <bool LOD>
+__device__ __forceinline__ int descend_walk(const RenderArgs &A, const Ray &R, double tmin, double &tmax) {
 #pragma clang fp contract(off)
     uint32_t ni = 0;
     for (int it = 0; it <= A.depth; it++) {
         DNode n = A.nodes[ni];
         uint32_t axis = n.meta & 3u;
         if (axis == kLeafAxis) return (int)n.child;
-        if (A.lod_on && (n.meta >> 8)) {
+        if (LOD && (n.meta >> 8)) {
             // a kind-(a) node: stop here when the cells of its coarse patch project to fewer than
             // lod pixels at the segment start; the segment is then [tmin, tmax] across the node
             const int vl = A.nleaves + (int)(n.meta >> 8) - 1;
@@ -173,6 +172,12 @@ __device__ __forceinline__ int descend(const RenderArgs &A, const Ray &R, double
         else { ni = nearc; tmax = ts; }
     }
     return -1;
+}
+
+// kD-restart: descend from the root for the ray interval [tmin, tmax]; returns the leaf id
+// and shrinks tmax to the leaf's exit.  Returns -1 if the walk exceeds the tree depth.
+__device__ __forceinline__ int descend(const RenderArgs &A, const Ray &R, double tmin, double &tmax) {
+    return A.lod_on ? descend_walk<true>(A, R, tmin, tmax) : descend_walk<false>(A, R, tmin, tmax);
 }
 
 // Leaf holding point x (half-open comparisons against the split planes), descending from
