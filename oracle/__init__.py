@@ -83,6 +83,9 @@ def _load():
                                        _P, _P, _P, ctypes.c_int, _P, _P]
             lib.orc_grad.argtypes = [_P, ctypes.POINTER(Camera), ctypes.POINTER(Params), _P, ctypes.c_int64, _P,
                                      _P, _P, _P]
+            lib.orc_set_vertex.argtypes = [_P]
+            lib.orc_vertex_value.restype = ctypes.c_double
+            lib.orc_vertex_value.argtypes = [_P, ctypes.c_int, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64]
             lib.orc_num_threads.restype = ctypes.c_int
             _lib = lib
     return _lib
@@ -163,6 +166,11 @@ class Oracle:
         self.h = h
         self.tree = tree if tree is not None else kdbuild.build(finest_boxes(h), h.nlevels)
         np_ = len(h.patches)
+        self.vertex = getattr(h, "centering", "cell") == "vertex"
+        for p in h.patches:
+            want = tuple(int(d) + (1 if self.vertex else 0) for d in p.dims[::-1])
+            if tuple(np.shape(p.cells)) != want:
+                raise ValueError("patch samples have shape %s, expected %s" % (np.shape(p.cells), want))
         self._pmeta = np.zeros((np_, 7), dtype=np.int64)
         offs = np.zeros(np_, dtype=np.int64)
         total = 0
@@ -184,6 +192,8 @@ class Oracle:
                                           len(self._leaves), _ptr(self._leaves))
         self._anodes = lod_nodes(self.tree, h)
         self.lib.orc_set_lod_nodes(self.handle, len(self._anodes), _ptr(self._anodes))
+        if self.vertex:
+            self.lib.orc_set_vertex(self.handle)
 
     def __del__(self):
         if getattr(self, "handle", None):
@@ -196,11 +206,29 @@ class Oracle:
         return self.lib.orc_locate(self.handle, _ptr(x), int(brute))
 
     def field(self, x, interp: int = 0):
-        """F(x), trilinear (interp 0) or nearest cell (interp 1); None where no patch holds x."""
+        """F(x), trilinear (interp 0) or nearest cell (interp 1, cell-centred data only); None
+        where no patch holds x."""
+        self._check_interp(interp)
         x = np.ascontiguousarray(x, dtype=np.float64)
         ok = ctypes.c_int(0)
         v = self.lib.orc_field_mode(self.handle, _ptr(x), int(interp), ctypes.byref(ok))
         return v if ok.value else None
+
+    def _check_interp(self, interp):
+        if self.vertex and int(interp) != 0:
+            raise ValueError("nearest-cell sampling is defined for cell-centred data only")
+
+    def vertex_values(self, p) -> np.ndarray:
+        """Vertex samples of patch p after the dangling-node fix, shape (nz+1, ny+1, nx+1)."""
+        if not self.vertex:
+            raise ValueError("cell-centred hierarchy")
+        nx, ny, nz = (int(v) for v in self.h.patches[p].dims)
+        out = np.empty((nz + 1, ny + 1, nx + 1))
+        for k in range(nz + 1):
+            for j in range(ny + 1):
+                for i in range(nx + 1):
+                    out[k, j, i] = self.lib.orc_vertex_value(self.handle, int(p), i, j, k)
+        return out
 
     def patch_value(self, p, i, j, k) -> float:
         return self.lib.orc_patch_value(self.handle, int(p), int(i), int(j), int(k))
@@ -226,6 +254,7 @@ class Oracle:
     def render(self, cam, params, lut, pixels=None, trace_cap: int = 0, f32_params: bool = True):
         """Returns dict(rgba=[npix,4], nsamp=[npix], flags=[npix], trace=[npix, cap] SEG_DTYPE,
         trace_n=[npix]); full image order is row-major (row j, column i) when pixels is None."""
+        self._check_interp(params.get("interp", 0))
         pix = self._pixels(cam, pixels)
         n = len(pix)
         rgba = np.zeros((n, 4)); ns = np.zeros(n, dtype=np.int64); flags = np.zeros(n, dtype=np.int32)

@@ -12,6 +12,8 @@
  *     size, colour/opacity accumulation, one write per pixel           (Section 4 outline, 5.3)
  *   - cell-centred data; interpolation across patch interfaces needs a
  *     shared layer of samples at brick boundaries                      (Section 5 intro)
+ *   - vertex-centred data: trilinear interpolation of vertex samples, the
+ *     samples at dangling nodes replaced by the coarse interpolant       (Section 4.2)
  *   - gradient lighting with gradients taken on the fly, also across
  *     blocks of different subgrids                                      (Section 5, Section 6)
  *   - emission-absorption model                                          (Section 6)
@@ -82,6 +84,8 @@ typedef struct {
     int na;              /* kind-(a) nodes, in the tree's pre-order */
     int64_t *anode;      /* [na][9] lo3 hi3 (finest units), cover patch, cover level, depth */
     double *aw;          /* [na][6] world planes */
+    int vertex;          /* 1: vertex-centred data, (n+1)^3 samples per patch */
+    double **vfix;       /* vertex mode: per patch, the samples after the dangling-node fix */
 } Orc;
 
 static int64_t ipow(int64_t b, int e) { int64_t r = 1; while (e-- > 0) r *= b; return r; }
@@ -215,6 +219,7 @@ void orc_destroy(Orc *O) {
     free(O->hl); free(O->hs); free(O->rpow); free(O->leaf); free(O->lw);
     free(O->bin_start); free(O->bin_list);
     free(O->anode); free(O->aw);
+    if (O->vfix) { for (int p = 0; p < O->np; p++) free(O->vfix[p]); free(O->vfix); }
     free(O);
 }
 
@@ -349,6 +354,116 @@ static void ensure_ghosts(Orc *O, int p) {
     omp_unset_lock(&O->locks[p]);
 }
 
+/* ------------------------------------------------------------------------------------ */
+/* Vertex-centred data (Section 4.2): the samples sit on the grid vertices, a patch of n   */
+/* cells holds n+1 per axis, the field is their trilinear interpolant, and samples on a    */
+/* patch face that abuts coarser data (dangling nodes) are replaced by the interpolated    */
+/* value of the abutting coarse patch, so the field is continuous across the interface.   */
+/* ------------------------------------------------------------------------------------ */
+
+static double vsample(const Orc *O, int p, int64_t i, int64_t j, int64_t k) {
+    const int64_t *n = &O->pdims[3 * p];
+    return O->vfix[p][i + (n[0] + 1) * (j + (n[1] + 1) * k)];
+}
+
+/* Trilinear value of patch p's (fixed) vertex samples at vertex index position i0 + f. */
+static double vtrilin(const Orc *O, int p, const int64_t i0[3], const double f[3]) {
+    double v[8];
+    for (int c = 0; c < 8; c++)
+        v[c] = vsample(O, p, i0[0] + (c & 1), i0[1] + ((c >> 1) & 1), i0[2] + ((c >> 2) & 1));
+    double c00 = lerp(v[0], v[1], f[0]), c10 = lerp(v[2], v[3], f[0]);
+    double c01 = lerp(v[4], v[5], f[0]), c11 = lerp(v[6], v[7], f[0]);
+    double c0 = lerp(c00, c10, f[1]), c1 = lerp(c01, c11, f[1]);
+    return lerp(c0, c1, f[2]);
+}
+
+/* Value of patch p's vertex data at the point with finest-level coordinates G (a point of
+   p's closed box): level-p vertex position (G - lo) / S, the base index kept in [0, n-1]. */
+static double vertex_at_G(const Orc *O, int p, const int64_t G[3]) {
+    int64_t S = O->rpow[O->lmax - O->plev[p]];
+    int64_t i0[3]; double f[3];
+    for (int a = 0; a < 3; a++) {
+        int64_t num = G[a] - O->gplo[3 * p + a];
+        int64_t i = floordiv(num, S), n = O->pdims[3 * p + a];
+        if (i > n - 1) i = n - 1;
+        if (i < 0) i = 0;
+        i0[a] = i;
+        f[a] = (double)(num - i * S) / (double)S;
+    }
+    return vtrilin(O, p, i0, f);
+}
+
+/* Switches the oracle to vertex-centred data and applies the dangling-node fix.  For every
+ * vertex on the boundary of a level-l patch, the eight finest-level cells around it that lie
+ * in B are each owned by the finest patch holding them; if the coarsest such owner is coarser
+ * than l, the sample becomes that owner's interpolated value at the vertex (the first owner of
+ * that level in the octant order, bit a of the octant number set for the + side of axis a).
+ * Levels are fixed coarsest first, so coarse values are final before finer patches read them. */
+void orc_set_vertex(Orc *O) {
+    O->vertex = 1;
+    O->vfix = (double **)calloc(O->np, sizeof(double *));
+    for (int l = 0; l <= O->lmax; l++) {
+#pragma omp parallel for schedule(dynamic)
+        for (int p = 0; p < O->np; p++) {
+            if (O->plev[p] != l) continue;
+            const int64_t *n = &O->pdims[3 * p];
+            const int64_t nx = n[0] + 1, ny = n[1] + 1, nz = n[2] + 1;
+            const int64_t S = O->rpow[O->lmax - l];
+            double *buf = (double *)malloc(sizeof(double) * nx * ny * nz);
+            for (int64_t k = 0; k < nz; k++)
+                for (int64_t j = 0; j < ny; j++)
+                    for (int64_t i = 0; i < nx; i++) {
+                        const int64_t idx = i + nx * (j + ny * k);
+                        buf[idx] = (double)O->cells[O->poff[p] + idx];
+                        const int on_face = i == 0 || j == 0 || k == 0 || i == n[0] || j == n[1] || k == n[2];
+                        if (!on_face) continue;
+                        const int64_t G[3] = {O->gplo[3 * p] + i * S, O->gplo[3 * p + 1] + j * S,
+                                              O->gplo[3 * p + 2] + k * S};
+                        int m = l, own = -1;
+                        for (int s = 0; s < 8; s++) {
+                            int64_t c2[3];
+                            int inB = 1;
+                            for (int a = 0; a < 3; a++) {
+                                c2[a] = 2 * G[a] + (((s >> a) & 1) ? 1 : -1);
+                                if (c2[a] < 2 * O->Blo[a] || c2[a] >= 2 * O->Bhi[a]) inB = 0;
+                            }
+                            if (!inB) continue;
+                            int q = -1;   /* finest patch holding the cell */
+                            for (int ci = 0; ci < O->ncand[p]; ci++) {
+                                int c = O->cand[p][ci];
+                                if (contains2(O, c, c2) && (q < 0 || O->plev[c] > O->plev[q])) q = c;
+                            }
+                            if (q >= 0 && O->plev[q] < m) { m = (int)O->plev[q]; own = q; }
+                        }
+                        if (own >= 0) buf[idx] = vertex_at_G(O, own, G);
+                    }
+            O->vfix[p] = buf;
+        }
+    }
+}
+
+/* Sample of patch p after the fix, at vertex index (i, j, k) (0 <= index <= n). */
+double orc_vertex_value(Orc *O, int p, int64_t i, int64_t j, int64_t k) { return vsample(O, p, i, j, k); }
+
+/* Trilinear value of patch p's vertex data at world point x: q = (x - lo) / h, the base index
+   kept in [0, n-1] (a point on the upper face uses the last cell with weight 1). */
+static double vertex_in(Orc *O, int p, const double x[3]) {
+    int l = (int)O->plev[p];
+    int64_t i0[3]; double f[3];
+    for (int a = 0; a < 3; a++) {
+        double lo = plane(O, a, O->gplo[3 * p + a]);
+        double q = (x[a] - lo) / O->hl[3 * l + a];
+        double fl = floor(q);
+        int64_t n = O->pdims[3 * p + a];
+        int64_t i = (int64_t)fl;
+        if (i > n - 1) i = n - 1;
+        if (i < 0) i = 0;
+        i0[a] = i;
+        f[a] = q - (double)i;
+    }
+    return vtrilin(O, p, i0, f);
+}
+
 /* Does patch q contain world point x?  Half-open boxes, except that B's upper faces
    count as inside. */
 static int contains_world(const Orc *O, int q, const double x[3]) {
@@ -418,6 +533,7 @@ static double nearest_in(Orc *O, int p, const double x[3]) {
 }
 
 static double value_in(Orc *O, int p, const double x[3], int interp) {
+    if (O->vertex) return vertex_in(O, p, x);
     return interp ? nearest_in(O, p, x) : field_in(O, p, x);
 }
 

@@ -42,6 +42,7 @@ class Hierarchy:
     refine: int
     nlevels: int
     patches: List[Patch]
+    centering: str = "cell"  # "cell": dims cells per patch; "vertex": dims+1 vertex samples per axis
 
     @property
     def lmax(self) -> int:
@@ -85,7 +86,23 @@ class Hierarchy:
         rng = np.random.default_rng(seed)
         perm = rng.permutation(len(self.patches))
         return Hierarchy(self.origin.copy(), self.h0.copy(), self.refine, self.nlevels,
-                         [self.patches[i] for i in perm])
+                         [self.patches[i] for i in perm], self.centering)
+
+    def vertex_positions(self, p: Patch):
+        """World coordinates of the grid vertices of patch p (x, y, z 1-D arrays, dims+1 each)."""
+        h = self.h0 / float(self.refine) ** p.level
+        return [self.origin[a] + (p.lo[a] + np.arange(p.dims[a] + 1)) * h[a] for a in range(3)]
+
+    def with_vertex_field(self, fn) -> "Hierarchy":
+        """Same boxes, vertex-centred: each patch holds fn(X, Y, Z) at its (dims+1)^3 grid
+        vertices (FP64 -> fp32).  Patches sharing a vertex hold the same sample there."""
+        ps = []
+        for p in self.patches:
+            x, y, z = self.vertex_positions(p)
+            Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
+            v = np.broadcast_to(np.asarray(fn(X, Y, Z), dtype=np.float64), X.shape)
+            ps.append(Patch(p.level, p.lo.copy(), p.dims.copy(), np.ascontiguousarray(v, dtype=np.float32)))
+        return Hierarchy(self.origin.copy(), self.h0.copy(), self.refine, self.nlevels, ps, "vertex")
 
 
 def _rng(workload: int, stream: str, seed: int = MASTER_SEED) -> np.random.Generator:
@@ -188,10 +205,11 @@ def lod_blocks(seed: int = 0, field=None) -> Hierarchy:
 
 
 def random_tiny(seed: int, max_patches: int = 6, nlevels: int = 3, refine: int | None = None,
-                root_cells: int = 8, multi_root: bool = False) -> Hierarchy:
+                root_cells: int = 8, multi_root: bool = False, root_aligned: bool = False) -> Hierarchy:
     """Small random hierarchies for builder/oracle pins: up to `max_patches` patches on
     `nlevels` levels, r in {2, 4}; patches need not be properly nested (a level-l patch may
-    span several level-(l-1) parents or stick out of them)."""
+    span several level-(l-1) parents or stick out of them).  With `root_aligned` every box is
+    a union of root cells (its faces lie on planes of every level)."""
     rng = np.random.default_rng(np.random.SeedSequence([MASTER_SEED, 101, seed]))
     r = int(refine if refine is not None else rng.choice([2, 4]))
     ps: List[Patch] = []
@@ -216,6 +234,11 @@ def random_tiny(seed: int, max_patches: int = 6, nlevels: int = 3, refine: int |
             tries += 1
             ext = np.minimum(rng.integers(1, max(2, ncell // 2) + 1, 3), bhi - blo)
             lo = np.array([rng.integers(blo[a], bhi[a] - ext[a] + 1) for a in range(3)])
+            if root_aligned:
+                g = r ** lev
+                lo = lo // g * g
+                ext = np.maximum(ext // g, 1) * g
+                ext = np.minimum(ext, bhi - lo)
             hi = lo + ext
             if all(_disjoint(lo, hi, b0, b1) for b0, b1 in boxes):
                 boxes.append((lo, hi))
