@@ -121,7 +121,22 @@ typedef struct {
                              before the first and after the last brick, so the lit kernel reads
                              whole rows); 1: padded brick stored as 4x4x4-cell micro-bricks
                              (256 bytes each, x-fastest inside and between them) */
-    int32_t reserved_[5];
+    int32_t centering;    /* 0: cell-centred data, `cells` holds dims[0]*dims[1]*dims[2] values;
+                             1: vertex-centred data (Section 4.2), `cells` holds the
+                             (dims[0]+1)(dims[1]+1)(dims[2]+1) samples at the grid vertices
+                             lo + i h, i = 0..dims, x fastest.  The field is their trilinear
+                             interpolant.  Samples on a patch face that abuts coarser data
+                             (dangling nodes) are replaced, at pack time and in FP64, by the
+                             value of the abutting coarse patch: for each vertex on a patch's
+                             boundary, the eight finest-level cells around it that lie in B are
+                             each owned by the finest patch holding them, and when the coarsest
+                             owner is coarser than the patch the sample becomes that owner's
+                             trilinear value at the vertex (the first such owner with octant
+                             bit a set for the + side of axis a).  Coarser levels are fixed
+                             first.  Same-level neighbours are expected to carry equal values at
+                             shared vertices.  The brick holds the n+1 samples per axis plus a
+                             one-sample shell replicating the nearest sample. */
+    int32_t reserved_[4];
 } amr_pack_opts;
 
 /* Device view of a packed scene.  Filled by amr_pack_pool; every pointer points into the
@@ -146,16 +161,17 @@ typedef struct {
                                    further; Section 4.1): records nleaves .. nleaves + nlod - 1 of
                                    `leaves` (and of the face tables) describe them in pre-order,
                                    with the covering coarse patch, for level-of-detail renders */
-    int32_t reserved_i_;
+    int32_t centering;          /* 0 cell-centred, 1 vertex-centred (amr_pack_opts) */
     double box_lo[3], box_hi[3];        /* B in world coordinates */
     double origin[3], h0[3], hfine[3];  /* hfine = h0 / refine^lmax */
     double step_fine;                   /* min_a h^lmax_a */
     float v_min, v_max;                 /* range of all cell values */
 } amr_scene;
 
-/* Packs every patch into one padded brick (one ghost layer, values defined as in the design
- * notes: same-level copy, edge replication outside B, coarse trilinear interpolant, nearest
- * interior cell) computed in FP64 and stored as fp32, and writes the device tree, leaf table
+/* Packs every patch into one padded brick, computed in FP64 and stored as fp32: cell-centred
+ * data gets one ghost layer (same-level copy, edge replication outside B, coarse trilinear
+ * interpolant, nearest interior cell); vertex-centred data holds its samples after the
+ * dangling-node fix described at amr_pack_opts.centering.  Writes the device tree, leaf table
  * and patch headers to d_meta.  Two-call protocol: with d_pool == NULL and d_meta == NULL it
  * only writes the required sizes to *pool_bytes and *meta_bytes.  Otherwise the buffers
  * must hold at least those sizes (AMR_ECAPACITY).  The copies are enqueued on `stream` and
@@ -237,7 +253,8 @@ typedef struct {
     int32_t interp;                     /* sampling of the cell-centred data: 0 trilinear with the
                                            ghost layer, 1 the value of the cell holding the point
                                            (nearest cell, as Section 5 samples cell data; plain
-                                           forward kernel only, AMR_EINVAL elsewhere) */
+                                           forward kernel only, AMR_EINVAL elsewhere and on
+                                           vertex-centred scenes) */
     float lod;                          /* level of detail (Sections 4.1 and 5.3): the kD-restart
                                            descent stops at a kind-(a) node when the cells of its
                                            covering coarse patch project to fewer than lod pixels

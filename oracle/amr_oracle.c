@@ -393,12 +393,15 @@ static double vertex_at_G(const Orc *O, int p, const int64_t G[3]) {
     return vtrilin(O, p, i0, f);
 }
 
+int orc_locate(Orc *O, const double *x, int brute);
+
 /* Switches the oracle to vertex-centred data and applies the dangling-node fix.  For every
  * vertex on the boundary of a level-l patch, the eight finest-level cells around it that lie
- * in B are each owned by the finest patch holding them; if the coarsest such owner is coarser
- * than l, the sample becomes that owner's interpolated value at the vertex (the first owner of
- * that level in the octant order, bit a of the octant number set for the + side of axis a).
- * Levels are fixed coarsest first, so coarse values are final before finer patches read them. */
+ * in B are each owned by the finest patch holding them (the patch located at the cell's
+ * centre); if the coarsest such owner is coarser than l, the sample becomes that owner's
+ * interpolated value at the vertex (the first owner of that level in the octant order, bit a
+ * of the octant number set for the + side of axis a).  Levels are fixed coarsest first, so
+ * coarse values are final before finer patches read them. */
 void orc_set_vertex(Orc *O) {
     O->vertex = 1;
     O->vfix = (double **)calloc(O->np, sizeof(double *));
@@ -421,18 +424,15 @@ void orc_set_vertex(Orc *O) {
                                               O->gplo[3 * p + 2] + k * S};
                         int m = l, own = -1;
                         for (int s = 0; s < 8; s++) {
-                            int64_t c2[3];
+                            double xc[3];   /* centre of the finest cell on side s of the vertex */
                             int inB = 1;
                             for (int a = 0; a < 3; a++) {
-                                c2[a] = 2 * G[a] + (((s >> a) & 1) ? 1 : -1);
-                                if (c2[a] < 2 * O->Blo[a] || c2[a] >= 2 * O->Bhi[a]) inB = 0;
+                                int64_t c = ((s >> a) & 1) ? G[a] : G[a] - 1;
+                                if (c < O->Blo[a] || c >= O->Bhi[a]) inB = 0;
+                                xc[a] = plane(O, a, c) + 0.5 * O->hf[a];
                             }
                             if (!inB) continue;
-                            int q = -1;   /* finest patch holding the cell */
-                            for (int ci = 0; ci < O->ncand[p]; ci++) {
-                                int c = O->cand[p][ci];
-                                if (contains2(O, c, c2) && (q < 0 || O->plev[c] > O->plev[q])) q = c;
-                            }
+                            int q = orc_locate(O, xc, 0);
                             if (q >= 0 && O->plev[q] < m) { m = (int)O->plev[q]; own = q; }
                         }
                         if (own >= 0) buf[idx] = vertex_at_G(O, own, G);

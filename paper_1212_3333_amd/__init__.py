@@ -109,10 +109,20 @@ class Scene:
     def __init__(self, tree: Tree, h, device="cuda", host: bool = False, nthreads: int = 0, brick_layout: int = 1):
         self.lib = load()
         self.tree = tree
+        centering = getattr(h, "centering", "cell")
+        if centering not in ("cell", "vertex"):
+            raise ValueError("centering must be 'cell' or 'vertex'")
+        extra = 1 if centering == "vertex" else 0
+        for i, p in enumerate(h.patches):
+            want = tuple(int(d) + extra for d in p.dims[::-1])
+            if tuple(np.shape(p.cells)) != want:
+                raise ValueError("patch %d holds samples of shape %s; %s-centred data needs %s"
+                                 % (i, np.shape(p.cells), centering, want))
         opts = L.amr_pack_opts()
         opts.host_dst = 1 if host else 0
         opts.nthreads = int(nthreads)
         opts.brick_layout = int(brick_layout)
+        opts.centering = extra
         pb, mb = ctypes.c_int64(0), ctypes.c_int64(0)
         check(self.lib.amr_pack_pool(tree.ptr, tree._patches, len(h.patches), ctypes.byref(opts), None,
                                      ctypes.byref(pb), None, ctypes.byref(mb), None, None), "amr_pack_pool(size)")
@@ -136,7 +146,8 @@ class Scene:
 
     # host-side views (host=True scenes): padded bricks and device records
     def brick(self, p: int) -> np.ndarray:
-        """Padded brick of patch p as a (nz+2, ny+2, nx+2) array, whatever the pool layout."""
+        """Padded brick of patch p as a (nz+2, ny+2, nx+2) array, whatever the pool layout
+        (vertex-centred data: (nz+3, ny+3, nx+3), the samples plus their one-sample shell)."""
         assert self.host
         hdr = self.patch_headers()[p]
         nx, ny, nz = (int(v) for v in hdr["n"])

@@ -47,7 +47,7 @@ class amr_leaf_host(ctypes.Structure):
 
 class amr_pack_opts(ctypes.Structure):
     _fields_ = [("host_dst", ctypes.c_int32), ("nthreads", ctypes.c_int32), ("brick_layout", ctypes.c_int32),
-                ("reserved_", ctypes.c_int32 * 5)]
+                ("centering", ctypes.c_int32), ("reserved_", ctypes.c_int32 * 4)]
 
 
 class amr_scene(ctypes.Structure):
@@ -56,7 +56,7 @@ class amr_scene(ctypes.Structure):
                 ("nnodes", ctypes.c_int32), ("nleaves", ctypes.c_int32), ("npatches", ctypes.c_int32),
                 ("nlevels", ctypes.c_int32), ("lmax", ctypes.c_int32), ("refine", ctypes.c_int32),
                 ("depth", ctypes.c_int32), ("brick_layout", ctypes.c_int32), ("nlod", ctypes.c_int32),
-                ("reserved_i_", ctypes.c_int32),
+                ("centering", ctypes.c_int32),
                 ("box_lo", c_double3), ("box_hi", c_double3), ("origin", c_double3), ("h0", c_double3),
                 ("hfine", c_double3), ("step_fine", ctypes.c_double), ("v_min", ctypes.c_float),
                 ("v_max", ctypes.c_float)]

@@ -365,12 +365,15 @@ struct Packer {
     const amr_tree *T;
     const amr_patch *P;
     int np;
-    std::vector<std::vector<double>> brick;   // FP64 padded bricks (n+2 per axis)
+    int vertex;                               // 1: vertex-centred samples, n+1 per axis
+    std::vector<std::vector<double>> brick;   // FP64 padded bricks (samples + 2 per axis)
     std::vector<std::vector<int>> nbr;        // patches of level <= own meeting the dilated box
 
+    // brick entry of sample (i, j, k); -1 and n (cells) or n + 1 (vertices) are the shell
     double &at(int p, int64_t i, int64_t j, int64_t k) {
         const int64_t *n = P[p].dims;
-        return brick[p][(size_t)((i + 1) + (n[0] + 2) * ((j + 1) + (n[1] + 2) * (k + 1)))];
+        const int64_t sx = n[0] + vertex + 2, sy = n[1] + vertex + 2;
+        return brick[p][(size_t)((i + 1) + sx * ((j + 1) + sy * (k + 1)))];
     }
 
     // Interior cell of patch q holding the level-l cell centre c2 (twice the finest coordinate).
@@ -494,15 +497,99 @@ struct Packer {
         for (auto &x : th) x.join();
     }
 
+    // Vertex-centred data (Section 4.2).  Patch owning the finest-level cell c: the kD leaf
+    // holding it (half-open split planes); -1 for a leaf without data.
+    int cell_owner(const int64_t *c) const {
+        int ni = 0;
+        while (T->nodes[ni].axis >= 0) {
+            const Node &n = T->nodes[ni];
+            ni = c[n.axis] < n.split ? n.low : n.high;
+        }
+        return T->nodes[ni].patch;
+    }
+
+    // Trilinear value of patch q's samples at the vertex with finest-level coordinates G, a
+    // point of q's closed box (base index kept in [0, n-1], so a point on the upper face takes
+    // the last cell with weight one).
+    double vertex_value(int q, const int64_t *G) {
+        const int64_t Sq = T->scale[T->plevel[q]];
+        int64_t i0[3];
+        double f[3];
+        for (int a = 0; a < 3; a++) {
+            const int64_t num = G[a] - T->pbox[q].lo[a];
+            i0[a] = std::min<int64_t>(std::max<int64_t>(fdiv(num, Sq), 0), P[q].dims[a] - 1);
+            f[a] = (double)(num - i0[a] * Sq) / (double)Sq;
+        }
+        double v[2][2][2];
+        for (int dz = 0; dz < 2; dz++)
+            for (int dy = 0; dy < 2; dy++)
+                for (int dx = 0; dx < 2; dx++) v[dz][dy][dx] = at(q, i0[0] + dx, i0[1] + dy, i0[2] + dz);
+        double x00 = v[0][0][0] + f[0] * (v[0][0][1] - v[0][0][0]);
+        double x10 = v[0][1][0] + f[0] * (v[0][1][1] - v[0][1][0]);
+        double x01 = v[1][0][0] + f[0] * (v[1][0][1] - v[1][0][0]);
+        double x11 = v[1][1][0] + f[0] * (v[1][1][1] - v[1][1][0]);
+        double y0 = x00 + f[1] * (x10 - x00);
+        double y1 = x01 + f[1] * (x11 - x01);
+        return y0 + f[2] * (y1 - y0);
+    }
+
+    // Samples of a vertex-centred patch with the dangling-node fix: a sample on the patch
+    // boundary whose eight surrounding finest cells (those in B) have a coarsest owner coarser
+    // than the patch takes that owner's interpolated value (first such owner in octant order,
+    // bit a of the octant set for the + side of axis a).  Coarser levels are final before this
+    // runs.  The shell replicates the nearest sample: the kernels read it only with weight zero,
+    // or with a rounding-sized weight for a position a few ulps outside the box.
+    void fill_vertex(int p) {
+        const int64_t *n = P[p].dims;
+        const int64_t nx = n[0] + 1, ny = n[1] + 1, nz = n[2] + 1;
+        brick[p].assign((size_t)((nx + 2) * (ny + 2) * (nz + 2)), 0.0);
+        const int l = T->plevel[p];
+        const int64_t S = T->scale[l];
+        for (int64_t k = 0; k < nz; k++)
+            for (int64_t j = 0; j < ny; j++)
+                for (int64_t i = 0; i < nx; i++) {
+                    double v = (double)P[p].cells[i + nx * (j + ny * k)];
+                    if (i == 0 || j == 0 || k == 0 || i == n[0] || j == n[1] || k == n[2]) {
+                        const int64_t G[3] = {T->pbox[p].lo[0] + i * S, T->pbox[p].lo[1] + j * S,
+                                              T->pbox[p].lo[2] + k * S};
+                        int m = l, own = -1;
+                        for (int o = 0; o < 8; o++) {
+                            int64_t c[3];
+                            bool inB = true;
+                            for (int a = 0; a < 3; a++) {
+                                c[a] = ((o >> a) & 1) ? G[a] : G[a] - 1;
+                                inB = inB && c[a] >= T->B_lo[a] && c[a] < T->B_hi[a];
+                            }
+                            if (!inB) continue;
+                            const int q = cell_owner(c);
+                            if (q >= 0 && T->plevel[q] < m) { m = T->plevel[q]; own = q; }
+                        }
+                        if (own >= 0) v = vertex_value(own, G);
+                    }
+                    at(p, i, j, k) = v;
+                }
+        for (int64_t k = -1; k <= nz; k++)
+            for (int64_t j = -1; j <= ny; j++)
+                for (int64_t i = -1; i <= nx; i++) {
+                    if (i >= 0 && j >= 0 && k >= 0 && i < nx && j < ny && k < nz) continue;
+                    at(p, i, j, k) = at(p, std::min<int64_t>(std::max<int64_t>(i, 0), nx - 1),
+                                        std::min<int64_t>(std::max<int64_t>(j, 0), ny - 1),
+                                        std::min<int64_t>(std::max<int64_t>(k, 0), nz - 1));
+                }
+    }
+
     void run(int nthreads) {
         brick.assign(np, {});
-        neighbours(nthreads);
+        if (!vertex) neighbours(nthreads);
         for (int l = 0; l <= T->lmax; l++) {      // coarser bricks are complete before finer ones
             std::vector<int> ids;
             for (int p = 0; p < np; p++) if (T->plevel[p] == l) ids.push_back(p);
             std::atomic<size_t> next{0};
             auto work = [&]() {
-                for (size_t k; (k = next.fetch_add(1)) < ids.size();) fill_patch(ids[k]);
+                for (size_t k; (k = next.fetch_add(1)) < ids.size();) {
+                    if (vertex) fill_vertex(ids[k]);
+                    else fill_patch(ids[k]);
+                }
             };
             std::vector<std::thread> th;
             for (int t = 0; t < nthreads; t++) th.emplace_back(work);
@@ -653,11 +740,15 @@ int amr_pack_pool(const amr_tree *T, const amr_patch *patches, int32_t npatches,
     const int np = npatches;
     const int layout = opts ? opts->brick_layout : 0;
     if (layout != 0 && layout != 1) { set_error("brick_layout must be 0 or 1"); return AMR_EINVAL; }
+    const int vertex = opts ? opts->centering : 0;
+    if (vertex != 0 && vertex != 1) { set_error("centering must be 0 (cells) or 1 (vertices)"); return AMR_EINVAL; }
+    // kernels see a vertex-centred patch of n cells as n + 1 samples at integer positions of
+    // its patch-local index (the header's lower corner moves down by half a cell)
     // pool layout: 256-byte aligned padded bricks (linear, or 4^3 micro-bricks)
     std::vector<int64_t> off(np);
     int64_t nfl = 64;   // leading pad: row loads of the linear layout may start one float early
     for (int p = 0; p < np; p++) {
-        const int64_t *n = patches[p].dims;
+        const int64_t n[3] = {patches[p].dims[0] + vertex, patches[p].dims[1] + vertex, patches[p].dims[2] + vertex};
         if (patches[p].level != T->plevel[p]) { set_error("patch %d differs from the tree's", p); return AMR_EINVAL; }
         off[p] = nfl;
         int64_t cells = layout == 0 ? (n[0] + 2) * (n[1] + 2) * (n[2] + 2)
@@ -699,14 +790,14 @@ int amr_pack_pool(const amr_tree *T, const amr_patch *patches, int32_t npatches,
     try {
         pool.assign((size_t)nfl, 0.0f);
         meta.assign((size_t)mbytes, 0);
-        Packer pk{T, patches, np, {}, {}};
+        Packer pk{T, patches, np, vertex, {}, {}};
         pk.run(nthreads);
         float vmin = INFINITY, vmax = -INFINITY;
         for (int p = 0; p < np; p++) {
             const std::vector<double> &b = pk.brick[p];
             int32_t n32[3], nb[3];
             for (int a = 0; a < 3; a++) {
-                n32[a] = (int32_t)patches[p].dims[a];
+                n32[a] = (int32_t)patches[p].dims[a] + vertex;
                 nb[a] = (n32[a] + 5) / 4;
             }
             const int64_t px = n32[0] + 2, py = n32[1] + 2, pz = n32[2] + 2;
@@ -748,18 +839,19 @@ int amr_pack_pool(const amr_tree *T, const amr_patch *patches, int32_t npatches,
             for (double v : pk.brick[p]) { pmin = std::min(pmin, (float)v); pmax = std::max(pmax, (float)v); }
             h.vmin = pmin;
             h.vmax = pmax;
-            for (int a = 0; a < 3; a++) h.nb[a] = ((int32_t)patches[p].dims[a] + 5) / 4;
+            for (int a = 0; a < 3; a++) h.nb[a] = ((int32_t)patches[p].dims[a] + vertex + 5) / 4;
             h.layout = layout;
             vmin = std::min(vmin, pmin);
             vmax = std::max(vmax, pmax);
             double hmin = INFINITY;
             for (int a = 0; a < 3; a++) {
-                h.n[a] = (int32_t)patches[p].dims[a];
-                h.lo[a] = world_plane(T, a, T->pbox[p].lo[a]);
+                h.n[a] = (int32_t)patches[p].dims[a] + vertex;
                 double rl = 1.0;
                 for (int k = 0; k < l; k++) rl *= (double)T->dom.refine;
                 h.h[a] = T->dom.h0[a] / rl;
                 h.inv_h[a] = 1.0 / h.h[a];
+                h.lo[a] = world_plane(T, a, T->pbox[p].lo[a]);
+                if (vertex) h.lo[a] = h.lo[a] - 0.5 * h.h[a];
                 hmin = std::min(hmin, T->dom.h0[a]);
             }
             double rl = 1.0;
@@ -785,20 +877,23 @@ int amr_pack_pool(const amr_tree *T, const amr_patch *patches, int32_t npatches,
             L.vmin = 0.0f;
             L.vmax = 0.0f;
             if (np_k >= 0) {
-                // value range over the leaf's cells plus one halo cell (padded-brick indices)
+                // value range over what a sample in the leaf can read: cell-centred, the leaf's
+                // cells plus one halo cell; vertex-centred, the vertices of the leaf's cells
                 int p = np_k;
                 int64_t S = T->scale[T->plevel[p]];
                 int64_t i0[3], i1[3];
                 for (int a = 0; a < 3; a++) {
                     i0[a] = (n.lo[a] - T->pbox[p].lo[a]) / S;        // first interior index
-                    i1[a] = (n.hi[a] - T->pbox[p].lo[a] + S - 1) / S;  // one past the last
+                    i1[a] = (n.hi[a] - T->pbox[p].lo[a] + S - 1) / S;  // one past the last cell
                 }
-                const int64_t *d = patches[p].dims;
+                const int64_t d[3] = {patches[p].dims[0] + vertex, patches[p].dims[1] + vertex,
+                                      patches[p].dims[2] + vertex};
+                const int64_t first = vertex ? 0 : 1;
                 const std::vector<double> &bk = pk.brick[p];
                 float mn = INFINITY, mx = -INFINITY;
-                for (int64_t z = i0[2] - 1; z <= i1[2]; z++)
-                    for (int64_t y = i0[1] - 1; y <= i1[1]; y++)
-                        for (int64_t x = i0[0] - 1; x <= i1[0]; x++) {
+                for (int64_t z = i0[2] - first; z <= i1[2]; z++)
+                    for (int64_t y = i0[1] - first; y <= i1[1]; y++)
+                        for (int64_t x = i0[0] - first; x <= i1[0]; x++) {
                             float v = (float)bk[(size_t)((x + 1) + (d[0] + 2) * ((y + 1) + (d[1] + 2) * (z + 1)))];
                             mn = std::min(mn, v);
                             mx = std::max(mx, v);
@@ -856,6 +951,7 @@ int amr_pack_pool(const amr_tree *T, const amr_patch *patches, int32_t npatches,
         out->refine = T->dom.refine;
         out->depth = (int32_t)T->depth;
         out->brick_layout = layout;
+        out->centering = vertex;
         double hmin = std::min(T->dom.h0[0], std::min(T->dom.h0[1], T->dom.h0[2]));
         double rl = 1.0;
         for (int k = 0; k < T->lmax; k++) rl *= (double)T->dom.refine;

@@ -876,6 +876,7 @@ inline int fill_args(const amr_scene *S, const amr_camera *C, const amr_render_p
     A->patches = (const DPatch *)S->patches;
     A->face_xf = (const DFaceXf *)S->face_taps;
     if (P->interp != 0 && P->interp != 1) { set_error("interp must be 0 (trilinear) or 1 (nearest cell)"); return AMR_EINVAL; }
+    if (P->interp == 1 && S->centering != 0) { set_error("nearest-cell sampling needs cell-centred data"); return AMR_EINVAL; }
     A->nearest = P->interp;
     if (!(P->lod >= 0.f)) { set_error("lod must be >= 0"); return AMR_EINVAL; }
     A->lod_on = P->lod > 0.f && S->nlod > 0;

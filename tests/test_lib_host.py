@@ -332,3 +332,66 @@ def test_face_tap_records(seed):
                     assert np.allclose(got, qo, rtol=0, atol=1e-9 * (1 + np.abs(qo).max()))
         assert mapped > 0
 
+
+
+def _vertex_h(name):
+    fn = workloads.gaussian_sum_field(np.random.default_rng(17), n=4, smin=0.08, smax=0.25)
+    if name == "tiny":
+        h = workloads.tiny_samr(2)
+    elif name == "lod":
+        h = workloads.lod_blocks(0)
+    elif name.startswith("aligned"):
+        h = workloads.random_tiny(int(name[-1]), root_aligned=True)
+    else:
+        h = workloads.random_tiny(int(name[4]), multi_root=name.endswith("m"))
+    return h.with_vertex_field(fn)
+
+
+@pytest.mark.parametrize("name", ["tiny", "lod", "aligned0", "aligned5", "rand1", "rand2m", "rand3", "rand4m"])
+def test_vertex_bricks_match_oracle(name):
+    """Vertex-centred pack: each brick holds the oracle's samples after the dangling-node fix
+    (FP64 on both sides, then fp32) with a shell replicating the nearest sample; the header
+    presents the n+1 samples to the kernels as cells whose centres are the vertices (lower
+    corner half a cell down), and the leaf value range covers the vertices of the leaf's cells."""
+    h = _vertex_h(name)
+    tree = amr.build_tree(h)
+    O = Oracle(h)
+    for layout in (0, 1):
+        scene = amr.pack(tree, h, host=True, nthreads=3, brick_layout=layout)
+        assert scene.scene.centering == 1
+        ph = scene.patch_headers()
+        for p, pt in enumerate(h.patches):
+            ref = O.vertex_values(p).astype(np.float32)
+            got = scene.brick(p)
+            assert got.shape == tuple(int(d) + 3 for d in pt.dims[::-1])
+            assert np.array_equal(got[1:-1, 1:-1, 1:-1], ref), (layout, p)
+            assert np.array_equal(got, np.pad(ref, 1, mode="edge")), (layout, p)
+            hl = h.h0 / float(h.refine) ** pt.level
+            assert np.array_equal(ph["n"][p], pt.dims + 1)
+            assert np.allclose(ph["lo"][p], h.origin + pt.lo * hl - 0.5 * hl, rtol=0, atol=1e-15)
+    _, leaves = tree.export()
+    lr = scene.leaf_records()
+    for k, lf in enumerate(leaves):
+        p = int(lf["patch"])
+        if p < 0:
+            continue
+        sc = h.refine ** (h.lmax - int(lf["level"]))
+        lo = (lf["lo"] - h.patches[p].lo * sc) // sc
+        hi = -((-(lf["hi"] - h.patches[p].lo * sc)) // sc)
+        sub = O.vertex_values(p)[lo[2]:hi[2] + 1, lo[1]:hi[1] + 1, lo[0]:hi[0] + 1].astype(np.float32)
+        assert lr[k]["vmin"] == sub.min() and lr[k]["vmax"] == sub.max()
+
+
+def test_vertex_sample_shape_checked():
+    h = workloads.tiny_samr(0)
+    bad = workloads.Hierarchy(h.origin, h.h0, h.refine, h.nlevels, h.patches, "vertex")
+    tree = amr.build_tree(bad)
+    with pytest.raises(ValueError):
+        amr.pack(tree, bad, host=True)
+    opts = L.amr_pack_opts()
+    opts.host_dst = 1
+    opts.centering = 2
+    pb, mb = ctypes.c_int64(0), ctypes.c_int64(0)
+    lib = amr.load()
+    assert lib.amr_pack_pool(tree.ptr, tree._patches, len(h.patches), ctypes.byref(opts), None, ctypes.byref(pb),
+                             None, ctypes.byref(mb), None, None) == L.AMR_EINVAL

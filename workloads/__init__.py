@@ -489,6 +489,17 @@ def cosmology_view(seed: int = 0, width: int = 1024, height: int = 1024):
     return h, lut_cosmology(seed), cam, prm
 
 
+def cosmology_vertex_view(seed: int = 0, width: int = 1024, height: int = 1024):
+    """The cosmology-like view with vertex-centred data (Section 4.2): the same boxes, LUT,
+    camera and params, each patch holding the log-normal density at its (dims+1)^3 grid
+    vertices."""
+    h, lut, cam, prm = cosmology_view(seed, width, height)
+    field = LogNormalField(_rng(1, "field", MASTER_SEED + seed))
+    ps = [Patch(p.level, p.lo.copy(), p.dims.copy(),
+                np.ascontiguousarray(field.rho_lattice(*h.vertex_positions(p)), dtype=np.float32)) for p in h.patches]
+    return Hierarchy(h.origin.copy(), h.h0.copy(), h.refine, h.nlevels, ps, "vertex"), lut, cam, prm
+
+
 def tf_fit(seed: int = 0, res: int = 512, ncams: int = 8, h: Hierarchy | None = None):
     """Differentiable transfer function: the cosmology-like hierarchy, `ncams` seeded orbit cameras at
     res^2, a hidden target LUT and a different starting LUT."""
