@@ -117,6 +117,54 @@ def cpu_baseline(h, cam, lut, prm, target_s=15.0, seed=7):
                 seconds=dt)
 
 
+def next_rows_section(amr, dev, scene, h, cam, lut_t, prm, steps, out, seed):
+    """The widened rows on the same view: nearest-cell sampling, the level-of-detail cut at
+    kind-(a) nodes (2 pixels), secondary rays to a point light (256x256, light at the domain
+    centre) and vertex-centred data (the same boxes with samples at the grid vertices)."""
+    import torch
+    import workloads
+    res = {}
+
+    def stats_of(scn, c, p):
+        r = amr.render(scn, c, lut_t, p, stats=True)
+        torch.cuda.synchronize()
+        return amr.stats_dict(r)
+
+    unlit = dict(prm, lighting=False)
+    near = dict(prm, interp=1)
+    res["nearest"] = dict(lit_ms=round(time_frames(amr, scene, cam, lut_t, near, steps, 2, out), 4),
+                          unlit_ms=round(time_frames(amr, scene, cam, lut_t, dict(near, lighting=False), steps, 2, out), 4),
+                          samples_per_frame=int(stats_of(scene, cam, near)["samples"]))
+    lod = dict(prm, lod=2.0)
+    st = stats_of(scene, cam, lod)
+    res["lod"] = dict(lod_pixels=2.0, lit_ms=round(time_frames(amr, scene, cam, lut_t, lod, steps, 2, out), 4),
+                      samples_per_frame=int(st["samples"]), segments_per_frame=int(st["segments"]))
+    small = dict(cam, width=256, height=256)
+    pl = dict(prm, lighting=2, light=(0.5, 0.5, 0.5))
+    out_s = torch.empty(256 * 256 * 4, dtype=torch.float32, device=dev)
+    st = stats_of(scene, small, pl)
+    res["point_light"] = dict(width=256, height=256, light=[0.5, 0.5, 0.5],
+                              ms=round(time_frames(amr, scene, small, lut_t, pl, max(2, steps // 4), 1, out_s), 4),
+                              primary_samples_per_frame=int(st["samples"]))
+    t = time.time()
+    hv, _, _, _ = workloads.cosmology_vertex_view(seed)
+    gen_s = time.time() - t
+    t = time.time()
+    tv = amr.build_tree(hv)
+    sv = amr.pack(tv, hv, device=dev, brick_layout=0)
+    torch.cuda.synchronize()
+    pack_s = time.time() - t
+    st = stats_of(sv, cam, prm)
+    res["vertex_centred"] = dict(lit_ms=round(time_frames(amr, sv, cam, lut_t, prm, steps, 2, out), 4),
+                                 unlit_ms=round(time_frames(amr, sv, cam, lut_t, unlit, steps, 2, out), 4),
+                                 samples_per_frame=int(st["samples"]), pool_bytes=int(sv.scene.pool_bytes),
+                                 generate_s=round(gen_s, 2), build_pack_upload_s=round(pack_s, 2))
+    del sv
+    torch.cuda.empty_cache()
+    log("next rows:", res)
+    return res
+
+
 def learned_skip_section(amr, dev, steps, warmup):
     """Deep-range hierarchy (20 levels) at 1024^2: plain traversal vs learned segment proposals.
     The network is trained on the GPU from segments logged by the plain kernel on 16 views and
@@ -195,6 +243,7 @@ def main():
     ap.add_argument("--brick-layout", type=int, default=0,
                     help="pool layout: 0 linear bricks (row loads; faster lit), 1 4^3 micro-bricks")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-skip section")
+    ap.add_argument("--no-next", action="store_true", help="skip the widened-rows section")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: the renderer runs on one GPU per process and this benchmark measures one GPU; "
@@ -274,6 +323,9 @@ def main():
         unlit_ms = time_frames(amr, scene, cam, lut_t, dict(prm, lighting=False), max(3, args.steps // 2), 2, out)
 
     pool_bytes, meta_bytes = int(scene.scene.pool_bytes), int(scene.scene.meta_bytes)
+    next_res = None
+    if not args.no_next:
+        next_res = next_rows_section(amr, dev, scene, h, cam, lut_t, prm, max(3, args.steps // 2), out, args.seed)
     learned_res = None
     if not args.no_learned:
         del scene
@@ -317,6 +369,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "learned_skip": learned_res,
+        "next_rows": next_res,
     }
     print(json.dumps(line), flush=True)
 
