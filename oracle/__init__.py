@@ -84,6 +84,7 @@ def _load():
             lib.orc_grad.argtypes = [_P, ctypes.POINTER(Camera), ctypes.POINTER(Params), _P, ctypes.c_int64, _P,
                                      _P, _P, _P]
             lib.orc_set_vertex.argtypes = [_P]
+            lib.orc_set_resident.argtypes = [_P, _P]
             lib.orc_vertex_value.restype = ctypes.c_double
             lib.orc_vertex_value.argtypes = [_P, ctypes.c_int, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64]
             lib.orc_num_threads.restype = ctypes.c_int
@@ -161,7 +162,9 @@ def lod_nodes(tree: kdbuild.Tree, h) -> np.ndarray:
 class Oracle:
     """FP64 reference renderer for one hierarchy. Builds its own kD tree with the naive builder."""
 
-    def __init__(self, h, tree: kdbuild.Tree | None = None):
+    def __init__(self, h, tree: kdbuild.Tree | None = None, resident=None):
+        """`resident`: optional bool/uint8 mask over the patches for out-of-core renders (leaves of
+        absent patches take the finest resident patch holding them)."""
         self.lib = _load()
         self.h = h
         self.tree = tree if tree is not None else kdbuild.build(finest_boxes(h), h.nlevels)
@@ -194,6 +197,13 @@ class Oracle:
         self.lib.orc_set_lod_nodes(self.handle, len(self._anodes), _ptr(self._anodes))
         if self.vertex:
             self.lib.orc_set_vertex(self.handle)
+        self.resident = None
+        if resident is not None:
+            m = np.ascontiguousarray(np.asarray(resident).astype(np.uint8))
+            if m.shape != (np_,):
+                raise ValueError("resident mask must have one entry per patch")
+            self.resident = m
+            self.lib.orc_set_resident(self.handle, _ptr(m))
 
     def __del__(self):
         if getattr(self, "handle", None):

@@ -14,6 +14,8 @@
  *     shared layer of samples at brick boundaries                      (Section 5 intro)
  *   - vertex-centred data: trilinear interpolation of vertex samples, the
  *     samples at dangling nodes replaced by the coarse interpolant       (Section 4.2)
+ *   - out-of-core subsets: leaves of absent subgrids drawn from the finest
+ *     present subgrid holding them                                       (Sections 4.2, 7)
  *   - gradient lighting with gradients taken on the fly, also across
  *     blocks of different subgrids                                      (Section 5, Section 6)
  *   - emission-absorption model                                          (Section 6)
@@ -84,6 +86,9 @@ typedef struct {
     int na;              /* kind-(a) nodes, in the tree's pre-order */
     int64_t *anode;      /* [na][9] lo3 hi3 (finest units), cover patch, cover level, depth */
     double *aw;          /* [na][6] world planes */
+    uint8_t *res;        /* resident subset (NULL: every patch), out-of-core rendering */
+    int *lremap;         /* with res: per leaf, the finest resident patch holding the leaf box */
+    int *aremap;         /* with res: the same for the kind-(a) nodes */
     int vertex;          /* 1: vertex-centred data, (n+1)^3 samples per patch */
     double **vfix;       /* vertex mode: per patch, the samples after the dangling-node fix */
 } Orc;
@@ -220,6 +225,7 @@ void orc_destroy(Orc *O) {
     free(O->bin_start); free(O->bin_list);
     free(O->anode); free(O->aw);
     if (O->vfix) { for (int p = 0; p < O->np; p++) free(O->vfix[p]); free(O->vfix); }
+    free(O->res); free(O->lremap); free(O->aremap);
     free(O);
 }
 
@@ -236,6 +242,45 @@ void orc_set_lod_nodes(Orc *O, int na, const int64_t *recs) {
             O->aw[6 * i + a] = plane(O, a, O->anode[9 * i + a]);
             O->aw[6 * i + 3 + a] = plane(O, a, O->anode[9 * i + 3 + a]);
         }
+}
+
+/* Out-of-core rendering (the motive for per-subgrid storage, Sections 4.2 and 7): only the
+ * patches with res[p] != 0 are on the device.  Every leaf (and kind-(a) node) keeps its place
+ * in the tree but takes its data from the finest resident patch whose box holds the leaf's
+ * whole box, at that patch's level and step; a leaf with no resident holder is empty.  The
+ * field at a point (gradient taps) is the finest resident patch holding the point.  Ghost
+ * values and vertex samples stay those of the full hierarchy (they belong to the bricks).
+ * Must follow orc_set_lod_nodes. */
+static int box_holds(const Orc *O, int q, const int64_t *lo, const int64_t *hi) {
+    for (int a = 0; a < 3; a++)
+        if (lo[a] < O->gplo[3 * q + a] || hi[a] > O->gphi[3 * q + a]) return 0;
+    return 1;
+}
+
+static int resident_holder(const Orc *O, const int64_t *lo, const int64_t *hi) {
+    int best = -1;
+    for (int q = 0; q < O->np; q++)
+        if (O->res[q] && box_holds(O, q, lo, hi) && (best < 0 || O->plev[q] > O->plev[best])) best = q;
+    return best;
+}
+
+void orc_set_resident(Orc *O, const uint8_t *mask) {
+    free(O->res); free(O->lremap); free(O->aremap);
+    O->res = (uint8_t *)malloc(O->np > 0 ? O->np : 1);
+    memcpy(O->res, mask, O->np);
+    O->lremap = (int *)malloc(sizeof(int) * (O->nl > 0 ? O->nl : 1));
+    O->aremap = (int *)malloc(sizeof(int) * (O->na > 0 ? O->na : 1));
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int i = 0; i < O->nl; i++) {
+        const int64_t *L = &O->leaf[8 * i];
+        int p = (int)L[6];
+        O->lremap[i] = p < 0 ? -1 : (O->res[p] ? p : resident_holder(O, L, L + 3));
+    }
+    for (int i = 0; i < O->na; i++) {
+        const int64_t *A = &O->anode[9 * i];
+        int p = (int)A[6];
+        O->aremap[i] = O->res[p] ? p : resident_holder(O, A, A + 3);
+    }
 }
 
 /* ------------------------------------------------------------------------------------ */
@@ -486,7 +531,7 @@ int orc_locate(Orc *O, const double *x, int brute) {
     int best = -1;
     if (brute) {
         for (int q = 0; q < O->np; q++)
-            if (contains_world(O, q, x) && (best < 0 || O->plev[q] > O->plev[best])) best = q;
+            if ((!O->res || O->res[q]) && contains_world(O, q, x) && (best < 0 || O->plev[q] > O->plev[best])) best = q;
         return best;
     }
     int b[3];
@@ -498,6 +543,7 @@ int orc_locate(Orc *O, const double *x, int brute) {
     int bin = b[0] + NB * (b[1] + NB * b[2]);
     for (int s = O->bin_start[bin]; s < O->bin_start[bin + 1]; s++) {
         int q = O->bin_list[s];
+        if (O->res && !O->res[q]) continue;
         if (contains_world(O, q, x) && (best < 0 || O->plev[q] > O->plev[best])) best = q;
     }
     return best;
@@ -733,6 +779,7 @@ static double light_transmittance(Orc *O, const orc_params *P, const double *lut
         double tb = buf[k].tx;
         const int64_t *L = &O->leaf[8 * buf[k].leaf];
         int p = (int)L[6], lev = (int)L[7];
+        if (O->res && p >= 0) { p = O->lremap[buf[k].leaf]; if (p >= 0) lev = (int)O->plev[p]; }
         if (p >= 0) {
             int slev = P->uniform_step ? O->lmax : lev;
             double step = P->step_frac * O->hs[slev];
@@ -815,6 +862,7 @@ static int walk_ray(Orc *O, const orc_camera *cam, const orc_params *P, const do
         double tb = c->tx;
         const int64_t *L = &O->leaf[8 * c->leaf];
         int p = (int)L[6], lev = (int)L[7];
+        if (O->res && p >= 0) { p = O->lremap[c->leaf]; if (p >= 0) lev = (int)O->plev[p]; }
         int seg_id = c->leaf;
         const double *lodbox = NULL;
         if (lod_on) {
@@ -824,8 +872,13 @@ static int walk_ray(Orc *O, const orc_camera *cam, const orc_params *P, const do
             for (int q = 0; q < nA; q++) {
                 if (!(aint[2 * q] <= ta && ta < aint[2 * q + 1])) continue;
                 const int64_t *A = &O->anode[9 * aid[q]];
+                int alev = (int)A[7];
+                if (O->res) {        /* out-of-core: the node's resident holder, if any */
+                    if (O->aremap[aid[q]] < 0) continue;
+                    alev = (int)O->plev[O->aremap[aid[q]]];
+                }
                 double foot = cam->ortho ? pix : ta * pix;
-                if (!(O->hs[A[7]] < P->lod * foot)) continue;
+                if (!(O->hs[alev] < P->lod * foot)) continue;
                 if (best < 0 || A[8] < O->anode[9 * aid[best] + 8]) best = q;
             }
             if (best >= 0) {
@@ -833,6 +886,7 @@ static int walk_ray(Orc *O, const orc_camera *cam, const orc_params *P, const do
                 tb = aint[2 * best + 1];
                 p = (int)A[6];
                 lev = (int)A[7];
+                if (O->res) { p = O->aremap[aid[best]]; if (p >= 0) lev = (int)O->plev[p]; }
                 seg_id = O->nl + aid[best];
                 lodbox = &O->aw[6 * aid[best]];
                 while (k + 1 < n && (*cbuf)[k + 1].tx <= tb) k++;   /* leaves inside the node */
