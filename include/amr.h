@@ -336,6 +336,62 @@ int amr_mlp_adam_step(float *W, const float *dW, float *M, float *V, int32_t t, 
 int64_t amr_mlp_packed_bytes(void);
 int amr_mlp_pack(const float *W, void *d_out, void *stream);
 
+/* ---------------------------------------------------------------------------------------- */
+/* Out-of-core residency (Sections 4.2 and 7)                                                */
+/* ---------------------------------------------------------------------------------------- */
+
+/* The paper keeps one texture brick per subgrid, and with bindless access an out-of-core
+ * renderer can upload the subsets of bricks it needs.  A store holds every brick on the host,
+ * packed once as amr_pack_pool packs them; amr_store_update makes a subset resident in a device
+ * brick cache and writes a scene in which each leaf (and kind-(a) node) of an absent patch is
+ * drawn from the finest resident patch whose box holds the leaf's box, with that patch's cells
+ * and sample step; a leaf with no resident holder is empty, and a kind-(a) node without one is
+ * never a level-of-detail stop.  Gradient taps read the finest resident patch holding the tap
+ * point.  Ghost layers and vertex samples stay those of the full hierarchy.  The render entry
+ * points take the scene unchanged. */
+typedef struct amr_store amr_store;   /* opaque; not thread-safe */
+
+typedef struct {
+    int64_t npatches;
+    int64_t meta_bytes;        /* device metadata buffer amr_store_update needs */
+    int64_t full_cache_bytes;  /* cache that holds every brick at once */
+    int64_t pad_bytes;         /* bytes of a cache outside the bricks (row-load pads) */
+} amr_store_info;
+
+typedef struct {
+    int64_t uploaded_bricks, uploaded_bytes;   /* host-to-device brick copies of this update */
+    int64_t evicted_bricks;                    /* bricks dropped from the cache */
+    int64_t resident_bricks, resident_bytes;   /* after the update */
+    int64_t remapped_leaves;                   /* leaf records drawn from another patch */
+    int32_t repacked;                          /* 1: every resident brick was laid out again */
+    int32_t reserved_;
+} amr_store_report;
+
+/* Packs every patch into a host store (same options as amr_pack_pool; opts->host_dst = 1 makes
+ * amr_store_update write plain host memory, for tests without a GPU).  `tree` and `patches`
+ * are read only during the call.  Free with amr_store_free. */
+int amr_store_create(const amr_tree *tree, const amr_patch *patches, int32_t npatches,
+                     const amr_pack_opts *opts, amr_store **out);
+int amr_store_stats(const amr_store *s, amr_store_info *info);
+/* Cache bytes of each patch's brick (bytes[npatches]; AMR_ECAPACITY if cap < npatches). */
+int amr_store_brick_bytes(const amr_store *s, int64_t *bytes, int64_t cap);
+/* A resident set for `cam` within cache_bytes: levels coarse to fine, inside a level the
+ * patches whose bounding sphere meets the view volume nearest first; refinements out of view
+ * are left out; a brick that does not fit is skipped.  Writes resident[npatches] (0/1). */
+int amr_store_select(const amr_store *s, const amr_camera *cam, int64_t cache_bytes, uint8_t *resident);
+/* Makes the patches with resident[p] != 0 resident in the device cache d_cache (cache_bytes,
+ * 256-byte aligned; a cache never seen before, or of another size, is cleared and laid out from
+ * the start).  Bricks already in the cache stay where they are; new ones take the first free
+ * slot that fits, and when none does every resident brick is laid out again.  Writes the
+ * metadata to d_meta (>= amr_store_info.meta_bytes) and the scene to *out_scene, whose pool is
+ * d_cache.  The copies are enqueued on `stream` and waited for.  AMR_ECAPACITY when the
+ * resident bricks exceed the cache (the cache and the previous scene are unchanged).  Renders
+ * of an earlier scene must have finished before the call. */
+int amr_store_update(amr_store *s, const uint8_t *resident, void *d_cache, int64_t cache_bytes,
+                     void *d_meta, int64_t meta_bytes, amr_scene *out_scene, amr_store_report *report,
+                     void *stream);
+void amr_store_free(amr_store *s);
+
 #ifdef __cplusplus
 }
 #endif

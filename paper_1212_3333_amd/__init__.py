@@ -22,8 +22,8 @@ from ._lib import AMRError, check, load
 
 load()
 
-__all__ = ["AMRError", "Tree", "Scene", "build_tree", "pack", "render", "render_backward", "make_params",
-           "RenderOutput", "AMRRender"]
+__all__ = ["AMRError", "Tree", "Scene", "Store", "ResidentScene", "build_tree", "pack", "render",
+           "render_backward", "make_params", "RenderOutput", "AMRRender"]
 
 
 def _vp(t) -> ctypes.c_void_p:
@@ -109,20 +109,7 @@ class Scene:
     def __init__(self, tree: Tree, h, device="cuda", host: bool = False, nthreads: int = 0, brick_layout: int = 1):
         self.lib = load()
         self.tree = tree
-        centering = getattr(h, "centering", "cell")
-        if centering not in ("cell", "vertex"):
-            raise ValueError("centering must be 'cell' or 'vertex'")
-        extra = 1 if centering == "vertex" else 0
-        for i, p in enumerate(h.patches):
-            want = tuple(int(d) + extra for d in p.dims[::-1])
-            if tuple(np.shape(p.cells)) != want:
-                raise ValueError("patch %d holds samples of shape %s; %s-centred data needs %s"
-                                 % (i, np.shape(p.cells), centering, want))
-        opts = L.amr_pack_opts()
-        opts.host_dst = 1 if host else 0
-        opts.nthreads = int(nthreads)
-        opts.brick_layout = int(brick_layout)
-        opts.centering = extra
+        opts = _pack_opts(h, host, nthreads, brick_layout)
         pb, mb = ctypes.c_int64(0), ctypes.c_int64(0)
         check(self.lib.amr_pack_pool(tree.ptr, tree._patches, len(h.patches), ctypes.byref(opts), None,
                                      ctypes.byref(pb), None, ctypes.byref(mb), None, None), "amr_pack_pool(size)")
@@ -200,6 +187,103 @@ class Scene:
 
 def pack(tree: Tree, h, device="cuda", host: bool = False, nthreads: int = 0, brick_layout: int = 1) -> Scene:
     return Scene(tree, h, device=device, host=host, nthreads=nthreads, brick_layout=brick_layout)
+
+
+def _pack_opts(h, host: bool, nthreads: int, brick_layout: int) -> L.amr_pack_opts:
+    centering = getattr(h, "centering", "cell")
+    if centering not in ("cell", "vertex"):
+        raise ValueError("centering must be 'cell' or 'vertex'")
+    extra = 1 if centering == "vertex" else 0
+    for i, p in enumerate(h.patches):
+        want = tuple(int(d) + extra for d in p.dims[::-1])
+        if tuple(np.shape(p.cells)) != want:
+            raise ValueError("patch %d holds samples of shape %s; %s-centred data needs %s"
+                             % (i, np.shape(p.cells), centering, want))
+    opts = L.amr_pack_opts()
+    opts.host_dst = 1 if host else 0
+    opts.nthreads = int(nthreads)
+    opts.brick_layout = int(brick_layout)
+    opts.centering = extra
+    return opts
+
+
+class ResidentScene(Scene):
+    """Scene of a Store update: pool = the device brick cache, meta = its metadata buffer."""
+
+    def __init__(self, store, cache, meta, scene):
+        self.lib = store.lib
+        self.tree = store.tree
+        self.host = store.host
+        self.pool = cache
+        self.meta = meta
+        self.scene = scene
+
+
+class Store:
+    """Out-of-core residency (amr_store_*): every brick packed once on the host; `update` makes
+    a subset resident in a device brick cache and returns the scene that renders it."""
+
+    def __init__(self, tree: Tree, h, host: bool = False, nthreads: int = 0, brick_layout: int = 0):
+        self.lib = load()
+        self.tree = tree
+        self.host = host
+        self.npatches = len(h.patches)
+        opts = _pack_opts(h, host, nthreads, brick_layout)
+        ptr = ctypes.c_void_p()
+        check(self.lib.amr_store_create(tree.ptr, tree._patches, len(h.patches), ctypes.byref(opts),
+                                        ctypes.byref(ptr)), "amr_store_create")
+        self.ptr = ptr
+
+    def __del__(self):
+        if getattr(self, "ptr", None) and self.ptr.value:
+            self.lib.amr_store_free(self.ptr)
+            self.ptr = None
+
+    def info(self) -> dict:
+        s = L.amr_store_info()
+        check(self.lib.amr_store_stats(self.ptr, ctypes.byref(s)), "amr_store_stats")
+        return {k: int(getattr(s, k)) for k, _ in L.amr_store_info._fields_}
+
+    def brick_bytes(self) -> np.ndarray:
+        out = np.zeros(self.npatches, dtype=np.int64)
+        check(self.lib.amr_store_brick_bytes(self.ptr, _vp(out), len(out)), "amr_store_brick_bytes")
+        return out
+
+    def select(self, cam: dict, cache_bytes: int) -> np.ndarray:
+        out = np.zeros(self.npatches, dtype=np.uint8)
+        check(self.lib.amr_store_select(self.ptr, ctypes.byref(make_camera(cam)), int(cache_bytes), _vp(out)),
+              "amr_store_select")
+        return out.astype(bool)
+
+    @staticmethod
+    def host_buffer(nbytes: int) -> np.ndarray:
+        """Zeroed 256-byte aligned host bytes (a cache for a host store)."""
+        raw = np.zeros(int(nbytes) + 256, dtype=np.uint8)
+        off = (-raw.ctypes.data) % 256
+        return raw[off:off + int(nbytes)]
+
+    def alloc(self, cache_bytes: int, device="cuda"):
+        """(cache, meta) buffers: device tensors, or numpy arrays for a host store."""
+        mb = self.info()["meta_bytes"]
+        if self.host:
+            return self.host_buffer(cache_bytes), self.host_buffer(mb)
+        return (torch.zeros(int(cache_bytes), dtype=torch.uint8, device=device),
+                torch.empty(mb, dtype=torch.uint8, device=device))
+
+    def update(self, resident, cache, meta):
+        """Makes the patches with resident[p] true resident in `cache`; returns (scene, report)."""
+        m = np.ascontiguousarray(np.asarray(resident).astype(np.uint8))
+        if m.shape != (self.npatches,):
+            raise ValueError("resident mask must have one entry per patch")
+        sc = L.amr_scene()
+        rep = L.amr_store_report()
+        nbytes = cache.numel() if isinstance(cache, torch.Tensor) else cache.nbytes
+        mbytes = meta.numel() if isinstance(meta, torch.Tensor) else meta.nbytes
+        stream = ctypes.c_void_p(None) if self.host else _stream(cache.device)
+        check(self.lib.amr_store_update(self.ptr, _vp(m), _vp(cache), int(nbytes), _vp(meta), int(mbytes),
+                                        ctypes.byref(sc), ctypes.byref(rep), stream), "amr_store_update")
+        return ResidentScene(self, cache, meta, sc), {k: int(getattr(rep, k)) for k, _ in L.amr_store_report._fields_
+                                                      if k != "reserved_"}
 
 
 def make_camera(cam: dict) -> L.amr_camera:

@@ -62,6 +62,18 @@ class amr_scene(ctypes.Structure):
                 ("v_max", ctypes.c_float)]
 
 
+class amr_store_info(ctypes.Structure):
+    _fields_ = [("npatches", ctypes.c_int64), ("meta_bytes", ctypes.c_int64), ("full_cache_bytes", ctypes.c_int64),
+                ("pad_bytes", ctypes.c_int64)]
+
+
+class amr_store_report(ctypes.Structure):
+    _fields_ = [("uploaded_bricks", ctypes.c_int64), ("uploaded_bytes", ctypes.c_int64),
+                ("evicted_bricks", ctypes.c_int64), ("resident_bricks", ctypes.c_int64),
+                ("resident_bytes", ctypes.c_int64), ("remapped_leaves", ctypes.c_int64),
+                ("repacked", ctypes.c_int32), ("reserved_", ctypes.c_int32)]
+
+
 class amr_camera(ctypes.Structure):
     _fields_ = [("eye", c_double3), ("u", c_double3), ("v", c_double3), ("w", c_double3),
                 ("tan_half_fov", ctypes.c_double), ("win", ctypes.c_double * 2), ("ortho", ctypes.c_int32),
@@ -113,6 +125,14 @@ SIGNATURES = {
     "amr_pack_pool": (ctypes.c_int, [VP, ctypes.POINTER(amr_patch), ctypes.c_int32, ctypes.POINTER(amr_pack_opts),
                                      VP, ctypes.POINTER(ctypes.c_int64), VP, ctypes.POINTER(ctypes.c_int64),
                                      ctypes.POINTER(amr_scene), VP]),
+    "amr_store_create": (ctypes.c_int, [VP, ctypes.POINTER(amr_patch), ctypes.c_int32, ctypes.POINTER(amr_pack_opts),
+                                        ctypes.POINTER(VP)]),
+    "amr_store_stats": (ctypes.c_int, [VP, ctypes.POINTER(amr_store_info)]),
+    "amr_store_brick_bytes": (ctypes.c_int, [VP, VP, ctypes.c_int64]),
+    "amr_store_select": (ctypes.c_int, [VP, ctypes.POINTER(amr_camera), ctypes.c_int64, VP]),
+    "amr_store_update": (ctypes.c_int, [VP, VP, VP, ctypes.c_int64, VP, ctypes.c_int64, ctypes.POINTER(amr_scene),
+                                        ctypes.POINTER(amr_store_report), VP]),
+    "amr_store_free": (None, [VP]),
     "amr_render": (ctypes.c_int, [ctypes.POINTER(amr_scene), ctypes.POINTER(amr_camera), ctypes.c_int32,
                                   ctypes.POINTER(amr_render_params), VP, VP, VP]),
     "amr_queue_bytes": (ctypes.c_int64, [ctypes.c_int32]),
