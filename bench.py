@@ -146,6 +146,7 @@ def next_rows_section(amr, dev, scene, h, cam, lut_t, prm, steps, out, seed):
     res["point_light"] = dict(width=256, height=256, light=[0.5, 0.5, 0.5],
                               ms=round(time_frames(amr, scene, small, lut_t, pl, max(2, steps // 4), 1, out_s), 4),
                               primary_samples_per_frame=int(st["samples"]))
+    res["out_of_core"] = out_of_core_section(amr, dev, scene, h, cam, lut_t, prm, steps, out)
     t = time.time()
     hv, _, _, _ = workloads.cosmology_vertex_view(seed)
     gen_s = time.time() - t
@@ -163,6 +164,58 @@ def next_rows_section(amr, dev, scene, h, cam, lut_t, prm, steps, out, seed):
     torch.cuda.empty_cache()
     log("next rows:", res)
     return res
+
+
+def out_of_core_section(amr, dev, scene, h, cam, lut_t, prm, steps, out, frac=0.3, frames=8):
+    """Per-subgrid residency: a brick cache of `frac` of all bricks, an 8-frame orbit through
+    the benchmark view where each frame selects its subset (90% of the cache) and updates the
+    cache incrementally, then renders lit at 1024^2.  Reports the host update time, the bytes
+    uploaded per frame, the render time, and the last frame's error against the render with
+    every brick resident."""
+    import torch
+    t = time.time()
+    st = amr.Store(scene.tree, h, brick_layout=0)
+    create_s = time.time() - t
+    info = st.info()
+    cap = int(frac * info["full_cache_bytes"]) // 256 * 256
+    cache, meta = st.alloc(cap, device=dev)
+    upd_ms, up_b, ren_ms, remapped = [], [], [], []
+    for k in range(frames):
+        c = dict(cam) if k == frames - 1 else workloads_orbit(cam, k, frames)
+        t = time.time()
+        mask = st.select(c, int(0.9 * cap))
+        sc, rep = st.update(mask, cache, meta)
+        torch.cuda.synchronize()
+        upd_ms.append(1e3 * (time.time() - t))
+        up_b.append(rep["uploaded_bytes"])
+        remapped.append(rep["remapped_leaves"])
+        ren_ms.append(time_frames(amr, sc, c, lut_t, prm, max(2, steps // 2), 1, out))
+    img = out.view(-1, 4).clone()
+    ref = torch.empty_like(out)
+    time_frames(amr, scene, cam, lut_t, prm, 1, 0, ref)
+    err = float((img - ref.view(-1, 4)).abs().max().item())
+    res = dict(cache_bytes=cap, full_bytes=int(info["full_cache_bytes"]), frames=frames,
+               store_create_s=round(create_s, 2), first_upload_bytes=int(up_b[0]),
+               mean_upload_bytes_after_first=int(np.mean(up_b[1:])), mean_update_ms_after_first=round(float(np.mean(upd_ms[1:])), 2),
+               first_update_ms=round(upd_ms[0], 2), mean_render_ms=round(float(np.mean(ren_ms)), 4),
+               remapped_leaves_last=int(remapped[-1]), max_rgba_err_vs_all_resident=err)
+    del cache, meta, st
+    torch.cuda.empty_cache()
+    return res
+
+
+def workloads_orbit(cam, k, frames):
+    """Camera k of a short orbit ending at the benchmark view (same radius, fov, size)."""
+    import workloads
+    import math as _m
+    eye = np.asarray(cam["eye"], np.float64)
+    rel = eye - 0.5
+    r = float(np.linalg.norm(rel))
+    az = _m.atan2(rel[0], -rel[2]) - 0.12 * (frames - 1 - k)
+    el = _m.asin(rel[1] / r)
+    fov = 2.0 * _m.degrees(_m.atan(cam["tan_half_fov"]))
+    c = workloads.perspective_orbit(cam["width"], cam["height"], az, el, radius=r, fov_deg=fov)
+    return c
 
 
 def learned_skip_section(amr, dev, steps, warmup):
