@@ -120,7 +120,10 @@ typedef struct {
     int32_t brick_layout; /* 0: each padded brick x-fastest (the pool keeps 64 spare floats
                              before the first and after the last brick, so the lit kernel reads
                              whole rows); 1: padded brick stored as 4x4x4-cell micro-bricks
-                             (256 bytes each, x-fastest inside and between them) */
+                             (256 bytes each, x-fastest inside and between them); 2: halo rows,
+                             4x4x4-cell blocks of 16 rows of 8 floats (512 bytes), row (j, k) of
+                             block column bx holding padded x indices 4 bx - 1 .. 4 bx + 6, so a
+                             stencil row loads as one vector from one block (twice the floats) */
     int32_t centering;    /* 0: cell-centred data, `cells` holds dims[0]*dims[1]*dims[2] values;
                              1: vertex-centred data (Section 4.2), `cells` holds the
                              (dims[0]+1)(dims[1]+1)(dims[2]+1) samples at the grid vertices

@@ -106,7 +106,7 @@ class Scene:
     """Packed pool + device tree. On device, pool/meta are torch uint8 tensors on `device`;
     with host=True they are numpy arrays (no HIP involved)."""
 
-    def __init__(self, tree: Tree, h, device="cuda", host: bool = False, nthreads: int = 0, brick_layout: int = 1):
+    def __init__(self, tree: Tree, h, device="cuda", host: bool = False, nthreads: int = 0, brick_layout: int = 2):
         self.lib = load()
         self.tree = tree
         opts = _pack_opts(h, host, nthreads, brick_layout)
@@ -143,9 +143,22 @@ class Scene:
         if int(hdr["layout"]) == 0:
             return pool[off:off + (nx + 2) * (ny + 2) * (nz + 2)].reshape(nz + 2, ny + 2, nx + 2)
         bx, by, bz = (int(v) for v in hdr["nb"])
-        blocks = pool[off:off + bx * by * bz * 64].reshape(bz, by, bx, 4, 4, 4)
+        if int(hdr["layout"]) == 2:
+            # halo rows: block (bz, by, bx), row (k & 3, j & 3), slots 1..4 hold x = 4 bx .. 4 bx + 3
+            blocks = pool[off:off + bx * by * bz * 128].reshape(bz, by, bx, 4, 4, 8)[..., 1:5]
+        else:
+            blocks = pool[off:off + bx * by * bz * 64].reshape(bz, by, bx, 4, 4, 4)
         full = blocks.transpose(0, 3, 1, 4, 2, 5).reshape(4 * bz, 4 * by, 4 * bx)
         return full[: nz + 2, : ny + 2, : nx + 2]
+
+    def halo_rows(self, p: int) -> np.ndarray:
+        """Halo-row layout only: the raw [nbz, nby, nbx, 4 (z), 4 (y), 8] row store of patch p."""
+        assert self.host
+        hdr = self.patch_headers()[p]
+        assert int(hdr["layout"]) == 2
+        bx, by, bz = (int(v) for v in hdr["nb"])
+        off = int(hdr["off"])
+        return self.pool.view(np.float32)[off:off + bx * by * bz * 128].reshape(bz, by, bx, 4, 4, 8)
 
     def patch_headers(self) -> np.ndarray:
         dt = np.dtype([("off", np.uint64), ("n", np.int32, 3), ("level", np.int32), ("lo", np.float64, 3),
@@ -185,7 +198,7 @@ class Scene:
         return np.frombuffer(raw.tobytes(), dtype=dt)
 
 
-def pack(tree: Tree, h, device="cuda", host: bool = False, nthreads: int = 0, brick_layout: int = 1) -> Scene:
+def pack(tree: Tree, h, device="cuda", host: bool = False, nthreads: int = 0, brick_layout: int = 2) -> Scene:
     return Scene(tree, h, device=device, host=host, nthreads=nthreads, brick_layout=brick_layout)
 
 
@@ -223,7 +236,7 @@ class Store:
     """Out-of-core residency (amr_store_*): every brick packed once on the host; `update` makes
     a subset resident in a device brick cache and returns the scene that renders it."""
 
-    def __init__(self, tree: Tree, h, host: bool = False, nthreads: int = 0, brick_layout: int = 0):
+    def __init__(self, tree: Tree, h, host: bool = False, nthreads: int = 0, brick_layout: int = 2):
         self.lib = load()
         self.tree = tree
         self.host = host

@@ -739,7 +739,7 @@ int amr_pack_pool(const amr_tree *T, const amr_patch *patches, int32_t npatches,
     if (npatches != (int32_t)T->pbox.size()) { set_error("npatches differs from the tree's"); return AMR_EINVAL; }
     const int np = npatches;
     const int layout = opts ? opts->brick_layout : 0;
-    if (layout != 0 && layout != 1) { set_error("brick_layout must be 0 or 1"); return AMR_EINVAL; }
+    if (layout < 0 || layout > 2) { set_error("brick_layout must be 0, 1 or 2"); return AMR_EINVAL; }
     const int vertex = opts ? opts->centering : 0;
     if (vertex != 0 && vertex != 1) { set_error("centering must be 0 (cells) or 1 (vertices)"); return AMR_EINVAL; }
     // kernels see a vertex-centred patch of n cells as n + 1 samples at integer positions of
@@ -751,8 +751,9 @@ int amr_pack_pool(const amr_tree *T, const amr_patch *patches, int32_t npatches,
         const int64_t n[3] = {patches[p].dims[0] + vertex, patches[p].dims[1] + vertex, patches[p].dims[2] + vertex};
         if (patches[p].level != T->plevel[p]) { set_error("patch %d differs from the tree's", p); return AMR_EINVAL; }
         off[p] = nfl;
-        int64_t cells = layout == 0 ? (n[0] + 2) * (n[1] + 2) * (n[2] + 2)
-                                    : ((n[0] + 5) / 4) * ((n[1] + 5) / 4) * ((n[2] + 5) / 4) * 64;
+        const int32_t n32[3] = {(int32_t)n[0], (int32_t)n[1], (int32_t)n[2]};
+        const int32_t nb[3] = {(n32[0] + 5) / 4, (n32[1] + 5) / 4, (n32[2] + 5) / 4};
+        const int64_t cells = brick_floats(layout, n32, nb);
         nfl = align_up(nfl + cells, 64);
     }
     const int64_t nn = (int64_t)T->nodes.size(), nl0 = (int64_t)T->leaves.size();
@@ -801,6 +802,11 @@ int amr_pack_pool(const amr_tree *T, const amr_patch *patches, int32_t npatches,
                 nb[a] = (n32[a] + 5) / 4;
             }
             const int64_t px = n32[0] + 2, py = n32[1] + 2, pz = n32[2] + 2;
+            if (layout == 2) {
+                halo_row_fill(n32, nb, pool.data() + off[p],
+                              [&](int64_t i, int64_t j, int64_t k) { return (float)b[(size_t)(i + px * (j + py * k))]; });
+                continue;
+            }
             for (int64_t k = 0; k < pz; k++)
                 for (int64_t j = 0; j < py; j++)
                     for (int64_t i = 0; i < px; i++)
@@ -915,8 +921,8 @@ int amr_pack_pool(const amr_tree *T, const amr_patch *patches, int32_t npatches,
                     const DPatch &Po = dp[o], &Pp = dp[p];
                     X.off = Po.off;
                     for (int a = 0; a < 3; a++) X.n[a] = Po.n[a];
-                    if (layout == 1) {
-                        X.px = 64 * Po.nb[0];
+                    if (layout == 1 || layout == 2) {
+                        X.px = (layout == 1 ? 64 : 128) * Po.nb[0];
                         X.pxy = X.px * Po.nb[1];
                     } else {
                         X.px = Po.n[0] + 2;

@@ -22,7 +22,8 @@ namespace amr {
 
 // At least 3 waves per SIMD: the lit kernel then fits 168 VGPRs with a 12-byte spill instead
 // of running 2 waves at 171 (the unlit one needs 80 and runs 6).
-template <bool LIT, bool REC, bool NEAR>
+// LAY: the brick layout fixed at compile time for the timed variants (-1: read at run time).
+template <bool LIT, bool REC, bool NEAR, int LAY>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void render_fwd(RenderArgs A) {
     __shared__ float4 s_lut[256];
     for (int i = threadIdx.x; i < 256; i += 64) s_lut[i] = A.lut[i];
@@ -97,11 +98,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void re
                 dseg++;
             }
             Segment S;
-            setup_segment<LIT>(A, R, L, leaf, tcur, tb, S);
+            setup_segment<LIT, LAY>(A, R, L, leaf, tcur, tb, S);
             nsm = S.n;
             for (int k = 0; k < nsm; k++) {
                 SampleVals v;
-                eval_sample<LIT, REC, NEAR>(A, s_lut, R, S, k, v, cnt);
+                eval_sample<LIT, REC, NEAR, LAY>(A, s_lut, R, S, k, v, cnt);
                 float wgt = T * v.alpha * v.shade;
                 C0 += wgt * v.r;
                 C1 += wgt * v.g;
@@ -370,20 +371,26 @@ int amr_render(const amr_scene *S, const amr_camera *cams, int32_t ncams, const 
             pix_off += (int64_t)cams[c].width * cams[c].height;
             continue;
         }
+        const dim3 g(grid), b(64);
         if (A.nearest) {
             if (A.lighting) {
-                if (rec) hipLaunchKernelGGL((render_fwd<true, true, true>), dim3(grid), dim3(64), 0, s, A);
-                else hipLaunchKernelGGL((render_fwd<true, false, true>), dim3(grid), dim3(64), 0, s, A);
+                if (rec) hipLaunchKernelGGL((render_fwd<true, true, true, -1>), g, b, 0, s, A);
+                else hipLaunchKernelGGL((render_fwd<true, false, true, -1>), g, b, 0, s, A);
             } else {
-                if (rec) hipLaunchKernelGGL((render_fwd<false, true, true>), dim3(grid), dim3(64), 0, s, A);
-                else hipLaunchKernelGGL((render_fwd<false, false, true>), dim3(grid), dim3(64), 0, s, A);
+                if (rec) hipLaunchKernelGGL((render_fwd<false, true, true, -1>), g, b, 0, s, A);
+                else hipLaunchKernelGGL((render_fwd<false, false, true, -1>), g, b, 0, s, A);
             }
-        } else if (A.lighting) {
-            if (rec) hipLaunchKernelGGL((render_fwd<true, true, false>), dim3(grid), dim3(64), 0, s, A);
-            else hipLaunchKernelGGL((render_fwd<true, false, false>), dim3(grid), dim3(64), 0, s, A);
+        } else if (rec) {
+            if (A.lighting) hipLaunchKernelGGL((render_fwd<true, true, false, -1>), g, b, 0, s, A);
+            else hipLaunchKernelGGL((render_fwd<false, true, false, -1>), g, b, 0, s, A);
+        } else if (A.lighting) {   // the timed variants, one per brick layout
+            if (A.layout == 0) hipLaunchKernelGGL((render_fwd<true, false, false, 0>), g, b, 0, s, A);
+            else if (A.layout == 1) hipLaunchKernelGGL((render_fwd<true, false, false, 1>), g, b, 0, s, A);
+            else hipLaunchKernelGGL((render_fwd<true, false, false, 2>), g, b, 0, s, A);
         } else {
-            if (rec) hipLaunchKernelGGL((render_fwd<false, true, false>), dim3(grid), dim3(64), 0, s, A);
-            else hipLaunchKernelGGL((render_fwd<false, false, false>), dim3(grid), dim3(64), 0, s, A);
+            if (A.layout == 0) hipLaunchKernelGGL((render_fwd<false, false, false, 0>), g, b, 0, s, A);
+            else if (A.layout == 1) hipLaunchKernelGGL((render_fwd<false, false, false, 1>), g, b, 0, s, A);
+            else hipLaunchKernelGGL((render_fwd<false, false, false, 2>), g, b, 0, s, A);
         }
         rc = check_hip(hipGetLastError(), "render_fwd launch");
         if (rc) return rc;

@@ -43,7 +43,7 @@ struct RenderArgs {
     int32_t ortho, width, height, depth;
     float v_lo, inv_range, step_frac, t_min;
     float lhat[3], inv_lnorm, k_a, k_d, eps2;
-    int32_t uniform_step, lighting, micro;
+    int32_t uniform_step, lighting, layout;   // layout: 0 linear, 1 micro-bricks, 2 halo rows
     float *rgba;
     amr_trace_rec *trace;
     int32_t *trace_n;
@@ -203,17 +203,35 @@ __device__ __forceinline__ float lerpf(float a, float b, float f) { return a + f
 
 struct PatchView {
     const float *brick;
-    int px, pxy, nx, ny, nz;          // linear: row and slab strides; micro-bricks: 64 nbx, 64 nbx nby
+    int px, pxy, nx, ny, nz;          // linear: row and slab strides; micro-bricks: 64 nbx, 64 nbx nby;
+                                      // halo rows: 128 nbx, 128 nbx nby
 };
 
+// Halo-row layout (2): the padded brick is cut into 4x4x4-cell blocks; a block stores its 16
+// x-rows (y fastest, then z) of 8 floats each, holding padded x indices 4 bx - 1 .. 4 bx + 6, so
+// the four x cells a stencil row needs lie in one row of the block chosen by the stencil's first
+// core cell, and load as one vector.  Offset of padded x index x in the block column bx:
+__device__ __forceinline__ int halo_x(int x, int bx) { return x + 1 + 124 * bx; }
+__device__ __forceinline__ int halo_y(const PatchView &pv, int j) { return (j >> 2) * pv.px + (j & 3) * 8; }
+__device__ __forceinline__ int halo_z(const PatchView &pv, int k) { return (k >> 2) * pv.pxy + (k & 3) * 32; }
+
+// LAY: the brick layout when known at compile time (0, 1, 2), else -1 (read from A.layout).
+template <int LAY = -1>
+__device__ __forceinline__ int layout_of(const RenderArgs &A) { return LAY >= 0 ? LAY : A.layout; }
+
+template <int LAY = -1>
 __device__ __forceinline__ PatchView patch_view(const RenderArgs &A, const DPatch &P) {
+    const int lay = layout_of<LAY>(A);
     PatchView v;
     v.brick = A.pool + P.off;
     v.nx = P.n[0];
     v.ny = P.n[1];
     v.nz = P.n[2];
-    if (A.micro) {
+    if (lay == 1) {
         v.px = 64 * P.nb[0];
+        v.pxy = v.px * P.nb[1];
+    } else if (lay == 2) {
+        v.px = 128 * P.nb[0];
         v.pxy = v.px * P.nb[1];
     } else {
         v.px = v.nx + 2;
@@ -224,8 +242,9 @@ __device__ __forceinline__ PatchView patch_view(const RenderArgs &A, const DPatc
 
 // Trilinear value of a padded brick at patch-local continuous index q (cell centres at
 // integers; index -1 and n are the ghost layer).  Indices are clamped into the brick.
-template <bool REC>
+template <bool REC, int LAY = -1>
 __device__ __forceinline__ float trilinear(const RenderArgs &A, const PatchView &pv, float qx, float qy, float qz) {
+    const int lay = layout_of<LAY>(A);
     float fx = floorf(qx), fy = floorf(qy), fz = floorf(qz);
     int ix = min(max((int)fx, -1), pv.nx - 1);
     int iy = min(max((int)fy, -1), pv.ny - 1);
@@ -233,40 +252,45 @@ __device__ __forceinline__ float trilinear(const RenderArgs &A, const PatchView 
     fx = qx - (float)ix;
     fy = qy - (float)iy;
     fz = qz - (float)iz;
-    const float *b;
-    int dx, dy, dz;                   // offsets of the +1 neighbour along each axis
-    if (A.micro) {
-        // 4^3 micro-bricks: the +1 neighbour is in the same block unless the index is 3 mod 4
-        const int i = ix + 1, j = iy + 1, k = iz + 1;
-        b = pv.brick + ((k >> 2) * pv.pxy + (j >> 2) * pv.px + (i >> 2) * 64 + (k & 3) * 16 + (j & 3) * 4 + (i & 3));
-        dx = (i & 3) == 3 ? 61 : 1;
-        dy = (j & 3) == 3 ? pv.px - 12 : 4;
-        dz = (k & 3) == 3 ? pv.pxy - 48 : 16;
-    } else {
-        b = pv.brick + (ix + 1) + (iy + 1) * pv.px + (iz + 1) * pv.pxy;
-        dx = 1;
-        dy = pv.px;
-        dz = pv.pxy;
-    }
-    if (REC && A.touch) {   // measurement only: mark the eight cells read
-        uint64_t base = (uint64_t)(b - A.pool);
-        uint64_t offs[8] = {0, (uint64_t)dx, (uint64_t)dy, (uint64_t)(dx + dy), (uint64_t)dz, (uint64_t)(dz + dx),
-                            (uint64_t)(dz + dy), (uint64_t)(dz + dy + dx)};
-        #pragma unroll
-        for (int c = 0; c < 8; c++) {
-            uint64_t e = base + offs[c];
-            atomicOr(&A.touch[e >> 5], 1u << (e & 31));
-        }
-    }
-    // linear layout: each x pair is one 8-byte row load (the packer pads the pool on both ends)
     typedef float f2u __attribute__((ext_vector_type(2), aligned(4)));
     float v000, v100, v010, v110, v001, v101, v011, v111;
-    if (!A.micro) {
-        const f2u r00 = *(const f2u *)b, r10 = *(const f2u *)(b + dy), r01 = *(const f2u *)(b + dz), r11 = *(const f2u *)(b + dz + dy);
-        v000 = r00.x; v100 = r00.y; v010 = r10.x; v110 = r10.y; v001 = r01.x; v101 = r01.y; v011 = r11.x; v111 = r11.y;
-    } else {
+    if (lay == 1) {
+        // 4^3 micro-bricks: the +1 neighbour is in the same block unless the index is 3 mod 4
+        const int i = ix + 1, j = iy + 1, k = iz + 1;
+        const float *b = pv.brick + ((k >> 2) * pv.pxy + (j >> 2) * pv.px + (i >> 2) * 64 + (k & 3) * 16 + (j & 3) * 4 + (i & 3));
+        const int dx = (i & 3) == 3 ? 61 : 1;
+        const int dy = (j & 3) == 3 ? pv.px - 12 : 4;
+        const int dz = (k & 3) == 3 ? pv.pxy - 48 : 16;
+        if (REC && A.touch) {   // measurement only: mark the eight cells read
+            const uint64_t base = (uint64_t)(b - A.pool);
+            const uint64_t offs[8] = {0, (uint64_t)dx, (uint64_t)dy, (uint64_t)(dx + dy), (uint64_t)dz, (uint64_t)(dz + dx),
+                                      (uint64_t)(dz + dy), (uint64_t)(dz + dy + dx)};
+            #pragma unroll
+            for (int c = 0; c < 8; c++) atomicOr(&A.touch[(base + offs[c]) >> 5], 1u << ((base + offs[c]) & 31));
+        }
         v000 = b[0]; v100 = b[dx]; v010 = b[dy]; v110 = b[dy + dx];
         v001 = b[dz]; v101 = b[dz + dx]; v011 = b[dz + dy]; v111 = b[dz + dy + dx];
+    } else {
+        // linear and halo-row layouts: each x pair is one 8-byte row load (the packer pads the
+        // pool on both ends; a halo row always holds the pair)
+        const float *r[2][2];
+        if (lay == 2) {
+            const float *bx0 = pv.brick + halo_x(ix + 1, (ix + 1) >> 2);
+            const int y0 = halo_y(pv, iy + 1), y1 = halo_y(pv, iy + 2), z0 = halo_z(pv, iz + 1), z1 = halo_z(pv, iz + 2);
+            r[0][0] = bx0 + y0 + z0; r[1][0] = bx0 + y1 + z0; r[0][1] = bx0 + y0 + z1; r[1][1] = bx0 + y1 + z1;
+        } else {
+            const float *b = pv.brick + (ix + 1) + (iy + 1) * pv.px + (iz + 1) * pv.pxy;
+            r[0][0] = b; r[1][0] = b + pv.px; r[0][1] = b + pv.pxy; r[1][1] = b + pv.pxy + pv.px;
+        }
+        if (REC && A.touch) {
+            #pragma unroll
+            for (int c = 0; c < 8; c++) {
+                const uint64_t e = (uint64_t)(r[(c >> 1) & 1][(c >> 2) & 1] + (c & 1) - A.pool);
+                atomicOr(&A.touch[e >> 5], 1u << (e & 31));
+            }
+        }
+        const f2u r00 = *(const f2u *)r[0][0], r10 = *(const f2u *)r[1][0], r01 = *(const f2u *)r[0][1], r11 = *(const f2u *)r[1][1];
+        v000 = r00.x; v100 = r00.y; v010 = r10.x; v110 = r10.y; v001 = r01.x; v101 = r01.y; v011 = r11.x; v111 = r11.y;
     }
     float c00 = lerpf(v000, v100, fx), c10 = lerpf(v010, v110, fx);
     float c01 = lerpf(v001, v101, fx), c11 = lerpf(v011, v111, fx);
@@ -280,9 +304,10 @@ __device__ __forceinline__ float trilinear(const RenderArgs &A, const PatchView 
 // The centre must lie in the brick's interior (patch-local index range [-0.5, n - 0.5]); a tap
 // is exact when it also lies there, and the arm reads of a tap that does not are clamped into
 // the brick (the caller replaces that tap's value).
-template <bool REC>
+template <bool REC, int LAY = -1>
 __device__ __forceinline__ float trilinear_taps(const RenderArgs &A, const PatchView &pv, float qx, float qy,
                                                 float qz, float Fp[3], float Fm[3]) {
+    const int lay = layout_of<LAY>(A);
     float fx = floorf(qx), fy = floorf(qy), fz = floorf(qz);
     const int ix = min(max((int)fx, -1), pv.nx - 1);
     const int iy = min(max((int)fy, -1), pv.ny - 1);
@@ -292,15 +317,20 @@ __device__ __forceinline__ float trilinear_taps(const RenderArgs &A, const Patch
     fz = qz - (float)iz;
     // padded index ix + d holds cell ix - 1 + d; the arms (d = 0, 3) are clamped to [0, n + 1]
     int xo[4], yo[4], zo[4];
+    const int hbx = (ix + 1) >> 2;        // halo rows: the block column of the first core cell
     #pragma unroll
     for (int d = 0; d < 4; d++) {
         const int i = d == 0 ? max(ix, 0) : (d == 3 ? min(ix + 3, pv.nx + 1) : ix + d);
         const int j = d == 0 ? max(iy, 0) : (d == 3 ? min(iy + 3, pv.ny + 1) : iy + d);
         const int k = d == 0 ? max(iz, 0) : (d == 3 ? min(iz + 3, pv.nz + 1) : iz + d);
-        if (A.micro) {
+        if (lay == 1) {
             xo[d] = (i >> 2) * 64 + (i & 3);
             yo[d] = (j >> 2) * pv.px + (j & 3) * 4;
             zo[d] = (k >> 2) * pv.pxy + (k & 3) * 16;
+        } else if (lay == 2) {
+            xo[d] = halo_x(ix + d, hbx);
+            yo[d] = halo_y(pv, j);
+            zo[d] = halo_z(pv, k);
         } else {
             xo[d] = i;
             yo[d] = j * pv.px;
@@ -310,14 +340,16 @@ __device__ __forceinline__ float trilinear_taps(const RenderArgs &A, const Patch
     const float *b = pv.brick;
     // c[x][y][z] for the core (indices 1, 2 on every axis) and the arms (0 or 3 on one axis)
     float core[2][2][2], ax[2][2][2], ay[2][2][2], az[2][2][2];
-    if (!A.micro) {
-        // linear layout: the four x cells of a core row are one 16-byte load and each arm row
-        // pair one 8-byte load (12 loads instead of 32).  A row load may touch the float before
-        // or after the brick row (the arms of a tap that leaves the brick, replaced later); the
-        // packer pads the pool by 64 floats on both ends so such reads stay in the allocation.
+    if (lay != 1) {
+        // linear and halo-row layouts: the four x cells of a core row are one 16-byte load and
+        // each arm row pair one 8-byte load (12 loads instead of 32).  In the linear layout a
+        // row load may touch the float before or after the brick row (the arms of a tap that
+        // leaves the brick, replaced later); the packer pads the pool by 64 floats on both ends
+        // so such reads stay in the allocation.  A halo row holds all four.
         typedef float f4u __attribute__((ext_vector_type(4), aligned(4)));
         typedef float f2u __attribute__((ext_vector_type(2), aligned(4)));
-        const float *row0 = b + ix;          // padded x index ix holds cell ix - 1
+        // padded x index ix (holding cell ix - 1), unclamped
+        const float *row0 = b + (lay == 2 ? halo_x(ix, hbx) : ix);
         #pragma unroll
         for (int v = 0; v < 2; v++)
             #pragma unroll
@@ -390,7 +422,7 @@ __device__ __forceinline__ float trilinear_taps(const RenderArgs &A, const Patch
 
 // Brick and patch-local position of world point x located in the tree; false where no patch
 // holds data or x is outside B (closed).
-template <bool REC>
+template <bool REC, int LAY = -1>
 __device__ __forceinline__ bool locate_brick(const RenderArgs &A, const double x[3], PatchView &pv, float q[3],
                                              Counters &cnt, uint32_t start = 0) {
 #pragma clang fp contract(off)
@@ -403,7 +435,7 @@ __device__ __forceinline__ bool locate_brick(const RenderArgs &A, const double x
     int p = A.leaves[leaf].patch;
     if (p < 0) return false;
     const DPatch &P = A.patches[p];
-    pv = patch_view(A, P);
+    pv = patch_view<LAY>(A, P);
     #pragma unroll
     for (int a = 0; a < 3; a++) q[a] = (float)((x[a] - P.lo[a]) * P.inv_h[a] - 0.5);
     return true;
@@ -411,7 +443,7 @@ __device__ __forceinline__ bool locate_brick(const RenderArgs &A, const double x
 
 // Field value at world point x located in the tree; false where no patch holds data or x is
 // outside B (closed).
-template <bool REC>
+template <bool REC, int LAY = -1>
 __device__ __forceinline__ bool field_at(const RenderArgs &A, const double x[3], float *val, Counters &cnt,
                                          uint32_t start = 0) {
 #pragma clang fp contract(off)
@@ -424,11 +456,11 @@ __device__ __forceinline__ bool field_at(const RenderArgs &A, const double x[3],
     int p = A.leaves[leaf].patch;
     if (p < 0) return false;
     const DPatch &P = A.patches[p];
-    PatchView pv = patch_view(A, P);
+    PatchView pv = patch_view<LAY>(A, P);
     float q[3];
     #pragma unroll
     for (int a = 0; a < 3; a++) q[a] = (float)((x[a] - P.lo[a]) * P.inv_h[a] - 0.5);
-    *val = trilinear<REC>(A, pv, q[0], q[1], q[2]);
+    *val = trilinear<REC, LAY>(A, pv, q[0], q[1], q[2]);
     return true;
 }
 
@@ -448,7 +480,7 @@ struct Segment {
     int leaf, patch, n;
 };
 
-template <bool LIT>
+template <bool LIT, int LAY = -1>
 __device__ __forceinline__ void setup_segment(const RenderArgs &A, const Ray &R, const DLeaf &L, int leaf, double ta,
                                               double tb, Segment &S) {
     const DPatch &P = A.patches[L.patch];
@@ -461,7 +493,7 @@ __device__ __forceinline__ void setup_segment(const RenderArgs &A, const Ray &R,
         S.delta = (tb - ta) / (double)S.n;
     }
     S.ta = ta;
-    S.pv = patch_view(A, P);
+    S.pv = patch_view<LAY>(A, P);
     #pragma unroll
     for (int a = 0; a < 3; a++) {
         S.q0[a] = (float)(((R.o[a] - P.lo[a]) + ta * R.d[a]) * P.inv_h[a] - 0.5);
@@ -554,22 +586,25 @@ __device__ __forceinline__ int classify_tap_fp64(const RenderArgs &A, const Segm
 }
 
 // Value of patch p at world point x (x known to lie in p's data region).
-template <bool REC>
+template <bool REC, int LAY = -1>
 __device__ __forceinline__ float patch_value_at(const RenderArgs &A, int p, const double x[3]) {
     const DPatch &P = A.patches[p];
-    PatchView pv = patch_view(A, P);
+    PatchView pv = patch_view<LAY>(A, P);
     float q[3];
     #pragma unroll
     for (int a = 0; a < 3; a++) q[a] = (float)((x[a] - P.lo[a]) * P.inv_h[a] - 0.5);
-    return trilinear<REC>(A, pv, q[0], q[1], q[2]);
+    return trilinear<REC, LAY>(A, pv, q[0], q[1], q[2]);
 }
 
 // Interior cell (i, j, k) of a padded brick (0 <= index < n).
+template <int LAY = -1>
 __device__ __forceinline__ float brick_cell(const RenderArgs &A, const PatchView &pv, int i, int j, int k) {
+    const int lay = layout_of<LAY>(A);
     i++;
     j++;
     k++;
-    if (A.micro) return pv.brick[(k >> 2) * pv.pxy + (j >> 2) * pv.px + (i >> 2) * 64 + (k & 3) * 16 + (j & 3) * 4 + (i & 3)];
+    if (lay == 1) return pv.brick[(k >> 2) * pv.pxy + (j >> 2) * pv.px + (i >> 2) * 64 + (k & 3) * 16 + (j & 3) * 4 + (i & 3)];
+    if (lay == 2) return pv.brick[halo_x(i, i >> 2) + halo_y(pv, j) + halo_z(pv, k)];
     return pv.brick[i + j * pv.px + k * pv.pxy];
 }
 
@@ -583,7 +618,7 @@ __device__ __forceinline__ int cell_index(double x, double lo, double h, int n) 
 
 // Nearest-cell value of world point x located in the tree; false where no patch holds data or
 // x is outside B (closed).
-template <bool REC>
+template <bool REC, int LAY = -1>
 __device__ __forceinline__ bool nearest_at(const RenderArgs &A, const double x[3], float *val, Counters &cnt) {
     #pragma unroll
     for (int a = 0; a < 3; a++)
@@ -594,8 +629,8 @@ __device__ __forceinline__ bool nearest_at(const RenderArgs &A, const double x[3
     const int p = A.leaves[leaf].patch;
     if (p < 0) return false;
     const DPatch &P = A.patches[p];
-    const PatchView pv = patch_view(A, P);
-    *val = brick_cell(A, pv, cell_index(x[0], P.lo[0], P.h[0], P.n[0]), cell_index(x[1], P.lo[1], P.h[1], P.n[1]),
+    const PatchView pv = patch_view<LAY>(A, P);
+    *val = brick_cell<LAY>(A, pv, cell_index(x[0], P.lo[0], P.h[0], P.n[0]), cell_index(x[1], P.lo[1], P.h[1], P.n[1]),
                       cell_index(x[2], P.lo[2], P.h[2], P.n[2]));
     return true;
 }
@@ -605,7 +640,7 @@ __device__ __forceinline__ bool nearest_at(const RenderArgs &A, const double x[3
 // the classification margin away from every cell face, else from the FP64 position exactly as
 // defined; taps x +- h^l e_a step one cell in the same brick when they stay in it, else they
 // are located in the tree from their FP64 position.
-template <bool LIT, bool REC>
+template <bool LIT, bool REC, int LAY = -1>
 __device__ __forceinline__ float nearest_sample(const RenderArgs &A, const Ray &R, const Segment &S, int k, float qx,
                                                 float qy, float qz, float gv[3], Counters &cnt) {
     const float qc[3] = {qx, qy, qz};
@@ -632,7 +667,7 @@ __device__ __forceinline__ float nearest_sample(const RenderArgs &A, const Ray &
     ci[0] = min(max(ci[0], 0), S.pv.nx - 1);
     ci[1] = min(max(ci[1], 0), S.pv.ny - 1);
     ci[2] = min(max(ci[2], 0), S.pv.nz - 1);
-    const float F = brick_cell(A, S.pv, ci[0], ci[1], ci[2]);
+    const float F = brick_cell<LAY>(A, S.pv, ci[0], ci[1], ci[2]);
     if (LIT) {
         float Fs[6];
         uint32_t okbits = 0x3fu;
@@ -648,7 +683,7 @@ __device__ __forceinline__ float nearest_sample(const RenderArgs &A, const Ray &
                 cj[0] = min(max(cj[0], 0), S.pv.nx - 1);
                 cj[1] = min(max(cj[1], 0), S.pv.ny - 1);
                 cj[2] = min(max(cj[2], 0), S.pv.nz - 1);
-                Fs[t] = brick_cell(A, S.pv, cj[0], cj[1], cj[2]);
+                Fs[t] = brick_cell<LAY>(A, S.pv, cj[0], cj[1], cj[2]);
             } else {
                 double xt[3] = {x[0], x[1], x[2]};
                 {
@@ -656,7 +691,7 @@ __device__ __forceinline__ float nearest_sample(const RenderArgs &A, const Ray &
                     xt[a] = sgn ? x[a] - P.h[a] : x[a] + P.h[a];
                 }
                 float val = 0.f;
-                if (!nearest_at<REC>(A, xt, &val, cnt)) okbits &= ~(1u << t);
+                if (!nearest_at<REC, LAY>(A, xt, &val, cnt)) okbits &= ~(1u << t);
                 Fs[t] = val;
             }
         }
@@ -676,14 +711,14 @@ __device__ __forceinline__ float nearest_sample(const RenderArgs &A, const Ray &
 
 // Sample k of a segment: value, LUT classification, opacity over the step, and (LIT) the
 // gradient shading with taps at x +- h^l e_a located in the tree.
-template <bool LIT, bool REC, bool NEAR = false>
+template <bool LIT, bool REC, bool NEAR = false, int LAY = -1>
 __device__ __forceinline__ void eval_sample(const RenderArgs &A, const float4 *s_lut, const Ray &R, const Segment &S,
                                             int k, SampleVals &v, Counters &cnt) {
     const float kk = (float)k + 0.5f;
     const float qx = S.q0[0] + kk * S.dq[0], qy = S.q0[1] + kk * S.dq[1], qz = S.q0[2] + kk * S.dq[2];
     float F;
     if (NEAR) {
-        F = nearest_sample<LIT, REC>(A, R, S, k, qx, qy, qz, v.gv, cnt);
+        F = nearest_sample<LIT, REC, LAY>(A, R, S, k, qx, qy, qz, v.gv, cnt);
     } else if (LIT) {
         // value and the six taps x +- h^l e_a from this brick in one fused stencil; a tap that
         // leaves the brick (classified in fp32, else FP64) is then read where it lands
@@ -702,7 +737,7 @@ __device__ __forceinline__ void eval_sample(const RenderArgs &A, const float4 *s
                 }
         }
         float Fp[3], Fm[3];
-        F = trilinear_taps<REC>(A, S.pv, qx, qy, qz, Fp, Fm);
+        F = trilinear_taps<REC, LAY>(A, S.pv, qx, qy, qz, Fp, Fm);
         uint32_t okbits = 0x3fu;          // bit t: tap t holds data
         if (clsbits) {
             if (REC) cnt.split++;
@@ -768,13 +803,13 @@ __device__ __forceinline__ void eval_sample(const RenderArgs &A, const float4 *s
                         // descend from the rope node holding the slab, else from the root (a
                         // slab beyond B fails the box test there, except on B's closed upper faces)
                         float qq[3];
-                        ok = locate_brick<REC>(A, xt, pv, qq, cnt, c == kTapFace && X.rope > 0 ? (uint32_t)X.rope : 0u);
+                        ok = locate_brick<REC, LAY>(A, xt, pv, qq, cnt, c == kTapFace && X.rope > 0 ? (uint32_t)X.rope : 0u);
                         q0 = qq[0];
                         q1 = qq[1];
                         q2 = qq[2];
                     }
                 }
-                const float Fs = ok ? trilinear<REC>(A, pv, q0, q1, q2) : 0.f;
+                const float Fs = ok ? trilinear<REC, LAY>(A, pv, q0, q1, q2) : 0.f;
                 if (!ok) okbits &= ~(1u << t);
                 // write the tap back (selects keep the arrays in registers)
                 #pragma unroll
@@ -795,7 +830,7 @@ __device__ __forceinline__ void eval_sample(const RenderArgs &A, const float4 *s
             v.gv[a] = gr;
         }
     } else {
-        F = trilinear<REC>(A, S.pv, qx, qy, qz);
+        F = trilinear<REC, LAY>(A, S.pv, qx, qy, qz);
     }
     v.F = F;
     const float u = __saturatef((F - A.v_lo) * A.inv_range);
@@ -918,7 +953,8 @@ inline int fill_args(const amr_scene *S, const amr_camera *C, const amr_render_p
     if (P->lighting < 0 || P->lighting > 2) { set_error("lighting must be 0, 1 (gradient) or 2 (point light)"); return AMR_EINVAL; }
     A->lighting = P->lighting;
     for (int a = 0; a < 3; a++) A->plight[a] = (double)P->light[a];
-    A->micro = S->brick_layout;
+    if (S->brick_layout < 0 || S->brick_layout > 2) { set_error("unknown brick layout"); return AMR_EINVAL; }
+    A->layout = S->brick_layout;
     A->tiles_x = (C->width + 15) / 16;
     A->tiles_y = (C->height + 15) / 16;
     A->nblocks = A->tiles_x * A->tiles_y;

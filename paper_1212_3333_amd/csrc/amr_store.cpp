@@ -181,9 +181,7 @@ int amr_store_create(const amr_tree *tree, const amr_patch *patches, int32_t npa
         s->plevel.resize(npatches);
         s->pbox.resize(6 * (size_t)npatches);
         for (int p = 0; p < npatches; p++) {
-            const int64_t cells = s->layout == 0 ? (int64_t)(P[p].n[0] + 2) * (P[p].n[1] + 2) * (P[p].n[2] + 2)
-                                                 : (int64_t)P[p].nb[0] * P[p].nb[1] * P[p].nb[2] * 64;
-            s->bsz[p] = align64(cells);
+            s->bsz[p] = align64(brick_floats(s->layout, P[p].n, P[p].nb));
             s->plevel[p] = patches[p].level;
             int64_t S = 1;
             for (int k = 0; k < s->lmax - patches[p].level; k++) S *= s->refine;

@@ -48,7 +48,7 @@ def _compare_traces(amr, gout, ores, nrays_expect=None):
     return int(ok.sum())
 
 
-@pytest.mark.parametrize("layout", [0, 1])
+@pytest.mark.parametrize("layout", [0, 1, 2])
 @pytest.mark.parametrize("lit", [False, True])
 @pytest.mark.parametrize("uniform", [False, True])
 @pytest.mark.parametrize("cam_idx", [0, 1])

@@ -69,7 +69,7 @@ def _compare_traces(amr, gout, ores):
         assert np.array_equal(a["ta"], b["ta"]) and np.array_equal(a["tb"], b["tb"]), q
 
 
-@pytest.mark.parametrize("layout", [0, 1])
+@pytest.mark.parametrize("layout", [0, 1, 2])
 @pytest.mark.parametrize("lit", [False, True])
 @pytest.mark.parametrize("name", ["tiny", "lod", "vertex", "rand0", "rand1m", "rand3"])
 def test_resident_subsets_vs_oracle(gpu, name, lit, layout):

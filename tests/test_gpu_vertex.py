@@ -64,11 +64,11 @@ def _compare_traces(amr, gout, ores):
         assert np.array_equal(a["ta"], b["ta"]) and np.array_equal(a["tb"], b["tb"]), q
 
 
-@pytest.mark.parametrize("layout", [0, 1])
+@pytest.mark.parametrize("layout", [0, 1, 2])
 @pytest.mark.parametrize("lit", [False, True])
 @pytest.mark.parametrize("name", ["tiny", "lod", "aligned0", "aligned5", "rand1", "rand2m", "rand3"])
 def test_vertex_vs_oracle(gpu, name, lit, layout):
-    """Full images (ragged tiles) and segment traces against the oracle, both brick layouts."""
+    """Full images (ragged tiles) and segment traces against the oracle, all three brick layouts."""
     amr = gpu
     h = _hier(name)
     lut = workloads.lut_bumps(np.random.default_rng(len(name)), sigma_scale=10.0)

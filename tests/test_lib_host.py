@@ -72,7 +72,7 @@ def test_builder_shuffle_invariance():
 def _compare_ghosts(h):
     tree = amr.build_tree(h)
     O = Oracle(h)
-    for layout in (0, 1):
+    for layout in (0, 1, 2):
         scene = amr.pack(tree, h, host=True, nthreads=3, brick_layout=layout)
         for p in range(len(h.patches)):
             got = scene.brick(p)
@@ -295,7 +295,7 @@ def test_face_tap_records(seed):
     names the owner's brick; the other faces carry the rope node of the face table."""
     h = workloads.random_tiny(seed, multi_root=(seed == 1)) if seed < 2 else workloads.tiny_samr(0)
     tree = amr.build_tree(h)
-    for layout in (0, 1):
+    for layout in (0, 1, 2):
         scene = amr.pack(tree, h, host=True, brick_layout=layout)
         own = scene.leaf_face_owners()
         rec = scene.face_tap_records()
@@ -313,8 +313,9 @@ def test_face_tap_records(seed):
                     continue
                 mapped += 1
                 assert X["off"] == ph["off"][o] and np.array_equal(X["n"], ph["n"][o])
-                if layout == 1:
-                    assert X["px"] == 64 * ph["nb"][o][0] and X["pxy"] == X["px"] * ph["nb"][o][1]
+                if layout in (1, 2):
+                    w = 64 if layout == 1 else 128
+                    assert X["px"] == w * ph["nb"][o][0] and X["pxy"] == X["px"] * ph["nb"][o][1]
                 else:
                     assert X["px"] == ph["n"][o][0] + 2 and X["pxy"] == X["px"] * (ph["n"][o][1] + 2)
                 a, side = f // 2, f % 2
@@ -356,7 +357,7 @@ def test_vertex_bricks_match_oracle(name):
     h = _vertex_h(name)
     tree = amr.build_tree(h)
     O = Oracle(h)
-    for layout in (0, 1):
+    for layout in (0, 1, 2):
         scene = amr.pack(tree, h, host=True, nthreads=3, brick_layout=layout)
         assert scene.scene.centering == 1
         ph = scene.patch_headers()
@@ -395,3 +396,26 @@ def test_vertex_sample_shape_checked():
     lib = amr.load()
     assert lib.amr_pack_pool(tree.ptr, tree._patches, len(h.patches), ctypes.byref(opts), None, ctypes.byref(pb),
                              None, ctypes.byref(mb), None, None) == L.AMR_EINVAL
+
+
+@pytest.mark.parametrize("name", ["tiny", "vertex"])
+def test_halo_rows_layout(name):
+    """Halo-row layout: row (j, k) of block column bx holds padded x indices 4 bx - 1 .. 4 bx + 6
+    of the padded brick (zero beyond it), so every row also carries its neighbours' edge cells."""
+    h = workloads.tiny_samr(1)
+    if name == "vertex":
+        h = h.with_vertex_field(workloads.gaussian_sum_field(np.random.default_rng(2)))
+    tree = amr.build_tree(h)
+    lin = amr.pack(tree, h, host=True, brick_layout=0)
+    halo = amr.pack(tree, h, host=True, brick_layout=2)
+    for p in range(len(h.patches)):
+        ref = lin.brick(p)
+        assert np.array_equal(halo.brick(p), ref)
+        rows = halo.halo_rows(p)
+        nbz, nby, nbx = rows.shape[:3]
+        P = ref.shape
+        padded = np.zeros((4 * nbz, 4 * nby, 4 * nbx + 8), np.float32)
+        padded[:P[0], :P[1], 1:P[2] + 1] = ref          # x shifted by one: index -1 -> column 0
+        for bx in range(nbx):
+            want = padded[:, :, 4 * bx:4 * bx + 8].reshape(nbz, 4, nby, 4, 8).transpose(0, 2, 1, 3, 4)
+            assert np.array_equal(rows[:, :, bx], want), (p, bx)
