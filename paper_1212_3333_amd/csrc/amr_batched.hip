@@ -144,9 +144,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void r
         bool alive = valid && setup_ray(A, pi, pj, R);
         if (REC) cnt.hit += alive ? 1 : 0;
         double tcur = R.t0;
+        uint32_t start = 0;
         while (alive && tcur < R.t1) {
             double tb = R.t1;
-            int leaf = descend(A, R, tcur, tb);
+            int leaf = descend(A, R, tcur, tb, start);
             if (leaf < 0) break;
             if (REC) cnt.segments++;
             const DLeaf &L = A.leaves[leaf];

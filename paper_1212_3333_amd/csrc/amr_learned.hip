@@ -170,6 +170,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(LIT ? 2 : 4
     bool alive = valid && setup_ray(A, pi, pj, R);
     cnt.hit = alive ? 1 : 0;
     double tcur = R.t0;
+    uint32_t start = 0;
     SeglogHeader *lh = reinterpret_cast<SeglogHeader *>(G.seglog);
     amr_seglog_rec *lrec = reinterpret_cast<amr_seglog_rec *>(G.seglog + sizeof(SeglogHeader));
     const float inv_lmax = 1.f / (float)(G.lmax > 0 ? G.lmax : 1);
@@ -185,7 +186,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(LIT ? 2 : 4
         float a_use = 1.f;                // upper bound charged to the skip budget
         float len = 0.f, umin = 0.f, umax = 0.f, smin = 0.f, smax = 0.f, smean = 0.f;
         if (active) {
-            leaf = descend(A, R, tcur, tb);
+            leaf = descend(A, R, tcur, tb, start);
             if (leaf < 0) {
                 alive = false;
             } else {

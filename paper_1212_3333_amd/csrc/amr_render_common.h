@@ -140,10 +140,18 @@ __device__ __forceinline__ bool setup_ray(const RenderArgs &A, int i, int j, Ray
     return true;
 }
 
+// kD-restart with push-down: `start` is the deepest node known to hold the rest of the ray.
+// While the descent has not clipped tmax, every decision on the way down was independent of
+// tmin (the split lay outside [tmin, tmax], or behind tmin), so a later restart with a larger
+// tmin and the same tmax takes the same way: the walk can begin at the node reached so far.  The
+// leaves and exits found are exactly those of a restart from the root.  Level-of-detail walks
+// always start at the root (they must see every kind-(a) node on the way).
 template <bool LOD>
-__device__ __forceinline__ int descend_walk(const RenderArgs &A, const Ray &R, double tmin, double &tmax) {
+__device__ __forceinline__ int descend_walk(const RenderArgs &A, const Ray &R, double tmin, double &tmax,
+                                            uint32_t &start) {
 #pragma clang fp contract(off)
-    uint32_t ni = 0;
+    uint32_t ni = LOD ? 0u : start;
+    bool open = !LOD;
     for (int it = 0; it <= A.depth; it++) {
         DNode n = A.nodes[ni];
         uint32_t axis = n.meta & 3u;
@@ -162,22 +170,30 @@ __device__ __forceinline__ int descend_walk(const RenderArgs &A, const Ray &R, d
         uint32_t low = n.child, high = low + 1;
         if (da == 0.0) {
             ni = oa < s ? low : high;
-            continue;
+        } else {
+            bool near_low = (oa < s) || (oa == s && da < 0.0);
+            uint32_t nearc = near_low ? low : high, farc = near_low ? high : low;
+            double ts = (s - oa) * sel3(axis, R.invd[0], R.invd[1], R.invd[2]);
+            if (ts <= 0.0 || ts >= tmax) ni = nearc;
+            else if (ts <= tmin) ni = farc;
+            else { ni = nearc; tmax = ts; open = false; }
         }
-        bool near_low = (oa < s) || (oa == s && da < 0.0);
-        uint32_t nearc = near_low ? low : high, farc = near_low ? high : low;
-        double ts = (s - oa) * sel3(axis, R.invd[0], R.invd[1], R.invd[2]);
-        if (ts <= 0.0 || ts >= tmax) ni = nearc;
-        else if (ts <= tmin) ni = farc;
-        else { ni = nearc; tmax = ts; }
+        if (open) start = ni;
     }
     return -1;
 }
 
-// kD-restart: descend from the root for the ray interval [tmin, tmax]; returns the leaf id
-// and shrinks tmax to the leaf's exit.  Returns -1 if the walk exceeds the tree depth.
+// kD-restart: descend for the ray interval [tmin, tmax] (tmax the ray's exit from the clip box,
+// the same on every call for one ray; `start` 0 before the first call); returns the leaf id and
+// shrinks tmax to the leaf's exit.  Returns -1 if the walk exceeds the tree depth.
+__device__ __forceinline__ int descend(const RenderArgs &A, const Ray &R, double tmin, double &tmax, uint32_t &start) {
+    return A.lod_on ? descend_walk<true>(A, R, tmin, tmax, start) : descend_walk<false>(A, R, tmin, tmax, start);
+}
+
+// The same from the root (no push-down).
 __device__ __forceinline__ int descend(const RenderArgs &A, const Ray &R, double tmin, double &tmax) {
-    return A.lod_on ? descend_walk<true>(A, R, tmin, tmax) : descend_walk<false>(A, R, tmin, tmax);
+    uint32_t start = 0;
+    return descend(A, R, tmin, tmax, start);
 }
 
 // Leaf holding point x (half-open comparisons against the split planes), descending from

@@ -14,6 +14,7 @@
 namespace amr {
 
 // exp(-integral of sigma) from world point x to the light, over the part of the segment in B.
+template <int LAY>
 __device__ __forceinline__ float light_transmittance(const RenderArgs &A, const float4 *s_lut, const double x[3]) {
 #pragma clang fp contract(off)
     double v[3];
@@ -47,17 +48,18 @@ __device__ __forceinline__ float light_transmittance(const RenderArgs &A, const 
     Q.t1 = hi_t;
     float tau = 0.f;                      // sum of sigma delta, in units of ln 2
     double tcur = lo_t;
+    uint32_t start = 0;
     while (tcur < hi_t) {
         double tb = hi_t;
-        const int leaf = descend(A, Q, tcur, tb);
+        const int leaf = descend(A, Q, tcur, tb, start);
         if (leaf < 0) break;
         const DLeaf &L = A.leaves[leaf];
         if (L.patch >= 0) {
             Segment S;
-            setup_segment<false>(A, Q, L, leaf, tcur, tb, S);
+            setup_segment<false, LAY>(A, Q, L, leaf, tcur, tb, S);
             for (int j = 0; j < S.n; j++) {
                 const float kk = (float)j + 0.5f;
-                const float F = trilinear<false>(A, S.pv, S.q0[0] + kk * S.dq[0], S.q0[1] + kk * S.dq[1],
+                const float F = trilinear<false, LAY>(A, S.pv, S.q0[0] + kk * S.dq[0], S.q0[1] + kk * S.dq[1],
                                                  S.q0[2] + kk * S.dq[2]);
                 const float u = __saturatef((F - A.v_lo) * A.inv_range);
                 const float xs = 255.f * u;
@@ -72,7 +74,7 @@ __device__ __forceinline__ float light_transmittance(const RenderArgs &A, const 
     return exp2f(-tau);
 }
 
-template <bool REC>
+template <bool REC, int LAY>
 __global__ __launch_bounds__(64) void render_shadow(RenderArgs A) {
     __shared__ float4 s_lut[256];
     for (int i = threadIdx.x; i < 256; i += 64) s_lut[i] = A.lut[i];
@@ -100,20 +102,21 @@ __global__ __launch_bounds__(64) void render_shadow(RenderArgs A) {
     bool alive = valid && setup_ray(A, pi, pj, R);
     if (REC) cnt.hit = alive ? 1 : 0;
     double tcur = R.t0;
+    uint32_t start = 0;
     while (alive && tcur < R.t1) {
         double tb = R.t1;
-        const int leaf = descend(A, R, tcur, tb);
+        const int leaf = descend(A, R, tcur, tb, start);
         if (leaf < 0) break;
         if (REC) cnt.segments++;
         const DLeaf &L = A.leaves[leaf];
         int nsm = 0;
         if (L.patch >= 0) {
             Segment S;
-            setup_segment<false>(A, R, L, leaf, tcur, tb, S);
+            setup_segment<false, LAY>(A, R, L, leaf, tcur, tb, S);
             nsm = S.n;
             for (int k = 0; k < nsm; k++) {
                 SampleVals v;
-                eval_sample<false, REC>(A, s_lut, R, S, k, v, cnt);
+                eval_sample<false, REC, false, LAY>(A, s_lut, R, S, k, v, cnt);
                 double x[3];
                 {
 #pragma clang fp contract(off)
@@ -121,7 +124,7 @@ __global__ __launch_bounds__(64) void render_shadow(RenderArgs A) {
                     #pragma unroll
                     for (int b = 0; b < 3; b++) x[b] = R.o[b] + tk * R.d[b];
                 }
-                const float shade = A.k_a + A.k_d * light_transmittance(A, s_lut, x);
+                const float shade = A.k_a + A.k_d * light_transmittance<LAY>(A, s_lut, x);
                 const float wgt = T * v.alpha * shade;
                 C0 += wgt * v.r;
                 C1 += wgt * v.g;
@@ -166,8 +169,10 @@ __global__ __launch_bounds__(64) void render_shadow(RenderArgs A) {
 int launch_shadow(const RenderArgs &A, bool rec, void *stream) {
     hipStream_t s = (hipStream_t)stream;
     const int grid = 8 * ((A.sgrid * A.sgrid + 7) / 8) * 16;
-    if (rec) hipLaunchKernelGGL(render_shadow<true>, dim3(grid), dim3(64), 0, s, A);
-    else hipLaunchKernelGGL(render_shadow<false>, dim3(grid), dim3(64), 0, s, A);
+    if (rec) hipLaunchKernelGGL((render_shadow<true, -1>), dim3(grid), dim3(64), 0, s, A);
+    else if (A.layout == 0) hipLaunchKernelGGL((render_shadow<false, 0>), dim3(grid), dim3(64), 0, s, A);
+    else if (A.layout == 1) hipLaunchKernelGGL((render_shadow<false, 1>), dim3(grid), dim3(64), 0, s, A);
+    else hipLaunchKernelGGL((render_shadow<false, 2>), dim3(grid), dim3(64), 0, s, A);
     return check_hip(hipGetLastError(), "render_shadow launch");
 }
 
