@@ -635,11 +635,12 @@ __device__ __forceinline__ int cell_index(double x, double lo, double h, int n) 
 // Nearest-cell value of world point x located in the tree; false where no patch holds data or
 // x is outside B (closed).
 template <bool REC, int LAY = -1>
-__device__ __forceinline__ bool nearest_at(const RenderArgs &A, const double x[3], float *val, Counters &cnt) {
+__device__ __forceinline__ bool nearest_at(const RenderArgs &A, const double x[3], float *val, Counters &cnt,
+                                           uint32_t start = 0) {
     #pragma unroll
     for (int a = 0; a < 3; a++)
         if (x[a] < A.box_lo[a] || x[a] > A.box_hi[a]) return false;
-    const int leaf = locate_leaf(A, x, 0);
+    const int leaf = locate_leaf(A, x, start);
     if (REC) cnt.desc++;
     if (leaf < 0) return false;
     const int p = A.leaves[leaf].patch;
@@ -707,7 +708,46 @@ __device__ __forceinline__ float nearest_sample(const RenderArgs &A, const Ray &
                     xt[a] = sgn ? x[a] - P.h[a] : x[a] + P.h[a];
                 }
                 float val = 0.f;
-                if (!nearest_at<REC, LAY>(A, xt, &val, cnt)) okbits &= ~(1u << t);
+                bool ok = true, done = false;
+                const int c2 = c == kTapUnsure ? classify_tap_fp64(A, S, xt, a, sgn) : c;
+                uint32_t from = 0;
+                if (c2 == kTapSame) {
+                    // the tap lies where the sample's own patch is the finest: its cell, in FP64
+                    val = brick_cell<LAY>(A, S.pv, cell_index(xt[0], P.lo[0], P.h[0], P.n[0]),
+                                          cell_index(xt[1], P.lo[1], P.h[1], P.n[1]), cell_index(xt[2], P.lo[2], P.h[2], P.n[2]));
+                    done = true;
+                } else if (c2 == kTapFace) {
+                    const DFaceXf X = A.face_xf[6 * S.leaf + 2 * a + (sgn ? 0 : 1)];
+                    if (X.n[0] > 0) {
+                        // the slab's single owner: the cell under the mapped position when it is
+                        // clear of the owner's cell faces, else the FP64 location below
+                        const float qo[3] = {qt[0] * X.r + X.t[0], qt[1] * X.r + X.t[1], qt[2] * X.r + X.t[2]};
+                        int co[3];
+                        bool clear = true;
+                        #pragma unroll
+                        for (int b = 0; b < 3; b++) {
+                            const float u = qo[b] + 0.5f, fl = floorf(u), fr = u - fl;
+                            clear = clear && fr >= kTapMargin && fr <= 1.f - kTapMargin;
+                            co[b] = min(max((int)fl, 0), X.n[b] - 1);
+                        }
+                        if (clear) {
+                            PatchView pv;
+                            pv.brick = A.pool + X.off;
+                            pv.px = X.px;
+                            pv.pxy = X.pxy;
+                            pv.nx = X.n[0];
+                            pv.ny = X.n[1];
+                            pv.nz = X.n[2];
+                            val = brick_cell<LAY>(A, pv, co[0], co[1], co[2]);
+                            if (REC) cnt.face++;
+                            done = true;
+                        }
+                    } else if (X.rope > 0) {
+                        from = (uint32_t)X.rope;
+                    }
+                }
+                if (!done) ok = nearest_at<REC, LAY>(A, xt, &val, cnt, from);
+                if (!ok) okbits &= ~(1u << t);
                 Fs[t] = val;
             }
         }
