@@ -105,7 +105,8 @@ __device__ __forceinline__ void set_camera(RenderArgs &A, const amr_camera &C) {
     A.lod_pix = C.ortho ? (2.0 * C.win[1]) / (double)C.height : (2.0 * C.tan_half_fov) / (double)C.height;
 }
 
-template <bool LIT, bool REC>
+// LAY: the brick layout fixed at compile time (-1: read at run time, for the recording variants).
+template <bool LIT, bool REC, int LAY>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void render_batched(BatchArgs B) {
     __shared__ float4 s_lut[256];
     s_lut[threadIdx.x] = B.base.lut[threadIdx.x];
@@ -153,10 +154,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void r
             const DLeaf &L = A.leaves[leaf];
             if (L.patch >= 0) {
                 Segment S;
-                setup_segment<LIT>(A, R, L, leaf, tcur, tb, S);
+                setup_segment<LIT, LAY>(A, R, L, leaf, tcur, tb, S);
                 for (int k2 = 0; k2 < S.n; k2++) {
                     SampleVals v;
-                    eval_sample<LIT, REC>(A, s_lut, R, S, k2, v, cnt);
+                    eval_sample<LIT, REC, false, LAY>(A, s_lut, R, S, k2, v, cnt);
                     float wgt = T * v.alpha * v.shade;
                     C0 += wgt * v.r;
                     C1 += wgt * v.g;
@@ -237,11 +238,15 @@ int launch_persistent(const amr_scene *S, const amr_camera *cams, int32_t ncams,
     dim3 grid(device_cus() * bpc);
     const bool rec = d_stats != nullptr;
     if (B.base.lighting) {
-        if (rec) hipLaunchKernelGGL((render_batched<true, true>), grid, dim3(256), 0, s, B);
-        else hipLaunchKernelGGL((render_batched<true, false>), grid, dim3(256), 0, s, B);
+        if (rec) hipLaunchKernelGGL((render_batched<true, true, -1>), grid, dim3(256), 0, s, B);
+        else if (B.base.layout == 0) hipLaunchKernelGGL((render_batched<true, false, 0>), grid, dim3(256), 0, s, B);
+        else if (B.base.layout == 1) hipLaunchKernelGGL((render_batched<true, false, 1>), grid, dim3(256), 0, s, B);
+        else hipLaunchKernelGGL((render_batched<true, false, 2>), grid, dim3(256), 0, s, B);
     } else {
-        if (rec) hipLaunchKernelGGL((render_batched<false, true>), grid, dim3(256), 0, s, B);
-        else hipLaunchKernelGGL((render_batched<false, false>), grid, dim3(256), 0, s, B);
+        if (rec) hipLaunchKernelGGL((render_batched<false, true, -1>), grid, dim3(256), 0, s, B);
+        else if (B.base.layout == 0) hipLaunchKernelGGL((render_batched<false, false, 0>), grid, dim3(256), 0, s, B);
+        else if (B.base.layout == 1) hipLaunchKernelGGL((render_batched<false, false, 1>), grid, dim3(256), 0, s, B);
+        else hipLaunchKernelGGL((render_batched<false, false, 2>), grid, dim3(256), 0, s, B);
     }
     return check_hip(hipGetLastError(), "render_batched launch");
 }
