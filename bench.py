@@ -61,6 +61,17 @@ def committed_traffic():
     except (KeyError, ValueError):
         return None
 METRIC = "samples/s + Mrays/s at 1024², plain vs learned-skip at ≤1e-3 RGBA error"
+# The paper's own measurements (its results table and Section 6), on other hardware and data:
+# context for the numbers above, not a baseline of the same workload.
+PAPER_CONTEXT = {
+    "hardware": "NVIDIA GeForce GTX 680 (2 GB), OpenGL/GLSL fragment shaders, Xeon E5520 host",
+    "view": "1000x1000, emission-absorption, no early ray termination",
+    "datasets": "three Enzo AMR snapshots: 2,666 / 18,528 / 39,061 grids; 19 M / 33 M / 140 M cells",
+    "packing_fps": [3.2, 1.6, 1.2],
+    "packing_mrays_per_s_at_most": [3.2, 1.6, 1.2],
+    "gradient_shaded_isosurface_fps_dataset3": 0.8,
+    "point_light_secondary_rays_fps_dataset3": 0.1,
+}
 
 
 def log(*a):
@@ -219,10 +230,10 @@ def workloads_orbit(cam, k, frames):
 
 
 def learned_skip_section(amr, dev, steps, warmup):
-    """Deep-range hierarchy (20 levels) at 1024^2: plain traversal vs learned segment proposals.
-    The network is trained on the GPU from segments logged by the plain kernel on 16 views and
-    its thresholds calibrated on 6 held-out views (worst RGBA error <= 0.5e-3 there); the timed
-    view is the full-domain one."""
+    """Deep-range hierarchy (20 levels) at 1024^2 (and 2048^2, the hierarchy's own view size):
+    plain traversal vs learned segment proposals.  The network is trained on the GPU from
+    segments logged by the plain kernel on 16 views and its thresholds calibrated on 6 held-out
+    views (worst RGBA error <= 0.5e-3 there); the timed view is the full-domain one."""
     import torch
     import workloads
     from paper_1212_3333_amd import learned
@@ -244,28 +255,33 @@ def learned_skip_section(amr, dev, steps, warmup):
     train_s = time.time() - t
     cam = cams[0]
     W_, H_ = cam["width"], cam["height"]
-    out = torch.empty(W_ * H_ * 4, dtype=torch.float32, device=dev)
-    p_stats = amr.stats_dict(amr.render(scene, cam, lut_t, prm, stats=True))
-    l_res = learned.render_learned(scene, cam, lut_t, prm, net.packed, te, ts, stats=True)
-    l_stats = amr.stats_dict(l_res)
-    plain_img = amr.render(scene, cam, lut_t, prm)["rgba"]
-    err = float((l_res["rgba"] - plain_img).abs().max().item())
-    ms_p = time_frames(amr, scene, cam, lut_t, prm, steps, warmup, out)
-    prm_l = dict(prm, tau_e=te, tau_s=ts)
 
-    def run_l():
-        amr.render(scene, cam, lut_t, prm_l, out=out, d_mlp=net.packed)
-    for _ in range(warmup):
-        run_l()
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(steps):
-        run_l()
-    e1.record()
-    torch.cuda.synchronize()
-    ms_l = e0.elapsed_time(e1) / steps
-    log("learned skip: plain %.3f ms, learned %.3f ms, err %.2e, tau_e %g tau_s %g" % (ms_p, ms_l, err, te, ts))
+    def compare(c):
+        """Plain and learned frames of camera c: times, stats and the learned image's error."""
+        out = torch.empty(c["width"] * c["height"] * 4, dtype=torch.float32, device=dev)
+        p_stats = amr.stats_dict(amr.render(scene, c, lut_t, prm, stats=True))
+        l_res = learned.render_learned(scene, c, lut_t, prm, net.packed, te, ts, stats=True)
+        l_stats = amr.stats_dict(l_res)
+        plain_img = amr.render(scene, c, lut_t, prm)["rgba"]
+        err = float((l_res["rgba"] - plain_img).abs().max().item())
+        del l_res, plain_img
+        ms_p = time_frames(amr, scene, c, lut_t, prm, steps, warmup, out)
+        prm_l = dict(prm, tau_e=te, tau_s=ts)
+        for _ in range(warmup):
+            amr.render(scene, c, lut_t, prm_l, out=out, d_mlp=net.packed)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            amr.render(scene, c, lut_t, prm_l, out=out, d_mlp=net.packed)
+        e1.record()
+        torch.cuda.synchronize()
+        return ms_p, e0.elapsed_time(e1) / steps, p_stats, l_stats, err
+
+    ms_p, ms_l, p_stats, l_stats, err = compare(cam)
+    ms_p2, ms_l2, p_stats2, l_stats2, err2 = compare(dict(cam, width=2048, height=2048))
+    log("learned skip: plain %.3f ms, learned %.3f ms, err %.2e, tau_e %g tau_s %g; 2048^2: %.3f / %.3f ms, err %.2e"
+        % (ms_p, ms_l, err, te, ts, ms_p2, ms_l2, err2))
     return {
         "workload": "deep-range SAMR: root 64^3, 20 levels, r=2, %d patches around 3 power-law cores; 1024x1024 "
                     "full-domain view, unlit" % len(h.patches),
@@ -280,6 +296,11 @@ def learned_skip_section(amr, dev, steps, warmup):
         "net_segments": l_stats["net_segments"], "segments": l_stats["segments"],
         "plain_samples": p_stats["samples"], "learned_samples": l_stats["samples"],
         "train_segments": int(X.shape[0]), "train_calibrate_s": round(train_s, 2), "prepare_s": round(prep, 2),
+        "at_2048": {"plain_ms": round(ms_p2, 4), "learned_ms": round(ms_l2, 4), "speedup": round(ms_p2 / ms_l2, 3),
+                    "plain_mrays_per_s": round(2048 * 2048 / (ms_p2 * 1e-3) / 1e6, 3),
+                    "learned_mrays_per_s": round(2048 * 2048 / (ms_l2 * 1e-3) / 1e6, 3),
+                    "plain_samples": p_stats2["samples"], "learned_samples": l_stats2["samples"],
+                    "max_rgba_err_vs_plain": err2},
     }
 
 
@@ -430,6 +451,7 @@ def main():
         "cpu_baseline": cpu,
         "learned_skip": learned_res,
         "next_rows": next_res,
+        "paper_context": PAPER_CONTEXT,
     }
     print(json.dumps(line), flush=True)
 

@@ -125,7 +125,7 @@ typedef struct {
                              block column bx holding padded x indices 4 bx - 1 .. 4 bx + 6, so a
                              stencil row loads as one vector from one block (twice the floats) */
     int32_t centering;    /* 0: cell-centred data, `cells` holds dims[0]*dims[1]*dims[2] values;
-                             1: vertex-centred data (Section 4.2), `cells` holds the
+                             1: vertex-centred data (Section 5), `cells` holds the
                              (dims[0]+1)(dims[1]+1)(dims[2]+1) samples at the grid vertices
                              lo + i h, i = 0..dims, x fastest.  The field is their trilinear
                              interpolant.  Samples on a patch face that abuts coarser data
@@ -340,7 +340,7 @@ int64_t amr_mlp_packed_bytes(void);
 int amr_mlp_pack(const float *W, void *d_out, void *stream);
 
 /* ---------------------------------------------------------------------------------------- */
-/* Out-of-core residency (Sections 4.2 and 7)                                                */
+/* Out-of-core residency (Sections 5.2 and 7)                                                */
 /* ---------------------------------------------------------------------------------------- */
 
 /* The paper keeps one texture brick per subgrid, and with bindless access an out-of-core

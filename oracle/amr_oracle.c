@@ -13,9 +13,9 @@
  *   - cell-centred data; interpolation across patch interfaces needs a
  *     shared layer of samples at brick boundaries                      (Section 5 intro)
  *   - vertex-centred data: trilinear interpolation of vertex samples, the
- *     samples at dangling nodes replaced by the coarse interpolant       (Section 4.2)
+ *     samples at dangling nodes replaced by the coarse interpolant       (Section 5)
  *   - out-of-core subsets: leaves of absent subgrids drawn from the finest
- *     present subgrid holding them                                       (Sections 4.2, 7)
+ *     present subgrid holding them                                       (Sections 5.2, 7)
  *   - gradient lighting with gradients taken on the fly, also across
  *     blocks of different subgrids                                      (Section 5, Section 6)
  *   - emission-absorption model                                          (Section 6)
@@ -244,7 +244,7 @@ void orc_set_lod_nodes(Orc *O, int na, const int64_t *recs) {
         }
 }
 
-/* Out-of-core rendering (the motive for per-subgrid storage, Sections 4.2 and 7): only the
+/* Out-of-core rendering (the motive for per-subgrid storage, Sections 5.2 and 7): only the
  * patches with res[p] != 0 are on the device.  Every leaf (and kind-(a) node) keeps its place
  * in the tree but takes its data from the finest resident patch whose box holds the leaf's
  * whole box, at that patch's level and step; a leaf with no resident holder is empty.  The
@@ -400,7 +400,7 @@ static void ensure_ghosts(Orc *O, int p) {
 }
 
 /* ------------------------------------------------------------------------------------ */
-/* Vertex-centred data (Section 4.2): the samples sit on the grid vertices, a patch of n   */
+/* Vertex-centred data (Section 5): the samples sit on the grid vertices, a patch of n     */
 /* cells holds n+1 per axis, the field is their trilinear interpolant, and samples on a    */
 /* patch face that abuts coarser data (dangling nodes) are replaced by the interpolated    */
 /* value of the abutting coarse patch, so the field is continuous across the interface.   */

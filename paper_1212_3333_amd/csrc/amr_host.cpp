@@ -497,7 +497,7 @@ struct Packer {
         for (auto &x : th) x.join();
     }
 
-    // Vertex-centred data (Section 4.2).  Patch owning the finest-level cell c: the kD leaf
+    // Vertex-centred data (Section 5).  Patch owning the finest-level cell c: the kD leaf
     // holding it (half-open split planes); -1 for a leaf without data.
     int cell_owner(const int64_t *c) const {
         int ni = 0;

@@ -1,4 +1,4 @@
-// Out-of-core residency (Sections 4.2 and 7): the paper keeps one texture brick per subgrid so
+// Out-of-core residency (Sections 5.2 and 7): the paper keeps one texture brick per subgrid so
 // that, with bindless access, an out-of-core renderer can upload the subsets of bricks it needs.
 // Here a host store holds every brick once, packed exactly as amr_pack_pool packs the pool; a
 // subset is made resident in a device brick cache (first-fit slots, 256-byte aligned), and the

@@ -1,4 +1,4 @@
-"""GPU parity of vertex-centred scenes (Section 4.2: samples on the grid vertices, trilinear
+"""GPU parity of vertex-centred scenes (Section 5: samples on the grid vertices, trilinear
 interpolation, dangling nodes replaced at pack time) against the FP64 oracle, through the C ABI.
 
 The kernels are the cell-centred ones: the packer presents a patch of n cells as n + 1 samples at

@@ -1,4 +1,4 @@
-"""Pins of the oracle's out-of-core mode (per-subgrid storage, Sections 4.2 and 7): with a
+"""Pins of the oracle's out-of-core mode (per-subgrid storage, Sections 5.2 and 7): with a
 subset of the patches present, every leaf keeps its place in the tree and is drawn from the
 finest present patch holding its whole box.  Checked against brute-force holders, a
 closed-form composite over piecewise-constant data, and the unrestricted oracle."""

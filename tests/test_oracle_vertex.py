@@ -1,4 +1,4 @@
-"""Pins of the oracle's vertex-centred data mode (Section 4.2: texels on the grid vertices,
+"""Pins of the oracle's vertex-centred data mode (Section 5: texels on the grid vertices,
 trilinear interpolation, shared boundary samples, dangling nodes replaced by the interpolated
 value of the abutting coarse brick).  Checked against a textbook interpolator, hand-derived
 dangling-node values, linear fields (reproduced exactly everywhere, B's faces included),

@@ -490,7 +490,7 @@ def cosmology_view(seed: int = 0, width: int = 1024, height: int = 1024):
 
 
 def cosmology_vertex_view(seed: int = 0, width: int = 1024, height: int = 1024):
-    """The cosmology-like view with vertex-centred data (Section 4.2): the same boxes, LUT,
+    """The cosmology-like view with vertex-centred data (Section 5): the same boxes, LUT,
     camera and params, each patch holding the log-normal density at its (dims+1)^3 grid
     vertices."""
     h, lut, cam, prm = cosmology_view(seed, width, height)
