@@ -4,9 +4,16 @@
 // the transmittance of the segment from x to the light inside B, sampled with the primary rule
 // (kD-restart segments, midpoints, step proportional to each leaf level's cell size).
 //
-// One wave per block and one 8x8 pixel tile per wave, dealt to XCDs like the forward kernel.
-// The secondary march runs inside the primary sample loop, so the cost is (primary samples) x
-// (secondary samples); the images are for the workloads that need the lighting, not a timed path.
+// The secondary rays are not marched inside the primary sample loop: there a wave holds one
+// shadow ray per pixel, lanes finish at very different times and a small image leaves most of
+// the machine idle.  Instead the render runs as passes over the same primary march (whose
+// samples and early termination do not depend on the shading):
+//   1. count the samples of every ray; an exclusive scan gives each ray its first job;
+//   2. record the ray parameter of every sample as a job;
+//   3. trace every job's shadow ray, one per lane: consecutive lanes hold consecutive samples of
+//      a ray, whose shadow rays run side by side to the light;
+//   4. march again and composite with the stored transmittances.
+// The job arrays (16 bytes per sample) are allocated for the call and freed before it returns.
 #include <hip/hip_runtime.h>
 
 #include "amr_render_common.h"
@@ -74,8 +81,22 @@ __device__ __forceinline__ float light_transmittance(const RenderArgs &A, const 
     return exp2f(-tau);
 }
 
-template <bool REC, int LAY>
-__global__ __launch_bounds__(64) void render_shadow(RenderArgs A) {
+struct ShadowWork {
+    int32_t *cnt;       // [npix] samples per ray (pass 1)
+    int64_t *off;       // [npix] first job of each ray
+    double *tk;         // [njobs] ray parameter of each sample
+    int32_t *ray;       // [njobs] the sample's ray
+    float *tl;          // [njobs] transmittance to the light
+    int64_t njobs;
+};
+
+enum { kPassCount = 0, kPassRecord = 1, kPassShade = 2 };
+
+// One march of the primary rays (one wave per 8x8 tile, tiles dealt to XCDs as in the forward
+// kernel): PASS counts, records or shades the samples; the samples and the termination are the
+// same in every pass.
+template <int PASS, bool REC, int LAY>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void shadow_march(RenderArgs A, ShadowWork W) {
     __shared__ float4 s_lut[256];
     for (int i = threadIdx.x; i < 256; i += 64) s_lut[i] = A.lut[i];
     __syncthreads();
@@ -101,6 +122,9 @@ __global__ __launch_bounds__(64) void render_shadow(RenderArgs A) {
     Ray R;
     bool alive = valid && setup_ray(A, pi, pj, R);
     if (REC) cnt.hit = alive ? 1 : 0;
+    const int64_t base = (PASS != kPassCount && valid) ? W.off[ray] : 0;
+    // the later passes stay inside this ray's jobs even if a sample count came out differently
+    const int njob = (PASS != kPassCount && valid) ? W.cnt[ray] : 0;
     double tcur = R.t0;
     uint32_t start = 0;
     while (alive && tcur < R.t1) {
@@ -117,18 +141,19 @@ __global__ __launch_bounds__(64) void render_shadow(RenderArgs A) {
             for (int k = 0; k < nsm; k++) {
                 SampleVals v;
                 eval_sample<false, REC, false, LAY>(A, s_lut, R, S, k, v, cnt);
-                double x[3];
-                {
+                if (PASS == kPassRecord && nsamp_total < njob) {
 #pragma clang fp contract(off)
-                    const double tk = S.ta + ((double)k + 0.5) * S.delta;
-                    #pragma unroll
-                    for (int b = 0; b < 3; b++) x[b] = R.o[b] + tk * R.d[b];
+                    W.tk[base + nsamp_total] = S.ta + ((double)k + 0.5) * S.delta;
+                    W.ray[base + nsamp_total] = (int32_t)ray;
                 }
-                const float shade = A.k_a + A.k_d * light_transmittance<LAY>(A, s_lut, x);
-                const float wgt = T * v.alpha * shade;
-                C0 += wgt * v.r;
-                C1 += wgt * v.g;
-                C2 += wgt * v.b;
+                if (PASS == kPassShade) {
+                    const float tl = nsamp_total < njob ? W.tl[base + nsamp_total] : 1.f;
+                    const float shade = A.k_a + A.k_d * tl;
+                    const float wgt = T * v.alpha * shade;
+                    C0 += wgt * v.r;
+                    C1 += wgt * v.g;
+                    C2 += wgt * v.b;
+                }
                 T *= 1.f - v.alpha;
                 nsamp_total++;
                 if (T < A.t_min) { alive = false; break; }
@@ -155,7 +180,8 @@ __global__ __launch_bounds__(64) void render_shadow(RenderArgs A) {
         }
         tcur = tb;
     }
-    if (valid) {
+    if (PASS == kPassCount && valid) W.cnt[ray] = nsamp_total;
+    if (PASS == kPassShade && valid) {
         reinterpret_cast<float4 *>(A.rgba)[ray] = make_float4(C0, C1, C2, 1.f - T);
         if (REC && A.trace_n) A.trace_n[ray] = nseg;
         if (REC && A.nsamp) A.nsamp[ray] = nsamp_total;
@@ -166,14 +192,139 @@ __global__ __launch_bounds__(64) void render_shadow(RenderArgs A) {
     }
 }
 
+// Pass 3: one shadow ray per lane, from the recorded sample position to the light.
+template <int LAY>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void shadow_rays(RenderArgs A, ShadowWork W) {
+#pragma clang fp contract(off)
+    __shared__ float4 s_lut[256];
+    for (int i = threadIdx.x; i < 256; i += 64) s_lut[i] = A.lut[i];
+    __syncthreads();
+    const int64_t j = (int64_t)blockIdx.x * 64 + threadIdx.x;
+    if (j >= W.njobs) return;
+    const int r = W.ray[j];
+    Ray R;
+    setup_ray(A, r % A.width, r / A.width, R);   // a ray with samples, so it meets the clip box
+    const double tk = W.tk[j];
+    double x[3];
+    #pragma unroll
+    for (int b = 0; b < 3; b++) x[b] = R.o[b] + tk * R.d[b];
+    W.tl[j] = light_transmittance<LAY>(A, s_lut, x);
+}
+
+// Block-wise exclusive scan of the per-ray counts (1024 per block), then of the block sums.
+__global__ __launch_bounds__(1024) void scan_counts(const int32_t *cnt, int64_t n, int64_t *off, int64_t *bsum) {
+    __shared__ int64_t t[1024];
+    const int64_t i = (int64_t)blockIdx.x * 1024 + threadIdx.x;
+    const int64_t v = i < n ? (int64_t)cnt[i] : 0;
+    t[threadIdx.x] = v;
+    __syncthreads();
+    for (int d = 1; d < 1024; d *= 2) {
+        const int64_t add = threadIdx.x >= (unsigned)d ? t[threadIdx.x - d] : 0;
+        __syncthreads();
+        t[threadIdx.x] += add;
+        __syncthreads();
+    }
+    if (i < n) off[i] = t[threadIdx.x] - v;
+    if (threadIdx.x == 1023) bsum[blockIdx.x] = t[1023];
+}
+
+__global__ __launch_bounds__(1024) void scan_block_sums(int64_t *bsum, int64_t nb, int64_t *total) {
+    __shared__ int64_t t[1024];
+    int64_t carry = 0;
+    for (int64_t b0 = 0; b0 < nb; b0 += 1024) {
+        const int64_t i = b0 + threadIdx.x;
+        const int64_t v = i < nb ? bsum[i] : 0;
+        t[threadIdx.x] = v;
+        __syncthreads();
+        for (int d = 1; d < 1024; d *= 2) {
+            const int64_t add = threadIdx.x >= (unsigned)d ? t[threadIdx.x - d] : 0;
+            __syncthreads();
+            t[threadIdx.x] += add;
+            __syncthreads();
+        }
+        if (i < nb) bsum[i] = carry + t[threadIdx.x] - v;
+        carry += t[1023];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *total = carry;
+}
+
+__global__ __launch_bounds__(1024) void add_block_offsets(int64_t *off, int64_t n, const int64_t *bsum) {
+    const int64_t i = (int64_t)blockIdx.x * 1024 + threadIdx.x;
+    if (i < n) off[i] += bsum[blockIdx.x];
+}
+
+template <int LAY>
+static void launch_march(int pass, bool rec, int grid, hipStream_t s, const RenderArgs &A, const ShadowWork &W) {
+    if (pass == kPassCount) hipLaunchKernelGGL((shadow_march<kPassCount, false, LAY>), dim3(grid), dim3(64), 0, s, A, W);
+    else if (pass == kPassRecord) hipLaunchKernelGGL((shadow_march<kPassRecord, false, LAY>), dim3(grid), dim3(64), 0, s, A, W);
+    else if (rec) hipLaunchKernelGGL((shadow_march<kPassShade, true, -1>), dim3(grid), dim3(64), 0, s, A, W);
+    else hipLaunchKernelGGL((shadow_march<kPassShade, false, LAY>), dim3(grid), dim3(64), 0, s, A, W);
+}
+
 int launch_shadow(const RenderArgs &A, bool rec, void *stream) {
     hipStream_t s = (hipStream_t)stream;
     const int grid = 8 * ((A.sgrid * A.sgrid + 7) / 8) * 16;
-    if (rec) hipLaunchKernelGGL((render_shadow<true, -1>), dim3(grid), dim3(64), 0, s, A);
-    else if (A.layout == 0) hipLaunchKernelGGL((render_shadow<false, 0>), dim3(grid), dim3(64), 0, s, A);
-    else if (A.layout == 1) hipLaunchKernelGGL((render_shadow<false, 1>), dim3(grid), dim3(64), 0, s, A);
-    else hipLaunchKernelGGL((render_shadow<false, 2>), dim3(grid), dim3(64), 0, s, A);
-    return check_hip(hipGetLastError(), "render_shadow launch");
+    const int64_t npix = (int64_t)A.width * A.height;
+    const int64_t nb = (npix + 1023) / 1024;
+    RenderArgs Ap = A;                      // counting and recording passes record nothing else
+    Ap.trace = nullptr;
+    Ap.trace_n = nullptr;
+    Ap.nsamp = nullptr;
+    Ap.stats = nullptr;
+    Ap.touch = nullptr;
+    ShadowWork W{};
+    int64_t *bsum = nullptr, *d_total = nullptr;
+    int rc = AMR_OK;
+    auto march = [&](int pass, const RenderArgs &Aa) {
+        if (Aa.layout == 0) launch_march<0>(pass, rec, grid, s, Aa, W);
+        else if (Aa.layout == 1) launch_march<1>(pass, rec, grid, s, Aa, W);
+        else launch_march<2>(pass, rec, grid, s, Aa, W);
+    };
+    hipError_t e = hipMalloc((void **)&W.cnt, sizeof(int32_t) * npix);
+    if (e == hipSuccess) e = hipMalloc((void **)&W.off, sizeof(int64_t) * npix);
+    if (e == hipSuccess) e = hipMalloc((void **)&bsum, sizeof(int64_t) * nb);
+    if (e == hipSuccess) e = hipMalloc((void **)&d_total, sizeof(int64_t));
+    if (e == hipSuccess) {
+        march(kPassCount, Ap);
+        hipLaunchKernelGGL(scan_counts, dim3(nb), dim3(1024), 0, s, W.cnt, npix, W.off, bsum);
+        hipLaunchKernelGGL(scan_block_sums, dim3(1), dim3(1024), 0, s, bsum, nb, d_total);
+        hipLaunchKernelGGL(add_block_offsets, dim3(nb), dim3(1024), 0, s, W.off, npix, bsum);
+        int64_t total = 0;
+        e = hipGetLastError();
+        if (e == hipSuccess) e = hipMemcpyAsync(&total, d_total, sizeof(int64_t), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        W.njobs = total;
+        if (e == hipSuccess && total > 0) {
+            e = hipMalloc((void **)&W.tk, sizeof(double) * total);
+            if (e == hipSuccess) e = hipMalloc((void **)&W.ray, sizeof(int32_t) * total);
+            if (e == hipSuccess) e = hipMalloc((void **)&W.tl, sizeof(float) * total);
+            // defined contents for any job a differing count would leave unwritten
+            if (e == hipSuccess) e = hipMemsetAsync(W.tk, 0, sizeof(double) * total, s);
+            if (e == hipSuccess) e = hipMemsetAsync(W.ray, 0, sizeof(int32_t) * total, s);
+        }
+        if (e == hipSuccess) {
+            if (total > 0) {
+                march(kPassRecord, Ap);
+                const int64_t nj = (total + 63) / 64;
+                if (A.layout == 0) hipLaunchKernelGGL((shadow_rays<0>), dim3(nj), dim3(64), 0, s, Ap, W);
+                else if (A.layout == 1) hipLaunchKernelGGL((shadow_rays<1>), dim3(nj), dim3(64), 0, s, Ap, W);
+                else hipLaunchKernelGGL((shadow_rays<2>), dim3(nj), dim3(64), 0, s, Ap, W);
+            }
+            march(kPassShade, A);
+            e = hipGetLastError();
+            if (e == hipSuccess) e = hipStreamSynchronize(s);   // the job arrays are freed below
+        }
+    }
+    if (e != hipSuccess) rc = check_hip(e, "point-light passes");
+    hipFree(W.cnt);
+    hipFree(W.off);
+    hipFree(bsum);
+    hipFree(d_total);
+    hipFree(W.tk);
+    hipFree(W.ray);
+    hipFree(W.tl);
+    return rc;
 }
 
 }  // namespace amr
