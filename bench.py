@@ -229,6 +229,90 @@ def workloads_orbit(cam, k, frames):
     return c
 
 
+def batched_section(amr, dev, scene, lut_t, prm):
+    """Serving batch on the same hierarchy: 64 orbit cameras with resolutions from {256^2, 512^2,
+    768^2, 1024^2} in one persistent launch (tile shape and blocks per CU from the autotuner),
+    captured in a hipGraph and replayed; per-image latency from the kernel's completion stamps."""
+    import tempfile
+    import torch
+    import workloads
+    from paper_1212_3333_amd import autotune
+    cams = workloads.serving_cameras(0, 64)
+    dc = amr.camera_table(cams, device=dev)
+    q = amr.queue_buffer(len(cams), device=dev)
+    npix = sum(c["width"] * c["height"] for c in cams)
+    out = torch.zeros(npix * 4, dtype=torch.float32, device=dev)
+    with tempfile.TemporaryDirectory() as td:
+        best = autotune.tune(scene, cams, lut_t, prm, dc, q, out, workload_key="serving64", reps=1,
+                             cache_path=td + "/tune.json")
+    stamps = torch.zeros(len(cams) + 1, dtype=torch.int64, device=dev)
+    bprm = dict(prm, persistent=1, tile_w=best["tile_w"], tile_h=best["tile_h"], blocks_per_cu=best["blocks_per_cu"])
+    amr.render(scene, cams, lut_t, bprm, out=out, d_cams=dc, d_queue=q, d_stamps=stamps)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    st = torch.cuda.Stream(device=dev)
+    with torch.cuda.stream(st):
+        with torch.cuda.graph(g, stream=st):
+            amr.render(scene, cams, lut_t, bprm, out=out, d_cams=dc, d_queue=q, d_stamps=stamps)
+    lat, agg = [], []
+    khz = amr.wall_clock_khz()
+    for _ in range(3):
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        g.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        sv = stamps.cpu().numpy()
+        lat.append((sv[:-1] - sv[-1]) / khz)
+        agg.append(npix / (e0.elapsed_time(e1) * 1e-3) / 1e6)
+    lat = np.concatenate(lat)
+    res = dict(cameras=len(cams), rays=int(npix), tile_w=int(best["tile_w"]), tile_h=int(best["tile_h"]),
+               blocks_per_cu=int(best["blocks_per_cu"]), aggregate_mrays_per_s=round(float(np.median(agg)), 2),
+               latency_ms_p50=round(float(np.percentile(lat, 50)), 2),
+               latency_ms_p99=round(float(np.percentile(lat, 99)), 2))
+    del g, out
+    torch.cuda.empty_cache()
+    return res
+
+
+def adjoint_section(amr, dev, scene, h, steps=200):
+    """Transfer-function fit on the same hierarchy: 8 orbit cameras at 512^2, lit, Adam (lr 1e-2)
+    on the LUT through the checkpointed forward and the adjoint kernel, toward images rendered
+    with a hidden target LUT.  Reports the time per optimisation step (forward + backward of all
+    eight images) and the loss after `steps` steps."""
+    import torch
+    import workloads
+    _, cams, target, start, prm = workloads.tf_fit(0, h=h)
+    sh = torch.tensor([1.0, 1.0, 1.0, 0.3, 0.7], dtype=torch.float32)
+    with torch.no_grad():
+        tgt = amr.render(scene, cams, torch.from_numpy(target).to(dev), prm)["rgba"].clone()
+    lut = torch.from_numpy(start).to(dev).requires_grad_(True)
+    opt = torch.optim.Adam([lut], lr=1e-2)
+    losses = []
+
+    def step():
+        opt.zero_grad()
+        rgba = amr.AMRRender.apply(lut, sh, scene, cams, prm)
+        loss = ((rgba - tgt) ** 2).mean()
+        loss.backward()
+        opt.step()
+        with torch.no_grad():
+            lut.clamp_(min=0.0)
+        return loss
+    for _ in range(3):
+        losses.append(float(step().item()))
+    torch.cuda.synchronize()
+    t = time.time()
+    for _ in range(steps - 3):
+        last = step()
+    torch.cuda.synchronize()
+    ms = (time.time() - t) * 1e3 / (steps - 3)
+    losses.append(float(last.item()))
+    return dict(cameras=len(cams), width=512, height=512, steps=steps, ms_per_step=round(ms, 3),
+                loss_first=losses[0], loss_last=losses[-1])
+
+
 def learned_skip_section(amr, dev, steps, warmup):
     """Deep-range hierarchy (20 levels) at 1024^2 (and 2048^2, the hierarchy's own view size):
     plain traversal vs learned segment proposals.  The network is trained on the GPU from
@@ -404,6 +488,12 @@ def main():
         unlit_ms = time_frames(amr, scene, cam, lut_t, dict(prm, lighting=False), max(3, args.steps // 2), 2, out)
 
     pool_bytes, meta_bytes = int(scene.scene.pool_bytes), int(scene.scene.meta_bytes)
+    batched_res = adjoint_res = None
+    if not args.no_next:
+        batched_res = batched_section(amr, dev, scene, lut_t, prm)
+        log("batched:", batched_res)
+        adjoint_res = adjoint_section(amr, dev, scene, h)
+        log("adjoint:", adjoint_res)
     next_res = None
     if not args.no_next:
         next_res = next_rows_section(amr, dev, scene, h, cam, lut_t, prm, max(3, args.steps // 2), out, args.seed)
@@ -450,6 +540,8 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "learned_skip": learned_res,
+        "batched_serving": batched_res,
+        "adjoint_tf_fit": adjoint_res,
         "next_rows": next_res,
         "paper_context": PAPER_CONTEXT,
     }
