@@ -109,6 +109,8 @@ __device__ __forceinline__ void set_camera(RenderArgs &A, const amr_camera &C) {
 template <bool LIT, bool REC, int LAY>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void render_batched(BatchArgs B) {
     __shared__ float4 s_lut[256];
+    TapQueue *tq = nullptr;                        // lit: one deferred-tap queue per wave
+    if constexpr (LIT) tq = tap_queues<4>() + (threadIdx.x >> 6);
     s_lut[threadIdx.x] = B.base.lut[threadIdx.x];
     __syncthreads();
     const int lane = threadIdx.x & 63;
@@ -144,6 +146,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void r
         Ray R;
         bool alive = valid && setup_ray(A, pi, pj, R);
         if (REC) cnt.hit += alive ? 1 : 0;
+        if (LIT) tapq_init(*tq, lane);
         double tcur = R.t0;
         uint32_t start = 0;
         while (alive && tcur < R.t1) {
@@ -156,13 +159,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void r
                 Segment S;
                 setup_segment<LIT, LAY>(A, R, L, leaf, tcur, tb, S);
                 for (int k2 = 0; k2 < S.n; k2++) {
-                    SampleVals v;
-                    eval_sample<LIT, REC, false, LAY>(A, s_lut, R, S, k2, v, cnt);
-                    float wgt = T * v.alpha * v.shade;
-                    C0 += wgt * v.r;
-                    C1 += wgt * v.g;
-                    C2 += wgt * v.b;
-                    T *= 1.f - v.alpha;
+                    float alpha;
+                    if (LIT) {
+                        // as the single-camera kernel: taps that leave the brick are deferred
+                        TapQueue &Q = *tq;
+                        tapq_reserve<REC, LAY>(A, s_lut, Q, lane, cnt);
+                        alpha = lit_sample_deferred<REC, LAY>(A, s_lut, Q, lane, R, S, k2, T, C0, C1, C2, cnt);
+                    } else {
+                        SampleVals v;
+                        eval_sample<false, REC, false, LAY>(A, s_lut, R, S, k2, v, cnt);
+                        float wgt = T * v.alpha * v.shade;
+                        C0 += wgt * v.r;
+                        C1 += wgt * v.g;
+                        C2 += wgt * v.b;
+                        alpha = v.alpha;
+                    }
+                    T *= 1.f - alpha;
                     nsamp_total++;
                     if (T < A.t_min) { alive = false; break; }
                 }
@@ -172,6 +184,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void r
                 tb = nextafter(tcur, INFINITY);
             }
             tcur = tb;
+        }
+        if (LIT) {
+            float D0, D1, D2;
+            tapq_finish<REC, LAY>(A, s_lut, *tq, lane, cnt, D0, D1, D2);
+            C0 += D0;
+            C1 += D1;
+            C2 += D2;
         }
         if (REC) cnt.samples += nsamp_total;
         if (valid) reinterpret_cast<float4 *>(B.base.rgba)[q.pix0[c] + (long long)pj * C.width + pi] =

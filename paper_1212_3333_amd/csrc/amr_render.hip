@@ -23,9 +23,15 @@ namespace amr {
 // At least 3 waves per SIMD: the lit kernel then fits 168 VGPRs with a 12-byte spill instead
 // of running 2 waves at 171 (the unlit one needs 80 and runs 6).
 // LAY: the brick layout fixed at compile time for the timed variants (-1: read at run time).
+// Lit trilinear variants defer the samples whose gradient taps leave the brick (TapQueue),
+// except while recording checkpoints for the adjoint, whose (T, C) snapshots need every
+// earlier sample's colour.
 template <bool LIT, bool REC, bool NEAR, int LAY>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void render_fwd(RenderArgs A) {
+    constexpr bool kDefer = LIT && !NEAR;
     __shared__ float4 s_lut[256];
+    TapQueue *tq = nullptr;
+    if constexpr (kDefer) tq = tap_queues<1>();
     for (int i = threadIdx.x; i < 256; i += 64) s_lut[i] = A.lut[i];
     __syncthreads();
 
@@ -65,74 +71,159 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void re
         ckh = reinterpret_cast<CkptHeader *>(A.ckpt + (A.ckpt_ray0 + ray) * A.ckpt_stride);
         ck = reinterpret_cast<Ckpt *>(ckh + 1);
     }
-    double tcur = R.t0;
-    uint32_t start = 0;
-    while (alive && tcur < R.t1) {
-        double tb = R.t1;
-        int leaf = descend(A, R, tcur, tb, start);
-        if (leaf < 0) break;
-        if (REC) cnt.segments++;
-        const DLeaf &L = A.leaves[leaf];
-        const int p = L.patch;
-        int nsm = 0;
-        if (p >= 0) {
-            if (REC && ck) {
-                if (dseg % every == 0) {
-                    if (nck == A.ckpt_max) {             // full: keep every other, halve the rate
-                        for (int i = 0; i < A.ckpt_max / 2; i++) ck[i] = ck[2 * i];
-                        nck = A.ckpt_max / 2;
-                        every *= 2;
-                        if (REC) cnt.ckover++;
-                    }
-                    if (dseg % every == 0) {
-                        Ckpt c;
-                        c.t = tcur;
-                        c.T = T;
-                        c.C[0] = C0;
-                        c.C[1] = C1;
-                        c.C[2] = C2;
-                        c.dseg = dseg;
-                        c.sidx = nsamp_total;
-                        ck[nck++] = c;
+    const bool defer = kDefer && !(REC && A.ckpt);      // wave-uniform
+    if (kDefer && defer) {
+        // Lit, deferred taps: the wave's lanes step together.  A step either fetches the next
+        // data segment of the lanes that have none (once half of the live lanes wait, or
+        // all do) or takes one sample on every lane that has a segment; the tap queue is
+        // resolved at the top of a step, where every lane of the wave works on it.  The rays'
+        // arithmetic and traces are those of the per-segment loop below.
+        TapQueue &Q = *tq;
+        tapq_init(Q, lane);
+        double tcur = R.t0;
+        uint32_t start = 0;
+        Segment S;
+        int k = 0;
+        bool has = false;                 // a data segment with samples left
+        while (true) {
+            const unsigned long long live = __ballot(alive);
+            if (!live) break;
+            const unsigned long long samp = __ballot(has);
+            if (tq_count(Q) + (uint32_t)__popcll(samp) > (uint32_t)kTapQ) tapq_flush<REC, LAY>(A, s_lut, Q, lane, cnt);
+            const bool waiting = alive && !has;
+            const unsigned long long wait = __ballot(waiting);
+            if (wait == live || 2 * __popcll(wait) >= __popcll(live)) {
+                if (waiting) {
+                    while (true) {            // next segment with samples, or the end of the ray
+                        if (!(tcur < R.t1)) { alive = false; break; }
+                        double tb = R.t1;
+                        const int leaf = descend(A, R, tcur, tb, start);
+                        if (leaf < 0) { alive = false; break; }
+                        if (REC) cnt.segments++;
+                        const DLeaf &L = A.leaves[leaf];
+                        const int p = L.patch;
+                        int n = 0;
+                        if (p >= 0) {
+                            setup_segment<LIT, LAY>(A, R, L, leaf, tcur, tb, S);
+                            n = S.n;
+                        }
+                        if (REC && A.trace) {
+                            if (nseg < A.trace_cap) {
+                                amr_trace_rec rec;
+                                rec.leaf = leaf;
+                                rec.patch = p;
+                                rec.n = n;
+                                rec.level = leaf_level(L);
+                                rec.ta = tcur;
+                                rec.tb = tb;
+                                A.trace[ray * A.trace_cap + nseg] = rec;
+                            } else {
+                                cnt.tover++;
+                            }
+                        }
+                        nseg++;
+                        if (tb <= tcur) {   // never expected: keep the walk moving forward
+                            if (REC) cnt.guard++;
+                            tb = nextafter(tcur, INFINITY);
+                        }
+                        tcur = tb;
+                        if (n > 0) {
+                            k = 0;
+                            has = true;
+                            break;
+                        }
                     }
                 }
-                dseg++;
+                continue;
             }
-            Segment S;
-            setup_segment<LIT, LAY>(A, R, L, leaf, tcur, tb, S);
-            nsm = S.n;
-            for (int k = 0; k < nsm; k++) {
-                SampleVals v;
-                eval_sample<LIT, REC, NEAR, LAY>(A, s_lut, R, S, k, v, cnt);
-                float wgt = T * v.alpha * v.shade;
-                C0 += wgt * v.r;
-                C1 += wgt * v.g;
-                C2 += wgt * v.b;
-                T *= 1.f - v.alpha;
+            if (has) {
+                const float alpha = lit_sample_deferred<REC, LAY>(A, s_lut, Q, lane, R, S, k, T, C0, C1, C2, cnt);
+                T *= 1.f - alpha;
                 nsamp_total++;
-                if (T < A.t_min) { alive = false; break; }
+                k++;
+                if (T < A.t_min) {
+                    alive = false;
+                    has = false;
+                } else if (k == S.n) {
+                    has = false;
+                }
             }
         }
-        if (REC && A.trace) {
-            if (nseg < A.trace_cap) {
-                amr_trace_rec rec;
-                rec.leaf = leaf;
-                rec.patch = p;
-                rec.n = p >= 0 ? nsm : 0;
-                rec.level = leaf_level(L);
-                rec.ta = tcur;
-                rec.tb = tb;
-                A.trace[ray * A.trace_cap + nseg] = rec;
-            } else {
-                cnt.tover++;
+        float D0, D1, D2;
+        tapq_finish<REC, LAY>(A, s_lut, Q, lane, cnt, D0, D1, D2);
+        C0 += D0;
+        C1 += D1;
+        C2 += D2;
+    } else {
+        double tcur = R.t0;
+        uint32_t start = 0;
+        while (alive && tcur < R.t1) {
+            double tb = R.t1;
+            int leaf = descend(A, R, tcur, tb, start);
+            if (leaf < 0) break;
+            if (REC) cnt.segments++;
+            const DLeaf &L = A.leaves[leaf];
+            const int p = L.patch;
+            int nsm = 0;
+            if (p >= 0) {
+                if (REC && ck) {
+                    if (dseg % every == 0) {
+                        if (nck == A.ckpt_max) {             // full: keep every other, halve the rate
+                            for (int i = 0; i < A.ckpt_max / 2; i++) ck[i] = ck[2 * i];
+                            nck = A.ckpt_max / 2;
+                            every *= 2;
+                            if (REC) cnt.ckover++;
+                        }
+                        if (dseg % every == 0) {
+                            Ckpt c;
+                            c.t = tcur;
+                            c.T = T;
+                            c.C[0] = C0;
+                            c.C[1] = C1;
+                            c.C[2] = C2;
+                            c.dseg = dseg;
+                            c.sidx = nsamp_total;
+                            ck[nck++] = c;
+                        }
+                    }
+                    dseg++;
+                }
+                Segment S;
+                setup_segment<LIT, LAY>(A, R, L, leaf, tcur, tb, S);
+                nsm = S.n;
+                for (int k = 0; k < nsm; k++) {
+                    SampleVals v;
+                    eval_sample<LIT, REC, NEAR, LAY>(A, s_lut, R, S, k, v, cnt);
+                    float wgt = T * v.alpha * v.shade;
+                    C0 += wgt * v.r;
+                    C1 += wgt * v.g;
+                    C2 += wgt * v.b;
+                    T *= 1.f - v.alpha;
+                    nsamp_total++;
+                    if (T < A.t_min) { alive = false; break; }
+                }
             }
+            if (REC && A.trace) {
+                if (nseg < A.trace_cap) {
+                    amr_trace_rec rec;
+                    rec.leaf = leaf;
+                    rec.patch = p;
+                    rec.n = p >= 0 ? nsm : 0;
+                    rec.level = leaf_level(L);
+                    rec.ta = tcur;
+                    rec.tb = tb;
+                    A.trace[ray * A.trace_cap + nseg] = rec;
+                } else {
+                    cnt.tover++;
+                }
+            }
+            nseg++;
+            if (tb <= tcur) {   // never expected: keep the walk moving forward
+                if (REC) cnt.guard++;
+                tb = nextafter(tcur, INFINITY);
+            }
+            tcur = tb;
         }
-        nseg++;
-        if (tb <= tcur) {   // never expected: keep the walk moving forward
-            if (REC) cnt.guard++;
-            tb = nextafter(tcur, INFINITY);
-        }
-        tcur = tb;
     }
     if (valid) {
         reinterpret_cast<float4 *>(A.rgba)[ray] = make_float4(C0, C1, C2, 1.f - T);

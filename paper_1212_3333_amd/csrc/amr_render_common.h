@@ -580,11 +580,11 @@ __device__ __forceinline__ int classify_tap_fp32(const Segment &S, const float q
 }
 
 // Exact FP64 decision (same comparisons as the oracle's point location), for taps near a face.
-__device__ __forceinline__ int classify_tap_fp64(const RenderArgs &A, const Segment &S, const double xt[3], int a,
-                                                 int sgn) {
+__device__ __forceinline__ int classify_tap_fp64(const RenderArgs &A, int leaf, int patch, uint32_t safe,
+                                                 const double xt[3], int a, int sgn) {
 #pragma clang fp contract(off)
-    const DLeaf &L = A.leaves[S.leaf];
-    const DPatch &P = A.patches[S.patch];
+    const DLeaf &L = A.leaves[leaf];
+    const DPatch &P = A.patches[patch];
     bool in_leaf = true, others = true;
     #pragma unroll
     for (int b = 0; b < 3; b++) {
@@ -598,7 +598,12 @@ __device__ __forceinline__ int classify_tap_fp64(const RenderArgs &A, const Segm
     const double lim = sgn ? L.lo[a] - P.h[a] : L.hi[a] + P.h[a];
     const bool in_slab = sgn ? (xt[a] >= lim && xt[a] < L.lo[a]) : (xt[a] >= L.hi[a] && xt[a] < lim);
     if (!in_slab) return kTapLocate;
-    return ((S.safe >> face) & 1u) ? kTapSame : kTapFace;
+    return ((safe >> face) & 1u) ? kTapSame : kTapFace;
+}
+
+__device__ __forceinline__ int classify_tap_fp64(const RenderArgs &A, const Segment &S, const double xt[3], int a,
+                                                 int sgn) {
+    return classify_tap_fp64(A, S.leaf, S.patch, S.safe, xt, a, sgn);
 }
 
 // Value of patch p at world point x (x known to lie in p's data region).
@@ -767,127 +772,149 @@ __device__ __forceinline__ float nearest_sample(const RenderArgs &A, const Ray &
 
 // Sample k of a segment: value, LUT classification, opacity over the step, and (LIT) the
 // gradient shading with taps at x +- h^l e_a located in the tree.
-template <bool LIT, bool REC, bool NEAR = false, int LAY = -1>
-__device__ __forceinline__ void eval_sample(const RenderArgs &A, const float4 *s_lut, const Ray &R, const Segment &S,
-                                            int k, SampleVals &v, Counters &cnt) {
-    const float kk = (float)k + 0.5f;
-    const float qx = S.q0[0] + kk * S.dq[0], qy = S.q0[1] + kk * S.dq[1], qz = S.q0[2] + kk * S.dq[2];
-    float F;
-    if (NEAR) {
-        F = nearest_sample<LIT, REC, LAY>(A, R, S, k, qx, qy, qz, v.gv, cnt);
-    } else if (LIT) {
-        // value and the six taps x +- h^l e_a from this brick in one fused stencil; a tap that
-        // leaves the brick (classified in fp32, else FP64) is then read where it lands
-        const float qc[3] = {qx, qy, qz};
-        uint32_t clsbits = 0;             // 2 bits per tap t = 2 a + sgn
-        const bool inner = qx >= S.fs_lo[0] && qx < S.fs_hi[0] && qy >= S.fs_lo[1] && qy < S.fs_hi[1] &&
-                           qz >= S.fs_lo[2] && qz < S.fs_hi[2];
-        if (!inner) {
+// In-brick part of a lit sample at patch-local q: the value F and the six taps F(q +- e_a) from
+// one fused stencil of the segment's brick, and the class of every tap that leaves the brick
+// (2 bits per tap t = 2 a + sgn, sgn = 1 for the minus side; 0: in the brick).  Classified in
+// fp32 against the tap window; a class of kTapUnsure is decided later in FP64.
+template <bool REC, int LAY = -1>
+__device__ __forceinline__ uint32_t lit_stencil(const RenderArgs &A, const Segment &S, float qx, float qy, float qz,
+                                                float &F, float Fp[3], float Fm[3]) {
+    const float qc[3] = {qx, qy, qz};
+    uint32_t clsbits = 0;
+    const bool inner = qx >= S.fs_lo[0] && qx < S.fs_hi[0] && qy >= S.fs_lo[1] && qy < S.fs_hi[1] &&
+                       qz >= S.fs_lo[2] && qz < S.fs_hi[2];
+    if (!inner) {
+        #pragma unroll
+        for (int a = 0; a < 3; a++)
             #pragma unroll
-            for (int a = 0; a < 3; a++)
-                #pragma unroll
-                for (int sgn = 0; sgn < 2; sgn++) {
-                    float qt[3] = {qc[0], qc[1], qc[2]};
-                    qt[a] += sgn ? -1.f : 1.f;
-                    clsbits |= (uint32_t)classify_tap_fp32(S, qt, a, sgn) << (2 * (2 * a + sgn));
-                }
-        }
-        float Fp[3], Fm[3];
-        F = trilinear_taps<REC, LAY>(A, S.pv, qx, qy, qz, Fp, Fm);
-        uint32_t okbits = 0x3fu;          // bit t: tap t holds data
-        if (clsbits) {
-            if (REC) cnt.split++;
-            // the taps outside this brick, one at a time
-            uint32_t todo = 0;
-            #pragma unroll
-            for (int t = 0; t < 6; t++) todo |= ((clsbits >> (2 * t)) & 3u) ? (1u << t) : 0u;
-            while (todo) {
-                const int t = __builtin_ctz(todo);
-                todo &= todo - 1u;
-                const int a = t >> 1, sgn = t & 1;
-                int c = (int)((clsbits >> (2 * t)) & 3u);
-                const float step = sgn ? -1.f : 1.f;
-                const float qt0 = qx + (a == 0 ? step : 0.f), qt1 = qy + (a == 1 ? step : 0.f),
-                            qt2 = qz + (a == 2 ? step : 0.f);
-                // Each tap only chooses a brick and a position in it; one trilinear read follows.
-                // The exact FP64 tap position x = o + t_k d +- h^l e_a is formed near a face
-                // and for descents.
-                double xt[3] = {0.0, 0.0, 0.0};
-                const bool exact = c != kTapFace;
-                if (exact) {
+            for (int sgn = 0; sgn < 2; sgn++) {
+                float qt[3] = {qc[0], qc[1], qc[2]};
+                qt[a] += sgn ? -1.f : 1.f;
+                clsbits |= (uint32_t)classify_tap_fp32(S, qt, a, sgn) << (2 * (2 * a + sgn));
+            }
+    }
+    F = trilinear_taps<REC, LAY>(A, S.pv, qx, qy, qz, Fp, Fm);
+    return clsbits;
+}
+
+// FP64 position of sample k of a segment, o + t_k d (the point the gradient taps move from).
+__device__ __forceinline__ void sample_point(const Ray &R, const Segment &S, int k, double xs[3]) {
 #pragma clang fp contract(off)
-                    const double tk = S.ta + ((double)k + 0.5) * S.delta;
-                    #pragma unroll
-                    for (int b = 0; b < 3; b++) xt[b] = R.o[b] + tk * R.d[b];
-                    const double hl = A.patches[S.patch].h[a];
-                    const double xa = sel3(a, xt[0], xt[1], xt[2]);
-                    const double xn = sgn ? xa - hl : xa + hl;
-                    #pragma unroll
-                    for (int b = 0; b < 3; b++) xt[b] = b == a ? xn : xt[b];
-                }
-                if (REC && c == kTapUnsure) cnt.unsure++;
-                if (c == kTapUnsure) c = classify_tap_fp64(A, S, xt, a, sgn);
-                PatchView pv = S.pv;
-                float q0 = qt0, q1 = qt1, q2 = qt2;
-                bool ok = true;
-                if (c != kTapSame) {
-                    const DFaceXf X = c == kTapFace ? A.face_xf[6 * S.leaf + 2 * a + (sgn ? 0 : 1)] : DFaceXf{};
-                    if (c == kTapFace && X.n[0] > 0) {
-                        // the slab's single owner: its brick at the mapped position
-                        if (REC) cnt.face++;
-                        pv.brick = A.pool + X.off;
-                        pv.px = X.px;
-                        pv.pxy = X.pxy;
-                        pv.nx = X.n[0];
-                        pv.ny = X.n[1];
-                        pv.nz = X.n[2];
-                        q0 = qt0 * X.r + X.t[0];
-                        q1 = qt1 * X.r + X.t[1];
-                        q2 = qt2 * X.r + X.t[2];
-                    } else {
-                        if (!exact) {
+    const double tk = S.ta + ((double)k + 0.5) * S.delta;
+    #pragma unroll
+    for (int b = 0; b < 3; b++) xs[b] = R.o[b] + tk * R.d[b];
+}
+
+// Gradient tap point xs +- h^l e_a of a sample at FP64 position xs in patch `patch`.
+__device__ __forceinline__ void tap_point(const RenderArgs &A, int patch, const double xs[3], int a, int sgn,
+                                          double xt[3]) {
 #pragma clang fp contract(off)
-                            const double tk = S.ta + ((double)k + 0.5) * S.delta;
-                            #pragma unroll
-                            for (int b = 0; b < 3; b++) xt[b] = R.o[b] + tk * R.d[b];
-                            const double hl = A.patches[S.patch].h[a];
-                            const double xa = sel3(a, xt[0], xt[1], xt[2]);
-                            const double xn = sgn ? xa - hl : xa + hl;
-                            #pragma unroll
-                            for (int b = 0; b < 3; b++) xt[b] = b == a ? xn : xt[b];
-                        }
-                        // descend from the rope node holding the slab, else from the root (a
-                        // slab beyond B fails the box test there, except on B's closed upper faces)
-                        float qq[3];
-                        ok = locate_brick<REC, LAY>(A, xt, pv, qq, cnt, c == kTapFace && X.rope > 0 ? (uint32_t)X.rope : 0u);
-                        q0 = qq[0];
-                        q1 = qq[1];
-                        q2 = qq[2];
-                    }
-                }
-                const float Fs = ok ? trilinear<REC, LAY>(A, pv, q0, q1, q2) : 0.f;
-                if (!ok) okbits &= ~(1u << t);
-                // write the tap back (selects keep the arrays in registers)
-                #pragma unroll
-                for (int b = 0; b < 3; b++) {
-                    Fp[b] = (t == 2 * b) ? Fs : Fp[b];
-                    Fm[b] = (t == 2 * b + 1) ? Fs : Fm[b];
-                }
+    const double hl = A.patches[patch].h[a];
+    const double xa = sel3(a, xs[0], xs[1], xs[2]);
+    const double xn = sgn ? xa - hl : xa + hl;
+    #pragma unroll
+    for (int b = 0; b < 3; b++) xt[b] = b == a ? xn : xs[b];
+}
+
+// The taps of a lit sample that leave its brick (classes in clsbits, as lit_stencil returns
+// them), one at a time: each chooses a brick and a position in it, then one trilinear read
+// replaces Fp or Fm.  A tap beyond a face whose one-cell slab has a single owner patch is
+// mapped into that patch's brick (the face record of the leaf); otherwise the exact FP64 tap
+// point xs +- h^l e_a is located by a descent from the rope node holding the slab, else from
+// the root.  leaf, patch and safe describe the sample's segment, own its brick (null: read
+// from the patch header when a tap needs it); xs is the sample's FP64 position, (qx, qy, qz)
+// its patch-local position.  Returns bit t set where tap t holds data.
+template <bool REC, int LAY = -1>
+__device__ __forceinline__ uint32_t resolve_taps(const RenderArgs &A, int leaf, int patch, uint32_t safe,
+                                                 const PatchView *own, const double xs[3], float qx, float qy,
+                                                 float qz, uint32_t clsbits, float Fp[3], float Fm[3],
+                                                 Counters &cnt) {
+    uint32_t okbits = 0x3fu;
+    uint32_t todo = 0;
+    #pragma unroll
+    for (int t = 0; t < 6; t++) todo |= ((clsbits >> (2 * t)) & 3u) ? (1u << t) : 0u;
+    while (todo) {
+        const int t = __builtin_ctz(todo);
+        todo &= todo - 1u;
+        const int a = t >> 1, sgn = t & 1;
+        int c = (int)((clsbits >> (2 * t)) & 3u);
+        const float step = sgn ? -1.f : 1.f;
+        const float qt0 = qx + (a == 0 ? step : 0.f), qt1 = qy + (a == 1 ? step : 0.f),
+                    qt2 = qz + (a == 2 ? step : 0.f);
+        // the exact FP64 tap point, formed near a face and for descents only
+        double xt[3] = {0.0, 0.0, 0.0};
+        const bool exact = c != kTapFace;
+        if (exact) tap_point(A, patch, xs, a, sgn, xt);
+        if (REC && c == kTapUnsure) cnt.unsure++;
+        if (c == kTapUnsure) c = classify_tap_fp64(A, leaf, patch, safe, xt, a, sgn);
+        PatchView pv;
+        float q0 = qt0, q1 = qt1, q2 = qt2;
+        bool ok = true;
+        if (c == kTapSame) {
+            pv = own ? *own : patch_view<LAY>(A, A.patches[patch]);
+        } else {
+            const DFaceXf X = c == kTapFace ? A.face_xf[6 * leaf + 2 * a + (sgn ? 0 : 1)] : DFaceXf{};
+            if (c == kTapFace && X.n[0] > 0) {
+                // the slab's single owner: its brick at the mapped position
+                if (REC) cnt.face++;
+                pv.brick = A.pool + X.off;
+                pv.px = X.px;
+                pv.pxy = X.pxy;
+                pv.nx = X.n[0];
+                pv.ny = X.n[1];
+                pv.nz = X.n[2];
+                q0 = qt0 * X.r + X.t[0];
+                q1 = qt1 * X.r + X.t[1];
+                q2 = qt2 * X.r + X.t[2];
+            } else {
+                // descend from the rope node holding the slab, else from the root (a slab beyond
+                // B fails the box test there, except on B's closed upper faces)
+                if (!exact) tap_point(A, patch, xs, a, sgn, xt);
+                float qq[3];
+                ok = locate_brick<REC, LAY>(A, xt, pv, qq, cnt, c == kTapFace && X.rope > 0 ? (uint32_t)X.rope : 0u);
+                q0 = qq[0];
+                q1 = qq[1];
+                q2 = qq[2];
             }
         }
+        const float Fs = ok ? trilinear<REC, LAY>(A, pv, q0, q1, q2) : 0.f;
+        if (!ok) okbits &= ~(1u << t);
+        // write the tap back (selects keep the arrays in registers)
         #pragma unroll
-        for (int a = 0; a < 3; a++) {
-            const bool okp = (okbits >> (2 * a)) & 1u, okm = (okbits >> (2 * a + 1)) & 1u;
-            float gr;
-            if (okp && okm) gr = (Fp[a] - Fm[a]) * (0.5f * A.inv_range);
-            else if (okp) gr = (Fp[a] - F) * A.inv_range;
-            else if (okm) gr = (F - Fm[a]) * A.inv_range;
-            else gr = 0.f;
-            v.gv[a] = gr;
+        for (int b = 0; b < 3; b++) {
+            Fp[b] = (t == 2 * b) ? Fs : Fp[b];
+            Fm[b] = (t == 2 * b + 1) ? Fs : Fm[b];
         }
-    } else {
-        F = trilinear<REC, LAY>(A, S.pv, qx, qy, qz);
     }
+    return okbits;
+}
+
+// Normalised-value gradient by central differences of the taps, one-sided where a tap holds no
+// data, zero where neither does.
+__device__ __forceinline__ float lit_gradient_axis(const RenderArgs &A, float F, float fp, float fm, bool okp, bool okm) {
+    if (okp && okm) return (fp - fm) * (0.5f * A.inv_range);
+    if (okp) return (fp - F) * A.inv_range;
+    if (okm) return (F - fm) * A.inv_range;
+    return 0.f;
+}
+
+__device__ __forceinline__ void lit_gradient(const RenderArgs &A, float F, const float Fp[3], const float Fm[3],
+                                             uint32_t okbits, float gv[3]) {
+    #pragma unroll
+    for (int a = 0; a < 3; a++)
+        gv[a] = lit_gradient_axis(A, F, Fp[a], Fm[a], (okbits >> (2 * a)) & 1u, (okbits >> (2 * a + 1)) & 1u);
+}
+
+// Diffuse shading factor k_a + k_d |g . l| / sqrt(|g|^2 + eps^2) (Section 6).
+__device__ __forceinline__ float lit_shade(const RenderArgs &A, const float gv[3], float &dot, float &den) {
+    dot = gv[0] * A.lhat[0] + gv[1] * A.lhat[1] + gv[2] * A.lhat[2];
+    den = sqrtf(gv[0] * gv[0] + gv[1] * gv[1] + gv[2] * gv[2] + A.eps2);
+    return A.k_a + (den > 0.f ? A.k_d * fabsf(dot) / den : 0.f);
+}
+
+// Transfer function: colour and extinction by linear interpolation in the 256-entry LUT at the
+// normalised value, and the opacity 1 - exp(-sigma delta) of one step (Sections 3 and 5.3).
+__device__ __forceinline__ void lut_classify(const RenderArgs &A, const float4 *s_lut, float F, float dl, SampleVals &v) {
     v.F = F;
     const float u = __saturatef((F - A.v_lo) * A.inv_range);
     const float xs = 255.f * u;
@@ -900,13 +927,259 @@ __device__ __forceinline__ void eval_sample(const RenderArgs &A, const float4 *s
     v.g = lerpf(La.y, Lb.y, f);
     v.b = lerpf(La.z, Lb.z, f);
     v.sig = lerpf(La.w, Lb.w, f);
-    v.alpha = 1.f - exp2f(-v.sig * S.dl);
-    v.shade = 1.f;
-    if (LIT) {
-        v.dot = v.gv[0] * A.lhat[0] + v.gv[1] * A.lhat[1] + v.gv[2] * A.lhat[2];
-        v.den = sqrtf(v.gv[0] * v.gv[0] + v.gv[1] * v.gv[1] + v.gv[2] * v.gv[2] + A.eps2);
-        v.shade = A.k_a + (v.den > 0.f ? A.k_d * fabsf(v.dot) / v.den : 0.f);
+    v.alpha = 1.f - exp2f(-v.sig * dl);
+}
+
+template <bool LIT, bool REC, bool NEAR = false, int LAY = -1>
+__device__ __forceinline__ void eval_sample(const RenderArgs &A, const float4 *s_lut, const Ray &R, const Segment &S,
+                                            int k, SampleVals &v, Counters &cnt) {
+    const float kk = (float)k + 0.5f;
+    const float qx = S.q0[0] + kk * S.dq[0], qy = S.q0[1] + kk * S.dq[1], qz = S.q0[2] + kk * S.dq[2];
+    float F;
+    if (NEAR) {
+        F = nearest_sample<LIT, REC, LAY>(A, R, S, k, qx, qy, qz, v.gv, cnt);
+    } else if (LIT) {
+        // value and the six taps x +- h^l e_a from this brick in one fused stencil; a tap that
+        // leaves the brick is then read where it lands
+        float Fp[3], Fm[3];
+        const uint32_t clsbits = lit_stencil<REC, LAY>(A, S, qx, qy, qz, F, Fp, Fm);
+        uint32_t okbits = 0x3fu;
+        if (clsbits) {
+            if (REC) cnt.split++;
+            double xs[3];
+            sample_point(R, S, k, xs);
+            okbits = resolve_taps<REC, LAY>(A, S.leaf, S.patch, S.safe, &S.pv, xs, qx, qy, qz, clsbits, Fp, Fm, cnt);
+        }
+        lit_gradient(A, F, Fp, Fm, okbits, v.gv);
+    } else {
+        F = trilinear<REC, LAY>(A, S.pv, qx, qy, qz);
     }
+    lut_classify(A, s_lut, F, S.dl, v);
+    v.shade = LIT ? lit_shade(A, v.gv, v.dot, v.den) : 1.f;
+}
+
+// ------------------------------------------------------------------------------------------
+// Deferred gradient taps (lit forward kernels)
+// ------------------------------------------------------------------------------------------
+//
+// About a fifth of the lit samples of a large view have a gradient tap outside their brick.
+// Served where they occur, nearly every step of a wave waits on such a tap's dependent loads
+// (face record or tree descent, then a trilinear read) with one or two lanes busy.  Instead,
+// the in-brick part of such a sample is evaluated at once (value, colour and opacity from the
+// LUT, the in-brick taps).  Opacity and transmittance do not depend on the shading, so the ray
+// marches on, and the sample's remaining taps, gradient, shading and colour contribution wait
+// in a per-wave queue in LDS.  When the queue could not take one more sample from every
+// marching lane, the calling lanes resolve all queued samples together, one sample per lane.
+//
+// Each ray sums its colour in two accumulators, each in its own sample order: the samples
+// shaded at once (in registers), and the deferred ones (in LDS, added per owner in queue
+// order, which is the owner's sample order); the pixel is their sum.  So a ray's result does
+// not depend on which rays share its wave or on when the queue is resolved.
+
+constexpr int kTapQ = 96;   // queued samples per wave
+
+// A queued sample.  Per axis, g holds the finished central difference when neither tap of
+// the axis left the brick, else the in-brick tap value of the axis (or nothing).
+struct TapQueue {
+    double xs[3][kTapQ];           // FP64 sample position
+    float q[3][kTapQ];             // patch-local position; after resolution the contribution (r, g, b)
+    float g[4][kTapQ];             // F, then per axis as above
+    float ta[kTapQ], lf[kTapQ];    // T alpha; LUT fraction
+    int32_t leaf[kTapQ], patch[kTapQ];
+    uint32_t meta[kTapQ];          // owner lane | tap classes << 6 | LUT index << 18 | safe faces << 26
+    float cd[3][64];               // per lane: colour of its resolved deferred samples
+    uint32_t count, pad_;
+    unsigned long long bstart[2];  // bit j: the samples queued by one step start at slot j
+};
+
+// The block's queues (NW waves); a kernel that never calls this allocates no LDS for them.
+template <int NW>
+__device__ __forceinline__ TapQueue *tap_queues() {
+    __shared__ TapQueue q[NW];
+    return q;
+}
+
+__device__ __forceinline__ unsigned long long lanes_below(int lane) { return lane ? (~0ull >> (64 - lane)) : 0ull; }
+
+// Orders this wave's LDS accesses (the queue is written by some lanes and read by others).
+__device__ __forceinline__ void wave_lds_fence() {
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ uint32_t tq_count(TapQueue &Q) {
+    return __hip_atomic_load(&Q.count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+}
+
+__device__ __forceinline__ unsigned long long tq_bstart(TapQueue &Q, int w) {
+    return __hip_atomic_load(&Q.bstart[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+}
+
+__device__ __forceinline__ void tq_set(TapQueue &Q, uint32_t count, unsigned long long b0, unsigned long long b1) {
+    __hip_atomic_store(&Q.count, count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+    __hip_atomic_store(&Q.bstart[0], b0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+    __hip_atomic_store(&Q.bstart[1], b1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+}
+
+// All lanes of the wave: empty queue, zero deferred colour.
+__device__ __forceinline__ void tapq_init(TapQueue &Q, int lane) {
+    Q.cd[0][lane] = 0.f;
+    Q.cd[1][lane] = 0.f;
+    Q.cd[2][lane] = 0.f;
+    if (lane == 0) tq_set(Q, 0u, 0ull, 0ull);
+    wave_lds_fence();
+}
+
+// The calling (active) lanes resolve every queued sample: remaining taps, gradient, shading,
+// contribution; then each owner's deferred colour takes its contributions in queue order.
+template <bool REC, int LAY = -1>
+__device__ __forceinline__ void tapq_flush(const RenderArgs &A, const float4 *s_lut, TapQueue &Q, int lane,
+                                           Counters &cnt) {
+    const unsigned long long act = __ballot(1);
+    const uint32_t nact = (uint32_t)__popcll(act), rank = (uint32_t)__popcll(act & lanes_below(lane));
+    wave_lds_fence();
+    const uint32_t n = tq_count(Q);
+    for (uint32_t j = rank; j < n; j += nact) {
+        const double xs[3] = {Q.xs[0][j], Q.xs[1][j], Q.xs[2][j]};
+        const float F = Q.g[0][j];
+        const uint32_t m = Q.meta[j];
+        const uint32_t cls = (m >> 6) & 0xfffu, safe = m >> 26;
+        float Fp[3], Fm[3];
+        #pragma unroll
+        for (int a = 0; a < 3; a++) {
+            const float v = Q.g[1 + a][j];
+            Fp[a] = v;                 // the in-brick side; the other is replaced below
+            Fm[a] = v;
+        }
+        const uint32_t ok = resolve_taps<REC, LAY>(A, Q.leaf[j], Q.patch[j], safe, nullptr, xs, Q.q[0][j], Q.q[1][j],
+                                                   Q.q[2][j], cls, Fp, Fm, cnt);
+        float gv[3];
+        #pragma unroll
+        for (int a = 0; a < 3; a++) {
+            const bool outp = (cls >> (4 * a)) & 3u, outm = (cls >> (4 * a + 2)) & 3u;
+            gv[a] = (outp || outm) ? lit_gradient_axis(A, F, Fp[a], Fm[a], (ok >> (2 * a)) & 1u, (ok >> (2 * a + 1)) & 1u)
+                                   : Q.g[1 + a][j];
+        }
+        float dot, den;
+        const float wgt = Q.ta[j] * lit_shade(A, gv, dot, den);
+        const int i0 = (int)((m >> 18) & 0xffu);
+        const float f = Q.lf[j];
+        const float4 La = s_lut[i0], Lb = s_lut[i0 + 1];
+        Q.q[0][j] = wgt * lerpf(La.x, Lb.x, f);
+        Q.q[1][j] = wgt * lerpf(La.y, Lb.y, f);
+        Q.q[2][j] = wgt * lerpf(La.z, Lb.z, f);
+    }
+    wave_lds_fence();
+    // the samples of one step have distinct owners; steps are added one after the other
+    #pragma unroll
+    for (int w = 0; w < 2; w++) {
+        unsigned long long bs = tq_bstart(Q, w);
+        while (bs) {
+            const uint32_t s = 64u * w + (uint32_t)__builtin_ctzll(bs);
+            bs &= bs - 1ull;
+            uint32_t e = n;
+            if (bs) e = 64u * w + (uint32_t)__builtin_ctzll(bs);
+            else if (w == 0 && tq_bstart(Q, 1)) e = 64u + (uint32_t)__builtin_ctzll(tq_bstart(Q, 1));
+            for (uint32_t j = s + rank; j < e; j += nact) {
+                const uint32_t o = Q.meta[j] & 63u;
+                Q.cd[0][o] += Q.q[0][j];
+                Q.cd[1][o] += Q.q[1][j];
+                Q.cd[2][o] += Q.q[2][j];
+            }
+            wave_lds_fence();
+        }
+    }
+    if (rank == 0) tq_set(Q, 0u, 0ull, 0ull);
+    wave_lds_fence();
+}
+
+// At the top of a step, by the marching lanes: resolve the queue first unless it has a free
+// slot for each of them.
+template <bool REC, int LAY = -1>
+__device__ __forceinline__ void tapq_reserve(const RenderArgs &A, const float4 *s_lut, TapQueue &Q, int lane,
+                                             Counters &cnt) {
+    const unsigned long long act = __ballot(1);
+    if (tq_count(Q) + (uint32_t)__popcll(act) > (uint32_t)kTapQ) tapq_flush<REC, LAY>(A, s_lut, Q, lane, cnt);
+}
+
+// One lit sample of a marching lane with deferred taps: the in-brick part now; the sample is
+// queued when a tap leaves the brick, else shaded and added to (C0, C1, C2) at once.  Returns
+// the opacity.  All marching lanes call it in the same step, with a slot reserved for each.
+template <bool REC, int LAY = -1>
+__device__ __forceinline__ float lit_sample_deferred(const RenderArgs &A, const float4 *s_lut, TapQueue &Q, int lane,
+                                                     const Ray &R, const Segment &S, int k, float T, float &C0,
+                                                     float &C1, float &C2, Counters &cnt) {
+    const float kk = (float)k + 0.5f;
+    const float qx = S.q0[0] + kk * S.dq[0], qy = S.q0[1] + kk * S.dq[1], qz = S.q0[2] + kk * S.dq[2];
+    float F, Fp[3], Fm[3];
+    const uint32_t cls = lit_stencil<REC, LAY>(A, S, qx, qy, qz, F, Fp, Fm);
+    SampleVals v;
+    lut_classify(A, s_lut, F, S.dl, v);
+    const float Ta = T * v.alpha;
+    const bool defer = cls != 0;
+    if (!defer) {
+        float gv[3], dot, den;
+        lit_gradient(A, F, Fp, Fm, 0x3fu, gv);
+        const float wgt = Ta * lit_shade(A, gv, dot, den);
+        C0 += wgt * v.r;
+        C1 += wgt * v.g;
+        C2 += wgt * v.b;
+    }
+    const unsigned long long need = __ballot(defer);
+    if (need) {
+        const unsigned long long act = __ballot(1);
+        const uint32_t c0 = tq_count(Q);
+        if (defer) {
+            if (REC) cnt.split++;
+            const uint32_t j = c0 + (uint32_t)__popcll(need & lanes_below(lane));
+            if (j < (uint32_t)kTapQ) {          // always: a slot per lane was reserved
+                double xs[3];
+                sample_point(R, S, k, xs);
+                Q.xs[0][j] = xs[0];
+                Q.xs[1][j] = xs[1];
+                Q.xs[2][j] = xs[2];
+                Q.q[0][j] = qx;
+                Q.q[1][j] = qy;
+                Q.q[2][j] = qz;
+                Q.g[0][j] = F;
+                #pragma unroll
+                for (int a = 0; a < 3; a++) {
+                    const bool outp = (cls >> (4 * a)) & 3u, outm = (cls >> (4 * a + 2)) & 3u;
+                    Q.g[1 + a][j] = !(outp || outm) ? lit_gradient_axis(A, F, Fp[a], Fm[a], true, true)
+                                                    : (outp ? Fm[a] : Fp[a]);
+                }
+                Q.ta[j] = Ta;
+                Q.lf[j] = v.f;
+                Q.leaf[j] = S.leaf;
+                Q.patch[j] = S.patch;
+                Q.meta[j] = (uint32_t)lane | (cls << 6) | ((uint32_t)v.i0 << 18) | (S.safe << 26);
+            } else if (REC) {
+                cnt.guard++;
+            }
+        }
+        wave_lds_fence();
+        if (lane == __builtin_ctzll(act) && c0 < (uint32_t)kTapQ) {
+            const uint32_t c1 = min(c0 + (uint32_t)__popcll(need), (uint32_t)kTapQ);
+            unsigned long long b0 = tq_bstart(Q, 0), b1 = tq_bstart(Q, 1);
+            if (c0 < 64u) b0 |= 1ull << c0;
+            else b1 |= 1ull << (c0 - 64u);
+            tq_set(Q, c1, b0, b1);
+        }
+        wave_lds_fence();
+    }
+    return v.alpha;
+}
+
+// After the march, by all lanes of the wave: resolve what is queued; returns the lane's
+// deferred colour.
+template <bool REC, int LAY = -1>
+__device__ __forceinline__ void tapq_finish(const RenderArgs &A, const float4 *s_lut, TapQueue &Q, int lane,
+                                            Counters &cnt, float &D0, float &D1, float &D2) {
+    if (tq_count(Q)) tapq_flush<REC, LAY>(A, s_lut, Q, lane, cnt);
+    wave_lds_fence();
+    D0 = Q.cd[0][lane];
+    D1 = Q.cd[1][lane];
+    D2 = Q.cd[2][lane];
 }
 
 // ------------------------------------------------------------------------------------------
