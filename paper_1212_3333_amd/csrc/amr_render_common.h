@@ -31,6 +31,7 @@ struct RenderArgs {
     const DFaceXf *face_xf;          // [nleaves][6] gradient-tap records
     int32_t nearest;                 // 1: nearest-cell sampling instead of trilinear
     int32_t lod_on, nleaves;         // level of detail enabled; real leaves (kind-(a) records follow)
+    int32_t nrec, npatches;          // leaf records (real + kind-(a)); patch headers
     double lod;                      // pixels
     double lod_pix;                  // pixel footprint per unit distance (perspective) or per pixel
     double plight[3];                // lighting = 2: point-light position
@@ -1051,8 +1052,13 @@ __device__ __forceinline__ void tapq_flush(const RenderArgs &A, const float4 *s_
             Fp[a] = v;                 // the in-brick side; the other is replaced below
             Fm[a] = v;
         }
-        const uint32_t ok = resolve_taps<REC, LAY>(A, Q.leaf[j], Q.patch[j], safe, nullptr, xs, Q.q[0][j], Q.q[1][j],
-                                                   Q.q[2][j], cls, Fp, Fm, cnt);
+        const int leaf = Q.leaf[j], patch = Q.patch[j];
+        uint32_t ok = 0u;
+        if ((uint32_t)leaf < (uint32_t)A.nrec && (uint32_t)patch < (uint32_t)A.npatches)   // always
+            ok = resolve_taps<REC, LAY>(A, leaf, patch, safe, nullptr, xs, Q.q[0][j], Q.q[1][j], Q.q[2][j], cls, Fp,
+                                        Fm, cnt);
+        else if (REC)
+            cnt.guard++;
         float gv[3];
         #pragma unroll
         for (int a = 0; a < 3; a++) {
@@ -1246,6 +1252,8 @@ inline int fill_args(const amr_scene *S, const amr_camera *C, const amr_render_p
     A->lod_on = P->lod > 0.f && S->nlod > 0;
     A->lod = (double)P->lod;
     A->nleaves = S->nleaves;
+    A->nrec = S->nleaves + S->nlod;
+    A->npatches = S->npatches;
     A->lod_pix = C->ortho ? (2.0 * C->win[1]) / (double)C->height : (2.0 * C->tan_half_fov) / (double)C->height;
     A->lut = (const float4 *)P->d_lut;
     #pragma unroll
