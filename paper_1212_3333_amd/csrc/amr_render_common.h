@@ -785,14 +785,48 @@ __device__ __forceinline__ uint32_t lit_stencil(const RenderArgs &A, const Segme
     const bool inner = qx >= S.fs_lo[0] && qx < S.fs_hi[0] && qy >= S.fs_lo[1] && qy < S.fs_hi[1] &&
                        qz >= S.fs_lo[2] && qz < S.fs_hi[2];
     if (!inner) {
+        // With the sample inside the leaf box by the margin on every axis, a tap can only leave
+        // the box along its own axis, so that axis alone decides (the same classes as the full
+        // test below, which the rare samples within the margin of a box face take).
+        float lo[3], hi[3];
+        bool boxed = true;
         #pragma unroll
-        for (int a = 0; a < 3; a++)
+        for (int b = 0; b < 3; b++) {
+            seg_box(S, b, lo[b], hi[b]);
+            boxed = boxed && qc[b] >= lo[b] + kTapMargin && qc[b] < hi[b] - kTapMargin;
+        }
+        if (boxed) {
             #pragma unroll
-            for (int sgn = 0; sgn < 2; sgn++) {
-                float qt[3] = {qc[0], qc[1], qc[2]};
-                qt[a] += sgn ? -1.f : 1.f;
-                clsbits |= (uint32_t)classify_tap_fp32(S, qt, a, sgn) << (2 * (2 * a + sgn));
-            }
+            for (int a = 0; a < 3; a++)
+                #pragma unroll
+                for (int sgn = 0; sgn < 2; sgn++) {
+                    const float x = qc[a] + (sgn ? -1.f : 1.f);
+                    int c;
+                    if (x >= lo[a] + kTapMargin && x < hi[a] - kTapMargin) {
+                        c = kTapSame;
+                    } else if (x < lo[a] - kTapMargin || x >= hi[a] + kTapMargin) {
+                        // beyond the face: inside the one-cell slab there?
+                        const uint32_t face = 2u * a + (sgn ? 0u : 1u);
+                        const float lim = sgn ? lo[a] - 1.f : hi[a] + 1.f;
+                        const bool in_slab = sgn ? x >= lim + kTapMargin : x < lim - kTapMargin;
+                        const bool out_slab = sgn ? x < lim - kTapMargin : x >= lim + kTapMargin;
+                        c = in_slab ? (((S.safe >> face) & 1u) ? kTapSame : kTapFace)
+                                    : (out_slab ? kTapLocate : kTapUnsure);
+                    } else {
+                        c = kTapUnsure;
+                    }
+                    clsbits |= (uint32_t)c << (2 * (2 * a + sgn));
+                }
+        } else {
+            #pragma unroll
+            for (int a = 0; a < 3; a++)
+                #pragma unroll
+                for (int sgn = 0; sgn < 2; sgn++) {
+                    float qt[3] = {qc[0], qc[1], qc[2]};
+                    qt[a] += sgn ? -1.f : 1.f;
+                    clsbits |= (uint32_t)classify_tap_fp32(S, qt, a, sgn) << (2 * (2 * a + sgn));
+                }
+        }
     }
     F = trilinear_taps<REC, LAY>(A, S.pv, qx, qy, qz, Fp, Fm);
     return clsbits;
