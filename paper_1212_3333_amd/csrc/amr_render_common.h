@@ -658,6 +658,71 @@ __device__ __forceinline__ bool nearest_at(const RenderArgs &A, const double x[3
     return true;
 }
 
+// Classes of the six gradient taps q +- e_a of a sample at patch-local q (2 bits per tap
+// t = 2 a + sgn, sgn = 1 for the minus side; 0: in the brick), decided in fp32 against the tap
+// window; a class of kTapUnsure is decided later in FP64.
+__device__ __forceinline__ uint32_t classify_taps(const Segment &S, float qx, float qy, float qz) {
+    const float qc[3] = {qx, qy, qz};
+    uint32_t clsbits = 0;
+    const bool inner = qx >= S.fs_lo[0] && qx < S.fs_hi[0] && qy >= S.fs_lo[1] && qy < S.fs_hi[1] &&
+                       qz >= S.fs_lo[2] && qz < S.fs_hi[2];
+    if (!inner) {
+        // With the sample inside the leaf box by the margin on every axis, a tap can only leave
+        // the box along its own axis, so that axis alone decides (the same classes as the full
+        // test below, which the rare samples within the margin of a box face take).
+        float lo[3], hi[3];
+        bool boxed = true;
+        #pragma unroll
+        for (int b = 0; b < 3; b++) {
+            seg_box(S, b, lo[b], hi[b]);
+            boxed = boxed && qc[b] >= lo[b] + kTapMargin && qc[b] < hi[b] - kTapMargin;
+        }
+        if (boxed) {
+            #pragma unroll
+            for (int a = 0; a < 3; a++)
+                #pragma unroll
+                for (int sgn = 0; sgn < 2; sgn++) {
+                    const float x = qc[a] + (sgn ? -1.f : 1.f);
+                    int c;
+                    if (x >= lo[a] + kTapMargin && x < hi[a] - kTapMargin) {
+                        c = kTapSame;
+                    } else if (x < lo[a] - kTapMargin || x >= hi[a] + kTapMargin) {
+                        // beyond the face: inside the one-cell slab there?
+                        const uint32_t face = 2u * a + (sgn ? 0u : 1u);
+                        const float lim = sgn ? lo[a] - 1.f : hi[a] + 1.f;
+                        const bool in_slab = sgn ? x >= lim + kTapMargin : x < lim - kTapMargin;
+                        const bool out_slab = sgn ? x < lim - kTapMargin : x >= lim + kTapMargin;
+                        c = in_slab ? (((S.safe >> face) & 1u) ? kTapSame : kTapFace)
+                                    : (out_slab ? kTapLocate : kTapUnsure);
+                    } else {
+                        c = kTapUnsure;
+                    }
+                    clsbits |= (uint32_t)c << (2 * (2 * a + sgn));
+                }
+        } else {
+            #pragma unroll
+            for (int a = 0; a < 3; a++)
+                #pragma unroll
+                for (int sgn = 0; sgn < 2; sgn++) {
+                    float qt[3] = {qc[0], qc[1], qc[2]};
+                    qt[a] += sgn ? -1.f : 1.f;
+                    clsbits |= (uint32_t)classify_tap_fp32(S, qt, a, sgn) << (2 * (2 * a + sgn));
+                }
+        }
+    }
+    return clsbits;
+}
+
+// In-brick part of a lit sample at patch-local q: the value F and the six taps F(q +- e_a) from
+// one fused stencil of the segment's brick, and the classes of the taps (classify_taps).
+template <bool REC, int LAY = -1>
+__device__ __forceinline__ uint32_t lit_stencil(const RenderArgs &A, const Segment &S, float qx, float qy, float qz,
+                                                float &F, float Fp[3], float Fm[3]) {
+    const uint32_t clsbits = classify_taps(S, qx, qy, qz);
+    F = trilinear_taps<REC, LAY>(A, S.pv, qx, qy, qz, Fp, Fm);
+    return clsbits;
+}
+
 // Nearest-cell sampling (interp = 1): F(x) is the value of the cell of the finest patch that
 // holds x.  The cell index is taken in fp32 patch-local coordinates when the point is at least
 // the classification margin away from every cell face, else from the FP64 position exactly as
@@ -675,9 +740,10 @@ __device__ __forceinline__ float nearest_sample(const RenderArgs &A, const Ray &
         sure = sure && fr >= kTapMargin && fr <= 1.f - kTapMargin;
         ci[a] = (int)fl;
     }
+    const uint32_t clsbits = LIT ? classify_taps(S, qx, qy, qz) : 0u;
     const DPatch &P = A.patches[S.patch];
-    double x[3];
-    {
+    double x[3] = {0.0, 0.0, 0.0};
+    if (!sure || clsbits != 0u) {        // the FP64 sample position, where a cell or a tap needs it
 #pragma clang fp contract(off)
         const double tk = S.ta + ((double)k + 0.5) * S.delta;
         #pragma unroll
@@ -699,7 +765,7 @@ __device__ __forceinline__ float nearest_sample(const RenderArgs &A, const Ray &
             const int a = t >> 1, sgn = t & 1;
             float qt[3] = {qc[0], qc[1], qc[2]};
             qt[a] += sgn ? -1.f : 1.f;
-            const int c = classify_tap_fp32(S, qt, a, sgn);
+            const int c = (int)((clsbits >> (2 * t)) & 3u);
             if (sure && c == kTapSame) {
                 int cj[3] = {ci[0], ci[1], ci[2]};
                 cj[a] += sgn ? -1 : 1;
@@ -773,65 +839,6 @@ __device__ __forceinline__ float nearest_sample(const RenderArgs &A, const Ray &
 
 // Sample k of a segment: value, LUT classification, opacity over the step, and (LIT) the
 // gradient shading with taps at x +- h^l e_a located in the tree.
-// In-brick part of a lit sample at patch-local q: the value F and the six taps F(q +- e_a) from
-// one fused stencil of the segment's brick, and the class of every tap that leaves the brick
-// (2 bits per tap t = 2 a + sgn, sgn = 1 for the minus side; 0: in the brick).  Classified in
-// fp32 against the tap window; a class of kTapUnsure is decided later in FP64.
-template <bool REC, int LAY = -1>
-__device__ __forceinline__ uint32_t lit_stencil(const RenderArgs &A, const Segment &S, float qx, float qy, float qz,
-                                                float &F, float Fp[3], float Fm[3]) {
-    const float qc[3] = {qx, qy, qz};
-    uint32_t clsbits = 0;
-    const bool inner = qx >= S.fs_lo[0] && qx < S.fs_hi[0] && qy >= S.fs_lo[1] && qy < S.fs_hi[1] &&
-                       qz >= S.fs_lo[2] && qz < S.fs_hi[2];
-    if (!inner) {
-        // With the sample inside the leaf box by the margin on every axis, a tap can only leave
-        // the box along its own axis, so that axis alone decides (the same classes as the full
-        // test below, which the rare samples within the margin of a box face take).
-        float lo[3], hi[3];
-        bool boxed = true;
-        #pragma unroll
-        for (int b = 0; b < 3; b++) {
-            seg_box(S, b, lo[b], hi[b]);
-            boxed = boxed && qc[b] >= lo[b] + kTapMargin && qc[b] < hi[b] - kTapMargin;
-        }
-        if (boxed) {
-            #pragma unroll
-            for (int a = 0; a < 3; a++)
-                #pragma unroll
-                for (int sgn = 0; sgn < 2; sgn++) {
-                    const float x = qc[a] + (sgn ? -1.f : 1.f);
-                    int c;
-                    if (x >= lo[a] + kTapMargin && x < hi[a] - kTapMargin) {
-                        c = kTapSame;
-                    } else if (x < lo[a] - kTapMargin || x >= hi[a] + kTapMargin) {
-                        // beyond the face: inside the one-cell slab there?
-                        const uint32_t face = 2u * a + (sgn ? 0u : 1u);
-                        const float lim = sgn ? lo[a] - 1.f : hi[a] + 1.f;
-                        const bool in_slab = sgn ? x >= lim + kTapMargin : x < lim - kTapMargin;
-                        const bool out_slab = sgn ? x < lim - kTapMargin : x >= lim + kTapMargin;
-                        c = in_slab ? (((S.safe >> face) & 1u) ? kTapSame : kTapFace)
-                                    : (out_slab ? kTapLocate : kTapUnsure);
-                    } else {
-                        c = kTapUnsure;
-                    }
-                    clsbits |= (uint32_t)c << (2 * (2 * a + sgn));
-                }
-        } else {
-            #pragma unroll
-            for (int a = 0; a < 3; a++)
-                #pragma unroll
-                for (int sgn = 0; sgn < 2; sgn++) {
-                    float qt[3] = {qc[0], qc[1], qc[2]};
-                    qt[a] += sgn ? -1.f : 1.f;
-                    clsbits |= (uint32_t)classify_tap_fp32(S, qt, a, sgn) << (2 * (2 * a + sgn));
-                }
-        }
-    }
-    F = trilinear_taps<REC, LAY>(A, S.pv, qx, qy, qz, Fp, Fm);
-    return clsbits;
-}
-
 // FP64 position of sample k of a segment, o + t_k d (the point the gradient taps move from).
 __device__ __forceinline__ void sample_point(const Ray &R, const Segment &S, int k, double xs[3]) {
 #pragma clang fp contract(off)
