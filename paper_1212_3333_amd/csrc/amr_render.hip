@@ -23,9 +23,9 @@ namespace amr {
 // At least 3 waves per SIMD: the lit kernel then fits 168 VGPRs with a 12-byte spill instead
 // of running 2 waves at 171 (the unlit one needs 80 and runs 6).
 // LAY: the brick layout fixed at compile time for the timed variants (-1: read at run time).
-// Lit trilinear variants defer the samples whose gradient taps leave the brick (TapQueue),
-// except while recording checkpoints for the adjoint, whose (T, C) snapshots need every
-// earlier sample's colour.
+// Lit trilinear variants defer the samples whose gradient taps leave the brick (TapQueue).
+// While recording checkpoints for the adjoint, the queue is resolved before each segment fetch
+// that writes one, so a checkpoint's colour holds every earlier sample.
 template <bool LIT, bool REC, bool NEAR, int LAY>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void render_fwd(RenderArgs A) {
     constexpr bool kDefer = LIT && !NEAR;
@@ -71,7 +71,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void re
         ckh = reinterpret_cast<CkptHeader *>(A.ckpt + (A.ckpt_ray0 + ray) * A.ckpt_stride);
         ck = reinterpret_cast<Ckpt *>(ckh + 1);
     }
-    const bool defer = kDefer && !(REC && A.ckpt);      // wave-uniform
+    const bool defer = kDefer;
     if (kDefer && defer) {
         // Lit, deferred taps: the wave's lanes step together.  A step either fetches the next
         // data segment of the lanes that have none (once half of the live lanes wait, or
@@ -93,6 +93,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void re
             const bool waiting = alive && !has;
             const unsigned long long wait = __ballot(waiting);
             if (wait == live || 2 * __popcll(wait) >= __popcll(live)) {
+                if (REC && A.ckpt && tq_count(Q)) tapq_flush<REC, LAY>(A, s_lut, Q, lane, cnt);
                 if (waiting) {
                     while (true) {            // next segment with samples, or the end of the ray
                         if (!(tcur < R.t1)) { alive = false; break; }
@@ -104,6 +105,28 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void re
                         const int p = L.patch;
                         int n = 0;
                         if (p >= 0) {
+                            if (REC && ck) {
+                                if (dseg % every == 0) {
+                                    if (nck == A.ckpt_max) {     // full: keep every other, halve the rate
+                                        for (int i = 0; i < A.ckpt_max / 2; i++) ck[i] = ck[2 * i];
+                                        nck = A.ckpt_max / 2;
+                                        every *= 2;
+                                        cnt.ckover++;
+                                    }
+                                    if (dseg % every == 0) {     // colour: shaded at once + deferred, all resolved
+                                        Ckpt c;
+                                        c.t = tcur;
+                                        c.T = T;
+                                        c.C[0] = C0 + Q.cd[0][lane];
+                                        c.C[1] = C1 + Q.cd[1][lane];
+                                        c.C[2] = C2 + Q.cd[2][lane];
+                                        c.dseg = dseg;
+                                        c.sidx = nsamp_total;
+                                        ck[nck++] = c;
+                                    }
+                                }
+                                dseg++;
+                            }
                             setup_segment<LIT, LAY>(A, R, L, leaf, tcur, tb, S);
                             n = S.n;
                         }
