@@ -23,12 +23,13 @@ namespace amr {
 // At least 3 waves per SIMD: the lit kernel then fits 168 VGPRs with a 12-byte spill instead
 // of running 2 waves at 171 (the unlit one needs 80 and runs 6).
 // LAY: the brick layout fixed at compile time for the timed variants (-1: read at run time).
-// Lit trilinear variants defer the samples whose gradient taps leave the brick (TapQueue).
+// Lit variants defer the samples whose gradient taps leave the brick (trilinear) or need the
+// tree (nearest cell) to a per-wave queue (TapQueue).
 // While recording checkpoints for the adjoint, the queue is resolved before each segment fetch
 // that writes one, so a checkpoint's colour holds every earlier sample.
 template <bool LIT, bool REC, bool NEAR, int LAY>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void render_fwd(RenderArgs A) {
-    constexpr bool kDefer = LIT && !NEAR;
+    constexpr bool kDefer = LIT;
     __shared__ float4 s_lut[256];
     TapQueue *tq = nullptr;
     if constexpr (kDefer) tq = tap_queues<1>();
@@ -89,11 +90,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void re
             const unsigned long long live = __ballot(alive);
             if (!live) break;
             const unsigned long long samp = __ballot(has);
-            if (tq_count(Q) + (uint32_t)__popcll(samp) > (uint32_t)kTapQ) tapq_flush<REC, LAY>(A, s_lut, Q, lane, cnt);
+            if (tq_count(Q) + (uint32_t)__popcll(samp) > (uint32_t)kTapQ) tapq_flush<REC, LAY, NEAR>(A, s_lut, Q, lane, cnt);
             const bool waiting = alive && !has;
             const unsigned long long wait = __ballot(waiting);
             if (wait == live || 2 * __popcll(wait) >= __popcll(live)) {
-                if (REC && A.ckpt && tq_count(Q)) tapq_flush<REC, LAY>(A, s_lut, Q, lane, cnt);
+                if (REC && A.ckpt && tq_count(Q)) tapq_flush<REC, LAY, NEAR>(A, s_lut, Q, lane, cnt);
                 if (waiting) {
                     while (true) {            // next segment with samples, or the end of the ray
                         if (!(tcur < R.t1)) { alive = false; break; }
@@ -160,7 +161,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void re
                 continue;
             }
             if (has) {
-                const float alpha = lit_sample_deferred<REC, LAY>(A, s_lut, Q, lane, R, S, k, T, C0, C1, C2, cnt);
+                const float alpha = lit_sample_deferred<REC, LAY, NEAR>(A, s_lut, Q, lane, R, S, k, T, C0, C1, C2, cnt);
                 T *= 1.f - alpha;
                 nsamp_total++;
                 k++;
@@ -173,7 +174,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void re
             }
         }
         float D0, D1, D2;
-        tapq_finish<REC, LAY>(A, s_lut, Q, lane, cnt, D0, D1, D2);
+        tapq_finish<REC, LAY, NEAR>(A, s_lut, Q, lane, cnt, D0, D1, D2);
         C0 += D0;
         C1 += D1;
         C2 += D2;

@@ -931,6 +931,81 @@ __device__ __forceinline__ uint32_t resolve_taps(const RenderArgs &A, int leaf, 
     return okbits;
 }
 
+// The pending taps (bit t of pend) of a nearest-cell lit sample, one at a time: each reads the
+// cell of the finest patch holding the exact FP64 tap point xs +- h^l e_a.  A tap classified
+// in the sample's own patch takes its cell from the FP64 position; beyond a face whose slab has
+// a single owner, the cell under the mapped position when that is clear of the owner's cell
+// faces; otherwise a descent from the slab's rope node, else from the root.  leaf, patch and
+// safe describe the sample's segment, q its patch-local position, cls the fp32 classes.
+// Returns bit t set where tap t holds data.
+template <bool REC, int LAY = -1>
+__device__ __forceinline__ uint32_t resolve_taps_nearest(const RenderArgs &A, int leaf, int patch, uint32_t safe,
+                                                         const double xs[3], const float q[3], uint32_t cls,
+                                                         uint32_t pend, float Fp[3], float Fm[3], Counters &cnt) {
+    const DPatch &P = A.patches[patch];
+    uint32_t okbits = 0x3fu;
+    while (pend) {
+        const int t = __builtin_ctz(pend);
+        pend &= pend - 1u;
+        const int a = t >> 1, sgn = t & 1;
+        float qt[3] = {q[0], q[1], q[2]};
+        qt[a] += sgn ? -1.f : 1.f;
+        const int c = (int)((cls >> (2 * t)) & 3u);
+        double xt[3] = {xs[0], xs[1], xs[2]};
+        {
+#pragma clang fp contract(off)
+            xt[a] = sgn ? xs[a] - P.h[a] : xs[a] + P.h[a];
+        }
+        float val = 0.f;
+        bool ok = true, done = false;
+        if (REC && c == kTapUnsure) cnt.unsure++;
+        const int c2 = c == kTapUnsure ? classify_tap_fp64(A, leaf, patch, safe, xt, a, sgn) : c;
+        uint32_t from = 0;
+        if (c2 == kTapSame) {
+            // the tap lies where the sample's own patch is the finest: its cell, in FP64
+            const PatchView pv = patch_view<LAY>(A, P);
+            val = brick_cell<LAY>(A, pv, cell_index(xt[0], P.lo[0], P.h[0], P.n[0]),
+                                  cell_index(xt[1], P.lo[1], P.h[1], P.n[1]), cell_index(xt[2], P.lo[2], P.h[2], P.n[2]));
+            done = true;
+        } else if (c2 == kTapFace) {
+            const DFaceXf X = A.face_xf[6 * leaf + 2 * a + (sgn ? 0 : 1)];
+            if (X.n[0] > 0) {
+                const float qo[3] = {qt[0] * X.r + X.t[0], qt[1] * X.r + X.t[1], qt[2] * X.r + X.t[2]};
+                int co[3];
+                bool clear = true;
+                #pragma unroll
+                for (int b = 0; b < 3; b++) {
+                    const float u = qo[b] + 0.5f, fl = floorf(u), fr = u - fl;
+                    clear = clear && fr >= kTapMargin && fr <= 1.f - kTapMargin;
+                    co[b] = min(max((int)fl, 0), X.n[b] - 1);
+                }
+                if (clear) {
+                    PatchView pv;
+                    pv.brick = A.pool + X.off;
+                    pv.px = X.px;
+                    pv.pxy = X.pxy;
+                    pv.nx = X.n[0];
+                    pv.ny = X.n[1];
+                    pv.nz = X.n[2];
+                    val = brick_cell<LAY>(A, pv, co[0], co[1], co[2]);
+                    if (REC) cnt.face++;
+                    done = true;
+                }
+            } else if (X.rope > 0) {
+                from = (uint32_t)X.rope;
+            }
+        }
+        if (!done) ok = nearest_at<REC, LAY>(A, xt, &val, cnt, from);
+        if (!ok) okbits &= ~(1u << t);
+        #pragma unroll
+        for (int b = 0; b < 3; b++) {
+            Fp[b] = (t == 2 * b) ? val : Fp[b];
+            Fm[b] = (t == 2 * b + 1) ? val : Fm[b];
+        }
+    }
+    return okbits;
+}
+
 // Normalised-value gradient by central differences of the taps, one-sided where a tap holds no
 // data, zero where neither does.
 __device__ __forceinline__ float lit_gradient_axis(const RenderArgs &A, float F, float fp, float fm, bool okp, bool okm) {
@@ -1029,6 +1104,7 @@ struct TapQueue {
     float ta[kTapQ], lf[kTapQ];    // T alpha; LUT fraction
     int32_t leaf[kTapQ], patch[kTapQ];
     uint32_t meta[kTapQ];          // owner lane | tap classes << 6 | LUT index << 18 | safe faces << 26
+    uint32_t pend[kTapQ];          // taps left to resolve (bit t)
     float cd[3][64];               // per lane: colour of its resolved deferred samples
     uint32_t count, pad_;
     unsigned long long bstart[2];  // bit j: the samples queued by one step start at slot j
@@ -1074,7 +1150,7 @@ __device__ __forceinline__ void tapq_init(TapQueue &Q, int lane) {
 
 // The calling (active) lanes resolve every queued sample: remaining taps, gradient, shading,
 // contribution; then each owner's deferred colour takes its contributions in queue order.
-template <bool REC, int LAY = -1>
+template <bool REC, int LAY = -1, bool NEAR = false>
 __device__ __forceinline__ void tapq_flush(const RenderArgs &A, const float4 *s_lut, TapQueue &Q, int lane,
                                            Counters &cnt) {
     const unsigned long long act = __ballot(1);
@@ -1084,7 +1160,7 @@ __device__ __forceinline__ void tapq_flush(const RenderArgs &A, const float4 *s_
     for (uint32_t j = rank; j < n; j += nact) {
         const double xs[3] = {Q.xs[0][j], Q.xs[1][j], Q.xs[2][j]};
         const float F = Q.g[0][j];
-        const uint32_t m = Q.meta[j];
+        const uint32_t m = Q.meta[j], pend = Q.pend[j];
         const uint32_t cls = (m >> 6) & 0xfffu, safe = m >> 26;
         float Fp[3], Fm[3];
         #pragma unroll
@@ -1095,17 +1171,23 @@ __device__ __forceinline__ void tapq_flush(const RenderArgs &A, const float4 *s_
         }
         const int leaf = Q.leaf[j], patch = Q.patch[j];
         uint32_t ok = 0u;
-        if ((uint32_t)leaf < (uint32_t)A.nrec && (uint32_t)patch < (uint32_t)A.npatches)   // always
-            ok = resolve_taps<REC, LAY>(A, leaf, patch, safe, nullptr, xs, Q.q[0][j], Q.q[1][j], Q.q[2][j], cls, Fp,
-                                        Fm, cnt);
-        else if (REC)
+        if ((uint32_t)leaf < (uint32_t)A.nrec && (uint32_t)patch < (uint32_t)A.npatches) {   // always
+            if (NEAR) {
+                const float q[3] = {Q.q[0][j], Q.q[1][j], Q.q[2][j]};
+                ok = resolve_taps_nearest<REC, LAY>(A, leaf, patch, safe, xs, q, cls, pend, Fp, Fm, cnt);
+            } else {
+                ok = resolve_taps<REC, LAY>(A, leaf, patch, safe, nullptr, xs, Q.q[0][j], Q.q[1][j], Q.q[2][j], cls,
+                                            Fp, Fm, cnt);
+            }
+        } else if (REC) {
             cnt.guard++;
+        }
         float gv[3];
         #pragma unroll
         for (int a = 0; a < 3; a++) {
-            const bool outp = (cls >> (4 * a)) & 3u, outm = (cls >> (4 * a + 2)) & 3u;
-            gv[a] = (outp || outm) ? lit_gradient_axis(A, F, Fp[a], Fm[a], (ok >> (2 * a)) & 1u, (ok >> (2 * a + 1)) & 1u)
-                                   : Q.g[1 + a][j];
+            const bool pp = (pend >> (2 * a)) & 1u, pm = (pend >> (2 * a + 1)) & 1u;
+            gv[a] = (pp || pm) ? lit_gradient_axis(A, F, Fp[a], Fm[a], (ok >> (2 * a)) & 1u, (ok >> (2 * a + 1)) & 1u)
+                               : Q.g[1 + a][j];
         }
         float dot, den;
         const float wgt = Q.ta[j] * lit_shade(A, gv, dot, den);
@@ -1142,28 +1224,141 @@ __device__ __forceinline__ void tapq_flush(const RenderArgs &A, const float4 *s_
 
 // At the top of a step, by the marching lanes: resolve the queue first unless it has a free
 // slot for each of them.
-template <bool REC, int LAY = -1>
+template <bool REC, int LAY = -1, bool NEAR = false>
 __device__ __forceinline__ void tapq_reserve(const RenderArgs &A, const float4 *s_lut, TapQueue &Q, int lane,
                                              Counters &cnt) {
     const unsigned long long act = __ballot(1);
-    if (tq_count(Q) + (uint32_t)__popcll(act) > (uint32_t)kTapQ) tapq_flush<REC, LAY>(A, s_lut, Q, lane, cnt);
+    if (tq_count(Q) + (uint32_t)__popcll(act) > (uint32_t)kTapQ) tapq_flush<REC, LAY, NEAR>(A, s_lut, Q, lane, cnt);
+}
+
+// Queues a lit sample whose taps in `pend` are left to resolve (all marching lanes call it in
+// the same step, with a slot reserved for each; lanes with want = false queue nothing).
+// Fp/Fm hold the in-brick tap values; an axis with neither tap pending is stored as its
+// finished central difference, else as the in-brick side's value.
+__device__ __forceinline__ void tapq_push(const RenderArgs &A, TapQueue &Q, int lane, bool want, const Ray &R,
+                                          const Segment &S, int k, const double *xs_known, float qx, float qy,
+                                          float qz, float F, const float Fp[3], const float Fm[3], uint32_t cls,
+                                          uint32_t pend, float Ta, const SampleVals &v, Counters &cnt, bool rec) {
+    const unsigned long long need = __ballot(want);
+    if (!need) return;
+    const unsigned long long act = __ballot(1);
+    const uint32_t c0 = tq_count(Q);
+    if (want) {
+        if (rec) cnt.split++;
+        const uint32_t j = c0 + (uint32_t)__popcll(need & lanes_below(lane));
+        if (j < (uint32_t)kTapQ) {          // always: a slot per lane was reserved
+            double xs[3];
+            if (xs_known) {
+                xs[0] = xs_known[0];
+                xs[1] = xs_known[1];
+                xs[2] = xs_known[2];
+            } else {
+                sample_point(R, S, k, xs);
+            }
+            Q.xs[0][j] = xs[0];
+            Q.xs[1][j] = xs[1];
+            Q.xs[2][j] = xs[2];
+            Q.q[0][j] = qx;
+            Q.q[1][j] = qy;
+            Q.q[2][j] = qz;
+            Q.g[0][j] = F;
+            #pragma unroll
+            for (int a = 0; a < 3; a++) {
+                const bool pp = (pend >> (2 * a)) & 1u, pm = (pend >> (2 * a + 1)) & 1u;
+                Q.g[1 + a][j] = !(pp || pm) ? lit_gradient_axis(A, F, Fp[a], Fm[a], true, true) : (pp ? Fm[a] : Fp[a]);
+            }
+            Q.ta[j] = Ta;
+            Q.lf[j] = v.f;
+            Q.leaf[j] = S.leaf;
+            Q.patch[j] = S.patch;
+            Q.meta[j] = (uint32_t)lane | (cls << 6) | ((uint32_t)v.i0 << 18) | (S.safe << 26);
+            Q.pend[j] = pend;
+        } else if (rec) {
+            cnt.guard++;
+        }
+    }
+    wave_lds_fence();
+    if (lane == __builtin_ctzll(act) && c0 < (uint32_t)kTapQ) {
+        const uint32_t c1 = min(c0 + (uint32_t)__popcll(need), (uint32_t)kTapQ);
+        unsigned long long b0 = tq_bstart(Q, 0), b1 = tq_bstart(Q, 1);
+        if (c0 < 64u) b0 |= 1ull << c0;
+        else b1 |= 1ull << (c0 - 64u);
+        tq_set(Q, c1, b0, b1);
+    }
+    wave_lds_fence();
+}
+
+// Pending taps of a classified sample: bit t where tap t leaves the brick.
+__device__ __forceinline__ uint32_t pending_taps(uint32_t cls) {
+    uint32_t pend = 0;
+    #pragma unroll
+    for (int t = 0; t < 6; t++) pend |= ((cls >> (2 * t)) & 3u) ? (1u << t) : 0u;
+    return pend;
 }
 
 // One lit sample of a marching lane with deferred taps: the in-brick part now; the sample is
-// queued when a tap leaves the brick, else shaded and added to (C0, C1, C2) at once.  Returns
-// the opacity.  All marching lanes call it in the same step, with a slot reserved for each.
-template <bool REC, int LAY = -1>
+// queued when a tap leaves the brick (trilinear) or needs the tree (nearest cell), else shaded
+// and added to (C0, C1, C2) at once.  Returns the opacity.  All marching lanes call it in the
+// same step, after tapq_reserve.
+template <bool REC, int LAY = -1, bool NEAR = false>
 __device__ __forceinline__ float lit_sample_deferred(const RenderArgs &A, const float4 *s_lut, TapQueue &Q, int lane,
                                                      const Ray &R, const Segment &S, int k, float T, float &C0,
                                                      float &C1, float &C2, Counters &cnt) {
     const float kk = (float)k + 0.5f;
     const float qx = S.q0[0] + kk * S.dq[0], qy = S.q0[1] + kk * S.dq[1], qz = S.q0[2] + kk * S.dq[2];
     float F, Fp[3], Fm[3];
-    const uint32_t cls = lit_stencil<REC, LAY>(A, S, qx, qy, qz, F, Fp, Fm);
+    uint32_t cls, pend;
+    double xs[3] = {0.0, 0.0, 0.0};
+    bool have_xs = false;
+    if (NEAR) {
+        // the sample's cell and the taps one cell over in this brick; the rest needs the tree
+        const float qc[3] = {qx, qy, qz};
+        int ci[3];
+        bool sure = true;
+        #pragma unroll
+        for (int a = 0; a < 3; a++) {
+            const float u = qc[a] + 0.5f, fl = floorf(u), fr = u - fl;
+            sure = sure && fr >= kTapMargin && fr <= 1.f - kTapMargin;
+            ci[a] = (int)fl;
+        }
+        cls = classify_taps(S, qx, qy, qz);
+        pend = sure ? pending_taps(cls) : 0x3fu;
+        if (pend) {
+            sample_point(R, S, k, xs);
+            have_xs = true;
+        }
+        if (!sure) {
+            const DPatch &P = A.patches[S.patch];
+            #pragma unroll
+            for (int a = 0; a < 3; a++) ci[a] = cell_index(xs[a], P.lo[a], P.h[a], P.n[a]);
+        }
+        ci[0] = min(max(ci[0], 0), S.pv.nx - 1);
+        ci[1] = min(max(ci[1], 0), S.pv.ny - 1);
+        ci[2] = min(max(ci[2], 0), S.pv.nz - 1);
+        F = brick_cell<LAY>(A, S.pv, ci[0], ci[1], ci[2]);
+        #pragma unroll
+        for (int t = 0; t < 6; t++) {
+            const int a = t >> 1, sgn = t & 1;
+            float val = F;
+            if (!((pend >> t) & 1u)) {
+                int cj[3] = {ci[0], ci[1], ci[2]};
+                cj[a] += sgn ? -1 : 1;
+                cj[0] = min(max(cj[0], 0), S.pv.nx - 1);
+                cj[1] = min(max(cj[1], 0), S.pv.ny - 1);
+                cj[2] = min(max(cj[2], 0), S.pv.nz - 1);
+                val = brick_cell<LAY>(A, S.pv, cj[0], cj[1], cj[2]);
+            }
+            if (sgn) Fm[a] = val;
+            else Fp[a] = val;
+        }
+    } else {
+        cls = lit_stencil<REC, LAY>(A, S, qx, qy, qz, F, Fp, Fm);
+        pend = pending_taps(cls);
+    }
     SampleVals v;
     lut_classify(A, s_lut, F, S.dl, v);
     const float Ta = T * v.alpha;
-    const bool defer = cls != 0;
+    const bool defer = pend != 0;
     if (!defer) {
         float gv[3], dot, den;
         lit_gradient(A, F, Fp, Fm, 0x3fu, gv);
@@ -1172,57 +1367,16 @@ __device__ __forceinline__ float lit_sample_deferred(const RenderArgs &A, const 
         C1 += wgt * v.g;
         C2 += wgt * v.b;
     }
-    const unsigned long long need = __ballot(defer);
-    if (need) {
-        const unsigned long long act = __ballot(1);
-        const uint32_t c0 = tq_count(Q);
-        if (defer) {
-            if (REC) cnt.split++;
-            const uint32_t j = c0 + (uint32_t)__popcll(need & lanes_below(lane));
-            if (j < (uint32_t)kTapQ) {          // always: a slot per lane was reserved
-                double xs[3];
-                sample_point(R, S, k, xs);
-                Q.xs[0][j] = xs[0];
-                Q.xs[1][j] = xs[1];
-                Q.xs[2][j] = xs[2];
-                Q.q[0][j] = qx;
-                Q.q[1][j] = qy;
-                Q.q[2][j] = qz;
-                Q.g[0][j] = F;
-                #pragma unroll
-                for (int a = 0; a < 3; a++) {
-                    const bool outp = (cls >> (4 * a)) & 3u, outm = (cls >> (4 * a + 2)) & 3u;
-                    Q.g[1 + a][j] = !(outp || outm) ? lit_gradient_axis(A, F, Fp[a], Fm[a], true, true)
-                                                    : (outp ? Fm[a] : Fp[a]);
-                }
-                Q.ta[j] = Ta;
-                Q.lf[j] = v.f;
-                Q.leaf[j] = S.leaf;
-                Q.patch[j] = S.patch;
-                Q.meta[j] = (uint32_t)lane | (cls << 6) | ((uint32_t)v.i0 << 18) | (S.safe << 26);
-            } else if (REC) {
-                cnt.guard++;
-            }
-        }
-        wave_lds_fence();
-        if (lane == __builtin_ctzll(act) && c0 < (uint32_t)kTapQ) {
-            const uint32_t c1 = min(c0 + (uint32_t)__popcll(need), (uint32_t)kTapQ);
-            unsigned long long b0 = tq_bstart(Q, 0), b1 = tq_bstart(Q, 1);
-            if (c0 < 64u) b0 |= 1ull << c0;
-            else b1 |= 1ull << (c0 - 64u);
-            tq_set(Q, c1, b0, b1);
-        }
-        wave_lds_fence();
-    }
+    tapq_push(A, Q, lane, defer, R, S, k, have_xs ? xs : nullptr, qx, qy, qz, F, Fp, Fm, cls, pend, Ta, v, cnt, REC);
     return v.alpha;
 }
 
 // After the march, by all lanes of the wave: resolve what is queued; returns the lane's
 // deferred colour.
-template <bool REC, int LAY = -1>
+template <bool REC, int LAY = -1, bool NEAR = false>
 __device__ __forceinline__ void tapq_finish(const RenderArgs &A, const float4 *s_lut, TapQueue &Q, int lane,
                                             Counters &cnt, float &D0, float &D1, float &D2) {
-    if (tq_count(Q)) tapq_flush<REC, LAY>(A, s_lut, Q, lane, cnt);
+    if (tq_count(Q)) tapq_flush<REC, LAY, NEAR>(A, s_lut, Q, lane, cnt);
     wave_lds_fence();
     D0 = Q.cd[0][lane];
     D1 = Q.cd[1][lane];
