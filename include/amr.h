@@ -283,7 +283,9 @@ int amr_render(const amr_scene *scene, const amr_camera *cams, int32_t ncams,
 /* Persistent mode (params.persistent = 1): one launch renders all cameras; waves take 64-pixel
  * tiles (tile_w x tile_h) from a device queue ordered largest image first; the launch and its
  * setup are device-only work, so the call may be captured in a hipGraph.  Needs d_queue and
- * d_cams; images are identical to the non-persistent path's. */
+ * d_cams; images are identical to the non-persistent path's.  Trilinear sampling with
+ * lighting 0 or 1 only: nearest-cell sampling, the point light, learned proposals, segment
+ * logging, traces and checkpoints are rejected with AMR_EINVAL. */
 /* Bytes of device scratch the persistent batched kernel needs for ncams cameras. */
 int64_t amr_queue_bytes(int32_t ncams);
 /* Rate of the device clock written to d_stamps, in kHz. */

@@ -450,6 +450,10 @@ int amr_render(const amr_scene *S, const amr_camera *cams, int32_t ncams, const 
                   "(not persistent, learned, logging or checkpointed)");
         return AMR_EINVAL;
     }
+    if (P->persistent && (P->d_mlp || P->d_seglog)) {
+        set_error("learned proposals and segment logging run in their own kernel (not persistent)");
+        return AMR_EINVAL;
+    }
     if (P->persistent) return launch_persistent(S, cams, ncams, P, d_rgba, d_stats, stream);
     hipStream_t s = (hipStream_t)stream;
     if (d_stats) {

@@ -308,6 +308,10 @@ def test_nearest_rejected_outside_plain_forward(gpu):
         amr.render_checkpointed(scene, cams[0], lut_t, dict(prm, interp=1))
     with pytest.raises(amr.AMRError, match="interp"):
         amr.render(scene, cams[0], lut_t, dict(prm, interp=2))
+    two = [cams[0], cams[1]]
+    with pytest.raises(amr.AMRError, match="nearest"):
+        amr.render(scene, two, lut_t, dict(prm, interp=1, persistent=1), d_cams=amr.camera_table(two),
+                   d_queue=amr.queue_buffer(2))
 
 
 @pytest.mark.parametrize("lit", [False, True])
@@ -394,4 +398,8 @@ def test_point_light_rejected_elsewhere(gpu):
         amr.render(scene, cams[0], lut_t, dict(prm, lighting=2, lod=2.0))
     with pytest.raises(amr.AMRError, match="lighting"):
         amr.render(scene, cams[0], lut_t, dict(prm, lighting=3))
+    two = [cams[0], cams[1]]
+    with pytest.raises(amr.AMRError, match="point-light"):
+        amr.render(scene, two, lut_t, dict(prm, lighting=2, persistent=1), d_cams=amr.camera_table(two),
+                   d_queue=amr.queue_buffer(2))
 
