@@ -72,13 +72,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void re
         ckh = reinterpret_cast<CkptHeader *>(A.ckpt + (A.ckpt_ray0 + ray) * A.ckpt_stride);
         ck = reinterpret_cast<Ckpt *>(ckh + 1);
     }
-    const bool defer = kDefer;
-    if (kDefer && defer) {
+    if constexpr (kDefer) {
         // Lit, deferred taps: the wave's lanes step together.  A step either fetches the next
         // data segment of the lanes that have none (once half of the live lanes wait, or
         // all do) or takes one sample on every lane that has a segment; the tap queue is
-        // resolved at the top of a step, where every lane of the wave works on it.  The rays'
-        // arithmetic and traces are those of the per-segment loop below.
+        // resolved at the top of a step, where every lane of the wave works on it.  Segments,
+        // sample positions and traces are those of the per-segment loop of the unlit variants
+        // below.
         TapQueue &Q = *tq;
         tapq_init(Q, lane);
         double tcur = R.t0;

@@ -723,120 +723,6 @@ __device__ __forceinline__ uint32_t lit_stencil(const RenderArgs &A, const Segme
     return clsbits;
 }
 
-// Nearest-cell sampling (interp = 1): F(x) is the value of the cell of the finest patch that
-// holds x.  The cell index is taken in fp32 patch-local coordinates when the point is at least
-// the classification margin away from every cell face, else from the FP64 position exactly as
-// defined; taps x +- h^l e_a step one cell in the same brick when they stay in it, else they
-// are located in the tree from their FP64 position.
-template <bool LIT, bool REC, int LAY = -1>
-__device__ __forceinline__ float nearest_sample(const RenderArgs &A, const Ray &R, const Segment &S, int k, float qx,
-                                                float qy, float qz, float gv[3], Counters &cnt) {
-    const float qc[3] = {qx, qy, qz};
-    int ci[3];
-    bool sure = true;
-    #pragma unroll
-    for (int a = 0; a < 3; a++) {
-        const float u = qc[a] + 0.5f, fl = floorf(u), fr = u - fl;
-        sure = sure && fr >= kTapMargin && fr <= 1.f - kTapMargin;
-        ci[a] = (int)fl;
-    }
-    const uint32_t clsbits = LIT ? classify_taps(S, qx, qy, qz) : 0u;
-    const DPatch &P = A.patches[S.patch];
-    double x[3] = {0.0, 0.0, 0.0};
-    if (!sure || clsbits != 0u) {        // the FP64 sample position, where a cell or a tap needs it
-#pragma clang fp contract(off)
-        const double tk = S.ta + ((double)k + 0.5) * S.delta;
-        #pragma unroll
-        for (int b = 0; b < 3; b++) x[b] = R.o[b] + tk * R.d[b];
-    }
-    if (!sure) {
-        #pragma unroll
-        for (int a = 0; a < 3; a++) ci[a] = cell_index(x[a], P.lo[a], P.h[a], P.n[a]);
-    }
-    ci[0] = min(max(ci[0], 0), S.pv.nx - 1);
-    ci[1] = min(max(ci[1], 0), S.pv.ny - 1);
-    ci[2] = min(max(ci[2], 0), S.pv.nz - 1);
-    const float F = brick_cell<LAY>(A, S.pv, ci[0], ci[1], ci[2]);
-    if (LIT) {
-        float Fs[6];
-        uint32_t okbits = 0x3fu;
-        #pragma unroll
-        for (int t = 0; t < 6; t++) {
-            const int a = t >> 1, sgn = t & 1;
-            float qt[3] = {qc[0], qc[1], qc[2]};
-            qt[a] += sgn ? -1.f : 1.f;
-            const int c = (int)((clsbits >> (2 * t)) & 3u);
-            if (sure && c == kTapSame) {
-                int cj[3] = {ci[0], ci[1], ci[2]};
-                cj[a] += sgn ? -1 : 1;
-                cj[0] = min(max(cj[0], 0), S.pv.nx - 1);
-                cj[1] = min(max(cj[1], 0), S.pv.ny - 1);
-                cj[2] = min(max(cj[2], 0), S.pv.nz - 1);
-                Fs[t] = brick_cell<LAY>(A, S.pv, cj[0], cj[1], cj[2]);
-            } else {
-                double xt[3] = {x[0], x[1], x[2]};
-                {
-#pragma clang fp contract(off)
-                    xt[a] = sgn ? x[a] - P.h[a] : x[a] + P.h[a];
-                }
-                float val = 0.f;
-                bool ok = true, done = false;
-                const int c2 = c == kTapUnsure ? classify_tap_fp64(A, S, xt, a, sgn) : c;
-                uint32_t from = 0;
-                if (c2 == kTapSame) {
-                    // the tap lies where the sample's own patch is the finest: its cell, in FP64
-                    val = brick_cell<LAY>(A, S.pv, cell_index(xt[0], P.lo[0], P.h[0], P.n[0]),
-                                          cell_index(xt[1], P.lo[1], P.h[1], P.n[1]), cell_index(xt[2], P.lo[2], P.h[2], P.n[2]));
-                    done = true;
-                } else if (c2 == kTapFace) {
-                    const DFaceXf X = A.face_xf[6 * S.leaf + 2 * a + (sgn ? 0 : 1)];
-                    if (X.n[0] > 0) {
-                        // the slab's single owner: the cell under the mapped position when it is
-                        // clear of the owner's cell faces, else the FP64 location below
-                        const float qo[3] = {qt[0] * X.r + X.t[0], qt[1] * X.r + X.t[1], qt[2] * X.r + X.t[2]};
-                        int co[3];
-                        bool clear = true;
-                        #pragma unroll
-                        for (int b = 0; b < 3; b++) {
-                            const float u = qo[b] + 0.5f, fl = floorf(u), fr = u - fl;
-                            clear = clear && fr >= kTapMargin && fr <= 1.f - kTapMargin;
-                            co[b] = min(max((int)fl, 0), X.n[b] - 1);
-                        }
-                        if (clear) {
-                            PatchView pv;
-                            pv.brick = A.pool + X.off;
-                            pv.px = X.px;
-                            pv.pxy = X.pxy;
-                            pv.nx = X.n[0];
-                            pv.ny = X.n[1];
-                            pv.nz = X.n[2];
-                            val = brick_cell<LAY>(A, pv, co[0], co[1], co[2]);
-                            if (REC) cnt.face++;
-                            done = true;
-                        }
-                    } else if (X.rope > 0) {
-                        from = (uint32_t)X.rope;
-                    }
-                }
-                if (!done) ok = nearest_at<REC, LAY>(A, xt, &val, cnt, from);
-                if (!ok) okbits &= ~(1u << t);
-                Fs[t] = val;
-            }
-        }
-        #pragma unroll
-        for (int a = 0; a < 3; a++) {
-            const bool okp = (okbits >> (2 * a)) & 1u, okm = (okbits >> (2 * a + 1)) & 1u;
-            float gr;
-            if (okp && okm) gr = (Fs[2 * a] - Fs[2 * a + 1]) * (0.5f * A.inv_range);
-            else if (okp) gr = (Fs[2 * a] - F) * A.inv_range;
-            else if (okm) gr = (F - Fs[2 * a + 1]) * A.inv_range;
-            else gr = 0.f;
-            gv[a] = gr;
-        }
-    }
-    return F;
-}
-
 // Sample k of a segment: value, LUT classification, opacity over the step, and (LIT) the
 // gradient shading with taps at x +- h^l e_a located in the tree.
 // FP64 position of sample k of a segment, o + t_k d (the point the gradient taps move from).
@@ -1047,14 +933,44 @@ __device__ __forceinline__ void lut_classify(const RenderArgs &A, const float4 *
     v.alpha = 1.f - exp2f(-v.sig * dl);
 }
 
+// Nearest-cell sampling (interp = 1): F(x) is the value of the cell of the finest patch that
+// holds x.  The cell index is taken in fp32 patch-local coordinates when the point is at least
+// the classification margin away from every cell face, else from the FP64 position exactly as
+// defined.  (Lit nearest-cell samples take their taps through the tap queue.)
+template <int LAY = -1>
+__device__ __forceinline__ float nearest_value(const RenderArgs &A, const Ray &R, const Segment &S, int k, float qx,
+                                               float qy, float qz) {
+    const float qc[3] = {qx, qy, qz};
+    int ci[3];
+    bool sure = true;
+    #pragma unroll
+    for (int a = 0; a < 3; a++) {
+        const float u = qc[a] + 0.5f, fl = floorf(u), fr = u - fl;
+        sure = sure && fr >= kTapMargin && fr <= 1.f - kTapMargin;
+        ci[a] = (int)fl;
+    }
+    if (!sure) {
+        const DPatch &P = A.patches[S.patch];
+        double x[3];
+        sample_point(R, S, k, x);
+        #pragma unroll
+        for (int a = 0; a < 3; a++) ci[a] = cell_index(x[a], P.lo[a], P.h[a], P.n[a]);
+    }
+    ci[0] = min(max(ci[0], 0), S.pv.nx - 1);
+    ci[1] = min(max(ci[1], 0), S.pv.ny - 1);
+    ci[2] = min(max(ci[2], 0), S.pv.nz - 1);
+    return brick_cell<LAY>(A, S.pv, ci[0], ci[1], ci[2]);
+}
+
 template <bool LIT, bool REC, bool NEAR = false, int LAY = -1>
 __device__ __forceinline__ void eval_sample(const RenderArgs &A, const float4 *s_lut, const Ray &R, const Segment &S,
                                             int k, SampleVals &v, Counters &cnt) {
     const float kk = (float)k + 0.5f;
     const float qx = S.q0[0] + kk * S.dq[0], qy = S.q0[1] + kk * S.dq[1], qz = S.q0[2] + kk * S.dq[2];
     float F;
-    if (NEAR) {
-        F = nearest_sample<LIT, REC, LAY>(A, R, S, k, qx, qy, qz, v.gv, cnt);
+    if constexpr (NEAR) {
+        static_assert(!LIT, "lit nearest-cell samples take the tap queue (lit_sample_deferred)");
+        F = nearest_value<LAY>(A, R, S, k, qx, qy, qz);
     } else if (LIT) {
         // value and the six taps x +- h^l e_a from this brick in one fused stencil; a tap that
         // leaves the brick is then read where it lands
