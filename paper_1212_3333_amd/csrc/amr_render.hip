@@ -6,7 +6,9 @@
 // taps) are written with contraction disabled so that every operation is correctly rounded
 // exactly once; the per-sample arithmetic (trilinear, LUT, exp, compositing) is fp32 in
 // patch-local cell coordinates.  Forward and adjoint evaluate samples with the same device
-// function, so the adjoint replays the forward's values.
+// functions (stencil, tap resolution, LUT, shading), so the adjoint replays the forward's sample
+// values; the lit forward defers samples whose taps leave the brick to a per-wave queue and
+// sums their colour separately, which changes a pixel by rounding only.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
