@@ -1151,16 +1151,17 @@ __device__ __forceinline__ void tapq_reserve(const RenderArgs &A, const float4 *
 // the same step, with a slot reserved for each; lanes with want = false queue nothing).
 // Fp/Fm hold the in-brick tap values; an axis with neither tap pending is stored as its
 // finished central difference, else as the in-brick side's value.
+template <bool REC>
 __device__ __forceinline__ void tapq_push(const RenderArgs &A, TapQueue &Q, int lane, bool want, const Ray &R,
                                           const Segment &S, int k, const double *xs_known, float qx, float qy,
                                           float qz, float F, const float Fp[3], const float Fm[3], uint32_t cls,
-                                          uint32_t pend, float Ta, const SampleVals &v, Counters &cnt, bool rec) {
+                                          uint32_t pend, float Ta, const SampleVals &v, Counters &cnt) {
     const unsigned long long need = __ballot(want);
     if (!need) return;
     const unsigned long long act = __ballot(1);
     const uint32_t c0 = tq_count(Q);
     if (want) {
-        if (rec) cnt.split++;
+        if (REC) cnt.split++;
         const uint32_t j = c0 + (uint32_t)__popcll(need & lanes_below(lane));
         if (j < (uint32_t)kTapQ) {          // always: a slot per lane was reserved
             double xs[3];
@@ -1189,7 +1190,7 @@ __device__ __forceinline__ void tapq_push(const RenderArgs &A, TapQueue &Q, int 
             Q.patch[j] = S.patch;
             Q.meta[j] = (uint32_t)lane | (cls << 6) | ((uint32_t)v.i0 << 18) | (S.safe << 26);
             Q.pend[j] = pend;
-        } else if (rec) {
+        } else if (REC) {
             cnt.guard++;
         }
     }
@@ -1283,7 +1284,7 @@ __device__ __forceinline__ float lit_sample_deferred(const RenderArgs &A, const 
         C1 += wgt * v.g;
         C2 += wgt * v.b;
     }
-    tapq_push(A, Q, lane, defer, R, S, k, have_xs ? xs : nullptr, qx, qy, qz, F, Fp, Fm, cls, pend, Ta, v, cnt, REC);
+    tapq_push<REC>(A, Q, lane, defer, R, S, k, have_xs ? xs : nullptr, qx, qy, qz, F, Fp, Fm, cls, pend, Ta, v, cnt);
     return v.alpha;
 }
 
