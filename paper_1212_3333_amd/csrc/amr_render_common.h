@@ -995,14 +995,15 @@ __device__ __forceinline__ void eval_sample(const RenderArgs &A, const float4 *s
 // Deferred gradient taps (lit forward kernels)
 // ------------------------------------------------------------------------------------------
 //
-// About a fifth of the lit samples of a large view have a gradient tap outside their brick.
-// Served where they occur, nearly every step of a wave waits on such a tap's dependent loads
-// (face record or tree descent, then a trilinear read) with one or two lanes busy.  Instead,
-// the in-brick part of such a sample is evaluated at once (value, colour and opacity from the
-// LUT, the in-brick taps).  Opacity and transmittance do not depend on the shading, so the ray
-// marches on, and the sample's remaining taps, gradient, shading and colour contribution wait
-// in a per-wave queue in LDS.  When the queue could not take one more sample from every
-// marching lane, the calling lanes resolve all queued samples together, one sample per lane.
+// About a fifth of the lit samples of a large view have a gradient tap outside their brick
+// (trilinear), or one that needs the tree (nearest cell).  Served where they occur, nearly every
+// step of a wave waits on such a tap's dependent loads (face record or tree descent, then a
+// brick read) with one or two lanes busy.  Instead, the in-brick part of such a sample is
+// evaluated at once (value, colour and opacity from the LUT, the in-brick taps).  Opacity and
+// transmittance do not depend on the shading, so the ray marches on, and the sample's pending
+// taps, gradient, shading and colour contribution wait in a per-wave queue in LDS.  When the
+// queue could not take one more sample from every marching lane, the calling lanes resolve all
+// queued samples together, one sample per lane.
 //
 // Each ray sums its colour in two accumulators, each in its own sample order: the samples
 // shaded at once (in registers), and the deferred ones (in LDS, added per owner in queue
@@ -1012,7 +1013,7 @@ __device__ __forceinline__ void eval_sample(const RenderArgs &A, const float4 *s
 constexpr int kTapQ = 96;   // queued samples per wave
 
 // A queued sample.  Per axis, g holds the finished central difference when neither tap of
-// the axis left the brick, else the in-brick tap value of the axis (or nothing).
+// the axis is pending, else the value of the tap that is not (or nothing).
 struct TapQueue {
     double xs[3][kTapQ];           // FP64 sample position
     float q[3][kTapQ];             // patch-local position; after resolution the contribution (r, g, b)
