@@ -16,6 +16,8 @@
 #include <map>
 #include <new>
 #include <numeric>
+#include <unordered_map>
+#include <utility>
 #include <vector>
 
 #include "amr.h"
@@ -44,6 +46,9 @@ struct amr_store {
     std::vector<int64_t> rbox;           // per record: lo[3], hi[3]
     std::vector<int32_t> chain_at, chain;  // per record: patches holding its box, coarse to fine
     std::vector<int32_t> lod_node;       // per kind-(a) record: its device node index
+    // value range of record k drawn from holder patch h, keyed (k << 32) | h (the scan of the
+    // holder's cells depends on nothing else, and an orbit remaps the same records again)
+    std::unordered_map<uint64_t, std::pair<float, float>> range_memo;
     // cache state
     void *cache = nullptr;
     int64_t cache_floats = 0;
@@ -469,7 +474,15 @@ int amr_store_update(amr_store *s, const uint8_t *resident, void *d_cache, int64
             if (h >= 0) {
                 L[k].patch = h;
                 L[k].level_flags = (uint32_t)s->plevel[h];
-                leaf_range(s, h, &s->rbox[6 * k], &s->rbox[6 * k + 3], &L[k].vmin, &L[k].vmax);
+                const uint64_t key = ((uint64_t)k << 32) | (uint32_t)h;
+                auto it = s->range_memo.find(key);
+                if (it == s->range_memo.end()) {
+                    float mn, mx;
+                    leaf_range(s, h, &s->rbox[6 * k], &s->rbox[6 * k + 3], &mn, &mx);
+                    it = s->range_memo.emplace(key, std::make_pair(mn, mx)).first;
+                }
+                L[k].vmin = it->second.first;
+                L[k].vmax = it->second.second;
             } else {
                 L[k].patch = -1;
                 L[k].level_flags &= 0xffu;
