@@ -22,8 +22,8 @@ namespace amr {
 // Forward kernel
 // ------------------------------------------------------------------------------------------
 
-// At least 3 waves per SIMD: the lit kernel then fits 168 VGPRs with a 12-byte spill instead
-// of running 2 waves at 171 (the unlit one needs 80 and runs 6).
+// At least 3 waves per SIMD: the timed lit kernel fits in 158 VGPRs without spilling and 12 KB
+// of LDS (its tap queue), so 12 waves share a CU; the unlit one needs 78 VGPRs and runs 6.
 // LAY: the brick layout fixed at compile time for the timed variants (-1: read at run time).
 // Lit variants defer the samples whose gradient taps leave the brick (trilinear) or need the
 // tree (nearest cell) to a per-wave queue (TapQueue).

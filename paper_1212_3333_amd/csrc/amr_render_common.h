@@ -723,8 +723,6 @@ __device__ __forceinline__ uint32_t lit_stencil(const RenderArgs &A, const Segme
     return clsbits;
 }
 
-// Sample k of a segment: value, LUT classification, opacity over the step, and (LIT) the
-// gradient shading with taps at x +- h^l e_a located in the tree.
 // FP64 position of sample k of a segment, o + t_k d (the point the gradient taps move from).
 __device__ __forceinline__ void sample_point(const Ray &R, const Segment &S, int k, double xs[3]) {
 #pragma clang fp contract(off)
@@ -962,6 +960,9 @@ __device__ __forceinline__ float nearest_value(const RenderArgs &A, const Ray &R
     return brick_cell<LAY>(A, S.pv, ci[0], ci[1], ci[2]);
 }
 
+// Sample k of a segment, every part in place: value, LUT classification, opacity over the step,
+// and (LIT) the gradient shading with taps at x +- h^l e_a, those outside the brick read where
+// they land.  The adjoint, the learned kernel and the unlit forward variants sample this way.
 template <bool LIT, bool REC, bool NEAR = false, int LAY = -1>
 __device__ __forceinline__ void eval_sample(const RenderArgs &A, const float4 *s_lut, const Ray &R, const Segment &S,
                                             int k, SampleVals &v, Counters &cnt) {
