@@ -535,6 +535,7 @@ def main():
         "samples_per_frame": int(samples),
         "segments_per_frame": int(st["segments"]),
         "tap_descents_per_frame": int(st["tap_descents"]),
+        "deferred_tap_samples_per_frame": int(st["split_samples"]),
         "unlit_ms_per_step": round(unlit_ms, 4) if unlit_ms else None,
         "preprocess_s": {"generate": round(gen_s, 2), "build": round(build_s, 4), "pack_upload": round(pack_s, 3)},
         "roofline": roof,
