@@ -458,29 +458,6 @@ __device__ __forceinline__ bool locate_brick(const RenderArgs &A, const double x
     return true;
 }
 
-// Field value at world point x located in the tree; false where no patch holds data or x is
-// outside B (closed).
-template <bool REC, int LAY = -1>
-__device__ __forceinline__ bool field_at(const RenderArgs &A, const double x[3], float *val, Counters &cnt,
-                                         uint32_t start = 0) {
-#pragma clang fp contract(off)
-    #pragma unroll
-    for (int a = 0; a < 3; a++)
-        if (x[a] < A.box_lo[a] || x[a] > A.box_hi[a]) return false;
-    int leaf = locate_leaf(A, x, start);
-    if (REC) cnt.desc++;
-    if (leaf < 0) return false;
-    int p = A.leaves[leaf].patch;
-    if (p < 0) return false;
-    const DPatch &P = A.patches[p];
-    PatchView pv = patch_view<LAY>(A, P);
-    float q[3];
-    #pragma unroll
-    for (int a = 0; a < 3; a++) q[a] = (float)((x[a] - P.lo[a]) * P.inv_h[a] - 0.5);
-    *val = trilinear<REC, LAY>(A, pv, q[0], q[1], q[2]);
-    return true;
-}
-
 // Per-segment sampling state: n midpoint samples of step delta on [ta, tb] (Section 5.3:
 // the step is proportional to the leaf level's cell size).
 enum { kTapSame = 0, kTapLocate = 1, kTapUnsure = 2, kTapFace = 3 };
@@ -605,17 +582,6 @@ __device__ __forceinline__ int classify_tap_fp64(const RenderArgs &A, int leaf, 
 __device__ __forceinline__ int classify_tap_fp64(const RenderArgs &A, const Segment &S, const double xt[3], int a,
                                                  int sgn) {
     return classify_tap_fp64(A, S.leaf, S.patch, S.safe, xt, a, sgn);
-}
-
-// Value of patch p at world point x (x known to lie in p's data region).
-template <bool REC, int LAY = -1>
-__device__ __forceinline__ float patch_value_at(const RenderArgs &A, int p, const double x[3]) {
-    const DPatch &P = A.patches[p];
-    PatchView pv = patch_view<LAY>(A, P);
-    float q[3];
-    #pragma unroll
-    for (int a = 0; a < 3; a++) q[a] = (float)((x[a] - P.lo[a]) * P.inv_h[a] - 0.5);
-    return trilinear<REC, LAY>(A, pv, q[0], q[1], q[2]);
 }
 
 // Interior cell (i, j, k) of a padded brick (0 <= index < n).
