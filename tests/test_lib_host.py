@@ -419,3 +419,32 @@ def test_halo_rows_layout(name):
         for bx in range(nbx):
             want = padded[:, :, 4 * bx:4 * bx + 8].reshape(nbz, 4, nby, 4, 8).transpose(0, 2, 1, 3, 4)
             assert np.array_equal(rows[:, :, bx], want), (p, bx)
+
+
+def test_persistent_mode_argument_checks():
+    """amr_render rejects, before touching any device memory, the requests the persistent kernel
+    does not serve: learned proposals, nearest-cell sampling and the point light.  Host buffers
+    stand in for the device pointers, so the test runs only where no GPU is visible."""
+    import torch
+    if torch.cuda.device_count() > 0:
+        pytest.skip("host buffers stand in for device pointers: CPU only")
+    h, lut, cams, prm = workloads.small_nested(0)
+    tree = amr.build_tree(h)
+    scene = amr.pack(tree, h, host=True)
+    lib = amr.load()
+    two = [cams[0], cams[1]]
+    carr = (L.amr_camera * 2)(*[amr.make_camera(c) for c in two])
+    lutbuf = np.zeros((256, 4), np.float32)
+    rgba = np.zeros(4 * sum(c["width"] * c["height"] for c in two), np.float32)
+    scratch = np.zeros(4096, np.uint8)
+    for extra, words in [(dict(), "learned proposals"), (dict(interp=1), "nearest-cell"),
+                         (dict(lighting=2), "point-light")]:
+        q = amr.make_params(dict(prm, persistent=1, **extra), lutbuf)
+        q.d_queue = scratch.ctypes.data
+        q.d_cams = ctypes.cast(carr, ctypes.c_void_p).value
+        if not extra:
+            q.d_mlp = scratch.ctypes.data
+        rc = lib.amr_render(ctypes.byref(scene.scene), carr, 2, ctypes.byref(q), rgba.ctypes.data, None, None)
+        assert rc == 1, extra
+        msg = lib.amr_last_error().decode()
+        assert words in msg and "persistent" in msg, msg
