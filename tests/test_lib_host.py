@@ -448,3 +448,64 @@ def test_persistent_mode_argument_checks():
         assert rc == 1, extra
         msg = lib.amr_last_error().decode()
         assert words in msg and "persistent" in msg, msg
+
+
+def _render_call(lib, scene, cams, prm, set_fields=None, lut_ok=True):
+    """amr_render on host buffers standing in for device pointers (rejected calls only)."""
+    carr = (L.amr_camera * len(cams))(*[amr.make_camera(c) for c in cams])
+    lutbuf = np.zeros((256, 4), np.float32)
+    rgba = np.zeros(4 * max(1, sum(max(0, c["width"]) * max(0, c["height"]) for c in cams)), np.float32)
+    scratch = np.zeros(1 << 16, np.uint8)
+    q = amr.make_params(prm, lutbuf)
+    if not lut_ok:
+        q.d_lut = None
+    for k, v in (set_fields or {}).items():
+        setattr(q, k, scratch.ctypes.data if v == "buf" else v)
+    if q.persistent and not (set_fields and "d_cams" in set_fields):
+        q.d_cams = ctypes.cast(carr, ctypes.c_void_p).value
+    rc = lib.amr_render(ctypes.byref(scene.scene), carr, len(cams), ctypes.byref(q), rgba.ctypes.data, None, None)
+    return rc, lib.amr_last_error().decode()
+
+
+@pytest.mark.parametrize("case", ["v_range", "step", "cam_size", "interp", "lighting", "lod", "lut", "trace_cap",
+                                  "ckpt_odd", "ckpt_small", "tile", "no_queue"])
+def test_render_argument_checks(case):
+    """amr_render's argument checks, each of which returns before any device access (host buffers
+    stand in for device pointers, so the test runs only where no GPU is visible)."""
+    import torch
+    if torch.cuda.device_count() > 0:
+        pytest.skip("host buffers stand in for device pointers: CPU only")
+    h, lut, cams, prm = workloads.small_nested(0)
+    tree = amr.build_tree(h)
+    scene = amr.pack(tree, h, host=True)
+    lib = amr.load()
+    cam = cams[0]
+    want_code, words = 1, None
+    fields, p, cl, lut_ok = {}, dict(prm), [cam], True
+    if case == "v_range":
+        p, words = dict(prm, v_hi=prm["v_lo"]), "v_hi"
+    elif case == "step":
+        p, words = dict(prm, step_frac=0.0), "step_frac"
+    elif case == "cam_size":
+        cl, words = [dict(cam, width=0)], "camera size"
+    elif case == "interp":
+        p, words = dict(prm, interp=2), "interp"
+    elif case == "lighting":
+        p, words = dict(prm, lighting=3), "lighting"
+    elif case == "lod":
+        p, words = dict(prm, lod=-1.0), "lod"
+    elif case == "lut":
+        lut_ok, words = False, "d_lut"
+    elif case == "trace_cap":
+        fields, words = dict(d_trace="buf", trace_cap=0), "trace_cap"
+    elif case == "ckpt_odd":
+        fields, words = dict(d_ckpt="buf", ckpt_bytes=1 << 16, ckpt_every=2, ckpt_max=3), "ckpt_max"
+    elif case == "ckpt_small":
+        fields, words, want_code = dict(d_ckpt="buf", ckpt_bytes=64, ckpt_every=2, ckpt_max=4), "ckpt_bytes", 3
+    elif case == "tile":
+        p, fields, words = dict(prm, persistent=1, tile_w=16, tile_h=8), dict(d_queue="buf"), "tile_w * tile_h"
+    elif case == "no_queue":
+        p, words = dict(prm, persistent=1), "d_queue"
+    rc, msg = _render_call(lib, scene, cl, p, fields, lut_ok)
+    assert rc == want_code, (case, rc, msg)
+    assert words in msg, (case, msg)
