@@ -509,3 +509,40 @@ def test_render_argument_checks(case):
     rc, msg = _render_call(lib, scene, cl, p, fields, lut_ok)
     assert rc == want_code, (case, rc, msg)
     assert words in msg, (case, msg)
+
+
+@pytest.mark.parametrize("case", ["no_ckpt", "nearest", "point_light", "ckpt_small"])
+def test_backward_argument_checks(case):
+    """amr_render_backward's checks that precede its scratch allocation: checkpoints required,
+    trilinear sampling and gradient lighting only, a checkpoint buffer of the forward's size
+    (host buffers stand in for device pointers: CPU only)."""
+    import torch
+    if torch.cuda.device_count() > 0:
+        pytest.skip("host buffers stand in for device pointers: CPU only")
+    h, lut, cams, prm = workloads.small_nested(0)
+    tree = amr.build_tree(h)
+    scene = amr.pack(tree, h, host=True)
+    lib = amr.load()
+    cam = cams[0]
+    npix = cam["width"] * cam["height"]
+    carr = (L.amr_camera * 1)(amr.make_camera(cam))
+    lutbuf = np.zeros((256, 4), np.float32)
+    g = np.zeros(4 * npix, np.float32)
+    glut = np.zeros((256, 4), np.float32)
+    glight = np.zeros(5, np.float32)
+    ck = np.zeros(1 << 16, np.uint8)
+    p = dict(prm, lighting=True)
+    if case == "nearest":
+        p["interp"] = 1
+    elif case == "point_light":
+        p["lighting"] = 2
+    q = amr.make_params(p, lutbuf)
+    if case != "no_ckpt":
+        q.d_ckpt, q.ckpt_every, q.ckpt_max = ck.ctypes.data, 2, 4
+        q.ckpt_bytes = 64 if case == "ckpt_small" else int(lib.amr_ckpt_bytes(npix, 4))
+    rc = lib.amr_render_backward(ctypes.byref(scene.scene), carr, 1, ctypes.byref(q), g.ctypes.data, glut.ctypes.data,
+                                 glight.ctypes.data, 0, None)
+    msg = lib.amr_last_error().decode()
+    want = {"no_ckpt": (1, "checkpoints"), "nearest": (1, "trilinear"), "point_light": (1, "lighting 0 and 1"),
+            "ckpt_small": (3, "too small")}[case]
+    assert rc == want[0] and want[1] in msg, (case, rc, msg)
