@@ -9,6 +9,7 @@ import pytest
 
 import oracle
 import workloads
+from _parity import compare_traces, pixel_set
 
 pytestmark = pytest.mark.gpu
 
@@ -31,23 +32,6 @@ def _gpu_render(amr, scene, cam, lut, prm, trace_cap=0, stats=False, nsamp=False
     return out
 
 
-def _compare_traces(amr, gout, ores, nrays_expect=None):
-    g = amr.trace_records(gout)
-    gn = gout["trace_n"].cpu().numpy()
-    on = ores["trace_n"]
-    ok = ores["flags"] == 0
-    assert ok.mean() > 0.99
-    assert np.array_equal(gn[ok], on[ok])
-    cap = g.shape[1]
-    for q in np.flatnonzero(ok):
-        n = min(on[q], cap)
-        a, b = g[q, :n], ores["trace"][q, :n]
-        for f in ("leaf", "patch", "n", "level"):
-            assert np.array_equal(a[f], b[f]), (q, f)
-        assert np.array_equal(a["ta"], b["ta"]) and np.array_equal(a["tb"], b["tb"]), q
-    return int(ok.sum())
-
-
 @pytest.mark.parametrize("layout", [0, 1, 2])
 @pytest.mark.parametrize("lit", [False, True])
 @pytest.mark.parametrize("uniform", [False, True])
@@ -65,7 +49,7 @@ def test_small_nested_full_image(gpu, cam_idx, uniform, lit, layout):
     err = np.abs(rgba - ores["rgba"]).max()
     print("small_nested cam%d uniform=%d lit=%d max|err|=%.3g" % (cam_idx, uniform, lit, err))
     assert err <= TOL
-    _compare_traces(amr, gout, ores)
+    compare_traces(amr, gout, ores)
     st = amr.stats_dict(gout)
     assert st["guard_hits"] == 0 and st["trace_overflow"] == 0
     ns = gout["nsamp"].cpu().numpy()
@@ -147,7 +131,7 @@ def test_random_hierarchies(gpu, seed):
     ores = oracle.Oracle(h).render(cam, prm, lut, trace_cap=256)
     rgba = gout["rgba"].cpu().numpy().reshape(-1, 4)
     assert np.abs(rgba - ores["rgba"]).max() <= TOL
-    _compare_traces(amr, gout, ores)
+    compare_traces(amr, gout, ores)
 
 
 def test_degenerate_views(gpu):
@@ -214,21 +198,13 @@ def test_cosmology_linear_layout_sampled(gpu, cosmology_scene):
     del scene0
 
 
-def _sample_pixels(W, H, seed):
-    rng = np.random.default_rng(seed)
-    pix = [np.stack([rng.integers(0, W, 3000), rng.integers(0, H, 3000)], 1)]
-    for row in (H // 3, H // 2 + 7):
-        pix.append(np.stack([np.arange(W), np.full(W, row)], 1))
-    cy, cx = H // 2 - 16, W // 2 - 16
-    jj, ii = np.meshgrid(np.arange(cy, cy + 32), np.arange(cx, cx + 32), indexing="ij")
-    pix.append(np.stack([ii.ravel(), jj.ravel()], 1))
-    return np.ascontiguousarray(np.concatenate(pix), dtype=np.int32)
-
-
 @pytest.mark.parametrize("lit", [True, False])
 def test_cosmology_full_size_sampled(gpu, cosmology_scene, lit):
-    """The 1024x1024 cosmology-like frame in the launch configuration the benchmark times;
-    the oracle checks 3000 random pixels, two full rows and a 32x32 crop."""
+    """The 1024x1024 cosmology-like frame through the recording forward variant (trace and
+    counters on, brick layout read at run time) on the micro-brick pool: 16,384 seeded pixels,
+    four full rows and a 64x64 crop against the oracle, RGBA within 1e-4 and segment traces
+    bit-exact.  The benchmark's own launch (halo-row pool, non-recording kernel) is checked in
+    test_gpu_timed_config.py."""
     import torch
     amr = gpu
     h, lut, cam, prm, tree, scene = cosmology_scene
@@ -236,7 +212,7 @@ def test_cosmology_full_size_sampled(gpu, cosmology_scene, lit):
     W, H = cam["width"], cam["height"]
     cap = 192
     out = _gpu_render(amr, scene, cam, lut, prm, trace_cap=cap, stats=True)
-    pix = _sample_pixels(W, H, 11)
+    pix = pixel_set(W, H, 11)
     idx = torch.from_numpy(pix[:, 1].astype(np.int64) * W + pix[:, 0]).cuda()
     rgba = out["rgba"].view(-1, 4)[idx].cpu().numpy().astype(np.float64)
     sub = dict(trace_raw=out["trace_raw"][idx], trace_n=out["trace_n"][idx])
@@ -246,7 +222,7 @@ def test_cosmology_full_size_sampled(gpu, cosmology_scene, lit):
     print("cosmology_view lit=%d: %d pixels, max|err| = %.3g, max segments %d" % (lit, len(pix), err, ores["trace_n"].max()))
     assert err <= TOL
     assert ores["trace_n"].max() <= cap
-    _compare_traces(amr, sub, ores)
+    compare_traces(amr, sub, ores, "cosmology micro-bricks lit=%d" % lit)
 
 
 @pytest.mark.parametrize("interp", [0, 1])
@@ -298,7 +274,7 @@ def test_nearest_small_nested(gpu, cam_idx, lit):
     err = np.abs(gout["rgba"].cpu().numpy().reshape(-1, 4) - ores["rgba"]).max()
     print("nearest cam%d lit=%d max|err|=%.3g" % (cam_idx, lit, err))
     assert err <= TOL
-    _compare_traces(amr, gout, ores)
+    compare_traces(amr, gout, ores)
 
 
 @pytest.mark.parametrize("seed", range(4))
@@ -313,7 +289,7 @@ def test_nearest_random_hierarchies(gpu, seed):
     gout = _gpu_render(amr, scene, cam, lut, prm, trace_cap=256)
     ores = oracle.Oracle(h).render(cam, prm, lut, trace_cap=256)
     assert np.abs(gout["rgba"].cpu().numpy().reshape(-1, 4) - ores["rgba"]).max() <= TOL
-    _compare_traces(amr, gout, ores)
+    compare_traces(amr, gout, ores)
 
 
 def test_nearest_cosmology_sampled(gpu, cosmology_scene):
@@ -369,7 +345,7 @@ def test_lod_vs_oracle(gpu, seed, lod, lit):
         gout = _gpu_render(amr, scene, cam, lut, prm, trace_cap=128)
         ores = oracle.Oracle(h).render(cam, prm, lut, trace_cap=128)
         assert np.abs(gout["rgba"].cpu().numpy().reshape(-1, 4) - ores["rgba"]).max() <= TOL
-        _compare_traces(amr, gout, ores)
+        compare_traces(amr, gout, ores)
         if lod >= 3.0:
             assert np.any(ores["trace"]["leaf"] >= scene.scene.nleaves)
 
@@ -419,7 +395,7 @@ def test_point_light_vs_oracle(gpu, case, light):
     err = np.abs(gout["rgba"].cpu().numpy().reshape(-1, 4) - ores["rgba"]).max()
     print("point light %s %s: max|err| = %.3g" % (case, light, err))
     assert err <= TOL
-    _compare_traces(amr, gout, ores)
+    compare_traces(amr, gout, ores)
 
 
 def test_point_light_rejected_elsewhere(gpu):

@@ -6,6 +6,7 @@ import pytest
 
 import oracle
 import workloads
+from _parity import compare_traces
 
 pytestmark = pytest.mark.gpu
 
@@ -55,18 +56,6 @@ def _check_bounds(st, sc, mask):
     assert np.array_equal(fx["off"][single], ph["off"][own[single]])
 
 
-def _compare_traces(amr, gout, ores):
-    g = amr.trace_records(gout)
-    gn = gout["trace_n"].cpu().numpy()
-    ok = ores["flags"] == 0
-    assert ok.mean() > 0.99
-    assert np.array_equal(gn[ok], ores["trace_n"][ok])
-    for q in np.flatnonzero(ok):
-        n = min(ores["trace_n"][q], g.shape[1])
-        a, b = g[q, :n], ores["trace"][q, :n]
-        for f in ("leaf", "patch", "n", "level"):
-            assert np.array_equal(a[f], b[f]), (q, f)
-        assert np.array_equal(a["ta"], b["ta"]) and np.array_equal(a["tb"], b["tb"]), q
 
 
 @pytest.mark.parametrize("layout", [0, 1, 2])
@@ -98,7 +87,7 @@ def test_resident_subsets_vs_oracle(gpu, name, lit, layout):
         print("store %s lit=%d layout=%d seed=%d: %d resident, %d remapped, max|err| = %.3g" % (
             name, lit, layout, seed, rep["resident_bricks"], rep["remapped_leaves"], err))
         assert err <= TOL
-        _compare_traces(amr, out, ores)
+        compare_traces(amr, out, ores)
         assert amr.stats_dict(out)["guard_hits"] == 0
 
 
@@ -165,4 +154,4 @@ def test_streaming_cosmology_orbit(gpu):
     err = np.abs(rgba - ores["rgba"]).max()
     print("streamed frame vs restricted oracle: max|err| = %.3g" % err)
     assert err <= TOL
-    _compare_traces(amr, sub, ores)
+    compare_traces(amr, sub, ores)

@@ -1,0 +1,99 @@
+"""The benchmark's timed launches against the FP64 oracle, through the C ABI.
+
+The benchmark packs the cosmology-like hierarchy (root 128^3, 6 levels, about 2000 patches) in
+the halo-row brick layout (brick_layout = 2, the 3.4 GB pool) and times amr_render with no
+recording output (no trace, counters, sample counts, touch map or checkpoints) for its
+1024x1024 perspective view, lit and unlit.  For that call the launcher picks the forward kernel
+compiled for layout 2 without recording code.  These tests make exactly that call and compare
+a seeded pixel set (16,384 random pixels, four full rows and a 64x64 crop) with the oracle at
+1e-4; the recording variant on the same layout-2 scene gives the same image bit for bit and
+segment traces equal to the oracle's bit for bit.  The benchmark's persistent batch (64 serving
+cameras of mixed sizes, one launch) is checked the same way on pixels of several images."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from _parity import compare_traces, pixel_set
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-4
+CAP = 192
+
+
+@pytest.fixture(scope="module")
+def timed_scene(gpu):
+    import torch
+    amr = gpu
+    h, lut, cam, prm = workloads.cosmology_view(0)
+    tree = amr.build_tree(h)
+    scene = amr.pack(tree, h, device="cuda", brick_layout=2)
+    torch.cuda.synchronize()
+    assert scene.scene.brick_layout == 2
+    lut_t = torch.from_numpy(lut).cuda()
+    yield h, lut, lut_t, cam, prm, scene, oracle.Oracle(h)
+    del scene
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("lit", [True, False])
+def test_timed_launch_vs_oracle(gpu, timed_scene, lit):
+    import torch
+    amr = gpu
+    h, lut, lut_t, cam, prm, scene, O = timed_scene
+    prm = dict(prm, lighting=lit)
+    W, H = cam["width"], cam["height"]
+    # the benchmark's call: preallocated output, nothing recorded
+    out = torch.empty(W * H * 4, dtype=torch.float32, device="cuda")
+    amr.render(scene, cam, lut_t, prm, out=out)
+    torch.cuda.synchronize()
+    img = out.view(H, W, 4)
+    pix = pixel_set(W, H, 1212)
+    print("timed launch lit=%d: %d oracle pixels" % (lit, len(pix)), flush=True)
+    ores = O.render(cam, prm, lut, pixels=pix, trace_cap=CAP)
+    got = img[torch.from_numpy(pix[:, 1].astype(np.int64)).cuda(), torch.from_numpy(pix[:, 0].astype(np.int64)).cuda()]
+    err = np.abs(got.cpu().numpy().astype(np.float64) - ores["rgba"]).max()
+    print("timed launch lit=%d: max|RGBA - oracle| = %.3g over %d pixels" % (lit, err, len(pix)))
+    assert err <= TOL
+    assert ores["trace_n"].max() <= CAP
+    # the recording variant on the same halo-row scene: same image, traces bit-exact
+    rec = amr.render(scene, cam, lut_t, prm, trace_cap=CAP, stats=True)
+    torch.cuda.synchronize()
+    st = amr.stats_dict(rec)
+    assert st["guard_hits"] == 0 and st["trace_overflow"] == 0
+    assert torch.equal(rec["rgba"], img)
+    idx = torch.from_numpy(pix[:, 1].astype(np.int64) * W + pix[:, 0]).cuda()
+    sub = dict(trace_raw=rec["trace_raw"][idx], trace_n=rec["trace_n"][idx])
+    del rec
+    compare_traces(amr, sub, ores, "halo-row layout lit=%d" % lit)
+
+
+@pytest.mark.parametrize("lit", [True, False])
+def test_persistent_batch_vs_oracle(gpu, timed_scene, lit):
+    """The serving batch in one persistent launch on the halo-row scene: the two largest and the
+    two smallest images (and two in between) on 1,024 seeded pixels each against the oracle."""
+    import torch
+    amr = gpu
+    h, lut, lut_t, _, prm, scene, O = timed_scene
+    prm = dict(prm, lighting=lit)
+    cams = workloads.serving_cameras(0, 64)
+    npix = [c["width"] * c["height"] for c in cams]
+    off = np.concatenate([[0], np.cumsum(npix)])
+    out = amr.render(scene, cams, lut_t, dict(prm, persistent=1, tile_w=8, tile_h=8, blocks_per_cu=8),
+                     d_cams=amr.camera_table(cams), d_queue=amr.queue_buffer(len(cams)))["rgba"]
+    torch.cuda.synchronize()
+    order = np.argsort(npix, kind="stable")
+    pick = [int(order[-1]), int(order[-2]), int(order[0]), int(order[1]), int(order[len(order) // 2]), 17]
+    worst = 0.0
+    for k, c in enumerate(pick):
+        cam = cams[c]
+        W, H = cam["width"], cam["height"]
+        rng = np.random.default_rng(100 + k)
+        pix = np.stack([rng.integers(0, W, 1024), rng.integers(0, H, 1024)], 1).astype(np.int32)
+        ref = O.render(cam, prm, lut, pixels=pix)["rgba"]
+        idx = torch.from_numpy(off[c] + pix[:, 1].astype(np.int64) * W + pix[:, 0]).cuda()
+        err = np.abs(out[idx].cpu().numpy().astype(np.float64) - ref).max()
+        print("persistent batch lit=%d camera %d (%dx%d): max|RGBA - oracle| = %.3g" % (lit, c, W, H, err))
+        worst = max(worst, err)
+    assert worst <= TOL

@@ -12,6 +12,7 @@ import pytest
 
 import oracle
 import workloads
+from _parity import compare_traces
 
 pytestmark = pytest.mark.gpu
 
@@ -50,18 +51,6 @@ def _render(amr, scene, cam, lut, prm, **kw):
     return out
 
 
-def _compare_traces(amr, gout, ores):
-    g = amr.trace_records(gout)
-    gn = gout["trace_n"].cpu().numpy()
-    ok = ores["flags"] == 0
-    assert ok.mean() > 0.99
-    assert np.array_equal(gn[ok], ores["trace_n"][ok])
-    for q in np.flatnonzero(ok):
-        n = min(ores["trace_n"][q], g.shape[1])
-        a, b = g[q, :n], ores["trace"][q, :n]
-        for f in ("leaf", "patch", "n", "level"):
-            assert np.array_equal(a[f], b[f]), (q, f)
-        assert np.array_equal(a["ta"], b["ta"]) and np.array_equal(a["tb"], b["tb"]), q
 
 
 @pytest.mark.parametrize("layout", [0, 1, 2])
@@ -83,7 +72,7 @@ def test_vertex_vs_oracle(gpu, name, lit, layout):
         err = np.abs(gout["rgba"].cpu().numpy().reshape(-1, 4) - ores["rgba"]).max()
         print("vertex %s lit=%d layout=%d: max|err| = %.3g" % (name, lit, layout, err))
         assert err <= TOL
-        _compare_traces(amr, gout, ores)
+        compare_traces(amr, gout, ores)
         assert amr.stats_dict(gout)["guard_hits"] == 0
 
 
@@ -147,7 +136,7 @@ def test_vertex_lod_and_batched(gpu, lit):
     gout = _render(amr, scene, cam, lut, prm, trace_cap=128)
     ores = oracle.Oracle(h).render(cam, prm, lut, trace_cap=128)
     assert np.abs(gout["rgba"].cpu().numpy().reshape(-1, 4) - ores["rgba"]).max() <= TOL
-    _compare_traces(amr, gout, ores)
+    compare_traces(amr, gout, ores)
     assert np.any(ores["trace"]["leaf"] >= scene.scene.nleaves)
     cams = [workloads.perspective_orbit(w, hh, 0.5 * k, 0.1 * k - 0.2, radius=1.9)
             for k, (w, hh) in enumerate([(16, 8), (40, 32), (24, 48), (64, 64)])]
@@ -219,4 +208,4 @@ def test_vertex_cosmology_full_size_sampled(gpu):
     err = np.abs(rgba - ores["rgba"]).max()
     print("cosmology vertex view: %d pixels, max|err| = %.3g" % (len(pix), err))
     assert err <= TOL
-    _compare_traces(amr, sub, ores)
+    compare_traces(amr, sub, ores)
