@@ -131,8 +131,9 @@ def cpu_baseline(h, cam, lut, prm, target_s=15.0, seed=7):
 def next_rows_section(amr, dev, scene, h, cam, lut_t, prm, steps, out, seed):
     """The widened rows on the same view: nearest-cell sampling, the level-of-detail cut at
     kind-(a) nodes (2 pixels), secondary rays to a point light (light at the domain centre; the
-    time includes the passes' device allocations), out-of-core residency and vertex-centred data
-    (the same boxes with samples at the grid vertices)."""
+    job arrays of the secondary-ray pass in a workspace sized for the frame's samples, allocated
+    before the timed frames), out-of-core residency and vertex-centred data (the same boxes with
+    samples at the grid vertices)."""
     import torch
     import workloads
     res = {}
@@ -153,9 +154,12 @@ def next_rows_section(amr, dev, scene, h, cam, lut_t, prm, steps, out, seed):
                       samples_per_frame=int(st["samples"]), segments_per_frame=int(st["segments"]))
     pl = dict(prm, lighting=2, light=(0.5, 0.5, 0.5))
     st = stats_of(scene, cam, pl)
+    pl = dict(pl, light_jobs=int(st["samples"]))
+    st = stats_of(scene, cam, pl)
     ms_pl = time_frames(amr, scene, cam, lut_t, pl, 3, 1, out)
     res["point_light"] = dict(width=cam["width"], height=cam["height"], light=[0.5, 0.5, 0.5], ms=round(ms_pl, 4),
-                              primary_samples_per_frame=int(st["samples"]),
+                              primary_samples_per_frame=int(st["samples"]), light_jobs=int(pl["light_jobs"]),
+                              samples_traced_inline=int(st["light_inline"]),
                               secondary_rays_per_s=round(st["samples"] / (ms_pl * 1e-3), 1))
     res["out_of_core"] = out_of_core_section(amr, dev, scene, h, cam, lut_t, prm, steps, out)
     t = time.time()

@@ -207,7 +207,10 @@ typedef struct {                        /* device counters, accumulated by amr_r
     unsigned long long face_taps;       /* taps read from a leaf face's single slab owner */
     unsigned long long unsure_taps;     /* taps classified in FP64 (within 1e-3 cell of a face) */
     unsigned long long net_segments;    /* learned form: segments the network was asked about */
-    unsigned long long reserved_[2];
+    unsigned long long light_inline;    /* lighting = 2: samples whose secondary ray did not fit
+                                           the workspace's job arrays (params.light_jobs) and was
+                                           traced in the shading pass instead */
+    unsigned long long reserved_[1];
 } amr_render_stats;
 
 typedef struct {
@@ -272,11 +275,23 @@ typedef struct {
     /* measurement (device, NULL to skip): one bit per pool float, set for every cell a sample
        or gradient tap reads; its population count gives a frame's compulsory pool bytes */
     uint32_t *d_touch;
+    /* caller-owned device workspace (the library allocates no device memory during a render):
+       amr_render with lighting = 2 needs amr_render_work_bytes(...) bytes, amr_render_backward
+       needs amr_backward_work_bytes(deterministic); other calls ignore it.  NULL or too small
+       where needed: AMR_EINVAL / AMR_ECAPACITY, nothing enqueued.  Its contents on entry do not
+       matter; calls that share one workspace must be ordered (one stream). */
+    void *d_work;
+    int64_t work_bytes;
+    int64_t light_jobs;                 /* lighting = 2: secondary rays the workspace holds per
+                                           camera (16 bytes each); a sample beyond this count has
+                                           its secondary ray traced in the shading pass (same
+                                           value, slower; counted in light_inline) */
 } amr_render_params;
 
 /* Renders ncams cameras (host array) into d_rgba (device, premultiplied RGBA fp32, images
  * concatenated, image i has width_i*height_i*4 floats, row 0 at the top).  d_stats
- * (device, optional) is zeroed and then accumulated.  Asynchronous on `stream`. */
+ * (device, optional) is zeroed and then accumulated.  Asynchronous on `stream`: no device
+ * allocation, no host synchronisation (the point light's passes included). */
 int amr_render(const amr_scene *scene, const amr_camera *cams, int32_t ncams,
                const amr_render_params *params, float *d_rgba, amr_render_stats *d_stats, void *stream);
 
@@ -294,12 +309,25 @@ int64_t amr_wall_clock_khz(void);
 /* Checkpoint buffer bytes for nrays rays with ckpt_max checkpoints each. */
 int64_t amr_ckpt_bytes(int64_t nrays, int32_t ckpt_max);
 
+/* Workspace bytes (params->d_work) amr_render needs for these cameras and params: with
+ * lighting = 2, per-ray sample counts and job offsets for the largest camera plus
+ * params->light_jobs jobs of 16 bytes (the cameras are rendered one after another and reuse
+ * it); 0 otherwise.  -1 on invalid arguments (NULL, ncams <= 0, negative light_jobs). */
+int64_t amr_render_work_bytes(const amr_camera *cams, int32_t ncams, const amr_render_params *params);
+/* Workspace bytes (params->d_work) amr_render_backward needs: the 1029-float gradient
+ * accumulator, plus one partial sum per block of the adjoint's fixed grid when
+ * deterministic = 1. */
+int64_t amr_backward_work_bytes(int32_t deterministic);
+
 /* Adjoint of amr_render for a loss L(RGBA): given dL/dRGBA (device, same layout as d_rgba),
  * accumulates dL/dLUT into d_grad_lut (device [256][4], fp32, zeroed by the call) and
  * dL/d(light_x, light_y, light_z, k_a, k_d) into d_grad_light (device [5]).  `params` must be
  * the ones of the forward call that filled params->d_ckpt (same scene, cameras, LUT).
  * The early-termination point of each ray is the forward's.  deterministic = 1 reduces
- * per-block partial sums in a fixed order (bit-reproducible); 0 uses atomics.  Asynchronous. */
+ * per-block partial sums in a fixed order (bit-reproducible); 0 uses atomics.  The gradient
+ * accumulators live in params->d_work (amr_backward_work_bytes(deterministic) bytes, caller
+ * owned; AMR_EINVAL if NULL, AMR_ECAPACITY if smaller).  Asynchronous: no device allocation,
+ * no host synchronisation. */
 int amr_render_backward(const amr_scene *scene, const amr_camera *cams, int32_t ncams,
                         const amr_render_params *params, const float *d_grad_rgba,
                         float *d_grad_lut, float *d_grad_light, int32_t deterministic, void *stream);

@@ -344,6 +344,11 @@ def _cams(cams):
     return cams, arr
 
 
+# Default job slots of the point light's secondary-ray pass, per pixel of the largest camera
+# (samples beyond them trace their secondary ray in the shading pass: same image, slower).
+LIGHT_JOBS_PER_PIXEL = 512
+
+
 def render(scene: Scene, cams, lut: torch.Tensor, params: dict, trace_cap: int = 0, stats: bool = False,
            nsamp: bool = False, out: torch.Tensor | None = None, **extra) -> RenderOutput:
     """Renders one camera (dict) or several (list) with amr_render.  Returns RenderOutput with
@@ -368,10 +373,18 @@ def render(scene: Scene, cams, lut: torch.Tensor, params: dict, trace_cap: int =
         res["nsamp"] = ns
     st = torch.zeros(16, dtype=torch.int64, device=dev) if stats else None
     for k in ("d_ckpt", "ckpt_bytes", "ckpt_every", "ckpt_max", "d_mlp", "d_seglog", "seglog_cap", "d_queue",
-              "d_stamps", "d_touch", "d_cams"):
+              "d_stamps", "d_touch", "d_cams", "d_work", "work_bytes", "light_jobs"):
         if k in extra:
             v = extra[k]
             setattr(q, k, v.data_ptr() if isinstance(v, torch.Tensor) else v)
+    if q.lighting == 2 and "d_work" not in extra:
+        # point light: the job arrays of the secondary-ray pass live in a workspace owned here
+        npix_max = max(int(c["width"]) * int(c["height"]) for c in cam_list)
+        q.light_jobs = int(params.get("light_jobs", extra.get("light_jobs", LIGHT_JOBS_PER_PIXEL * npix_max)))
+        nwork = int(lib.amr_render_work_bytes(carr, len(cam_list), ctypes.byref(q)))
+        work = torch.empty(max(nwork, 1), dtype=torch.uint8, device=dev)
+        q.d_work, q.work_bytes = work.data_ptr(), nwork
+        res["_work"] = work
     check(lib.amr_render(ctypes.byref(scene.scene), carr, len(cam_list), ctypes.byref(q), _vp(rgba), _vp(st),
                          _stream(dev)), "amr_render")
     res["rgba"] = rgba.view(cam_list[0]["height"], cam_list[0]["width"], 4) if len(cam_list) == 1 else rgba.view(-1, 4)
@@ -487,6 +500,9 @@ def render_backward(scene: Scene, cams, lut: torch.Tensor, params: dict, ckpt: C
     q.d_ckpt, q.ckpt_bytes, q.ckpt_every, q.ckpt_max = ckpt.buf.data_ptr(), ckpt.nbytes, ckpt.every, ckpt.max
     glut = torch.empty((256, 4), dtype=torch.float32, device=dev)
     glight = torch.empty(5, dtype=torch.float32, device=dev)
+    nwork = int(lib.amr_backward_work_bytes(int(bool(deterministic))))
+    work = torch.empty(nwork, dtype=torch.uint8, device=dev)
+    q.d_work, q.work_bytes = work.data_ptr(), nwork
     check(lib.amr_render_backward(ctypes.byref(scene.scene), carr, len(cam_list), ctypes.byref(q), _vp(g), _vp(glut),
                                   _vp(glight), int(bool(deterministic)), _stream(dev)), "amr_render_backward")
     return glut, glight

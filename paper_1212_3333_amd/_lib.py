@@ -87,11 +87,11 @@ class amr_trace_rec(ctypes.Structure):
 
 STATS_FIELDS = ("samples", "segments", "rays_hit", "tap_descents", "guard_hits", "trace_overflow",
                 "skipped_segments", "coarse_segments", "seglog_count", "ckpt_overflow", "split_samples",
-                "face_taps", "unsure_taps", "net_segments")
+                "face_taps", "unsure_taps", "net_segments", "light_inline")
 
 
 class amr_render_stats(ctypes.Structure):
-    _fields_ = [(n, ctypes.c_uint64) for n in STATS_FIELDS] + [("reserved_", ctypes.c_uint64 * 2)]
+    _fields_ = [(n, ctypes.c_uint64) for n in STATS_FIELDS] + [("reserved_", ctypes.c_uint64 * 1)]
 
 
 class amr_render_params(ctypes.Structure):
@@ -106,7 +106,8 @@ class amr_render_params(ctypes.Structure):
                 ("d_seglog", VP), ("seglog_cap", ctypes.c_int64),
                 ("persistent", ctypes.c_int32), ("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32),
                 ("blocks_per_cu", ctypes.c_int32), ("interp", ctypes.c_int32), ("lod", ctypes.c_float),
-                ("d_queue", VP), ("d_stamps", VP), ("d_cams", VP), ("d_touch", VP)]
+                ("d_queue", VP), ("d_stamps", VP), ("d_cams", VP), ("d_touch", VP),
+                ("d_work", VP), ("work_bytes", ctypes.c_int64), ("light_jobs", ctypes.c_int64)]
 
 
 class amr_seglog_rec(ctypes.Structure):
@@ -138,6 +139,9 @@ SIGNATURES = {
     "amr_queue_bytes": (ctypes.c_int64, [ctypes.c_int32]),
     "amr_wall_clock_khz": (ctypes.c_int64, []),
     "amr_ckpt_bytes": (ctypes.c_int64, [ctypes.c_int64, ctypes.c_int32]),
+    "amr_render_work_bytes": (ctypes.c_int64, [ctypes.POINTER(amr_camera), ctypes.c_int32,
+                                               ctypes.POINTER(amr_render_params)]),
+    "amr_backward_work_bytes": (ctypes.c_int64, [ctypes.c_int32]),
     "amr_render_backward": (ctypes.c_int, [ctypes.POINTER(amr_scene), ctypes.POINTER(amr_camera), ctypes.c_int32,
                                            ctypes.POINTER(amr_render_params), VP, VP, VP, ctypes.c_int32, VP]),
     "amr_mlp_param_count": (ctypes.c_int32, []),

@@ -11,6 +11,7 @@
 // sums their colour separately, which changes a pixel by rounding only.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 
@@ -414,6 +415,56 @@ __global__ void split_grad(const float *grad, float *grad_lut, float *grad_light
     else if (i < kGradLen) grad_light[i - 1024] = grad[i];
 }
 
+// The adjoint's launches with the gradient accumulators at `work` (device, at least
+// amr_backward_work_bytes(deterministic) bytes): zero the accumulator, one render_bwd launch per
+// camera (plus the fixed-order partial reduction in deterministic mode), then split the result
+// into the LUT and shading gradients.  Enqueued on `stream`; no allocation, no synchronisation.
+int backward_launch(const amr_scene *S, const amr_camera *cams, int32_t ncams, const amr_render_params *P,
+                    const float *d_grad_rgba, float *d_grad_lut, float *d_grad_light, int32_t deterministic,
+                    float *work, void *stream) {
+    if (!S || !cams || !P || !d_grad_rgba || !d_grad_lut || !d_grad_light || ncams <= 0 || !work) {
+        set_error("null argument or ncams <= 0");
+        return AMR_EINVAL;
+    }
+    if (!P->d_ckpt) { set_error("the adjoint needs the forward's checkpoints (params.d_ckpt)"); return AMR_EINVAL; }
+    if (P->interp != 0) { set_error("the adjoint is defined for trilinear sampling (interp = 0)"); return AMR_EINVAL; }
+    if (P->lighting == 2) { set_error("the adjoint is defined for lighting 0 and 1"); return AMR_EINVAL; }
+    int64_t total = 0;
+    for (int c = 0; c < ncams; c++) total += (int64_t)cams[c].width * cams[c].height;
+    if (P->ckpt_max < 2 || P->ckpt_bytes < amr_ckpt_bytes(total, P->ckpt_max)) {
+        set_error("checkpoint buffer too small");
+        return AMR_ECAPACITY;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    float *grad = work;
+    float *partials = deterministic ? work + kGradLen : nullptr;
+    hipLaunchKernelGGL(zero_f32, dim3((kGradLen + 255) / 256), dim3(256), 0, s, grad, kGradLen);
+    int rc = check_hip(hipGetLastError(), "adjoint accumulator reset");
+    int64_t pix_off = 0;
+    for (int c = 0; c < ncams && rc == AMR_OK; c++) {
+        RenderArgs A;
+        rc = fill_args(S, &cams[c], P, &A);
+        if (rc) break;
+        A.ckpt_ray0 = pix_off;
+        BwdArgs B;
+        B.grad_rgba = d_grad_rgba + 4 * pix_off;
+        B.grad = grad;
+        B.partials = partials;
+        if (A.lighting) hipLaunchKernelGGL(render_bwd<true>, dim3(kBwdGrid), dim3(256), 0, s, A, B);
+        else hipLaunchKernelGGL(render_bwd<false>, dim3(kBwdGrid), dim3(256), 0, s, A, B);
+        rc = check_hip(hipGetLastError(), "render_bwd launch");
+        if (rc) break;
+        if (deterministic)
+            hipLaunchKernelGGL(reduce_partials, dim3((kGradLen + 255) / 256), dim3(256), 0, s, partials, kBwdGrid, grad);
+        pix_off += (int64_t)cams[c].width * cams[c].height;
+    }
+    if (rc == AMR_OK) {
+        hipLaunchKernelGGL(split_grad, dim3((kGradLen + 255) / 256), dim3(256), 0, s, grad, d_grad_lut, d_grad_light);
+        rc = check_hip(hipGetLastError(), "adjoint gradient split");
+    }
+    return rc;
+}
+
 }  // namespace amr
 
 using namespace amr;
@@ -423,6 +474,14 @@ extern "C" {
 int64_t amr_ckpt_bytes(int64_t nrays, int32_t ckpt_max) {
     if (nrays < 0 || ckpt_max < 2) return 0;
     return nrays * (int64_t)sizeof(Ckpt) * (1 + (int64_t)ckpt_max);
+}
+
+int64_t amr_render_work_bytes(const amr_camera *cams, int32_t ncams, const amr_render_params *P) {
+    if (!cams || !P || ncams <= 0 || P->light_jobs < 0) return -1;
+    if (P->lighting != 2) return 0;
+    int64_t npix = 0;
+    for (int c = 0; c < ncams; c++) npix = std::max<int64_t>(npix, (int64_t)cams[c].width * cams[c].height);
+    return shadow_work_bytes(npix, P->light_jobs);
 }
 
 int amr_render(const amr_scene *S, const amr_camera *cams, int32_t ncams, const amr_render_params *P,
@@ -488,7 +547,7 @@ int amr_render(const amr_scene *S, const amr_camera *cams, int32_t ncams, const 
         const int grid = 8 * ((A.sgrid * A.sgrid + 7) / 8) * 16;
         const bool rec = A.trace || A.trace_n || A.nsamp || A.stats || A.touch || A.ckpt;
         if (A.lighting == 2) {
-            rc = launch_shadow(A, rec, stream);
+            rc = launch_shadow(A, rec, stream, P->d_work, P->work_bytes, P->light_jobs);
             if (rc) return rc;
             pix_off += (int64_t)cams[c].width * cams[c].height;
             continue;
@@ -521,53 +580,23 @@ int amr_render(const amr_scene *S, const amr_camera *cams, int32_t ncams, const 
     return AMR_OK;
 }
 
+int64_t amr_backward_work_bytes(int32_t deterministic) {
+    return (int64_t)sizeof(float) * ((int64_t)kGradLen + (deterministic ? (int64_t)kBwdGrid * kGradLen : 0));
+}
+
 int amr_render_backward(const amr_scene *S, const amr_camera *cams, int32_t ncams, const amr_render_params *P,
                         const float *d_grad_rgba, float *d_grad_lut, float *d_grad_light, int32_t deterministic,
                         void *stream) {
-    if (!S || !cams || !P || !d_grad_rgba || !d_grad_lut || !d_grad_light || ncams <= 0) {
-        set_error("null argument or ncams <= 0");
+    if (P && !P->d_work) {
+        set_error("amr_render_backward needs a workspace: params.d_work of amr_backward_work_bytes(deterministic) bytes");
         return AMR_EINVAL;
     }
-    if (!P->d_ckpt) { set_error("the adjoint needs the forward's checkpoints (params.d_ckpt)"); return AMR_EINVAL; }
-    if (P->interp != 0) { set_error("the adjoint is defined for trilinear sampling (interp = 0)"); return AMR_EINVAL; }
-    if (P->lighting == 2) { set_error("the adjoint is defined for lighting 0 and 1"); return AMR_EINVAL; }
-    int64_t total = 0;
-    for (int c = 0; c < ncams; c++) total += (int64_t)cams[c].width * cams[c].height;
-    if (P->ckpt_max < 2 || P->ckpt_bytes < amr_ckpt_bytes(total, P->ckpt_max)) {
-        set_error("checkpoint buffer too small");
+    if (P && P->work_bytes < amr_backward_work_bytes(deterministic)) {
+        set_error("work_bytes %lld < %lld", (long long)P->work_bytes, (long long)amr_backward_work_bytes(deterministic));
         return AMR_ECAPACITY;
     }
-    hipStream_t s = (hipStream_t)stream;
-    const int grid = 2048;   // fixed, so deterministic mode sums a fixed set of partials in order
-    float *scratch = nullptr;
-    size_t scratch_bytes = sizeof(float) * ((size_t)kGradLen + (deterministic ? (size_t)grid * kGradLen : 0));
-    int rc = check_hip(hipMallocAsync((void **)&scratch, scratch_bytes, s), "hipMallocAsync");
-    if (rc) return rc;
-    float *grad = scratch;
-    float *partials = deterministic ? scratch + kGradLen : nullptr;
-    hipLaunchKernelGGL(zero_f32, dim3((kGradLen + 255) / 256), dim3(256), 0, s, grad, kGradLen);
-    int64_t pix_off = 0;
-    for (int c = 0; c < ncams && rc == AMR_OK; c++) {
-        RenderArgs A;
-        rc = fill_args(S, &cams[c], P, &A);
-        if (rc) break;
-        A.ckpt_ray0 = pix_off;
-        BwdArgs B;
-        B.grad_rgba = d_grad_rgba + 4 * pix_off;
-        B.grad = grad;
-        B.partials = partials;
-        if (A.lighting) hipLaunchKernelGGL(render_bwd<true>, dim3(grid), dim3(256), 0, s, A, B);
-        else hipLaunchKernelGGL(render_bwd<false>, dim3(grid), dim3(256), 0, s, A, B);
-        rc = check_hip(hipGetLastError(), "render_bwd launch");
-        if (rc) break;
-        if (deterministic)
-            hipLaunchKernelGGL(reduce_partials, dim3((kGradLen + 255) / 256), dim3(256), 0, s, partials, grid, grad);
-        pix_off += (int64_t)cams[c].width * cams[c].height;
-    }
-    if (rc == AMR_OK)
-        hipLaunchKernelGGL(split_grad, dim3((kGradLen + 255) / 256), dim3(256), 0, s, grad, d_grad_lut, d_grad_light);
-    int rc2 = check_hip(hipFreeAsync(scratch, s), "hipFreeAsync");
-    return rc ? rc : rc2;
+    return backward_launch(S, cams, ncams, P, d_grad_rgba, d_grad_lut, d_grad_light, deterministic,
+                           P ? (float *)P->d_work : nullptr, stream);
 }
 
 }  // extern "C"

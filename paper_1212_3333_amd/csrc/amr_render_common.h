@@ -11,6 +11,7 @@
 namespace amr {
 
 constexpr int kGradLen = 1024 + 5;   // dL/dLUT [256][4] then dL/d(light xyz, k_a, k_d)
+constexpr int kBwdGrid = 2048;       // adjoint blocks: fixed, so deterministic mode sums a fixed set of partials
 
 struct CkptHeader {                  // per ray, written at the end of the forward
     float T, C[3];
@@ -69,7 +70,7 @@ struct BwdArgs {
 
 struct Counters {   // per lane (32-bit); summed over the wave in 64 bits when flushed
     unsigned int samples = 0, segments = 0, hit = 0, desc = 0, guard = 0, tover = 0, ckover = 0;
-    unsigned int split = 0, face = 0, unsure = 0;
+    unsigned int split = 0, face = 0, unsure = 0, linl = 0;
 };
 
 // ------------------------------------------------------------------------------------------
@@ -1288,6 +1289,7 @@ __device__ __forceinline__ void flush_counters(amr_render_stats *st, Counters c,
     u64 d = wave_sum((u64)c.desc), gu = wave_sum((u64)c.guard), to = wave_sum((u64)c.tover);
     u64 co = wave_sum((u64)c.ckover);
     u64 sp = wave_sum((u64)c.split), fa = wave_sum((u64)c.face), un = wave_sum((u64)c.unsure);
+    u64 li = wave_sum((u64)c.linl);
     if (lane == 0) {
         if (s) atomicAdd(&st->samples, s);
         if (g) atomicAdd(&st->segments, g);
@@ -1299,6 +1301,7 @@ __device__ __forceinline__ void flush_counters(amr_render_stats *st, Counters c,
         if (sp) atomicAdd(&st->split_samples, sp);
         if (fa) atomicAdd(&st->face_taps, fa);
         if (un) atomicAdd(&st->unsure_taps, un);
+        if (li) atomicAdd(&st->light_inline, li);
     }
 }
 
@@ -1386,8 +1389,10 @@ inline int fill_args(const amr_scene *S, const amr_camera *C, const amr_render_p
     return AMR_OK;
 }
 
-// Point-light secondary-ray launch for one camera (amr_shadow.hip).
-int launch_shadow(const RenderArgs &A, bool rec, void *stream);
+// Point-light secondary-ray launch for one camera (amr_shadow.hip), with its workspace of
+// shadow_work_bytes(npix, jobs) bytes.
+int64_t shadow_work_bytes(int64_t npix, int64_t jobs);
+int launch_shadow(const RenderArgs &A, bool rec, void *stream, void *work, int64_t work_bytes, int64_t jobs);
 
 // Learned-proposal / segment-logging launch for one camera (amr_learned.hip).
 int launch_learned(const RenderArgs &A, const amr_render_params *P, int lmax, void *stream, bool first_camera);

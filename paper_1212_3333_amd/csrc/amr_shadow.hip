@@ -13,8 +13,13 @@
 //   3. trace every job's shadow ray, one per lane: consecutive lanes hold consecutive samples of
 //      a ray, whose shadow rays run side by side to the light;
 //   4. march again and composite with the stored transmittances.
-// The job arrays (16 bytes per sample) are allocated for the call and freed before it returns.
+// The per-ray counts and offsets and the job arrays (16 bytes per sample) live in the caller's
+// workspace; a sample whose job does not fit traces its secondary ray in the shading pass, so
+// the image never depends on the workspace's size.  Nothing is read back to the host: the job
+// count stays on the device and bounds the secondary-ray pass.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 
 #include "amr_render_common.h"
 
@@ -84,10 +89,11 @@ __device__ __forceinline__ float light_transmittance(const RenderArgs &A, const 
 struct ShadowWork {
     int32_t *cnt;       // [npix] samples per ray (pass 1)
     int64_t *off;       // [npix] first job of each ray
-    double *tk;         // [njobs] ray parameter of each sample
-    int32_t *ray;       // [njobs] the sample's ray
-    float *tl;          // [njobs] transmittance to the light
-    int64_t njobs;
+    int64_t *total;     // [1] jobs of the frame (all samples), written by the scan
+    double *tk;         // [cap] ray parameter of each sample
+    int32_t *ray;       // [cap] the sample's ray
+    float *tl;          // [cap] transmittance to the light
+    int64_t cap;        // jobs the arrays hold
 };
 
 enum { kPassCount = 0, kPassRecord = 1, kPassShade = 2 };
@@ -141,13 +147,26 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void sh
             for (int k = 0; k < nsm; k++) {
                 SampleVals v;
                 eval_sample<false, REC, false, LAY>(A, s_lut, R, S, k, v, cnt);
-                if (PASS == kPassRecord && nsamp_total < njob) {
+                const bool job = nsamp_total < njob && base + nsamp_total < W.cap;
+                if (PASS == kPassRecord && job) {
 #pragma clang fp contract(off)
                     W.tk[base + nsamp_total] = S.ta + ((double)k + 0.5) * S.delta;
                     W.ray[base + nsamp_total] = (int32_t)ray;
                 }
                 if (PASS == kPassShade) {
-                    const float tl = nsamp_total < njob ? W.tl[base + nsamp_total] : 1.f;
+                    float tl;
+                    if (job) {
+                        tl = W.tl[base + nsamp_total];
+                    } else {
+                        // no job slot: the secondary ray from the same FP64 sample position
+#pragma clang fp contract(off)
+                        const double tk = S.ta + ((double)k + 0.5) * S.delta;
+                        double x[3];
+                        #pragma unroll
+                        for (int b = 0; b < 3; b++) x[b] = R.o[b] + tk * R.d[b];
+                        tl = light_transmittance<LAY>(A, s_lut, x);
+                        if (REC) cnt.linl++;
+                    }
                     const float shade = A.k_a + A.k_d * tl;
                     const float wgt = T * v.alpha * shade;
                     C0 += wgt * v.r;
@@ -192,23 +211,31 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void sh
     }
 }
 
-// Pass 3: one shadow ray per lane, from the recorded sample position to the light.
+// Pass 3: one shadow ray per lane, from the recorded sample position to the light; the grid
+// strides over the jobs recorded (the frame's job count, capped by the arrays), consecutive
+// lanes taking consecutive jobs.
 template <int LAY>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void shadow_rays(RenderArgs A, ShadowWork W) {
 #pragma clang fp contract(off)
     __shared__ float4 s_lut[256];
     for (int i = threadIdx.x; i < 256; i += 64) s_lut[i] = A.lut[i];
     __syncthreads();
-    const int64_t j = (int64_t)blockIdx.x * 64 + threadIdx.x;
-    if (j >= W.njobs) return;
-    const int r = W.ray[j];
-    Ray R;
-    setup_ray(A, r % A.width, r / A.width, R);   // a ray with samples, so it meets the clip box
-    const double tk = W.tk[j];
-    double x[3];
-    #pragma unroll
-    for (int b = 0; b < 3; b++) x[b] = R.o[b] + tk * R.d[b];
-    W.tl[j] = light_transmittance<LAY>(A, s_lut, x);
+    const int64_t njobs = min(*W.total, W.cap);
+    const int64_t npix = (int64_t)A.width * A.height;
+    for (int64_t j = (int64_t)blockIdx.x * 64 + threadIdx.x; j < njobs; j += (int64_t)gridDim.x * 64) {
+        const int r = W.ray[j];
+        float tl = 1.f;
+        if (r >= 0 && r < npix) {              // every job below the count was recorded
+            Ray R;
+            setup_ray(A, r % A.width, r / A.width, R);   // a ray with samples, so it meets the clip box
+            const double tk = W.tk[j];
+            double x[3];
+            #pragma unroll
+            for (int b = 0; b < 3; b++) x[b] = R.o[b] + tk * R.d[b];
+            tl = light_transmittance<LAY>(A, s_lut, x);
+        }
+        W.tl[j] = tl;
+    }
 }
 
 // Block-wise exclusive scan of the per-ray counts (1024 per block), then of the block sums.
@@ -262,69 +289,66 @@ static void launch_march(int pass, bool rec, int grid, hipStream_t s, const Rend
     else hipLaunchKernelGGL((shadow_march<kPassShade, false, LAY>), dim3(grid), dim3(64), 0, s, A, W);
 }
 
-int launch_shadow(const RenderArgs &A, bool rec, void *stream) {
+// Workspace of the point-light passes for npix rays and `jobs` job slots: counts, offsets,
+// scan block sums and the job total, then the three job arrays, each 256-byte aligned.
+static inline int64_t align256(int64_t b) { return (b + 255) / 256 * 256; }
+
+int64_t shadow_work_bytes(int64_t npix, int64_t jobs) {
+    const int64_t nb = (npix + 1023) / 1024;
+    return align256(4 * npix) + align256(8 * npix) + align256(8 * nb) + 256 + align256(8 * jobs) + align256(4 * jobs) +
+           align256(4 * jobs);
+}
+
+int launch_shadow(const RenderArgs &A, bool rec, void *stream, void *work, int64_t work_bytes, int64_t jobs) {
     hipStream_t s = (hipStream_t)stream;
     const int grid = 8 * ((A.sgrid * A.sgrid + 7) / 8) * 16;
     const int64_t npix = (int64_t)A.width * A.height;
     const int64_t nb = (npix + 1023) / 1024;
+    if (!work || jobs < 0 || work_bytes < shadow_work_bytes(npix, jobs)) {
+        set_error("point-light lighting needs a workspace of amr_render_work_bytes() bytes (params.d_work, "
+                  "params.work_bytes, params.light_jobs)");
+        return work ? AMR_ECAPACITY : AMR_EINVAL;
+    }
     RenderArgs Ap = A;                      // counting and recording passes record nothing else
     Ap.trace = nullptr;
     Ap.trace_n = nullptr;
     Ap.nsamp = nullptr;
     Ap.stats = nullptr;
     Ap.touch = nullptr;
+    char *p = (char *)work;
     ShadowWork W{};
-    int64_t *bsum = nullptr, *d_total = nullptr;
-    int rc = AMR_OK;
+    W.cnt = (int32_t *)p;
+    p += align256(4 * npix);
+    W.off = (int64_t *)p;
+    p += align256(8 * npix);
+    int64_t *bsum = (int64_t *)p;
+    p += align256(8 * nb);
+    W.total = (int64_t *)p;
+    p += 256;
+    W.tk = (double *)p;
+    p += align256(8 * jobs);
+    W.ray = (int32_t *)p;
+    p += align256(4 * jobs);
+    W.tl = (float *)p;
+    W.cap = jobs;
     auto march = [&](int pass, const RenderArgs &Aa) {
         if (Aa.layout == 0) launch_march<0>(pass, rec, grid, s, Aa, W);
         else if (Aa.layout == 1) launch_march<1>(pass, rec, grid, s, Aa, W);
         else launch_march<2>(pass, rec, grid, s, Aa, W);
     };
-    hipError_t e = hipMalloc((void **)&W.cnt, sizeof(int32_t) * npix);
-    if (e == hipSuccess) e = hipMalloc((void **)&W.off, sizeof(int64_t) * npix);
-    if (e == hipSuccess) e = hipMalloc((void **)&bsum, sizeof(int64_t) * nb);
-    if (e == hipSuccess) e = hipMalloc((void **)&d_total, sizeof(int64_t));
-    if (e == hipSuccess) {
-        march(kPassCount, Ap);
-        hipLaunchKernelGGL(scan_counts, dim3(nb), dim3(1024), 0, s, W.cnt, npix, W.off, bsum);
-        hipLaunchKernelGGL(scan_block_sums, dim3(1), dim3(1024), 0, s, bsum, nb, d_total);
-        hipLaunchKernelGGL(add_block_offsets, dim3(nb), dim3(1024), 0, s, W.off, npix, bsum);
-        int64_t total = 0;
-        e = hipGetLastError();
-        if (e == hipSuccess) e = hipMemcpyAsync(&total, d_total, sizeof(int64_t), hipMemcpyDeviceToHost, s);
-        if (e == hipSuccess) e = hipStreamSynchronize(s);
-        W.njobs = total;
-        if (e == hipSuccess && total > 0) {
-            e = hipMalloc((void **)&W.tk, sizeof(double) * total);
-            if (e == hipSuccess) e = hipMalloc((void **)&W.ray, sizeof(int32_t) * total);
-            if (e == hipSuccess) e = hipMalloc((void **)&W.tl, sizeof(float) * total);
-            // defined contents for any job a differing count would leave unwritten
-            if (e == hipSuccess) e = hipMemsetAsync(W.tk, 0, sizeof(double) * total, s);
-            if (e == hipSuccess) e = hipMemsetAsync(W.ray, 0, sizeof(int32_t) * total, s);
-        }
-        if (e == hipSuccess) {
-            if (total > 0) {
-                march(kPassRecord, Ap);
-                const int64_t nj = (total + 63) / 64;
-                if (A.layout == 0) hipLaunchKernelGGL((shadow_rays<0>), dim3(nj), dim3(64), 0, s, Ap, W);
-                else if (A.layout == 1) hipLaunchKernelGGL((shadow_rays<1>), dim3(nj), dim3(64), 0, s, Ap, W);
-                else hipLaunchKernelGGL((shadow_rays<2>), dim3(nj), dim3(64), 0, s, Ap, W);
-            }
-            march(kPassShade, A);
-            e = hipGetLastError();
-            if (e == hipSuccess) e = hipStreamSynchronize(s);   // the job arrays are freed below
-        }
+    march(kPassCount, Ap);
+    hipLaunchKernelGGL(scan_counts, dim3(nb), dim3(1024), 0, s, W.cnt, npix, W.off, bsum);
+    hipLaunchKernelGGL(scan_block_sums, dim3(1), dim3(1024), 0, s, bsum, nb, W.total);
+    hipLaunchKernelGGL(add_block_offsets, dim3(nb), dim3(1024), 0, s, W.off, npix, bsum);
+    if (jobs > 0) {
+        march(kPassRecord, Ap);
+        const int64_t nj = std::min<int64_t>((jobs + 63) / 64, 256 * 32);
+        if (A.layout == 0) hipLaunchKernelGGL((shadow_rays<0>), dim3(nj), dim3(64), 0, s, Ap, W);
+        else if (A.layout == 1) hipLaunchKernelGGL((shadow_rays<1>), dim3(nj), dim3(64), 0, s, Ap, W);
+        else hipLaunchKernelGGL((shadow_rays<2>), dim3(nj), dim3(64), 0, s, Ap, W);
     }
-    if (e != hipSuccess) rc = check_hip(e, "point-light passes");
-    hipFree(W.cnt);
-    hipFree(W.off);
-    hipFree(bsum);
-    hipFree(d_total);
-    hipFree(W.tk);
-    hipFree(W.ray);
-    hipFree(W.tl);
-    return rc;
+    march(kPassShade, A);
+    return check_hip(hipGetLastError(), "point-light passes");
 }
 
 }  // namespace amr

@@ -468,7 +468,7 @@ def _render_call(lib, scene, cams, prm, set_fields=None, lut_ok=True):
 
 
 @pytest.mark.parametrize("case", ["v_range", "step", "cam_size", "interp", "lighting", "lod", "lut", "trace_cap",
-                                  "ckpt_odd", "ckpt_small", "tile", "no_queue"])
+                                  "ckpt_odd", "ckpt_small", "tile", "no_queue", "light_no_work", "light_work_small"])
 def test_render_argument_checks(case):
     """amr_render's argument checks, each of which returns before any device access (host buffers
     stand in for device pointers, so the test runs only where no GPU is visible)."""
@@ -506,16 +506,23 @@ def test_render_argument_checks(case):
         p, fields, words = dict(prm, persistent=1, tile_w=16, tile_h=8), dict(d_queue="buf"), "tile_w * tile_h"
     elif case == "no_queue":
         p, words = dict(prm, persistent=1), "d_queue"
+    elif case == "light_no_work":
+        p, words = dict(prm, lighting=2), "workspace"
+    elif case == "light_work_small":
+        p, words, want_code = dict(prm, lighting=2), "workspace", 3
+        fields = dict(d_work="buf", work_bytes=1 << 16, light_jobs=1 << 20)
     rc, msg = _render_call(lib, scene, cl, p, fields, lut_ok)
     assert rc == want_code, (case, rc, msg)
     assert words in msg, (case, msg)
 
 
-@pytest.mark.parametrize("case", ["no_ckpt", "nearest", "point_light", "ckpt_small"])
+@pytest.mark.parametrize("case", ["no_ckpt", "nearest", "point_light", "ckpt_small", "no_work", "work_small",
+                                  "work_small_det"])
 def test_backward_argument_checks(case):
-    """amr_render_backward's checks that precede its scratch allocation: checkpoints required,
-    trilinear sampling and gradient lighting only, a checkpoint buffer of the forward's size
-    (host buffers stand in for device pointers: CPU only)."""
+    """amr_render_backward's checks that precede any launch: a caller workspace of
+    amr_backward_work_bytes(deterministic) bytes, checkpoints required, trilinear sampling and
+    gradient lighting only, a checkpoint buffer of the forward's size (host buffers stand in
+    for device pointers: CPU only)."""
     import torch
     if torch.cuda.device_count() > 0:
         pytest.skip("host buffers stand in for device pointers: CPU only")
@@ -540,9 +547,49 @@ def test_backward_argument_checks(case):
     if case != "no_ckpt":
         q.d_ckpt, q.ckpt_every, q.ckpt_max = ck.ctypes.data, 2, 4
         q.ckpt_bytes = 64 if case == "ckpt_small" else int(lib.amr_ckpt_bytes(npix, 4))
+    det = 1 if case == "work_small_det" else 0
+    need = int(lib.amr_backward_work_bytes(det))
+    assert need == 4 * 1029 * (1 + 2048 * det)
+    work = np.zeros(need, np.uint8)
+    if case != "no_work":
+        q.d_work = work.ctypes.data
+        q.work_bytes = int(lib.amr_backward_work_bytes(0)) if case == "work_small_det" else (
+            need - 4 if case == "work_small" else need)
     rc = lib.amr_render_backward(ctypes.byref(scene.scene), carr, 1, ctypes.byref(q), g.ctypes.data, glut.ctypes.data,
-                                 glight.ctypes.data, 0, None)
+                                 glight.ctypes.data, det, None)
     msg = lib.amr_last_error().decode()
     want = {"no_ckpt": (1, "checkpoints"), "nearest": (1, "trilinear"), "point_light": (1, "lighting 0 and 1"),
-            "ckpt_small": (3, "too small")}[case]
+            "ckpt_small": (3, "too small"), "no_work": (1, "workspace"), "work_small": (3, "work_bytes"),
+            "work_small_det": (3, "work_bytes")}[case]
     assert rc == want[0] and want[1] in msg, (case, rc, msg)
+
+
+def test_render_work_bytes():
+    """Workspace size queries: the point light's per-ray counts, offsets, scan sums and job total
+    for the largest camera plus 16 bytes per job slot, each section 256-byte aligned; nothing for
+    the other lighting modes; -1 for invalid arguments.  The adjoint's: 1029 floats, plus one
+    partial sum of 1029 floats per block of its 2048-block grid when deterministic."""
+    lib = amr.load()
+    h, lut, cams, prm = workloads.small_nested(0)
+    two = [dict(cams[0], width=300, height=200), dict(cams[1], width=100, height=700)]
+    carr = (L.amr_camera * 2)(*[amr.make_camera(c) for c in two])
+    lutbuf = np.zeros((256, 4), np.float32)
+
+    def a256(b):
+        return (b + 255) // 256 * 256
+    for jobs in (0, 1, 1000, 123457):
+        q = amr.make_params(dict(prm, lighting=2), lutbuf)
+        q.light_jobs = jobs
+        n = 100 * 700
+        nb = (n + 1023) // 1024
+        want = a256(4 * n) + a256(8 * n) + a256(8 * nb) + 256 + a256(8 * jobs) + 2 * a256(4 * jobs)
+        assert lib.amr_render_work_bytes(carr, 2, ctypes.byref(q)) == want
+    for lighting in (0, 1):
+        q = amr.make_params(dict(prm, lighting=lighting), lutbuf)
+        assert lib.amr_render_work_bytes(carr, 2, ctypes.byref(q)) == 0
+    q = amr.make_params(dict(prm, lighting=2), lutbuf)
+    q.light_jobs = -1
+    assert lib.amr_render_work_bytes(carr, 2, ctypes.byref(q)) == -1
+    assert lib.amr_render_work_bytes(carr, 0, ctypes.byref(q)) == -1
+    assert lib.amr_backward_work_bytes(0) == 4 * 1029
+    assert lib.amr_backward_work_bytes(1) == 4 * 1029 * 2049
