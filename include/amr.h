@@ -332,6 +332,22 @@ int amr_render_backward(const amr_scene *scene, const amr_camera *cams, int32_t 
                         const amr_render_params *params, const float *d_grad_rgba,
                         float *d_grad_lut, float *d_grad_light, int32_t deterministic, void *stream);
 
+/* For callers that cannot allocate device memory or pass a workspace (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): amr_render_backward with its
+ * gradient accumulators in a fixed device array inside the library instead of params->d_work
+ * (ignored here).  The array holds amr_backward_static_bytes() bytes (the deterministic
+ * mode's need, 8.4 MB) on every GPU the library runs on, until the process ends; a need beyond
+ * it returns AMR_ECAPACITY.  Its address on a device is looked up on the first call there.
+ * The call allocates nothing and clears the accumulators itself (with a kernel, no memset),
+ * so each call starts from zero; every call on one GPU shares that GPU's array, so calls that
+ * overlap on one GPU (different streams, or threads without ordering) race and must not be
+ * made.  Arguments, outputs and errors otherwise as amr_render_backward. */
+int64_t amr_backward_static_bytes(void);
+int amr_render_backward_static(const amr_scene *scene, const amr_camera *cams, int32_t ncams,
+                               const amr_render_params *params, const float *d_grad_rgba,
+                               float *d_grad_lut, float *d_grad_light, int32_t deterministic,
+                               void *stream);
+
 /* ---------------------------------------------------------------------------------------- */
 /* Proposal network for learned segment skipping (an addition to the paper)                 */
 /* ---------------------------------------------------------------------------------------- */

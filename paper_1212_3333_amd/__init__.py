@@ -488,9 +488,11 @@ def render_checkpointed(scene: Scene, cams, lut: torch.Tensor, params: dict, ckp
 
 
 def render_backward(scene: Scene, cams, lut: torch.Tensor, params: dict, ckpt: Checkpoints,
-                    grad_rgba: torch.Tensor, deterministic: bool = False):
+                    grad_rgba: torch.Tensor, deterministic: bool = False, static_work: bool = False):
     """dL/dLUT [256,4] and dL/d(light_x, light_y, light_z, k_a, k_d) [5] from dL/dRGBA, using the
-    checkpoints of the matching forward call (amr_render_backward)."""
+    checkpoints of the matching forward call (amr_render_backward).  static_work: call
+    amr_render_backward_static, whose accumulators live in the library's fixed device array
+    (no workspace is allocated here)."""
     lib = load()
     dev = scene.pool.device
     cam_list, carr = _cams(cams)
@@ -500,6 +502,11 @@ def render_backward(scene: Scene, cams, lut: torch.Tensor, params: dict, ckpt: C
     q.d_ckpt, q.ckpt_bytes, q.ckpt_every, q.ckpt_max = ckpt.buf.data_ptr(), ckpt.nbytes, ckpt.every, ckpt.max
     glut = torch.empty((256, 4), dtype=torch.float32, device=dev)
     glight = torch.empty(5, dtype=torch.float32, device=dev)
+    if static_work:
+        check(lib.amr_render_backward_static(ctypes.byref(scene.scene), carr, len(cam_list), ctypes.byref(q), _vp(g),
+                                             _vp(glut), _vp(glight), int(bool(deterministic)), _stream(dev)),
+              "amr_render_backward_static")
+        return glut, glight
     nwork = int(lib.amr_backward_work_bytes(int(bool(deterministic))))
     work = torch.empty(nwork, dtype=torch.uint8, device=dev)
     q.d_work, q.work_bytes = work.data_ptr(), nwork

@@ -142,7 +142,10 @@ SIGNATURES = {
     "amr_render_work_bytes": (ctypes.c_int64, [ctypes.POINTER(amr_camera), ctypes.c_int32,
                                                ctypes.POINTER(amr_render_params)]),
     "amr_backward_work_bytes": (ctypes.c_int64, [ctypes.c_int32]),
+    "amr_backward_static_bytes": (ctypes.c_int64, []),
     "amr_render_backward": (ctypes.c_int, [ctypes.POINTER(amr_scene), ctypes.POINTER(amr_camera), ctypes.c_int32,
+                                           ctypes.POINTER(amr_render_params), VP, VP, VP, ctypes.c_int32, VP]),
+    "amr_render_backward_static": (ctypes.c_int, [ctypes.POINTER(amr_scene), ctypes.POINTER(amr_camera), ctypes.c_int32,
                                            ctypes.POINTER(amr_render_params), VP, VP, VP, ctypes.c_int32, VP]),
     "amr_mlp_param_count": (ctypes.c_int32, []),
     "amr_mlp_forward": (ctypes.c_int, [VP, VP, VP, VP, ctypes.c_int64, VP]),

@@ -14,6 +14,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 
 #include "amr_render_common.h"
 
@@ -465,11 +466,57 @@ int backward_launch(const amr_scene *S, const amr_camera *cams, int32_t ncams, c
     return rc;
 }
 
+// Workspace of amr_render_backward_static: the adjoint's gradient accumulators (1029 floats)
+// and deterministic partial sums (one 1029-float row per block of the fixed grid), in a
+// fixed array of the library's code object.  Each GPU the library runs on holds its own copy
+// until the process ends.  Host code never uses the array's name as a device address; it takes
+// each device's address once from hipGetSymbolAddress, with that device current.
+constexpr size_t kStaticWorkFloats = (size_t)kGradLen * (1 + (size_t)kBwdGrid);
+static __device__ __align__(256) float scratch[kStaticWorkFloats];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_static_work_mu;
+static float *g_static_work[kMaxDevices];
+
+// Device address of this device's copy of `scratch` (the current device), looked up on the
+// first call on that device; nullptr (with the error set) if HIP fails.
+static float *static_work_ptr() {
+    int dev = -1;
+    if (check_hip(hipGetDevice(&dev), "hipGetDevice")) return nullptr;
+    if (dev < 0 || dev >= kMaxDevices) {
+        set_error("device %d beyond the %d devices the static workspace serves", dev, kMaxDevices);
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(g_static_work_mu);
+    if (!g_static_work[dev]) {
+        void *ptr = nullptr;
+        if (check_hip(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)")) return nullptr;
+        g_static_work[dev] = (float *)ptr;
+    }
+    return g_static_work[dev];
+}
+
 }  // namespace amr
 
 using namespace amr;
 
 extern "C" {
+
+int64_t amr_backward_static_bytes(void) { return (int64_t)sizeof(scratch); }
+
+int amr_render_backward_static(const amr_scene *S, const amr_camera *cams, int32_t ncams, const amr_render_params *P,
+                               const float *d_grad_rgba, float *d_grad_lut, float *d_grad_light, int32_t deterministic,
+                               void *stream) {
+    const int64_t need = amr_backward_work_bytes(deterministic);
+    if (need > (int64_t)sizeof(scratch)) {
+        set_error("the adjoint needs %lld workspace bytes, more than the %lld of the static workspace", (long long)need,
+                  (long long)sizeof(scratch));
+        return AMR_ECAPACITY;
+    }
+    float *work = static_work_ptr();
+    if (!work) return AMR_EHIP;
+    return backward_launch(S, cams, ncams, P, d_grad_rgba, d_grad_lut, d_grad_light, deterministic, work, stream);
+}
 
 int64_t amr_ckpt_bytes(int64_t nrays, int32_t ckpt_max) {
     if (nrays < 0 || ckpt_max < 2) return 0;
