@@ -339,37 +339,64 @@ def learned_skip_section(amr, dev, steps, warmup):
     held = workloads.deep_range_orbits(h, 6, 2, 192)
     plain_held = [amr.render(scene, c, lut_t, prm)["rgba"].clone() for c in held]
     te, ts, table = learned.calibrate(scene, held, lut_t, prm, net.packed, plain_held, max_err=1e-3)
+    tb, table_b = learned.calibrate_bound_only(scene, held, lut_t, prm, plain_held, max_err=1e-3)
     torch.cuda.synchronize()
     train_s = time.time() - t
     cam = cams[0]
     W_, H_ = cam["width"], cam["height"]
 
-    def compare(c):
-        """Plain and learned frames of camera c: times, stats and the learned image's error."""
+    def timed(c, prm_x, **kw):
         out = torch.empty(c["width"] * c["height"] * 4, dtype=torch.float32, device=dev)
-        p_stats = amr.stats_dict(amr.render(scene, c, lut_t, prm, stats=True))
-        l_res = learned.render_learned(scene, c, lut_t, prm, net.packed, te, ts, stats=True)
-        l_stats = amr.stats_dict(l_res)
-        plain_img = amr.render(scene, c, lut_t, prm)["rgba"]
-        err = float((l_res["rgba"] - plain_img).abs().max().item())
-        del l_res, plain_img
-        ms_p = time_frames(amr, scene, c, lut_t, prm, steps, warmup, out)
-        prm_l = dict(prm, tau_e=te, tau_s=ts)
         for _ in range(warmup):
-            amr.render(scene, c, lut_t, prm_l, out=out, d_mlp=net.packed)
+            amr.render(scene, c, lut_t, prm_x, out=out, **kw)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
         for _ in range(steps):
-            amr.render(scene, c, lut_t, prm_l, out=out, d_mlp=net.packed)
+            amr.render(scene, c, lut_t, prm_x, out=out, **kw)
         e1.record()
         torch.cuda.synchronize()
-        return ms_p, e0.elapsed_time(e1) / steps, p_stats, l_stats, err
+        return e0.elapsed_time(e1) / steps
 
-    ms_p, ms_l, p_stats, l_stats, err = compare(cam)
-    ms_p2, ms_l2, p_stats2, l_stats2, err2 = compare(dict(cam, width=2048, height=2048))
-    log("learned skip: plain %.3f ms, learned %.3f ms, err %.2e, tau_e %g tau_s %g; 2048^2: %.3f / %.3f ms, err %.2e"
-        % (ms_p, ms_l, err, te, ts, ms_p2, ms_l2, err2))
+    def form(c, prm_x, plain_img, **kw):
+        """Time, counters and error against the plain image of one form of the render."""
+        r = amr.render(scene, c, lut_t, prm_x, stats=True, **kw)
+        st = amr.stats_dict(r)
+        err = float((r["rgba"] - plain_img).abs().max().item())
+        del r
+        return dict(ms=round(timed(c, prm_x, **kw), 4), samples=st["samples"], segments=st["segments"],
+                    skipped_segments=st["skipped_segments"], net_segments=st["net_segments"],
+                    coarse_segments=st["coarse_segments"], max_rgba_err_vs_plain=err)
+
+    def compare(c):
+        """Plain, learned (bound + network, its calibrated thresholds), bound-only at its own
+        calibrated threshold and bound-only at the network's threshold, on camera c."""
+        p_res = amr.render(scene, c, lut_t, prm, stats=True)
+        p_stats, plain_img = amr.stats_dict(p_res), p_res["rgba"].clone()
+        del p_res
+        res = dict(plain=dict(ms=round(timed(c, prm), 4), samples=p_stats["samples"], segments=p_stats["segments"]))
+        res["learned"] = form(c, dict(prm, tau_e=te, tau_s=ts), plain_img, d_mlp=net.packed)
+        res["bound_only"] = form(c, dict(prm, tau_e=tb, tau_s=0.0, bound_only=1), plain_img)
+        res["bound_only_at_learned_tau"] = form(c, dict(prm, tau_e=te, tau_s=0.0, bound_only=1), plain_img)
+        return res
+
+    r1 = compare(cam)
+    r2 = compare(dict(cam, width=2048, height=2048))
+    ms_p, ms_l, p_stats, l_stats, err = (r1["plain"]["ms"], r1["learned"]["ms"], r1["plain"],
+                                         r1["learned"], r1["learned"]["max_rgba_err_vs_plain"])
+    ms_p2, ms_l2 = r2["plain"]["ms"], r2["learned"]["ms"]
+    log("learned skip: plain %.3f ms, learned %.3f ms, bound-only %.3f ms, err %.2e, tau_e %g tau_s %g (bound-only "
+        "tau_e %g); 2048^2: %.3f / %.3f / %.3f ms" % (ms_p, ms_l, r1["bound_only"]["ms"], err, te, ts, tb, ms_p2, ms_l2,
+                                                     r2["bound_only"]["ms"]))
+
+    def forms(r):
+        """The bound-only rows of one resolution, with their speed-up over plain."""
+        out = {}
+        for k in ("bound_only", "bound_only_at_learned_tau"):
+            out[k] = dict(r[k], speedup=round(r["plain"]["ms"] / r[k]["ms"], 3))
+        out["network_fewer_samples_than_bound_at_same_tau"] = int(r["bound_only_at_learned_tau"]["samples"] -
+                                                                  r["learned"]["samples"])
+        return out
     return {
         "workload": "deep-range SAMR: root 64^3, 20 levels, r=2, %d patches around 3 power-law cores; 1024x1024 "
                     "full-domain view, unlit" % len(h.patches),
@@ -383,12 +410,14 @@ def learned_skip_section(amr, dev, steps, warmup):
         "skipped_segments": l_stats["skipped_segments"], "coarse_segments": l_stats["coarse_segments"],
         "net_segments": l_stats["net_segments"], "segments": l_stats["segments"],
         "plain_samples": p_stats["samples"], "learned_samples": l_stats["samples"],
+        "bound_only_tau_e": tb, **forms(r1),
         "train_segments": int(X.shape[0]), "train_calibrate_s": round(train_s, 2), "prepare_s": round(prep, 2),
         "at_2048": {"plain_ms": round(ms_p2, 4), "learned_ms": round(ms_l2, 4), "speedup": round(ms_p2 / ms_l2, 3),
                     "plain_mrays_per_s": round(2048 * 2048 / (ms_p2 * 1e-3) / 1e6, 3),
                     "learned_mrays_per_s": round(2048 * 2048 / (ms_l2 * 1e-3) / 1e6, 3),
-                    "plain_samples": p_stats2["samples"], "learned_samples": l_stats2["samples"],
-                    "max_rgba_err_vs_plain": err2},
+                    "plain_samples": r2["plain"]["samples"], "learned_samples": r2["learned"]["samples"],
+                    "segments": r2["plain"]["segments"],
+                    "max_rgba_err_vs_plain": r2["learned"]["max_rgba_err_vs_plain"], **forms(r2)},
     }
 
 

@@ -286,6 +286,12 @@ typedef struct {
                                            camera (16 bytes each); a sample beyond this count has
                                            its secondary ray traced in the shading pass (same
                                            value, slower; counted in light_inline) */
+    int32_t bound_only;                 /* 1: skip segments by the analytic bound alone (the learned
+                                           kernel with the network never consulted; d_mlp must be
+                                           NULL): a data segment is skipped if B + T * alpha_max <
+                                           tau_e, with B and alpha_max as for learned proposals; no
+                                           coarse sampling.  0: learned proposals when d_mlp is set */
+    int32_t pad1_;
 } amr_render_params;
 
 /* Renders ncams cameras (host array) into d_rgba (device, premultiplied RGBA fp32, images
@@ -347,6 +353,18 @@ int amr_render_backward_static(const amr_scene *scene, const amr_camera *cams, i
                                const amr_render_params *params, const float *d_grad_rgba,
                                float *d_grad_lut, float *d_grad_light, int32_t deterministic,
                                void *stream);
+
+/* ---------------------------------------------------------------------------------------- */
+/* Measurement (not a step of the method)                                                     */
+/* ---------------------------------------------------------------------------------------- */
+
+/* Read-bandwidth probe for the rooflines: `blocks` blocks of 256 threads stride over d_buf
+ * (device, `bytes` bytes of non-negative floats, 16-byte aligned; the tail beyond a multiple
+ * of 16 bytes is not read) `reps` times, each block reading the same elements every time, and
+ * store nothing (d_sink, device [1], is written only if the sum of the data is -1).  Timed by
+ * the caller around the launch on `stream`: bytes/16*16 * reps / time is the sustained read
+ * rate of the cache level the buffer fits in (a few MB per XCD: L2). */
+int amr_probe_read(const void *d_buf, int64_t bytes, int32_t reps, int32_t blocks, float *d_sink, void *stream);
 
 /* ---------------------------------------------------------------------------------------- */
 /* Proposal network for learned segment skipping (an addition to the paper)                 */

@@ -328,6 +328,7 @@ def make_params(p: dict, d_lut) -> L.amr_render_params:
     q.blocks_per_cu = int(p.get("blocks_per_cu", 0))
     q.interp = int(p.get("interp", 0))
     q.lod = float(p.get("lod", 0.0))
+    q.bound_only = int(bool(p.get("bound_only", 0)))
     return q
 
 
@@ -444,6 +445,22 @@ def camera_table(cams, device="cuda") -> torch.Tensor:
 
 def queue_buffer(ncams: int, device="cuda") -> torch.Tensor:
     return torch.zeros(int(load().amr_queue_bytes(ncams)), dtype=torch.uint8, device=device)
+
+
+def read_bandwidth(nbytes: int, reps: int, blocks: int = 2048, device="cuda") -> float:
+    """Sustained read rate (GB/s) of the cache level a buffer of nbytes fits in, from the
+    library's read probe timed with HIP events on the current stream (one warm-up launch)."""
+    lib = load()
+    buf = torch.ones(max(16, nbytes) // 4, dtype=torch.float32, device=device)
+    sink = torch.zeros(1, dtype=torch.float32, device=device)
+    st = _stream(device)
+    check(lib.amr_probe_read(_vp(buf), buf.numel() * 4, 1, blocks, _vp(sink), st), "amr_probe_read")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    check(lib.amr_probe_read(_vp(buf), buf.numel() * 4, reps, blocks, _vp(sink), st), "amr_probe_read")
+    e1.record()
+    torch.cuda.synchronize(device)
+    return buf.numel() * 4 // 16 * 16 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
 
 
 def wall_clock_khz() -> int:

@@ -107,7 +107,8 @@ class amr_render_params(ctypes.Structure):
                 ("persistent", ctypes.c_int32), ("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32),
                 ("blocks_per_cu", ctypes.c_int32), ("interp", ctypes.c_int32), ("lod", ctypes.c_float),
                 ("d_queue", VP), ("d_stamps", VP), ("d_cams", VP), ("d_touch", VP),
-                ("d_work", VP), ("work_bytes", ctypes.c_int64), ("light_jobs", ctypes.c_int64)]
+                ("d_work", VP), ("work_bytes", ctypes.c_int64), ("light_jobs", ctypes.c_int64),
+                ("bound_only", ctypes.c_int32), ("pad1_", ctypes.c_int32)]
 
 
 class amr_seglog_rec(ctypes.Structure):
@@ -143,6 +144,7 @@ SIGNATURES = {
                                                ctypes.POINTER(amr_render_params)]),
     "amr_backward_work_bytes": (ctypes.c_int64, [ctypes.c_int32]),
     "amr_backward_static_bytes": (ctypes.c_int64, []),
+    "amr_probe_read": (ctypes.c_int, [VP, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, VP, VP]),
     "amr_render_backward": (ctypes.c_int, [ctypes.POINTER(amr_scene), ctypes.POINTER(amr_camera), ctypes.c_int32,
                                            ctypes.POINTER(amr_render_params), VP, VP, VP, ctypes.c_int32, VP]),
     "amr_render_backward_static": (ctypes.c_int, [ctypes.POINTER(amr_scene), ctypes.POINTER(amr_camera), ctypes.c_int32,

@@ -10,13 +10,16 @@
 //   sample it as the plain traversal does (the fallback).
 // Every sample of the leaf lies in the leaf's value range, so the segment opacity is at most
 // alpha_max = 1 - exp(-sigma_max L) with sigma_max the largest extinction of the LUT over that
-// range; a lane whose bound already proves the skip needs no network.  The network
+// range; a lane whose bound already proves the skip needs no network (and with bound_only
+// the network is never asked: the same kernel then shows what the network adds).  The network
 // (12 -> 64 -> 64 -> 2, fp16 matrix cores, fp32 accumulation) predicts quantiles of the ratio
 // alpha / alpha_max in [0, 1], so its error scales with the bound instead of being a fixed
 // absolute error at the fp16 resolution; it runs on the 16-lane row tiles that hold
 // undecided lanes.  With d_mlp == NULL and d_seglog set, the
 // kernel renders plainly and logs (features, true segment opacity) for training.
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 
 #include "amr_mlp.h"
 #include "amr_render_common.h"
@@ -37,16 +40,24 @@ struct LearnArgs {
     int32_t lmax;
 };
 
-struct LearnLds {
+struct LearnLds {               // every variant: the LUT and its extinction tables
     float4 lut[256];
     float bmax[16], bmin[16];  // extinction max/min per 16-entry bucket
     float prefix[257];         // prefix sums of extinction
-    _Float16 w1t[64 * 16], w2t[64 * 64], w3t[16 * 64];
-    float b1[64], b2[64], b3[4];
-    _Float16 feat[4][64 * 16];
-    _Float16 hid[4][16 * 64];  // layer 1 output, then layer 2 output in place
-    float out[4][64 * 2];
 };
+
+struct NetLds {                 // the network variant: per-wave inference buffers (the weights,
+                                // 12 KB read by every query, stay in global memory and the caches)
+    _Float16 feat[64 * 16];
+    _Float16 hid[16 * 64];     // layer 1 output, then layer 2 output in place
+    float out[64 * 2];
+};
+
+// The block's network buffers; a variant that never calls this allocates no LDS for them.
+__device__ __forceinline__ NetLds *net_lds() {
+    __shared__ NetLds n;
+    return &n;
+}
 
 // Extinction range [smin, smax] and mean over LUT entries [i0, i1] (bucket-conservative bounds).
 __device__ __forceinline__ void sigma_range(const LearnLds &s, int i0, int i1, float &smin, float &smax, float &smean) {
@@ -61,19 +72,19 @@ __device__ __forceinline__ void sigma_range(const LearnLds &s, int i0, int i1, f
     smean = (s.prefix[i1 + 1] - s.prefix[i0]) / (float)(i1 - i0 + 1);
 }
 
-// Wave-level inference for row tile rt (lanes 16 rt .. 16 rt + 15) of this wave's features.
-__device__ __forceinline__ void infer_tile(LearnLds &s, int wave, int rt) {
+// Wave-level inference for row tile rt (lanes 16 rt .. 16 rt + 15) of the wave's features.
+__device__ __forceinline__ void infer_tile(NetLds &s, const MlpLds *__restrict__ w, int rt) {
     const int lane = threadIdx.x & 63, lr = lane & 15, lq = lane >> 4;
-    const _Float16 *x16 = s.feat[wave] + rt * 16 * 16;
-    _Float16 *hid = s.hid[wave];
+    const _Float16 *x16 = s.feat + rt * 16 * 16;
+    _Float16 *hid = s.hid;
     half4 a = *reinterpret_cast<const half4 *>(x16 + lr * 16 + 4 * lq);
-    #pragma unroll
+    #pragma unroll 1
     for (int ct = 0; ct < 4; ct++) {
-        half4 b = *reinterpret_cast<const half4 *>(s.w1t + (ct * 16 + lr) * 16 + 4 * lq);
+        half4 b = *reinterpret_cast<const half4 *>(w->w1t + (ct * 16 + lr) * 16 + 4 * lq);
         float4v acc = {0.f, 0.f, 0.f, 0.f};
         acc = __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, acc, 0, 0, 0);
         #pragma unroll
-        for (int j = 0; j < 4; j++) hid[(4 * lq + j) * 64 + ct * 16 + lr] = (_Float16)fmaxf(acc[j] + s.b1[ct * 16 + lr], 0.f);
+        for (int j = 0; j < 4; j++) hid[(4 * lq + j) * 64 + ct * 16 + lr] = (_Float16)fmaxf(acc[j] + w->b1[ct * 16 + lr], 0.f);
     }
     __builtin_amdgcn_wave_barrier();
     // layer 2: the A fragments of h1 are the same for every output block, so read them once and
@@ -82,48 +93,48 @@ __device__ __forceinline__ void infer_tile(LearnLds &s, int wave, int rt) {
     #pragma unroll
     for (int ks = 0; ks < 4; ks++) a2[ks] = *reinterpret_cast<const half4 *>(hid + lr * 64 + ks * 16 + 4 * lq);
     __builtin_amdgcn_wave_barrier();
-    #pragma unroll
+    #pragma unroll 1
     for (int ct = 0; ct < 4; ct++) {
         float4v acc = {0.f, 0.f, 0.f, 0.f};
         #pragma unroll
         for (int ks = 0; ks < 4; ks++) {
-            half4 b = *reinterpret_cast<const half4 *>(s.w2t + (ct * 16 + lr) * 64 + ks * 16 + 4 * lq);
+            half4 b = *reinterpret_cast<const half4 *>(w->w2t + (ct * 16 + lr) * 64 + ks * 16 + 4 * lq);
             acc = __builtin_amdgcn_mfma_f32_16x16x16f16(a2[ks], b, acc, 0, 0, 0);
         }
         #pragma unroll
-        for (int j = 0; j < 4; j++) hid[(4 * lq + j) * 64 + ct * 16 + lr] = (_Float16)fmaxf(acc[j] + s.b2[ct * 16 + lr], 0.f);
+        for (int j = 0; j < 4; j++) hid[(4 * lq + j) * 64 + ct * 16 + lr] = (_Float16)fmaxf(acc[j] + w->b2[ct * 16 + lr], 0.f);
     }
     __builtin_amdgcn_wave_barrier();
     float4v acc = {0.f, 0.f, 0.f, 0.f};
     #pragma unroll
     for (int ks = 0; ks < 4; ks++) {
         half4 a3 = *reinterpret_cast<const half4 *>(hid + lr * 64 + ks * 16 + 4 * lq);
-        half4 b = *reinterpret_cast<const half4 *>(s.w3t + lr * 64 + ks * 16 + 4 * lq);
+        half4 b = *reinterpret_cast<const half4 *>(w->w3t + lr * 64 + ks * 16 + 4 * lq);
         acc = __builtin_amdgcn_mfma_f32_16x16x16f16(a3, b, acc, 0, 0, 0);
     }
     if (lr < kOut) {
         #pragma unroll
         for (int j = 0; j < 4; j++)
-            s.out[wave][(rt * 16 + 4 * lq + j) * 2 + lr] = 1.f / (1.f + __expf(-(acc[j] + s.b3[lr])));
+            s.out[(rt * 16 + 4 * lq + j) * 2 + lr] = 1.f / (1.f + __expf(-(acc[j] + w->b3[lr])));
     }
     __builtin_amdgcn_wave_barrier();
 }
 
 enum { kModePlain = 0, kModeSkip = 1, kModeCoarse = 2 };
-constexpr int kNetMinSamples = 8;
+// Segments shorter than this are never worth a query: a query round costs the wave about as
+// much as 30 unlit samples (measured on the deep-range view at 1024^2: with a threshold of 8
+// the network removed 29% more samples than the bound alone but the frame took 10% longer).
+constexpr int kNetMinSamples = 32;
 
-// NET: the network decides (G.mlp set); LOG: segments are logged for training (G.seglog set).
-template <bool LIT, bool NET, bool LOG>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(LIT ? 2 : 4))) void render_learned(RenderArgs A, LearnArgs G) {
+// DEC: how data segments are decided: 0 all sampled plainly (logging), 1 skipped by the
+// analytic bound alone, 2 the bound and then the network (G.mlp set).  LOG: segments are logged
+// for training (G.seglog set).  LAY: the brick layout (-1: read at run time).
+template <bool LIT, int DEC, bool LOG, int LAY>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(LIT ? 2 : (LOG ? 4 : 5)))) void render_learned(RenderArgs A, LearnArgs G) {
     __shared__ LearnLds s;
-    s.lut[threadIdx.x] = A.lut[threadIdx.x];
-    if (NET) {
-        const MlpLds *m = G.mlp;
-        for (int i = threadIdx.x; i < 64 * 16; i += blockDim.x) { s.w1t[i] = m->w1t[i]; s.w3t[i] = m->w3t[i]; }
-        for (int i = threadIdx.x; i < 64 * 64; i += blockDim.x) s.w2t[i] = m->w2t[i];
-        if (threadIdx.x < 64) { s.b1[threadIdx.x] = m->b1[threadIdx.x]; s.b2[threadIdx.x] = m->b2[threadIdx.x]; }
-        if (threadIdx.x < 4) s.b3[threadIdx.x] = m->b3[threadIdx.x];
-    }
+    NetLds *sn = nullptr;
+    for (int i = threadIdx.x; i < 256; i += 64) s.lut[i] = A.lut[i];
+    if constexpr (DEC == 2) sn = net_lds();
     __syncthreads();
     if (threadIdx.x < 16) {
         float mx = -INFINITY, mn = INFINITY;
@@ -135,7 +146,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(LIT ? 2 : 4
         s.bmax[threadIdx.x] = mx;
         s.bmin[threadIdx.x] = mn;
     }
-    if (threadIdx.x == 64) {
+    if (threadIdx.x == 32) {
         float acc = 0.f;
         s.prefix[0] = 0.f;
         for (int i = 0; i < 256; i++) { acc += s.lut[i].w; s.prefix[i + 1] = acc; }
@@ -143,21 +154,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(LIT ? 2 : 4
     __syncthreads();
     const float4 *s_lut = s.lut;
 
-    // 16x16-pixel tiles (four waves) grouped in 2x2 super-tiles of 32x32 pixels numbered along
-    // a Morton curve and dealt round-robin to the 8 XCDs, as in the plain forward kernel.
+    // One wave per block and one 8x8 pixel tile per wave, tiles grouped in 4x4 super-tiles along
+    // a Morton curve and dealt round-robin to the 8 XCDs, as in the plain forward kernel (a
+    // wave's slot frees as soon as its rays end).
     const int xcd = (int)(blockIdx.x % 8), li = (int)(blockIdx.x / 8);
-    const int sidx = (li >> 2) * 8 + xcd;
+    const int sidx = (li >> 4) * 8 + xcd;
     int sx = 0, sy = 0;
     #pragma unroll
     for (int bit = 0; bit < 12; bit++) {
         sx |= ((sidx >> (2 * bit)) & 1) << bit;
         sy |= ((sidx >> (2 * bit + 1)) & 1) << bit;
     }
-    const int tx = sx * 2 + ((li & 3) >> 1), ty = sy * 2 + (li & 1);
-    if (tx >= A.tiles_x || ty >= A.tiles_y) return;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int pi = tx * 16 + (wave & 1) * 8 + (lane & 7);
-    const int pj = ty * 16 + (wave >> 1) * 8 + (lane >> 3);
+    const int col = sx * 4 + ((li & 15) >> 2), row = sy * 4 + (li & 3);
+    if (col >= A.t8x || row >= A.t8y) return;
+    const int lane = threadIdx.x & 63;
+    const int pi = col * 8 + (lane & 7);
+    const int pj = row * 8 + (lane >> 3);
     const bool valid = pi < A.width && pj < A.height;
     const int64_t ray = (int64_t)pj * A.width + pi;
 
@@ -185,6 +197,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(LIT ? 2 : 4
         float a_bound_lo = 0.f;           // and its analytic lower bound
         float a_use = 1.f;                // upper bound charged to the skip budget
         float len = 0.f, umin = 0.f, umax = 0.f, smin = 0.f, smax = 0.f, smean = 0.f;
+        int nsm = 0;                      // the segment's plain sample count
         if (active) {
             leaf = descend(A, R, tcur, tb, start);
             if (leaf < 0) {
@@ -194,7 +207,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(LIT ? 2 : 4
                 const DLeaf &L = A.leaves[leaf];
                 data = L.patch >= 0;
                 if (data) {
-                    setup_segment<LIT>(A, R, L, leaf, tcur, tb, S);
+                    // the full sampling state is set up after the decision, for segments sampled
+                    nsm = segment_samples(A, A.patches[L.patch], tcur, tb);
                     len = (float)(tb - tcur);
                     umin = __saturatef((L.vmin - A.v_lo) * A.inv_range);
                     umax = __saturatef((L.vmax - A.v_lo) * A.inv_range);
@@ -218,7 +232,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(LIT ? 2 : 4
             feat[4] = a_bound_hi;
             feat[5] = 1.f - __expf(-smean * len);
             feat[6] = a_bound_lo;
-            feat[7] = (float)min(S.n, 256) * (1.f / 256.f);
+            feat[7] = (float)min(nsm, 256) * (1.f / 256.f);
             feat[8] = (float)fabs(R.d[0]);
             feat[9] = (float)fabs(R.d[1]);
             feat[10] = (float)fabs(R.d[2]);
@@ -226,13 +240,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(LIT ? 2 : 4
         };
         // decide: skip by the analytic bound, else ask the network (wave-level MFMA)
         int mode = kModePlain;
-        if (NET) {
+        if constexpr (DEC == 1) {
+            if (data && budget + T * a_bound_hi < G.tau_e) {
+                mode = kModeSkip;
+                budget += T * a_bound_hi;
+            }
+        }
+        if constexpr (DEC == 2) {
+            NetLds &sw = *sn;
             const bool bound_skip = data && budget + T * a_bound_hi < G.tau_e;
             // the network is asked only where its answer can change the decision and skipping
             // pays for it: segments of at least kNetMinSamples samples whose bound did not
             // already decide and whose analytic lower bound still fits the budget (or whose
             // upper bound reaches the coarse threshold)
-            const bool undecided = data && !bound_skip && S.n >= kNetMinSamples &&
+            const bool undecided = data && !bound_skip && nsm >= kNetMinSamples &&
                                    (budget + T * a_bound_lo < G.tau_e || a_bound_hi > 1.f - G.tau_s);
             if (undecided) c_net++;
             if (bound_skip) mode = kModeSkip;
@@ -243,14 +264,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(LIT ? 2 : 4
                 for (int j = 0; j < kIn; j++) feat[j] = 0.f;
                 if (undecided) features(feat);
                 #pragma unroll
-                for (int j = 0; j < 16; j++) s.feat[wave][lane * 16 + j] = (_Float16)(j < kIn ? feat[j < kIn ? j : 0] : 0.f);
+                for (int j = 0; j < 16; j++) sw.feat[lane * 16 + j] = (_Float16)(j < kIn ? feat[j < kIn ? j : 0] : 0.f);
                 __builtin_amdgcn_wave_barrier();
                 #pragma unroll 1
                 for (int rt = 0; rt < 4; rt++)
-                    if ((need >> (16 * rt)) & 0xffffull) infer_tile(s, wave, rt);
+                    if ((need >> (16 * rt)) & 0xffffull) infer_tile(sw, G.mlp, rt);
                 if (undecided) {
-                    a_use = __saturatef(s.out[wave][lane * 2 + 1]) * a_bound_hi;
-                    const float a_lo = __saturatef(s.out[wave][lane * 2]) * a_bound_hi;
+                    a_use = __saturatef(sw.out[lane * 2 + 1]) * a_bound_hi;
+                    const float a_lo = __saturatef(sw.out[lane * 2]) * a_bound_hi;
                     if (budget + T * a_use < G.tau_e) mode = kModeSkip;
                     else if (a_lo > 1.f - G.tau_s) mode = kModeCoarse;
                 }
@@ -261,6 +282,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(LIT ? 2 : 4
         const float t_in = T;
         bool full = true;
         if (data && mode != kModeSkip) {
+            setup_segment<LIT, LAY>(A, R, A.leaves[leaf], leaf, tcur, tb, S, nsm);
             if (mode == kModeCoarse) {
                 // one step per cell of the leaf's level, then the ray stops after this segment
 #pragma clang fp contract(off)
@@ -276,7 +298,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(LIT ? 2 : 4
             }
             for (int k = 0; k < S.n; k++) {
                 SampleVals v;
-                eval_sample<LIT, false>(A, s_lut, R, S, k, v, cnt);
+                eval_sample<LIT, false, false, LAY>(A, s_lut, R, S, k, v, cnt);
                 float wgt = T * v.alpha * v.shade;
                 C0 += wgt * v.r;
                 C1 += wgt * v.g;
@@ -349,16 +371,34 @@ int launch_learned(const RenderArgs &A, const amr_render_params *P, int lmax, vo
     G.lmax = lmax;
     hipStream_t s = (hipStream_t)stream;
     if (G.seglog && first_camera) hipLaunchKernelGGL(seglog_reset, dim3(1), dim3(64), 0, s, G.seglog);
-    const int grid = 8 * ((A.sgrid * A.sgrid + 7) / 8) * 4;
-    const bool net = G.mlp != nullptr, log = G.seglog != nullptr;
+    const int grid = 8 * ((A.sgrid * A.sgrid + 7) / 8) * 16;
+    const bool log = G.seglog != nullptr;
+    const int dec = P->bound_only ? 1 : (G.mlp ? 2 : 0);
+    const dim3 g(grid), b(64);
+    // the timed forms (deciding, not logging) are compiled for the brick layout
+    auto timed = [&](auto lit, auto decc) {
+        constexpr bool L = decltype(lit)::value;
+        constexpr int D = decltype(decc)::value;
+        if (A.layout == 0) hipLaunchKernelGGL((render_learned<L, D, false, 0>), g, b, 0, s, A, G);
+        else if (A.layout == 1) hipLaunchKernelGGL((render_learned<L, D, false, 1>), g, b, 0, s, A, G);
+        else hipLaunchKernelGGL((render_learned<L, D, false, 2>), g, b, 0, s, A, G);
+    };
+    using T_ = std::true_type;
+    using F_ = std::false_type;
+    using D1 = std::integral_constant<int, 1>;
+    using D2 = std::integral_constant<int, 2>;
     if (A.lighting) {
-        if (net && log) hipLaunchKernelGGL((render_learned<true, true, true>), dim3(grid), dim3(256), 0, s, A, G);
-        else if (net) hipLaunchKernelGGL((render_learned<true, true, false>), dim3(grid), dim3(256), 0, s, A, G);
-        else hipLaunchKernelGGL((render_learned<true, false, true>), dim3(grid), dim3(256), 0, s, A, G);
+        if (dec == 2 && log) hipLaunchKernelGGL((render_learned<true, 2, true, -1>), g, b, 0, s, A, G);
+        else if (dec == 1 && log) hipLaunchKernelGGL((render_learned<true, 1, true, -1>), g, b, 0, s, A, G);
+        else if (dec == 2) timed(T_{}, D2{});
+        else if (dec == 1) timed(T_{}, D1{});
+        else hipLaunchKernelGGL((render_learned<true, 0, true, -1>), g, b, 0, s, A, G);
     } else {
-        if (net && log) hipLaunchKernelGGL((render_learned<false, true, true>), dim3(grid), dim3(256), 0, s, A, G);
-        else if (net) hipLaunchKernelGGL((render_learned<false, true, false>), dim3(grid), dim3(256), 0, s, A, G);
-        else hipLaunchKernelGGL((render_learned<false, false, true>), dim3(grid), dim3(256), 0, s, A, G);
+        if (dec == 2 && log) hipLaunchKernelGGL((render_learned<false, 2, true, -1>), g, b, 0, s, A, G);
+        else if (dec == 1 && log) hipLaunchKernelGGL((render_learned<false, 1, true, -1>), g, b, 0, s, A, G);
+        else if (dec == 2) timed(F_{}, D2{});
+        else if (dec == 1) timed(F_{}, D1{});
+        else hipLaunchKernelGGL((render_learned<false, 0, true, -1>), g, b, 0, s, A, G);
     }
     return check_hip(hipGetLastError(), "render_learned launch");
 }

@@ -548,17 +548,22 @@ int amr_render(const amr_scene *S, const amr_camera *cams, int32_t ncams, const 
             return AMR_ECAPACITY;
         }
     }
-    if (P->lighting == 2 && (P->persistent || P->d_mlp || P->d_seglog || P->d_ckpt || P->interp != 0 || P->lod > 0.f)) {
+    const bool learned = P->d_mlp || P->d_seglog || P->bound_only;
+    if (P->bound_only && P->d_mlp) {
+        set_error("bound_only skips by the analytic bound alone: d_mlp must be NULL");
+        return AMR_EINVAL;
+    }
+    if (P->lighting == 2 && (P->persistent || learned || P->d_ckpt || P->interp != 0 || P->lod > 0.f)) {
         set_error("point-light lighting (lighting = 2) is rendered by its own forward kernel only, with trilinear "
                   "sampling and no level of detail (not persistent, learned, logging or checkpointed)");
         return AMR_EINVAL;
     }
-    if (P->interp == 1 && (P->persistent || P->d_mlp || P->d_seglog || P->d_ckpt)) {
+    if (P->interp == 1 && (P->persistent || learned || P->d_ckpt)) {
         set_error("nearest-cell sampling (interp = 1) is rendered by the plain forward kernel only "
                   "(not persistent, learned, logging or checkpointed)");
         return AMR_EINVAL;
     }
-    if (P->persistent && (P->d_mlp || P->d_seglog)) {
+    if (P->persistent && learned) {
         set_error("learned proposals and segment logging run in their own kernel (not persistent)");
         return AMR_EINVAL;
     }
@@ -581,7 +586,7 @@ int amr_render(const amr_scene *S, const amr_camera *cams, int32_t ncams, const 
         A.stats = d_stats;
         A.touch = P->d_touch;
         A.ckpt_ray0 = pix_off;
-        if (P->d_mlp || P->d_seglog) {
+        if (learned) {
             if (P->d_trace || P->d_ckpt || P->d_touch) {
                 set_error("learned proposals / segment logging do not record traces, checkpoints or touch maps");
                 return AMR_EINVAL;

@@ -475,16 +475,26 @@ struct Segment {
     int leaf, patch, n;
 };
 
+// Sample count of a segment [ta, tb] of a leaf of patch P: n = max(1, ceil((tb - ta) / step -
+// 2^-20)) with step = step_frac h^l (Section 5.3; the 2^-20 keeps ratios within rounding of an
+// integer from gaining a sample).
+__device__ __forceinline__ int segment_samples(const RenderArgs &A, const DPatch &P, double ta, double tb) {
+#pragma clang fp contract(off)
+    const double step = (double)A.step_frac * (A.uniform_step ? A.step_fine : P.step);
+    const double ratio = (tb - ta) / step;
+    const double nn = ceil(ratio - 0x1p-20);
+    return nn < 1.0 ? 1 : (int)nn;
+}
+
+// The sampling state of a segment [ta, tb] of leaf L; n: its sample count when known
+// (segment_samples), else 0.
 template <bool LIT, int LAY = -1>
 __device__ __forceinline__ void setup_segment(const RenderArgs &A, const Ray &R, const DLeaf &L, int leaf, double ta,
-                                              double tb, Segment &S) {
+                                              double tb, Segment &S, int n = 0) {
     const DPatch &P = A.patches[L.patch];
+    S.n = n > 0 ? n : segment_samples(A, P, ta, tb);
     {
 #pragma clang fp contract(off)
-        double step = (double)A.step_frac * (A.uniform_step ? A.step_fine : P.step);
-        double ratio = (tb - ta) / step;
-        double nn = ceil(ratio - 0x1p-20);
-        S.n = nn < 1.0 ? 1 : (int)nn;
         S.delta = (tb - ta) / (double)S.n;
     }
     S.ta = ta;

@@ -211,31 +211,30 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void sh
     }
 }
 
-// Pass 3: one shadow ray per lane, from the recorded sample position to the light; the grid
-// strides over the jobs recorded (the frame's job count, capped by the arrays), consecutive
-// lanes taking consecutive jobs.
+// Pass 3: one shadow ray per lane, from the recorded sample position to the light.  The grid
+// covers the job arrays; lanes beyond the frame's job count (read on the device) return.
 template <int LAY>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void shadow_rays(RenderArgs A, ShadowWork W) {
 #pragma clang fp contract(off)
+    const int64_t njobs = min(*W.total, W.cap);
+    if ((int64_t)blockIdx.x * 64 >= njobs) return;
     __shared__ float4 s_lut[256];
     for (int i = threadIdx.x; i < 256; i += 64) s_lut[i] = A.lut[i];
     __syncthreads();
-    const int64_t njobs = min(*W.total, W.cap);
-    const int64_t npix = (int64_t)A.width * A.height;
-    for (int64_t j = (int64_t)blockIdx.x * 64 + threadIdx.x; j < njobs; j += (int64_t)gridDim.x * 64) {
-        const int r = W.ray[j];
-        float tl = 1.f;
-        if (r >= 0 && r < npix) {              // every job below the count was recorded
-            Ray R;
-            setup_ray(A, r % A.width, r / A.width, R);   // a ray with samples, so it meets the clip box
-            const double tk = W.tk[j];
-            double x[3];
-            #pragma unroll
-            for (int b = 0; b < 3; b++) x[b] = R.o[b] + tk * R.d[b];
-            tl = light_transmittance<LAY>(A, s_lut, x);
-        }
-        W.tl[j] = tl;
+    const int64_t j = (int64_t)blockIdx.x * 64 + threadIdx.x;
+    if (j >= njobs) return;
+    const int r = W.ray[j];
+    float tl = 1.f;
+    if (r >= 0 && (int64_t)r < (int64_t)A.width * A.height) {   // every job below the count was recorded
+        Ray R;
+        setup_ray(A, r % A.width, r / A.width, R);   // a ray with samples, so it meets the clip box
+        const double tk = W.tk[j];
+        double x[3];
+        #pragma unroll
+        for (int b = 0; b < 3; b++) x[b] = R.o[b] + tk * R.d[b];
+        tl = light_transmittance<LAY>(A, s_lut, x);
     }
+    W.tl[j] = tl;
 }
 
 // Block-wise exclusive scan of the per-ray counts (1024 per block), then of the block sums.
@@ -309,6 +308,10 @@ int launch_shadow(const RenderArgs &A, bool rec, void *stream, void *work, int64
                   "params.work_bytes, params.light_jobs)");
         return work ? AMR_ECAPACITY : AMR_EINVAL;
     }
+    if ((jobs + 63) / 64 > 0x7fffffffLL) {
+        set_error("light_jobs %lld exceeds one launch of the secondary-ray pass", (long long)jobs);
+        return AMR_EINVAL;
+    }
     RenderArgs Ap = A;                      // counting and recording passes record nothing else
     Ap.trace = nullptr;
     Ap.trace_n = nullptr;
@@ -342,7 +345,7 @@ int launch_shadow(const RenderArgs &A, bool rec, void *stream, void *work, int64
     hipLaunchKernelGGL(add_block_offsets, dim3(nb), dim3(1024), 0, s, W.off, npix, bsum);
     if (jobs > 0) {
         march(kPassRecord, Ap);
-        const int64_t nj = std::min<int64_t>((jobs + 63) / 64, 256 * 32);
+        const int64_t nj = (jobs + 63) / 64;
         if (A.layout == 0) hipLaunchKernelGGL((shadow_rays<0>), dim3(nj), dim3(64), 0, s, Ap, W);
         else if (A.layout == 1) hipLaunchKernelGGL((shadow_rays<1>), dim3(nj), dim3(64), 0, s, Ap, W);
         else hipLaunchKernelGGL((shadow_rays<2>), dim3(nj), dim3(64), 0, s, Ap, W);

@@ -86,6 +86,32 @@ def render_learned(scene, cams, lut, params, packed: torch.Tensor, tau_e: float,
     return render(scene, cams, lut, dict(params, tau_e=tau_e, tau_s=tau_s), d_mlp=packed, **kw)
 
 
+def render_bound_only(scene, cams, lut, params, tau_e: float, **kw):
+    """The same kernel and skip rule with the network never consulted: a data segment is skipped
+    when the ray's charged opacity plus T * alpha_max (the analytic bound) stays below tau_e."""
+    return render(scene, cams, lut, dict(params, tau_e=tau_e, tau_s=0.0, bound_only=1), **kw)
+
+
+def calibrate_bound_only(scene, views, lut, params, plain_images, max_err: float = 1e-3, safety: float = 0.5,
+                         tau_e_grid=(0.0, 5e-5, 1e-4, 2e-4, 3e-4, 5e-4, 1e-3, 2e-3)):
+    """Largest tau_e of the bound-only form whose worst RGBA error against the plain renders of
+    the held-out `views` stays within safety * max_err (the same rule as `calibrate`).  Returns
+    (tau_e, table)."""
+    from . import stats_dict
+    table = []
+    best = (0.0, None)
+    for te in tau_e_grid:
+        err, samples = 0.0, 0
+        for cam, ref in zip(views, plain_images):
+            out = render_bound_only(scene, cam, lut, params, te, stats=True)
+            err = max(err, float((out["rgba"] - ref).abs().max().item()))
+            samples += stats_dict(out)["samples"]
+        table.append(dict(tau_e=te, max_err=err, samples=samples))
+        if err <= safety * max_err and (best[1] is None or samples < best[1]):
+            best = (te, samples)
+    return best[0], table
+
+
 def calibrate(scene, views, lut, params, packed, plain_images, max_err: float = 1e-3, safety: float = 0.5,
               tau_e_grid=(0.0, 5e-5, 1e-4, 2e-4, 3e-4, 5e-4, 1e-3), tau_s_grid=(0.0, 1e-4, 1e-3, 1e-2)):
     """Largest thresholds whose worst RGBA error against the plain renders of the held-out

@@ -1,7 +1,9 @@
 """Learned segment proposals on the deep-range hierarchy: the logger's analytic bounds bracket
 the true segment opacities, zero thresholds reproduce the plain render bit for bit, training on
 the GPU lowers the pinball loss, calibrated thresholds keep held-out views within 1e-3 of the
-plain render (which the FP64 oracle checks), and the learned form takes fewer samples."""
+plain render (which the FP64 oracle checks), the learned form takes fewer samples, and at the
+same threshold it takes fewer samples than the same kernel with the network never asked
+(bound_only), both within 1e-3 of the plain render."""
 import math
 
 import numpy as np
@@ -59,6 +61,37 @@ def test_zero_thresholds_bit_identical(gpu, deep):
         assert torch.equal(plain, lr)
 
 
+def test_bound_only_zero_threshold_and_bound(gpu, deep):
+    """bound_only with tau_e = 0 skips nothing and reproduces the plain render bit for bit; with
+    tau_e > 0 every ray's skipped opacity is charged at its analytic bound, so the image stays
+    within about tau_e of the plain render; it is rejected with a network or in persistent mode."""
+    import torch
+    from paper_1212_3333_amd import learned
+    amr = gpu
+    h, lut, cams, prm = deep[:4]
+    scene = deep[5]
+    lut_t = torch.from_numpy(lut).cuda()
+    for cam in cams:
+        plain = amr.render(scene, cam, lut_t, prm, stats=True)
+        b0 = learned.render_bound_only(scene, cam, lut_t, prm, 0.0, stats=True)
+        b1 = learned.render_bound_only(scene, cam, lut_t, prm, 5e-4, stats=True)
+        torch.cuda.synchronize()
+        assert torch.equal(plain["rgba"], b0["rgba"])
+        assert amr.stats_dict(b0)["skipped_segments"] == 0 and amr.stats_dict(b0)["net_segments"] == 0
+        err = float((b1["rgba"] - plain["rgba"]).abs().max().item())
+        s1 = amr.stats_dict(b1)
+        print("bound_only tau 5e-4: max err %.3g, samples %d of %d, skipped %d" % (
+            err, s1["samples"], amr.stats_dict(plain)["samples"], s1["skipped_segments"]))
+        assert err <= 1e-3 and s1["net_segments"] == 0
+    W = learned.init_weights(1, "cuda")
+    with pytest.raises(amr.AMRError, match="bound_only"):
+        amr.render(scene, cams[0], lut_t, dict(prm, bound_only=1), d_mlp=amr.mlp_pack(W))
+    two = list(cams[:2])
+    with pytest.raises(amr.AMRError, match="persistent"):
+        amr.render(scene, two, lut_t, dict(prm, bound_only=1, persistent=1), d_cams=amr.camera_table(two),
+                   d_queue=amr.queue_buffer(2))
+
+
 def test_train_calibrate_gain(gpu, deep):
     import torch
     from paper_1212_3333_amd import learned
@@ -103,3 +136,17 @@ def test_train_calibrate_gain(gpu, deep):
     print("eval: worst err %.3g, sample savings %s" % (worst, np.round(saved, 3)))
     assert worst <= 1e-3
     assert np.mean(saved) > 0.05
+    # what the network adds: the same kernel and threshold with the network never asked
+    nb, nn, worst_b = 0, 0, 0.0
+    for cam in evalv:
+        p = amr.render(scene, cam, lut_t, prm)["rgba"]
+        b = learned.render_bound_only(scene, cam, lut_t, prm, te, stats=True)
+        q = learned.render_learned(scene, cam, lut_t, prm, net.packed, te, ts, stats=True)
+        torch.cuda.synchronize()
+        worst_b = max(worst_b, float((b["rgba"] - p).abs().max().item()))
+        nb += amr.stats_dict(b)["samples"]
+        nn += amr.stats_dict(q)["samples"]
+    print("tau_e %g: bound only %d samples (worst err %.3g), bound + network %d samples (%.1f%% fewer)" % (
+        te, nb, worst_b, nn, 100.0 * (1 - nn / max(nb, 1))))
+    assert worst_b <= 1e-3
+    assert te > 0 and nn < nb
