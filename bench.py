@@ -26,10 +26,20 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# the sources of the timed kernel; committed counter readings are used only while these match
+FP32_PEAK_TFLOPS = 157.3
+# VALU issue: each of a CU's 4 SIMDs issues one wave64 vector instruction every 4 cycles, so the
+# chip issues 256 CUs x 2.4 GHz wave instructions per second
+VALU_ISSUE_PEAK = 256 * 2.4e9
+# algorithmic fp32 operations per sample (counted in the design notes): position, trilinear,
+# value normalisation, LUT lerp, opacity, compositing; lit adds the six taps' trilinears on the
+# centre's weights, the central differences and the shading
+FLOPS_PER_SAMPLE = {False: 59, True: 206}
+# gather request bytes per sample: 8 cells, plus 6 taps of 8 cells each when lit
+GATHER_BYTES_PER_SAMPLE = {False: 32, True: 32 + 192}
+# the sources of the timed kernels; committed counter readings are used only while these match
 KERNEL_SOURCES = ("paper_1212_3333_amd/csrc/amr_render.hip", "paper_1212_3333_amd/csrc/amr_render_common.h",
                   "paper_1212_3333_amd/csrc/amr_internal.h")
-TRAFFIC_FILE = "profiles/render_fwd_lit_cosmology_1024_traffic.txt"
+COUNTERS_FILE = "profiles/render_fwd_cosmology_1024_counters.txt"
 
 
 def kernel_source_hash() -> str:
@@ -41,11 +51,12 @@ def kernel_source_hash() -> str:
     return hsh.hexdigest()
 
 
-def committed_traffic():
-    """HBM bytes per launch of the lit kernel from the committed rocprofv3 counter summary
-    (FETCH_SIZE and WRITE_SIZE, each scaled by a copy kernel's reading), or None when the
+def committed_counters():
+    """Per-launch counter readings of the timed kernels from the committed rocprofv3 summary:
+    HBM bytes (FETCH_SIZE and WRITE_SIZE, each scaled by a copy kernel's reading), the raw
+    FETCH_SIZE bytes, and VALU instructions, for the lit and the unlit kernel; None when the
     summary is missing or the kernel sources have changed since the counters were taken."""
-    path = os.path.join(ROOT, TRAFFIC_FILE)
+    path = os.path.join(ROOT, COUNTERS_FILE)
     if not os.path.exists(path):
         return None
     kv = {}
@@ -57,9 +68,25 @@ def committed_traffic():
     if kv.get("kernel_source_sha256") != kernel_source_hash():
         return None
     try:
-        return int(float(kv["traffic_bytes_per_launch"]))
+        return {lit: dict(traffic=int(float(kv[p + "traffic_bytes_per_launch"])),
+                          fetch_raw=int(float(kv[p + "fetch_kib_per_dispatch"]) * 1024),
+                          valu_insts=float(kv[p + "valu_insts_per_dispatch"]))
+                for lit, p in ((True, "lit_"), (False, "unlit_"))}
     except (KeyError, ValueError):
         return None
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 METRIC = "samples/s + Mrays/s at 1024², plain vs learned-skip at ≤1e-3 RGBA error"
 # The paper's own measurements (its results table and Section 6), on other hardware and data:
 # context for the numbers above, not a baseline of the same workload.
@@ -121,6 +148,7 @@ def cpu_baseline(h, cam, lut, prm, target_s=15.0, seed=7):
     dt = time.time() - t
     samples = int(r["nsamp"].sum())
     return dict(value=samples / dt, unit="samples/s", cores=oracle.num_threads(), kind="oracle",
+                cpu_model=cpu_model(), nproc=os.cpu_count(),
                 mrays_per_s=n / dt / 1e6,
                 sample="%d random pixels of the same %dx%d view (seed %d), %.1f s of oracle work after a "
                        "warm-up pass that fills the oracle's lazily built ghost layers; oracle tree build %.1f s"
@@ -488,37 +516,77 @@ def main():
     value = samples / (ms * 1e-3)
     mrays = W * H / (ms * 1e-3) / 1e6
 
-    # compulsory bytes: distinct pool cells the frame's stencils read + tree/leaf/header tables
-    # + the RGBA output
-    roof = None
+    # the unlit kernel: timed, and its own roofline below
+    unlit_prm = dict(prm, lighting=False)
+    unlit_ms = unlit_samples = None
+    if prm["lighting"]:
+        unlit_ms = time_frames(amr, scene, cam, lut_t, unlit_prm, max(3, args.steps // 2), 2, out)
+        r = amr.render(scene, cam, lut_t, unlit_prm, stats=True)
+        torch.cuda.synchronize()
+        unlit_samples = amr.stats_dict(r)["samples"]
+        del r
+
+    # compulsory bytes of each kernel: distinct pool cells its stencils read, the node, leaf,
+    # patch-header and face records it reads, and the RGBA output; then the floors each roof
+    # sets on the frame time, from the live timing, the live L2 probe and the committed counters
+    roof = unlit_roof = None
     if not args.no_touch:
+        l2_gbs = amr.read_bandwidth(16 << 20, 250, device=dev)
+        log("L2 read bandwidth (16 MB probe): %.0f GB/s" % l2_gbs)
+        counters = committed_counters()
         # counted on a linear-layout copy of the pool, where every padded cell is one float: the
         # halo-row layout stores edge cells twice, and which copy a stencil reads is a layout detail
         tscene = scene if args.brick_layout == 0 else amr.pack(tree, h, device=dev, brick_layout=0)
-        nwords = tscene.scene.pool_bytes // 4 // 32 + 1
-        touch = torch.zeros(nwords, dtype=torch.int32, device=dev)
-        amr.render(tscene, cam, lut_t, prm, d_touch=touch)
-        torch.cuda.synchronize()
+
+        def touched(p):
+            touch = torch.zeros(tscene.scene.pool_bytes // 4 // 32 + 1, dtype=torch.int32, device=dev)
+            tmeta = torch.zeros(tscene.scene.meta_bytes // 16 // 32 + 1, dtype=torch.int32, device=dev)
+            amr.render(tscene, cam, lut_t, p, d_touch=touch, d_touch_meta=tmeta)
+            torch.cuda.synchronize()
+            cells = popcount_bytes(touch.view(torch.uint8))
+            lines = int((touch != 0).sum().item())      # 128-byte lines (32 cells) holding a read cell
+            meta = 16 * popcount_bytes(tmeta.view(torch.uint8))
+            return cells, lines, meta
+
+        def roofline_of(lit, t_ms, nsamp, cells, lines, meta):
+            b_alg = 4 * cells + meta + 16 * W * H
+            achieved = b_alg / (t_ms * 1e-3) / 1e9
+            gather = nsamp * GATHER_BYTES_PER_SAMPLE[lit]
+            flops = nsamp * FLOPS_PER_SAMPLE[lit]
+            c = counters[lit] if counters else None
+            floors = {"hbm": b_alg / (HBM_PEAK_GBS * 1e9) * 1e3,
+                      "l2_gather": gather / (l2_gbs * 1e9) * 1e3,
+                      "fp32_alu": flops / (FP32_PEAK_TFLOPS * 1e12) * 1e3}
+            if c:
+                floors["valu_issue"] = c["valu_insts"] / VALU_ISSUE_PEAK * 1e3
+            binding = max(floors, key=floors.get)
+            return dict(bound="hbm", achieved=round(achieved, 2), peak=HBM_PEAK_GBS, unit="GB/s",
+                        frac=round(achieved / HBM_PEAK_GBS, 5), traffic=c["traffic"] if c else None,
+                        kernel="render_fwd<%s, REC=false, NEAR=false, LAY=%d>" % ("LIT" if lit else "UNLIT",
+                                                                                  args.brick_layout),
+                        ms=round(t_ms, 4), algorithmic_bytes=int(b_alg), distinct_cells=int(cells),
+                        metadata_bytes_read=int(meta), distinct_line_bytes=128 * lines,
+                        gather_request_bytes=int(gather), algorithmic_flops=int(flops),
+                        counter_gbs=round(c["traffic"] / (t_ms * 1e-3) / 1e9, 1) if c else None,
+                        fetch_bytes_raw=c["fetch_raw"] if c else None,
+                        line_efficiency=round(b_alg / c["traffic"], 4) if c else None,
+                        valu_insts=c["valu_insts"] if c else None,
+                        l2_read_gbs=round(l2_gbs, 1),
+                        floors_ms={k: round(v, 4) for k, v in floors.items()},
+                        binding_roof=binding, frac_of_binding_roof=round(floors[binding] / t_ms, 4))
+
+        cells, lines, meta = touched(prm)
+        roof = roofline_of(bool(prm["lighting"]), ms, samples, cells, lines, meta)
+        log("compulsory bytes %.1f MB (%d distinct cells, %d metadata bytes read); floors %s" % (
+            roof["algorithmic_bytes"] / 1e6, cells, meta, roof["floors_ms"]))
+        if prm["lighting"]:
+            cu, lu, mu = touched(unlit_prm)
+            unlit_roof = roofline_of(False, unlit_ms, unlit_samples, cu, lu, mu)
+            log("unlit: compulsory bytes %.1f MB; floors %s" % (unlit_roof["algorithmic_bytes"] / 1e6,
+                                                              unlit_roof["floors_ms"]))
         if tscene is not scene:
             del tscene
             torch.cuda.empty_cache()
-        cells = popcount_bytes(touch.view(torch.uint8))
-        lines = int((touch != 0).sum().item())      # 128-byte lines (32 cells) holding a read cell
-        b_alg = 4 * cells + scene.scene.meta_bytes + 16 * W * H
-        achieved = b_alg / (ms * 1e-3) / 1e9
-        traffic = committed_traffic() if prm["lighting"] else None
-        roof = dict(bound="hbm", achieved=round(achieved, 2), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 5), traffic=traffic,
-                    kernel="render_fwd", algorithmic_bytes=int(b_alg), distinct_cells=int(cells),
-                    distinct_line_bytes=128 * lines,
-                    gather_request_bytes=int(samples * (32 + (192 if prm["lighting"] else 0))))
-        log("compulsory bytes %.1f MB (%d distinct cells)" % (b_alg / 1e6, cells))
-        del touch
-
-    # the unlit kernel, as a second line of context
-    unlit_ms = None
-    if prm["lighting"]:
-        unlit_ms = time_frames(amr, scene, cam, lut_t, dict(prm, lighting=False), max(3, args.steps // 2), 2, out)
 
     pool_bytes, meta_bytes = int(scene.scene.pool_bytes), int(scene.scene.meta_bytes)
     batched_res = adjoint_res = None
@@ -572,6 +640,7 @@ def main():
         "unlit_ms_per_step": round(unlit_ms, 4) if unlit_ms else None,
         "preprocess_s": {"generate": round(gen_s, 2), "build": round(build_s, 4), "pack_upload": round(pack_s, 3)},
         "roofline": roof,
+        "unlit_roofline": unlit_roof,
         "cpu_baseline": cpu,
         "learned_skip": learned_res,
         "batched_serving": batched_res,

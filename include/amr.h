@@ -286,6 +286,10 @@ typedef struct {
                                            camera (16 bytes each); a sample beyond this count has
                                            its secondary ray traced in the shading pass (same
                                            value, slower; counted in light_inline) */
+    uint32_t *d_touch_meta;             /* measurement (device, NULL to skip): one bit per 16 bytes
+                                           of the scene's metadata buffer (from scene.nodes), set for
+                                           the node, leaf, patch-header and face records the frame
+                                           reads */
     int32_t bound_only;                 /* 1: skip segments by the analytic bound alone (the learned
                                            kernel with the network never consulted; d_mlp must be
                                            NULL): a data segment is skipped if B + T * alpha_max <

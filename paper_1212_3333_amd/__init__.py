@@ -374,7 +374,7 @@ def render(scene: Scene, cams, lut: torch.Tensor, params: dict, trace_cap: int =
         res["nsamp"] = ns
     st = torch.zeros(16, dtype=torch.int64, device=dev) if stats else None
     for k in ("d_ckpt", "ckpt_bytes", "ckpt_every", "ckpt_max", "d_mlp", "d_seglog", "seglog_cap", "d_queue",
-              "d_stamps", "d_touch", "d_cams", "d_work", "work_bytes", "light_jobs"):
+              "d_stamps", "d_touch", "d_touch_meta", "d_cams", "d_work", "work_bytes", "light_jobs"):
         if k in extra:
             v = extra[k]
             setattr(q, k, v.data_ptr() if isinstance(v, torch.Tensor) else v)

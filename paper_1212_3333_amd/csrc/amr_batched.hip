@@ -229,7 +229,7 @@ int launch_persistent(const amr_scene *S, const amr_camera *cams, int32_t ncams,
         set_error("persistent mode needs params.d_queue (amr_queue_bytes) and params.d_cams (device cameras)");
         return AMR_EINVAL;
     }
-    if (P->d_trace || P->d_ckpt || P->d_nsamp || P->d_touch) {
+    if (P->d_trace || P->d_ckpt || P->d_nsamp || P->d_touch || P->d_touch_meta) {
         set_error("persistent mode renders images only (no trace, checkpoints, sample counts or touch map)");
         return AMR_EINVAL;
     }

@@ -106,6 +106,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void re
                         const int leaf = descend(A, R, tcur, tb, start);
                         if (leaf < 0) { alive = false; break; }
                         if (REC) cnt.segments++;
+                        if (REC && A.touch_meta) touch_segment_meta(A, R, tcur, leaf);
                         const DLeaf &L = A.leaves[leaf];
                         const int p = L.patch;
                         int n = 0;
@@ -190,6 +191,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void re
             int leaf = descend(A, R, tcur, tb, start);
             if (leaf < 0) break;
             if (REC) cnt.segments++;
+            if (REC && A.touch_meta) touch_segment_meta(A, R, tcur, leaf);
             const DLeaf &L = A.leaves[leaf];
             const int p = L.patch;
             int nsm = 0;
@@ -587,7 +589,7 @@ int amr_render(const amr_scene *S, const amr_camera *cams, int32_t ncams, const 
         A.touch = P->d_touch;
         A.ckpt_ray0 = pix_off;
         if (learned) {
-            if (P->d_trace || P->d_ckpt || P->d_touch) {
+            if (P->d_trace || P->d_ckpt || P->d_touch || P->d_touch_meta) {
                 set_error("learned proposals / segment logging do not record traces, checkpoints or touch maps");
                 return AMR_EINVAL;
             }
@@ -597,7 +599,7 @@ int amr_render(const amr_scene *S, const amr_camera *cams, int32_t ncams, const 
             continue;
         }
         const int grid = 8 * ((A.sgrid * A.sgrid + 7) / 8) * 16;
-        const bool rec = A.trace || A.trace_n || A.nsamp || A.stats || A.touch || A.ckpt;
+        const bool rec = A.trace || A.trace_n || A.nsamp || A.stats || A.touch || A.touch_meta || A.ckpt;
         if (A.lighting == 2) {
             rc = launch_shadow(A, rec, stream, P->d_work, P->work_bytes, P->light_jobs);
             if (rc) return rc;

@@ -53,6 +53,8 @@ struct RenderArgs {
     int64_t trace_cap;
     amr_render_stats *stats;
     uint32_t *touch;
+    uint32_t *touch_meta;            // measurement: one bit per 16 bytes of the scene's metadata
+    const uint8_t *meta_base;        // start of the metadata buffer (the node array)
     uint8_t *ckpt;                   // checkpoint buffer base (all cameras)
     int64_t ckpt_ray0;               // first ray of this camera in the buffer
     int64_t ckpt_stride;             // bytes per ray
@@ -142,13 +144,20 @@ __device__ __forceinline__ bool setup_ray(const RenderArgs &A, int i, int j, Ray
     return true;
 }
 
+// Measurement only: marks the metadata bytes [p, p + bytes) as read (16-byte granules).
+__device__ __forceinline__ void touch_meta(const RenderArgs &A, const void *p, int bytes) {
+    const int64_t off = (const uint8_t *)p - A.meta_base;
+    for (int64_t g = off >> 4; g <= (off + bytes - 1) >> 4; g++) atomicOr(&A.touch_meta[g >> 5], 1u << (g & 31));
+}
+
 // kD-restart with push-down: `start` is the deepest node known to hold the rest of the ray.
 // While the descent has not clipped tmax, every decision on the way down was independent of
 // tmin (the split lay outside [tmin, tmax], or behind tmin), so a later restart with a larger
 // tmin and the same tmax takes the same way: the walk can begin at the node reached so far.  The
 // leaves and exits found are exactly those of a restart from the root.  Level-of-detail walks
 // always start at the root (they must see every kind-(a) node on the way).
-template <bool LOD>
+// MARK (measurement): every node read is marked in A.touch_meta.
+template <bool LOD, bool MARK = false>
 __device__ __forceinline__ int descend_walk(const RenderArgs &A, const Ray &R, double tmin, double &tmax,
                                             uint32_t &start) {
 #pragma clang fp contract(off)
@@ -156,12 +165,17 @@ __device__ __forceinline__ int descend_walk(const RenderArgs &A, const Ray &R, d
     bool open = !LOD;
     for (int it = 0; it <= A.depth; it++) {
         DNode n = A.nodes[ni];
+        if (MARK) touch_meta(A, &A.nodes[ni], (int)sizeof(DNode));
         uint32_t axis = n.meta & 3u;
         if (axis == kLeafAxis) return (int)n.child;
         if (LOD && (n.meta >> 8)) {
             // a kind-(a) node: stop here when the cells of its coarse patch project to fewer than
             // lod pixels at the segment start; the segment is then [tmin, tmax] across the node
             const int vl = A.nleaves + (int)(n.meta >> 8) - 1;
+            if (MARK) {
+                touch_meta(A, &A.leaves[vl], (int)sizeof(DLeaf));
+                touch_meta(A, &A.patches[A.leaves[vl].patch], (int)sizeof(DPatch));
+            }
             const double h = A.patches[A.leaves[vl].patch].step;
             const double foot = A.ortho ? A.lod_pix : tmin * A.lod_pix;
             if (h < A.lod * foot) return vl;
@@ -198,12 +212,26 @@ __device__ __forceinline__ int descend(const RenderArgs &A, const Ray &R, double
     return descend(A, R, tmin, tmax, start);
 }
 
+// The metadata a recorded segment read: the nodes from the root to its leaf (the push-down
+// walks read a subset of them, the restarts before it the rest), its leaf record and the
+// patch header.
+__device__ __forceinline__ void touch_segment_meta(const RenderArgs &A, const Ray &R, double tcur, int leaf) {
+    double tmax = R.t1;
+    uint32_t start = 0;
+    if (A.lod_on) descend_walk<true, true>(A, R, tcur, tmax, start);
+    else descend_walk<false, true>(A, R, tcur, tmax, start);
+    touch_meta(A, &A.leaves[leaf], (int)sizeof(DLeaf));
+    if (A.leaves[leaf].patch >= 0) touch_meta(A, &A.patches[A.leaves[leaf].patch], (int)sizeof(DPatch));
+}
+
 // Leaf holding point x (half-open comparisons against the split planes), descending from
-// node `start` (the root, or a node known to hold x).
+// node `start` (the root, or a node known to hold x).  MARK: nodes read are marked.
+template <bool MARK = false>
 __device__ __forceinline__ int locate_leaf(const RenderArgs &A, const double x[3], uint32_t start = 0) {
     uint32_t ni = start;
     for (int it = 0; it <= A.depth; it++) {
         DNode n = A.nodes[ni];
+        if (MARK) touch_meta(A, &A.nodes[ni], (int)sizeof(DNode));
         uint32_t axis = n.meta & 3u;
         if (axis == kLeafAxis) return (int)n.child;
         ni = sel3(axis, x[0], x[1], x[2]) < n.split ? n.child : n.child + 1;
@@ -447,12 +475,14 @@ __device__ __forceinline__ bool locate_brick(const RenderArgs &A, const double x
     #pragma unroll
     for (int a = 0; a < 3; a++)
         if (x[a] < A.box_lo[a] || x[a] > A.box_hi[a]) return false;
-    int leaf = locate_leaf(A, x, start);
+    int leaf = (REC && A.touch_meta) ? locate_leaf<true>(A, x, start) : locate_leaf(A, x, start);
     if (REC) cnt.desc++;
     if (leaf < 0) return false;
+    if (REC && A.touch_meta) touch_meta(A, &A.leaves[leaf], (int)sizeof(DLeaf));
     int p = A.leaves[leaf].patch;
     if (p < 0) return false;
     const DPatch &P = A.patches[p];
+    if (REC && A.touch_meta) touch_meta(A, &P, (int)sizeof(DPatch));
     pv = patch_view<LAY>(A, P);
     #pragma unroll
     for (int a = 0; a < 3; a++) q[a] = (float)((x[a] - P.lo[a]) * P.inv_h[a] - 0.5);
@@ -757,6 +787,8 @@ __device__ __forceinline__ uint32_t resolve_taps(const RenderArgs &A, int leaf, 
             pv = own ? *own : patch_view<LAY>(A, A.patches[patch]);
         } else {
             const DFaceXf X = c == kTapFace ? A.face_xf[6 * leaf + 2 * a + (sgn ? 0 : 1)] : DFaceXf{};
+            if (REC && A.touch_meta && c == kTapFace)
+                touch_meta(A, &A.face_xf[6 * leaf + 2 * a + (sgn ? 0 : 1)], (int)sizeof(DFaceXf));
             if (c == kTapFace && X.n[0] > 0) {
                 // the slab's single owner: its brick at the mapped position
                 if (REC) cnt.face++;
@@ -1349,6 +1381,8 @@ inline int fill_args(const amr_scene *S, const amr_camera *C, const amr_render_p
     A->npatches = S->npatches;
     A->lod_pix = C->ortho ? (2.0 * C->win[1]) / (double)C->height : (2.0 * C->tan_half_fov) / (double)C->height;
     A->lut = (const float4 *)P->d_lut;
+    A->touch_meta = P->d_touch_meta;
+    A->meta_base = (const uint8_t *)S->nodes;
     #pragma unroll
     for (int a = 0; a < 3; a++) {
         A->box_lo[a] = S->box_lo[a];

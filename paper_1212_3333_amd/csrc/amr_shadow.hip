@@ -318,6 +318,7 @@ int launch_shadow(const RenderArgs &A, bool rec, void *stream, void *work, int64
     Ap.nsamp = nullptr;
     Ap.stats = nullptr;
     Ap.touch = nullptr;
+    Ap.touch_meta = nullptr;
     char *p = (char *)work;
     ShadowWork W{};
     W.cnt = (int32_t *)p;
