@@ -295,7 +295,12 @@ typedef struct {
                                            NULL): a data segment is skipped if B + T * alpha_max <
                                            tau_e, with B and alpha_max as for learned proposals; no
                                            coarse sampling.  0: learned proposals when d_mlp is set */
-    int32_t pad1_;
+    int32_t queue_order;                /* persistent: 0 cameras largest image first, 1 smallest first */
+    int32_t xcd_tiles;                  /* persistent: 0 one tile queue, images row by row; 1 one queue per
+                                           XCD (blocks b with b mod 8 = x take queue x), holding the
+                                           4x4-tile super-tiles x, x + 8, ... of each image along a
+                                           Morton curve, so the tiles in flight on an XCD stay close */
+    int32_t pad2_;
 } amr_render_params;
 
 /* Renders ncams cameras (host array) into d_rgba (device, premultiplied RGBA fp32, images

@@ -329,6 +329,8 @@ def make_params(p: dict, d_lut) -> L.amr_render_params:
     q.interp = int(p.get("interp", 0))
     q.lod = float(p.get("lod", 0.0))
     q.bound_only = int(bool(p.get("bound_only", 0)))
+    q.queue_order = int(p.get("queue_order", 0))
+    q.xcd_tiles = int(p.get("xcd_tiles", 0))
     return q
 
 

@@ -108,7 +108,8 @@ class amr_render_params(ctypes.Structure):
                 ("blocks_per_cu", ctypes.c_int32), ("interp", ctypes.c_int32), ("lod", ctypes.c_float),
                 ("d_queue", VP), ("d_stamps", VP), ("d_cams", VP), ("d_touch", VP),
                 ("d_work", VP), ("work_bytes", ctypes.c_int64), ("light_jobs", ctypes.c_int64),
-                ("d_touch_meta", VP), ("bound_only", ctypes.c_int32), ("pad1_", ctypes.c_int32)]
+                ("d_touch_meta", VP), ("bound_only", ctypes.c_int32), ("queue_order", ctypes.c_int32),
+                ("xcd_tiles", ctypes.c_int32), ("pad2_", ctypes.c_int32)]
 
 
 class amr_seglog_rec(ctypes.Structure):

@@ -13,45 +13,61 @@
 
 namespace amr {
 
-// Queue scratch layout (amr_queue_bytes): counters first, then per-camera tables.
+// Queue scratch layout (amr_queue_bytes): counters first, then per-camera tables.  There are
+// kQueues tile queues: with XCD-aware tiles, queue x serves the waves of blocks x, x + 8, ...
+// (the hardware deals blocks to the 8 XCDs in turn) and lists, image by image, the 4x4-tile
+// super-tiles x, x + 8, x + 16, ... of each image along a Morton curve, as the single-camera
+// kernel deals them; otherwise queue 0 lists every image's tiles row by row.
+constexpr int kQueues = 8;
+
 struct QueueView {
-    unsigned int *next;          // [1] next tile to hand out
+    unsigned int *next;          // [kQueues] next tile of each queue, 64 bytes apart
     unsigned int *done;          // [ncams] tiles finished per camera
-    int *order;                  // [ncams] cameras, largest first
-    long long *tile0;            // [ncams + 1] first tile of the k-th camera in `order`
+    unsigned int *ntiles;        // [ncams] tiles of each camera over all queues
+    int *order;                  // [ncams] cameras in queue order
+    long long *tile0;            // [kQueues][ncams + 1] first tile of the k-th camera in `order`
     long long *pix0;             // [ncams] first pixel of camera c in the rgba output
-    int *tiles_x;                // [ncams]
+    int *tiles_x, *tiles_y;      // [ncams]
+    int *sgrid;                  // [ncams] side of the power-of-two super-tile grid
 };
+
+__host__ __device__ __forceinline__ int64_t q_align(int64_t b) { return (b + 255) / 256 * 256; }
 
 __host__ __device__ __forceinline__ QueueView queue_view(void *base, int ncams) {
     char *p = (char *)base;
     QueueView q;
     q.next = (unsigned int *)p;
-    p += 256;
+    p += 64 * kQueues;
     q.done = (unsigned int *)p;
-    p += ((4 * ncams + 255) / 256) * 256;
+    p += q_align(4 * (int64_t)ncams);
+    q.ntiles = (unsigned int *)p;
+    p += q_align(4 * (int64_t)ncams);
     q.order = (int *)p;
-    p += ((4 * ncams + 255) / 256) * 256;
+    p += q_align(4 * (int64_t)ncams);
     q.tile0 = (long long *)p;
-    p += ((8 * (ncams + 1) + 255) / 256) * 256;
+    p += q_align(8 * (int64_t)kQueues * (ncams + 1));
     q.pix0 = (long long *)p;
-    p += ((8 * ncams + 255) / 256) * 256;
+    p += q_align(8 * (int64_t)ncams);
     q.tiles_x = (int *)p;
+    p += q_align(4 * (int64_t)ncams);
+    q.tiles_y = (int *)p;
+    p += q_align(4 * (int64_t)ncams);
+    q.sgrid = (int *)p;
     return q;
 }
 
 inline int64_t queue_bytes(int ncams) {
-    return 256 + 2 * ((4 * (int64_t)ncams + 255) / 256) * 256 + ((8 * ((int64_t)ncams + 1) + 255) / 256) * 256 +
-           ((8 * (int64_t)ncams + 255) / 256) * 256 + ((4 * (int64_t)ncams + 255) / 256) * 256;
+    return 64 * kQueues + 3 * q_align(4 * (int64_t)ncams) + q_align(8 * (int64_t)kQueues * (ncams + 1)) +
+           q_align(8 * (int64_t)ncams) + 3 * q_align(4 * (int64_t)ncams);
 }
 
-// One thread: reset the queue, order cameras by pixel count (descending, ties by index) and
-// build the tile and pixel prefix tables.
+// One thread: reset the queues, order the cameras by pixel count (largest first, or smallest
+// first with `smallest`; ties by index) and build the tile and pixel prefix tables.
 __global__ void queue_setup(const amr_camera *cams, int ncams, void *qbase, int tw, int th,
-                            unsigned long long *stamps) {
+                            unsigned long long *stamps, int smallest, int xcd_tiles) {
     if (blockIdx.x != 0 || threadIdx.x != 0) return;
     QueueView q = queue_view(qbase, ncams);
-    *q.next = 0u;
+    for (int x = 0; x < kQueues; x++) q.next[16 * x] = 0u;
     long long pix = 0;
     for (int c = 0; c < ncams; c++) {
         q.done[c] = 0u;
@@ -59,32 +75,46 @@ __global__ void queue_setup(const amr_camera *cams, int ncams, void *qbase, int 
         q.pix0[c] = pix;
         pix += (long long)cams[c].width * cams[c].height;
         q.tiles_x[c] = (cams[c].width + tw - 1) / tw;
+        q.tiles_y[c] = (cams[c].height + th - 1) / th;
+        int sg = 1;
+        while (sg * 4 < q.tiles_x[c] || sg * 4 < q.tiles_y[c]) sg *= 2;
+        q.sgrid[c] = sg;
+        q.ntiles[c] = xcd_tiles ? (unsigned int)(16 * sg * sg) : (unsigned int)(q.tiles_x[c] * q.tiles_y[c]);
         if (stamps) stamps[c] = 0ull;
     }
     if (stamps) stamps[ncams] = 0ull;
-    for (int i = 1; i < ncams; i++) {          // insertion sort, largest image first
+    for (int i = 1; i < ncams; i++) {          // insertion sort by pixel count
         int c = q.order[i];
         long long sz = (long long)cams[c].width * cams[c].height;
         int j = i - 1;
-        while (j >= 0 && (long long)cams[q.order[j]].width * cams[q.order[j]].height < sz) {
+        while (j >= 0) {
+            const long long sj = (long long)cams[q.order[j]].width * cams[q.order[j]].height;
+            if (!(smallest ? sj > sz : sj < sz)) break;
             q.order[j + 1] = q.order[j];
             j--;
         }
         q.order[j + 1] = c;
     }
-    long long t = 0;
-    for (int k = 0; k < ncams; k++) {
-        q.tile0[k] = t;
-        int c = q.order[k];
-        t += (long long)q.tiles_x[c] * ((cams[c].height + th - 1) / th);
+    for (int x = 0; x < kQueues; x++) {
+        long long t = 0;
+        for (int k = 0; k < ncams; k++) {
+            q.tile0[x * (ncams + 1) + k] = t;
+            const int c = q.order[k];
+            if (xcd_tiles) {
+                const long long S = (long long)q.sgrid[c] * q.sgrid[c];      // super-tiles x, x + 8, ...
+                t += x < S ? 16 * ((S - x + kQueues - 1) / kQueues) : 0;
+            } else if (x == 0) {
+                t += q.ntiles[c];
+            }
+        }
+        q.tile0[x * (ncams + 1) + ncams] = t;
     }
-    q.tile0[ncams] = t;
 }
 
 struct BatchArgs {
     RenderArgs base;                 // scene, LUT and shading parameters; camera fields unused
     const amr_camera *cams;          // device camera table
-    int ncams, tw, th;
+    int ncams, tw, th, xcd_tiles;
     void *queue;
     unsigned long long *stamps;
 };
@@ -115,29 +145,47 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void r
     __syncthreads();
     const int lane = threadIdx.x & 63;
     QueueView q = queue_view(B.queue, B.ncams);
-    const long long total = q.tile0[B.ncams];
+    const int qx = B.xcd_tiles ? (int)(blockIdx.x % kQueues) : 0;   // this wave's queue
+    const long long *tile0 = q.tile0 + (long long)qx * (B.ncams + 1);
+    const long long total = tile0[B.ncams];
     Counters cnt;
     RenderArgs A = B.base;
     while (true) {
         unsigned int tile = 0;
-        if (lane == 0) tile = atomicAdd(q.next, 1u);
+        if (lane == 0) tile = atomicAdd(q.next + 16 * qx, 1u);
         tile = __shfl(tile, 0, 64);
-        if ((long long)tile >= total) break;           // every wave leaves once the queue is empty
-        if (tile == 0 && lane == 0 && B.stamps) B.stamps[B.ncams] = wall_clock64();
+        if ((long long)tile >= total) break;           // every wave leaves once its queue is empty
+        if (tile == 0 && lane == 0 && B.stamps && qx == 0) B.stamps[B.ncams] = wall_clock64();
         int k = 0;                                     // camera slot: largest k with tile0[k] <= tile
         int lo = 0, hi = B.ncams - 1;
         while (lo < hi) {
             int mid = (lo + hi + 1) >> 1;
-            if (q.tile0[mid] <= (long long)tile) lo = mid;
+            if (tile0[mid] <= (long long)tile) lo = mid;
             else hi = mid - 1;
         }
         k = lo;
         const int c = q.order[k];
         const amr_camera C = B.cams[c];
         set_camera(A, C);
-        const long long local = (long long)tile - q.tile0[k];
-        const int txs = q.tiles_x[c];
-        const int tx = (int)(local % txs), ty = (int)(local / txs);
+        const long long local = (long long)tile - tile0[k];
+        int tx, ty;
+        if (B.xcd_tiles) {
+            // super-tile qx + 8 (local / 16) along the Morton curve, tile local % 16 in it
+            const long long st = qx + (long long)kQueues * (local / 16);
+            const int sub = (int)(local % 16);
+            int sx = 0, sy = 0;
+            #pragma unroll
+            for (int bit = 0; bit < 15; bit++) {
+                sx |= (int)((st >> (2 * bit)) & 1) << bit;
+                sy |= (int)((st >> (2 * bit + 1)) & 1) << bit;
+            }
+            tx = sx * 4 + (sub >> 2);
+            ty = sy * 4 + (sub & 3);
+        } else {
+            const int txs = q.tiles_x[c];
+            tx = (int)(local % txs);
+            ty = (int)(local / txs);
+        }
         const int pi = tx * B.tw + lane % B.tw;
         const int pj = ty * B.th + lane / B.tw;
         const bool valid = pi < C.width && pj < C.height;
@@ -198,9 +246,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void r
         // completion: the wave that finishes the image's last tile stamps it
         __threadfence();
         if (lane == 0) {
-            unsigned int ntiles = (unsigned int)(q.tile0[k + 1] - q.tile0[k]);
             unsigned int d = atomicAdd(&q.done[c], 1u) + 1u;
-            if (d == ntiles && B.stamps) B.stamps[c] = wall_clock64();
+            if (d == q.ntiles[c] && B.stamps) B.stamps[c] = wall_clock64();
         }
     }
     if (REC && B.base.stats) flush_counters(B.base.stats, cnt, lane);
@@ -248,11 +295,17 @@ int launch_persistent(const amr_scene *S, const amr_camera *cams, int32_t ncams,
     B.th = th;
     B.queue = P->d_queue;
     B.stamps = P->d_stamps;
+    if (P->queue_order < 0 || P->queue_order > 1 || P->xcd_tiles < 0 || P->xcd_tiles > 1) {
+        set_error("queue_order and xcd_tiles must be 0 or 1");
+        return AMR_EINVAL;
+    }
+    B.xcd_tiles = P->xcd_tiles;
     hipStream_t s = (hipStream_t)stream;
     if (d_stats)
         hipLaunchKernelGGL(zero_stats, dim3(1), dim3(64), 0, s, (unsigned long long *)d_stats,
                            (int)(sizeof(amr_render_stats) / 8));
-    hipLaunchKernelGGL(queue_setup, dim3(1), dim3(64), 0, s, P->d_cams, ncams, P->d_queue, tw, th, P->d_stamps);
+    hipLaunchKernelGGL(queue_setup, dim3(1), dim3(64), 0, s, P->d_cams, ncams, P->d_queue, tw, th, P->d_stamps,
+                       (int)P->queue_order, (int)P->xcd_tiles);
     int bpc = P->blocks_per_cu > 0 ? P->blocks_per_cu : 4;
     dim3 grid(device_cus() * bpc);
     const bool rec = d_stats != nullptr;

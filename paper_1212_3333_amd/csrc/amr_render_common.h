@@ -915,11 +915,16 @@ __device__ __forceinline__ void lit_gradient(const RenderArgs &A, float F, const
         gv[a] = lit_gradient_axis(A, F, Fp[a], Fm[a], (okbits >> (2 * a)) & 1u, (okbits >> (2 * a + 1)) & 1u);
 }
 
-// Diffuse shading factor k_a + k_d |g . l| / sqrt(|g|^2 + eps^2) (Section 6).
+// Diffuse shading factor k_a + k_d |g . l| / sqrt(|g|^2 + eps^2) (Section 6), the fraction 0
+// where the denominator is 0.  The reciprocal square root is the hardware's (within 1 ulp),
+// which replaces a correctly rounded square root and division (some 30 instructions per lit
+// sample); den = n2 / sqrt(n2) is kept for the adjoint.
 __device__ __forceinline__ float lit_shade(const RenderArgs &A, const float gv[3], float &dot, float &den) {
     dot = gv[0] * A.lhat[0] + gv[1] * A.lhat[1] + gv[2] * A.lhat[2];
-    den = sqrtf(gv[0] * gv[0] + gv[1] * gv[1] + gv[2] * gv[2] + A.eps2);
-    return A.k_a + (den > 0.f ? A.k_d * fabsf(dot) / den : 0.f);
+    const float n2 = gv[0] * gv[0] + gv[1] * gv[1] + gv[2] * gv[2] + A.eps2;
+    const float r = n2 > 0.f ? __builtin_amdgcn_rsqf(n2) : 0.f;
+    den = n2 * r;
+    return A.k_a + A.k_d * fabsf(dot) * r;
 }
 
 // Transfer function: colour and extinction by linear interpolation in the 256-entry LUT at the
@@ -937,7 +942,9 @@ __device__ __forceinline__ void lut_classify(const RenderArgs &A, const float4 *
     v.g = lerpf(La.y, Lb.y, f);
     v.b = lerpf(La.z, Lb.z, f);
     v.sig = lerpf(La.w, Lb.w, f);
-    v.alpha = 1.f - exp2f(-v.sig * dl);
+    // the hardware exp2 (1 ulp); its results below the normal range flush to 0, where 1 - exp2
+    // is 1 either way
+    v.alpha = 1.f - __builtin_amdgcn_exp2f(-v.sig * dl);
 }
 
 // Nearest-cell sampling (interp = 1): F(x) is the value of the cell of the finest patch that

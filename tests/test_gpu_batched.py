@@ -29,9 +29,14 @@ def _cams(n, seed=0):
     return out
 
 
+@pytest.mark.parametrize("order", [0, 1])
+@pytest.mark.parametrize("xcd", [0, 1])
 @pytest.mark.parametrize("tile", [(8, 8), (16, 4), (4, 16), (32, 2)])
 @pytest.mark.parametrize("lit", [False, True])
-def test_batched_bit_identical(gpu, tiny, tile, lit):
+def test_batched_bit_identical(gpu, tiny, tile, lit, xcd, order):
+    """Every image of a persistent batch equals its single-camera render bit for bit, for every
+    tile shape, both tile queues (one row-major queue; per-XCD Morton super-tiles) and both
+    camera orders; every image gets a completion stamp after the launch-start stamp."""
     import torch
     amr = gpu
     h, lut, prm, tree, scene = tiny
@@ -41,7 +46,8 @@ def test_batched_bit_identical(gpu, tiny, tile, lit):
     dc = amr.camera_table(cams)
     q = amr.queue_buffer(len(cams))
     stamps = torch.zeros(len(cams) + 1, dtype=torch.int64, device="cuda")
-    out = amr.render(scene, cams, lut_t, dict(prm, persistent=1, tile_w=tile[0], tile_h=tile[1], blocks_per_cu=2),
+    out = amr.render(scene, cams, lut_t, dict(prm, persistent=1, tile_w=tile[0], tile_h=tile[1], blocks_per_cu=2,
+                                              xcd_tiles=xcd, queue_order=order),
                      d_cams=dc, d_queue=q, d_stamps=stamps, stats=True)
     ref = amr.render(scene, cams, lut_t, prm, stats=True)
     torch.cuda.synchronize()
@@ -99,12 +105,21 @@ def test_autotune_picks_a_candidate(gpu, tiny, tmp_path):
     q = amr.queue_buffer(len(cams))
     npix = sum(c["width"] * c["height"] for c in cams)
     out = torch.empty(npix * 4, dtype=torch.float32, device="cuda")
+    scenes = {1: scene, 2: amr.pack(tree, h, device="cuda", brick_layout=2)}
     res = autotune.tune(scene, cams, lut_t, prm, dc, q, out, "tiny-test", reps=1,
-                        cache_path=str(tmp_path / "cache.json"))
+                        cache_path=str(tmp_path / "cache.json"), scenes=scenes)
     assert (res["tile_w"], res["tile_h"]) in autotune.CANDIDATE_TILES
-    assert len(res["table"]) == len(autotune.CANDIDATE_TILES) * len(autotune.CANDIDATE_BPC)
+    assert res["xcd_tiles"] in (0, 1) and res["brick_layout"] in (1, 2)
+    assert len(res["table"]) == len(autotune.candidates((1, 2)))
     again = autotune.tune(scene, cams, lut_t, prm, dc, q, out, "tiny-test", cache_path=str(tmp_path / "cache.json"))
     assert again == res
+    # the chosen configuration renders what the single-camera kernel renders
+    best = dict(prm, persistent=1, tile_w=res["tile_w"], tile_h=res["tile_h"], blocks_per_cu=res["blocks_per_cu"],
+                xcd_tiles=res["xcd_tiles"], queue_order=res["queue_order"])
+    got = amr.render(scenes[res["brick_layout"]], cams, lut_t, best, d_cams=dc, d_queue=q)["rgba"]
+    ref = amr.render(scene, cams, lut_t, prm)["rgba"]
+    torch.cuda.synchronize()
+    assert torch.equal(got, ref)
 
 
 def test_serving_batch_latency(gpu, tmp_path):
@@ -127,9 +142,10 @@ def test_serving_batch_latency(gpu, tmp_path):
     out = torch.zeros(npix * 4, dtype=torch.float32, device="cuda")
     best = autotune.tune(scene, cams, lut_t, prm, dc, q, out, workload_key="serving64", reps=1,
                          cache_path=str(tmp_path / "tune.json"))
-    print("autotuned:", {k: best[k] for k in ("tile_w", "tile_h", "blocks_per_cu", "ms")})
+    print("autotuned:", {k: best[k] for k in ("tile_w", "tile_h", "blocks_per_cu", "xcd_tiles", "queue_order", "ms")})
     stamps = torch.zeros(len(cams) + 1, dtype=torch.int64, device="cuda")
-    bprm = dict(prm, persistent=1, tile_w=best["tile_w"], tile_h=best["tile_h"], blocks_per_cu=best["blocks_per_cu"])
+    bprm = dict(prm, persistent=1, tile_w=best["tile_w"], tile_h=best["tile_h"], blocks_per_cu=best["blocks_per_cu"],
+                xcd_tiles=best["xcd_tiles"], queue_order=best["queue_order"])
     amr.render(scene, cams, lut_t, bprm, out=out, d_cams=dc, d_queue=q, d_stamps=stamps)
     torch.cuda.synchronize()
     g = torch.cuda.CUDAGraph()

@@ -71,8 +71,9 @@ def test_timed_launch_vs_oracle(gpu, timed_scene, lit):
 
 @pytest.mark.parametrize("lit", [True, False])
 def test_persistent_batch_vs_oracle(gpu, timed_scene, lit):
-    """The serving batch in one persistent launch on the halo-row scene: the two largest and the
-    two smallest images (and two in between) on 1,024 seeded pixels each against the oracle."""
+    """The serving batch in one persistent launch (per-XCD Morton tile queues) on the halo-row
+    scene: the two largest and the two smallest images (and two in between) on 1,024 seeded
+    pixels each against the oracle."""
     import torch
     amr = gpu
     h, lut, lut_t, _, prm, scene, O = timed_scene
@@ -80,7 +81,7 @@ def test_persistent_batch_vs_oracle(gpu, timed_scene, lit):
     cams = workloads.serving_cameras(0, 64)
     npix = [c["width"] * c["height"] for c in cams]
     off = np.concatenate([[0], np.cumsum(npix)])
-    out = amr.render(scene, cams, lut_t, dict(prm, persistent=1, tile_w=8, tile_h=8, blocks_per_cu=8),
+    out = amr.render(scene, cams, lut_t, dict(prm, persistent=1, tile_w=8, tile_h=8, blocks_per_cu=8, xcd_tiles=1),
                      d_cams=amr.camera_table(cams), d_queue=amr.queue_buffer(len(cams)))["rgba"]
     torch.cuda.synchronize()
     order = np.argsort(npix, kind="stable")
