@@ -238,6 +238,13 @@ typedef struct {
     int64_t ckpt_bytes;
     int32_t ckpt_every;                 /* checkpoint every k-th data segment (>= 1) */
     int32_t ckpt_max;                   /* checkpoints per ray */
+    float *d_tape;                      /* optional with d_ckpt, lit: [nrays][tape_cap][3] fp32 (device),
+                                           the gradient of every sample whose gradient taps left its
+                                           brick, in the ray's order of such samples, written by the
+                                           forward and read by amr_render_backward instead of
+                                           resolving those taps again; rays with more such samples
+                                           than tape_cap are resolved in place by the adjoint */
+    int64_t tape_cap;                   /* tape entries per ray (amr_tape_bytes) */
     /* learned segment proposals (NULL = plain traversal).  alpha_max = 1 - exp(-sigma_max L)
        is the analytic bound on a segment's opacity from the leaf's value range; the network
        predicts quantiles (r_lo, r_hi) of alpha / alpha_max, clamped to [0, 1], and
@@ -323,6 +330,8 @@ int64_t amr_wall_clock_khz(void);
 
 /* Checkpoint buffer bytes for nrays rays with ckpt_max checkpoints each. */
 int64_t amr_ckpt_bytes(int64_t nrays, int32_t ckpt_max);
+/* Gradient tape bytes for nrays rays with tape_cap entries each (12 bytes per entry). */
+int64_t amr_tape_bytes(int64_t nrays, int64_t tape_cap);
 
 /* Workspace bytes (params->d_work) amr_render needs for these cameras and params: with
  * lighting = 2, per-ray sample counts and job offsets for the largest camera plus

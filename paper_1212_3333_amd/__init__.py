@@ -375,7 +375,8 @@ def render(scene: Scene, cams, lut: torch.Tensor, params: dict, trace_cap: int =
         q.d_nsamp = ns.data_ptr()
         res["nsamp"] = ns
     st = torch.zeros(16, dtype=torch.int64, device=dev) if stats else None
-    for k in ("d_ckpt", "ckpt_bytes", "ckpt_every", "ckpt_max", "d_mlp", "d_seglog", "seglog_cap", "d_queue",
+    for k in ("d_ckpt", "ckpt_bytes", "ckpt_every", "ckpt_max", "d_tape", "tape_cap", "d_mlp", "d_seglog", "seglog_cap",
+              "d_queue",
               "d_stamps", "d_touch", "d_touch_meta", "d_cams", "d_work", "work_bytes", "light_jobs"):
         if k in extra:
             v = extra[k]
@@ -482,26 +483,50 @@ def stats_dict(res: RenderOutput) -> dict:
     return {k: int(v[i]) for i, k in enumerate(L.STATS_FIELDS)}
 
 
-class Checkpoints:
-    """Device buffer the checkpointed forward fills and the adjoint reads: per ray a header
-    (final T and C, samples, checkpoint count) and up to ckpt_max (t, T, C) records taken at the
-    start of every ckpt_every-th data segment (the rate halves when a ray runs out of slots)."""
+# Gradient tape entries per ray for lit checkpointed renders (12 bytes each); rays with more
+# samples whose taps leave the brick are resolved in place by the adjoint.
+TAPE_CAP = 512
 
-    def __init__(self, nrays: int, device, ckpt_every: int = 4, ckpt_max: int = 16):
-        self.nbytes = int(load().amr_ckpt_bytes(nrays, ckpt_max))
+
+class Checkpoints:
+    """Device buffers the checkpointed forward fills and the adjoint reads: per ray a header
+    (final T and C, samples, checkpoint count, tape entries) and up to ckpt_max (t, T, C) records
+    taken at the start of every ckpt_every-th data segment (the rate halves when a ray runs out of
+    slots); with tape_cap > 0 (lit renders) the gradient tape of the samples whose taps left the
+    brick."""
+
+    def __init__(self, nrays: int, device, ckpt_every: int = 4, ckpt_max: int = 16, tape_cap: int = 0):
+        lib = load()
+        self.nbytes = int(lib.amr_ckpt_bytes(nrays, ckpt_max))
         self.buf = torch.empty(self.nbytes, dtype=torch.uint8, device=device)
         self.every, self.max = int(ckpt_every), int(ckpt_max)
+        self.tape_cap = int(tape_cap)
+        self.tape = (torch.empty(int(lib.amr_tape_bytes(nrays, tape_cap)) // 4, dtype=torch.float32, device=device)
+                     if tape_cap > 0 else None)
 
     def params(self) -> dict:
-        return dict(d_ckpt=self.buf, ckpt_bytes=self.nbytes, ckpt_every=self.every, ckpt_max=self.max)
+        p = dict(d_ckpt=self.buf, ckpt_bytes=self.nbytes, ckpt_every=self.every, ckpt_max=self.max)
+        if self.tape is not None:
+            p.update(d_tape=self.tape, tape_cap=self.tape_cap)
+        return p
+
+    def tape_overflow_rays(self) -> int:
+        """Rays whose tape ran out (their adjoint resolves taps in place); synchronises."""
+        if self.tape is None:
+            return 0
+        hdr = self.buf.view(-1, 32 * (1 + self.max))[:, :32].contiguous().view(torch.int32)[:, 7]
+        return int((hdr > self.tape_cap).sum().item())
 
 
 def render_checkpointed(scene: Scene, cams, lut: torch.Tensor, params: dict, ckpt_every: int = 4,
-                        ckpt_max: int = 16, **kw):
-    """Forward render that also records the adjoint's checkpoints. Returns (RenderOutput, Checkpoints)."""
+                        ckpt_max: int = 16, tape_cap: int | None = None, **kw):
+    """Forward render that also records the adjoint's checkpoints (and, lit, the gradient tape of
+    tape_cap entries per ray, default TAPE_CAP; 0 for none). Returns (RenderOutput, Checkpoints)."""
     cam_list = [cams] if isinstance(cams, dict) else list(cams)
     npix = sum(int(c["width"]) * int(c["height"]) for c in cam_list)
-    ck = Checkpoints(npix, scene.pool.device, ckpt_every, ckpt_max)
+    if tape_cap is None:
+        tape_cap = TAPE_CAP if int(params.get("lighting", 0)) == 1 else 0
+    ck = Checkpoints(npix, scene.pool.device, ckpt_every, ckpt_max, tape_cap)
     out = render(scene, cams, lut, params, **ck.params(), **kw)
     return out, ck
 
@@ -519,6 +544,8 @@ def render_backward(scene: Scene, cams, lut: torch.Tensor, params: dict, ckpt: C
     g = grad_rgba.to(device=dev, dtype=torch.float32).contiguous()
     q = make_params(params, lut)
     q.d_ckpt, q.ckpt_bytes, q.ckpt_every, q.ckpt_max = ckpt.buf.data_ptr(), ckpt.nbytes, ckpt.every, ckpt.max
+    if ckpt.tape is not None:
+        q.d_tape, q.tape_cap = ckpt.tape.data_ptr(), ckpt.tape_cap
     glut = torch.empty((256, 4), dtype=torch.float32, device=dev)
     glight = torch.empty(5, dtype=torch.float32, device=dev)
     if static_work:

@@ -101,7 +101,7 @@ class amr_render_params(ctypes.Structure):
                 ("clip_lo", c_double3), ("clip_hi", c_double3),
                 ("d_trace", VP), ("d_trace_n", VP), ("d_nsamp", VP), ("trace_cap", ctypes.c_int64),
                 ("d_ckpt", VP), ("ckpt_bytes", ctypes.c_int64), ("ckpt_every", ctypes.c_int32),
-                ("ckpt_max", ctypes.c_int32),
+                ("ckpt_max", ctypes.c_int32), ("d_tape", VP), ("tape_cap", ctypes.c_int64),
                 ("d_mlp", VP), ("tau_e", ctypes.c_float), ("tau_s", ctypes.c_float),
                 ("d_seglog", VP), ("seglog_cap", ctypes.c_int64),
                 ("persistent", ctypes.c_int32), ("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32),
@@ -141,6 +141,7 @@ SIGNATURES = {
     "amr_queue_bytes": (ctypes.c_int64, [ctypes.c_int32]),
     "amr_wall_clock_khz": (ctypes.c_int64, []),
     "amr_ckpt_bytes": (ctypes.c_int64, [ctypes.c_int64, ctypes.c_int32]),
+    "amr_tape_bytes": (ctypes.c_int64, [ctypes.c_int64, ctypes.c_int64]),
     "amr_render_work_bytes": (ctypes.c_int64, [ctypes.POINTER(amr_camera), ctypes.c_int32,
                                                ctypes.POINTER(amr_render_params)]),
     "amr_backward_work_bytes": (ctypes.c_int64, [ctypes.c_int32]),

@@ -30,10 +30,14 @@ namespace amr {
 // Lit variants defer the samples whose gradient taps leave the brick (trilinear) or need the
 // tree (nearest cell) to a per-wave queue (TapQueue).
 // While recording checkpoints for the adjoint, the queue is resolved before each segment fetch
-// that writes one, so a checkpoint's colour holds every earlier sample.
-template <bool LIT, bool REC, bool NEAR, int LAY>
+// that writes one, so a checkpoint's colour holds every earlier sample; the gradients the queue
+// resolves are written to the ray's tape, so the adjoint reads them instead of resolving taps.
+// CK: checkpoints (and the tape) without the other recording outputs, for the adjoint's forward
+// pass at the layout's compiled addressing.
+template <bool LIT, bool REC, bool NEAR, int LAY, bool CK = false>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void render_fwd(RenderArgs A) {
     constexpr bool kDefer = LIT;
+    constexpr bool kCk = REC || CK;             // checkpoints (and the tape) may be recorded
     __shared__ float4 s_lut[256];
     TapQueue *tq = nullptr;
     if constexpr (kDefer) tq = tap_queues<1>();
@@ -72,7 +76,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void re
     CkptHeader *ckh = nullptr;
     Ckpt *ck = nullptr;
     int nck = 0, every = A.ckpt_every, dseg = 0;
-    if (REC && A.ckpt && valid) {
+    uint32_t ndef = 0;                            // the ray's queued samples so far (tape ordinals)
+    const int64_t tape_base = (kCk && LIT && A.tape) ? A.ckpt_ray0 + (int64_t)(row * 8) * A.width + col * 8 : -1;
+    if (kCk && A.ckpt && valid) {
         ckh = reinterpret_cast<CkptHeader *>(A.ckpt + (A.ckpt_ray0 + ray) * A.ckpt_stride);
         ck = reinterpret_cast<Ckpt *>(ckh + 1);
     }
@@ -94,11 +100,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void re
             const unsigned long long live = __ballot(alive);
             if (!live) break;
             const unsigned long long samp = __ballot(has);
-            if (tq_count(Q) + (uint32_t)__popcll(samp) > (uint32_t)kTapQ) tapq_flush<REC, LAY, NEAR>(A, s_lut, Q, lane, cnt);
+            if (tq_count(Q) + (uint32_t)__popcll(samp) > (uint32_t)kTapQ)
+                tapq_flush<REC, LAY, NEAR, kCk>(A, s_lut, Q, lane, cnt, tape_base);
             const bool waiting = alive && !has;
             const unsigned long long wait = __ballot(waiting);
             if (wait == live || 2 * __popcll(wait) >= __popcll(live)) {
-                if (REC && A.ckpt && tq_count(Q)) tapq_flush<REC, LAY, NEAR>(A, s_lut, Q, lane, cnt);
+                if (kCk && A.ckpt && tq_count(Q)) tapq_flush<REC, LAY, NEAR, kCk>(A, s_lut, Q, lane, cnt, tape_base);
                 if (waiting) {
                     while (true) {            // next segment with samples, or the end of the ray
                         if (!(tcur < R.t1)) { alive = false; break; }
@@ -111,13 +118,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void re
                         const int p = L.patch;
                         int n = 0;
                         if (p >= 0) {
-                            if (REC && ck) {
+                            if (kCk && ck) {
                                 if (dseg % every == 0) {
                                     if (nck == A.ckpt_max) {     // full: keep every other, halve the rate
                                         for (int i = 0; i < A.ckpt_max / 2; i++) ck[i] = ck[2 * i];
                                         nck = A.ckpt_max / 2;
                                         every *= 2;
-                                        cnt.ckover++;
+                                        if (REC) cnt.ckover++;
                                     }
                                     if (dseg % every == 0) {     // colour: shaded at once + deferred, all resolved
                                         Ckpt c;
@@ -126,7 +133,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void re
                                         c.C[0] = C0 + Q.cd[0][lane];
                                         c.C[1] = C1 + Q.cd[1][lane];
                                         c.C[2] = C2 + Q.cd[2][lane];
-                                        c.dseg = dseg;
+                                        c.ndef = (int32_t)ndef;
                                         c.sidx = nsamp_total;
                                         ck[nck++] = c;
                                     }
@@ -166,7 +173,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void re
                 continue;
             }
             if (has) {
-                const float alpha = lit_sample_deferred<REC, LAY, NEAR>(A, s_lut, Q, lane, R, S, k, T, C0, C1, C2, cnt);
+                const float alpha = lit_sample_deferred<REC, LAY, NEAR>(A, s_lut, Q, lane, R, S, k, T, C0, C1, C2, cnt,
+                                                                       kCk ? &ndef : nullptr);
                 T *= 1.f - alpha;
                 nsamp_total++;
                 k++;
@@ -179,7 +187,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void re
             }
         }
         float D0, D1, D2;
-        tapq_finish<REC, LAY, NEAR>(A, s_lut, Q, lane, cnt, D0, D1, D2);
+        tapq_finish<REC, LAY, NEAR, kCk>(A, s_lut, Q, lane, cnt, D0, D1, D2, tape_base);
         C0 += D0;
         C1 += D1;
         C2 += D2;
@@ -196,7 +204,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void re
             const int p = L.patch;
             int nsm = 0;
             if (p >= 0) {
-                if (REC && ck) {
+                if (kCk && ck) {
                     if (dseg % every == 0) {
                         if (nck == A.ckpt_max) {             // full: keep every other, halve the rate
                             for (int i = 0; i < A.ckpt_max / 2; i++) ck[i] = ck[2 * i];
@@ -211,7 +219,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void re
                             c.C[0] = C0;
                             c.C[1] = C1;
                             c.C[2] = C2;
-                            c.dseg = dseg;
+                            c.ndef = 0;
                             c.sidx = nsamp_total;
                             ck[nck++] = c;
                         }
@@ -259,7 +267,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void re
         reinterpret_cast<float4 *>(A.rgba)[ray] = make_float4(C0, C1, C2, 1.f - T);
         if (REC && A.trace_n) A.trace_n[ray] = nseg;
         if (REC && A.nsamp) A.nsamp[ray] = nsamp_total;
-        if (REC && ckh) {
+        if (kCk && ckh) {
             CkptHeader hd;
             hd.T = T;
             hd.C[0] = C0;
@@ -268,7 +276,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void re
             hd.nsamp = nsamp_total;
             hd.nck = nck;
             hd.every = every;
-            hd.pad_ = 0;
+            hd.ndef = (int32_t)ndef;
             *ckh = hd;
         }
     }
@@ -287,8 +295,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void re
 // LUT gradients are accumulated per wave in LDS and combined per block in a fixed order.
 // ------------------------------------------------------------------------------------------
 
-template <bool LIT>
-__global__ __launch_bounds__(256) void render_bwd(RenderArgs A, BwdArgs B) {
+// TAPE: lit samples whose taps left the brick take their gradient from the forward's tape, and
+// only rays whose tape holds all of them are processed; otherwise (TAPE = false) every sample is
+// evaluated in place, for every ray when there is no tape, else for the rays whose tape ran out.
+// LAY: the brick layout fixed at compile time (-1: read at run time).
+template <bool LIT, bool TAPE, int LAY>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(LIT ? 3 : 4))) void render_bwd(RenderArgs A, BwdArgs B) {
     __shared__ float4 s_lut[256];
     __shared__ float s_acc[4][kGradLen];      // one accumulator per wave
     s_lut[threadIdx.x] = A.lut[threadIdx.x];
@@ -311,6 +323,10 @@ __global__ __launch_bounds__(256) void render_bwd(RenderArgs A, BwdArgs B) {
         const Ckpt *ck = reinterpret_cast<const Ckpt *>(ckh + 1);
         const Ckpt c0 = ck[interval];
         const int s_end = interval + 1 < nck ? ck[interval + 1].sidx : hd.nsamp;
+        // the interval's tape entries are [c0.ndef, end): on the tape if all of them fit
+        const int d_end = interval + 1 < nck ? ck[interval + 1].ndef : hd.ndef;
+        const bool taped = LIT && A.tape && (int64_t)d_end <= A.tape_cap;
+        if (TAPE != taped) continue;      // the other launch serves this interval
         const int pi = (int)(ray % A.width), pj = (int)(ray / A.width);
         Ray R;
         if (!setup_ray(A, pi, pj, R)) continue;
@@ -319,6 +335,16 @@ __global__ __launch_bounds__(256) void render_bwd(RenderArgs A, BwdArgs B) {
         float T = c0.T, C0 = c0.C[0], C1 = c0.C[1], C2 = c0.C[2];
         int s = c0.sidx;
         double tcur = c0.t;
+        const float *tape = TAPE ? A.tape + 3 * (A.ckpt_ray0 + ray) * A.tape_cap : nullptr;
+        int64_t ord = TAPE ? c0.ndef : 0;
+        // the next tape entry, loaded one entry ahead so its latency overlaps the samples before
+        // the sample that uses it
+        float n0 = 0.f, n1 = 0.f, n2 = 0.f;
+        if (TAPE && ord < d_end) {
+            n0 = tape[3 * ord];
+            n1 = tape[3 * ord + 1];
+            n2 = tape[3 * ord + 2];
+        }
         while (s < s_end && tcur < R.t1) {
             double tb = R.t1;
             int leaf = descend(A, R, tcur, tb);
@@ -326,11 +352,34 @@ __global__ __launch_bounds__(256) void render_bwd(RenderArgs A, BwdArgs B) {
             const DLeaf &L = A.leaves[leaf];
             if (L.patch >= 0) {
                 Segment S;
-                setup_segment<LIT>(A, R, L, leaf, tcur, tb, S);
+                setup_segment<LIT, LAY>(A, R, L, leaf, tcur, tb, S);
                 const float dlt = (float)S.delta;
                 for (int k = 0; k < S.n && s < s_end; k++, s++) {
                     SampleVals v;
-                    eval_sample<LIT, false>(A, s_lut, R, S, k, v, cnt);
+                    if (TAPE) {
+                        // the forward's decision: a sample with a tap beyond the brick was queued,
+                        // and the tape holds the gradient its resolution found
+                        const float kk = (float)k + 0.5f;
+                        const float qx = S.q0[0] + kk * S.dq[0], qy = S.q0[1] + kk * S.dq[1], qz = S.q0[2] + kk * S.dq[2];
+                        float F, Fp[3], Fm[3];
+                        const uint32_t cls = lit_stencil<false, LAY>(A, S, qx, qy, qz, F, Fp, Fm);
+                        if (pending_taps(cls)) {
+                            v.gv[0] = n0;
+                            v.gv[1] = n1;
+                            v.gv[2] = n2;
+                            if (++ord < d_end) {
+                                n0 = tape[3 * ord];
+                                n1 = tape[3 * ord + 1];
+                                n2 = tape[3 * ord + 2];
+                            }
+                        } else {
+                            lit_gradient(A, F, Fp, Fm, 0x3fu, v.gv);
+                        }
+                        lut_classify(A, s_lut, F, S.dl, v);
+                        v.shade = lit_shade(A, v.gv, v.dot, v.den);
+                    } else {
+                        eval_sample<LIT, false, false, LAY>(A, s_lut, R, S, k, v, cnt);
+                    }
                     const float ta = T * v.alpha;
                     const float e0 = v.shade * v.r, e1 = v.shade * v.g, e2 = v.shade * v.b;
                     C0 += ta * e0;
@@ -453,12 +502,28 @@ int backward_launch(const amr_scene *S, const amr_camera *cams, int32_t ncams, c
         B.grad_rgba = d_grad_rgba + 4 * pix_off;
         B.grad = grad;
         B.partials = partials;
-        if (A.lighting) hipLaunchKernelGGL(render_bwd<true>, dim3(kBwdGrid), dim3(256), 0, s, A, B);
-        else hipLaunchKernelGGL(render_bwd<false>, dim3(kBwdGrid), dim3(256), 0, s, A, B);
-        rc = check_hip(hipGetLastError(), "render_bwd launch");
+        // lit with a tape: the rays the tape covers at the layout's addressing, then the others in
+        // place; otherwise one launch
+        const int nl = A.lighting && A.tape ? 2 : 1;
+        for (int l = 0; l < nl && rc == AMR_OK; l++) {
+            const dim3 g(kBwdGrid), b(256);
+            if (A.lighting && A.tape && l == 0) {
+                if (A.layout == 0) hipLaunchKernelGGL((render_bwd<true, true, 0>), g, b, 0, s, A, B);
+                else if (A.layout == 1) hipLaunchKernelGGL((render_bwd<true, true, 1>), g, b, 0, s, A, B);
+                else hipLaunchKernelGGL((render_bwd<true, true, 2>), g, b, 0, s, A, B);
+            } else if (A.lighting) {
+                hipLaunchKernelGGL((render_bwd<true, false, -1>), g, b, 0, s, A, B);
+            } else {
+                if (A.layout == 0) hipLaunchKernelGGL((render_bwd<false, false, 0>), g, b, 0, s, A, B);
+                else if (A.layout == 1) hipLaunchKernelGGL((render_bwd<false, false, 1>), g, b, 0, s, A, B);
+                else hipLaunchKernelGGL((render_bwd<false, false, 2>), g, b, 0, s, A, B);
+            }
+            rc = check_hip(hipGetLastError(), "render_bwd launch");
+            if (rc == AMR_OK && deterministic)
+                hipLaunchKernelGGL(reduce_partials, dim3((kGradLen + 255) / 256), dim3(256), 0, s, partials, kBwdGrid,
+                                   grad);
+        }
         if (rc) break;
-        if (deterministic)
-            hipLaunchKernelGGL(reduce_partials, dim3((kGradLen + 255) / 256), dim3(256), 0, s, partials, kBwdGrid, grad);
         pix_off += (int64_t)cams[c].width * cams[c].height;
     }
     if (rc == AMR_OK) {
@@ -520,6 +585,11 @@ int amr_render_backward_static(const amr_scene *S, const amr_camera *cams, int32
     return backward_launch(S, cams, ncams, P, d_grad_rgba, d_grad_lut, d_grad_light, deterministic, work, stream);
 }
 
+int64_t amr_tape_bytes(int64_t nrays, int64_t tape_cap) {
+    if (nrays < 0 || tape_cap < 0) return 0;
+    return nrays * tape_cap * 3 * (int64_t)sizeof(float);
+}
+
 int64_t amr_ckpt_bytes(int64_t nrays, int32_t ckpt_max) {
     if (nrays < 0 || ckpt_max < 2) return 0;
     return nrays * (int64_t)sizeof(Ckpt) * (1 + (int64_t)ckpt_max);
@@ -549,6 +619,7 @@ int amr_render(const amr_scene *S, const amr_camera *cams, int32_t ncams, const 
             set_error("ckpt_bytes %lld < %lld", (long long)P->ckpt_bytes, (long long)amr_ckpt_bytes(total, P->ckpt_max));
             return AMR_ECAPACITY;
         }
+        if (P->d_tape && P->tape_cap < 0) { set_error("tape_cap must be >= 0"); return AMR_EINVAL; }
     }
     const bool learned = P->d_mlp || P->d_seglog || P->bound_only;
     if (P->bound_only && P->d_mlp) {
@@ -615,9 +686,19 @@ int amr_render(const amr_scene *S, const amr_camera *cams, int32_t ncams, const 
                 if (rec) hipLaunchKernelGGL((render_fwd<false, true, true, -1>), g, b, 0, s, A);
                 else hipLaunchKernelGGL((render_fwd<false, false, true, -1>), g, b, 0, s, A);
             }
-        } else if (rec) {
+        } else if (rec && !(A.ckpt && !A.trace && !A.trace_n && !A.nsamp && !A.stats && !A.touch && !A.touch_meta)) {
             if (A.lighting) hipLaunchKernelGGL((render_fwd<true, true, false, -1>), g, b, 0, s, A);
             else hipLaunchKernelGGL((render_fwd<false, true, false, -1>), g, b, 0, s, A);
+        } else if (A.ckpt) {       // checkpoints (and the tape) only: the adjoint's forward pass
+            if (A.lighting) {
+                if (A.layout == 0) hipLaunchKernelGGL((render_fwd<true, false, false, 0, true>), g, b, 0, s, A);
+                else if (A.layout == 1) hipLaunchKernelGGL((render_fwd<true, false, false, 1, true>), g, b, 0, s, A);
+                else hipLaunchKernelGGL((render_fwd<true, false, false, 2, true>), g, b, 0, s, A);
+            } else {
+                if (A.layout == 0) hipLaunchKernelGGL((render_fwd<false, false, false, 0, true>), g, b, 0, s, A);
+                else if (A.layout == 1) hipLaunchKernelGGL((render_fwd<false, false, false, 1, true>), g, b, 0, s, A);
+                else hipLaunchKernelGGL((render_fwd<false, false, false, 2, true>), g, b, 0, s, A);
+            }
         } else if (A.lighting) {   // the timed variants, one per brick layout
             if (A.layout == 0) hipLaunchKernelGGL((render_fwd<true, false, false, 0>), g, b, 0, s, A);
             else if (A.layout == 1) hipLaunchKernelGGL((render_fwd<true, false, false, 1>), g, b, 0, s, A);

@@ -15,12 +15,12 @@ constexpr int kBwdGrid = 2048;       // adjoint blocks: fixed, so deterministic 
 
 struct CkptHeader {                  // per ray, written at the end of the forward
     float T, C[3];
-    int32_t nsamp, nck, every, pad_;
+    int32_t nsamp, nck, every, ndef;  // ndef: lit samples whose taps left the brick (tape entries)
 };
 struct Ckpt {                        // (t, T, C) at the start of a data segment
     double t;
     float T, C[3];
-    int32_t dseg, sidx;
+    int32_t ndef, sidx;              // tape entries and samples of the ray before this point
 };
 static_assert(sizeof(CkptHeader) == 32 && sizeof(Ckpt) == 32, "checkpoint layout");
 
@@ -59,6 +59,8 @@ struct RenderArgs {
     int64_t ckpt_ray0;               // first ray of this camera in the buffer
     int64_t ckpt_stride;             // bytes per ray
     int32_t ckpt_every, ckpt_max;
+    float *tape;                     // checkpointed lit forward: per ray, the gradient of every
+    int64_t tape_cap;                // sample whose taps left the brick ([rays][tape_cap][3])
     int32_t tiles_x, tiles_y, nblocks;     // 16x16 tiles of four waves (learned kernel)
     int32_t t8x, t8y, sgrid;               // 8x8 one-wave tiles; side of the power-of-two
                                            // grid of 4x4-tile super-tiles covering them
@@ -1084,9 +1086,13 @@ __device__ __forceinline__ void tapq_init(TapQueue &Q, int lane) {
 
 // The calling (active) lanes resolve every queued sample: remaining taps, gradient, shading,
 // contribution; then each owner's deferred colour takes its contributions in queue order.
-template <bool REC, int LAY = -1, bool NEAR = false>
+// TAPE (checkpointed single-camera forward, one 8x8 pixel tile per wave): each resolved gradient
+// is also written to the owner ray's tape at the sample's ordinal among the ray's queued
+// samples, so the adjoint need not resolve the taps.  tape_base: the tape row (ray) of lane 0,
+// whose tile row holds lanes 0..7; lane o's ray is tape_base + (o / 8) * width + o % 8.
+template <bool REC, int LAY = -1, bool NEAR = false, bool TAPE = false>
 __device__ __forceinline__ void tapq_flush(const RenderArgs &A, const float4 *s_lut, TapQueue &Q, int lane,
-                                           Counters &cnt) {
+                                           Counters &cnt, int64_t tape_base = -1) {
     const unsigned long long act = __ballot(1);
     const uint32_t nact = (uint32_t)__popcll(act), rank = (uint32_t)__popcll(act & lanes_below(lane));
     wave_lds_fence();
@@ -1094,7 +1100,7 @@ __device__ __forceinline__ void tapq_flush(const RenderArgs &A, const float4 *s_
     for (uint32_t j = rank; j < n; j += nact) {
         const double xs[3] = {Q.xs[0][j], Q.xs[1][j], Q.xs[2][j]};
         const float F = Q.g[0][j];
-        const uint32_t m = Q.meta[j], pend = Q.pend[j];
+        const uint32_t m = Q.meta[j], pend = Q.pend[j] & 63u;
         const uint32_t cls = (m >> 6) & 0xfffu, safe = m >> 26;
         float Fp[3], Fm[3];
         #pragma unroll
@@ -1122,6 +1128,17 @@ __device__ __forceinline__ void tapq_flush(const RenderArgs &A, const float4 *s_
             const bool pp = (pend >> (2 * a)) & 1u, pm = (pend >> (2 * a + 1)) & 1u;
             gv[a] = (pp || pm) ? lit_gradient_axis(A, F, Fp[a], Fm[a], (ok >> (2 * a)) & 1u, (ok >> (2 * a + 1)) & 1u)
                                : Q.g[1 + a][j];
+        }
+        if (TAPE && tape_base >= 0) {
+            const int o = (int)(m & 63u);
+            const int64_t row = tape_base + (int64_t)(o >> 3) * A.width + (o & 7);
+            const int64_t ord = (int64_t)(Q.pend[j] >> 6);
+            if (ord < A.tape_cap) {
+                float *e = A.tape + 3 * (row * A.tape_cap + ord);
+                e[0] = gv[0];
+                e[1] = gv[1];
+                e[2] = gv[2];
+            }
         }
         float dot, den;
         const float wgt = Q.ta[j] * lit_shade(A, gv, dot, den);
@@ -1169,11 +1186,13 @@ __device__ __forceinline__ void tapq_reserve(const RenderArgs &A, const float4 *
 // the same step, with a slot reserved for each; lanes with want = false queue nothing).
 // Fp/Fm hold the in-brick tap values; an axis with neither tap pending is stored as its
 // finished central difference, else as the in-brick side's value.
+// ord: the sample's ordinal among its ray's queued samples (tape position; 0 without a tape).
 template <bool REC>
 __device__ __forceinline__ void tapq_push(const RenderArgs &A, TapQueue &Q, int lane, bool want, const Ray &R,
                                           const Segment &S, int k, const double *xs_known, float qx, float qy,
                                           float qz, float F, const float Fp[3], const float Fm[3], uint32_t cls,
-                                          uint32_t pend, float Ta, const SampleVals &v, Counters &cnt) {
+                                          uint32_t pend, float Ta, const SampleVals &v, Counters &cnt,
+                                          uint32_t ord = 0) {
     const unsigned long long need = __ballot(want);
     if (!need) return;
     const unsigned long long act = __ballot(1);
@@ -1207,7 +1226,7 @@ __device__ __forceinline__ void tapq_push(const RenderArgs &A, TapQueue &Q, int 
             Q.leaf[j] = S.leaf;
             Q.patch[j] = S.patch;
             Q.meta[j] = (uint32_t)lane | (cls << 6) | ((uint32_t)v.i0 << 18) | (S.safe << 26);
-            Q.pend[j] = pend;
+            Q.pend[j] = pend | (ord << 6);
         } else if (REC) {
             cnt.guard++;
         }
@@ -1235,10 +1254,11 @@ __device__ __forceinline__ uint32_t pending_taps(uint32_t cls) {
 // queued when a tap leaves the brick (trilinear) or needs the tree (nearest cell), else shaded
 // and added to (C0, C1, C2) at once.  Returns the opacity.  All marching lanes call it in the
 // same step, after tapq_reserve.
+// ndef: the ray's count of queued samples (its tape ordinals), advanced when this one is queued.
 template <bool REC, int LAY = -1, bool NEAR = false>
 __device__ __forceinline__ float lit_sample_deferred(const RenderArgs &A, const float4 *s_lut, TapQueue &Q, int lane,
                                                      const Ray &R, const Segment &S, int k, float T, float &C0,
-                                                     float &C1, float &C2, Counters &cnt) {
+                                                     float &C1, float &C2, Counters &cnt, uint32_t *ndef = nullptr) {
     const float kk = (float)k + 0.5f;
     const float qx = S.q0[0] + kk * S.dq[0], qy = S.q0[1] + kk * S.dq[1], qz = S.q0[2] + kk * S.dq[2];
     float F, Fp[3], Fm[3];
@@ -1302,16 +1322,19 @@ __device__ __forceinline__ float lit_sample_deferred(const RenderArgs &A, const 
         C1 += wgt * v.g;
         C2 += wgt * v.b;
     }
-    tapq_push<REC>(A, Q, lane, defer, R, S, k, have_xs ? xs : nullptr, qx, qy, qz, F, Fp, Fm, cls, pend, Ta, v, cnt);
+    const uint32_t ord = ndef ? *ndef : 0u;
+    if (ndef && defer) (*ndef)++;
+    tapq_push<REC>(A, Q, lane, defer, R, S, k, have_xs ? xs : nullptr, qx, qy, qz, F, Fp, Fm, cls, pend, Ta, v, cnt,
+                   ord);
     return v.alpha;
 }
 
 // After the march, by all lanes of the wave: resolve what is queued; returns the lane's
 // deferred colour.
-template <bool REC, int LAY = -1, bool NEAR = false>
+template <bool REC, int LAY = -1, bool NEAR = false, bool TAPE = false>
 __device__ __forceinline__ void tapq_finish(const RenderArgs &A, const float4 *s_lut, TapQueue &Q, int lane,
-                                            Counters &cnt, float &D0, float &D1, float &D2) {
-    if (tq_count(Q)) tapq_flush<REC, LAY, NEAR>(A, s_lut, Q, lane, cnt);
+                                            Counters &cnt, float &D0, float &D1, float &D2, int64_t tape_base = -1) {
+    if (tq_count(Q)) tapq_flush<REC, LAY, NEAR, TAPE>(A, s_lut, Q, lane, cnt, tape_base);
     wave_lds_fence();
     D0 = Q.cd[0][lane];
     D1 = Q.cd[1][lane];
@@ -1437,6 +1460,8 @@ inline int fill_args(const amr_scene *S, const amr_camera *C, const amr_render_p
     A->ckpt_stride = (int64_t)sizeof(Ckpt) * (1 + (int64_t)P->ckpt_max);
     A->ckpt_every = P->ckpt_every > 0 ? P->ckpt_every : 1;
     A->ckpt_max = P->ckpt_max;
+    A->tape = P->d_ckpt && P->d_tape && P->tape_cap > 0 ? P->d_tape : nullptr;
+    A->tape_cap = A->tape ? P->tape_cap : 0;
     return AMR_OK;
 }
 
