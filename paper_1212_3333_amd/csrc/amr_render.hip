@@ -100,11 +100,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void re
             const unsigned long long live = __ballot(alive);
             if (!live) break;
             const unsigned long long samp = __ballot(has);
-            if (tq_count(Q) + (uint32_t)__popcll(samp) > (uint32_t)kTapQ)
-                tapq_flush<REC, LAY, NEAR, kCk>(A, s_lut, Q, lane, cnt, tape_base);
+            if (tapq_full(tq_count(Q), samp)) tapq_flush<REC, LAY, NEAR, kCk>(A, s_lut, Q, lane, cnt, tape_base);
             const bool waiting = alive && !has;
             const unsigned long long wait = __ballot(waiting);
-            if (wait == live || 2 * __popcll(wait) >= __popcll(live)) {
+            if (stepped_fetch(live, wait)) {
                 if (kCk && A.ckpt && tq_count(Q)) tapq_flush<REC, LAY, NEAR, kCk>(A, s_lut, Q, lane, cnt, tape_base);
                 if (waiting) {
                     while (true) {            // next segment with samples, or the end of the ray

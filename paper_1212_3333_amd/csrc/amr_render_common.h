@@ -7,6 +7,7 @@
 #include <cstring>
 
 #include "amr_internal.h"
+#include "amr_tapq_index.h"
 
 namespace amr {
 
@@ -1029,8 +1030,6 @@ __device__ __forceinline__ void eval_sample(const RenderArgs &A, const float4 *s
 // order, which is the owner's sample order); the pixel is their sum.  So a ray's result does
 // not depend on which rays share its wave or on when the queue is resolved.
 
-constexpr int kTapQ = 96;   // queued samples per wave
-
 // A queued sample.  Per axis, g holds the finished central difference when neither tap of
 // the axis is pending, else the value of the tap that is not (or nothing).
 struct TapQueue {
@@ -1052,8 +1051,6 @@ __device__ __forceinline__ TapQueue *tap_queues() {
     __shared__ TapQueue q[NW];
     return q;
 }
-
-__device__ __forceinline__ unsigned long long lanes_below(int lane) { return lane ? (~0ull >> (64 - lane)) : 0ull; }
 
 // Orders this wave's LDS accesses (the queue is written by some lanes and read by others).
 __device__ __forceinline__ void wave_lds_fence() {
@@ -1094,7 +1091,7 @@ template <bool REC, int LAY = -1, bool NEAR = false, bool TAPE = false>
 __device__ __forceinline__ void tapq_flush(const RenderArgs &A, const float4 *s_lut, TapQueue &Q, int lane,
                                            Counters &cnt, int64_t tape_base = -1) {
     const unsigned long long act = __ballot(1);
-    const uint32_t nact = (uint32_t)__popcll(act), rank = (uint32_t)__popcll(act & lanes_below(lane));
+    const uint32_t nact = popc64(act), rank = popc64(act & lanes_below(lane));
     wave_lds_fence();
     const uint32_t n = tq_count(Q);
     for (uint32_t j = rank; j < n; j += nact) {
@@ -1151,15 +1148,14 @@ __device__ __forceinline__ void tapq_flush(const RenderArgs &A, const float4 *s_
     }
     wave_lds_fence();
     // the samples of one step have distinct owners; steps are added one after the other
+    const unsigned long long b0 = tq_bstart(Q, 0), b1 = tq_bstart(Q, 1);
     #pragma unroll
     for (int w = 0; w < 2; w++) {
-        unsigned long long bs = tq_bstart(Q, w);
+        unsigned long long bs = w ? b1 : b0;
         while (bs) {
-            const uint32_t s = 64u * w + (uint32_t)__builtin_ctzll(bs);
+            const uint32_t s = 64u * w + ctz64(bs);
             bs &= bs - 1ull;
-            uint32_t e = n;
-            if (bs) e = 64u * w + (uint32_t)__builtin_ctzll(bs);
-            else if (w == 0 && tq_bstart(Q, 1)) e = 64u + (uint32_t)__builtin_ctzll(tq_bstart(Q, 1));
+            const uint32_t e = tapq_run_end(b0, b1, s, n);
             for (uint32_t j = s + rank; j < e; j += nact) {
                 const uint32_t o = Q.meta[j] & 63u;
                 Q.cd[0][o] += Q.q[0][j];
@@ -1179,7 +1175,7 @@ template <bool REC, int LAY = -1, bool NEAR = false>
 __device__ __forceinline__ void tapq_reserve(const RenderArgs &A, const float4 *s_lut, TapQueue &Q, int lane,
                                              Counters &cnt) {
     const unsigned long long act = __ballot(1);
-    if (tq_count(Q) + (uint32_t)__popcll(act) > (uint32_t)kTapQ) tapq_flush<REC, LAY, NEAR>(A, s_lut, Q, lane, cnt);
+    if (tapq_full(tq_count(Q), act)) tapq_flush<REC, LAY, NEAR>(A, s_lut, Q, lane, cnt);
 }
 
 // Queues a lit sample whose taps in `pend` are left to resolve (all marching lanes call it in
@@ -1199,7 +1195,7 @@ __device__ __forceinline__ void tapq_push(const RenderArgs &A, TapQueue &Q, int 
     const uint32_t c0 = tq_count(Q);
     if (want) {
         if (REC) cnt.split++;
-        const uint32_t j = c0 + (uint32_t)__popcll(need & lanes_below(lane));
+        const uint32_t j = tapq_slot(c0, need, lane);
         if (j < (uint32_t)kTapQ) {          // always: a slot per lane was reserved
             double xs[3];
             if (xs_known) {
@@ -1232,12 +1228,9 @@ __device__ __forceinline__ void tapq_push(const RenderArgs &A, TapQueue &Q, int 
         }
     }
     wave_lds_fence();
-    if (lane == __builtin_ctzll(act) && c0 < (uint32_t)kTapQ) {
-        const uint32_t c1 = min(c0 + (uint32_t)__popcll(need), (uint32_t)kTapQ);
-        unsigned long long b0 = tq_bstart(Q, 0), b1 = tq_bstart(Q, 1);
-        if (c0 < 64u) b0 |= 1ull << c0;
-        else b1 |= 1ull << (c0 - 64u);
-        tq_set(Q, c1, b0, b1);
+    if (lane == (int)ctz64(act) && c0 < (uint32_t)kTapQ) {
+        const TapqStarts b = tapq_mark(tq_bstart(Q, 0), tq_bstart(Q, 1), c0);
+        tq_set(Q, tapq_count_after(c0, need), b.w0, b.w1);
     }
     wave_lds_fence();
 }
