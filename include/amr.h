@@ -238,13 +238,16 @@ typedef struct {
     int64_t ckpt_bytes;
     int32_t ckpt_every;                 /* checkpoint every k-th data segment (>= 1) */
     int32_t ckpt_max;                   /* checkpoints per ray */
-    float *d_tape;                      /* optional with d_ckpt, lit: [nrays][tape_cap][3] fp32 (device),
-                                           the gradient of every sample whose gradient taps left its
-                                           brick, in the ray's order of such samples, written by the
-                                           forward and read by amr_render_backward instead of
-                                           resolving those taps again; rays with more such samples
-                                           than tape_cap are resolved in place by the adjoint */
-    int64_t tape_cap;                   /* tape entries per ray (amr_tape_bytes) */
+    float *d_tape;                      /* optional with d_ckpt, lit: [nrays][tape_cap][4] fp32 (device,
+                                           16-byte aligned), written by the forward: per ray, in
+                                           order, a record (delta, delta log2 e, n as int32 bits, 0)
+                                           at each data segment with n samples, then a record
+                                           (F, g_x, g_y, g_z) per sample: the value and the gradient
+                                           it was shaded with.  amr_render_backward replays the
+                                           checkpoint intervals whose records all fit from the tape
+                                           and evaluates the rest in place; records beyond tape_cap
+                                           are not written */
+    int64_t tape_cap;                   /* records per ray (amr_tape_bytes), at most 2^26 - 1 */
     /* learned segment proposals (NULL = plain traversal).  alpha_max = 1 - exp(-sigma_max L)
        is the analytic bound on a segment's opacity from the leaf's value range; the network
        predicts quantiles (r_lo, r_hi) of alpha / alpha_max, clamped to [0, 1], and
@@ -330,7 +333,7 @@ int64_t amr_wall_clock_khz(void);
 
 /* Checkpoint buffer bytes for nrays rays with ckpt_max checkpoints each. */
 int64_t amr_ckpt_bytes(int64_t nrays, int32_t ckpt_max);
-/* Gradient tape bytes for nrays rays with tape_cap entries each (12 bytes per entry). */
+/* Tape bytes for nrays rays with tape_cap records each (16 bytes per record). */
 int64_t amr_tape_bytes(int64_t nrays, int64_t tape_cap);
 
 /* Workspace bytes (params->d_work) amr_render needs for these cameras and params: with

@@ -483,17 +483,28 @@ def stats_dict(res: RenderOutput) -> dict:
     return {k: int(v[i]) for i, k in enumerate(L.STATS_FIELDS)}
 
 
-# Gradient tape entries per ray for lit checkpointed renders (12 bytes each); rays with more
-# samples whose taps leave the brick are resolved in place by the adjoint.
-TAPE_CAP = 512
+# Tape records per ray for lit checkpointed renders (16 bytes each: one per data segment and
+# one per sample); the adjoint evaluates the intervals of a ray past its cap in place, at several
+# times the cost of reading them.  The default cap is the largest multiple of 8 up to TAPE_CAP
+# whose tape fits in TAPE_MEM_FRACTION of the device's memory.
+TAPE_CAP = 2048
+TAPE_MEM_FRACTION = 0.3
+
+
+def default_tape_cap(nrays: int, device=None, total_memory: int | None = None) -> int:
+    """Tape records per ray for nrays rays on `device` (or a device of total_memory bytes)."""
+    total = total_memory if total_memory is not None else torch.cuda.get_device_properties(
+        torch.device(device)).total_memory
+    cap = int(TAPE_MEM_FRACTION * total) // (16 * max(int(nrays), 1))
+    return max(0, min(TAPE_CAP, cap // 8 * 8))
 
 
 class Checkpoints:
     """Device buffers the checkpointed forward fills and the adjoint reads: per ray a header
-    (final T and C, samples, checkpoint count, tape entries) and up to ckpt_max (t, T, C) records
+    (final T and C, samples, checkpoint count, tape records) and up to ckpt_max (t, T, C) records
     taken at the start of every ckpt_every-th data segment (the rate halves when a ray runs out of
-    slots); with tape_cap > 0 (lit renders) the gradient tape of the samples whose taps left the
-    brick."""
+    slots); with tape_cap > 0 (lit renders) the tape: per ray, a record per data segment (its
+    sample spacing and count) and per sample (value and gradient), tape_cap records at most."""
 
     def __init__(self, nrays: int, device, ckpt_every: int = 4, ckpt_max: int = 16, tape_cap: int = 0):
         lib = load()
@@ -503,6 +514,7 @@ class Checkpoints:
         self.tape_cap = int(tape_cap)
         self.tape = (torch.empty(int(lib.amr_tape_bytes(nrays, tape_cap)) // 4, dtype=torch.float32, device=device)
                      if tape_cap > 0 else None)
+        assert self.tape is None or self.tape.data_ptr() % 16 == 0
 
     def params(self) -> dict:
         p = dict(d_ckpt=self.buf, ckpt_bytes=self.nbytes, ckpt_every=self.every, ckpt_max=self.max)
@@ -511,7 +523,8 @@ class Checkpoints:
         return p
 
     def tape_overflow_rays(self) -> int:
-        """Rays whose tape ran out (their adjoint resolves taps in place); synchronises."""
+        """Rays with more tape records than tape_cap (the adjoint evaluates their later intervals in
+        place); synchronises."""
         if self.tape is None:
             return 0
         hdr = self.buf.view(-1, 32 * (1 + self.max))[:, :32].contiguous().view(torch.int32)[:, 7]
@@ -520,12 +533,12 @@ class Checkpoints:
 
 def render_checkpointed(scene: Scene, cams, lut: torch.Tensor, params: dict, ckpt_every: int = 4,
                         ckpt_max: int = 16, tape_cap: int | None = None, **kw):
-    """Forward render that also records the adjoint's checkpoints (and, lit, the gradient tape of
-    tape_cap entries per ray, default TAPE_CAP; 0 for none). Returns (RenderOutput, Checkpoints)."""
+    """Forward render that also records the adjoint's checkpoints (and, lit, the tape of tape_cap
+    records per ray, default default_tape_cap(); 0 for none). Returns (RenderOutput, Checkpoints)."""
     cam_list = [cams] if isinstance(cams, dict) else list(cams)
     npix = sum(int(c["width"]) * int(c["height"]) for c in cam_list)
     if tape_cap is None:
-        tape_cap = TAPE_CAP if int(params.get("lighting", 0)) == 1 else 0
+        tape_cap = default_tape_cap(npix, scene.pool.device) if int(params.get("lighting", 0)) == 1 else 0
     ck = Checkpoints(npix, scene.pool.device, ckpt_every, ckpt_max, tape_cap)
     out = render(scene, cams, lut, params, **ck.params(), **kw)
     return out, ck

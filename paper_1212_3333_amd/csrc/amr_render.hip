@@ -76,8 +76,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void re
     CkptHeader *ckh = nullptr;
     Ckpt *ck = nullptr;
     int nck = 0, every = A.ckpt_every, dseg = 0;
-    uint32_t ndef = 0;                            // the ray's queued samples so far (tape ordinals)
+    // the tape (lit, with checkpoints): the ray's row and its records so far; tape_base is the row
+    // of the tile's lane 0, which the queue resolution addresses owners from
+    uint32_t tpos = 0;
     const int64_t tape_base = (kCk && LIT && A.tape) ? A.ckpt_ray0 + (int64_t)(row * 8) * A.width + col * 8 : -1;
+    float4 *trow = (kCk && LIT && A.tape && valid) ? A.tape + (A.ckpt_ray0 + ray) * A.tape_cap : nullptr;
     if (kCk && A.ckpt && valid) {
         ckh = reinterpret_cast<CkptHeader *>(A.ckpt + (A.ckpt_ray0 + ray) * A.ckpt_stride);
         ck = reinterpret_cast<Ckpt *>(ckh + 1);
@@ -132,7 +135,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void re
                                         c.C[0] = C0 + Q.cd[0][lane];
                                         c.C[1] = C1 + Q.cd[1][lane];
                                         c.C[2] = C2 + Q.cd[2][lane];
-                                        c.ndef = (int32_t)ndef;
+                                        c.rec = (int32_t)tpos;
                                         c.sidx = nsamp_total;
                                         ck[nck++] = c;
                                     }
@@ -141,6 +144,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void re
                             }
                             setup_segment<LIT, LAY>(A, R, L, leaf, tcur, tb, S);
                             n = S.n;
+                            if (kCk && trow && n > 0) {
+                                if (tpos < (uint32_t)A.tape_cap) trow[tpos] = tape_segment(S.delta, S.dl, n);
+                                tpos++;
+                            }
                         }
                         if (REC && A.trace) {
                             if (nseg < A.trace_cap) {
@@ -173,7 +180,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void re
             }
             if (has) {
                 const float alpha = lit_sample_deferred<REC, LAY, NEAR>(A, s_lut, Q, lane, R, S, k, T, C0, C1, C2, cnt,
-                                                                       kCk ? &ndef : nullptr);
+                                                                       trow, &tpos);
                 T *= 1.f - alpha;
                 nsamp_total++;
                 k++;
@@ -218,7 +225,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void re
                             c.C[0] = C0;
                             c.C[1] = C1;
                             c.C[2] = C2;
-                            c.ndef = 0;
+                            c.rec = 0;
                             c.sidx = nsamp_total;
                             ck[nck++] = c;
                         }
@@ -275,7 +282,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void re
             hd.nsamp = nsamp_total;
             hd.nck = nck;
             hd.every = every;
-            hd.ndef = (int32_t)ndef;
+            hd.nrec = (int32_t)tpos;
             *ckh = hd;
         }
     }
@@ -286,35 +293,172 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void re
 }
 
 // ------------------------------------------------------------------------------------------
-// Adjoint kernel: one work item = one (ray, checkpoint interval).  Given (T, C) at the
+// Adjoint kernels: one work item = one (ray, checkpoint interval).  Given (T, C) at the
 // interval's start and the ray's final (T_N, C_N), every sample's derivatives are local:
 //   dL/dsigma_k = delta_k [ gC . (T_{k+1} e_k - (C_N - C_<=k)) + gA T_N ],
 //   dL/drgb_k   = gC T_k alpha_k shade_k,   dL/dshade_k = T_k alpha_k (gC . rgb_k),
 // with e_k = shade_k rgb_k and C_<=k the colour accumulated up to and including sample k.
 // LUT gradients are accumulated per wave in LDS and combined per block in a fixed order.
+// The lit intervals whose tape records all fit are replayed from the tape (render_bwd_tape);
+// the others walk the tree and evaluate their samples again (render_bwd).
 // ------------------------------------------------------------------------------------------
 
-// TAPE: lit samples whose taps left the brick take their gradient from the forward's tape, and
-// only rays whose tape holds all of them are processed; otherwise (TAPE = false) every sample is
-// evaluated in place, for every ray when there is no tape, else for the rays whose tape ran out.
-// LAY: the brick layout fixed at compile time (-1: read at run time).
-template <bool LIT, bool TAPE, int LAY>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(LIT ? 3 : 4))) void render_bwd(RenderArgs A, BwdArgs B) {
-    __shared__ float4 s_lut[256];
-    __shared__ float s_acc[4][kGradLen];      // one accumulator per wave
+// An interval's pixel gradient, the ray's final transmittance and colour, and (T, C) at the
+// current sample.
+struct AdjRay {
+    float4 g4;
+    float TN, CN0, CN1, CN2;
+    float T, C0, C1, C2;
+};
+
+// A lane's sums of the shading-parameter gradients: light direction, k_a, k_d.
+struct AdjSums {
+    float gl0 = 0.f, gl1 = 0.f, gl2 = 0.f, gka = 0.f, gkd = 0.f;
+};
+
+// LUT-gradient terms x of consecutive samples in one LUT interval [b, b + 1], summed in
+// registers (s = sum x, sf = sum f x with f the sample's position in the interval) and added
+// to the wave's LDS accumulator when the interval changes: entry b takes s - sf, b + 1 takes
+// sf.  Samples along a ray often stay in one interval, so this saves most LDS atomics, which
+// collide when the lanes of a wave hit the same entries.  b < 0: nothing held.
+struct LutRun {
+    int b = -1;
+    float s[4] = {0.f, 0.f, 0.f, 0.f}, sf[4] = {0.f, 0.f, 0.f, 0.f};
+};
+
+__device__ __forceinline__ void lut_run_flush(float *acc, const LutRun &r) {
+    if (r.b < 0) return;
+    float *a0 = acc + 4 * r.b;
+    #pragma unroll
+    for (int c = 0; c < 4; c++) {
+        atomicAdd(a0 + c, r.s[c] - r.sf[c]);
+        atomicAdd(a0 + 4 + c, r.sf[c]);
+    }
+}
+
+// One sample's adjoint: advances (T, C) past the sample and accumulates its LUT and
+// shading-parameter gradients.  RUN: LUT terms through the register run (else straight to LDS).
+template <bool LIT, bool RUN>
+__device__ __forceinline__ void adjoint_sample(const RenderArgs &A, const SampleVals &v, float dlt, AdjRay &a,
+                                               float *acc, LutRun &run, AdjSums &gs) {
+    const float ta = a.T * v.alpha;
+    const float e0 = v.shade * v.r, e1 = v.shade * v.g, e2 = v.shade * v.b;
+    a.C0 += ta * e0;
+    a.C1 += ta * e1;
+    a.C2 += ta * e2;
+    const float Tn = a.T * (1.f - v.alpha);
+    const float dsig = dlt * (a.g4.x * (Tn * e0 - (a.CN0 - a.C0)) + a.g4.y * (Tn * e1 - (a.CN1 - a.C1)) +
+                              a.g4.z * (Tn * e2 - (a.CN2 - a.C2)) + a.g4.w * a.TN);
+    const float wr = ta * v.shade;
+    const float x[4] = {a.g4.x * wr, a.g4.y * wr, a.g4.z * wr, dsig};
+    if (RUN) {
+        if (v.i0 != run.b) {
+            lut_run_flush(acc, run);
+            run = LutRun();
+            run.b = v.i0;
+        }
+        #pragma unroll
+        for (int c = 0; c < 4; c++) {
+            run.s[c] += x[c];
+            run.sf[c] += v.f * x[c];
+        }
+    } else {
+        const float w1 = v.f, w0 = 1.f - v.f;
+        float *a0 = acc + 4 * v.i0;
+        #pragma unroll
+        for (int c = 0; c < 4; c++) {
+            atomicAdd(a0 + c, w0 * x[c]);
+            atomicAdd(a0 + 4 + c, w1 * x[c]);
+        }
+    }
+    if (LIT) {
+        const float dshade = ta * (a.g4.x * v.r + a.g4.y * v.g + a.g4.z * v.b);
+        gs.gka += dshade;
+        if (v.den > 0.f) {
+            const float sg = v.dot > 0.f ? 1.f : (v.dot < 0.f ? -1.f : 0.f);
+            const float q = dshade / v.den;
+            const float cf = q * A.k_d * sg * A.inv_lnorm;
+            gs.gl0 += cf * (v.gv[0] - v.dot * A.lhat[0]);
+            gs.gl1 += cf * (v.gv[1] - v.dot * A.lhat[1]);
+            gs.gl2 += cf * (v.gv[2] - v.dot * A.lhat[2]);
+            gs.gkd += q * fabsf(v.dot);
+        }
+    }
+    a.T = Tn;
+}
+
+// Start of an adjoint block (256 threads, four waves): the LUT and the wave accumulators in LDS.
+__device__ __forceinline__ void adjoint_block_begin(const RenderArgs &A, float4 *s_lut, float (*s_acc)[kGradLen]) {
     s_lut[threadIdx.x] = A.lut[threadIdx.x];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     for (int i = lane; i < kGradLen; i += 64) s_acc[wave][i] = 0.f;
     __syncthreads();
-    float *acc = s_acc[wave];
-    float gl0 = 0.f, gl1 = 0.f, gl2 = 0.f, gka = 0.f, gkd = 0.f;
+}
+
+// End of an adjoint block: the shading-parameter sums reduced over each wave, the four wave
+// accumulators combined in a fixed order, then written as the block's partial sum
+// (deterministic mode) or added to the result.
+template <bool LIT>
+__device__ __forceinline__ void adjoint_block_end(const BwdArgs &B, float (*s_acc)[kGradLen], AdjSums gs) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (LIT) {
+        gs.gl0 = wave_sumf(gs.gl0);
+        gs.gl1 = wave_sumf(gs.gl1);
+        gs.gl2 = wave_sumf(gs.gl2);
+        gs.gka = wave_sumf(gs.gka);
+        gs.gkd = wave_sumf(gs.gkd);
+        if (lane == 0) {
+            s_acc[wave][1024] += gs.gl0;
+            s_acc[wave][1025] += gs.gl1;
+            s_acc[wave][1026] += gs.gl2;
+            s_acc[wave][1027] += gs.gka;
+            s_acc[wave][1028] += gs.gkd;
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kGradLen; i += blockDim.x) {
+        float v = ((s_acc[0][i] + s_acc[1][i]) + s_acc[2][i]) + s_acc[3][i];
+        if (B.partials) B.partials[(int64_t)blockIdx.x * kGradLen + i] = v;
+        else if (v != 0.f) atomicAdd(&B.grad[i], v);
+    }
+}
+
+// The tape records of an interval: [rec0, end) with end the next checkpoint's position or the
+// ray's total; the interval is on the tape when all of them were written.
+__device__ __forceinline__ int interval_records_end(const CkptHeader &hd, const Ckpt *ck, int interval, int nck) {
+    return interval + 1 < nck ? ck[interval + 1].rec : hd.nrec;
+}
+
+// In place: every sample of the interval is evaluated again (tree walk from the checkpoint,
+// stencil, tap resolution).  Serves the unlit adjoint, lit renders without a tape, and the lit
+// intervals whose tape records did not all fit.  Work items run interval by interval (the
+// lanes of a wave take neighbouring rays at one interval) when every interval is served here,
+// and ray by ray (consecutive lanes take one ray's intervals) when only the tape's leftovers
+// are: those are the late intervals of the longest rays, which would otherwise queue up on
+// few threads.
+// LAY: the brick layout fixed at compile time (-1: read at run time).
+template <bool LIT, int LAY>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(LIT ? 3 : 4))) void render_bwd(RenderArgs A, BwdArgs B) {
+    __shared__ float4 s_lut[256];
+    __shared__ float s_acc[4][kGradLen];      // one accumulator per wave
+    adjoint_block_begin(A, s_lut, s_acc);
+    float *acc = s_acc[threadIdx.x >> 6];
+    AdjSums gs;
+    LutRun run;
     Counters cnt;
     const int64_t nrays = (int64_t)A.width * A.height;
     const int64_t nitems = nrays * A.ckpt_max;
     for (int64_t item = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; item < nitems;
          item += (int64_t)gridDim.x * blockDim.x) {
-        const int interval = (int)(item / nrays);
-        const int64_t ray = item - (int64_t)interval * nrays;
+        int interval;
+        int64_t ray;
+        if (B.ray_major) {
+            ray = item / A.ckpt_max;
+            interval = (int)(item - ray * A.ckpt_max);
+        } else {
+            interval = (int)(item / nrays);
+            ray = item - (int64_t)interval * nrays;
+        }
         const CkptHeader *ckh = reinterpret_cast<const CkptHeader *>(A.ckpt + (A.ckpt_ray0 + ray) * A.ckpt_stride);
         const CkptHeader hd = *ckh;
         const int nck = min(hd.nck, A.ckpt_max);
@@ -322,28 +466,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(LIT ? 3 : 4
         const Ckpt *ck = reinterpret_cast<const Ckpt *>(ckh + 1);
         const Ckpt c0 = ck[interval];
         const int s_end = interval + 1 < nck ? ck[interval + 1].sidx : hd.nsamp;
-        // the interval's tape entries are [c0.ndef, end): on the tape if all of them fit
-        const int d_end = interval + 1 < nck ? ck[interval + 1].ndef : hd.ndef;
-        const bool taped = LIT && A.tape && (int64_t)d_end <= A.tape_cap;
-        if (TAPE != taped) continue;      // the other launch serves this interval
+        if (LIT && A.tape && (int64_t)interval_records_end(hd, ck, interval, nck) <= A.tape_cap) continue;   // on the tape
         const int pi = (int)(ray % A.width), pj = (int)(ray / A.width);
         Ray R;
         if (!setup_ray(A, pi, pj, R)) continue;
-        const float4 g4 = reinterpret_cast<const float4 *>(B.grad_rgba)[ray];
-        const float TN = hd.T, CN0 = hd.C[0], CN1 = hd.C[1], CN2 = hd.C[2];
-        float T = c0.T, C0 = c0.C[0], C1 = c0.C[1], C2 = c0.C[2];
+        AdjRay a;
+        a.g4 = reinterpret_cast<const float4 *>(B.grad_rgba)[ray];
+        a.TN = hd.T;
+        a.CN0 = hd.C[0];
+        a.CN1 = hd.C[1];
+        a.CN2 = hd.C[2];
+        a.T = c0.T;
+        a.C0 = c0.C[0];
+        a.C1 = c0.C[1];
+        a.C2 = c0.C[2];
         int s = c0.sidx;
         double tcur = c0.t;
-        const float *tape = TAPE ? A.tape + 3 * (A.ckpt_ray0 + ray) * A.tape_cap : nullptr;
-        int64_t ord = TAPE ? c0.ndef : 0;
-        // the next tape entry, loaded one entry ahead so its latency overlaps the samples before
-        // the sample that uses it
-        float n0 = 0.f, n1 = 0.f, n2 = 0.f;
-        if (TAPE && ord < d_end) {
-            n0 = tape[3 * ord];
-            n1 = tape[3 * ord + 1];
-            n2 = tape[3 * ord + 2];
-        }
         while (s < s_end && tcur < R.t1) {
             double tb = R.t1;
             int leaf = descend(A, R, tcur, tb);
@@ -355,90 +493,96 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(LIT ? 3 : 4
                 const float dlt = (float)S.delta;
                 for (int k = 0; k < S.n && s < s_end; k++, s++) {
                     SampleVals v;
-                    if (TAPE) {
-                        // the forward's decision: a sample with a tap beyond the brick was queued,
-                        // and the tape holds the gradient its resolution found
-                        const float kk = (float)k + 0.5f;
-                        const float qx = S.q0[0] + kk * S.dq[0], qy = S.q0[1] + kk * S.dq[1], qz = S.q0[2] + kk * S.dq[2];
-                        float F, Fp[3], Fm[3];
-                        const uint32_t cls = lit_stencil<false, LAY>(A, S, qx, qy, qz, F, Fp, Fm);
-                        if (pending_taps(cls)) {
-                            v.gv[0] = n0;
-                            v.gv[1] = n1;
-                            v.gv[2] = n2;
-                            if (++ord < d_end) {
-                                n0 = tape[3 * ord];
-                                n1 = tape[3 * ord + 1];
-                                n2 = tape[3 * ord + 2];
-                            }
-                        } else {
-                            lit_gradient(A, F, Fp, Fm, 0x3fu, v.gv);
-                        }
-                        lut_classify(A, s_lut, F, S.dl, v);
-                        v.shade = lit_shade(A, v.gv, v.dot, v.den);
-                    } else {
-                        eval_sample<LIT, false, false, LAY>(A, s_lut, R, S, k, v, cnt);
-                    }
-                    const float ta = T * v.alpha;
-                    const float e0 = v.shade * v.r, e1 = v.shade * v.g, e2 = v.shade * v.b;
-                    C0 += ta * e0;
-                    C1 += ta * e1;
-                    C2 += ta * e2;
-                    const float Tn = T * (1.f - v.alpha);
-                    const float dsig = dlt * (g4.x * (Tn * e0 - (CN0 - C0)) + g4.y * (Tn * e1 - (CN1 - C1)) +
-                                              g4.z * (Tn * e2 - (CN2 - C2)) + g4.w * TN);
-                    const float wr = ta * v.shade;
-                    const float w1 = v.f, w0 = 1.f - v.f;
-                    float *a0 = acc + 4 * v.i0;
-                    atomicAdd(a0 + 0, w0 * g4.x * wr);
-                    atomicAdd(a0 + 1, w0 * g4.y * wr);
-                    atomicAdd(a0 + 2, w0 * g4.z * wr);
-                    atomicAdd(a0 + 3, w0 * dsig);
-                    atomicAdd(a0 + 4, w1 * g4.x * wr);
-                    atomicAdd(a0 + 5, w1 * g4.y * wr);
-                    atomicAdd(a0 + 6, w1 * g4.z * wr);
-                    atomicAdd(a0 + 7, w1 * dsig);
-                    if (LIT) {
-                        const float dshade = ta * (g4.x * v.r + g4.y * v.g + g4.z * v.b);
-                        gka += dshade;
-                        if (v.den > 0.f) {
-                            const float sg = v.dot > 0.f ? 1.f : (v.dot < 0.f ? -1.f : 0.f);
-                            const float cf = dshade * A.k_d * sg / v.den * A.inv_lnorm;
-                            gl0 += cf * (v.gv[0] - v.dot * A.lhat[0]);
-                            gl1 += cf * (v.gv[1] - v.dot * A.lhat[1]);
-                            gl2 += cf * (v.gv[2] - v.dot * A.lhat[2]);
-                            gkd += dshade * fabsf(v.dot) / v.den;
-                        }
-                    }
-                    T = Tn;
+                    eval_sample<LIT, false, false, LAY>(A, s_lut, R, S, k, v, cnt);
+                    adjoint_sample<LIT, false>(A, v, dlt, a, acc, run, gs);
                 }
             }
             if (tb <= tcur) tb = nextafter(tcur, INFINITY);
             tcur = tb;
         }
     }
-    if (LIT) {
-        // light gradients: reduce over the wave, one LDS update per wave
-        gl0 = wave_sumf(gl0);
-        gl1 = wave_sumf(gl1);
-        gl2 = wave_sumf(gl2);
-        gka = wave_sumf(gka);
-        gkd = wave_sumf(gkd);
-        if (lane == 0) {
-            acc[1024] += gl0;
-            acc[1025] += gl1;
-            acc[1026] += gl2;
-            acc[1027] += gka;
-            acc[1028] += gkd;
+    adjoint_block_end<LIT>(B, s_acc, gs);
+}
+
+// From the tape: the lit intervals whose records all fit are replayed from their segment and
+// sample records alone (no tree walk, no brick reads).  Each lane reads its ray's records a
+// group of kTapeGroup at a time (the group's records share cache lines, aligned in the tape):
+// the group arrives with one fetch of its lines, where reading a record at a time would have
+// the lines of the other lanes' streams evict them between reads.
+constexpr int kTapeGroup = 8;
+
+__global__ __launch_bounds__(256) void render_bwd_tape(RenderArgs A, BwdArgs B) {
+    __shared__ float4 s_lut[256];
+    __shared__ float s_acc[4][kGradLen];
+    adjoint_block_begin(A, s_lut, s_acc);
+    float *acc = s_acc[threadIdx.x >> 6];
+    AdjSums gs;
+    LutRun run;
+    const int64_t nrays = (int64_t)A.width * A.height;
+    const int64_t nitems = nrays * A.ckpt_max;
+    const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int64_t item = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; item < nitems;
+         item += (int64_t)gridDim.x * blockDim.x) {
+        const int interval = (int)(item / nrays);
+        const int64_t ray = item - (int64_t)interval * nrays;
+        const CkptHeader *ckh = reinterpret_cast<const CkptHeader *>(A.ckpt + (A.ckpt_ray0 + ray) * A.ckpt_stride);
+        const CkptHeader hd = *ckh;
+        const int nck = min(hd.nck, A.ckpt_max);
+        if (interval >= nck) continue;
+        const Ckpt *ck = reinterpret_cast<const Ckpt *>(ckh + 1);
+        const Ckpt c0 = ck[interval];
+        const int s_end = interval + 1 < nck ? ck[interval + 1].sidx : hd.nsamp;
+        const int r_end = interval_records_end(hd, ck, interval, nck);
+        if ((int64_t)r_end > A.tape_cap || c0.rec < 0) continue;      // the in-place kernel's
+        const int64_t row0 = (A.ckpt_ray0 + ray) * A.tape_cap;    // the ray's first record
+        AdjRay a;
+        a.g4 = reinterpret_cast<const float4 *>(B.grad_rgba)[ray];
+        a.TN = hd.T;
+        a.CN0 = hd.C[0];
+        a.CN1 = hd.C[1];
+        a.CN2 = hd.C[2];
+        a.T = c0.T;
+        a.C0 = c0.C[0];
+        a.C1 = c0.C[1];
+        a.C2 = c0.C[2];
+        // absolute record indices: the interval's records are [p, e)
+        int64_t p = row0 + c0.rec;
+        const int64_t e = row0 + r_end;
+        int s = c0.sidx, left = 0;        // left: samples of the current segment still to come
+        float dlt = 0.f, dl = 0.f;
+        bool more = s < s_end && p < e;
+        while (more) {
+            const int64_t g0 = p & ~(int64_t)(kTapeGroup - 1);
+            float4 buf[kTapeGroup];
+            #pragma unroll
+            for (int j = 0; j < kTapeGroup; j++) buf[j] = (g0 + j >= p && g0 + j < e) ? A.tape[g0 + j] : zero;
+            #pragma unroll
+            for (int j = 0; j < kTapeGroup; j++) {
+                if (more && g0 + j == p) {
+                    const float4 r = buf[j];
+                    p++;
+                    if (left <= 0) {              // a segment record
+                        left = __float_as_int(r.z);
+                        dlt = r.x;
+                        dl = r.y;
+                    } else {                      // a sample record
+                        SampleVals v;
+                        v.gv[0] = r.y;
+                        v.gv[1] = r.z;
+                        v.gv[2] = r.w;
+                        lut_classify(A, s_lut, r.x, dl, v);
+                        v.shade = lit_shade(A, v.gv, v.dot, v.den);
+                        adjoint_sample<true, true>(A, v, dlt, a, acc, run, gs);
+                        left--;
+                        s++;
+                    }
+                    more = s < s_end && p < e;
+                }
+            }
         }
     }
-    __syncthreads();
-    // combine the four wave accumulators in a fixed order, then flush
-    for (int i = threadIdx.x; i < kGradLen; i += blockDim.x) {
-        float v = ((s_acc[0][i] + s_acc[1][i]) + s_acc[2][i]) + s_acc[3][i];
-        if (B.partials) B.partials[(int64_t)blockIdx.x * kGradLen + i] = v;
-        else if (v != 0.f) atomicAdd(&B.grad[i], v);
-    }
+    lut_run_flush(acc, run);
+    adjoint_block_end<true>(B, s_acc, gs);
 }
 
 // Fixed-order sum of per-block partials (deterministic adjoint).
@@ -486,6 +630,10 @@ int backward_launch(const amr_scene *S, const amr_camera *cams, int32_t ncams, c
         set_error("checkpoint buffer too small");
         return AMR_ECAPACITY;
     }
+    if (P->d_tape && (P->tape_cap < 0 || P->tape_cap > kTapeCapMax || (reinterpret_cast<uintptr_t>(P->d_tape) & 15u))) {
+        set_error("d_tape needs 16-byte alignment and tape_cap in [0, %lld]", (long long)kTapeCapMax);
+        return AMR_EINVAL;
+    }
     hipStream_t s = (hipStream_t)stream;
     float *grad = work;
     float *partials = deterministic ? work + kGradLen : nullptr;
@@ -501,21 +649,22 @@ int backward_launch(const amr_scene *S, const amr_camera *cams, int32_t ncams, c
         B.grad_rgba = d_grad_rgba + 4 * pix_off;
         B.grad = grad;
         B.partials = partials;
-        // lit with a tape: the rays the tape covers at the layout's addressing, then the others in
-        // place; otherwise one launch
+        // lit with a tape: the intervals the tape holds, then the others in place; otherwise one
+        // launch
         const int nl = A.lighting && A.tape ? 2 : 1;
         for (int l = 0; l < nl && rc == AMR_OK; l++) {
+            B.ray_major = nl == 2 && l == 1;
             const dim3 g(kBwdGrid), b(256);
             if (A.lighting && A.tape && l == 0) {
-                if (A.layout == 0) hipLaunchKernelGGL((render_bwd<true, true, 0>), g, b, 0, s, A, B);
-                else if (A.layout == 1) hipLaunchKernelGGL((render_bwd<true, true, 1>), g, b, 0, s, A, B);
-                else hipLaunchKernelGGL((render_bwd<true, true, 2>), g, b, 0, s, A, B);
+                hipLaunchKernelGGL(render_bwd_tape, g, b, 0, s, A, B);
             } else if (A.lighting) {
-                hipLaunchKernelGGL((render_bwd<true, false, -1>), g, b, 0, s, A, B);
+                if (A.layout == 0) hipLaunchKernelGGL((render_bwd<true, 0>), g, b, 0, s, A, B);
+                else if (A.layout == 1) hipLaunchKernelGGL((render_bwd<true, 1>), g, b, 0, s, A, B);
+                else hipLaunchKernelGGL((render_bwd<true, 2>), g, b, 0, s, A, B);
             } else {
-                if (A.layout == 0) hipLaunchKernelGGL((render_bwd<false, false, 0>), g, b, 0, s, A, B);
-                else if (A.layout == 1) hipLaunchKernelGGL((render_bwd<false, false, 1>), g, b, 0, s, A, B);
-                else hipLaunchKernelGGL((render_bwd<false, false, 2>), g, b, 0, s, A, B);
+                if (A.layout == 0) hipLaunchKernelGGL((render_bwd<false, 0>), g, b, 0, s, A, B);
+                else if (A.layout == 1) hipLaunchKernelGGL((render_bwd<false, 1>), g, b, 0, s, A, B);
+                else hipLaunchKernelGGL((render_bwd<false, 2>), g, b, 0, s, A, B);
             }
             rc = check_hip(hipGetLastError(), "render_bwd launch");
             if (rc == AMR_OK && deterministic)
@@ -586,7 +735,7 @@ int amr_render_backward_static(const amr_scene *S, const amr_camera *cams, int32
 
 int64_t amr_tape_bytes(int64_t nrays, int64_t tape_cap) {
     if (nrays < 0 || tape_cap < 0) return 0;
-    return nrays * tape_cap * 3 * (int64_t)sizeof(float);
+    return nrays * tape_cap * (int64_t)sizeof(float4);
 }
 
 int64_t amr_ckpt_bytes(int64_t nrays, int32_t ckpt_max) {
@@ -618,7 +767,14 @@ int amr_render(const amr_scene *S, const amr_camera *cams, int32_t ncams, const 
             set_error("ckpt_bytes %lld < %lld", (long long)P->ckpt_bytes, (long long)amr_ckpt_bytes(total, P->ckpt_max));
             return AMR_ECAPACITY;
         }
-        if (P->d_tape && P->tape_cap < 0) { set_error("tape_cap must be >= 0"); return AMR_EINVAL; }
+        if (P->d_tape && (P->tape_cap < 0 || P->tape_cap > kTapeCapMax)) {
+            set_error("tape_cap must lie in [0, %lld]", (long long)kTapeCapMax);
+            return AMR_EINVAL;
+        }
+        if (P->d_tape && (reinterpret_cast<uintptr_t>(P->d_tape) & 15u)) {
+            set_error("d_tape must be 16-byte aligned");
+            return AMR_EINVAL;
+        }
     }
     const bool learned = P->d_mlp || P->d_seglog || P->bound_only;
     if (P->bound_only && P->d_mlp) {

@@ -16,14 +16,24 @@ constexpr int kBwdGrid = 2048;       // adjoint blocks: fixed, so deterministic 
 
 struct CkptHeader {                  // per ray, written at the end of the forward
     float T, C[3];
-    int32_t nsamp, nck, every, ndef;  // ndef: lit samples whose taps left the brick (tape entries)
+    int32_t nsamp, nck, every, nrec;  // nrec: the ray's tape records (those beyond the cap unwritten)
 };
 struct Ckpt {                        // (t, T, C) at the start of a data segment
     double t;
     float T, C[3];
-    int32_t ndef, sidx;              // tape entries and samples of the ray before this point
+    int32_t rec, sidx;               // tape records and samples of the ray before this point
 };
 static_assert(sizeof(CkptHeader) == 32 && sizeof(Ckpt) == 32, "checkpoint layout");
+
+// The tape of the checkpointed lit forward: per ray, in the ray's order, one 16-byte record
+// at the start of each data segment, (delta, delta log2(e), n as int bits, 0), then one per
+// sample, (F, g_x, g_y, g_z): the sampled value and the central-difference gradient the
+// forward shaded with.  The adjoint replays an interval from these records alone.  Records
+// at or beyond tape_cap are not written; the header counts them all.
+constexpr int64_t kTapeCapMax = (1 << 26) - 1;   // tape positions travel in 26 bits of the queue
+__device__ __forceinline__ float4 tape_segment(double delta, float dl, int n) {
+    return make_float4((float)delta, dl, __int_as_float(n), 0.f);
+}
 
 struct RenderArgs {
     const float *pool;
@@ -60,8 +70,8 @@ struct RenderArgs {
     int64_t ckpt_ray0;               // first ray of this camera in the buffer
     int64_t ckpt_stride;             // bytes per ray
     int32_t ckpt_every, ckpt_max;
-    float *tape;                     // checkpointed lit forward: per ray, the gradient of every
-    int64_t tape_cap;                // sample whose taps left the brick ([rays][tape_cap][3])
+    float4 *tape;                    // checkpointed lit forward: per ray, a record per data
+    int64_t tape_cap;                // segment and per sample ([rays][tape_cap]; see TapeSeg)
     int32_t tiles_x, tiles_y, nblocks;     // 16x16 tiles of four waves (learned kernel)
     int32_t t8x, t8y, sgrid;               // 8x8 one-wave tiles; side of the power-of-two
                                            // grid of 4x4-tile super-tiles covering them
@@ -71,6 +81,7 @@ struct BwdArgs {
     const float *grad_rgba;
     float *grad;                     // kGradLen accumulator
     float *partials;                 // deterministic: [grid][kGradLen]
+    int32_t ray_major;               // work items numbered ray by ray (else interval by interval)
 };
 
 struct Counters {   // per lane (32-bit); summed over the wave in 64 bits when flushed
@@ -1083,10 +1094,10 @@ __device__ __forceinline__ void tapq_init(TapQueue &Q, int lane) {
 
 // The calling (active) lanes resolve every queued sample: remaining taps, gradient, shading,
 // contribution; then each owner's deferred colour takes its contributions in queue order.
-// TAPE (checkpointed single-camera forward, one 8x8 pixel tile per wave): each resolved gradient
-// is also written to the owner ray's tape at the sample's ordinal among the ray's queued
-// samples, so the adjoint need not resolve the taps.  tape_base: the tape row (ray) of lane 0,
-// whose tile row holds lanes 0..7; lane o's ray is tape_base + (o / 8) * width + o % 8.
+// TAPE (checkpointed single-camera forward, one 8x8 pixel tile per wave): each resolved sample's
+// record (value, gradient) is also written to the owner ray's tape at the sample's position, so
+// the adjoint need not evaluate it again.  tape_base: the tape row (ray) of lane 0, whose tile
+// row holds lanes 0..7; lane o's ray is tape_base + (o / 8) * width + o % 8.
 template <bool REC, int LAY = -1, bool NEAR = false, bool TAPE = false>
 __device__ __forceinline__ void tapq_flush(const RenderArgs &A, const float4 *s_lut, TapQueue &Q, int lane,
                                            Counters &cnt, int64_t tape_base = -1) {
@@ -1129,13 +1140,8 @@ __device__ __forceinline__ void tapq_flush(const RenderArgs &A, const float4 *s_
         if (TAPE && tape_base >= 0) {
             const int o = (int)(m & 63u);
             const int64_t row = tape_base + (int64_t)(o >> 3) * A.width + (o & 7);
-            const int64_t ord = (int64_t)(Q.pend[j] >> 6);
-            if (ord < A.tape_cap) {
-                float *e = A.tape + 3 * (row * A.tape_cap + ord);
-                e[0] = gv[0];
-                e[1] = gv[1];
-                e[2] = gv[2];
-            }
+            const int64_t pos = (int64_t)(Q.pend[j] >> 6);
+            if (pos < A.tape_cap) A.tape[row * A.tape_cap + pos] = make_float4(F, gv[0], gv[1], gv[2]);
         }
         float dot, den;
         const float wgt = Q.ta[j] * lit_shade(A, gv, dot, den);
@@ -1182,7 +1188,8 @@ __device__ __forceinline__ void tapq_reserve(const RenderArgs &A, const float4 *
 // the same step, with a slot reserved for each; lanes with want = false queue nothing).
 // Fp/Fm hold the in-brick tap values; an axis with neither tap pending is stored as its
 // finished central difference, else as the in-brick side's value.
-// ord: the sample's ordinal among its ray's queued samples (tape position; 0 without a tape).
+// ord: the sample's tape position (below 2^26; tape_cap, which is never written, when beyond it;
+// 0 without a tape).
 template <bool REC>
 __device__ __forceinline__ void tapq_push(const RenderArgs &A, TapQueue &Q, int lane, bool want, const Ray &R,
                                           const Segment &S, int k, const double *xs_known, float qx, float qy,
@@ -1247,11 +1254,13 @@ __device__ __forceinline__ uint32_t pending_taps(uint32_t cls) {
 // queued when a tap leaves the brick (trilinear) or needs the tree (nearest cell), else shaded
 // and added to (C0, C1, C2) at once.  Returns the opacity.  All marching lanes call it in the
 // same step, after tapq_reserve.
-// ndef: the ray's count of queued samples (its tape ordinals), advanced when this one is queued.
+// trow, tpos (checkpointed forward with a tape): the lane's tape row and the sample's position in
+// it, advanced here; a sample shaded at once writes its record now, a queued one when resolved.
 template <bool REC, int LAY = -1, bool NEAR = false>
 __device__ __forceinline__ float lit_sample_deferred(const RenderArgs &A, const float4 *s_lut, TapQueue &Q, int lane,
                                                      const Ray &R, const Segment &S, int k, float T, float &C0,
-                                                     float &C1, float &C2, Counters &cnt, uint32_t *ndef = nullptr) {
+                                                     float &C1, float &C2, Counters &cnt, float4 *trow = nullptr,
+                                                     uint32_t *tpos = nullptr) {
     const float kk = (float)k + 0.5f;
     const float qx = S.q0[0] + kk * S.dq[0], qy = S.q0[1] + kk * S.dq[1], qz = S.q0[2] + kk * S.dq[2];
     float F, Fp[3], Fm[3];
@@ -1307,6 +1316,8 @@ __device__ __forceinline__ float lit_sample_deferred(const RenderArgs &A, const 
     lut_classify(A, s_lut, F, S.dl, v);
     const float Ta = T * v.alpha;
     const bool defer = pend != 0;
+    const uint32_t pos = trow ? *tpos : 0u;
+    const uint32_t cap = (uint32_t)A.tape_cap;
     if (!defer) {
         float gv[3], dot, den;
         lit_gradient(A, F, Fp, Fm, 0x3fu, gv);
@@ -1314,9 +1325,10 @@ __device__ __forceinline__ float lit_sample_deferred(const RenderArgs &A, const 
         C0 += wgt * v.r;
         C1 += wgt * v.g;
         C2 += wgt * v.b;
+        if (trow && pos < cap) trow[pos] = make_float4(F, gv[0], gv[1], gv[2]);
     }
-    const uint32_t ord = ndef ? *ndef : 0u;
-    if (ndef && defer) (*ndef)++;
+    const uint32_t ord = pos < cap ? pos : cap;
+    if (trow) *tpos = pos + 1u;
     tapq_push<REC>(A, Q, lane, defer, R, S, k, have_xs ? xs : nullptr, qx, qy, qz, F, Fp, Fm, cls, pend, Ta, v, cnt,
                    ord);
     return v.alpha;
@@ -1453,7 +1465,7 @@ inline int fill_args(const amr_scene *S, const amr_camera *C, const amr_render_p
     A->ckpt_stride = (int64_t)sizeof(Ckpt) * (1 + (int64_t)P->ckpt_max);
     A->ckpt_every = P->ckpt_every > 0 ? P->ckpt_every : 1;
     A->ckpt_max = P->ckpt_max;
-    A->tape = P->d_ckpt && P->d_tape && P->tape_cap > 0 ? P->d_tape : nullptr;
+    A->tape = P->d_ckpt && P->d_tape && P->tape_cap > 0 ? reinterpret_cast<float4 *>(P->d_tape) : nullptr;
     A->tape_cap = A->tape ? P->tape_cap : 0;
     return AMR_OK;
 }

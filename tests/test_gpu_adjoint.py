@@ -123,12 +123,12 @@ def test_adjoint_deterministic_and_checkpoint_rate(gpu):
 
 @pytest.mark.parametrize("layout", [0, 1, 2])
 def test_adjoint_tape_matches_in_place(gpu, layout):
-    """The checkpointed lit forward writes the gradient of every sample whose taps left its brick
-    to the ray's tape; the adjoint reads it instead of resolving the taps.  Gradients with a tape
-    that holds every entry, with a tape too short for most rays (those intervals are served in
-    place by the second launch) and with none agree to the fp32 bar of the adjoint, on the
-    cosmology-like hierarchy at 96x96 (its gradient taps cross many patches), in every brick
-    layout; the oracle checks the tape form on a pixel subset."""
+    """The checkpointed lit forward writes every segment's and sample's record to the ray's tape;
+    the adjoint replays the intervals whose records all fit from it and evaluates the others in
+    place.  Gradients with a tape that holds every record, with one that holds the first
+    intervals of most rays, with one too short for nearly all of them and with none agree to the
+    fp32 bar of the adjoint, on the cosmology-like hierarchy at 96x96 (its gradient taps cross
+    many patches), in every brick layout; the oracle checks the tape form on a pixel subset."""
     import torch
     amr = gpu
     h, cams, target, start, prm = workloads.tf_fit(0, res=96, ncams=1)
@@ -138,15 +138,15 @@ def test_adjoint_tape_matches_in_place(gpu, layout):
     lut_t = torch.from_numpy(start).cuda()
     W = torch.from_numpy(np.random.default_rng(4).normal(size=(96 * 96, 4)).astype(np.float32)).cuda()
     got = {}
-    for cap in (0, 3, 4096):
+    for cap in (0, 3, 400, 4096):
         out, ck = amr.render_checkpointed(scene, cam, lut_t, prm, tape_cap=cap)
         glut, glight = amr.render_backward(scene, cam, lut_t, prm, ck, W, deterministic=True)
         torch.cuda.synchronize()
         got[cap] = (glut.cpu().numpy(), glight.cpu().numpy(), ck.tape_overflow_rays())
         print("layout %d tape_cap %d: %d rays beyond the tape, max |dLUT| %.4g" % (
             layout, cap, got[cap][2], np.abs(got[cap][0]).max()))
-    assert got[3][2] > 100 and got[4096][2] == 0
-    for cap in (3, 4096):
+    assert got[3][2] > 100 and got[4096][2] == 0 and 0 < got[400][2] < got[3][2]
+    for cap in (3, 400, 4096):
         assert _bar_ok(got[cap][0], got[0][0], 1e-4)
         assert np.all(np.abs(got[cap][1] - got[0][1]) <= 1e-4 * np.abs(got[0][1]) + 1e-5 * np.abs(got[0][1]).max())
     if layout == 2:
@@ -166,6 +166,81 @@ def test_adjoint_tape_matches_in_place(gpu, layout):
         e, n = _rel_ok(glut.cpu().numpy(), ref_lut, 1e-3, 1e-3)
         print("tape adjoint vs oracle: LUT grad max rel err %.3g over %d entries" % (e, n))
         assert _bar_ok(glut.cpu().numpy(), ref_lut, 1e-3) and n > 20
+
+
+def test_tape_records_vs_oracle(gpu):
+    """The tape the checkpointed lit forward writes, record by record, against the oracle: per ray
+    one record per data segment, (delta, delta log2 e, n, 0) with n and the segment's sample
+    spacing from the oracle's segment list, then one per sample, (F, g): the trilinear value at
+    the sample and the central-difference gradient of the oracle's shading (taps one cell of the
+    segment's level away, one-sided outside the domain, divided by the LUT's value range).  The
+    header's record count is the number of records the ray wrote; early termination ends the
+    records with the ray's last sample.  Small nested hierarchy (gradient taps cross patch and
+    level boundaries), lit, 64x64 oblique view, 1000 seeded rays."""
+    import torch
+    amr = gpu
+    h, lut, cams, prm = workloads.small_nested(1)
+    prm = dict(prm, lighting=True)
+    W = H = 64
+    cam = workloads.small_nested_cameras(W, H)[1]
+    tree, scene = _scene(amr, h)
+    cap = 4096
+    out, ck = amr.render_checkpointed(scene, cam, torch.from_numpy(lut).cuda(), prm, tape_cap=cap)
+    torch.cuda.synchronize()
+    tape = ck.tape.view(W * H, cap, 4).cpu().numpy()
+    hdr = ck.buf.view(-1, 32 * (1 + ck.max))[:, :32].contiguous().view(torch.int32).cpu().numpy()
+    O = oracle.Oracle(h)
+    sel = np.sort(np.random.default_rng(12).choice(W * H, 1000, replace=False))
+    pix = np.stack([sel % W, sel // W], 1).astype(np.int32)
+    res = O.render(cam, prm, lut, pixels=pix, trace_cap=512)
+    assert res["trace_n"].max() <= 512 and int(np.count_nonzero(res["flags"])) == 0
+    same = hdr[sel, 4] == res["nsamp"]
+    print("rays whose early termination differs (fp32 against FP64 transmittance): %d of %d" % ((~same).sum(), len(sel)))
+    assert (~same).sum() <= 2
+    levels = np.array([p.level for p in h.patches])
+    hl = lambda lev: np.asarray(h.h0, np.float64) / float(h.refine) ** lev
+    rng_v = prm["v_hi"] - prm["v_lo"]
+    nrec = nsmp = 0
+    dF = dg = 0.0
+    for s in np.flatnonzero(same):
+        q = int(sel[s])
+        i, j = q % W, q // W
+        o, d = (np.asarray(a) for a in oracle.ray(cam, int(i), int(j)))
+        left = int(res["nsamp"][s])
+        pos = 0
+        for rec in res["trace"][s, :res["trace_n"][s]]:
+            n, patch = int(rec["n"]), int(rec["patch"])
+            if patch < 0 or n == 0 or left == 0:
+                continue
+            delta = (rec["tb"] - rec["ta"]) / n
+            seg = tape[q, pos]
+            assert seg.view(np.int32)[2] == n and seg[3] == 0.0, (q, pos)
+            assert abs(seg[0] - delta) <= 1e-6 * delta and abs(seg[1] - delta * np.log2(np.e)) <= 2e-6 * delta
+            pos += 1
+            step = hl(levels[patch])
+            for k in range(min(n, left)):
+                x = o + (rec["ta"] + (k + 0.5) * delta) * d
+                F = O.field(x)
+                g = np.zeros(3)
+                for a in range(3):
+                    e = np.zeros(3)
+                    e[a] = step[a]
+                    Fp, Fm = O.field(x + e), O.field(x - e)
+                    g[a] = ((Fp - Fm) / 2 if Fp is not None and Fm is not None else
+                            (Fp - F) if Fp is not None else (F - Fm) if Fm is not None else 0.0) / rng_v
+                r = tape[q, pos]
+                dF = max(dF, abs(r[0] - F) / rng_v)
+                dg = max(dg, float(np.abs(r[1:] - g).max()))
+                pos += 1
+                nsmp += 1
+            left -= min(n, left)
+        assert hdr[q, 7] == pos, (q, hdr[q, 7], pos)
+        nrec += pos
+    print("tape: %d records, %d samples; max |F - F_ref| / range %.3g, max |g - g_ref| %.3g" % (nrec, nsmp, dF, dg))
+    assert nsmp > 12000
+    # fp32 trilinear in patch-local coordinates against FP64: ~1e-7 of the range; the gradient is
+    # a difference of two such values over two cells, so its error is of the same order
+    assert dF <= 1e-6 and dg <= 1e-5
 
 
 def test_autograd_function(gpu):

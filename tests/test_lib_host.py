@@ -460,7 +460,8 @@ def _render_call(lib, scene, cams, prm, set_fields=None, lut_ok=True):
     if not lut_ok:
         q.d_lut = None
     for k, v in (set_fields or {}).items():
-        setattr(q, k, scratch.ctypes.data if v == "buf" else v)
+        # "buf": a host buffer standing in for a device one; "buf+4": the same, 4-byte misaligned
+        setattr(q, k, scratch.ctypes.data + (4 if v == "buf+4" else 0) if v in ("buf", "buf+4") else v)
     if q.persistent and not (set_fields and "d_cams" in set_fields):
         q.d_cams = ctypes.cast(carr, ctypes.c_void_p).value
     rc = lib.amr_render(ctypes.byref(scene.scene), carr, len(cams), ctypes.byref(q), rgba.ctypes.data, None, None)
@@ -468,7 +469,8 @@ def _render_call(lib, scene, cams, prm, set_fields=None, lut_ok=True):
 
 
 @pytest.mark.parametrize("case", ["v_range", "step", "cam_size", "interp", "lighting", "lod", "lut", "trace_cap",
-                                  "ckpt_odd", "ckpt_small", "tile", "no_queue", "light_no_work", "light_work_small"])
+                                  "ckpt_odd", "ckpt_small", "tile", "no_queue", "light_no_work", "light_work_small",
+                                  "tape_cap", "tape_align"])
 def test_render_argument_checks(case):
     """amr_render's argument checks, each of which returns before any device access (host buffers
     stand in for device pointers, so the test runs only where no GPU is visible)."""
@@ -511,6 +513,12 @@ def test_render_argument_checks(case):
     elif case == "light_work_small":
         p, words, want_code = dict(prm, lighting=2), "workspace", 3
         fields = dict(d_work="buf", work_bytes=1 << 16, light_jobs=1 << 20)
+    elif case == "tape_cap":
+        p, words = dict(prm, lighting=1), "tape_cap"
+        fields = dict(d_ckpt="buf", ckpt_bytes=1 << 40, ckpt_every=2, ckpt_max=4, d_tape="buf", tape_cap=1 << 26)
+    elif case == "tape_align":
+        p, words = dict(prm, lighting=1), "16-byte"
+        fields = dict(d_ckpt="buf", ckpt_bytes=1 << 40, ckpt_every=2, ckpt_max=4, d_tape="buf+4", tape_cap=8)
     rc, msg = _render_call(lib, scene, cl, p, fields, lut_ok)
     assert rc == want_code, (case, rc, msg)
     assert words in msg, (case, msg)
@@ -593,3 +601,11 @@ def test_render_work_bytes():
     assert lib.amr_render_work_bytes(carr, 0, ctypes.byref(q)) == -1
     assert lib.amr_backward_work_bytes(0) == 4 * 1029
     assert lib.amr_backward_work_bytes(1) == 4 * 1029 * 2049
+    # the tape: 16-byte records, tape_cap of them per ray; by default as many as fit in 30 % of the
+    # device's memory (multiples of 8, at most 2048)
+    assert lib.amr_tape_bytes(1000, 7) == 1000 * 7 * 16
+    assert amr.default_tape_cap(8 * 512 * 512, total_memory=288 * 10**9) == 2048
+    assert amr.default_tape_cap(8 * 1024 * 1024, total_memory=288 * 10**9) == 640
+    assert amr.default_tape_cap(8 * 2048 * 2048, total_memory=288 * 10**9) == 160
+    assert amr.default_tape_cap(10**12, total_memory=288 * 10**9) == 0
+    assert lib.amr_tape_bytes(0, 7) == 0 and lib.amr_tape_bytes(-1, 7) == 0 and lib.amr_tape_bytes(5, -1) == 0
