@@ -256,7 +256,7 @@ typedef struct {
        bound alone decides), B being the sum of T * alpha_hi over the ray's earlier skips, so
        the charged opacity of a ray stays below tau_e; it is sampled with one step per cell
        and ends the ray if alpha_lo > 1 - tau_s; otherwise it is sampled plainly */
-    const void *d_mlp;                  /* packed network, see amr_mlp_pack */
+    const void *d_mlp;                  /* packed network, see amr_mlp_pack (16-byte aligned) */
     float tau_e, tau_s;
     /* segment log for training (device): a 256-byte header whose first 8 bytes count the
        segments met, then amr_seglog_rec records; seglog_cap is the buffer size in bytes */
@@ -420,7 +420,7 @@ int amr_mlp_backward(const float *X, const float *W, const float *H, const float
 int amr_mlp_adam_step(float *W, const float *dW, float *M, float *V, int32_t t, float lr,
                       float beta1, float beta2, float eps, void *stream);
 /* Packs fp32 master weights W into the fp16 inference layout used by amr_render (d_out of
- * amr_mlp_packed_bytes() bytes, device). */
+ * amr_mlp_packed_bytes() bytes, device, 16-byte aligned as amr_render requires of d_mlp). */
 int64_t amr_mlp_packed_bytes(void);
 int amr_mlp_pack(const float *W, void *d_out, void *stream);
 

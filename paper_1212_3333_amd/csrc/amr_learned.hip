@@ -46,8 +46,9 @@ struct LearnLds {               // every variant: the LUT and its extinction tab
     float prefix[257];         // prefix sums of extinction
 };
 
-struct NetLds {                 // the network variant: per-wave inference buffers (the weights,
-                                // 12 KB read by every query, stay in global memory and the caches)
+struct __attribute__((aligned(16))) NetLds {   // the network variant: per-wave inference buffers
+                                // (the weights, 12 KB read by every query, stay in global memory
+                                // and the caches)
     _Float16 feat[64 * 16];
     _Float16 hid[16 * 64];     // layer 1 output, then layer 2 output in place
     float out[64 * 2];
@@ -82,24 +83,24 @@ __device__ __forceinline__ void infer_tile(NetLds &s, const MlpLds *__restrict__
     for (int ct = 0; ct < 4; ct++) {
         half4 b = *reinterpret_cast<const half4 *>(w->w1t + (ct * 16 + lr) * 16 + 4 * lq);
         float4v acc = {0.f, 0.f, 0.f, 0.f};
-        acc = __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, acc, 0, 0, 0);
+        acc = mfma_k16(a, b, acc);
         #pragma unroll
         for (int j = 0; j < 4; j++) hid[(4 * lq + j) * 64 + ct * 16 + lr] = (_Float16)fmaxf(acc[j] + w->b1[ct * 16 + lr], 0.f);
     }
     __builtin_amdgcn_wave_barrier();
     // layer 2: the A fragments of h1 are the same for every output block, so read them once and
     // overwrite the buffer with h2
-    half4 a2[4];
+    half8 a2[2];
     #pragma unroll
-    for (int ks = 0; ks < 4; ks++) a2[ks] = *reinterpret_cast<const half4 *>(hid + lr * 64 + ks * 16 + 4 * lq);
+    for (int ks = 0; ks < 2; ks++) a2[ks] = *reinterpret_cast<const half8 *>(hid + lr * 64 + ks * 32 + 8 * lq);
     __builtin_amdgcn_wave_barrier();
     #pragma unroll 1
     for (int ct = 0; ct < 4; ct++) {
         float4v acc = {0.f, 0.f, 0.f, 0.f};
         #pragma unroll
-        for (int ks = 0; ks < 4; ks++) {
-            half4 b = *reinterpret_cast<const half4 *>(w->w2t + (ct * 16 + lr) * 64 + ks * 16 + 4 * lq);
-            acc = __builtin_amdgcn_mfma_f32_16x16x16f16(a2[ks], b, acc, 0, 0, 0);
+        for (int ks = 0; ks < 2; ks++) {
+            half8 b = *reinterpret_cast<const half8 *>(w->w2t + (ct * 16 + lr) * 64 + ks * 32 + 8 * lq);
+            acc = mfma_k32(a2[ks], b, acc);
         }
         #pragma unroll
         for (int j = 0; j < 4; j++) hid[(4 * lq + j) * 64 + ct * 16 + lr] = (_Float16)fmaxf(acc[j] + w->b2[ct * 16 + lr], 0.f);
@@ -107,10 +108,10 @@ __device__ __forceinline__ void infer_tile(NetLds &s, const MlpLds *__restrict__
     __builtin_amdgcn_wave_barrier();
     float4v acc = {0.f, 0.f, 0.f, 0.f};
     #pragma unroll
-    for (int ks = 0; ks < 4; ks++) {
-        half4 a3 = *reinterpret_cast<const half4 *>(hid + lr * 64 + ks * 16 + 4 * lq);
-        half4 b = *reinterpret_cast<const half4 *>(w->w3t + lr * 64 + ks * 16 + 4 * lq);
-        acc = __builtin_amdgcn_mfma_f32_16x16x16f16(a3, b, acc, 0, 0, 0);
+    for (int ks = 0; ks < 2; ks++) {
+        half8 a3 = *reinterpret_cast<const half8 *>(hid + lr * 64 + ks * 32 + 8 * lq);
+        half8 b = *reinterpret_cast<const half8 *>(w->w3t + lr * 64 + ks * 32 + 8 * lq);
+        acc = mfma_k32(a3, b, acc);
     }
     if (lr < kOut) {
         #pragma unroll

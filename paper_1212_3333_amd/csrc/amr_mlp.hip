@@ -1,11 +1,9 @@
 // The segment-proposal network (an addition to the paper's method): 12 -> 64 -> 64 -> 2,
 // ReLU hidden layers, sigmoid outputs (alpha_lo, alpha_hi), trained with a pinball loss.
 //
-// GEMMs run on the matrix cores: v_mfma_f32_16x16x16f16, fp16 operands, fp32 accumulation.
-// A wave handles a 64-row tile.  Operand layout of the 16x16x16 instruction (wave64):
-//   A (16 x 16, M x K): lane l holds A[l % 16][4 (l / 16) + j], j = 0..3
-//   B (16 x 16, K x N): lane l holds B[4 (l / 16) + j][l % 16]
-//   D (16 x 16, M x N): lane l holds D[4 (l / 16) + j][l % 16]
+// GEMMs run on the matrix cores, fp16 operands and fp32 accumulation: the 16x16x16 shape for
+// layer 1 (K = 16, the 12 inputs padded), gfx950's 16x16x32 shape for every K = 64 product
+// (operand layouts in amr_mlp.h).  A wave handles a 64-row tile.
 // Parameters are fp32 masters packed as W1 [12][64], b1 [64], W2 [64][64], b2 [64],
 // W3 [64][2], b3 [2] (input-major); the fp16 operands are rounded from them.
 #include <hip/hip_runtime.h>
@@ -50,7 +48,7 @@ __device__ inline void mlp_tile_forward(const MlpLds &s, const _Float16 *x16, _F
         for (int ct = 0; ct < 4; ct++) {
             half4 b = *reinterpret_cast<const half4 *>(s.w1t + (ct * 16 + lr) * 16 + 4 * lq);
             float4v acc = {0.f, 0.f, 0.f, 0.f};
-            acc = __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, acc, 0, 0, 0);
+            acc = mfma_k16(a, b, acc);
             for (int j = 0; j < 4; j++) {
                 int row = rt * 16 + 4 * lq + j, col = ct * 16 + lr;
                 float hv = fmaxf(acc[j] + s.b1[col], 0.f);
@@ -64,10 +62,10 @@ __device__ inline void mlp_tile_forward(const MlpLds &s, const _Float16 *x16, _F
     for (int rt = 0; rt < 4; rt++)
         for (int ct = 0; ct < 4; ct++) {
             float4v acc = {0.f, 0.f, 0.f, 0.f};
-            for (int ks = 0; ks < 4; ks++) {
-                half4 a = *reinterpret_cast<const half4 *>(h1 + (rt * 16 + lr) * 64 + ks * 16 + 4 * lq);
-                half4 b = *reinterpret_cast<const half4 *>(s.w2t + (ct * 16 + lr) * 64 + ks * 16 + 4 * lq);
-                acc = __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, acc, 0, 0, 0);
+            for (int ks = 0; ks < 2; ks++) {
+                half8 a = *reinterpret_cast<const half8 *>(h1 + (rt * 16 + lr) * 64 + ks * 32 + 8 * lq);
+                half8 b = *reinterpret_cast<const half8 *>(s.w2t + (ct * 16 + lr) * 64 + ks * 32 + 8 * lq);
+                acc = mfma_k32(a, b, acc);
             }
             for (int j = 0; j < 4; j++) {
                 int row = rt * 16 + 4 * lq + j, col = ct * 16 + lr;
@@ -80,10 +78,10 @@ __device__ inline void mlp_tile_forward(const MlpLds &s, const _Float16 *x16, _F
     // layer 3: [64 x 64] . [64 x 16] (two valid columns)
     for (int rt = 0; rt < 4; rt++) {
         float4v acc = {0.f, 0.f, 0.f, 0.f};
-        for (int ks = 0; ks < 4; ks++) {
-            half4 a = *reinterpret_cast<const half4 *>(h2 + (rt * 16 + lr) * 64 + ks * 16 + 4 * lq);
-            half4 b = *reinterpret_cast<const half4 *>(s.w3t + lr * 64 + ks * 16 + 4 * lq);
-            acc = __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, acc, 0, 0, 0);
+        for (int ks = 0; ks < 2; ks++) {
+            half8 a = *reinterpret_cast<const half8 *>(h2 + (rt * 16 + lr) * 64 + ks * 32 + 8 * lq);
+            half8 b = *reinterpret_cast<const half8 *>(s.w3t + lr * 64 + ks * 32 + 8 * lq);
+            acc = mfma_k32(a, b, acc);
         }
         for (int j = 0; j < 4; j++) z3[rt][j] = acc[j] + (lr < kOut ? s.b3[lr] : 0.f);
     }
@@ -94,8 +92,8 @@ __device__ inline float sigmoidf_(float z) { return 1.f / (1.f + __expf(-z)); }
 __global__ __launch_bounds__(256) void mlp_forward_kernel(const float *X, const float *W, float *Y, float *H,
                                                          int64_t n) {
     __shared__ MlpLds s;
-    __shared__ _Float16 xs[4][64 * 16];
-    __shared__ _Float16 hs1[4][64 * 64], hs2[4][64 * 64];
+    __shared__ __attribute__((aligned(16))) _Float16 xs[4][64 * 16];
+    __shared__ __attribute__((aligned(16))) _Float16 hs1[4][64 * 64], hs2[4][64 * 64];
     stage_weights(W, s);
     __syncthreads();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -138,7 +136,7 @@ __global__ __launch_bounds__(256) void mlp_backward_kernel(const float *X, const
                                                           const float *Y, const float *Tg, int64_t n, float q_lo,
                                                           float q_hi, float *dW, float *loss) {
     __shared__ MlpLds s;
-    __shared__ _Float16 hs1[4][64 * 64], dz2s[4][64 * 64];
+    __shared__ __attribute__((aligned(16))) _Float16 hs1[4][64 * 64], dz2s[4][64 * 64];
     __shared__ float acc_s[kParams];
     stage_weights(W, s);
     for (int i = threadIdx.x; i < kParams; i += blockDim.x) acc_s[i] = 0.f;
@@ -185,24 +183,24 @@ __global__ __launch_bounds__(256) void mlp_backward_kernel(const float *X, const
         // dW2 += H1^T dZ2: M = unit u, K = row, N = unit v
         for (int mt = 0; mt < 4; mt++)
             for (int nt = 0; nt < 4; nt++)
-                for (int ks = 0; ks < 4; ks++) {
-                    half4 a, b;
-                    for (int j = 0; j < 4; j++) {
-                        int row = ks * 16 + 4 * lq + j;
+                for (int ks = 0; ks < 2; ks++) {
+                    half8 a, b;
+                    for (int j = 0; j < 8; j++) {
+                        int row = ks * 32 + 8 * lq + j;
                         a[j] = hs1[wave][row * 64 + mt * 16 + lr];
                         b[j] = dz2s[wave][row * 64 + nt * 16 + lr];
                     }
-                    dw2[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, dw2[mt][nt], 0, 0, 0);
+                    dw2[mt][nt] = mfma_k32(a, b, dw2[mt][nt]);
                 }
         // dH1 = dZ2 W2^T (M = row, K = unit v, N = unit u), then dZ1 = dH1 (H1 > 0);
         // dW1 += X^T dZ1 and db1 on the VALU (lane = unit u after the shuffle through LDS)
         for (int rt = 0; rt < 4; rt++)
             for (int ct = 0; ct < 4; ct++) {
                 float4v acc = {0.f, 0.f, 0.f, 0.f};
-                for (int ks = 0; ks < 4; ks++) {
-                    half4 a = *reinterpret_cast<const half4 *>(&dz2s[wave][(rt * 16 + lr) * 64 + ks * 16 + 4 * lq]);
-                    half4 b = *reinterpret_cast<const half4 *>(&s.w2[(ct * 16 + lr) * 64 + ks * 16 + 4 * lq]);
-                    acc = __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, acc, 0, 0, 0);
+                for (int ks = 0; ks < 2; ks++) {
+                    half8 a = *reinterpret_cast<const half8 *>(&dz2s[wave][(rt * 16 + lr) * 64 + ks * 32 + 8 * lq]);
+                    half8 b = *reinterpret_cast<const half8 *>(&s.w2[(ct * 16 + lr) * 64 + ks * 32 + 8 * lq]);
+                    acc = mfma_k32(a, b, acc);
                 }
                 __builtin_amdgcn_wave_barrier();
                 for (int j = 0; j < 4; j++) {
@@ -310,6 +308,7 @@ int amr_mlp_adam_step(float *W, const float *dW, float *M, float *V, int32_t t, 
 
 int amr_mlp_pack(const float *W, void *d_out, void *stream) {
     if (!W || !d_out) { set_error("amr_mlp_pack: null argument"); return AMR_EINVAL; }
+    if (reinterpret_cast<uintptr_t>(d_out) & 15u) { set_error("amr_mlp_pack: d_out must be 16-byte aligned"); return AMR_EINVAL; }
     hipLaunchKernelGGL(mlp_pack_kernel, dim3(1), dim3(256), 0, (hipStream_t)stream, W, (MlpLds *)d_out);
     return check_hip_mlp(hipGetLastError(), "mlp_pack launch");
 }

@@ -777,6 +777,10 @@ int amr_render(const amr_scene *S, const amr_camera *cams, int32_t ncams, const 
         }
     }
     const bool learned = P->d_mlp || P->d_seglog || P->bound_only;
+    if (P->d_mlp && (reinterpret_cast<uintptr_t>(P->d_mlp) & 15u)) {
+        set_error("d_mlp must be 16-byte aligned");
+        return AMR_EINVAL;
+    }
     if (P->bound_only && P->d_mlp) {
         set_error("bound_only skips by the analytic bound alone: d_mlp must be NULL");
         return AMR_EINVAL;
