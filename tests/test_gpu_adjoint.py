@@ -20,6 +20,12 @@ def _scene(amr, h):
 # fp32 bar: |g - g_ref| <= rel |g_ref| + 1e-5 max|g_ref|.  The absolute term is the fp32 noise
 # floor of a gradient entry summed from ~1e5 per-sample terms (observed worst 2.3e-6 max).
 ABS_FLOOR = 1e-5
+# Entries checked at the relative bar (|g_ref| >= 1e-3 max|g_ref|) must number more than
+# MIN_SIGNIFICANT, so that a comparison is never carried by a handful of entries.  The views
+# with a full image of dL/dRGBA reach 500-750 such entries; the pixel-subset views of the
+# cosmology-like hierarchy (600-800 pixels, values concentrated in a few LUT bins by its
+# log-normal density) reach 45-75, the 32x32 autograd view 578.
+MIN_SIGNIFICANT = 20
 
 
 def _bar_ok(got, ref, rel):
@@ -100,6 +106,46 @@ def test_adjoint_vs_gpu_finite_differences(gpu):
     assert np.max(np.abs(fd - ad) / np.abs(ad)) <= 1e-2
 
 
+def test_adjoint_vs_gpu_finite_differences_cosmology(gpu):
+    """The same check on the transfer-function fit's hierarchy (cosmology-like, 2008 patches),
+    lit without early termination, one 96x96 orbit camera, the adjoint reading the tape: central
+    differences of L = sum W * RGBA over the LUT entries with gradients of at least 3e-3 of the
+    largest (17 here: the hierarchy's log-normal values fill few LUT bins).  The loss is
+    piecewise linear in the colour entries and smooth in the extinction ones, so a step of 1 %
+    of the entry (plus 1e-2) keeps the truncation error far below the fp32 noise of the renders."""
+    import torch
+    amr = gpu
+    h, cams, target, start, prm = workloads.tf_fit(0, res=96, ncams=1)
+    cam = cams[0]
+    tree, scene = _scene(amr, h)
+    W = np.random.default_rng(8).normal(size=(96 * 96, 4))
+    lut64 = start.astype(np.float64)
+    out, ck = amr.render_checkpointed(scene, cam, torch.from_numpy(start).cuda(), prm)
+    assert ck.tape is not None and ck.tape_overflow_rays() == 0
+    glut, _ = amr.render_backward(scene, cam, torch.from_numpy(start).cuda(), prm, ck,
+                                  torch.from_numpy(W.astype(np.float32)).cuda())
+    g = glut.cpu().numpy().astype(np.float64)
+
+    def loss(l):
+        o = amr.render(scene, cam, torch.from_numpy(l.astype(np.float32)).cuda(), prm)["rgba"]
+        return float((o.double().cpu().numpy().reshape(-1, 4) * W).sum())
+    rng = np.random.default_rng(1)
+    idx = np.argwhere(np.abs(g) >= 3e-3 * np.abs(g).max())
+    sel = idx[rng.choice(len(idx), size=min(40, len(idx)), replace=False)]
+    fd = []
+    for e, c in sel:
+        hs = 1e-2 * (1.0 + abs(lut64[e, c]))
+        lp = lut64.copy(); lp[e, c] += hs
+        lm = lut64.copy(); lm[e, c] -= hs
+        fd.append((loss(lp) - loss(lm)) / (2 * hs))
+    fd = np.array(fd)
+    ad = np.array([g[e, c] for e, c in sel])
+    cos = fd @ ad / (np.linalg.norm(fd) * np.linalg.norm(ad))
+    rel = np.abs(fd - ad) / np.abs(ad)
+    print("cosmology: %d entries, cosine %.6f, max rel %.3g, median rel %.3g" % (len(sel), cos, rel.max(), np.median(rel)))
+    assert len(sel) >= 12 and cos >= 0.999 and rel.max() <= 2e-2
+
+
 def test_adjoint_deterministic_and_checkpoint_rate(gpu):
     import torch
     amr = gpu
@@ -165,7 +211,7 @@ def test_adjoint_tape_matches_in_place(gpu, layout):
                                                    pixels=pix)
         e, n = _rel_ok(glut.cpu().numpy(), ref_lut, 1e-3, 1e-3)
         print("tape adjoint vs oracle: LUT grad max rel err %.3g over %d entries" % (e, n))
-        assert _bar_ok(glut.cpu().numpy(), ref_lut, 1e-3) and n > 20
+        assert _bar_ok(glut.cpu().numpy(), ref_lut, 1e-3) and n > MIN_SIGNIFICANT
 
 
 def test_tape_records_vs_oracle(gpu):
@@ -259,7 +305,8 @@ def test_autograd_function(gpu):
     ref_lut, ref_sh = oracle.Oracle(h).grad(cam, prm, lut.astype(np.float64),
                                            (2 * rgba.detach().double().cpu().numpy().reshape(-1, 4)) / rgba.numel())
     e, n = _rel_ok(lut_p.grad.cpu().numpy(), ref_lut, 2e-3, 1e-3)
-    assert _bar_ok(lut_p.grad.cpu().numpy(), ref_lut, 1e-3) and n > 20
+    print("autograd: LUT grad max rel err %.3g over %d entries" % (e, n))
+    assert _bar_ok(lut_p.grad.cpu().numpy(), ref_lut, 1e-3) and n > MIN_SIGNIFICANT
     assert np.allclose(sh.grad.numpy(), ref_sh, rtol=2e-3, atol=1e-4 * np.abs(ref_sh).max())
 
 
@@ -289,7 +336,7 @@ def test_adjoint_vs_oracle_tf_fit_subset(gpu, lit):
     glut, glight = amr.render_backward(scene, cams, lut_t, prm, ck, torch.from_numpy(G.reshape(-1, 4)).cuda())
     e, n = _rel_ok(glut.cpu().numpy(), ref_lut, 1e-3, 1e-3)
     print("tf_fit: LUT grad max rel err %.3g over %d entries; light %s vs %s" % (e, n, glight.cpu().numpy(), ref_light))
-    assert _bar_ok(glut.cpu().numpy(), ref_lut, 1e-3) and n > 20
+    assert _bar_ok(glut.cpu().numpy(), ref_lut, 1e-3) and n > MIN_SIGNIFICANT
     assert np.all(np.abs(glight.cpu().numpy() - ref_light) <= 1e-3 * np.abs(ref_light) + 1e-4 * np.abs(ref_light).max())
 
 
@@ -347,7 +394,7 @@ def test_adjoint_with_lod(gpu, lit):
     ref_lut, ref_light = oracle.Oracle(h).grad(cam, prm, lut.astype(np.float64), G)
     e, n = _rel_ok(glut.cpu().numpy(), ref_lut, 1e-3, 1e-3)
     print("lod adjoint lit=%d: LUT grad max rel err %.3g over %d entries" % (lit, e, n))
-    assert _bar_ok(glut.cpu().numpy(), ref_lut, 1e-3) and n > 20
+    assert _bar_ok(glut.cpu().numpy(), ref_lut, 1e-3) and n > MIN_SIGNIFICANT
     if lit:
         gl = glight.cpu().numpy()
         assert np.all(np.abs(gl - ref_light) <= 1e-3 * np.abs(ref_light) + 1e-4 * np.abs(ref_light).max())
