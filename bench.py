@@ -285,7 +285,8 @@ def batched_section(amr, dev, scene, lut_t, prm):
         """The tuned launch with cameras largest (0) or smallest (1) first, captured in a hipGraph
         and replayed three times: per-image latency from the stamps, aggregate Mrays/s."""
         bprm = dict(prm, persistent=1, tile_w=best["tile_w"], tile_h=best["tile_h"],
-                    blocks_per_cu=best["blocks_per_cu"], xcd_tiles=best["xcd_tiles"], queue_order=order)
+                    blocks_per_cu=best["blocks_per_cu"], waves_per_simd=best["waves_per_simd"],
+                    xcd_tiles=best["xcd_tiles"], queue_order=order)
         amr.render(scene, cams, lut_t, bprm, out=out, d_cams=dc, d_queue=q, d_stamps=stamps)
         torch.cuda.synchronize()
         g = torch.cuda.CUDAGraph()
@@ -312,7 +313,8 @@ def batched_section(amr, dev, scene, lut_t, prm):
     tuned = replayed(best["queue_order"])
     other = replayed(1 - best["queue_order"])
     res = dict(cameras=len(cams), rays=int(npix), tile_w=int(best["tile_w"]), tile_h=int(best["tile_h"]),
-               blocks_per_cu=int(best["blocks_per_cu"]), xcd_tiles=int(best["xcd_tiles"]),
+               blocks_per_cu=int(best["blocks_per_cu"]), waves_per_simd=int(best["waves_per_simd"]),
+               xcd_tiles=int(best["xcd_tiles"]),
                queue_order="smallest first" if best["queue_order"] else "largest first",
                tuned_ms=best["ms"], candidates=len(best["table"]), **tuned,
                other_order=other)

@@ -310,7 +310,9 @@ typedef struct {
                                            XCD (blocks b with b mod 8 = x take queue x), holding the
                                            4x4-tile super-tiles x, x + 8, ... of each image along a
                                            Morton curve, so the tiles in flight on an XCD stay close */
-    int32_t pad2_;
+    int32_t waves_per_simd;             /* persistent, lit: the register budget of the kernel, 2 or 3
+                                           waves per SIMD (0 = 3; 3 spills part of the state to
+                                           scratch, 2 holds it in registers); AMR_EINVAL otherwise */
 } amr_render_params;
 
 /* Renders ncams cameras (host array) into d_rgba (device, premultiplied RGBA fp32, images

@@ -331,6 +331,7 @@ def make_params(p: dict, d_lut) -> L.amr_render_params:
     q.bound_only = int(bool(p.get("bound_only", 0)))
     q.queue_order = int(p.get("queue_order", 0))
     q.xcd_tiles = int(p.get("xcd_tiles", 0))
+    q.waves_per_simd = int(p.get("waves_per_simd", 0))
     return q
 
 

@@ -109,7 +109,7 @@ class amr_render_params(ctypes.Structure):
                 ("d_queue", VP), ("d_stamps", VP), ("d_cams", VP), ("d_touch", VP),
                 ("d_work", VP), ("work_bytes", ctypes.c_int64), ("light_jobs", ctypes.c_int64),
                 ("d_touch_meta", VP), ("bound_only", ctypes.c_int32), ("queue_order", ctypes.c_int32),
-                ("xcd_tiles", ctypes.c_int32), ("pad2_", ctypes.c_int32)]
+                ("xcd_tiles", ctypes.c_int32), ("waves_per_simd", ctypes.c_int32)]
 
 
 class amr_seglog_rec(ctypes.Structure):

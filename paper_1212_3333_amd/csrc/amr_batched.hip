@@ -136,8 +136,10 @@ __device__ __forceinline__ void set_camera(RenderArgs &A, const amr_camera &C) {
 }
 
 // LAY: the brick layout fixed at compile time (-1: read at run time, for the recording variants).
-template <bool LIT, bool REC, int LAY>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void render_batched(BatchArgs B) {
+// WPS: waves per SIMD the register allocation must allow (the lit kernel: 3 fits 168 VGPRs and
+// spills about 120 bytes per lane, 2 keeps everything in registers with a third fewer waves).
+template <bool LIT, bool REC, int LAY, int WPS = 3>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPS))) void render_batched(BatchArgs B) {
     __shared__ float4 s_lut[256];
     TapQueue *tq = nullptr;                        // lit: one deferred-tap queue per wave
     if constexpr (LIT) tq = tap_queues<4>() + (threadIdx.x >> 6);
@@ -299,6 +301,11 @@ int launch_persistent(const amr_scene *S, const amr_camera *cams, int32_t ncams,
         set_error("queue_order and xcd_tiles must be 0 or 1");
         return AMR_EINVAL;
     }
+    if (P->waves_per_simd != 0 && P->waves_per_simd != 2 && P->waves_per_simd != 3) {
+        set_error("waves_per_simd must be 0 (default 3), 2 or 3");
+        return AMR_EINVAL;
+    }
+    const bool two = P->waves_per_simd == 2;
     B.xcd_tiles = P->xcd_tiles;
     hipStream_t s = (hipStream_t)stream;
     if (d_stats)
@@ -311,8 +318,11 @@ int launch_persistent(const amr_scene *S, const amr_camera *cams, int32_t ncams,
     const bool rec = d_stats != nullptr;
     if (B.base.lighting) {
         if (rec) hipLaunchKernelGGL((render_batched<true, true, -1>), grid, dim3(256), 0, s, B);
+        else if (B.base.layout == 0 && two) hipLaunchKernelGGL((render_batched<true, false, 0, 2>), grid, dim3(256), 0, s, B);
         else if (B.base.layout == 0) hipLaunchKernelGGL((render_batched<true, false, 0>), grid, dim3(256), 0, s, B);
+        else if (B.base.layout == 1 && two) hipLaunchKernelGGL((render_batched<true, false, 1, 2>), grid, dim3(256), 0, s, B);
         else if (B.base.layout == 1) hipLaunchKernelGGL((render_batched<true, false, 1>), grid, dim3(256), 0, s, B);
+        else if (two) hipLaunchKernelGGL((render_batched<true, false, 2, 2>), grid, dim3(256), 0, s, B);
         else hipLaunchKernelGGL((render_batched<true, false, 2>), grid, dim3(256), 0, s, B);
     } else {
         if (rec) hipLaunchKernelGGL((render_batched<false, true, -1>), grid, dim3(256), 0, s, B);

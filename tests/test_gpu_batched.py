@@ -58,6 +58,28 @@ def test_batched_bit_identical(gpu, tiny, tile, lit, xcd, order):
     assert np.all(st[:-1] > 0) and np.all(st[:-1] >= st[-1])
 
 
+@pytest.mark.parametrize("layout", [0, 1, 2])
+@pytest.mark.parametrize("wps", [2, 3])
+def test_batched_waves_per_simd(gpu, tiny, layout, wps):
+    """The lit persistent kernel compiled for 2 or 3 waves per SIMD (its timed variants, no
+    statistics) renders every image of a batch bit for bit as the single-camera kernel does, in
+    every brick layout."""
+    import torch
+    amr = gpu
+    h, lut, prm, tree, scene = tiny
+    prm = dict(prm, lighting=True)
+    sc = amr.pack(tree, h, device="cuda", brick_layout=layout)
+    cams = _cams(7, seed=5)
+    lut_t = torch.from_numpy(lut).cuda()
+    dc = amr.camera_table(cams)
+    q = amr.queue_buffer(len(cams))
+    out = amr.render(sc, cams, lut_t, dict(prm, persistent=1, blocks_per_cu=2, waves_per_simd=wps), d_cams=dc,
+                     d_queue=q)["rgba"]
+    ref = amr.render(sc, cams, lut_t, prm)["rgba"]
+    torch.cuda.synchronize()
+    assert torch.equal(out, ref)
+
+
 def test_graph_capture_replay(gpu, tiny):
     import torch
     amr = gpu
@@ -110,12 +132,13 @@ def test_autotune_picks_a_candidate(gpu, tiny, tmp_path):
                         cache_path=str(tmp_path / "cache.json"), scenes=scenes)
     assert (res["tile_w"], res["tile_h"]) in autotune.CANDIDATE_TILES
     assert res["xcd_tiles"] in (0, 1) and res["brick_layout"] in (1, 2)
-    assert len(res["table"]) == len(autotune.candidates((1, 2)))
+    assert len(res["table"]) == len(autotune.candidates((1, 2), int(prm.get("lighting", 0)) == 1))
+    assert res["waves_per_simd"] in autotune.CANDIDATE_WPS
     again = autotune.tune(scene, cams, lut_t, prm, dc, q, out, "tiny-test", cache_path=str(tmp_path / "cache.json"))
     assert again == res
     # the chosen configuration renders what the single-camera kernel renders
     best = dict(prm, persistent=1, tile_w=res["tile_w"], tile_h=res["tile_h"], blocks_per_cu=res["blocks_per_cu"],
-                xcd_tiles=res["xcd_tiles"], queue_order=res["queue_order"])
+                waves_per_simd=res["waves_per_simd"], xcd_tiles=res["xcd_tiles"], queue_order=res["queue_order"])
     got = amr.render(scenes[res["brick_layout"]], cams, lut_t, best, d_cams=dc, d_queue=q)["rgba"]
     ref = amr.render(scene, cams, lut_t, prm)["rgba"]
     torch.cuda.synchronize()

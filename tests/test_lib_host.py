@@ -470,7 +470,7 @@ def _render_call(lib, scene, cams, prm, set_fields=None, lut_ok=True):
 
 @pytest.mark.parametrize("case", ["v_range", "step", "cam_size", "interp", "lighting", "lod", "lut", "trace_cap",
                                   "ckpt_odd", "ckpt_small", "tile", "no_queue", "light_no_work", "light_work_small",
-                                  "tape_cap", "tape_align"])
+                                  "tape_cap", "tape_align", "waves_per_simd"])
 def test_render_argument_checks(case):
     """amr_render's argument checks, each of which returns before any device access (host buffers
     stand in for device pointers, so the test runs only where no GPU is visible)."""
@@ -513,6 +513,8 @@ def test_render_argument_checks(case):
     elif case == "light_work_small":
         p, words, want_code = dict(prm, lighting=2), "workspace", 3
         fields = dict(d_work="buf", work_bytes=1 << 16, light_jobs=1 << 20)
+    elif case == "waves_per_simd":
+        p, fields, words = dict(prm, persistent=1, lighting=1, waves_per_simd=4), dict(d_queue="buf"), "waves_per_simd"
     elif case == "tape_cap":
         p, words = dict(prm, lighting=1), "tape_cap"
         fields = dict(d_ckpt="buf", ckpt_bytes=1 << 40, ckpt_every=2, ckpt_max=4, d_tape="buf", tape_cap=1 << 26)
