@@ -35,7 +35,8 @@ namespace amr {
 // CK: checkpoints (and the tape) without the other recording outputs, for the adjoint's forward
 // pass at the layout's compiled addressing.
 template <bool LIT, bool REC, bool NEAR, int LAY, bool CK = false>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void render_fwd(RenderArgs A) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void render_fwd(RenderArgs A, CamGroup G) {
+    take_camera(A, G);
     constexpr bool kDefer = LIT;
     constexpr bool kCk = REC || CK;             // checkpoints (and the tape) may be recorded
     __shared__ float4 s_lut[256];
@@ -505,7 +506,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(LIT ? 3 : 4
 }
 
 // From the tape: the lit intervals whose records all fit are replayed from their segment and
-// sample records alone (no tree walk, no brick reads).  Each lane reads its ray's records a
+// sample records alone (no tree walk, no brick reads), for every camera of the call in one launch
+// (a ray's records need no camera).  Each lane reads its ray's records a
 // group of kTapeGroup at a time (the group's records share cache lines, aligned in the tape):
 // the group arrives with one fetch of its lines, where reading a record at a time would have
 // the lines of the other lanes' streams evict them between reads.
@@ -518,7 +520,7 @@ __global__ __launch_bounds__(256) void render_bwd_tape(RenderArgs A, BwdArgs B) 
     float *acc = s_acc[threadIdx.x >> 6];
     AdjSums gs;
     LutRun run;
-    const int64_t nrays = (int64_t)A.width * A.height;
+    const int64_t nrays = B.nrays;
     const int64_t nitems = nrays * A.ckpt_max;
     const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
     for (int64_t item = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; item < nitems;
@@ -639,6 +641,29 @@ int backward_launch(const amr_scene *S, const amr_camera *cams, int32_t ncams, c
     float *partials = deterministic ? work + kGradLen : nullptr;
     hipLaunchKernelGGL(zero_f32, dim3((kGradLen + 255) / 256), dim3(256), 0, s, grad, kGradLen);
     int rc = check_hip(hipGetLastError(), "adjoint accumulator reset");
+    const dim3 g(kBwdGrid), b(256);
+    // lit with a tape: the intervals the tape holds, every camera in one launch; then, per
+    // camera, the others in place.  Otherwise one launch per camera, every interval in place.
+    bool taped = false;
+    if (rc == AMR_OK && P->lighting == 1 && P->d_tape && P->tape_cap > 0) {
+        RenderArgs A;
+        rc = fill_args(S, &cams[0], P, &A);
+        if (rc == AMR_OK) {
+            A.ckpt_ray0 = 0;
+            BwdArgs B;
+            B.grad_rgba = d_grad_rgba;
+            B.grad = grad;
+            B.partials = partials;
+            B.ray_major = 0;
+            B.nrays = total;
+            hipLaunchKernelGGL(render_bwd_tape, g, b, 0, s, A, B);
+            rc = check_hip(hipGetLastError(), "render_bwd_tape launch");
+            if (rc == AMR_OK && deterministic)
+                hipLaunchKernelGGL(reduce_partials, dim3((kGradLen + 255) / 256), dim3(256), 0, s, partials, kBwdGrid,
+                                   grad);
+            taped = true;
+        }
+    }
     int64_t pix_off = 0;
     for (int c = 0; c < ncams && rc == AMR_OK; c++) {
         RenderArgs A;
@@ -649,15 +674,10 @@ int backward_launch(const amr_scene *S, const amr_camera *cams, int32_t ncams, c
         B.grad_rgba = d_grad_rgba + 4 * pix_off;
         B.grad = grad;
         B.partials = partials;
-        // lit with a tape: the intervals the tape holds, then the others in place; otherwise one
-        // launch
-        const int nl = A.lighting && A.tape ? 2 : 1;
-        for (int l = 0; l < nl && rc == AMR_OK; l++) {
-            B.ray_major = nl == 2 && l == 1;
-            const dim3 g(kBwdGrid), b(256);
-            if (A.lighting && A.tape && l == 0) {
-                hipLaunchKernelGGL(render_bwd_tape, g, b, 0, s, A, B);
-            } else if (A.lighting) {
+        B.nrays = (int64_t)A.width * A.height;
+        {
+            B.ray_major = taped;
+            if (A.lighting) {
                 if (A.layout == 0) hipLaunchKernelGGL((render_bwd<true, 0>), g, b, 0, s, A, B);
                 else if (A.layout == 1) hipLaunchKernelGGL((render_bwd<true, 1>), g, b, 0, s, A, B);
                 else hipLaunchKernelGGL((render_bwd<true, 2>), g, b, 0, s, A, B);
@@ -805,11 +825,56 @@ int amr_render(const amr_scene *S, const amr_camera *cams, int32_t ncams, const 
         int n = (int)(sizeof(amr_render_stats) / 8);
         hipLaunchKernelGGL(zero_u64, dim3(1), dim3(64), 0, s, (unsigned long long *)d_stats, n);
     }
+    // learned proposals and the point light: one launch per camera
+    if (learned || P->lighting == 2) {
+        int64_t pix_off = 0;
+        for (int c = 0; c < ncams; c++) {
+            RenderArgs A;
+            int rc = fill_args(S, &cams[c], P, &A);
+            if (rc) return rc;
+            A.rgba = d_rgba + 4 * pix_off;
+            A.trace = P->d_trace ? P->d_trace + pix_off * P->trace_cap : nullptr;
+            A.trace_cap = P->trace_cap;
+            A.trace_n = P->d_trace_n ? P->d_trace_n + pix_off : nullptr;
+            A.nsamp = P->d_nsamp ? P->d_nsamp + pix_off : nullptr;
+            A.stats = d_stats;
+            A.touch = P->d_touch;
+            A.ckpt_ray0 = pix_off;
+            if (learned) {
+                if (P->d_trace || P->d_ckpt || P->d_touch || P->d_touch_meta) {
+                    set_error("learned proposals / segment logging do not record traces, checkpoints or touch maps");
+                    return AMR_EINVAL;
+                }
+                rc = launch_learned(A, P, S->lmax, stream, c == 0);
+            } else {
+                const bool rec = A.trace || A.trace_n || A.nsamp || A.stats || A.touch || A.touch_meta || A.ckpt;
+                rc = launch_shadow(A, rec, stream, P->d_work, P->work_bytes, P->light_jobs);
+            }
+            if (rc) return rc;
+            pix_off += (int64_t)cams[c].width * cams[c].height;
+        }
+        return AMR_OK;
+    }
+    // the raycaster: up to kCamGroup cameras per launch (blockIdx.y picks the camera), so that
+    // the blocks of several images share the GPU and one image's last blocks do not leave it idle
     int64_t pix_off = 0;
-    for (int c = 0; c < ncams; c++) {
+    for (int c0 = 0; c0 < ncams; c0 += kCamGroup) {
+        const int n = std::min(kCamGroup, ncams - c0);
         RenderArgs A;
-        int rc = fill_args(S, &cams[c], P, &A);
-        if (rc) return rc;
+        CamGroup G;
+        memset(&G, 0, sizeof(G));
+        int gx = 0;
+        int64_t rel = 0;
+        for (int i = 0; i < n; i++) {
+            RenderArgs Ai;
+            int rc = fill_args(S, &cams[c0 + i], P, &Ai);
+            if (rc) return rc;
+            if (i == 0) A = Ai;
+            G.cam[i] = cam_args_of(Ai, rel);
+            gx = std::max(gx, 8 * ((Ai.sgrid * Ai.sgrid + 7) / 8) * 16);
+            rel += (int64_t)cams[c0 + i].width * cams[c0 + i].height;
+        }
+        G.n = n > 1 ? n : 0;
         A.rgba = d_rgba + 4 * pix_off;
         A.trace = P->d_trace ? P->d_trace + pix_off * P->trace_cap : nullptr;
         A.trace_cap = P->trace_cap;
@@ -818,58 +883,41 @@ int amr_render(const amr_scene *S, const amr_camera *cams, int32_t ncams, const 
         A.stats = d_stats;
         A.touch = P->d_touch;
         A.ckpt_ray0 = pix_off;
-        if (learned) {
-            if (P->d_trace || P->d_ckpt || P->d_touch || P->d_touch_meta) {
-                set_error("learned proposals / segment logging do not record traces, checkpoints or touch maps");
-                return AMR_EINVAL;
-            }
-            rc = launch_learned(A, P, S->lmax, stream, c == 0);
-            if (rc) return rc;
-            pix_off += (int64_t)cams[c].width * cams[c].height;
-            continue;
-        }
-        const int grid = 8 * ((A.sgrid * A.sgrid + 7) / 8) * 16;
         const bool rec = A.trace || A.trace_n || A.nsamp || A.stats || A.touch || A.touch_meta || A.ckpt;
-        if (A.lighting == 2) {
-            rc = launch_shadow(A, rec, stream, P->d_work, P->work_bytes, P->light_jobs);
-            if (rc) return rc;
-            pix_off += (int64_t)cams[c].width * cams[c].height;
-            continue;
-        }
-        const dim3 g(grid), b(64);
+        const dim3 g(gx, n), b(64);
         if (A.nearest) {
             if (A.lighting) {
-                if (rec) hipLaunchKernelGGL((render_fwd<true, true, true, -1>), g, b, 0, s, A);
-                else hipLaunchKernelGGL((render_fwd<true, false, true, -1>), g, b, 0, s, A);
+                if (rec) hipLaunchKernelGGL((render_fwd<true, true, true, -1>), g, b, 0, s, A, G);
+                else hipLaunchKernelGGL((render_fwd<true, false, true, -1>), g, b, 0, s, A, G);
             } else {
-                if (rec) hipLaunchKernelGGL((render_fwd<false, true, true, -1>), g, b, 0, s, A);
-                else hipLaunchKernelGGL((render_fwd<false, false, true, -1>), g, b, 0, s, A);
+                if (rec) hipLaunchKernelGGL((render_fwd<false, true, true, -1>), g, b, 0, s, A, G);
+                else hipLaunchKernelGGL((render_fwd<false, false, true, -1>), g, b, 0, s, A, G);
             }
         } else if (rec && !(A.ckpt && !A.trace && !A.trace_n && !A.nsamp && !A.stats && !A.touch && !A.touch_meta)) {
-            if (A.lighting) hipLaunchKernelGGL((render_fwd<true, true, false, -1>), g, b, 0, s, A);
-            else hipLaunchKernelGGL((render_fwd<false, true, false, -1>), g, b, 0, s, A);
+            if (A.lighting) hipLaunchKernelGGL((render_fwd<true, true, false, -1>), g, b, 0, s, A, G);
+            else hipLaunchKernelGGL((render_fwd<false, true, false, -1>), g, b, 0, s, A, G);
         } else if (A.ckpt) {       // checkpoints (and the tape) only: the adjoint's forward pass
             if (A.lighting) {
-                if (A.layout == 0) hipLaunchKernelGGL((render_fwd<true, false, false, 0, true>), g, b, 0, s, A);
-                else if (A.layout == 1) hipLaunchKernelGGL((render_fwd<true, false, false, 1, true>), g, b, 0, s, A);
-                else hipLaunchKernelGGL((render_fwd<true, false, false, 2, true>), g, b, 0, s, A);
+                if (A.layout == 0) hipLaunchKernelGGL((render_fwd<true, false, false, 0, true>), g, b, 0, s, A, G);
+                else if (A.layout == 1) hipLaunchKernelGGL((render_fwd<true, false, false, 1, true>), g, b, 0, s, A, G);
+                else hipLaunchKernelGGL((render_fwd<true, false, false, 2, true>), g, b, 0, s, A, G);
             } else {
-                if (A.layout == 0) hipLaunchKernelGGL((render_fwd<false, false, false, 0, true>), g, b, 0, s, A);
-                else if (A.layout == 1) hipLaunchKernelGGL((render_fwd<false, false, false, 1, true>), g, b, 0, s, A);
-                else hipLaunchKernelGGL((render_fwd<false, false, false, 2, true>), g, b, 0, s, A);
+                if (A.layout == 0) hipLaunchKernelGGL((render_fwd<false, false, false, 0, true>), g, b, 0, s, A, G);
+                else if (A.layout == 1) hipLaunchKernelGGL((render_fwd<false, false, false, 1, true>), g, b, 0, s, A, G);
+                else hipLaunchKernelGGL((render_fwd<false, false, false, 2, true>), g, b, 0, s, A, G);
             }
         } else if (A.lighting) {   // the timed variants, one per brick layout
-            if (A.layout == 0) hipLaunchKernelGGL((render_fwd<true, false, false, 0>), g, b, 0, s, A);
-            else if (A.layout == 1) hipLaunchKernelGGL((render_fwd<true, false, false, 1>), g, b, 0, s, A);
-            else hipLaunchKernelGGL((render_fwd<true, false, false, 2>), g, b, 0, s, A);
+            if (A.layout == 0) hipLaunchKernelGGL((render_fwd<true, false, false, 0>), g, b, 0, s, A, G);
+            else if (A.layout == 1) hipLaunchKernelGGL((render_fwd<true, false, false, 1>), g, b, 0, s, A, G);
+            else hipLaunchKernelGGL((render_fwd<true, false, false, 2>), g, b, 0, s, A, G);
         } else {
-            if (A.layout == 0) hipLaunchKernelGGL((render_fwd<false, false, false, 0>), g, b, 0, s, A);
-            else if (A.layout == 1) hipLaunchKernelGGL((render_fwd<false, false, false, 1>), g, b, 0, s, A);
-            else hipLaunchKernelGGL((render_fwd<false, false, false, 2>), g, b, 0, s, A);
+            if (A.layout == 0) hipLaunchKernelGGL((render_fwd<false, false, false, 0>), g, b, 0, s, A, G);
+            else if (A.layout == 1) hipLaunchKernelGGL((render_fwd<false, false, false, 1>), g, b, 0, s, A, G);
+            else hipLaunchKernelGGL((render_fwd<false, false, false, 2>), g, b, 0, s, A, G);
         }
-        rc = check_hip(hipGetLastError(), "render_fwd launch");
+        int rc = check_hip(hipGetLastError(), "render_fwd launch");
         if (rc) return rc;
-        pix_off += (int64_t)cams[c].width * cams[c].height;
+        pix_off += rel;
     }
     return AMR_OK;
 }

@@ -77,11 +77,78 @@ struct RenderArgs {
                                            // grid of 4x4-tile super-tiles covering them
 };
 
+// The per-camera fields of RenderArgs, for launches that render a group of cameras (one camera
+// per blockIdx.y): each block takes its camera's fields and its pixel offset in the outputs.
+struct CamArgs {
+    double eye[3], u[3], v[3], w[3];
+    double tanf, win0, win1, lod_pix;
+    int32_t ortho, width, height, t8x, t8y, sgrid;
+    int64_t ray0;                    // the camera's first pixel, relative to the group's first
+};
+constexpr int kCamGroup = 8;
+struct CamGroup {
+    CamArgs cam[kCamGroup];
+    int32_t n;                       // cameras in the group; 0: one camera, RenderArgs as given
+};
+static_assert(sizeof(RenderArgs) + sizeof(CamGroup) <= 4096, "kernel arguments of a group launch");
+
+inline CamArgs cam_args_of(const RenderArgs &A, int64_t ray0) {
+    CamArgs C;
+    for (int a = 0; a < 3; a++) {
+        C.eye[a] = A.eye[a];
+        C.u[a] = A.u[a];
+        C.v[a] = A.v[a];
+        C.w[a] = A.w[a];
+    }
+    C.tanf = A.tanf;
+    C.win0 = A.win0;
+    C.win1 = A.win1;
+    C.lod_pix = A.lod_pix;
+    C.ortho = A.ortho;
+    C.width = A.width;
+    C.height = A.height;
+    C.t8x = A.t8x;
+    C.t8y = A.t8y;
+    C.sgrid = A.sgrid;
+    C.ray0 = ray0;
+    return C;
+}
+
+// A block of a group launch takes its camera (blockIdx.y) into A.
+__device__ __forceinline__ void take_camera(RenderArgs &A, const CamGroup &G) {
+    if (G.n == 0) return;
+    const CamArgs &C = G.cam[blockIdx.y];
+    #pragma unroll
+    for (int a = 0; a < 3; a++) {
+        A.eye[a] = C.eye[a];
+        A.u[a] = C.u[a];
+        A.v[a] = C.v[a];
+        A.w[a] = C.w[a];
+    }
+    A.tanf = C.tanf;
+    A.win0 = C.win0;
+    A.win1 = C.win1;
+    A.lod_pix = C.lod_pix;
+    A.ortho = C.ortho;
+    A.width = C.width;
+    A.height = C.height;
+    A.t8x = C.t8x;
+    A.t8y = C.t8y;
+    A.sgrid = C.sgrid;
+    A.rgba += 4 * C.ray0;
+    if (A.trace) A.trace += C.ray0 * A.trace_cap;
+    if (A.trace_n) A.trace_n += C.ray0;
+    if (A.nsamp) A.nsamp += C.ray0;
+    A.ckpt_ray0 += C.ray0;
+}
+
 struct BwdArgs {
     const float *grad_rgba;
     float *grad;                     // kGradLen accumulator
     float *partials;                 // deterministic: [grid][kGradLen]
     int32_t ray_major;               // work items numbered ray by ray (else interval by interval)
+    int64_t nrays;                   // rays the launch covers, from A.ckpt_ray0 (the tape kernel
+                                     // covers every camera of the call at once)
 };
 
 struct Counters {   // per lane (32-bit); summed over the wave in 64 bits when flushed
