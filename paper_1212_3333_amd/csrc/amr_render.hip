@@ -419,7 +419,7 @@ __device__ __forceinline__ void adjoint_block_end(const BwdArgs &B, float (*s_ac
     __syncthreads();
     for (int i = threadIdx.x; i < kGradLen; i += blockDim.x) {
         float v = ((s_acc[0][i] + s_acc[1][i]) + s_acc[2][i]) + s_acc[3][i];
-        if (B.partials) B.partials[(int64_t)blockIdx.x * kGradLen + i] = v;
+        if (B.partials) B.partials[((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * kGradLen + i] = v;
         else if (v != 0.f) atomicAdd(&B.grad[i], v);
     }
 }
@@ -432,14 +432,18 @@ __device__ __forceinline__ int interval_records_end(const CkptHeader &hd, const 
 
 // In place: every sample of the interval is evaluated again (tree walk from the checkpoint,
 // stencil, tap resolution).  Serves the unlit adjoint, lit renders without a tape, and the lit
-// intervals whose tape records did not all fit.  Work items run interval by interval (the
+// intervals whose tape records did not all fit.  Up to kCamGroup cameras per launch, one per
+// blockIdx.y (their blocks split the fixed grid).  Work items run interval by interval (the
 // lanes of a wave take neighbouring rays at one interval) when every interval is served here,
 // and ray by ray (consecutive lanes take one ray's intervals) when only the tape's leftovers
 // are: those are the late intervals of the longest rays, which would otherwise queue up on
 // few threads.
 // LAY: the brick layout fixed at compile time (-1: read at run time).
 template <bool LIT, int LAY>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(LIT ? 3 : 4))) void render_bwd(RenderArgs A, BwdArgs B) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(LIT ? 3 : 4))) void render_bwd(RenderArgs A, BwdArgs B,
+                                                                                                     CamGroup G) {
+    take_camera(A, G);
+    if (G.n) B.grad_rgba += 4 * G.cam[blockIdx.y].ray0;
     __shared__ float4 s_lut[256];
     __shared__ float s_acc[4][kGradLen];      // one accumulator per wave
     adjoint_block_begin(A, s_lut, s_acc);
@@ -664,35 +668,46 @@ int backward_launch(const amr_scene *S, const amr_camera *cams, int32_t ncams, c
             taped = true;
         }
     }
+    // in place, up to kCamGroup cameras per launch, the fixed grid's blocks split among them
     int64_t pix_off = 0;
-    for (int c = 0; c < ncams && rc == AMR_OK; c++) {
+    for (int c0 = 0; c0 < ncams && rc == AMR_OK; c0 += kCamGroup) {
+        const int n = std::min(kCamGroup, ncams - c0);
         RenderArgs A;
-        rc = fill_args(S, &cams[c], P, &A);
+        CamGroup G;
+        memset(&G, 0, sizeof(G));
+        int64_t rel = 0;
+        for (int i = 0; i < n && rc == AMR_OK; i++) {
+            RenderArgs Ai;
+            rc = fill_args(S, &cams[c0 + i], P, &Ai);
+            if (rc) break;
+            if (i == 0) A = Ai;
+            G.cam[i] = cam_args_of(Ai, rel);
+            rel += (int64_t)cams[c0 + i].width * cams[c0 + i].height;
+        }
         if (rc) break;
+        G.n = n > 1 ? n : 0;
         A.ckpt_ray0 = pix_off;
         BwdArgs B;
         B.grad_rgba = d_grad_rgba + 4 * pix_off;
         B.grad = grad;
         B.partials = partials;
-        B.nrays = (int64_t)A.width * A.height;
-        {
-            B.ray_major = taped;
-            if (A.lighting) {
-                if (A.layout == 0) hipLaunchKernelGGL((render_bwd<true, 0>), g, b, 0, s, A, B);
-                else if (A.layout == 1) hipLaunchKernelGGL((render_bwd<true, 1>), g, b, 0, s, A, B);
-                else hipLaunchKernelGGL((render_bwd<true, 2>), g, b, 0, s, A, B);
-            } else {
-                if (A.layout == 0) hipLaunchKernelGGL((render_bwd<false, 0>), g, b, 0, s, A, B);
-                else if (A.layout == 1) hipLaunchKernelGGL((render_bwd<false, 1>), g, b, 0, s, A, B);
-                else hipLaunchKernelGGL((render_bwd<false, 2>), g, b, 0, s, A, B);
-            }
-            rc = check_hip(hipGetLastError(), "render_bwd launch");
-            if (rc == AMR_OK && deterministic)
-                hipLaunchKernelGGL(reduce_partials, dim3((kGradLen + 255) / 256), dim3(256), 0, s, partials, kBwdGrid,
-                                   grad);
+        B.nrays = (int64_t)A.width * A.height;     // one camera's (taken per block)
+        B.ray_major = taped;
+        const dim3 gg(kBwdGrid / n, n);
+        if (A.lighting) {
+            if (A.layout == 0) hipLaunchKernelGGL((render_bwd<true, 0>), gg, b, 0, s, A, B, G);
+            else if (A.layout == 1) hipLaunchKernelGGL((render_bwd<true, 1>), gg, b, 0, s, A, B, G);
+            else hipLaunchKernelGGL((render_bwd<true, 2>), gg, b, 0, s, A, B, G);
+        } else {
+            if (A.layout == 0) hipLaunchKernelGGL((render_bwd<false, 0>), gg, b, 0, s, A, B, G);
+            else if (A.layout == 1) hipLaunchKernelGGL((render_bwd<false, 1>), gg, b, 0, s, A, B, G);
+            else hipLaunchKernelGGL((render_bwd<false, 2>), gg, b, 0, s, A, B, G);
         }
-        if (rc) break;
-        pix_off += (int64_t)cams[c].width * cams[c].height;
+        rc = check_hip(hipGetLastError(), "render_bwd launch");
+        if (rc == AMR_OK && deterministic)
+            hipLaunchKernelGGL(reduce_partials, dim3((kGradLen + 255) / 256), dim3(256), 0, s, partials,
+                               (int)(gg.x * gg.y), grad);
+        pix_off += rel;
     }
     if (rc == AMR_OK) {
         hipLaunchKernelGGL(split_grad, dim3((kGradLen + 255) / 256), dim3(256), 0, s, grad, d_grad_lut, d_grad_light);
