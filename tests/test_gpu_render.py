@@ -415,3 +415,66 @@ def test_point_light_rejected_elsewhere(gpu):
         amr.render(scene, two, lut_t, dict(prm, lighting=2, persistent=1), d_cams=amr.camera_table(two),
                    d_queue=amr.queue_buffer(2))
 
+
+
+def _orbit_cams(n, seed):
+    rng = np.random.default_rng(seed)
+    sizes = [(40, 24), (64, 64), (17, 33), (48, 40), (8, 8), (72, 56), (33, 17), (56, 48), (24, 40), (64, 24)]
+    return [workloads.perspective_orbit(sizes[i % len(sizes)][0], sizes[i % len(sizes)][1],
+                                        float(rng.uniform(0, 2 * math.pi)), float(rng.uniform(-0.6, 0.6)),
+                                        radius=float(rng.uniform(1.5, 2.5))) for i in range(n)]
+
+
+@pytest.mark.parametrize("mode", ["timed", "recording", "checkpoints"])
+@pytest.mark.parametrize("lit", [False, True])
+def test_camera_groups_match_single_camera_launches(gpu, lit, mode):
+    """Several cameras in one amr_render call are rendered up to 8 per launch (one camera per
+    blockIdx.y).  Ten cameras of different sizes (two launches: 8 and 2) against one call per
+    camera: images, per-ray sample counts and segment traces (recording kernels), checkpoint
+    records and the lit tape (checkpointed kernels) are bit-identical."""
+    import torch
+    amr = gpu
+    h, lut, cams, prm = workloads.small_nested(1)
+    prm = dict(prm, lighting=lit)
+    tree, scene = _setup(amr, h, layout=2)
+    lut_t = torch.from_numpy(lut).cuda()
+    cl = _orbit_cams(10, seed=21)
+    npix = [c["width"] * c["height"] for c in cl]
+    if mode == "checkpoints":
+        out, ck = amr.render_checkpointed(scene, cl, lut_t, prm, ckpt_every=2, ckpt_max=8, tape_cap=256 if lit else 0)
+        torch.cuda.synchronize()
+        off = 0
+        for c, cam in enumerate(cl):
+            o1, k1 = amr.render_checkpointed(scene, cam, lut_t, prm, ckpt_every=2, ckpt_max=8,
+                                             tape_cap=256 if lit else 0)
+            torch.cuda.synchronize()
+            assert torch.equal(out["rgba"].view(-1, 4)[off:off + npix[c]], o1["rgba"].view(-1, 4)), c
+            # per ray a 32-byte header and up to 8 32-byte checkpoints, of which the first nck are
+            # written; the tape rows hold nrec records, of which the first 256 are written
+            a = ck.buf.view(sum(npix), 9, 32)[off:off + npix[c]].cpu().numpy()
+            b = k1.buf.view(npix[c], 9, 32).cpu().numpy()
+            assert np.array_equal(a[:, 0], b[:, 0]), c
+            nck = b[:, 0].copy().view(np.int32)[:, 5]
+            for r in range(npix[c]):
+                assert np.array_equal(a[r, 1:1 + nck[r]], b[r, 1:1 + nck[r]]), (c, r)
+            if lit:
+                nrec = np.minimum(b[:, 0].copy().view(np.int32)[:, 7], 256)
+                ta = ck.tape.view(sum(npix), 256, 4)[off:off + npix[c]].cpu().numpy()
+                tb = k1.tape.view(npix[c], 256, 4).cpu().numpy()
+                for r in range(npix[c]):
+                    assert np.array_equal(ta[r, :nrec[r]], tb[r, :nrec[r]]), (c, r)
+            off += npix[c]
+        return
+    kw = dict(trace_cap=64, nsamp=True, stats=True) if mode == "recording" else {}
+    out = amr.render(scene, cl, lut_t, prm, **kw)
+    torch.cuda.synchronize()
+    off = 0
+    for c, cam in enumerate(cl):
+        o1 = amr.render(scene, cam, lut_t, prm, **kw)
+        torch.cuda.synchronize()
+        assert torch.equal(out["rgba"].view(-1, 4)[off:off + npix[c]], o1["rgba"].view(-1, 4)), c
+        if mode == "recording":
+            assert torch.equal(out["nsamp"][off:off + npix[c]], o1["nsamp"]), c
+            assert torch.equal(out["trace_n"][off:off + npix[c]], o1["trace_n"]), c
+            assert torch.equal(out["trace_raw"][off:off + npix[c]], o1["trace_raw"]), c
+        off += npix[c]
