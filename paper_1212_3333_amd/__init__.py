@@ -378,7 +378,8 @@ def render(scene: Scene, cams, lut: torch.Tensor, params: dict, trace_cap: int =
     st = torch.zeros(16, dtype=torch.int64, device=dev) if stats else None
     for k in ("d_ckpt", "ckpt_bytes", "ckpt_every", "ckpt_max", "d_tape", "tape_cap", "d_mlp", "d_seglog", "seglog_cap",
               "d_queue",
-              "d_stamps", "d_touch", "d_touch_meta", "d_cams", "d_work", "work_bytes", "light_jobs"):
+              "d_stamps", "d_touch", "d_touch_meta", "d_cams", "d_work", "work_bytes", "light_jobs", "d_sched",
+              "sched_bytes"):
         if k in extra:
             v = extra[k]
             setattr(q, k, v.data_ptr() if isinstance(v, torch.Tensor) else v)
@@ -500,6 +501,27 @@ def default_tape_cap(nrays: int, device=None, total_memory: int | None = None) -
     return max(0, min(TAPE_CAP, cap // 8 * 8))
 
 
+class Schedule:
+    """Tile schedule for repeated renders of the same cameras (amr_sched_bytes; pass **params()
+    to render): every call records each 8x8 tile's time, and the next call renders the tiles
+    longest first.  Zeroed at creation; reset() forgets the recorded order (after a large camera
+    change)."""
+
+    def __init__(self, cams, device):
+        lib = load()
+        cam_list, carr = _cams(cams)
+        self.nbytes = int(lib.amr_sched_bytes(carr, len(cam_list)))
+        if self.nbytes < 0:
+            raise ValueError("invalid cameras")
+        self.buf = torch.zeros(self.nbytes, dtype=torch.uint8, device=device)
+
+    def params(self) -> dict:
+        return dict(d_sched=self.buf, sched_bytes=self.nbytes)
+
+    def reset(self) -> None:
+        self.buf.zero_()
+
+
 class Checkpoints:
     """Device buffers the checkpointed forward fills and the adjoint reads: per ray a header
     (final T and C, samples, checkpoint count, tape records) and up to ckpt_max (t, T, C) records
@@ -578,13 +600,17 @@ def render_backward(scene: Scene, cams, lut: torch.Tensor, params: dict, ckpt: C
 class AMRRender(torch.autograd.Function):
     """Differentiable render: rgba = AMRRender.apply(lut [256,4], shading [5] = (light xyz, k_a,
     k_d), scene, cams, params).  Gradients flow to the LUT and the shading parameters through
-    the library's adjoint kernel; the forward keeps segment checkpoints, not samples."""
+    the library's adjoint kernel; the forward keeps segment checkpoints and, lit, the sample
+    tape.  schedule: an optional Schedule for these cameras, kept across calls (an optimisation
+    loop renders the same views every step)."""
 
     @staticmethod
-    def forward(ctx, lut, shading, scene, cams, params, ckpt_every=4, ckpt_max=16, deterministic=False):
+    def forward(ctx, lut, shading, scene, cams, params, ckpt_every=4, ckpt_max=16, deterministic=False,
+                schedule=None):
         sh = shading.detach().double().cpu().tolist()
         prm = dict(params, light=tuple(sh[:3]), k_a=sh[3], k_d=sh[4])
-        out, ck = render_checkpointed(scene, cams, lut.detach(), prm, ckpt_every, ckpt_max)
+        kw = schedule.params() if schedule is not None else {}
+        out, ck = render_checkpointed(scene, cams, lut.detach(), prm, ckpt_every, ckpt_max, **kw)
         ctx.scene, ctx.cams, ctx.prm, ctx.ck, ctx.det = scene, cams, prm, ck, deterministic
         ctx.lut = lut.detach().to(device=scene.pool.device, dtype=torch.float32).contiguous()
         ctx.lut_device, ctx.sh_device = lut.device, shading.device
@@ -593,4 +619,4 @@ class AMRRender(torch.autograd.Function):
     @staticmethod
     def backward(ctx, grad_rgba):
         glut, glight = render_backward(ctx.scene, ctx.cams, ctx.lut, ctx.prm, ctx.ck, grad_rgba, ctx.det)
-        return glut.to(ctx.lut_device), glight.to(ctx.sh_device), None, None, None, None, None, None
+        return glut.to(ctx.lut_device), glight.to(ctx.sh_device), None, None, None, None, None, None, None

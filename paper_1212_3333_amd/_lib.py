@@ -109,7 +109,8 @@ class amr_render_params(ctypes.Structure):
                 ("d_queue", VP), ("d_stamps", VP), ("d_cams", VP), ("d_touch", VP),
                 ("d_work", VP), ("work_bytes", ctypes.c_int64), ("light_jobs", ctypes.c_int64),
                 ("d_touch_meta", VP), ("bound_only", ctypes.c_int32), ("queue_order", ctypes.c_int32),
-                ("xcd_tiles", ctypes.c_int32), ("waves_per_simd", ctypes.c_int32)]
+                ("xcd_tiles", ctypes.c_int32), ("waves_per_simd", ctypes.c_int32), ("pad3_", ctypes.c_int32),
+                ("d_sched", VP), ("sched_bytes", ctypes.c_int64)]
 
 
 class amr_seglog_rec(ctypes.Structure):
@@ -142,6 +143,7 @@ SIGNATURES = {
     "amr_wall_clock_khz": (ctypes.c_int64, []),
     "amr_ckpt_bytes": (ctypes.c_int64, [ctypes.c_int64, ctypes.c_int32]),
     "amr_tape_bytes": (ctypes.c_int64, [ctypes.c_int64, ctypes.c_int64]),
+    "amr_sched_bytes": (ctypes.c_int64, [ctypes.POINTER(amr_camera), ctypes.c_int32]),
     "amr_render_work_bytes": (ctypes.c_int64, [ctypes.POINTER(amr_camera), ctypes.c_int32,
                                                ctypes.POINTER(amr_render_params)]),
     "amr_backward_work_bytes": (ctypes.c_int64, [ctypes.c_int32]),

@@ -50,17 +50,30 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void re
     // and XCD x renders super-tiles x, x + 8, x + 16, ...  Every XCD thus gets a share of every
     // part of the image (the work per tile varies by 10x and more across the screen), while
     // the tiles in flight on one XCD stay grouped in a few compact 32x32 patches whose rays
-    // share bricks in that XCD's L2.
-    const int xcd = (int)(blockIdx.x % 8), li = (int)(blockIdx.x / 8);
-    const int sidx = (li >> 4) * 8 + xcd;          // Morton index of the super-tile
-    int sx = 0, sy = 0;
-    #pragma unroll
-    for (int bit = 0; bit < 12; bit++) {
-        sx |= ((sidx >> (2 * bit)) & 1) << bit;
-        sy |= ((sidx >> (2 * bit + 1)) & 1) << bit;
+    // share bricks in that XCD's L2.  With a tile schedule sorted for this camera's tile count,
+    // block b takes the b-th longest tile of the last call instead (dealt to the XCDs in turn).
+    const uint32_t ntile = (uint32_t)A.t8x * (uint32_t)A.t8y;
+    int col, row;
+    if (A.sched_hdr && A.sched_hdr[4 * A.cam] == ntile) {
+        if (blockIdx.x >= ntile) return;
+        const uint32_t tl = A.sched_order[A.tile0 + blockIdx.x];
+        if (tl >= ntile) return;             // never for an order the library wrote
+        col = (int)(tl % (uint32_t)A.t8x);
+        row = (int)(tl / (uint32_t)A.t8x);
+    } else {
+        const int xcd = (int)(blockIdx.x % 8), li = (int)(blockIdx.x / 8);
+        const int sidx = (li >> 4) * 8 + xcd;          // Morton index of the super-tile
+        int sx = 0, sy = 0;
+        #pragma unroll
+        for (int bit = 0; bit < 12; bit++) {
+            sx |= ((sidx >> (2 * bit)) & 1) << bit;
+            sy |= ((sidx >> (2 * bit + 1)) & 1) << bit;
+        }
+        col = sx * 4 + ((li & 15) >> 2);
+        row = sy * 4 + (li & 3);
     }
-    const int col = sx * 4 + ((li & 15) >> 2), row = sy * 4 + (li & 3);
     if (col >= A.t8x || row >= A.t8y) return;
+    const unsigned long long tile_t0 = A.sched_time ? wall_clock64() : 0ull;
     const int lane = threadIdx.x & 63;
     const int pi = col * 8 + (lane & 7);
     const int pj = row * 8 + (lane >> 3);
@@ -269,6 +282,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void re
             }
             tcur = tb;
         }
+    }
+    if (A.sched_time && lane == 0) {
+        const unsigned long long dt = wall_clock64() - tile_t0;
+        A.sched_time[A.tile0 + (int64_t)row * A.t8x + col] = dt < 0xffffffffull ? (uint32_t)dt : 0xffffffffu;
     }
     if (valid) {
         reinterpret_cast<float4 *>(A.rgba)[ray] = make_float4(C0, C1, C2, 1.f - T);
@@ -591,6 +608,49 @@ __global__ __launch_bounds__(256) void render_bwd_tape(RenderArgs A, BwdArgs B) 
     adjoint_block_end<true>(B, s_acc, gs);
 }
 
+// Tile schedule for the next call: the tiles of each camera of a launch ordered by the time they
+// took, longest first (a counting sort over 512 logarithmic buckets, 16 per octave of the wall
+// clock's ticks; the order within a bucket is arbitrary), one block per camera; the camera's
+// header then records the tile count the order was sorted for.
+struct SchedGroup {
+    int64_t tile0[kCamGroup];
+    int32_t ntiles[kCamGroup];
+    int32_t cam[kCamGroup];
+};
+constexpr int kSchedBuckets = 512;
+
+__device__ __forceinline__ int sched_bucket(uint32_t t) {
+    if (t < 16u) return (int)t;
+    const int msb = 31 - __builtin_clz(t);
+    return min(kSchedBuckets - 1, (msb - 3) * 16 + (int)((t >> (msb - 4)) & 15u));
+}
+
+__global__ __launch_bounds__(1024) void sched_sort(uint32_t *hdr, const uint32_t *time, uint32_t *order,
+                                                   SchedGroup G) {
+    __shared__ uint32_t cnt[kSchedBuckets], cur[kSchedBuckets];
+    const int c = blockIdx.x;
+    const int64_t t0 = G.tile0[c];
+    const uint32_t n = (uint32_t)G.ntiles[c];
+    for (int i = threadIdx.x; i < kSchedBuckets; i += blockDim.x) cnt[i] = 0u;
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) atomicAdd(&cnt[sched_bucket(time[t0 + i])], 1u);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t s = 0u;
+        for (int b = kSchedBuckets - 1; b >= 0; b--) {
+            cur[b] = s;
+            s += cnt[b];
+        }
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
+        const uint32_t pos = atomicAdd(&cur[sched_bucket(time[t0 + i])], 1u);
+        order[t0 + pos] = i;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) hdr[4 * G.cam[c]] = n;
+}
+
 // Fixed-order sum of per-block partials (deterministic adjoint).
 __global__ void reduce_partials(const float *partials, int nblocks, float *grad) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -768,6 +828,16 @@ int amr_render_backward_static(const amr_scene *S, const amr_camera *cams, int32
     return backward_launch(S, cams, ncams, P, d_grad_rgba, d_grad_lut, d_grad_light, deterministic, work, stream);
 }
 
+int64_t amr_sched_bytes(const amr_camera *cams, int32_t ncams) {
+    if (!cams || ncams <= 0) return -1;
+    int64_t ntot = 0;
+    for (int c = 0; c < ncams; c++) {
+        if (cams[c].width <= 0 || cams[c].height <= 0) return -1;
+        ntot += sched_tiles(cams[c]);
+    }
+    return 4 * (sched_header_words(ncams) + 2 * ntot);
+}
+
 int64_t amr_tape_bytes(int64_t nrays, int64_t tape_cap) {
     if (nrays < 0 || tape_cap < 0) return 0;
     return nrays * tape_cap * (int64_t)sizeof(float4);
@@ -812,6 +882,22 @@ int amr_render(const amr_scene *S, const amr_camera *cams, int32_t ncams, const 
         }
     }
     const bool learned = P->d_mlp || P->d_seglog || P->bound_only;
+    if (P->d_sched) {
+        if (P->persistent || learned || P->lighting == 2) {
+            set_error("the tile schedule (d_sched) serves the raycaster's single-camera kernels only (not persistent "
+                      "mode, learned proposals or the point light)");
+            return AMR_EINVAL;
+        }
+        const int64_t need = amr_sched_bytes(cams, ncams);
+        if (need < 0 || P->sched_bytes < need) {
+            set_error("sched_bytes %lld < %lld", (long long)P->sched_bytes, (long long)need);
+            return AMR_ECAPACITY;
+        }
+        if (reinterpret_cast<uintptr_t>(P->d_sched) & 3u) {
+            set_error("d_sched must be 4-byte aligned");
+            return AMR_EINVAL;
+        }
+    }
     if (P->d_mlp && (reinterpret_cast<uintptr_t>(P->d_mlp) & 15u)) {
         set_error("d_mlp must be 16-byte aligned");
         return AMR_EINVAL;
@@ -872,24 +958,40 @@ int amr_render(const amr_scene *S, const amr_camera *cams, int32_t ncams, const 
     }
     // the raycaster: up to kCamGroup cameras per launch (blockIdx.y picks the camera), so that
     // the blocks of several images share the GPU and one image's last blocks do not leave it idle
-    int64_t pix_off = 0;
+    uint32_t *sched = (uint32_t *)P->d_sched;
+    int64_t sched_ntot = 0;
+    for (int c = 0; c < ncams; c++) sched_ntot += sched_tiles(cams[c]);
+    uint32_t *sched_time = sched ? sched + sched_header_words(ncams) : nullptr;
+    uint32_t *sched_order = sched ? sched_time + sched_ntot : nullptr;
+    int64_t pix_off = 0, tile_off = 0;
     for (int c0 = 0; c0 < ncams; c0 += kCamGroup) {
         const int n = std::min(kCamGroup, ncams - c0);
         RenderArgs A;
         CamGroup G;
         memset(&G, 0, sizeof(G));
+        SchedGroup SG;
+        memset(&SG, 0, sizeof(SG));
         int gx = 0;
         int64_t rel = 0;
         for (int i = 0; i < n; i++) {
             RenderArgs Ai;
             int rc = fill_args(S, &cams[c0 + i], P, &Ai);
             if (rc) return rc;
+            Ai.tile0 = tile_off;
+            Ai.cam = c0 + i;
             if (i == 0) A = Ai;
             G.cam[i] = cam_args_of(Ai, rel);
             gx = std::max(gx, 8 * ((Ai.sgrid * Ai.sgrid + 7) / 8) * 16);
+            SG.tile0[i] = tile_off;
+            SG.ntiles[i] = (int32_t)sched_tiles(cams[c0 + i]);
+            SG.cam[i] = c0 + i;
             rel += (int64_t)cams[c0 + i].width * cams[c0 + i].height;
+            tile_off += sched_tiles(cams[c0 + i]);
         }
         G.n = n > 1 ? n : 0;
+        A.sched_hdr = sched;
+        A.sched_time = sched_time;
+        A.sched_order = sched_order;
         A.rgba = d_rgba + 4 * pix_off;
         A.trace = P->d_trace ? P->d_trace + pix_off * P->trace_cap : nullptr;
         A.trace_cap = P->trace_cap;
@@ -932,6 +1034,11 @@ int amr_render(const amr_scene *S, const amr_camera *cams, int32_t ncams, const 
         }
         int rc = check_hip(hipGetLastError(), "render_fwd launch");
         if (rc) return rc;
+        if (sched) {
+            hipLaunchKernelGGL(sched_sort, dim3(n), dim3(1024), 0, s, sched, sched_time, sched_order, SG);
+            rc = check_hip(hipGetLastError(), "tile schedule sort");
+            if (rc) return rc;
+        }
         pix_off += rel;
     }
     return AMR_OK;

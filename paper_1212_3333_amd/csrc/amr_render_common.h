@@ -72,6 +72,11 @@ struct RenderArgs {
     int32_t ckpt_every, ckpt_max;
     float4 *tape;                    // checkpointed lit forward: per ray, a record per data
     int64_t tape_cap;                // segment and per sample ([rays][tape_cap]; see TapeSeg)
+    uint32_t *sched_hdr;             // tile schedule (null: none): per camera the tile count its
+    uint32_t *sched_time;            // order was sorted for (4 words each); per tile its time in
+    uint32_t *sched_order;           // the last call; per camera its tiles, longest first
+    int64_t tile0;                   // this camera's first tile in the schedule
+    int32_t cam;                     // this camera's index in the call
     int32_t tiles_x, tiles_y, nblocks;     // 16x16 tiles of four waves (learned kernel)
     int32_t t8x, t8y, sgrid;               // 8x8 one-wave tiles; side of the power-of-two
                                            // grid of 4x4-tile super-tiles covering them
@@ -84,6 +89,8 @@ struct CamArgs {
     double tanf, win0, win1, lod_pix;
     int32_t ortho, width, height, t8x, t8y, sgrid;
     int64_t ray0;                    // the camera's first pixel, relative to the group's first
+    int64_t tile0;                   // the camera's first tile in the schedule
+    int32_t cam, pad_;               // the camera's index in the call
 };
 constexpr int kCamGroup = 8;
 struct CamGroup {
@@ -94,6 +101,9 @@ static_assert(sizeof(RenderArgs) + sizeof(CamGroup) <= 4096, "kernel arguments o
 
 inline CamArgs cam_args_of(const RenderArgs &A, int64_t ray0) {
     CamArgs C;
+    C.tile0 = A.tile0;
+    C.cam = A.cam;
+    C.pad_ = 0;
     for (int a = 0; a < 3; a++) {
         C.eye[a] = A.eye[a];
         C.u[a] = A.u[a];
@@ -135,12 +145,20 @@ __device__ __forceinline__ void take_camera(RenderArgs &A, const CamGroup &G) {
     A.t8x = C.t8x;
     A.t8y = C.t8y;
     A.sgrid = C.sgrid;
+    A.tile0 = C.tile0;
+    A.cam = C.cam;
     A.rgba += 4 * C.ray0;
     if (A.trace) A.trace += C.ray0 * A.trace_cap;
     if (A.trace_n) A.trace_n += C.ray0;
     if (A.nsamp) A.nsamp += C.ray0;
     A.ckpt_ray0 += C.ray0;
 }
+
+// Tile schedule layout (words of 4 bytes): a 4-word header per camera, padded to 256 bytes, then
+// one time per tile of every camera (camera by camera, tiles row-major), then one order slot per
+// tile.
+inline int64_t sched_header_words(int64_t ncams) { return (4 * ncams + 63) / 64 * 64; }
+inline int64_t sched_tiles(const amr_camera &C) { return (int64_t)((C.width + 7) / 8) * ((C.height + 7) / 8); }
 
 struct BwdArgs {
     const float *grad_rgba;

@@ -478,3 +478,74 @@ def test_camera_groups_match_single_camera_launches(gpu, lit, mode):
             assert torch.equal(out["trace_n"][off:off + npix[c]], o1["trace_n"]), c
             assert torch.equal(out["trace_raw"][off:off + npix[c]], o1["trace_raw"]), c
         off += npix[c]
+
+
+def _sched_bucket(t):
+    t = int(t)
+    if t < 16:
+        return t
+    msb = t.bit_length() - 1
+    return min(511, (msb - 3) * 16 + ((t >> (msb - 4)) & 15))
+
+
+@pytest.mark.parametrize("mode", ["timed", "recording", "checkpoints"])
+@pytest.mark.parametrize("lit", [False, True])
+def test_tile_schedule(gpu, lit, mode):
+    """With a tile schedule, each call records every tile's time and sorts each camera's tiles
+    longest first; the next call renders them in that order.  Over three calls of ten cameras of
+    different sizes (two launches), images, sample counts and traces (recording kernels),
+    checkpoint records and tape records (checkpointed kernels) are bit-identical to the calls
+    without a schedule; afterwards each camera's header holds its tile count and its order is a
+    permutation of its tiles in non-increasing time buckets."""
+    import torch
+    amr = gpu
+    h, lut, cams, prm = workloads.small_nested(1)
+    prm = dict(prm, lighting=lit)
+    tree, scene = _setup(amr, h, layout=2)
+    lut_t = torch.from_numpy(lut).cuda()
+    cl = _orbit_cams(10, seed=22)
+    npix = sum(c["width"] * c["height"] for c in cl)
+    sch = amr.Schedule(cl, "cuda")
+
+    def run(**kw):
+        if mode == "checkpoints":
+            out, ck = amr.render_checkpointed(scene, cl, lut_t, prm, ckpt_every=2, ckpt_max=8,
+                                              tape_cap=256 if lit else 0, **kw)
+            torch.cuda.synchronize()
+            return out, ck
+        extra = dict(trace_cap=64, nsamp=True, stats=True) if mode == "recording" else {}
+        out = amr.render(scene, cl, lut_t, prm, **extra, **kw)
+        torch.cuda.synchronize()
+        return out, None
+    ref, rck = run()
+    for call in range(3):
+        out, ck = run(**sch.params())
+        assert torch.equal(out["rgba"], ref["rgba"]), call
+        if mode == "recording":
+            for k in ("nsamp", "trace_n", "trace_raw"):
+                assert torch.equal(out[k], ref[k]), (call, k)
+        if mode == "checkpoints":
+            a = ck.buf.view(npix, 9, 32).cpu().numpy()
+            b = rck.buf.view(npix, 9, 32).cpu().numpy()
+            assert np.array_equal(a[:, 0], b[:, 0])
+            nck = b[:, 0].copy().view(np.int32)[:, 5]
+            nrec = np.minimum(b[:, 0].copy().view(np.int32)[:, 7], 256)
+            for r in range(0, npix, 7):
+                assert np.array_equal(a[r, 1:1 + nck[r]], b[r, 1:1 + nck[r]]), r
+                if lit:
+                    ta = ck.tape.view(npix, 256, 4)[r, :nrec[r]].cpu().numpy()
+                    tb = rck.tape.view(npix, 256, 4)[r, :nrec[r]].cpu().numpy()
+                    assert np.array_equal(ta, tb), r
+    words = sch.buf.view(torch.int32).cpu().numpy()
+    hw = (4 * len(cl) + 63) // 64 * 64
+    ntiles = [((c["width"] + 7) // 8) * ((c["height"] + 7) // 8) for c in cl]
+    ntot = sum(ntiles)
+    tm, order = words[hw:hw + ntot].view(np.uint32), words[hw + ntot:hw + 2 * ntot]
+    off = 0
+    for c, n in enumerate(ntiles):
+        assert words[4 * c] == n, c
+        o = order[off:off + n]
+        assert sorted(o.tolist()) == list(range(n)), c
+        bk = [_sched_bucket(tm[off + i]) for i in o]
+        assert all(bk[i] >= bk[i + 1] for i in range(n - 1)), c
+        off += n

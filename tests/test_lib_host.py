@@ -470,7 +470,7 @@ def _render_call(lib, scene, cams, prm, set_fields=None, lut_ok=True):
 
 @pytest.mark.parametrize("case", ["v_range", "step", "cam_size", "interp", "lighting", "lod", "lut", "trace_cap",
                                   "ckpt_odd", "ckpt_small", "tile", "no_queue", "light_no_work", "light_work_small",
-                                  "tape_cap", "tape_align", "waves_per_simd"])
+                                  "tape_cap", "tape_align", "waves_per_simd", "sched_small", "sched_persistent"])
 def test_render_argument_checks(case):
     """amr_render's argument checks, each of which returns before any device access (host buffers
     stand in for device pointers, so the test runs only where no GPU is visible)."""
@@ -513,6 +513,12 @@ def test_render_argument_checks(case):
     elif case == "light_work_small":
         p, words, want_code = dict(prm, lighting=2), "workspace", 3
         fields = dict(d_work="buf", work_bytes=1 << 16, light_jobs=1 << 20)
+    elif case == "sched_small":
+        p, words, want_code = dict(prm), "sched_bytes", 3
+        fields = dict(d_sched="buf", sched_bytes=64)
+    elif case == "sched_persistent":
+        p, words = dict(prm, persistent=1), "tile schedule"
+        fields = dict(d_queue="buf", d_sched="buf", sched_bytes=1 << 16)
     elif case == "waves_per_simd":
         p, fields, words = dict(prm, persistent=1, lighting=1, waves_per_simd=4), dict(d_queue="buf"), "waves_per_simd"
     elif case == "tape_cap":
@@ -610,4 +616,7 @@ def test_render_work_bytes():
     assert amr.default_tape_cap(8 * 1024 * 1024, total_memory=288 * 10**9) == 640
     assert amr.default_tape_cap(8 * 2048 * 2048, total_memory=288 * 10**9) == 160
     assert amr.default_tape_cap(10**12, total_memory=288 * 10**9) == 0
+    # the tile schedule: 16 bytes per camera (a 256-byte multiple), then 8 bytes per 8x8 tile
+    assert lib.amr_sched_bytes(carr, 2) == 256 + 8 * ((38 * 25) + (13 * 88))
+    assert lib.amr_sched_bytes(carr, 0) == -1
     assert lib.amr_tape_bytes(0, 7) == 0 and lib.amr_tape_bytes(-1, 7) == 0 and lib.amr_tape_bytes(5, -1) == 0
