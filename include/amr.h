@@ -316,10 +316,11 @@ typedef struct {
     int32_t pad3_;
     /* tile schedule (device, NULL to skip; amr_sched_bytes bytes, caller-owned, zeroed before its
        first use and kept across calls for the same cameras): every call records how long each
-       8x8 tile of each camera took, and sorts the tiles longest first; a later call whose camera
-       has the recorded tile count renders its tiles in that order, so that the launch does not
-       end waiting on long tiles started late.  Images do not depend on the order.  The
-       raycaster only: AMR_EINVAL with persistent mode, learned proposals or the point light */
+       8x8 tile of each camera took and sorts the camera's 32x32-pixel super-tiles by their
+       longest tile; a later call whose camera has the recorded super-tile count starts them in
+       that order, longest first, so that the launch does not end waiting on long tiles started
+       late.  Images do not depend on the order.  The raycaster only: AMR_EINVAL with
+       persistent mode, learned proposals or the point light */
     void *d_sched;
     int64_t sched_bytes;
 } amr_render_params;
@@ -344,8 +345,9 @@ int64_t amr_wall_clock_khz(void);
 
 /* Checkpoint buffer bytes for nrays rays with ckpt_max checkpoints each. */
 int64_t amr_ckpt_bytes(int64_t nrays, int32_t ckpt_max);
-/* Tile schedule bytes (params->d_sched) for these cameras: a 16-byte header per camera, then a
- * time and an order slot of 4 bytes each per 8x8 tile; -1 on invalid arguments. */
+/* Tile schedule bytes (params->d_sched) for these cameras: a 16-byte header per camera (padded to
+ * 256 bytes), then a time and an order slot of 4 bytes each per 8x8 tile; -1 on invalid
+ * arguments. */
 int64_t amr_sched_bytes(const amr_camera *cams, int32_t ncams);
 /* Tape bytes for nrays rays with tape_cap records each (16 bytes per record). */
 int64_t amr_tape_bytes(int64_t nrays, int64_t tape_cap);

@@ -50,16 +50,19 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void re
     // and XCD x renders super-tiles x, x + 8, x + 16, ...  Every XCD thus gets a share of every
     // part of the image (the work per tile varies by 10x and more across the screen), while
     // the tiles in flight on one XCD stay grouped in a few compact 32x32 patches whose rays
-    // share bricks in that XCD's L2.  With a tile schedule sorted for this camera's tile count,
-    // block b takes the b-th longest tile of the last call instead (dealt to the XCDs in turn).
-    const uint32_t ntile = (uint32_t)A.t8x * (uint32_t)A.t8y;
+    // share bricks in that XCD's L2.  With a tile schedule sorted for this camera's super-tile
+    // count, the super-tiles are dealt the same way in the schedule's order (longest tile of the
+    // last call first) instead of the Morton order.
+    const uint32_t sgw = (uint32_t)(A.t8x + 3) / 4u, nst = sgw * (uint32_t)((A.t8y + 3) / 4);
     int col, row;
-    if (A.sched_hdr && A.sched_hdr[4 * A.cam] == ntile) {
-        if (blockIdx.x >= ntile) return;
-        const uint32_t tl = A.sched_order[A.tile0 + blockIdx.x];
-        if (tl >= ntile) return;             // never for an order the library wrote
-        col = (int)(tl % (uint32_t)A.t8x);
-        row = (int)(tl / (uint32_t)A.t8x);
+    if (A.sched_hdr && A.sched_hdr[4 * A.cam] == nst) {
+        const int xcd = (int)(blockIdx.x % 8), li = (int)(blockIdx.x / 8);
+        const uint32_t rank = (uint32_t)((li >> 4) * 8 + xcd);
+        if (rank >= nst) return;
+        const uint32_t st = A.sched_order[A.tile0 + rank];
+        if (st >= nst) return;
+        col = (int)(st % sgw) * 4 + ((li & 15) >> 2);
+        row = (int)(st / sgw) * 4 + (li & 3);
     } else {
         const int xcd = (int)(blockIdx.x % 8), li = (int)(blockIdx.x / 8);
         const int sidx = (li >> 4) * 8 + xcd;          // Morton index of the super-tile
@@ -608,14 +611,17 @@ __global__ __launch_bounds__(256) void render_bwd_tape(RenderArgs A, BwdArgs B) 
     adjoint_block_end<true>(B, s_acc, gs);
 }
 
-// Tile schedule for the next call: the tiles of each camera of a launch ordered by the time they
-// took, longest first (a counting sort over 512 logarithmic buckets, 16 per octave of the wall
-// clock's ticks; the order within a bucket is arbitrary), one block per camera; the camera's
-// header then records the tile count the order was sorted for.
+// Tile schedule for the next call: the 4x4-tile super-tiles of each camera of a launch ordered by
+// the time of their longest tile, longest first (a counting sort over 512 logarithmic buckets, 16
+// per octave of the wall clock's ticks; the order within a bucket is arbitrary), one block per
+// camera; the camera's header then records the super-tile count the order was sorted for.  A
+// super-tile keeps its tiles together on one XCD, as in the default order, so the schedule
+// reorders the image's regions without scattering their tiles.
 struct SchedGroup {
     int64_t tile0[kCamGroup];
     int32_t ntiles[kCamGroup];
     int32_t cam[kCamGroup];
+    int32_t t8x[kCamGroup], t8y[kCamGroup];
 };
 constexpr int kSchedBuckets = 512;
 
@@ -630,10 +636,20 @@ __global__ __launch_bounds__(1024) void sched_sort(uint32_t *hdr, const uint32_t
     __shared__ uint32_t cnt[kSchedBuckets], cur[kSchedBuckets];
     const int c = blockIdx.x;
     const int64_t t0 = G.tile0[c];
-    const uint32_t n = (uint32_t)G.ntiles[c];
+    const int t8x = G.t8x[c], t8y = G.t8y[c];
+    const uint32_t sgw = (uint32_t)(t8x + 3) / 4u, n = sgw * (uint32_t)((t8y + 3) / 4);
+    auto stime = [&](uint32_t st) {
+        const int sx = (int)(st % sgw) * 4, sy = (int)(st / sgw) * 4;
+        uint32_t m = 0u;
+        for (int j = 0; j < 16; j++) {
+            const int cx = sx + (j >> 2), cy = sy + (j & 3);
+            if (cx < t8x && cy < t8y) m = max(m, time[t0 + (int64_t)cy * t8x + cx]);
+        }
+        return m;
+    };
     for (int i = threadIdx.x; i < kSchedBuckets; i += blockDim.x) cnt[i] = 0u;
     __syncthreads();
-    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) atomicAdd(&cnt[sched_bucket(time[t0 + i])], 1u);
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) atomicAdd(&cnt[sched_bucket(stime(i))], 1u);
     __syncthreads();
     if (threadIdx.x == 0) {
         uint32_t s = 0u;
@@ -644,7 +660,7 @@ __global__ __launch_bounds__(1024) void sched_sort(uint32_t *hdr, const uint32_t
     }
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
-        const uint32_t pos = atomicAdd(&cur[sched_bucket(time[t0 + i])], 1u);
+        const uint32_t pos = atomicAdd(&cur[sched_bucket(stime(i))], 1u);
         order[t0 + pos] = i;
     }
     __syncthreads();
@@ -985,6 +1001,8 @@ int amr_render(const amr_scene *S, const amr_camera *cams, int32_t ncams, const 
             SG.tile0[i] = tile_off;
             SG.ntiles[i] = (int32_t)sched_tiles(cams[c0 + i]);
             SG.cam[i] = c0 + i;
+            SG.t8x[i] = Ai.t8x;
+            SG.t8y[i] = Ai.t8y;
             rel += (int64_t)cams[c0 + i].width * cams[c0 + i].height;
             tile_off += sched_tiles(cams[c0 + i]);
         }

@@ -491,12 +491,13 @@ def _sched_bucket(t):
 @pytest.mark.parametrize("mode", ["timed", "recording", "checkpoints"])
 @pytest.mark.parametrize("lit", [False, True])
 def test_tile_schedule(gpu, lit, mode):
-    """With a tile schedule, each call records every tile's time and sorts each camera's tiles
-    longest first; the next call renders them in that order.  Over three calls of ten cameras of
-    different sizes (two launches), images, sample counts and traces (recording kernels),
-    checkpoint records and tape records (checkpointed kernels) are bit-identical to the calls
-    without a schedule; afterwards each camera's header holds its tile count and its order is a
-    permutation of its tiles in non-increasing time buckets."""
+    """With a tile schedule, each call records every tile's time and sorts each camera's 4x4-tile
+    super-tiles by their longest tile; the next call starts them in that order.  Over three calls
+    of ten cameras of different sizes (two launches), images, sample counts and traces
+    (recording kernels), checkpoint records and tape records (checkpointed kernels) are
+    bit-identical to the calls without a schedule; afterwards each camera's header holds its
+    super-tile count and its order is a permutation of its super-tiles in non-increasing buckets
+    of their longest tile's time."""
     import torch
     amr = gpu
     h, lut, cams, prm = workloads.small_nested(1)
@@ -538,14 +539,18 @@ def test_tile_schedule(gpu, lit, mode):
                     assert np.array_equal(ta, tb), r
     words = sch.buf.view(torch.int32).cpu().numpy()
     hw = (4 * len(cl) + 63) // 64 * 64
-    ntiles = [((c["width"] + 7) // 8) * ((c["height"] + 7) // 8) for c in cl]
-    ntot = sum(ntiles)
+    t8 = [((c["width"] + 7) // 8, (c["height"] + 7) // 8) for c in cl]
+    ntot = sum(x * y for x, y in t8)
     tm, order = words[hw:hw + ntot].view(np.uint32), words[hw + ntot:hw + 2 * ntot]
     off = 0
-    for c, n in enumerate(ntiles):
+    for c, (tx, ty) in enumerate(t8):
+        sgw, sgh = (tx + 3) // 4, (ty + 3) // 4
+        n = sgw * sgh
         assert words[4 * c] == n, c
         o = order[off:off + n]
         assert sorted(o.tolist()) == list(range(n)), c
-        bk = [_sched_bucket(tm[off + i]) for i in o]
+        times = tm[off:off + tx * ty].reshape(ty, tx)
+        longest = [int(times[(s // sgw) * 4:(s // sgw) * 4 + 4, (s % sgw) * 4:(s % sgw) * 4 + 4].max()) for s in o]
+        bk = [_sched_bucket(v) for v in longest]
         assert all(bk[i] >= bk[i + 1] for i in range(n - 1)), c
-        off += n
+        off += tx * ty
