@@ -347,12 +347,11 @@ def adjoint_section(amr, dev, scene, h, steps=200):
         tgt = amr.render(scene, cams, torch.from_numpy(target).to(dev), prm)["rgba"].clone()
     lut = torch.from_numpy(start).to(dev).requires_grad_(True)
     opt = torch.optim.Adam([lut], lr=1e-2)
-    sched = amr.Schedule(cams, dev)
     losses = []
 
     def step():
         opt.zero_grad()
-        rgba = amr.AMRRender.apply(lut, sh, scene, cams, prm, 4, 16, False, sched)
+        rgba = amr.AMRRender.apply(lut, sh, scene, cams, prm)
         loss = ((rgba - tgt) ** 2).mean()
         loss.backward()
         opt.step()
