@@ -338,7 +338,8 @@ def adjoint_section(amr, dev, scene, h, steps=200):
     """Transfer-function fit on the same hierarchy: 8 orbit cameras at 512^2, lit, Adam (lr 1e-2)
     on the LUT through the checkpointed forward and the adjoint kernel, toward images rendered
     with a hidden target LUT.  Reports the time per optimisation step (forward + backward of all
-    eight images) and the loss after `steps` steps."""
+    eight images) and the loss after `steps` steps.  The steps share a tile schedule: every
+    forward starts the cameras' tiles longest first by the previous step's tile times."""
     import torch
     import workloads
     _, cams, target, start, prm = workloads.tf_fit(0, h=h)
@@ -348,10 +349,11 @@ def adjoint_section(amr, dev, scene, h, steps=200):
     lut = torch.from_numpy(start).to(dev).requires_grad_(True)
     opt = torch.optim.Adam([lut], lr=1e-2)
     losses = []
+    sched = amr.Schedule(cams, dev)
 
     def step():
         opt.zero_grad()
-        rgba = amr.AMRRender.apply(lut, sh, scene, cams, prm)
+        rgba = amr.AMRRender.apply(lut, sh, scene, cams, prm, 4, 16, False, sched)
         loss = ((rgba - tgt) ** 2).mean()
         loss.backward()
         opt.step()
@@ -368,7 +370,7 @@ def adjoint_section(amr, dev, scene, h, steps=200):
     ms = (time.time() - t) * 1e3 / (steps - 3)
     losses.append(float(last.item()))
     return dict(cameras=len(cams), width=512, height=512, steps=steps, ms_per_step=round(ms, 3),
-                loss_first=losses[0], loss_last=losses[-1])
+                loss_first=losses[0], loss_last=losses[-1], tile_schedule=True)
 
 
 def learned_skip_section(amr, dev, steps, warmup):

@@ -36,7 +36,26 @@ namespace amr {
 // pass at the layout's compiled addressing.
 template <bool LIT, bool REC, bool NEAR, int LAY, bool CK = false>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void render_fwd(RenderArgs A, CamGroup G) {
-    take_camera(A, G);
+    // scheduled launches: this block's camera and super-tile from the order (or, before a call
+    // has recorded it, camera by camera, super-tiles row by row)
+    int gc = (int)blockIdx.y;
+    uint32_t sst = 0xffffffffu;
+    if (G.sched) {
+        const uint32_t rank = (blockIdx.x / 128u) * 8u + blockIdx.x % 8u;
+        if (rank >= G.nst) return;
+        uint32_t e;
+        if (A.sched_hdr[4 * G.cam0 + 1] == G.sig) {
+            e = A.sched_order[G.order0 + rank];
+        } else {
+            int c = 0;
+            while (c + 1 < kCamGroup && c + 1 < G.n && rank >= G.stpre[c + 1]) c++;
+            e = ((uint32_t)c << 24) | (rank - G.stpre[c]);
+        }
+        gc = (int)(e >> 24);
+        sst = e & 0xffffffu;
+        if (gc >= (G.n > 0 ? G.n : 1)) return;       // never for an order the library wrote
+    }
+    take_camera(A, G, gc);
     constexpr bool kDefer = LIT;
     constexpr bool kCk = REC || CK;             // checkpoints (and the tape) may be recorded
     __shared__ float4 s_lut[256];
@@ -50,19 +69,15 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void re
     // and XCD x renders super-tiles x, x + 8, x + 16, ...  Every XCD thus gets a share of every
     // part of the image (the work per tile varies by 10x and more across the screen), while
     // the tiles in flight on one XCD stay grouped in a few compact 32x32 patches whose rays
-    // share bricks in that XCD's L2.  With a tile schedule sorted for this camera's super-tile
-    // count, the super-tiles are dealt the same way in the schedule's order (longest tile of the
-    // last call first) instead of the Morton order.
-    const uint32_t sgw = (uint32_t)(A.t8x + 3) / 4u, nst = sgw * (uint32_t)((A.t8y + 3) / 4);
+    // share bricks in that XCD's L2.  With a tile schedule, the super-tiles of all the launch's
+    // cameras are dealt the same way in the schedule's order (longest tile of the last call
+    // first) instead.
     int col, row;
-    if (A.sched_hdr && A.sched_hdr[4 * A.cam] == nst) {
-        const int xcd = (int)(blockIdx.x % 8), li = (int)(blockIdx.x / 8);
-        const uint32_t rank = (uint32_t)((li >> 4) * 8 + xcd);
-        if (rank >= nst) return;
-        const uint32_t st = A.sched_order[A.tile0 + rank];
-        if (st >= nst) return;
-        col = (int)(st % sgw) * 4 + ((li & 15) >> 2);
-        row = (int)(st / sgw) * 4 + (li & 3);
+    if (G.sched) {
+        const uint32_t sgw = (uint32_t)(A.t8x + 3) / 4u;
+        const int li = (int)(blockIdx.x / 8);
+        col = (int)(sst % sgw) * 4 + ((li & 15) >> 2);
+        row = (int)(sst / sgw) * 4 + (li & 3);
     } else {
         const int xcd = (int)(blockIdx.x % 8), li = (int)(blockIdx.x / 8);
         const int sidx = (li >> 4) * 8 + xcd;          // Morton index of the super-tile
@@ -462,7 +477,7 @@ __device__ __forceinline__ int interval_records_end(const CkptHeader &hd, const 
 template <bool LIT, int LAY>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(LIT ? 3 : 4))) void render_bwd(RenderArgs A, BwdArgs B,
                                                                                                      CamGroup G) {
-    take_camera(A, G);
+    take_camera(A, G, (int)blockIdx.y);
     if (G.n) B.grad_rgba += 4 * G.cam[blockIdx.y].ray0;
     __shared__ float4 s_lut[256];
     __shared__ float s_acc[4][kGradLen];      // one accumulator per wave
@@ -611,17 +626,23 @@ __global__ __launch_bounds__(256) void render_bwd_tape(RenderArgs A, BwdArgs B) 
     adjoint_block_end<true>(B, s_acc, gs);
 }
 
-// Tile schedule for the next call: the 4x4-tile super-tiles of each camera of a launch ordered by
+// Tile schedule for the next call: the 4x4-tile super-tiles of all cameras of a launch ordered by
 // the time of their longest tile, longest first (a counting sort over 512 logarithmic buckets, 16
-// per octave of the wall clock's ticks; the order within a bucket is arbitrary), one block per
-// camera; the camera's header then records the super-tile count the order was sorted for.  A
-// super-tile keeps its tiles together on one XCD, as in the default order, so the schedule
-// reorders the image's regions without scattering their tiles.
+// per octave of the wall clock's ticks; the order within a bucket is arbitrary), one block; the
+// header of the group's first camera then records the order's key, a signature of the call's
+// camera sizes and of the group's place among them.  A super-tile keeps its tiles together on one
+// XCD, as in the default order, so the schedule reorders the image's regions without scattering
+// their tiles.  The first group's sort of a call whose camera sizes differ from the previous
+// call's (word 2 of camera 0's header) first clears the keys of the call's other groups: their
+// order slots may hold another list's entries.
 struct SchedGroup {
-    int64_t tile0[kCamGroup];
-    int32_t ntiles[kCamGroup];
-    int32_t cam[kCamGroup];
+    int64_t tile0[kCamGroup];        // each camera's first tile time
     int32_t t8x[kCamGroup], t8y[kCamGroup];
+    uint32_t stpre[kCamGroup + 1];   // each camera's first super-tile in the group
+    int32_t n, cam0;
+    uint32_t sig, list_sig;
+    int64_t order0;
+    int32_t ncams, pad_;
 };
 constexpr int kSchedBuckets = 512;
 
@@ -634,22 +655,29 @@ __device__ __forceinline__ int sched_bucket(uint32_t t) {
 __global__ __launch_bounds__(1024) void sched_sort(uint32_t *hdr, const uint32_t *time, uint32_t *order,
                                                    SchedGroup G) {
     __shared__ uint32_t cnt[kSchedBuckets], cur[kSchedBuckets];
-    const int c = blockIdx.x;
-    const int64_t t0 = G.tile0[c];
-    const int t8x = G.t8x[c], t8y = G.t8y[c];
-    const uint32_t sgw = (uint32_t)(t8x + 3) / 4u, n = sgw * (uint32_t)((t8y + 3) / 4);
-    auto stime = [&](uint32_t st) {
+    const uint32_t n = G.stpre[G.n];
+    // rank r of the default order: camera c with stpre[c] <= r < stpre[c + 1], its super-tile r - stpre[c]
+    auto entry = [&](uint32_t r) {
+        int c = 0;
+        while (c + 1 < G.n && r >= G.stpre[c + 1]) c++;
+        return ((uint32_t)c << 24) | (r - G.stpre[c]);
+    };
+    auto stime = [&](uint32_t e) {
+        const int c = (int)(e >> 24);
+        const uint32_t st = e & 0xffffffu;
+        const int t8x = G.t8x[c], t8y = G.t8y[c];
+        const uint32_t sgw = (uint32_t)(t8x + 3) / 4u;
         const int sx = (int)(st % sgw) * 4, sy = (int)(st / sgw) * 4;
         uint32_t m = 0u;
         for (int j = 0; j < 16; j++) {
             const int cx = sx + (j >> 2), cy = sy + (j & 3);
-            if (cx < t8x && cy < t8y) m = max(m, time[t0 + (int64_t)cy * t8x + cx]);
+            if (cx < t8x && cy < t8y) m = max(m, time[G.tile0[c] + (int64_t)cy * t8x + cx]);
         }
         return m;
     };
     for (int i = threadIdx.x; i < kSchedBuckets; i += blockDim.x) cnt[i] = 0u;
     __syncthreads();
-    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) atomicAdd(&cnt[sched_bucket(stime(i))], 1u);
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) atomicAdd(&cnt[sched_bucket(stime(entry(i)))], 1u);
     __syncthreads();
     if (threadIdx.x == 0) {
         uint32_t s = 0u;
@@ -660,11 +688,18 @@ __global__ __launch_bounds__(1024) void sched_sort(uint32_t *hdr, const uint32_t
     }
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
-        const uint32_t pos = atomicAdd(&cur[sched_bucket(stime(i))], 1u);
-        order[t0 + pos] = i;
+        const uint32_t e = entry(i);
+        const uint32_t pos = atomicAdd(&cur[sched_bucket(stime(e))], 1u);
+        order[G.order0 + pos] = e;
     }
     __syncthreads();
-    if (threadIdx.x == 0) hdr[4 * G.cam[c]] = n;
+    if (threadIdx.x == 0) {
+        if (G.cam0 == 0 && hdr[2] != G.list_sig) {
+            for (int c = kCamGroup; c < G.ncams; c += kCamGroup) hdr[4 * c + 1] = 0u;
+            hdr[2] = G.list_sig;
+        }
+        hdr[4 * G.cam0 + 1] = G.sig;
+    }
 }
 
 // Fixed-order sum of per-block partials (deterministic adjoint).
@@ -979,6 +1014,12 @@ int amr_render(const amr_scene *S, const amr_camera *cams, int32_t ncams, const 
     for (int c = 0; c < ncams; c++) sched_ntot += sched_tiles(cams[c]);
     uint32_t *sched_time = sched ? sched + sched_header_words(ncams) : nullptr;
     uint32_t *sched_order = sched ? sched_time + sched_ntot : nullptr;
+    // the key of an order: FNV-1a over the call's camera count and every camera's tile grid,
+    // then the group's first camera (0 is left for a zeroed schedule)
+    uint32_t list_sig = (2166136261u ^ (uint32_t)ncams) * 16777619u;
+    for (int c = 0; c < ncams; c++)
+        for (uint32_t w : {(uint32_t)(cams[c].width + 7) / 8u, (uint32_t)(cams[c].height + 7) / 8u})
+            list_sig = (list_sig ^ w) * 16777619u;
     int64_t pix_off = 0, tile_off = 0;
     for (int c0 = 0; c0 < ncams; c0 += kCamGroup) {
         const int n = std::min(kCamGroup, ncams - c0);
@@ -989,6 +1030,8 @@ int amr_render(const amr_scene *S, const amr_camera *cams, int32_t ncams, const 
         memset(&SG, 0, sizeof(SG));
         int gx = 0;
         int64_t rel = 0;
+        const int64_t order0 = tile_off;
+        uint32_t nst = 0;
         for (int i = 0; i < n; i++) {
             RenderArgs Ai;
             int rc = fill_args(S, &cams[c0 + i], P, &Ai);
@@ -999,14 +1042,30 @@ int amr_render(const amr_scene *S, const amr_camera *cams, int32_t ncams, const 
             G.cam[i] = cam_args_of(Ai, rel);
             gx = std::max(gx, 8 * ((Ai.sgrid * Ai.sgrid + 7) / 8) * 16);
             SG.tile0[i] = tile_off;
-            SG.ntiles[i] = (int32_t)sched_tiles(cams[c0 + i]);
-            SG.cam[i] = c0 + i;
             SG.t8x[i] = Ai.t8x;
             SG.t8y[i] = Ai.t8y;
+            SG.stpre[i] = G.stpre[i] = nst;
+            nst += (uint32_t)((Ai.t8x + 3) / 4) * (uint32_t)((Ai.t8y + 3) / 4);
             rel += (int64_t)cams[c0 + i].width * cams[c0 + i].height;
             tile_off += sched_tiles(cams[c0 + i]);
         }
+        SG.stpre[n] = G.stpre[n] = nst;
+        uint32_t sig = (list_sig ^ (uint32_t)c0) * 16777619u;
+        if (sig == 0u) sig = 1u;
         G.n = n > 1 ? n : 0;
+        if (sched) {
+            G.sched = 1;
+            G.nst = nst;
+            G.sig = sig;
+            G.cam0 = c0;
+            G.order0 = order0;
+            SG.n = n;
+            SG.cam0 = c0;
+            SG.sig = sig;
+            SG.order0 = order0;
+            SG.list_sig = list_sig;
+            SG.ncams = ncams;
+        }
         A.sched_hdr = sched;
         A.sched_time = sched_time;
         A.sched_order = sched_order;
@@ -1019,7 +1078,8 @@ int amr_render(const amr_scene *S, const amr_camera *cams, int32_t ncams, const 
         A.touch = P->d_touch;
         A.ckpt_ray0 = pix_off;
         const bool rec = A.trace || A.trace_n || A.nsamp || A.stats || A.touch || A.touch_meta || A.ckpt;
-        const dim3 g(gx, n), b(64);
+        // scheduled: one-dimensional, 16 blocks per super-tile, ranks dealt to the 8 XCDs in turn
+        const dim3 g(sched ? 128 * ((nst + 7) / 8) : gx, sched ? 1 : n), b(64);
         if (A.nearest) {
             if (A.lighting) {
                 if (rec) hipLaunchKernelGGL((render_fwd<true, true, true, -1>), g, b, 0, s, A, G);
@@ -1053,7 +1113,7 @@ int amr_render(const amr_scene *S, const amr_camera *cams, int32_t ncams, const 
         int rc = check_hip(hipGetLastError(), "render_fwd launch");
         if (rc) return rc;
         if (sched) {
-            hipLaunchKernelGGL(sched_sort, dim3(n), dim3(1024), 0, s, sched, sched_time, sched_order, SG);
+            hipLaunchKernelGGL(sched_sort, dim3(1), dim3(1024), 0, s, sched, sched_time, sched_order, SG);
             rc = check_hip(hipGetLastError(), "tile schedule sort");
             if (rc) return rc;
         }

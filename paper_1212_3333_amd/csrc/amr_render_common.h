@@ -96,6 +96,15 @@ constexpr int kCamGroup = 8;
 struct CamGroup {
     CamArgs cam[kCamGroup];
     int32_t n;                       // cameras in the group; 0: one camera, RenderArgs as given
+    // with a tile schedule: the launch is one-dimensional over the group's super-tiles
+    // (32x32 pixels), block b taking rank (b / 128) * 8 + b % 8 of the order and tile (b / 8) % 16
+    // of that super-tile; an order entry is camera << 24 | super-tile
+    int32_t sched;                   // 1: a scheduled launch
+    uint32_t nst;                    // super-tiles of the group
+    uint32_t sig;                    // signature of the group's camera sizes, the order's key
+    int32_t cam0;                    // the group's first camera in the call (its header holds sig)
+    int64_t order0;                  // the group's first order slot
+    uint32_t stpre[kCamGroup + 1];   // first super-tile of each camera in the default order
 };
 static_assert(sizeof(RenderArgs) + sizeof(CamGroup) <= 4096, "kernel arguments of a group launch");
 
@@ -124,10 +133,10 @@ inline CamArgs cam_args_of(const RenderArgs &A, int64_t ray0) {
     return C;
 }
 
-// A block of a group launch takes its camera (blockIdx.y) into A.
-__device__ __forceinline__ void take_camera(RenderArgs &A, const CamGroup &G) {
+// A block of a group launch takes its camera (c, for unscheduled launches blockIdx.y) into A.
+__device__ __forceinline__ void take_camera(RenderArgs &A, const CamGroup &G, int c) {
     if (G.n == 0) return;
-    const CamArgs &C = G.cam[blockIdx.y];
+    const CamArgs &C = G.cam[c];
     #pragma unroll
     for (int a = 0; a < 3; a++) {
         A.eye[a] = C.eye[a];

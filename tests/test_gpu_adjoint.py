@@ -344,8 +344,9 @@ def test_tf_fit_200_adam_steps(gpu):
     """Transfer-function fit (cosmology-like hierarchy, 8 cameras at 512^2, lit): 200 Adam steps
     (lr 1e-2) on the LUT through AMRRender from the starting LUT toward images rendered with a
     hidden target LUT.  The image loss falls by more than 10x and the LUT moves toward the target
-    on the entries the images constrain.  A second, shorter run keeps a tile schedule across its
-    steps and must follow the same losses."""
+    on the entries the images constrain.  The steps share a tile schedule (each forward starts the
+    tiles longest first by the previous step's tile times); a second, shorter run without one must
+    follow the same losses."""
     import torch
     amr = gpu
     h, cams, target, start, prm = workloads.tf_fit(0)
@@ -357,9 +358,10 @@ def test_tf_fit_200_adam_steps(gpu):
     opt = torch.optim.Adam([lut], lr=1e-2)
     losses = []
     touched = None
+    sched = amr.Schedule(cams, "cuda")
     for step in range(200):
         opt.zero_grad()
-        rgba = amr.AMRRender.apply(lut, sh, scene, cams, prm)
+        rgba = amr.AMRRender.apply(lut, sh, scene, cams, prm, 4, 16, False, sched)
         loss = ((rgba - tgt) ** 2).mean()
         loss.backward()
         if touched is None:
@@ -374,13 +376,12 @@ def test_tf_fit_200_adam_steps(gpu):
     d1 = np.abs(lut.detach().cpu().numpy() - target)[touched[:, :3].any(axis=1)][:, :3].mean()
     print("colour LUT error on constrained entries %.4g -> %.4g" % (d0, d1))
     assert d1 < d0
-    # with a tile schedule (tiles in another order): the same images, so the same first losses
+    # without a tile schedule (tiles in the default order): the same images, so the same first losses
     lut2 = torch.from_numpy(start).cuda().requires_grad_(True)
     opt2 = torch.optim.Adam([lut2], lr=1e-2)
-    sched = amr.Schedule(cams, "cuda")
     for step in range(5):
         opt2.zero_grad()
-        rgba = amr.AMRRender.apply(lut2, sh, scene, cams, prm, 4, 16, False, sched)
+        rgba = amr.AMRRender.apply(lut2, sh, scene, cams, prm)
         loss = ((rgba - tgt) ** 2).mean()
         loss.backward()
         opt2.step()

@@ -491,13 +491,13 @@ def _sched_bucket(t):
 @pytest.mark.parametrize("mode", ["timed", "recording", "checkpoints"])
 @pytest.mark.parametrize("lit", [False, True])
 def test_tile_schedule(gpu, lit, mode):
-    """With a tile schedule, each call records every tile's time and sorts each camera's 4x4-tile
-    super-tiles by their longest tile; the next call starts them in that order.  Over three calls
-    of ten cameras of different sizes (two launches), images, sample counts and traces
-    (recording kernels), checkpoint records and tape records (checkpointed kernels) are
-    bit-identical to the calls without a schedule; afterwards each camera's header holds its
-    super-tile count and its order is a permutation of its super-tiles in non-increasing buckets
-    of their longest tile's time."""
+    """With a tile schedule, each call records every tile's time and sorts the 4x4-tile super-tiles
+    of each launch's cameras (up to 8) by their longest tile; the next call starts them in that
+    order.  Over three calls of ten cameras of different sizes (two launches), images, sample
+    counts and traces (recording kernels), checkpoint records and tape records (checkpointed
+    kernels) are bit-identical to the calls without a schedule; afterwards each launch's order
+    holds every (camera, super-tile) of its cameras once, in non-increasing buckets of their
+    longest tile's time, and its first camera's header holds the order's key (non-zero)."""
     import torch
     amr = gpu
     h, lut, cams, prm = workloads.small_nested(1)
@@ -537,20 +537,53 @@ def test_tile_schedule(gpu, lit, mode):
                     ta = ck.tape.view(npix, 256, 4)[r, :nrec[r]].cpu().numpy()
                     tb = rck.tape.view(npix, 256, 4)[r, :nrec[r]].cpu().numpy()
                     assert np.array_equal(ta, tb), r
-    words = sch.buf.view(torch.int32).cpu().numpy()
+    words = sch.buf.view(torch.int32).cpu().numpy().view(np.uint32)
     hw = (4 * len(cl) + 63) // 64 * 64
     t8 = [((c["width"] + 7) // 8, (c["height"] + 7) // 8) for c in cl]
-    ntot = sum(x * y for x, y in t8)
-    tm, order = words[hw:hw + ntot].view(np.uint32), words[hw + ntot:hw + 2 * ntot]
-    off = 0
-    for c, (tx, ty) in enumerate(t8):
-        sgw, sgh = (tx + 3) // 4, (ty + 3) // 4
-        n = sgw * sgh
-        assert words[4 * c] == n, c
-        o = order[off:off + n]
-        assert sorted(o.tolist()) == list(range(n)), c
-        times = tm[off:off + tx * ty].reshape(ty, tx)
-        longest = [int(times[(s // sgw) * 4:(s // sgw) * 4 + 4, (s % sgw) * 4:(s % sgw) * 4 + 4].max()) for s in o]
-        bk = [_sched_bucket(v) for v in longest]
-        assert all(bk[i] >= bk[i + 1] for i in range(n - 1)), c
-        off += tx * ty
+    toff = np.concatenate([[0], np.cumsum([x * y for x, y in t8])])
+    ntot = int(toff[-1])
+    tm, order = words[hw:hw + ntot], words[hw + ntot:hw + 2 * ntot]
+    for c0 in range(0, len(cl), 8):
+        grp = list(range(c0, min(c0 + 8, len(cl))))
+        assert words[4 * c0 + 1] != 0, c0
+        pairs = [(i, s) for i, c in enumerate(grp) for s in range(((t8[c][0] + 3) // 4) * ((t8[c][1] + 3) // 4))]
+        o = order[toff[c0]:toff[c0] + len(pairs)]
+        got = [(int(e) >> 24, int(e) & 0xffffff) for e in o]
+        assert sorted(got) == sorted(pairs), c0
+
+        def longest(i, s):
+            c = grp[i]
+            tx, ty = t8[c]
+            sgw = (tx + 3) // 4
+            times = tm[toff[c]:toff[c] + tx * ty].reshape(ty, tx)
+            return int(times[(s // sgw) * 4:(s // sgw) * 4 + 4, (s % sgw) * 4:(s % sgw) * 4 + 4].max())
+        bk = [_sched_bucket(longest(i, s)) for (i, s) in got]
+        assert all(bk[j] >= bk[j + 1] for j in range(len(bk) - 1)), c0
+
+
+def test_tile_schedule_camera_list_change(gpu):
+    """One schedule buffer used with 18 cameras (three launches), then 9 other cameras of other
+    sizes, whose header, times and orders overwrite parts of the first list's, then the 18 again:
+    every call's images equal those of calls without a schedule (the 9-camera call and the
+    return to the 18 render in the default order and record afresh; the next call of the 18
+    uses the new order)."""
+    import torch
+    amr = gpu
+    h, lut, cams, prm = workloads.small_nested(1)
+    prm = dict(prm, lighting=True)
+    tree, scene = _setup(amr, h, layout=2)
+    lut_t = torch.from_numpy(lut).cuda()
+    l1 = _orbit_cams(18, seed=5)
+    l2 = _orbit_cams(12, seed=6)[3:]
+    sch = amr.Schedule(l1, "cuda")
+    assert int(amr.load().amr_sched_bytes(amr._cams(l2)[1], len(l2))) <= sch.nbytes
+
+    def img(cl, **kw):
+        r = amr.render(scene, cl, lut_t, prm, **kw)["rgba"].clone()
+        torch.cuda.synchronize()
+        return r
+    ref1, ref2 = img(l1), img(l2)
+    for i, cl in enumerate([l1, l1, l2, l2, l1, l1, l2, l1]):
+        assert torch.equal(img(cl, **sch.params()), ref1 if cl is l1 else ref2), i
+    words = sch.buf.view(torch.int32).cpu().numpy().view(np.uint32)
+    assert all(words[4 * c0 + 1] != 0 for c0 in (0, 8, 16))
