@@ -208,25 +208,32 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPS))) void
             if (L.patch >= 0) {
                 Segment S;
                 setup_segment<LIT, LAY>(A, R, L, leaf, tcur, tb, S);
-                for (int k2 = 0; k2 < S.n; k2++) {
-                    float alpha;
-                    if (LIT) {
-                        // as the single-camera kernel: taps that leave the brick are deferred
-                        TapQueue &Q = *tq;
-                        tapq_reserve<REC, LAY>(A, s_lut, Q, lane, cnt);
-                        alpha = lit_sample_deferred<REC, LAY>(A, s_lut, Q, lane, R, S, k2, T, C0, C1, C2, cnt);
-                    } else {
-                        SampleVals v;
-                        eval_sample<false, REC, false, LAY>(A, s_lut, R, S, k2, v, cnt);
-                        float wgt = T * v.alpha * v.shade;
-                        C0 += wgt * v.r;
-                        C1 += wgt * v.g;
-                        C2 += wgt * v.b;
-                        alpha = v.alpha;
+                if constexpr (!LIT && !REC) {
+                    float tseg = 1.f;
+                    bool stop;
+                    nsamp_total += composite_unlit<LAY>(A, s_lut, R, S, T, C0, C1, C2, tseg, stop, cnt);
+                    if (stop) alive = false;
+                } else {
+                    for (int k2 = 0; k2 < S.n; k2++) {
+                        float alpha;
+                        if (LIT) {
+                            // as the single-camera kernel: taps that leave the brick are deferred
+                            TapQueue &Q = *tq;
+                            tapq_reserve<REC, LAY>(A, s_lut, Q, lane, cnt);
+                            alpha = lit_sample_deferred<REC, LAY>(A, s_lut, Q, lane, R, S, k2, T, C0, C1, C2, cnt);
+                        } else {
+                            SampleVals v;
+                            eval_sample<false, REC, false, LAY>(A, s_lut, R, S, k2, v, cnt);
+                            float wgt = T * v.alpha * v.shade;
+                            C0 += wgt * v.r;
+                            C1 += wgt * v.g;
+                            C2 += wgt * v.b;
+                            alpha = v.alpha;
+                        }
+                        T *= 1.f - alpha;
+                        nsamp_total++;
+                        if (T < A.t_min) { alive = false; break; }
                     }
-                    T *= 1.f - alpha;
-                    nsamp_total++;
-                    if (T < A.t_min) { alive = false; break; }
                 }
             }
             if (tb <= tcur) {

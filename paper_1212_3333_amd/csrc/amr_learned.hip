@@ -297,17 +297,24 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(LIT ? 2 : (L
                 S.dl = (float)S.delta * 1.44269504088896340736f;
                 c_coarse++;
             }
-            for (int k = 0; k < S.n; k++) {
-                SampleVals v;
-                eval_sample<LIT, false, false, LAY>(A, s_lut, R, S, k, v, cnt);
-                float wgt = T * v.alpha * v.shade;
-                C0 += wgt * v.r;
-                C1 += wgt * v.g;
-                C2 += wgt * v.b;
-                T *= 1.f - v.alpha;
-                tseg *= 1.f - v.alpha;
-                nsamp_total++;
-                if (T < A.t_min) { alive = false; full = k + 1 == S.n; break; }
+            if constexpr (!LIT && !LOG) {
+                bool stop;
+                const int done = composite_unlit<LAY>(A, s_lut, R, S, T, C0, C1, C2, tseg, stop, cnt);
+                nsamp_total += done;
+                if (stop) { alive = false; full = done == S.n; }
+            } else {
+                for (int k = 0; k < S.n; k++) {
+                    SampleVals v;
+                    eval_sample<LIT, false, false, LAY>(A, s_lut, R, S, k, v, cnt);
+                    float wgt = T * v.alpha * v.shade;
+                    C0 += wgt * v.r;
+                    C1 += wgt * v.g;
+                    C2 += wgt * v.b;
+                    T *= 1.f - v.alpha;
+                    tseg *= 1.f - v.alpha;
+                    nsamp_total++;
+                    if (T < A.t_min) { alive = false; full = k + 1 == S.n; break; }
+                }
             }
             if (mode == kModeCoarse) alive = false;
         } else if (data) {

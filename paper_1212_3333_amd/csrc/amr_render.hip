@@ -267,16 +267,23 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void re
                 Segment S;
                 setup_segment<LIT, LAY>(A, R, L, leaf, tcur, tb, S);
                 nsm = S.n;
-                for (int k = 0; k < nsm; k++) {
-                    SampleVals v;
-                    eval_sample<LIT, REC, NEAR, LAY>(A, s_lut, R, S, k, v, cnt);
-                    float wgt = T * v.alpha * v.shade;
-                    C0 += wgt * v.r;
-                    C1 += wgt * v.g;
-                    C2 += wgt * v.b;
-                    T *= 1.f - v.alpha;
-                    nsamp_total++;
-                    if (T < A.t_min) { alive = false; break; }
+                if constexpr (!REC && !kCk && !NEAR) {
+                    float tseg = 1.f;
+                    bool stop;
+                    nsamp_total += composite_unlit<LAY>(A, s_lut, R, S, T, C0, C1, C2, tseg, stop, cnt);
+                    if (stop) alive = false;
+                } else {
+                    for (int k = 0; k < nsm; k++) {
+                        SampleVals v;
+                        eval_sample<LIT, REC, NEAR, LAY>(A, s_lut, R, S, k, v, cnt);
+                        float wgt = T * v.alpha * v.shade;
+                        C0 += wgt * v.r;
+                        C1 += wgt * v.g;
+                        C2 += wgt * v.b;
+                        T *= 1.f - v.alpha;
+                        nsamp_total++;
+                        if (T < A.t_min) { alive = false; break; }
+                    }
                 }
             }
             if (REC && A.trace) {

@@ -1116,6 +1116,44 @@ __device__ __forceinline__ void eval_sample(const RenderArgs &A, const float4 *s
     v.shade = LIT ? lit_shade(A, v.gv, v.dot, v.den) : 1.f;
 }
 
+// Unlit samples of one data segment, composited front to back (emission-absorption with early
+// termination, Section 5.3).  A ray's samples depend on each other only through T, so the
+// values of kUnlitBatch samples are evaluated (their brick loads in flight together) before
+// they are composited one by one in sample order; the ray's dependent memory round trips fall
+// by that factor.  A batch that runs past the segment's end repeats its last sample, which is
+// not composited, and samples past early termination are not composited either: results are
+// bit-identical to one sample at a time.  tseg: the segment's own transmittance, multiplied
+// alike.  Returns the samples composited; stop: the ray terminated in this segment.
+constexpr int kUnlitBatch = 4;
+template <int LAY>
+__device__ __forceinline__ int composite_unlit(const RenderArgs &A, const float4 *s_lut, const Ray &R,
+                                               const Segment &S, float &T, float &C0, float &C1, float &C2,
+                                               float &tseg, bool &stop, Counters &cnt) {
+    int done = 0;
+    stop = false;
+    for (int k = 0; k < S.n; k += kUnlitBatch) {
+        SampleVals v[kUnlitBatch];
+        #pragma unroll
+        for (int u = 0; u < kUnlitBatch; u++)
+            eval_sample<false, false, false, LAY>(A, s_lut, R, S, min(k + u, S.n - 1), v[u], cnt);
+        #pragma unroll
+        for (int u = 0; u < kUnlitBatch; u++) {
+            if (!stop && k + u < S.n) {
+                const float wgt = T * v[u].alpha * v[u].shade;
+                C0 += wgt * v[u].r;
+                C1 += wgt * v[u].g;
+                C2 += wgt * v[u].b;
+                T *= 1.f - v[u].alpha;
+                tseg *= 1.f - v[u].alpha;
+                done++;
+                if (T < A.t_min) stop = true;
+            }
+        }
+        if (stop) break;
+    }
+    return done;
+}
+
 // ------------------------------------------------------------------------------------------
 // Deferred gradient taps (lit forward kernels)
 // ------------------------------------------------------------------------------------------
