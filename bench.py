@@ -36,9 +36,10 @@ VALU_ISSUE_PEAK = 256 * 2.4e9
 FLOPS_PER_SAMPLE = {False: 59, True: 206}
 # gather request bytes per sample: 8 cells, plus 6 taps of 8 cells each when lit
 GATHER_BYTES_PER_SAMPLE = {False: 32, True: 32 + 192}
-# the sources of the timed kernels; committed counter readings are used only while these match
+# the sources of the timed kernels and the script that compiles them (its flags change the code);
+# committed counter readings are used only while these match
 KERNEL_SOURCES = ("paper_1212_3333_amd/csrc/amr_render.hip", "paper_1212_3333_amd/csrc/amr_render_common.h",
-                  "paper_1212_3333_amd/csrc/amr_internal.h")
+                  "paper_1212_3333_amd/csrc/amr_internal.h", "paper_1212_3333_amd/build.py")
 COUNTERS_FILE = "profiles/render_fwd_cosmology_1024_counters.txt"
 
 

@@ -18,8 +18,11 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 # FP32 packed math is disabled on purpose (see the design notes); the host pass warns that it
 # does not know the feature, which is harmless.
+# -ffp-contract=on: a multiply and an add are fused only where one expression holds both, so the
+# rounding of a formula does not depend on the code around it (the kernel variants that share a
+# formula give bit-identical results)
 DEVICE_FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-munsafe-fp-atomics",
-                "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+                "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-ffp-contract=on"]
 HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-ffp-contract=off", "-fno-fast-math"]
 
 

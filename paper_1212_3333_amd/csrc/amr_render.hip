@@ -210,7 +210,56 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void re
                 }
                 continue;
             }
-            if (has) {
+            if constexpr (!REC && !NEAR) {
+                // Two samples per step: the stencils of a lane's next two samples are read
+                // together (one round of brick reads for both), the first is taken as above,
+                // and the second too when the queue has a slot for each lane whose second
+                // sample defers (tapq_full over those lanes); otherwise it is read again in the
+                // next step.  The samples are taken in order and each lane's queued samples
+                // stay in its sample order (one run per push), so results are those of one
+                // sample per step.
+                float qa[3], qb[3], Fa, Fpa[3], Fma[3], Fb, Fpb[3], Fmb[3];
+                uint32_t cla = 0u, clb = 0u;
+                if (has) {
+                    const int kb = min(k + 1, S.n - 1);
+                    const float kka = (float)k + 0.5f, kkb = (float)kb + 0.5f;
+                    #pragma unroll
+                    for (int a = 0; a < 3; a++) {
+                        qa[a] = S.q0[a] + kka * S.dq[a];
+                        qb[a] = S.q0[a] + kkb * S.dq[a];
+                    }
+                    cla = lit_stencil<REC, LAY>(A, S, qa[0], qa[1], qa[2], Fa, Fpa, Fma);
+                    clb = lit_stencil<REC, LAY>(A, S, qb[0], qb[1], qb[2], Fb, Fpb, Fmb);
+                    const float alpha = lit_consume<REC>(A, s_lut, Q, lane, R, S, k, nullptr, qa[0], qa[1], qa[2], Fa,
+                                                         Fpa, Fma, cla, pending_taps(cla), T, C0, C1, C2, cnt, trow,
+                                                         &tpos);
+                    T *= 1.f - alpha;
+                    nsamp_total++;
+                    k++;
+                    if (T < A.t_min) {
+                        alive = false;
+                        has = false;
+                    } else if (k == S.n) {
+                        has = false;
+                    }
+                }
+                const unsigned long long second = __ballot(has);
+                const unsigned long long needb = __ballot(has && pending_taps(clb) != 0u);
+                if (second && !tapq_full(tq_count(Q), needb) && has) {
+                    const float alpha = lit_consume<REC>(A, s_lut, Q, lane, R, S, k, nullptr, qb[0], qb[1], qb[2], Fb,
+                                                         Fpb, Fmb, clb, pending_taps(clb), T, C0, C1, C2, cnt, trow,
+                                                         &tpos);
+                    T *= 1.f - alpha;
+                    nsamp_total++;
+                    k++;
+                    if (T < A.t_min) {
+                        alive = false;
+                        has = false;
+                    } else if (k == S.n) {
+                        has = false;
+                    }
+                }
+            } else if (has) {
                 const float alpha = lit_sample_deferred<REC, LAY, NEAR>(A, s_lut, Q, lane, R, S, k, T, C0, C1, C2, cnt,
                                                                        trow, &tpos);
                 T *= 1.f - alpha;

@@ -1382,6 +1382,37 @@ __device__ __forceinline__ uint32_t pending_taps(uint32_t cls) {
     return pend;
 }
 
+// The part of a lit sample after its stencil: LUT classification, then either the shading and
+// colour at once (every tap in the brick) or a queue slot (tapq_push: every lane of the calling
+// set takes part).  xs: the sample's FP64 position if already known (else null).  With a tape
+// row, the sample's record is written (at once) or its tape position queued.  Returns alpha.
+template <bool REC>
+__device__ __forceinline__ float lit_consume(const RenderArgs &A, const float4 *s_lut, TapQueue &Q, int lane,
+                                             const Ray &R, const Segment &S, int k, const double *xs, float qx,
+                                             float qy, float qz, float F, const float Fp[3], const float Fm[3],
+                                             uint32_t cls, uint32_t pend, float T, float &C0, float &C1, float &C2,
+                                             Counters &cnt, float4 *trow, uint32_t *tpos) {
+    SampleVals v;
+    lut_classify(A, s_lut, F, S.dl, v);
+    const float Ta = T * v.alpha;
+    const bool defer = pend != 0;
+    const uint32_t pos = trow ? *tpos : 0u;
+    const uint32_t cap = (uint32_t)A.tape_cap;
+    if (!defer) {
+        float gv[3], dot, den;
+        lit_gradient(A, F, Fp, Fm, 0x3fu, gv);
+        const float wgt = Ta * lit_shade(A, gv, dot, den);
+        C0 += wgt * v.r;
+        C1 += wgt * v.g;
+        C2 += wgt * v.b;
+        if (trow && pos < cap) trow[pos] = make_float4(F, gv[0], gv[1], gv[2]);
+    }
+    const uint32_t ord = pos < cap ? pos : cap;
+    if (trow) *tpos = pos + 1u;
+    tapq_push<REC>(A, Q, lane, defer, R, S, k, xs, qx, qy, qz, F, Fp, Fm, cls, pend, Ta, v, cnt, ord);
+    return v.alpha;
+}
+
 // One lit sample of a marching lane with deferred taps: the in-brick part now; the sample is
 // queued when a tap leaves the brick (trilinear) or needs the tree (nearest cell), else shaded
 // and added to (C0, C1, C2) at once.  Returns the opacity.  All marching lanes call it in the
@@ -1444,26 +1475,8 @@ __device__ __forceinline__ float lit_sample_deferred(const RenderArgs &A, const 
         cls = lit_stencil<REC, LAY>(A, S, qx, qy, qz, F, Fp, Fm);
         pend = pending_taps(cls);
     }
-    SampleVals v;
-    lut_classify(A, s_lut, F, S.dl, v);
-    const float Ta = T * v.alpha;
-    const bool defer = pend != 0;
-    const uint32_t pos = trow ? *tpos : 0u;
-    const uint32_t cap = (uint32_t)A.tape_cap;
-    if (!defer) {
-        float gv[3], dot, den;
-        lit_gradient(A, F, Fp, Fm, 0x3fu, gv);
-        const float wgt = Ta * lit_shade(A, gv, dot, den);
-        C0 += wgt * v.r;
-        C1 += wgt * v.g;
-        C2 += wgt * v.b;
-        if (trow && pos < cap) trow[pos] = make_float4(F, gv[0], gv[1], gv[2]);
-    }
-    const uint32_t ord = pos < cap ? pos : cap;
-    if (trow) *tpos = pos + 1u;
-    tapq_push<REC>(A, Q, lane, defer, R, S, k, have_xs ? xs : nullptr, qx, qy, qz, F, Fp, Fm, cls, pend, Ta, v, cnt,
-                   ord);
-    return v.alpha;
+    return lit_consume<REC>(A, s_lut, Q, lane, R, S, k, have_xs ? xs : nullptr, qx, qy, qz, F, Fp, Fm, cls, pend, T,
+                            C0, C1, C2, cnt, trow, tpos);
 }
 
 // After the march, by all lanes of the wave: resolve what is queued; returns the lane's

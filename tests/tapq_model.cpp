@@ -7,7 +7,10 @@
 //           sampling lane, and, with checkpoints, before each segment fetch);
 //   mode 1: the persistent kernel's per-segment loop (the lanes still sampling a segment
 //           reserve slots and resolve the queue themselves; four such waves share a block but
-//           each has its own queue, so one wave is modelled at a time).
+//           each has its own queue, so one wave is modelled at a time);
+//   mode 2: the stepped loop of the non-recording single-camera kernels: after a step's sample,
+//           the lanes that still have one take their next sample in the same step when the
+//           queue has a slot for each of them whose sample is queued.
 // Every slot, owner, run bound, leaf, patch and pool index is checked; every queued sample
 // must be resolved exactly once, and each owner's deferred contributions must arrive in its
 // sample order.  Input (stdin, whitespace separated):
@@ -188,7 +191,7 @@ static void fetch(Lane &l) {
     }
 }
 
-static void run_stepped(Queue &Q, std::vector<Lane> &L, bool ckpt) {
+static void run_stepped(Queue &Q, std::vector<Lane> &L, bool ckpt, bool two) {
     while (true) {
         uint64_t live = 0, samp = 0, wait = 0;
         for (int i = 0; i < 64; i++) {
@@ -207,6 +210,16 @@ static void run_stepped(Queue &Q, std::vector<Lane> &L, bool ckpt) {
         }
         CHECK(samp != 0);
         sample_step(Q, samp, L);
+        if (two) {
+            uint64_t samp2 = 0, need2 = 0;
+            for (int i = 0; i < 64; i++) {
+                if (!L[i].has) continue;
+                samp2 |= 1ull << i;
+                const int f = L[i].segs[L[i].cur].flag[L[i].k];
+                if (f == 1 || f == 2) need2 |= 1ull << i;
+            }
+            if (samp2 && !tapq_full(Q.count, need2)) sample_step(Q, samp2, L);
+        }
     }
     if (Q.count) flush(Q, ~0ull, L);
 }
@@ -263,8 +276,8 @@ int main() {
         }
         Queue Q;
         g_step = 0;
-        if (mode == 0) run_stepped(Q, L, ckpt != 0);
-        else run_per_segment(Q, L);
+        if (mode == 1) run_per_segment(Q, L);
+        else run_stepped(Q, L, ckpt != 0, mode == 2);
         for (int i = 0; i < 64; i++) {
             CHECK(!L[i].alive && !L[i].has);
             CHECK(L[i].resolved == L[i].queued && L[i].last_ord + 1 == L[i].queued);

@@ -10,9 +10,10 @@ streams of real views: the oracle's segment lists of the tiny SAMR view and of 8
 1024x1024 cosmology-like view, each sample marked as queued when one of its six gradient taps
 leaves its leaf box (the kernels queue a subset of those: taps beyond a face whose one-cell slab
 is the same patch's stay in the brick), and the ray's last sample marked as its end where early
-termination cuts it short.  Both kernels' loops are modelled: the single-camera stepped loop
-(with and without checkpoints, which resolve the queue before every segment fetch) and the
-persistent kernel's per-segment loop."""
+termination cuts it short.  The kernels' loops are modelled: the single-camera stepped loop
+with one sample per step (recording kernels) and with a second sample when the queue has room
+for it (the others), each with and without checkpoints (which resolve the queue before every
+segment fetch), and the persistent kernel's per-segment loop."""
 import os
 import shutil
 import subprocess
@@ -24,6 +25,9 @@ import oracle
 import workloads
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+# (mode, checkpoints): 0 stepped loop, one sample per step; 1 per-segment loop; 2 stepped loop
+# with a second sample per step when the queue has room
+MODES = [(0, 0), (0, 1), (1, 0), (2, 0), (2, 1)]
 
 
 @pytest.fixture(scope="module")
@@ -88,7 +92,7 @@ def _synthetic(seed, p_queue, nwaves=24, p_end=0.002, empty_rays=0.05):
 
 
 @pytest.mark.parametrize("p_queue", [0.0, 0.19, 0.6, 1.0])
-@pytest.mark.parametrize("mode,ckpt", [(0, 0), (0, 1), (1, 0)])
+@pytest.mark.parametrize("mode,ckpt", MODES)
 def test_queue_protocol_synthetic(model, mode, ckpt, p_queue):
     stats = _run(model, _encode(mode, ckpt, 50, 20, 4096, _synthetic(11 + int(100 * p_queue), p_queue)))
     print(mode, ckpt, p_queue, stats)
@@ -102,7 +106,7 @@ def test_queue_protocol_single_lane_and_full_pressure(model):
     one = [[] for _ in range(64)]
     one[37] = [(300, 1, 0, 0, [1] * 299 + [2])]
     full = [[(200, 0, 0, 0, [1] * 200)] for _ in range(64)]
-    for mode, ckpt in ((0, 0), (0, 1), (1, 0)):
+    for mode, ckpt in MODES:
         s = _run(model, _encode(mode, ckpt, 2, 1, 64, [one, full]))
         assert int(s["queued"]) == 300 + 64 * 200
 
@@ -162,7 +166,7 @@ def test_queue_protocol_tiny_view(model):
     prm = dict(prm, lighting=True)
     tiles = [(tx, ty) for ty in range(0, 32, 3) for tx in range(0, 32, 3)]
     waves, nl, npch = _view_waves(h, cams[1], lut, prm, tiles)
-    for mode, ckpt in ((0, 0), (0, 1), (1, 0)):
+    for mode, ckpt in MODES:
         s = _run(model, _encode(mode, ckpt, nl, npch, npch, waves))
         print("tiny view mode %d ckpt %d:" % (mode, ckpt), s)
         assert int(s["queued"]) > 0
@@ -174,7 +178,7 @@ def test_queue_protocol_cosmology_view(model):
     tiles = [(60 + i, 60 + j) for i in range(6) for j in range(6)] + [(8 * k, 7 * k + 3) for k in range(16)] + \
             [(100 + k, 30) for k in range(12)]
     waves, nl, npch = _view_waves(h, cam, lut, prm, tiles)
-    for mode, ckpt in ((0, 0), (0, 1), (1, 0)):
+    for mode, ckpt in MODES:
         s = _run(model, _encode(mode, ckpt, nl, npch, npch, waves))
         print("cosmology view mode %d ckpt %d:" % (mode, ckpt), s)
         assert int(s["queued"]) > 1000 and int(s["flushes"]) > 0
