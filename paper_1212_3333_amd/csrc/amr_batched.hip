@@ -213,6 +213,41 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPS))) void
                     bool stop;
                     nsamp_total += composite_unlit<LAY>(A, s_lut, R, S, T, C0, C1, C2, tseg, stop, cnt);
                     if (stop) alive = false;
+                } else if constexpr (LIT && !REC) {
+                    // as the single-camera kernel: the stencils of a lane's next two samples are
+                    // read together; after the first, the lanes still in this loop (each with a
+                    // second sample) take it when the queue has a slot for those of them whose
+                    // second sample defers, else they read it again in the next round
+                    TapQueue &Q = *tq;
+                    for (int k2 = 0; k2 < S.n;) {
+                        tapq_reserve<REC, LAY>(A, s_lut, Q, lane, cnt);
+                        const int kb = min(k2 + 1, S.n - 1);
+                        const float kka = (float)k2 + 0.5f, kkb = (float)kb + 0.5f;
+                        float qa[3], qb[3], Fa, Fpa[3], Fma[3], Fb, Fpb[3], Fmb[3];
+                        #pragma unroll
+                        for (int a = 0; a < 3; a++) {
+                            qa[a] = S.q0[a] + kka * S.dq[a];
+                            qb[a] = S.q0[a] + kkb * S.dq[a];
+                        }
+                        const uint32_t cla = lit_stencil<REC, LAY>(A, S, qa[0], qa[1], qa[2], Fa, Fpa, Fma);
+                        const uint32_t clb = lit_stencil<REC, LAY>(A, S, qb[0], qb[1], qb[2], Fb, Fpb, Fmb);
+                        float alpha = lit_consume<REC>(A, s_lut, Q, lane, R, S, k2, nullptr, qa[0], qa[1], qa[2], Fa,
+                                                       Fpa, Fma, cla, pending_taps(cla), T, C0, C1, C2, cnt, nullptr,
+                                                       nullptr);
+                        T *= 1.f - alpha;
+                        nsamp_total++;
+                        k2++;
+                        if (T < A.t_min) { alive = false; break; }
+                        if (k2 == S.n) break;
+                        const unsigned long long needb = __ballot(pending_taps(clb) != 0u);
+                        if (tapq_full(tq_count(Q), needb)) continue;
+                        alpha = lit_consume<REC>(A, s_lut, Q, lane, R, S, k2, nullptr, qb[0], qb[1], qb[2], Fb, Fpb,
+                                                 Fmb, clb, pending_taps(clb), T, C0, C1, C2, cnt, nullptr, nullptr);
+                        T *= 1.f - alpha;
+                        nsamp_total++;
+                        k2++;
+                        if (T < A.t_min) { alive = false; break; }
+                    }
                 } else {
                     for (int k2 = 0; k2 < S.n; k2++) {
                         float alpha;

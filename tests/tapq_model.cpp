@@ -10,7 +10,9 @@
 //           each has its own queue, so one wave is modelled at a time);
 //   mode 2: the stepped loop of the non-recording single-camera kernels: after a step's sample,
 //           the lanes that still have one take their next sample in the same step when the
-//           queue has a slot for each of them whose sample is queued.
+//           queue has a slot for each of them whose sample is queued;
+//   mode 3: the per-segment loop of the non-recording persistent kernel, with the same second
+//           sample per round for the lanes still in their segment.
 // Every slot, owner, run bound, leaf, patch and pool index is checked; every queued sample
 // must be resolved exactly once, and each owner's deferred contributions must arrive in its
 // sample order.  Input (stdin, whitespace separated):
@@ -224,7 +226,7 @@ static void run_stepped(Queue &Q, std::vector<Lane> &L, bool ckpt, bool two) {
     if (Q.count) flush(Q, ~0ull, L);
 }
 
-static void run_per_segment(Queue &Q, std::vector<Lane> &L) {
+static void run_per_segment(Queue &Q, std::vector<Lane> &L, bool two) {
     while (true) {
         // the lanes still marching fetch their next segment together
         uint64_t outer = 0;
@@ -250,6 +252,16 @@ static void run_per_segment(Queue &Q, std::vector<Lane> &L) {
             g_step++;
             if (tapq_full(Q.count, act)) flush(Q, act, L);
             sample_step(Q, act, L);
+            if (two) {
+                uint64_t act2 = 0, need2 = 0;
+                for (int i = 0; i < 64; i++) {
+                    if (!((act >> i) & 1ull) || !L[i].has) continue;
+                    act2 |= 1ull << i;
+                    const int f = L[i].segs[L[i].cur].flag[L[i].k];
+                    if (f == 1 || f == 2) need2 |= 1ull << i;
+                }
+                if (act2 && !tapq_full(Q.count, need2)) sample_step(Q, act2, L);
+            }
         }
     }
     if (Q.count) flush(Q, ~0ull, L);
@@ -276,7 +288,7 @@ int main() {
         }
         Queue Q;
         g_step = 0;
-        if (mode == 1) run_per_segment(Q, L);
+        if (mode == 1 || mode == 3) run_per_segment(Q, L, mode == 3);
         else run_stepped(Q, L, ckpt != 0, mode == 2);
         for (int i = 0; i < 64; i++) {
             CHECK(!L[i].alive && !L[i].has);

@@ -13,7 +13,8 @@ is the same patch's stay in the brick), and the ray's last sample marked as its 
 termination cuts it short.  The kernels' loops are modelled: the single-camera stepped loop
 with one sample per step (recording kernels) and with a second sample when the queue has room
 for it (the others), each with and without checkpoints (which resolve the queue before every
-segment fetch), and the persistent kernel's per-segment loop."""
+segment fetch), and the persistent kernel's per-segment loop, with one sample per round
+(recording) and with a second one when the queue has room."""
 import os
 import shutil
 import subprocess
@@ -25,9 +26,9 @@ import oracle
 import workloads
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-# (mode, checkpoints): 0 stepped loop, one sample per step; 1 per-segment loop; 2 stepped loop
-# with a second sample per step when the queue has room
-MODES = [(0, 0), (0, 1), (1, 0), (2, 0), (2, 1)]
+# (mode, checkpoints): 0 stepped loop, one sample per step; 1 per-segment loop; 2 and 3 the same
+# loops with a second sample per step or round when the queue has room
+MODES = [(0, 0), (0, 1), (1, 0), (2, 0), (2, 1), (3, 0)]
 
 
 @pytest.fixture(scope="module")
