@@ -321,8 +321,9 @@ typedef struct {
        of the same sizes starts them in that order, longest first, so that the launch does not
        end waiting on long tiles started late.  A call whose camera sizes differ renders in the
        default order and records a new order.  Images do not depend on the order.  The
-       raycaster only: AMR_EINVAL with persistent mode, learned proposals or the point light.
-       Calls that overlap on one schedule race on it */
+       raycaster only: AMR_EINVAL with persistent mode, learned proposals or the point light, or
+       for a camera of 2^24 or more 32x32-pixel super-tiles.  Calls that overlap on one schedule
+       race on it */
     void *d_sched;
     int64_t sched_bytes;
 } amr_render_params;

@@ -1004,6 +1004,13 @@ int amr_render(const amr_scene *S, const amr_camera *cams, int32_t ncams, const 
             set_error("d_sched must be 4-byte aligned");
             return AMR_EINVAL;
         }
+        for (int c = 0; c < ncams; c++) {      // an order entry holds the super-tile in 24 bits
+            const int64_t nst = (int64_t)((cams[c].width + 31) / 32) * (int64_t)((cams[c].height + 31) / 32);
+            if (nst >= ((int64_t)1 << 24)) {
+                set_error("the tile schedule takes cameras of fewer than 2^24 super-tiles of 32x32 pixels");
+                return AMR_EINVAL;
+            }
+        }
     }
     if (P->d_mlp && (reinterpret_cast<uintptr_t>(P->d_mlp) & 15u)) {
         set_error("d_mlp must be 16-byte aligned");

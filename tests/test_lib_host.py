@@ -454,7 +454,8 @@ def _render_call(lib, scene, cams, prm, set_fields=None, lut_ok=True):
     """amr_render on host buffers standing in for device pointers (rejected calls only)."""
     carr = (L.amr_camera * len(cams))(*[amr.make_camera(c) for c in cams])
     lutbuf = np.zeros((256, 4), np.float32)
-    rgba = np.zeros(4 * max(1, sum(max(0, c["width"]) * max(0, c["height"]) for c in cams)), np.float32)
+    # never written (every call here is rejected first), so capped for the huge-camera cases
+    rgba = np.zeros(min(1 << 20, 4 * max(1, sum(max(0, c["width"]) * max(0, c["height"]) for c in cams))), np.float32)
     scratch = np.zeros(1 << 16, np.uint8)
     q = amr.make_params(prm, lutbuf)
     if not lut_ok:
@@ -470,7 +471,8 @@ def _render_call(lib, scene, cams, prm, set_fields=None, lut_ok=True):
 
 @pytest.mark.parametrize("case", ["v_range", "step", "cam_size", "interp", "lighting", "lod", "lut", "trace_cap",
                                   "ckpt_odd", "ckpt_small", "tile", "no_queue", "light_no_work", "light_work_small",
-                                  "tape_cap", "tape_align", "waves_per_simd", "sched_small", "sched_persistent"])
+                                  "tape_cap", "tape_align", "waves_per_simd", "sched_small", "sched_persistent",
+                                  "sched_huge"])
 def test_render_argument_checks(case):
     """amr_render's argument checks, each of which returns before any device access (host buffers
     stand in for device pointers, so the test runs only where no GPU is visible)."""
@@ -519,6 +521,10 @@ def test_render_argument_checks(case):
     elif case == "sched_persistent":
         p, words = dict(prm, persistent=1), "tile schedule"
         fields = dict(d_queue="buf", d_sched="buf", sched_bytes=1 << 16)
+    elif case == "sched_huge":
+        # 4096 x 4097 super-tiles: one past the 24 bits an order entry holds them in
+        cl, words = [cam, dict(cam, width=4096 * 32, height=4096 * 32 + 1)], "2^24 super-tiles"
+        fields = dict(d_sched="buf", sched_bytes=1 << 40)
     elif case == "waves_per_simd":
         p, fields, words = dict(prm, persistent=1, lighting=1, waves_per_simd=4), dict(d_queue="buf"), "waves_per_simd"
     elif case == "tape_cap":
