@@ -316,13 +316,14 @@ typedef struct {
     int32_t pad3_;
     /* tile schedule (device, NULL to skip; amr_sched_bytes bytes, caller-owned, zeroed before its
        first use and kept across calls for the same cameras): every call records how long each
-       8x8 tile of each camera took and sorts the 32x32-pixel super-tiles of each launch's
-       cameras (up to 8 per launch) together by their longest tile; the next call with cameras
+       8x8 tile of each camera took and sorts the super-tiles (16x16 pixels lit, 32x32 unlit) of
+       each launch's cameras (up to 8 per launch) together by their longest tile; the next call
+       with the same lighting and cameras
        of the same sizes starts them in that order, longest first, so that the launch does not
-       end waiting on long tiles started late.  A call whose camera sizes differ renders in the
-       default order and records a new order.  Images do not depend on the order.  The
+       end waiting on long tiles started late.  A call whose lighting or camera sizes differ
+       renders in the default order and records a new order.  Images do not depend on the order.  The
        raycaster only: AMR_EINVAL with persistent mode, learned proposals or the point light, or
-       for a camera of 2^24 or more 32x32-pixel super-tiles.  Calls that overlap on one schedule
+       for a camera of 2^24 or more super-tiles.  Calls that overlap on one schedule
        race on it */
     void *d_sched;
     int64_t sched_bytes;

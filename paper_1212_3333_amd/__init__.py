@@ -503,9 +503,9 @@ def default_tape_cap(nrays: int, device=None, total_memory: int | None = None) -
 
 class Schedule:
     """Tile schedule for repeated renders of the same cameras (amr_sched_bytes; pass **params()
-    to render): every call records each 8x8 tile's time, and the next call with cameras of the
-    same sizes starts the 32x32-pixel super-tiles of each launch's cameras (up to 8) with the
-    longest tiles first.  Zeroed at creation; reset() forgets the recorded order (after a large
+    to render): every call records each 8x8 tile's time, and the next call with the same
+    lighting and cameras of the same sizes starts the super-tiles (16x16 pixels lit, 32x32 unlit)
+    of each launch's cameras (up to 8) with the longest tiles first.  Zeroed at creation; reset() forgets the recorded order (after a large
     change of view)."""
 
     def __init__(self, cams, device):

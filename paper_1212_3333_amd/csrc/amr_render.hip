@@ -40,8 +40,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void re
     // has recorded it, camera by camera, super-tiles row by row)
     int gc = (int)blockIdx.y;
     uint32_t sst = 0xffffffffu;
+    constexpr uint32_t kSide = sched_side(LIT);
     if (G.sched) {
-        const uint32_t rank = (blockIdx.x / 128u) * 8u + blockIdx.x % 8u;
+        const uint32_t rank = (blockIdx.x / (8u * kSide * kSide)) * 8u + blockIdx.x % 8u;
         if (rank >= G.nst) return;
         uint32_t e;
         if (A.sched_hdr[4 * G.cam0 + 1] == G.sig) {
@@ -70,14 +71,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void re
     // part of the image (the work per tile varies by 10x and more across the screen), while
     // the tiles in flight on one XCD stay grouped in a few compact 32x32 patches whose rays
     // share bricks in that XCD's L2.  With a tile schedule, the super-tiles of all the launch's
-    // cameras are dealt the same way in the schedule's order (longest tile of the last call
-    // first) instead.
+    // cameras (kSide x kSide tiles) are dealt the same way in the schedule's order (longest tile
+    // of the last call first) instead.
     int col, row;
     if (G.sched) {
-        const uint32_t sgw = (uint32_t)(A.t8x + 3) / 4u;
-        const int li = (int)(blockIdx.x / 8);
-        col = (int)(sst % sgw) * 4 + ((li & 15) >> 2);
-        row = (int)(sst / sgw) * 4 + (li & 3);
+        const uint32_t sgw = ((uint32_t)A.t8x + kSide - 1u) / kSide;
+        const uint32_t li = blockIdx.x / 8u;
+        col = (int)((sst % sgw) * kSide + (li % (kSide * kSide)) / kSide);
+        row = (int)((sst / sgw) * kSide + li % kSide);
     } else {
         const int xcd = (int)(blockIdx.x % 8), li = (int)(blockIdx.x / 8);
         const int sidx = (li >> 4) * 8 + xcd;          // Morton index of the super-tile
@@ -682,7 +683,7 @@ __global__ __launch_bounds__(256) void render_bwd_tape(RenderArgs A, BwdArgs B) 
     adjoint_block_end<true>(B, s_acc, gs);
 }
 
-// Tile schedule for the next call: the 4x4-tile super-tiles of all cameras of a launch ordered by
+// Tile schedule for the next call: the super-tiles (sched_side) of all cameras of a launch ordered by
 // the time of their longest tile, longest first (a counting sort over 512 logarithmic buckets, 16
 // per octave of the wall clock's ticks; the order within a bucket is arbitrary), one block; the
 // header of the group's first camera then records the order's key, a signature of the call's
@@ -698,7 +699,8 @@ struct SchedGroup {
     int32_t n, cam0;
     uint32_t sig, list_sig;
     int64_t order0;
-    int32_t ncams, pad_;
+    int32_t ncams;
+    uint32_t side;                   // super-tile side in tiles (sched_side)
 };
 constexpr int kSchedBuckets = 512;
 
@@ -722,11 +724,12 @@ __global__ __launch_bounds__(1024) void sched_sort(uint32_t *hdr, const uint32_t
         const int c = (int)(e >> 24);
         const uint32_t st = e & 0xffffffu;
         const int t8x = G.t8x[c], t8y = G.t8y[c];
-        const uint32_t sgw = (uint32_t)(t8x + 3) / 4u;
-        const int sx = (int)(st % sgw) * 4, sy = (int)(st / sgw) * 4;
+        const uint32_t side = G.side;
+        const uint32_t sgw = ((uint32_t)t8x + side - 1u) / side;
+        const int sx = (int)((st % sgw) * side), sy = (int)((st / sgw) * side);
         uint32_t m = 0u;
-        for (int j = 0; j < 16; j++) {
-            const int cx = sx + (j >> 2), cy = sy + (j & 3);
+        for (int j = 0; j < (int)(side * side); j++) {
+            const int cx = sx + j / (int)side, cy = sy + j % (int)side;
             if (cx < t8x && cy < t8y) m = max(m, time[G.tile0[c] + (int64_t)cy * t8x + cx]);
         }
         return m;
@@ -1004,10 +1007,12 @@ int amr_render(const amr_scene *S, const amr_camera *cams, int32_t ncams, const 
             set_error("d_sched must be 4-byte aligned");
             return AMR_EINVAL;
         }
+        const int64_t sp = 8 * (int64_t)sched_side(P->lighting == 1);   // super-tile side in pixels
         for (int c = 0; c < ncams; c++) {      // an order entry holds the super-tile in 24 bits
-            const int64_t nst = (int64_t)((cams[c].width + 31) / 32) * (int64_t)((cams[c].height + 31) / 32);
+            const int64_t nst = ((cams[c].width + sp - 1) / sp) * ((cams[c].height + sp - 1) / sp);
             if (nst >= ((int64_t)1 << 24)) {
-                set_error("the tile schedule takes cameras of fewer than 2^24 super-tiles of 32x32 pixels");
+                set_error("the tile schedule takes cameras of fewer than 2^24 super-tiles (16x16 pixels lit, "
+                          "32x32 unlit)");
                 return AMR_EINVAL;
             }
         }
@@ -1077,9 +1082,10 @@ int amr_render(const amr_scene *S, const amr_camera *cams, int32_t ncams, const 
     for (int c = 0; c < ncams; c++) sched_ntot += sched_tiles(cams[c]);
     uint32_t *sched_time = sched ? sched + sched_header_words(ncams) : nullptr;
     uint32_t *sched_order = sched ? sched_time + sched_ntot : nullptr;
-    // the key of an order: FNV-1a over the call's camera count and every camera's tile grid,
-    // then the group's first camera (0 is left for a zeroed schedule)
-    uint32_t list_sig = (2166136261u ^ (uint32_t)ncams) * 16777619u;
+    // the key of an order: FNV-1a over the super-tile side, the call's camera count and every
+    // camera's tile grid, then the group's first camera (0 is left for a zeroed schedule)
+    const uint32_t side = sched_side(P->lighting == 1);
+    uint32_t list_sig = (((2166136261u ^ side) * 16777619u) ^ (uint32_t)ncams) * 16777619u;
     for (int c = 0; c < ncams; c++)
         for (uint32_t w : {(uint32_t)(cams[c].width + 7) / 8u, (uint32_t)(cams[c].height + 7) / 8u})
             list_sig = (list_sig ^ w) * 16777619u;
@@ -1108,7 +1114,7 @@ int amr_render(const amr_scene *S, const amr_camera *cams, int32_t ncams, const 
             SG.t8x[i] = Ai.t8x;
             SG.t8y[i] = Ai.t8y;
             SG.stpre[i] = G.stpre[i] = nst;
-            nst += (uint32_t)((Ai.t8x + 3) / 4) * (uint32_t)((Ai.t8y + 3) / 4);
+            nst += (((uint32_t)Ai.t8x + side - 1u) / side) * (((uint32_t)Ai.t8y + side - 1u) / side);
             rel += (int64_t)cams[c0 + i].width * cams[c0 + i].height;
             tile_off += sched_tiles(cams[c0 + i]);
         }
@@ -1128,6 +1134,7 @@ int amr_render(const amr_scene *S, const amr_camera *cams, int32_t ncams, const 
             SG.order0 = order0;
             SG.list_sig = list_sig;
             SG.ncams = ncams;
+            SG.side = side;
         }
         A.sched_hdr = sched;
         A.sched_time = sched_time;
@@ -1142,7 +1149,7 @@ int amr_render(const amr_scene *S, const amr_camera *cams, int32_t ncams, const 
         A.ckpt_ray0 = pix_off;
         const bool rec = A.trace || A.trace_n || A.nsamp || A.stats || A.touch || A.touch_meta || A.ckpt;
         // scheduled: one-dimensional, 16 blocks per super-tile, ranks dealt to the 8 XCDs in turn
-        const dim3 g(sched ? 128 * ((nst + 7) / 8) : gx, sched ? 1 : n), b(64);
+        const dim3 g(sched ? 8 * side * side * ((nst + 7) / 8) : gx, sched ? 1 : n), b(64);
         if (A.nearest) {
             if (A.lighting) {
                 if (rec) hipLaunchKernelGGL((render_fwd<true, true, true, -1>), g, b, 0, s, A, G);

@@ -93,12 +93,17 @@ struct CamArgs {
     int32_t cam, pad_;               // the camera's index in the call
 };
 constexpr int kCamGroup = 8;
+// Side of a tile schedule's super-tile in 8x8 tiles: 2 (16x16 pixels) for lit renders, whose
+// longest tiles are long enough that a finer order shortens the launch's tail, 4 (32x32 pixels)
+// for unlit ones, whose short tiles gain more from sharing bricks in an XCD's L2.
+__host__ __device__ constexpr uint32_t sched_side(bool lit) { return lit ? 2u : 4u; }
+
 struct CamGroup {
     CamArgs cam[kCamGroup];
     int32_t n;                       // cameras in the group; 0: one camera, RenderArgs as given
-    // with a tile schedule: the launch is one-dimensional over the group's super-tiles
-    // (32x32 pixels), block b taking rank (b / 128) * 8 + b % 8 of the order and tile (b / 8) % 16
-    // of that super-tile; an order entry is camera << 24 | super-tile
+    // with a tile schedule: the launch is one-dimensional over the group's super-tiles of
+    // s x s tiles (s = sched_side), block b taking rank (b / (8 s^2)) * 8 + b % 8 of the order
+    // and tile (b / 8) % s^2 of that super-tile; an order entry is camera << 24 | super-tile
     int32_t sched;                   // 1: a scheduled launch
     uint32_t nst;                    // super-tiles of the group
     uint32_t sig;                    // signature of the group's camera sizes, the order's key

@@ -491,9 +491,9 @@ def _sched_bucket(t):
 @pytest.mark.parametrize("mode", ["timed", "recording", "checkpoints"])
 @pytest.mark.parametrize("lit", [False, True])
 def test_tile_schedule(gpu, lit, mode):
-    """With a tile schedule, each call records every tile's time and sorts the 4x4-tile super-tiles
-    of each launch's cameras (up to 8) by their longest tile; the next call starts them in that
-    order.  Over three calls of ten cameras of different sizes (two launches), images, sample
+    """With a tile schedule, each call records every tile's time and sorts the super-tiles (2x2
+    tiles lit, 4x4 unlit) of each launch's cameras (up to 8) by their longest tile; the next call
+    starts them in that order.  Over three calls of ten cameras of different sizes (two launches), images, sample
     counts and traces (recording kernels), checkpoint records and tape records (checkpointed
     kernels) are bit-identical to the calls without a schedule; afterwards each launch's order
     holds every (camera, super-tile) of its cameras once, in non-increasing buckets of their
@@ -543,10 +543,12 @@ def test_tile_schedule(gpu, lit, mode):
     toff = np.concatenate([[0], np.cumsum([x * y for x, y in t8])])
     ntot = int(toff[-1])
     tm, order = words[hw:hw + ntot], words[hw + ntot:hw + 2 * ntot]
+    side = 2 if lit else 4
     for c0 in range(0, len(cl), 8):
         grp = list(range(c0, min(c0 + 8, len(cl))))
         assert words[4 * c0 + 1] != 0, c0
-        pairs = [(i, s) for i, c in enumerate(grp) for s in range(((t8[c][0] + 3) // 4) * ((t8[c][1] + 3) // 4))]
+        pairs = [(i, s) for i, c in enumerate(grp)
+                 for s in range(((t8[c][0] + side - 1) // side) * ((t8[c][1] + side - 1) // side))]
         o = order[toff[c0]:toff[c0] + len(pairs)]
         got = [(int(e) >> 24, int(e) & 0xffffff) for e in o]
         assert sorted(got) == sorted(pairs), c0
@@ -554,19 +556,20 @@ def test_tile_schedule(gpu, lit, mode):
         def longest(i, s):
             c = grp[i]
             tx, ty = t8[c]
-            sgw = (tx + 3) // 4
+            sgw = (tx + side - 1) // side
             times = tm[toff[c]:toff[c] + tx * ty].reshape(ty, tx)
-            return int(times[(s // sgw) * 4:(s // sgw) * 4 + 4, (s % sgw) * 4:(s % sgw) * 4 + 4].max())
+            y0, x0 = (s // sgw) * side, (s % sgw) * side
+            return int(times[y0:y0 + side, x0:x0 + side].max())
         bk = [_sched_bucket(longest(i, s)) for (i, s) in got]
         assert all(bk[j] >= bk[j + 1] for j in range(len(bk) - 1)), c0
 
 
 def test_tile_schedule_camera_list_change(gpu):
     """One schedule buffer used with 18 cameras (three launches), then 9 other cameras of other
-    sizes, whose header, times and orders overwrite parts of the first list's, then the 18 again:
-    every call's images equal those of calls without a schedule (the 9-camera call and the
-    return to the 18 render in the default order and record afresh; the next call of the 18
-    uses the new order)."""
+    sizes, whose header, times and orders overwrite parts of the first list's, then the 18 again,
+    then the 18 unlit (other super-tiles) and lit again: every call's images equal those of calls
+    without a schedule (a call after a change renders in the default order and records afresh;
+    the next one uses the new order)."""
     import torch
     amr = gpu
     h, lut, cams, prm = workloads.small_nested(1)
@@ -587,3 +590,11 @@ def test_tile_schedule_camera_list_change(gpu):
         assert torch.equal(img(cl, **sch.params()), ref1 if cl is l1 else ref2), i
     words = sch.buf.view(torch.int32).cpu().numpy().view(np.uint32)
     assert all(words[4 * c0 + 1] != 0 for c0 in (0, 8, 16))
+    # unlit calls use larger super-tiles: the lit order is not reused, and back again
+    prm_u = dict(prm, lighting=False)
+    ref_u = amr.render(scene, l1, lut_t, prm_u)["rgba"].clone()
+    for i in range(2):
+        got = amr.render(scene, l1, lut_t, prm_u, **sch.params())["rgba"]
+        torch.cuda.synchronize()
+        assert torch.equal(got, ref_u), i
+    assert torch.equal(img(l1, **sch.params()), ref1)
