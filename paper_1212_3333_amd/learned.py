@@ -1,6 +1,7 @@
 """Learned segment proposals: log segments with the plain traversal, train the 12-64-64-2
 network on the GPU with the library's kernels, calibrate the skip thresholds on held-out views,
-render with the learned form.  The plain traversal stays the fallback and the judge of error.
+render with the learned form.  The plain traversal stays the fallback and the reference for the
+error.
 """
 from __future__ import annotations
 
