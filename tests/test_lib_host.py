@@ -472,7 +472,7 @@ def _render_call(lib, scene, cams, prm, set_fields=None, lut_ok=True):
 @pytest.mark.parametrize("case", ["v_range", "step", "cam_size", "interp", "lighting", "lod", "lut", "trace_cap",
                                   "ckpt_odd", "ckpt_small", "tile", "no_queue", "light_no_work", "light_work_small",
                                   "tape_cap", "tape_align", "waves_per_simd", "sched_small", "sched_persistent",
-                                  "sched_huge"])
+                                  "sched_huge", "sched_huge_lit"])
 def test_render_argument_checks(case):
     """amr_render's argument checks, each of which returns before any device access (host buffers
     stand in for device pointers, so the test runs only where no GPU is visible)."""
@@ -522,8 +522,13 @@ def test_render_argument_checks(case):
         p, words = dict(prm, persistent=1), "tile schedule"
         fields = dict(d_queue="buf", d_sched="buf", sched_bytes=1 << 16)
     elif case == "sched_huge":
-        # 4096 x 4097 super-tiles: one past the 24 bits an order entry holds them in
+        # 4096 x 4097 super-tiles of 32x32 pixels (unlit): past the 24 bits an order entry holds
         cl, words = [cam, dict(cam, width=4096 * 32, height=4096 * 32 + 1)], "2^24 super-tiles"
+        fields = dict(d_sched="buf", sched_bytes=1 << 40)
+    elif case == "sched_huge_lit":
+        # lit super-tiles are 16x16 pixels: a camera of half that size is already past the limit
+        p, words = dict(prm, lighting=1), "2^24 super-tiles"
+        cl = [cam, dict(cam, width=4096 * 16, height=4096 * 16 + 1)]
         fields = dict(d_sched="buf", sched_bytes=1 << 40)
     elif case == "waves_per_simd":
         p, fields, words = dict(prm, persistent=1, lighting=1, waves_per_simd=4), dict(d_queue="buf"), "waves_per_simd"
